@@ -1,0 +1,192 @@
+"""Throughput benchmark of the encrypted linear-layer path on one MI355X.
+
+Workload (default): a batch of 64 independent RNS-CKKS ciphertexts at
+N = 2^16 with levels drawn uniformly from 4..12 (12 x 50-bit q, 3 special
+primes, dnum 4), each applying a 256x256 FC layer (He-normal FP64 weights,
+a seeded output and input neuron permutation folded into the plaintext
+weights) with the baby-step giant-step diagonal method (16 x 16: 30 rotations
+and 256 plaintext multiply-accumulates per ciphertext), then one rescale.
+
+One timed step = load the evaluation keys (coefficient domain -> NTT, resident),
+encode the layer weights (diagonals, shuffle folding, FP64 embedding, RNS,
+NTT), and apply the layer with rescale to the whole batch.  Inputs (key
+material, weights, ciphertexts) are resident in HBM before timing.  The keys
+and ciphertexts are uniform residues: RLWE samples are indistinguishable from
+uniform, and bit-exactness of the kernels is covered by the test suite.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--batch", type=int, default=64)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-level", type=int, default=8, help="level of the oracle's sampled request")
+    return ap.parse_args()
+
+
+WORKLOAD = dict(log_n=16, L=12, K=3, dnum=4, bits=50, scale=2.0 ** 40, fc=256, n1=16, lmin=4, lmax=12)
+
+
+def cpu_baseline(level: int) -> dict:
+    """The oracle (plain C + numpy, OpenMP over limbs) on one request of the same
+    workload at a single level; layers/s = 1 / time."""
+    from oracle import oracle as O
+    from paper_2509_01253_amd import synth
+
+    w = WORKLOAD
+    prm = O.make_params(w["log_n"], w["L"], w["K"], w["dnum"], w["bits"], w["scale"])
+    st = synth.Stream(synth.master_seed(3)).sub(99)
+    sched = O.fc_schedule(w["fc"], w["n1"])
+    gal = [O.galois_of(r, prm.log_n) for r in sched.rotations()]
+    evk = np.stack([np.stack([np.stack([synth.uniform_limbs(st, prm.mods, prm.N) for _ in range(2)])
+                              for _ in range(prm.dnum)]) for _ in gal])
+    keys = O.KeySet(gal, evk)
+    pts = np.stack([synth.uniform_limbs(st, prm.q[:level], prm.N) for _ in range(w["fc"])])
+    pts = pts.reshape(1, 1, sched.G, sched.B, level, prm.N)
+    ct = np.stack([synth.uniform_limbs(st, prm.q[:level], prm.N) for _ in range(2)])
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    y = O.linear(prm, ct[None], level, sched, pts, keys)
+    O.rescale(prm, y[0], level)
+    dt = time.perf_counter() - t0
+    return {"value": 1.0 / dt, "unit": "layers/s", "cores": threads, "kind": "oracle",
+            "sample": f"one request (FC 256x256, 30 rotations, 256 pt-MACs, rescale) at level {level} of "
+                      f"the N=2^16 workload; {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+
+    from paper_2509_01253_amd import fhelin as F
+    from paper_2509_01253_amd import synth
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    dev = torch.device("cuda:0")
+    w = WORKLOAD
+    primes = F.fhelin_primes_generate(w["log_n"], w["bits"], w["K"] + w["L"])
+    p, q = primes[: w["K"]], primes[w["K"]:]
+    N, L, K, dnum = 1 << w["log_n"], w["L"], w["K"], w["dnum"]
+    alpha = -(-L // dnum)
+    beta = -(-L // alpha)
+    t_setup = time.perf_counter()
+    ctx = F.fhelin_ctx_create(w["log_n"], q, p, dnum)
+    t_ctx = time.perf_counter() - t_setup
+    plan = F.fhelin_plan_create(ctx, F.FHELIN_LAYER_FC, fc_n=w["fc"], fc_out=w["fc"], fc_in=w["fc"], n1=w["n1"])
+    galois = F.fhelin_plan_galois(plan)
+    info = F.fhelin_plan_info(plan)
+    n_rot = sum(1 for r in F.fhelin_plan_rotations(plan)[0] if r) + sum(1 for r in F.fhelin_plan_rotations(plan)[1] if r)
+
+    root = synth.Stream(synth.master_seed(3))
+    sk = root.sub(synth.TAG_KEYS)
+    mods = q + p
+    # evaluation keys, coefficient domain [n_keys][beta][2][L+K][N], uniform residues
+    evk = torch.empty((len(galois), beta, 2, L + K, N), dtype=torch.int64, device=dev)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(int(sk.u64(1)[0] & 0x7FFFFFFFFFFFFFFF))
+    for m, qm in enumerate(mods):
+        evk[:, :, :, m].random_(0, qm, generator=gen)
+    sw = root.sub(synth.TAG_W)
+    W = torch.from_numpy(sw.he_normal((w["fc"], w["fc"]), w["fc"])).to(dev)
+    sp = root.sub(synth.TAG_PERM)
+    perm_out = torch.from_numpy(sp.permutation(w["fc"])).to(dev)
+    perm_in = torch.from_numpy(sp.permutation(w["fc"])).to(dev)
+    levels = [int(v) for v in root.sub(synth.TAG_LEVEL).integers(args.batch, w["lmin"], w["lmax"])]
+    x = torch.empty((args.batch, 2, L, N), dtype=torch.int64, device=dev)
+    for i in range(L):
+        x[:, :, i].random_(0, q[i], generator=gen)
+    y = torch.zeros((args.batch, 2, L, N), dtype=torch.int64, device=dev)
+    out_levels = [l - 1 for l in levels]
+    torch.cuda.synchronize()
+
+    def step():
+        ks = F.fhelin_keyset_load(ctx, galois, L, evk)
+        pts = F.fhelin_plan_encode_weights(ctx, plan, W, perm_out, perm_in, L, w["scale"])
+        F.fhelin_linear_apply(ctx, plan, ks, pts, x, levels, y, out_levels, F.FHELIN_APPLY_RESCALE)
+        return ks, pts
+
+    def release(h):
+        F.fhelin_ptset_release(h[1])
+        F.fhelin_keyset_release(h[0])
+
+    for _ in range(args.warmup):
+        release(step())
+        torch.cuda.synchronize()
+    # apply-only timing (keys and weights resident), for the breakdown
+    ks, pts = step()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    F.fhelin_linear_apply(ctx, plan, ks, pts, x, levels, y, out_levels, F.FHELIN_APPLY_RESCALE)
+    ev1.record()
+    torch.cuda.synchronize()
+    apply_ms = ev0.elapsed_time(ev1)
+    release((ks, pts))
+
+    torch.cuda.synchronize()
+    lat = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        s0 = time.perf_counter()
+        h = step()
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - s0) * 1e3)
+        release(h)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    ms = float(np.mean(lat))
+    layers_per_s = args.batch / (ms / 1e3)
+    res = {
+        "metric": "encrypted linear layers/s (N=2^16, 256x256 FC, batch of 64 at levels 4..12)",
+        "value": round(layers_per_s, 3),
+        "unit": "layers/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": "batched FC 256x256, 64 RNS-CKKS ciphertexts, N=2^16, levels U{4..12}, "
+                               "12+3 primes of 50 bits, dnum 4, BSGS 16x16, rescale",
+                   "batch": args.batch, "levels": levels},
+        "ks_rotations_per_s": round(args.batch * n_rot / (ms / 1e3), 1),
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3), "p99": round(float(np.percentile(lat, 99)), 3)},
+        "apply_only_ms": round(apply_ms, 3),
+        "layers_per_s_apply_only": round(args.batch / (apply_ms / 1e3), 3),
+        "ctx_setup_ms": round(t_ctx * 1e3, 1),
+        "plan": info,
+        "timed_wall_s": round(total, 3),
+    }
+    F.fhelin_plan_destroy(plan)
+    F.fhelin_ctx_destroy(ctx)
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(args.cpu_level)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,234 @@
+/*
+ * fhelin.h -- C ABI of the MI355X encrypted linear-layer library.
+ *
+ * The library evaluates the server side of hybrid FHE inference (arxiv
+ * 2509.01253, Sec. 3-4): the linear layers of a network run on encrypted
+ * inputs, the client decrypts and applies the activations between layers.
+ * Ciphertexts are RNS-CKKS: a ciphertext at level l is a pair (c0, c1) of
+ * polynomials in Z_Q[X]/(X^N+1), Q = q_0 ... q_{l-1}, decrypting as c0 + c1*s.
+ * The library never sees a secret key: it loads evaluation keys, encodes the
+ * server's plaintext weights, applies linear layers and rescales.
+ *
+ * Conventions shared by every entry point
+ *   - Status: 0 on success, a negative FHELIN_E_* code otherwise; nothing is
+ *     thrown across the ABI.  fhelin_last_error() gives a message for the
+ *     calling thread's last failure.
+ *   - Device pointers are plain HIP device addresses (e.g. a torch tensor's
+ *     data_ptr()); they stay owned by the caller and are never freed by the
+ *     library.  Handles (ctx, keyset, ptset, plan) are owned by the library and
+ *     released with their destroy/release call.
+ *   - Streams: `stream` is a hipStream_t passed as void* (NULL = the null
+ *     stream).  Work is enqueued on it and ordered by it; a call returns once
+ *     the work is enqueued.  Inputs must stay valid until the stream reaches
+ *     the work.  Calls on different streams that share a handle may run
+ *     concurrently: each stream gets its own workspace.
+ *   - Ciphertext and plaintext data cross the ABI in the COEFFICIENT domain:
+ *     uint64 residues in [0, q_i), limb-major, N values per limb.
+ *   - The modulus list of a context is q_0..q_{L-1} followed by p_0..p_{K-1}
+ *     (K special primes of the hybrid key switch).
+ */
+#ifndef FHELIN_H
+#define FHELIN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define FHELIN_OK 0
+#define FHELIN_E_INVALID_ARG (-1)       /* null handle/pointer, bad size or layout */
+#define FHELIN_E_UNSUPPORTED_PARAM (-2) /* parameters outside what the kernels support */
+#define FHELIN_E_LEVEL_MISMATCH (-3)    /* levels inconsistent between operands */
+#define FHELIN_E_MISSING_GALOIS_KEY (-4)/* a rotation needs a key the keyset lacks */
+#define FHELIN_E_OOM (-5)               /* device allocation failed */
+#define FHELIN_E_BUDGET (-6)            /* the context's HBM budget would be exceeded */
+#define FHELIN_E_HIP (-7)               /* a HIP runtime call failed */
+#define FHELIN_E_UNIMPLEMENTED (-8)
+
+typedef struct fhelin_ctx fhelin_ctx;
+typedef struct fhelin_keyset fhelin_keyset;
+typedef struct fhelin_ptset fhelin_ptset;
+typedef struct fhelin_plan fhelin_plan;
+
+/* ---- parameters and context ------------------------------------------ */
+
+/* RNS-CKKS parameter set.  N = 2^log_n with 10 <= log_n <= 16; every modulus
+ * is a distinct prime below 2^60 with q = 1 (mod 2N); 1 <= n_q <= 32,
+ * 1 <= n_p <= 8, 1 <= dnum <= n_q.  Digits of the hybrid key switch hold
+ * alpha = ceil(n_q/dnum) consecutive q's; the product of the p's must exceed
+ * every digit's product (checked).  Arrays are host memory, copied. */
+typedef struct {
+    int32_t log_n;
+    int32_t n_q;        /* L */
+    int32_t n_p;        /* K */
+    int32_t dnum;
+    const uint64_t *q;  /* [n_q] */
+    const uint64_t *p;  /* [n_p] */
+} fhelin_params;
+
+/* Helper for choosing moduli: the first `count` primes q = 1 (mod 2N) below
+ * 2^bits, scanning downwards, written to host array out[count] in descending
+ * order.  A common choice takes the first n_p as special primes and the next
+ * n_q as q_0 > q_1 > ... .  Returns FHELIN_E_UNSUPPORTED_PARAM if the range
+ * runs out. */
+int fhelin_primes_generate(int32_t log_n, int32_t bits, int32_t count, uint64_t *out);
+
+/* Context setup (roots of unity, NTT twiddles, base-conversion constants) on
+ * the current HIP device.  The context owns its device tables. */
+int fhelin_ctx_create(const fhelin_params *prm, fhelin_ctx **out);
+int fhelin_ctx_destroy(fhelin_ctx *ctx);
+
+/* HBM budget (bytes) for everything the context allocates: keys, plaintexts
+ * and per-stream workspaces.  0 = unlimited (the default).  Allocations that
+ * would exceed it fail with FHELIN_E_BUDGET. */
+int fhelin_ctx_set_budget(fhelin_ctx *ctx, uint64_t bytes);
+/* Bytes currently allocated by the context (keys + plaintexts + workspaces). */
+int fhelin_ctx_memory(const fhelin_ctx *ctx, uint64_t *used_bytes);
+/* Release the per-stream workspaces (they are re-created on demand). */
+int fhelin_ctx_trim(fhelin_ctx *ctx);
+
+/* The minimal primitive 2N-th root of unity the context uses for modulus
+ * index mod_index (0..n_q+n_p-1); the forward NTT of fhelin_ntt evaluates at
+ * its odd powers. */
+int fhelin_ctx_root(const fhelin_ctx *ctx, int32_t mod_index, uint64_t *psi);
+
+/* ---- evaluation keys (paper Sec. 4.2: uploaded once at setup) --------- */
+
+/* Load Galois evaluation keys.  galois[n_keys] are odd elements g of
+ * (Z/2N)^*, rotation of slots left by r <=> g = 5^r mod 2N.  Keys are stored
+ * up to Q-level `level` (1..n_q) and serve every level <= level.
+ * evk layout, coefficient domain:
+ *   [n_keys][beta][2][level + n_p][N],  beta = ceil(level / alpha),
+ * digit j < beta, part 0 = b_j, part 1 = a_j, limbs q_0..q_{level-1} then
+ * p_0..p_{n_p-1}; the key for digit j satisfies
+ *   b_j + a_j s = e_j + P * [j-th digit CRT indicator] * s(X^g)  (mod QP).
+ * src_on_device selects whether evk is a device or host pointer; it is copied,
+ * transformed to the NTT domain and kept resident.  Charged to the budget. */
+int fhelin_keyset_load(fhelin_ctx *ctx, const uint32_t *galois, int32_t n_keys, int32_t level,
+                       const uint64_t *evk, int32_t src_on_device, void *stream, fhelin_keyset **out);
+int fhelin_keyset_release(fhelin_keyset *ks);
+
+/* ---- plaintexts -------------------------------------------------------- */
+
+/* Import integer plaintexts [n_pt][level][N] (coefficient domain, residues
+ * mod q_0..q_{level-1}); host or device source. */
+int fhelin_pt_import(fhelin_ctx *ctx, const uint64_t *pt, int32_t n_pt, int32_t level, int32_t src_on_device,
+                     void *stream, fhelin_ptset **out);
+
+/* CKKS encode (canonical embedding, slot j at zeta^(5^j), zeta = exp(i pi/N);
+ * Cheon-Kim-Kim-Song 2017): real slot vectors slots[n_pt][N/2] (device, FP64)
+ * -> m_k = round(scale * (2/N) * sum_j z_j Re(zeta^(-5^j k))), ties to even,
+ * reduced mod q_0..q_{level-1}.  |m_k| must stay below 2^62. */
+int fhelin_pt_encode(fhelin_ctx *ctx, const double *slots, int32_t n_pt, int32_t level, double scale, void *stream,
+                     fhelin_ptset **out);
+
+/* Write a plaintext set back in the coefficient domain: out[n_pt][level][N]
+ * (device), level <= the set's level. */
+int fhelin_pt_export(fhelin_ctx *ctx, const fhelin_ptset *pts, int32_t level, uint64_t *out, void *stream);
+int fhelin_ptset_info(const fhelin_ptset *pts, int32_t *n_pt, int32_t *level);
+int fhelin_ptset_release(fhelin_ptset *pts);
+
+/* ---- linear-layer plans ------------------------------------------------ */
+
+#define FHELIN_LAYER_FC 1
+#define FHELIN_LAYER_CONV 2
+
+/* Layer description.
+ *  FC (Halevi-Shoup diagonal method, baby-step giant-step):
+ *    fc_n: padded square size, a power of two dividing N/2; the weight is
+ *    fc_out x fc_in (<= fc_n each) and is zero-padded.  The input ciphertext
+ *    holds x (length fc_n, zero-padded) replicated N/(2 fc_n) times.  n1 is
+ *    the number of baby steps (a power of two dividing fc_n); n1 = fc_n is the
+ *    plain method with a single giant step.
+ *  CONV (multiplexed, channel-major packing): c_in, c_out channels, h x w
+ *    spatial, kernel k in {1, 3}, stride 1, zero padding k/2 ("same").  Slot
+ *    s = c*h*w + y*w + x with c_ct = N/(2hw) channels per ciphertext, so a
+ *    layer maps ceil(c_in/c_ct) input ciphertexts to ceil(c_out/c_ct) outputs.
+ *    Baby steps are the k*k spatial offsets (dy, dx), row-major, rotation
+ *    dy*w + dx; giant steps are channel offsets j < c_ct, rotation j*h*w.
+ * Every layer is evaluated as
+ *    y_o = sum_j rot_{G_j}( sum_i sum_b pt[o][i][j][b] * rot_{r_b}(x_i) )
+ * (rot_0 = identity, no key switch), with plaintext index
+ *    ((o*n_in + i)*n_giant + j)*n_baby + b. */
+typedef struct {
+    int32_t kind;
+    int32_t fc_n, fc_out, fc_in, n1;
+    int32_t c_in, c_out, h, w, k;
+} fhelin_layer_desc;
+
+int fhelin_plan_create(fhelin_ctx *ctx, const fhelin_layer_desc *desc, fhelin_plan **out);
+int fhelin_plan_destroy(fhelin_plan *plan);
+/* Shape of a plan: ciphertexts in/out per request, baby and giant step counts,
+ * number of plaintexts (n_out*n_in*n_giant*n_baby). */
+int fhelin_plan_info(const fhelin_plan *plan, int32_t *n_in, int32_t *n_out, int32_t *n_baby, int32_t *n_giant,
+                     int32_t *n_pt);
+/* Rotation amounts (slots, left): baby[n_baby], giant[n_giant]; either may be NULL. */
+int fhelin_plan_rotations(const fhelin_plan *plan, int32_t *baby, int32_t *giant);
+/* Distinct Galois elements the plan needs (ascending), up to cap; *n gets the count. */
+int fhelin_plan_galois(const fhelin_plan *plan, uint32_t *out, int32_t cap, int32_t *n);
+
+/* Encode a layer's weights for a plan (paper Sec. 4.4: the previous round's
+ * unshuffle and this round's shuffle are folded into the weights):
+ *   W'[t][u] = W[perm_out[t]][perm_in[u]]       (FC, W is fc_out x fc_in)
+ *   W'[t][u][.][.] = W[perm_out[t]][perm_in[u]][.][.]   (conv channels,
+ *                                                   W is c_out x c_in x k x k)
+ * weights, perm_out, perm_in are device pointers (perms may be NULL =
+ * identity).  The diagonals / multiplexed slot vectors of the plan are formed
+ * on the device and encoded like fhelin_pt_encode. */
+int fhelin_plan_encode_weights(fhelin_ctx *ctx, const fhelin_plan *plan, const double *weights,
+                               const int32_t *perm_out, const int32_t *perm_in, int32_t level, double scale,
+                               void *stream, fhelin_ptset **out);
+
+/* ---- ciphertext batches and evaluation -------------------------------- */
+
+/* A batch of ciphertexts in device memory, coefficient domain:
+ *   data[n_ct][2][stride][N]; ciphertext t uses limbs 0..levels[t]-1 of each
+ *   polynomial (levels is a host array).  stride >= max level. */
+typedef struct {
+    uint64_t *data;
+    int32_t n_ct;
+    int32_t stride;
+    const int32_t *levels;
+} fhelin_ct_batch;
+
+#define FHELIN_APPLY_RESCALE 1
+
+/* Apply a linear layer to a batch of requests.  in->n_ct = R * n_in (request
+ * r owns input ciphertexts r*n_in .. r*n_in+n_in-1, all at the same level);
+ * out->n_ct = R * n_out.  Without flags the outputs are at the input level;
+ * with FHELIN_APPLY_RESCALE they are rescaled by the top prime (level - 1).
+ * out->levels is read and must hold the resulting levels.  The plaintext set
+ * must be encoded for this plan at a level >= every request level; the keyset
+ * must cover the plan's Galois elements at a level >= every request level.
+ * Results are bit-identical whatever the batch composition. */
+int fhelin_linear_apply(fhelin_ctx *ctx, const fhelin_plan *plan, const fhelin_keyset *ks, const fhelin_ptset *pts,
+                        const fhelin_ct_batch *in, const fhelin_ct_batch *out, int32_t flags, void *stream);
+
+/* Rescale (full-RNS CKKS): drop the top prime q_{l-1} with rounding,
+ * c'_i = (c_i - [c]_{q_{l-1}}) * q_{l-1}^{-1} mod q_i with the centred
+ * representative of the top limb.  out levels = in levels - 1 (each >= 1).
+ * out may alias in only if the strides match. */
+int fhelin_rescale(fhelin_ctx *ctx, const fhelin_ct_batch *in, const fhelin_ct_batch *out, void *stream);
+
+/* Rotate every ciphertext of a batch left by steps[t] slots (host array):
+ * automorphism g = 5^steps mod 2N followed by a hybrid key switch. */
+int fhelin_rotate(fhelin_ctx *ctx, const fhelin_keyset *ks, const fhelin_ct_batch *in, const int32_t *steps,
+                  const fhelin_ct_batch *out, void *stream);
+
+/* Batched negacyclic NTT (inverse = 0) or INTT (inverse = 1) in place on
+ * rows[n_rows][N] (device), row t reduced modulo modulus mod_index[t] (host
+ * array).  Forward output: A[k] = sum_j a_j psi^(j(2 brv(k) + 1)) (bit-
+ * reversed order, psi = fhelin_ctx_root); the inverse undoes it exactly. */
+int fhelin_ntt(fhelin_ctx *ctx, uint64_t *rows, const int32_t *mod_index, int32_t n_rows, int32_t inverse,
+               void *stream);
+
+/* ---- diagnostics ------------------------------------------------------- */
+const char *fhelin_last_error(void);
+const char *fhelin_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FHELIN_H */

@@ -1,0 +1,381 @@
+// api.hip -- the extern "C" boundary: argument checks, handle ownership, stream plumbing,
+// and evaluation-key loading (hot-path row a2).
+#include <algorithm>
+
+#include "internal.h"
+
+namespace fl {
+int primes_generate(int log_n, int bits, int count, uint64_t *out);
+const char *last_error();
+int plan_create(Ctx *c, const fhelin_layer_desc *d, Plan **out);
+int linear_apply(Ctx *c, const Plan *p, const KeySet *ks, const PtSet *pts, const fhelin_ct_batch *in,
+                 const fhelin_ct_batch *out, int flags, hipStream_t s, int max_chunk);
+int rotate_batch(Ctx *c, const KeySet *ks, const fhelin_ct_batch *in, const int32_t *steps, const fhelin_ct_batch *out,
+                 hipStream_t s);
+int rescale_batch(Ctx *c, const fhelin_ct_batch *in, const fhelin_ct_batch *out, hipStream_t s);
+int ptset_new(Ctx *c, int n_pt, int level, PtSet **out);
+void ptset_free(PtSet *p);
+int pt_import(Ctx *c, const uint64_t *src, int n_pt, int level, int on_device, hipStream_t s, PtSet **out);
+int pt_export(Ctx *c, const PtSet *p, int level, uint64_t *dst, hipStream_t s);
+int pt_encode(Ctx *c, const double *slots, int n_pt, int level, double scale, hipStream_t s, PtSet **out);
+int plan_encode_weights(Ctx *c, const Plan *pl, const double *W, const int32_t *perm_out, const int32_t *perm_in,
+                        int level, double scale, hipStream_t s, PtSet **out);
+
+// device set of the context for the duration of a call
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(const Ctx *c) {
+        if (hipGetDevice(&prev) == hipSuccess && prev != c->device) (void)hipSetDevice(c->device);
+    }
+    ~DeviceGuard() {
+        int cur;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+static int keyset_load(Ctx *c, const uint32_t *galois, int n_keys, int level, const uint64_t *evk, int on_device,
+                       hipStream_t s, KeySet **out) {
+    FL_CHECK(galois && evk && out && n_keys >= 1, FHELIN_E_INVALID_ARG, "keyset_load: null argument or no keys");
+    FL_CHECK(level >= 1 && level <= c->L, FHELIN_E_LEVEL_MISMATCH, "keyset_load: level out of range");
+    const uint32_t two_n = 2u * (uint32_t)c->N;
+    for (int i = 0; i < n_keys; ++i) {
+        FL_CHECK(galois[i] % 2 == 1 && galois[i] < two_n, FHELIN_E_INVALID_ARG, "Galois elements must be odd and < 2N");
+        for (int j = 0; j < i; ++j) FL_CHECK(galois[j] != galois[i], FHELIN_E_INVALID_ARG, "duplicate Galois element");
+    }
+    std::unique_ptr<KeySet> k(new KeySet());
+    k->ctx = c;
+    k->level = level;
+    k->beta = (level + c->alpha - 1) / c->alpha;
+    k->n_keys = n_keys;
+    k->galois.assign(galois, galois + n_keys);
+    k->bytes = (size_t)n_keys * k->key_stride() * sizeof(uint64_t);
+    FL_RET(dev_alloc(c, (void **)&k->evk, k->bytes));
+    hipError_t e = hipMemcpyAsync(k->evk, evk, k->bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && !on_device) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        dev_free(c, k->evk, k->bytes);
+        return set_error(FHELIN_E_HIP, std::string("keyset_load copy: ") + hipGetErrorString(e));
+    }
+    // every row: NTT then Montgomery form; rows grouped per (key, digit, part)
+    RowMap m{};
+    m.kind = ROWS_KEY;
+    m.log_n = c->log_n;
+    m.L = c->L;
+    m.K = c->K;
+    m.alpha = c->alpha;
+    const int parts = n_keys * k->beta * 2;
+    const int per = 64;  // parts per launch (rows = per * (level + K))
+    int rc = FHELIN_OK;
+    for (int p0 = 0; p0 < parts && rc == FHELIN_OK; p0 += per) {
+        RowMap e2 = m;
+        e2.base = k->evk + (int64_t)p0 * (level + c->K) * c->N;
+        e2.n_ct = 1;
+        e2.n_part = std::min(per, parts - p0);
+        e2.level[0] = (uint8_t)level;
+        rc = launch_ntt(c, e2, 0, s);
+        if (rc == FHELIN_OK) rc = launch_to_mont(c, e2, s);
+    }
+    if (rc) {
+        dev_free(c, k->evk, k->bytes);
+        return rc;
+    }
+    *out = k.release();
+    return FHELIN_OK;
+}
+
+static void keyset_free(KeySet *k) {
+    if (!k) return;
+    dev_free(k->ctx, k->evk, k->bytes);
+    delete k;
+}
+
+static int ntt_rows(Ctx *c, uint64_t *rows, const int32_t *mods, int n_rows, int inverse, hipStream_t s) {
+    FL_CHECK(rows && mods && n_rows >= 0, FHELIN_E_INVALID_ARG, "ntt: null argument");
+    for (int i = 0; i < n_rows; ++i)
+        FL_CHECK(mods[i] >= 0 && mods[i] < c->L + c->K, FHELIN_E_INVALID_ARG, "ntt: modulus index out of range");
+    if (n_rows == 0) return FHELIN_OK;
+    const int per = 4096;
+    int32_t *d_mods = nullptr;
+    FL_RET(dev_alloc(c, (void **)&d_mods, (size_t)n_rows * sizeof(int32_t)));
+    hipError_t e = hipMemcpyAsync(d_mods, mods, (size_t)n_rows * sizeof(int32_t), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    int rc = e == hipSuccess ? FHELIN_OK : set_error(FHELIN_E_HIP, "ntt: module list upload failed");
+    for (int r0 = 0; r0 < n_rows && rc == FHELIN_OK; r0 += per) {
+        RowMap m{};
+        m.base = rows + (int64_t)r0 * c->N;
+        m.list = d_mods + r0;
+        m.kind = ROWS_LIST;
+        m.n_ct = 1;
+        m.n_list = std::min(per, n_rows - r0);
+        m.log_n = c->log_n;
+        m.L = c->L;
+        m.K = c->K;
+        m.alpha = c->alpha;
+        rc = launch_ntt(c, m, inverse, s);
+    }
+    (void)hipStreamSynchronize(s);
+    dev_free(c, d_mods, (size_t)n_rows * sizeof(int32_t));
+    return rc;
+}
+
+}  // namespace fl
+
+using namespace fl;
+
+#define API_BEGIN try {
+#define API_END                                                         \
+    }                                                                   \
+    catch (const std::bad_alloc &) {                                    \
+        return set_error(FHELIN_E_OOM, "host allocation failed");       \
+    }                                                                   \
+    catch (...) {                                                       \
+        return set_error(FHELIN_E_INVALID_ARG, "unexpected exception"); \
+    }
+
+#define FHELIN_EXPORT __attribute__((visibility("default")))
+
+extern "C" {
+
+FHELIN_EXPORT int fhelin_primes_generate(int32_t log_n, int32_t bits, int32_t count, uint64_t *out) {
+    API_BEGIN return primes_generate(log_n, bits, count, out);
+    API_END
+}
+
+FHELIN_EXPORT int fhelin_ctx_create(const fhelin_params *prm, fhelin_ctx **out) {
+    API_BEGIN Ctx *c = nullptr;
+    int rc = ctx_create(prm, &c);
+    if (rc == FHELIN_OK) *out = (fhelin_ctx *)c;
+    return rc;
+    API_END
+}
+
+FHELIN_EXPORT int fhelin_ctx_destroy(fhelin_ctx *ctx) {
+    API_BEGIN FL_CHECK(ctx, FHELIN_E_INVALID_ARG, "ctx_destroy: null context");
+    Ctx *c = (Ctx *)ctx;
+    DeviceGuard g(c);
+    (void)hipDeviceSynchronize();
+    ctx_destroy(c);
+    return FHELIN_OK;
+    API_END
+}
+
+FHELIN_EXPORT int fhelin_ctx_set_budget(fhelin_ctx *ctx, uint64_t bytes) {
+    API_BEGIN FL_CHECK(ctx, FHELIN_E_INVALID_ARG, "null context");
+    Ctx *c = (Ctx *)ctx;
+    std::lock_guard<std::mutex> g(c->mu);
+    c->budget = bytes;
+    return FHELIN_OK;
+    API_END
+}
+
+FHELIN_EXPORT int fhelin_ctx_memory(const fhelin_ctx *ctx, uint64_t *used) {
+    API_BEGIN FL_CHECK(ctx && used, FHELIN_E_INVALID_ARG, "null argument");
+    Ctx *c = (Ctx *)ctx;
+    std::lock_guard<std::mutex> g(c->mu);
+    *used = c->used;
+    return FHELIN_OK;
+    API_END
+}
+
+FHELIN_EXPORT int fhelin_ctx_trim(fhelin_ctx *ctx) {
+    API_BEGIN FL_CHECK(ctx, FHELIN_E_INVALID_ARG, "null context");
+    Ctx *c = (Ctx *)ctx;
+    DeviceGuard g(c);
+    FL_TRY_HIP(hipDeviceSynchronize());
+    std::map<void *, std::unique_ptr<Workspace>> old;
+    {
+        std::lock_guard<std::mutex> lk(c->mu);
+        old.swap(c->ws);
+    }
+    old.clear();
+    return FHELIN_OK;
+    API_END
+}
+
+FHELIN_EXPORT int fhelin_ctx_root(const fhelin_ctx *ctx, int32_t mod_index, uint64_t *psi) {
+    API_BEGIN FL_CHECK(ctx && psi, FHELIN_E_INVALID_ARG, "null argument");
+    const Ctx *c = (const Ctx *)ctx;
+    FL_CHECK(mod_index >= 0 && mod_index < c->L + c->K, FHELIN_E_INVALID_ARG, "modulus index out of range");
+    *psi = c->psi[mod_index];
+    return FHELIN_OK;
+    API_END
+}
+
+FHELIN_EXPORT int fhelin_keyset_load(fhelin_ctx *ctx, const uint32_t *galois, int32_t n_keys, int32_t level,
+                                     const uint64_t *evk, int32_t src_on_device, void *stream, fhelin_keyset **out) {
+    API_BEGIN FL_CHECK(ctx, FHELIN_E_INVALID_ARG, "null context");
+    Ctx *c = (Ctx *)ctx;
+    DeviceGuard g(c);
+    KeySet *k = nullptr;
+    int rc = keyset_load(c, galois, n_keys, level, evk, src_on_device, (hipStream_t)stream, &k);
+    if (rc == FHELIN_OK) *out = (fhelin_keyset *)k;
+    return rc;
+    API_END
+}
+
+FHELIN_EXPORT int fhelin_keyset_release(fhelin_keyset *ks) {
+    API_BEGIN FL_CHECK(ks, FHELIN_E_INVALID_ARG, "null keyset");
+    KeySet *k = (KeySet *)ks;
+    DeviceGuard g(k->ctx);
+    (void)hipDeviceSynchronize();
+    keyset_free(k);
+    return FHELIN_OK;
+    API_END
+}
+
+FHELIN_EXPORT int fhelin_pt_import(fhelin_ctx *ctx, const uint64_t *pt, int32_t n_pt, int32_t level,
+                                   int32_t src_on_device, void *stream, fhelin_ptset **out) {
+    API_BEGIN FL_CHECK(ctx && out, FHELIN_E_INVALID_ARG, "null argument");
+    Ctx *c = (Ctx *)ctx;
+    DeviceGuard g(c);
+    PtSet *p = nullptr;
+    int rc = pt_import(c, pt, n_pt, level, src_on_device, (hipStream_t)stream, &p);
+    if (rc == FHELIN_OK) *out = (fhelin_ptset *)p;
+    return rc;
+    API_END
+}
+
+FHELIN_EXPORT int fhelin_pt_encode(fhelin_ctx *ctx, const double *slots, int32_t n_pt, int32_t level, double scale,
+                                   void *stream, fhelin_ptset **out) {
+    API_BEGIN FL_CHECK(ctx && out, FHELIN_E_INVALID_ARG, "null argument");
+    Ctx *c = (Ctx *)ctx;
+    DeviceGuard g(c);
+    PtSet *p = nullptr;
+    int rc = pt_encode(c, slots, n_pt, level, scale, (hipStream_t)stream, &p);
+    if (rc == FHELIN_OK) *out = (fhelin_ptset *)p;
+    return rc;
+    API_END
+}
+
+FHELIN_EXPORT int fhelin_pt_export(fhelin_ctx *ctx, const fhelin_ptset *pts, int32_t level, uint64_t *out,
+                                   void *stream) {
+    API_BEGIN FL_CHECK(ctx && pts, FHELIN_E_INVALID_ARG, "null argument");
+    Ctx *c = (Ctx *)ctx;
+    DeviceGuard g(c);
+    return pt_export(c, (const PtSet *)pts, level, out, (hipStream_t)stream);
+    API_END
+}
+
+FHELIN_EXPORT int fhelin_ptset_info(const fhelin_ptset *pts, int32_t *n_pt, int32_t *level) {
+    API_BEGIN FL_CHECK(pts, FHELIN_E_INVALID_ARG, "null plaintext set");
+    const PtSet *p = (const PtSet *)pts;
+    if (n_pt) *n_pt = p->n_pt;
+    if (level) *level = p->level;
+    return FHELIN_OK;
+    API_END
+}
+
+FHELIN_EXPORT int fhelin_ptset_release(fhelin_ptset *pts) {
+    API_BEGIN FL_CHECK(pts, FHELIN_E_INVALID_ARG, "null plaintext set");
+    PtSet *p = (PtSet *)pts;
+    DeviceGuard g(p->ctx);
+    (void)hipDeviceSynchronize();
+    ptset_free(p);
+    return FHELIN_OK;
+    API_END
+}
+
+FHELIN_EXPORT int fhelin_plan_create(fhelin_ctx *ctx, const fhelin_layer_desc *desc, fhelin_plan **out) {
+    API_BEGIN FL_CHECK(ctx && out, FHELIN_E_INVALID_ARG, "null argument");
+    Plan *p = nullptr;
+    int rc = plan_create((Ctx *)ctx, desc, &p);
+    if (rc == FHELIN_OK) *out = (fhelin_plan *)p;
+    return rc;
+    API_END
+}
+
+FHELIN_EXPORT int fhelin_plan_destroy(fhelin_plan *plan) {
+    API_BEGIN FL_CHECK(plan, FHELIN_E_INVALID_ARG, "null plan");
+    delete (Plan *)plan;
+    return FHELIN_OK;
+    API_END
+}
+
+FHELIN_EXPORT int fhelin_plan_info(const fhelin_plan *plan, int32_t *n_in, int32_t *n_out, int32_t *n_baby,
+                                   int32_t *n_giant, int32_t *n_pt) {
+    API_BEGIN FL_CHECK(plan, FHELIN_E_INVALID_ARG, "null plan");
+    const Plan *p = (const Plan *)plan;
+    if (n_in) *n_in = p->n_in;
+    if (n_out) *n_out = p->n_out;
+    if (n_baby) *n_baby = (int32_t)p->rb.size();
+    if (n_giant) *n_giant = (int32_t)p->gk.size();
+    if (n_pt) *n_pt = p->n_pt();
+    return FHELIN_OK;
+    API_END
+}
+
+FHELIN_EXPORT int fhelin_plan_rotations(const fhelin_plan *plan, int32_t *baby, int32_t *giant) {
+    API_BEGIN FL_CHECK(plan, FHELIN_E_INVALID_ARG, "null plan");
+    const Plan *p = (const Plan *)plan;
+    if (baby) std::copy(p->rb.begin(), p->rb.end(), baby);
+    if (giant) std::copy(p->gk.begin(), p->gk.end(), giant);
+    return FHELIN_OK;
+    API_END
+}
+
+FHELIN_EXPORT int fhelin_plan_galois(const fhelin_plan *plan, uint32_t *out, int32_t cap, int32_t *n) {
+    API_BEGIN FL_CHECK(plan && n, FHELIN_E_INVALID_ARG, "null argument");
+    const Plan *p = (const Plan *)plan;
+    *n = (int32_t)p->galois.size();
+    if (out)
+        for (int i = 0; i < cap && i < *n; ++i) out[i] = p->galois[i];
+    return FHELIN_OK;
+    API_END
+}
+
+FHELIN_EXPORT int fhelin_plan_encode_weights(fhelin_ctx *ctx, const fhelin_plan *plan, const double *weights,
+                                             const int32_t *perm_out, const int32_t *perm_in, int32_t level,
+                                             double scale, void *stream, fhelin_ptset **out) {
+    API_BEGIN FL_CHECK(ctx && plan && out, FHELIN_E_INVALID_ARG, "null argument");
+    Ctx *c = (Ctx *)ctx;
+    DeviceGuard g(c);
+    PtSet *p = nullptr;
+    int rc = plan_encode_weights(c, (const Plan *)plan, weights, perm_out, perm_in, level, scale, (hipStream_t)stream, &p);
+    if (rc == FHELIN_OK) *out = (fhelin_ptset *)p;
+    return rc;
+    API_END
+}
+
+FHELIN_EXPORT int fhelin_linear_apply(fhelin_ctx *ctx, const fhelin_plan *plan, const fhelin_keyset *ks,
+                                      const fhelin_ptset *pts, const fhelin_ct_batch *in, const fhelin_ct_batch *out,
+                                      int32_t flags, void *stream) {
+    API_BEGIN FL_CHECK(ctx, FHELIN_E_INVALID_ARG, "null context");
+    Ctx *c = (Ctx *)ctx;
+    DeviceGuard g(c);
+    return linear_apply(c, (const Plan *)plan, (const KeySet *)ks, (const PtSet *)pts, in, out, flags,
+                        (hipStream_t)stream, MAX_BATCH);
+    API_END
+}
+
+FHELIN_EXPORT int fhelin_rescale(fhelin_ctx *ctx, const fhelin_ct_batch *in, const fhelin_ct_batch *out,
+                                 void *stream) {
+    API_BEGIN FL_CHECK(ctx, FHELIN_E_INVALID_ARG, "null context");
+    Ctx *c = (Ctx *)ctx;
+    DeviceGuard g(c);
+    return rescale_batch(c, in, out, (hipStream_t)stream);
+    API_END
+}
+
+FHELIN_EXPORT int fhelin_rotate(fhelin_ctx *ctx, const fhelin_keyset *ks, const fhelin_ct_batch *in,
+                                const int32_t *steps, const fhelin_ct_batch *out, void *stream) {
+    API_BEGIN FL_CHECK(ctx, FHELIN_E_INVALID_ARG, "null context");
+    Ctx *c = (Ctx *)ctx;
+    DeviceGuard g(c);
+    return rotate_batch(c, (const KeySet *)ks, in, steps, out, (hipStream_t)stream);
+    API_END
+}
+
+FHELIN_EXPORT int fhelin_ntt(fhelin_ctx *ctx, uint64_t *rows, const int32_t *mod_index, int32_t n_rows,
+                             int32_t inverse, void *stream) {
+    API_BEGIN FL_CHECK(ctx, FHELIN_E_INVALID_ARG, "null context");
+    Ctx *c = (Ctx *)ctx;
+    DeviceGuard g(c);
+    return ntt_rows(c, rows, mod_index, n_rows, inverse ? 1 : 0, (hipStream_t)stream);
+    API_END
+}
+
+FHELIN_EXPORT const char *fhelin_last_error(void) { return last_error(); }
+
+FHELIN_EXPORT const char *fhelin_status_string(int status) { return status_string(status); }
+
+}  // extern "C"

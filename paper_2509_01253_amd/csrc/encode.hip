@@ -1,0 +1,280 @@
+// encode.hip -- plaintext weights: diagonal / multiplexed slot vectors with the
+// shuffle folded in, CKKS encoding, RNS and NTT (hot-path row a3).
+//
+// Encoding (Cheon-Kim-Kim-Song 2017): m_k = round(Delta (2/N) Re sum_j z_j zeta^(-5^j k)),
+// zeta = exp(i pi / N).  Over all odd exponents e (z_j at 5^j, conj z_j at -5^j)
+// this is (Delta/N) Re(zeta^(-k) sum_t Z_t w^(-tk)) with e = 2t+1, w = exp(2 pi i/N):
+// one forward complex FFT of length N per plaintext (radix-2 Stockham, natural
+// order in and out).  Rounding is rint (ties to even).
+#include "internal.h"
+#include "modarith.h"
+
+namespace fl {
+
+// Z[p][(5^j-1)/2] = z_j, Z[p][(2N-5^j-1)/2] = z_j (real slots: conj z = z); every index once
+__global__ void __launch_bounds__(256) k_encode_scatter(const double *__restrict__ slots, double2 *__restrict__ Z,
+                                                        const int32_t *__restrict__ slot_idx, int log_n) {
+    const int64_t N = (int64_t)1 << log_n, S = N / 2;
+    const int p = blockIdx.y;
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= S) return;
+    double z = slots[(int64_t)p * S + j];
+    int t = slot_idx[j];
+    double2 *zp = Z + (int64_t)p * N;
+    zp[t] = make_double2(z, 0.0);
+    zp[N - 1 - t] = make_double2(z, 0.0);
+}
+
+// one radix-2 Stockham stage (Govindaraju et al. 2008 form), forward sign
+__global__ void __launch_bounds__(256) k_fft_stage(const double2 *__restrict__ in, double2 *__restrict__ out,
+                                                   const double *__restrict__ tw, int log_n, int log_ns) {
+    const int64_t N = (int64_t)1 << log_n, H = N / 2;
+    const int p = blockIdx.y;
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= H) return;
+    const double2 *x = in + (int64_t)p * N;
+    double2 *y = out + (int64_t)p * N;
+    const int64_t ns = (int64_t)1 << log_ns;
+    const int64_t k = j & (ns - 1);
+    const double2 a = x[j], b = x[j + H];
+    // w = exp(-2 pi i k / (2 ns)) = table[k * N / (2 ns)]
+    const int64_t ti = k << (log_n - 1 - log_ns);
+    const double wr = tw[2 * ti], wi = tw[2 * ti + 1];
+    const double br = b.x * wr - b.y * wi, bi = b.x * wi + b.y * wr;
+    const int64_t o = ((j >> log_ns) << (log_ns + 1)) + k;
+    y[o] = make_double2(a.x + br, a.y + bi);
+    y[o + ns] = make_double2(a.x - br, a.y - bi);
+}
+
+// m_k = rint(scale/N * Re(X_k zeta^-k)); residues mod q_i -> pt[p][i][k] (coefficient domain)
+__global__ void __launch_bounds__(256) k_encode_finish(const double2 *__restrict__ X, uint64_t *__restrict__ pt,
+                                                       const ModConst *__restrict__ mods,
+                                                       const double *__restrict__ zeta, int level, double scale,
+                                                       int log_n) {
+    const int64_t N = (int64_t)1 << log_n;
+    const int p = blockIdx.y;
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const double2 v = X[(int64_t)p * N + k];
+    // zeta^-k = cos(pi k/N) - i sin(pi k/N)
+    const double re = v.x * zeta[2 * k] + v.y * zeta[2 * k + 1];
+    const double m = rint(re * (scale / (double)N));
+    const int64_t mi = (int64_t)m;
+    const bool neg = mi < 0;
+    const uint64_t mag = neg ? (uint64_t)(-mi) : (uint64_t)mi;
+    uint64_t *o = pt + (int64_t)p * level * N + k;
+    for (int i = 0; i < level; ++i) {
+        const ModConst mc = mods[i];
+        uint64_t r = csub(shoup_lazy(mag, 1, mc.one_sh, mc.q), mc.q);
+        o[(int64_t)i * N] = (neg && r) ? mc.q - r : r;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// weights -> slot vectors for a plan
+// ---------------------------------------------------------------------------
+// FC: entry (j, b), i = n1 j + b: value[s] = W'[(s - n1 j) mod n][(s - n1 j + i) mod n]
+__global__ void __launch_bounds__(256) k_diag_fc(const double *__restrict__ W, const int32_t *__restrict__ perm_out,
+                                                 const int32_t *__restrict__ perm_in, int fc_out, int fc_in, int n,
+                                                 int n1, int S, int p0, double *__restrict__ out) {
+    const int pidx = p0 + blockIdx.y;
+    const int s = blockIdx.x * 256 + threadIdx.x;
+    if (s >= S) return;
+    const int j = pidx / n1, b = pidx % n1, i = n1 * j + b;
+    const int row = ((s - n1 * j) % n + n) % n;
+    const int col = (row + i) % n;
+    double v = 0.0;
+    if (row < fc_out && col < fc_in) {
+        int ro = perm_out ? perm_out[row] : row;
+        int ci = perm_in ? perm_in[col] : col;
+        v = W[(int64_t)ro * fc_in + ci];
+    }
+    out[(int64_t)blockIdx.y * S + s] = v;
+}
+
+// conv: entry (o, i, j, b) holds rot_{-j h w}(d) with
+// d[s] = W'[o c + co(s)][i c + (co(s) + j) mod c][dy + r][dx + r] * [inside]
+__global__ void __launch_bounds__(256) k_diag_conv(const double *__restrict__ W, const int32_t *__restrict__ perm_out,
+                                                   const int32_t *__restrict__ perm_in, int c_out, int c_in, int h,
+                                                   int w, int ks, int n_in, int S, int p0,
+                                                   double *__restrict__ out) {
+    const int pidx = p0 + blockIdx.y;
+    const int s = blockIdx.x * 256 + threadIdx.x;
+    if (s >= S) return;
+    const int hw = h * w, cct = S / hw, B = ks * ks, r = ks / 2;
+    const int b = pidx % B, j = (pidx / B) % cct, ii = (pidx / B / cct) % n_in, o = pidx / B / cct / n_in;
+    const int dy = b / ks - r, dx = b % ks - r;
+    const int sp = ((s - j * hw) % S + S) % S;
+    const int co = sp / hw, y = (sp % hw) / w, x = sp % w;
+    const int cog = o * cct + co, cig = ii * cct + (co + j) % cct;
+    double v = 0.0;
+    if (cog < c_out && cig < c_in && y + dy >= 0 && y + dy < h && x + dx >= 0 && x + dx < w) {
+        int a = perm_out ? perm_out[cog] : cog;
+        int c = perm_in ? perm_in[cig] : cig;
+        v = W[(((int64_t)a * c_in + c) * ks + (dy + r)) * ks + (dx + r)];
+    }
+    out[(int64_t)blockIdx.y * S + s] = v;
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+int ptset_new(Ctx *c, int n_pt, int level, PtSet **out) {
+    FL_CHECK(n_pt >= 1 && level >= 1 && level <= c->L, FHELIN_E_INVALID_ARG, "bad plaintext set shape");
+    std::unique_ptr<PtSet> p(new PtSet());
+    p->ctx = c;
+    p->n_pt = n_pt;
+    p->level = level;
+    p->bytes = (size_t)n_pt * level * c->N * sizeof(uint64_t);
+    FL_RET(dev_alloc(c, (void **)&p->data, p->bytes));
+    *out = p.release();
+    return FHELIN_OK;
+}
+
+void ptset_free(PtSet *p) {
+    if (!p) return;
+    dev_free(p->ctx, p->data, p->bytes);
+    delete p;
+}
+
+// rows of plaintexts p0 .. p0+n-1 of a [n_pt][level][N] buffer as one batch entry
+static RowMap pt_rows(const Ctx *c, uint64_t *data, int n, int level) {
+    RowMap m{};
+    m.base = data;
+    m.kind = ROWS_CT;
+    m.stride = level;
+    m.poly_lo = 0;
+    m.poly_cnt = n;
+    m.n_ct = 1;
+    m.L = c->L;
+    m.K = c->K;
+    m.alpha = c->alpha;
+    m.log_n = c->log_n;
+    m.level[0] = (uint8_t)level;
+    return m;
+}
+
+// coefficient domain -> NTT domain, Montgomery form, in place
+static int pt_to_internal(Ctx *c, PtSet *p, hipStream_t s) {
+    for (int p0 = 0; p0 < p->n_pt; p0 += 64) {
+        RowMap e = pt_rows(c, p->data + (int64_t)p0 * p->level * c->N, std::min(64, p->n_pt - p0), p->level);
+        FL_RET(launch_ntt(c, e, 0, s));
+        FL_RET(launch_to_mont(c, e, s));
+    }
+    return FHELIN_OK;
+}
+
+int pt_import(Ctx *c, const uint64_t *src, int n_pt, int level, int on_device, hipStream_t s, PtSet **out) {
+    FL_CHECK(c && src && out, FHELIN_E_INVALID_ARG, "pt_import: null argument");
+    PtSet *p;
+    FL_RET(ptset_new(c, n_pt, level, &p));
+    hipError_t e = hipMemcpyAsync(p->data, src, p->bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) {
+        ptset_free(p);
+        return set_error(FHELIN_E_HIP, std::string("pt_import copy: ") + hipGetErrorString(e));
+    }
+    if (!on_device) {  // the host source may be reused by the caller as soon as we return
+        e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            ptset_free(p);
+            return set_error(FHELIN_E_HIP, std::string("pt_import sync: ") + hipGetErrorString(e));
+        }
+    }
+    int rc = pt_to_internal(c, p, s);
+    if (rc) {
+        ptset_free(p);
+        return rc;
+    }
+    *out = p;
+    return FHELIN_OK;
+}
+
+int pt_export(Ctx *c, const PtSet *p, int level, uint64_t *dst, hipStream_t s) {
+    FL_CHECK(c && p && dst, FHELIN_E_INVALID_ARG, "pt_export: null argument");
+    FL_CHECK(level >= 1 && level <= p->level, FHELIN_E_LEVEL_MISMATCH, "pt_export: level above the set's level");
+    const int64_t N = c->N;
+    FL_TRY_HIP(hipMemcpy2DAsync(dst, (size_t)level * N * sizeof(uint64_t), p->data,
+                                (size_t)p->level * N * sizeof(uint64_t), (size_t)level * N * sizeof(uint64_t),
+                                p->n_pt, hipMemcpyDeviceToDevice, s));
+    for (int p0 = 0; p0 < p->n_pt; p0 += 64) {
+        RowMap e = pt_rows(c, dst + (int64_t)p0 * level * N, std::min(64, p->n_pt - p0), level);
+        FL_RET(launch_from_mont(c, e, s));
+        FL_RET(launch_ntt(c, e, 1, s));
+    }
+    return FHELIN_OK;
+}
+
+// encode n real slot vectors (device [n][S]) into coefficient-domain rows dst[n][level][N]
+static int encode_into(Ctx *c, const double *slots, int n, int level, double scale, uint64_t *dst, hipStream_t s) {
+    const int64_t N = c->N;
+    uint64_t *ws;
+    FL_RET(workspace_get(c, s, (size_t)n * N * 2 * sizeof(double2), &ws));
+    double2 *a = (double2 *)ws, *b = a + (int64_t)n * N;
+    hipLaunchKernelGGL(k_encode_scatter, dim3((unsigned)(N / 2 + 255) / 256, n), dim3(256), 0, s, slots, a,
+                       c->d_slot_idx, c->log_n);
+    for (int ls = 0; ls < c->log_n; ++ls) {
+        hipLaunchKernelGGL(k_fft_stage, dim3((unsigned)(N / 2 + 255) / 256, n), dim3(256), 0, s, a, b, c->d_fft_tw,
+                           c->log_n, ls);
+        std::swap(a, b);
+    }
+    hipLaunchKernelGGL(k_encode_finish, dim3((unsigned)N / 256, n), dim3(256), 0, s, a, dst, c->d_mods, c->d_zeta,
+                       level, scale, c->log_n);
+    FL_TRY_HIP(hipGetLastError());
+    return FHELIN_OK;
+}
+
+int pt_encode(Ctx *c, const double *slots, int n_pt, int level, double scale, hipStream_t s, PtSet **out) {
+    FL_CHECK(c && slots && out, FHELIN_E_INVALID_ARG, "pt_encode: null argument");
+    FL_CHECK(scale > 0 && scale < 0x1p62, FHELIN_E_INVALID_ARG, "pt_encode: scale out of range");
+    PtSet *p;
+    FL_RET(ptset_new(c, n_pt, level, &p));
+    const int64_t N = c->N;
+    int rc = FHELIN_OK;
+    for (int p0 = 0; p0 < n_pt && rc == FHELIN_OK; p0 += 64) {
+        const int n = std::min(64, n_pt - p0);
+        rc = encode_into(c, slots + (int64_t)p0 * (N / 2), n, level, scale, p->data + (int64_t)p0 * level * N, s);
+    }
+    if (rc == FHELIN_OK) rc = pt_to_internal(c, p, s);
+    if (rc) {
+        ptset_free(p);
+        return rc;
+    }
+    *out = p;
+    return FHELIN_OK;
+}
+
+int plan_encode_weights(Ctx *c, const Plan *pl, const double *W, const int32_t *perm_out, const int32_t *perm_in,
+                        int level, double scale, hipStream_t s, PtSet **out) {
+    FL_CHECK(c && pl && W && out, FHELIN_E_INVALID_ARG, "encode_weights: null argument");
+    FL_CHECK(scale > 0 && scale < 0x1p62, FHELIN_E_INVALID_ARG, "encode_weights: scale out of range");
+    const int S = c->N / 2, n_pt = pl->n_pt();
+    const int64_t N = c->N;
+    const int chunk = std::min(n_pt, 64);
+    double *slots = nullptr;
+    FL_RET(dev_alloc(c, (void **)&slots, (size_t)chunk * S * sizeof(double)));
+    PtSet *p = nullptr;
+    int rc = ptset_new(c, n_pt, level, &p);
+    const fhelin_layer_desc &d = pl->desc;
+    for (int p0 = 0; p0 < n_pt && rc == FHELIN_OK; p0 += chunk) {
+        const int n = std::min(chunk, n_pt - p0);
+        if (pl->kind == FHELIN_LAYER_FC)
+            hipLaunchKernelGGL(k_diag_fc, dim3((S + 255) / 256, n), dim3(256), 0, s, W, perm_out, perm_in, d.fc_out,
+                               d.fc_in, d.fc_n, d.n1, S, p0, slots);
+        else
+            hipLaunchKernelGGL(k_diag_conv, dim3((S + 255) / 256, n), dim3(256), 0, s, W, perm_out, perm_in, d.c_out,
+                               d.c_in, d.h, d.w, d.k, pl->n_in, S, p0, slots);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) rc = set_error(FHELIN_E_HIP, std::string("encode_weights: ") + hipGetErrorString(e));
+        if (rc == FHELIN_OK) rc = encode_into(c, slots, n, level, scale, p->data + (int64_t)p0 * level * N, s);
+    }
+    if (rc == FHELIN_OK) rc = pt_to_internal(c, p, s);
+    (void)hipStreamSynchronize(s);  // the slot buffer is read by queued kernels
+    dev_free(c, slots, (size_t)chunk * S * sizeof(double));
+    if (rc) {
+        ptset_free(p);
+        return rc;
+    }
+    *out = p;
+    return FHELIN_OK;
+}
+
+}  // namespace fl

@@ -1,0 +1,294 @@
+// keyswitch.hip -- hybrid key switching pieces (hot-path rows a5, a6, a8).
+//
+//   ModUp      digit j of a level-l polynomial (coefficient domain) is extended to
+//              every other modulus of B_l = {q_0..q_{l-1}, p_0..p_{K-1}} by the
+//              centred fast base conversion: v_i = [x_i (Q_j/q_i)^-1]_{q_i} in
+//              (-q_i/2, q_i/2], y_r = sum_i v_i (Q_j/q_i) mod r (Bajard et al. 2016).
+//   inner      u_p = sum_j sigma_g(y_j) * evk_g[j].p over B_l in the NTT domain; the
+//              automorphism is an index permutation there (hoisting: one ModUp
+//              serves every rotation of the same ciphertext; Halevi-Shoup 2018).
+//   ModDown    (u_p - conv_{P->q}(u_p)) * P^-1 mod q_i, centred conversion.
+//   rescale    c'_i = (c_i - [c]_{q_{l-1}} centred) * q_{l-1}^-1 (coefficient domain).
+//
+// Layout of per-entry workspace buffers (slot = modulus index):
+//   digits [dnum][L+K][N], u [2][L+K][N], md [2][L][N] (stride L), cts [2][stride][N].
+// Every kernel maps one thread to one coefficient; grid.z is the batch entry.
+#include "internal.h"
+#include "modarith.h"
+
+namespace fl {
+
+// automorphism X -> X^g as a permutation of the bit-reversed NTT order:
+// slot k holds a(psi^(2 brv(k) + 1)); sigma_g(a) at slot k is a at the slot of exponent
+// (2 brv(k) + 1) g mod 2N.
+__device__ __forceinline__ int auto_index(int k, uint32_t g, int log_n) {
+    uint32_t b = __builtin_bitreverse32((uint32_t)k) >> (32 - log_n);
+    uint32_t e = ((2u * b + 1u) * g) & ((2u << log_n) - 1u);
+    return (int)(__builtin_bitreverse32((e - 1u) >> 1) >> (32 - log_n));
+}
+
+// ---------------------------------------------------------------------------
+// ModUp: grid (N/256, beta_max, n)
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_modup(Batch b, const ModConst *__restrict__ mods,
+                                               const ModUpTab *__restrict__ tabs, const uint64_t *__restrict__ coef,
+                                               int64_t coef_es, const uint64_t *__restrict__ ntt, int64_t ntt_es,
+                                               uint64_t *__restrict__ digits, int64_t digits_es, int log_n, int L,
+                                               int K, int alpha, int dnum) {
+    const int t = blockIdx.z, j = blockIdx.y;
+    const int l = b.level[t];
+    const int beta = (l + alpha - 1) / alpha;
+    if (j >= beta) return;
+    const int64_t N = (int64_t)1 << log_n;
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    const ModUpTab &tab = tabs[(l - 1) * dnum + j];
+    const int lo = tab.lo, cnt = tab.cnt;
+    const uint64_t *x = coef + t * coef_es;
+    const uint64_t *xn = ntt + t * ntt_es;
+    uint64_t *y = digits + t * digits_es + (int64_t)j * (L + K) * N;
+    uint64_t v[MAX_ALPHA];
+    uint64_t nneg = 0;
+#pragma unroll
+    for (int a = 0; a < MAX_ALPHA; ++a) {
+        if (a < cnt) {
+            const ModConst mc = mods[lo + a];
+            uint64_t w = shoup(x[(int64_t)(lo + a) * N + k], tab.inv_hat[a], tab.inv_hat_sh[a], mc.q);
+            v[a] = w;
+            nneg += w > mc.half ? 1 : 0;
+            y[(int64_t)(lo + a) * N + k] = xn[(int64_t)(lo + a) * N + k];
+        }
+    }
+    for (int e = 0; e < l + K; ++e) {
+        if (e >= lo && e < lo + cnt) continue;
+        const int slot = e < l ? e : L + (e - l);
+        const ModConst mc = mods[slot];
+        Acc128 acc{0, 0};
+#pragma unroll
+        for (int a = 0; a < MAX_ALPHA; ++a)
+            if (a < cnt) mac128(acc, v[a], tab.hat_mont[a][slot]);
+        uint64_t r = redc(acc, mc.q, mc.mont_neg_inv);
+        if (nneg) r = sub_mod(r, mont_mul(nneg, tab.qj_mont[slot], mc.q, mc.mont_neg_inv), mc.q);
+        y[(int64_t)slot * N + k] = r;
+    }
+}
+
+int launch_modup(const Ctx *c, const Batch &b, const uint64_t *coef, int64_t coef_es, const uint64_t *ntt,
+                 int64_t ntt_es, uint64_t *digits, int64_t digits_es, hipStream_t s) {
+    if (b.n == 0) return FHELIN_OK;
+    int lmax = 0;
+    for (int t = 0; t < b.n; ++t) lmax = b.level[t] > lmax ? b.level[t] : lmax;
+    int beta = (lmax + c->alpha - 1) / c->alpha;
+    hipLaunchKernelGGL(k_modup, dim3(c->N / 256, beta, b.n), dim3(256), 0, s, b, c->d_mods, c->d_modup, coef, coef_es,
+                       ntt, ntt_es, digits, digits_es, c->log_n, c->L, c->K, c->alpha, c->dnum);
+    FL_TRY_HIP(hipGetLastError());
+    return FHELIN_OK;
+}
+
+// ---------------------------------------------------------------------------
+// inner product with the evaluation key: grid (N/256, l_max + K, n)
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_ks_inner(Batch b, const ModConst *__restrict__ mods,
+                                                  const uint64_t *__restrict__ evk, int64_t key_stride, int key_level,
+                                                  const uint64_t *__restrict__ digits, int64_t digits_es,
+                                                  uint64_t *__restrict__ u, int64_t u_es, int log_n, int L, int K,
+                                                  int alpha) {
+    const int t = blockIdx.z, e = blockIdx.y;
+    const int l = b.level[t];
+    if (e >= l + K) return;
+    const int64_t N = (int64_t)1 << log_n;
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    const int slot = e < l ? e : L + (e - l);
+    const int kp = e < l ? e : key_level + (e - l);
+    const int beta = (l + alpha - 1) / alpha;
+    const ModConst mc = mods[slot];
+    const int src = auto_index(k, b.g[t], log_n);
+    const uint64_t *key = evk + (int64_t)b.key[t] * key_stride;
+    const uint64_t *d = digits + t * digits_es + (int64_t)slot * N + src;
+    const int64_t kpart = (int64_t)(key_level + K) * N;
+    const uint64_t *kb = key + (int64_t)kp * N + k;
+    Acc128 a0{0, 0}, a1{0, 0};
+    uint64_t r0 = 0, r1 = 0;
+    for (int j = 0; j < beta; ++j) {
+        uint64_t dv = d[(int64_t)j * (L + K) * N];
+        mac128(a0, dv, kb[(2 * j) * kpart]);
+        mac128(a1, dv, kb[(2 * j + 1) * kpart]);
+        if ((j & 15) == 15) {  // keep the Montgomery input below q 2^64 (q < 2^60)
+            r0 = add_mod(r0, redc(a0, mc.q, mc.mont_neg_inv), mc.q);
+            r1 = add_mod(r1, redc(a1, mc.q, mc.mont_neg_inv), mc.q);
+            a0 = Acc128{0, 0};
+            a1 = Acc128{0, 0};
+        }
+    }
+    r0 = add_mod(r0, redc(a0, mc.q, mc.mont_neg_inv), mc.q);
+    r1 = add_mod(r1, redc(a1, mc.q, mc.mont_neg_inv), mc.q);
+    uint64_t *ut = u + t * u_es;
+    ut[(int64_t)slot * N + k] = r0;
+    ut[((int64_t)(L + K) + slot) * N + k] = r1;
+}
+
+int launch_ks_inner(const Ctx *c, const Batch &b, const KeySet *ks, const uint64_t *digits, int64_t digits_es,
+                    uint64_t *u, int64_t u_es, hipStream_t s) {
+    if (b.n == 0) return FHELIN_OK;
+    int lmax = 0;
+    for (int t = 0; t < b.n; ++t) lmax = b.level[t] > lmax ? b.level[t] : lmax;
+    hipLaunchKernelGGL(k_ks_inner, dim3(c->N / 256, lmax + c->K, b.n), dim3(256), 0, s, b, c->d_mods, ks->evk,
+                       ks->key_stride(), ks->level, digits, digits_es, u, u_es, c->log_n, c->L, c->K, c->alpha);
+    FL_TRY_HIP(hipGetLastError());
+    return FHELIN_OK;
+}
+
+// ---------------------------------------------------------------------------
+// ModDown base conversion P -> q_i: grid (N/256, 2, n); u P-slots in coefficient domain
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_moddown_fbc(Batch b, const ModConst *__restrict__ mods,
+                                                     const ModDownTab *__restrict__ tab,
+                                                     const uint64_t *__restrict__ u, int64_t u_es,
+                                                     uint64_t *__restrict__ md, int64_t md_es, int log_n, int L,
+                                                     int K) {
+    const int t = blockIdx.z, p = blockIdx.y;
+    const int l = b.level[t];
+    const int64_t N = (int64_t)1 << log_n;
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    const uint64_t *up = u + t * u_es + (int64_t)p * (L + K) * N;
+    uint64_t *out = md + t * md_es + (int64_t)p * L * N;
+    uint64_t v[MAX_P];
+    uint64_t nneg = 0;
+#pragma unroll
+    for (int a = 0; a < MAX_P; ++a) {
+        if (a < K) {
+            const ModConst mc = mods[L + a];
+            uint64_t w = shoup(up[(int64_t)(L + a) * N + k], tab->inv_hat[a], tab->inv_hat_sh[a], mc.q);
+            v[a] = w;
+            nneg += w > mc.half ? 1 : 0;
+        }
+    }
+    for (int i = 0; i < l; ++i) {
+        const ModConst mc = mods[i];
+        Acc128 acc{0, 0};
+#pragma unroll
+        for (int a = 0; a < MAX_P; ++a)
+            if (a < K) mac128(acc, v[a], tab->hat_mont[a][i]);
+        uint64_t r = redc(acc, mc.q, mc.mont_neg_inv);
+        if (nneg) r = sub_mod(r, mont_mul(nneg, tab->p_mont[i], mc.q, mc.mont_neg_inv), mc.q);
+        out[(int64_t)i * N + k] = r;
+    }
+}
+
+int launch_moddown_fbc(const Ctx *c, const Batch &b, const uint64_t *u, int64_t u_es, uint64_t *md, int64_t md_es,
+                       hipStream_t s) {
+    if (b.n == 0) return FHELIN_OK;
+    hipLaunchKernelGGL(k_moddown_fbc, dim3(c->N / 256, 2, b.n), dim3(256), 0, s, b, c->d_mods, c->d_moddown, u, u_es,
+                       md, md_es, c->log_n, c->L, c->K);
+    FL_TRY_HIP(hipGetLastError());
+    return FHELIN_OK;
+}
+
+// ---------------------------------------------------------------------------
+// ModDown combine (NTT domain): grid (N/256, 2*l_max, n)
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_moddown_combine(Batch b, const ModConst *__restrict__ mods,
+                                                         const ModDownTab *__restrict__ tab,
+                                                         const uint64_t *__restrict__ u, int64_t u_es,
+                                                         const uint64_t *__restrict__ md, int64_t md_es,
+                                                         uint64_t *__restrict__ dst, int64_t dst_es, int dst_stride,
+                                                         const uint64_t *__restrict__ c0, int64_t c0_es,
+                                                         int c0_stride, int accumulate, int log_n, int L, int K) {
+    const int t = blockIdx.z;
+    const int l = b.level[t];
+    const int r = blockIdx.y;
+    if (r >= 2 * l) return;
+    const int p = r / l, i = r % l;
+    const int64_t N = (int64_t)1 << log_n;
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    const ModConst mc = mods[i];
+    uint64_t x = u[t * u_es + ((int64_t)p * (L + K) + i) * N + k];
+    uint64_t y = md[t * md_es + ((int64_t)p * L + i) * N + k];
+    uint64_t v = shoup(sub_mod(x, y, mc.q), tab->pinv[i], tab->pinv_sh[i], mc.q);
+    if (p == 0 && c0) v = add_mod(v, c0[t * c0_es + (int64_t)i * N + auto_index(k, b.g[t], log_n)], mc.q);
+    uint64_t *o = dst + t * dst_es + ((int64_t)p * dst_stride + i) * N + k;
+    if (accumulate) v = add_mod(v, *o, mc.q);
+    *o = v;
+}
+
+int launch_moddown_combine(const Ctx *c, const Batch &b, const uint64_t *u, int64_t u_es, const uint64_t *md,
+                           int64_t md_es, uint64_t *dst, int64_t dst_es, int dst_stride, const uint64_t *c0,
+                           int64_t c0_es, int c0_stride, int accumulate, hipStream_t s) {
+    if (b.n == 0) return FHELIN_OK;
+    int lmax = 0;
+    for (int t = 0; t < b.n; ++t) lmax = b.level[t] > lmax ? b.level[t] : lmax;
+    hipLaunchKernelGGL(k_moddown_combine, dim3(c->N / 256, 2 * lmax, b.n), dim3(256), 0, s, b, c->d_mods,
+                       c->d_moddown, u, u_es, md, md_es, dst, dst_es, dst_stride, c0, c0_es, c0_stride, accumulate,
+                       c->log_n, c->L, c->K);
+    FL_TRY_HIP(hipGetLastError());
+    return FHELIN_OK;
+}
+
+// ---------------------------------------------------------------------------
+// rescale (coefficient domain): grid (N/256, 2*(l_max-1), n)
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_rescale(Batch b, const ModConst *__restrict__ mods,
+                                                 const uint64_t *__restrict__ rs_inv,
+                                                 const uint64_t *__restrict__ rs_inv_sh,
+                                                 const uint64_t *__restrict__ in, int64_t in_es, int in_stride,
+                                                 uint64_t *__restrict__ out, int64_t out_es, int out_stride,
+                                                 int log_n, int L) {
+    const int t = blockIdx.z;
+    const int l = b.level[t];
+    const int r = blockIdx.y;
+    if (r >= 2 * (l - 1)) return;
+    const int p = r / (l - 1), i = r % (l - 1);
+    const int64_t N = (int64_t)1 << log_n;
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    const ModConst mt = mods[l - 1], mc = mods[i];
+    const uint64_t *ip = in + t * in_es + (int64_t)p * in_stride * N;
+    uint64_t top = ip[(int64_t)(l - 1) * N + k];
+    uint64_t vi;  // centred top residue, reduced mod q_i
+    if (top <= mt.half) {
+        vi = csub(shoup_lazy(top, 1, mc.one_sh, mc.q), mc.q);
+    } else {
+        uint64_t m = csub(shoup_lazy(mt.q - top, 1, mc.one_sh, mc.q), mc.q);
+        vi = m ? mc.q - m : 0;
+    }
+    uint64_t x = ip[(int64_t)i * N + k];
+    const int64_t ti = (int64_t)(l - 1) * L + i;
+    out[t * out_es + ((int64_t)p * out_stride + i) * N + k] = shoup(sub_mod(x, vi, mc.q), rs_inv[ti], rs_inv_sh[ti], mc.q);
+}
+
+int launch_rescale(const Ctx *c, const Batch &b, const uint64_t *in, int64_t in_es, int in_stride, uint64_t *out,
+                   int64_t out_es, int out_stride, hipStream_t s) {
+    if (b.n == 0) return FHELIN_OK;
+    int lmax = 0;
+    for (int t = 0; t < b.n; ++t) lmax = b.level[t] > lmax ? b.level[t] : lmax;
+    if (lmax < 2) return FHELIN_OK;
+    hipLaunchKernelGGL(k_rescale, dim3(c->N / 256, 2 * (lmax - 1), b.n), dim3(256), 0, s, b, c->d_mods, c->d_rs_inv,
+                       c->d_rs_inv_sh, in, in_es, in_stride, out, out_es, out_stride, c->log_n, c->L);
+    FL_TRY_HIP(hipGetLastError());
+    return FHELIN_OK;
+}
+
+// ---------------------------------------------------------------------------
+// row copy between two row maps of identical shape: grid (N/256 capped, rows, n)
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_copy_rows(RowMap dst, RowMap src) {
+    const int t = blockIdx.z, r = blockIdx.y;
+    if (r >= rowmap_rows(dst, t)) return;
+    int64_t od, os;
+    int md, ms;
+    rowmap_get(dst, t, r, &od, &md);
+    rowmap_get(src, t, r, &os, &ms);
+    const int N = 1 << dst.log_n;
+    const uint64_t *a = src.base + os;
+    uint64_t *o = dst.base + od;
+    for (int e = blockIdx.x * 256 + threadIdx.x; e < N; e += gridDim.x * 256) o[e] = a[e];
+}
+
+int launch_copy_rows(const Ctx *c, const RowMap &dst, const RowMap &src, hipStream_t s) {
+    int rows = rowmap_max_rows(dst);
+    if (rows == 0 || dst.n_ct == 0) return FHELIN_OK;
+    int bx = c->N / 256 < 32 ? c->N / 256 : 32;
+    hipLaunchKernelGGL(k_copy_rows, dim3(bx, rows, dst.n_ct), dim3(256), 0, s, dst, src);
+    FL_TRY_HIP(hipGetLastError());
+    return FHELIN_OK;
+}
+
+}  // namespace fl

@@ -1,0 +1,486 @@
+// linear.hip -- encrypted linear layers: plans, pt x ct multiply-accumulate, and the
+// batched evaluation schedule (hot-path rows a5-a9).
+//
+// A layer is the baby-step / giant-step form
+//     y_o = sum_j rot_{G_j}( sum_i sum_b pt[o][i][j][b] * rot_{r_b}(x_i) ),
+// which covers the Halevi-Shoup diagonal method for FC layers (baby steps b < n1,
+// giant steps n1*j) and multiplexed convolutions (baby = spatial offsets, giant =
+// channel offsets).  The baby rotations of each input share one ModUp (hoisting);
+// each giant rotation is a full key switch.  The paper's server round (Sec. 4.4)
+// folds the unshuffle of the previous round and the shuffle of this round into
+// the plaintexts, so they cost nothing here.
+//
+// Batching: requests are processed in chunks; each kernel of the schedule covers
+// every ciphertext of the chunk at its own level (grid.z = entry), so one
+// evaluation key or plaintext tile is read once per chunk.
+#include <algorithm>
+
+#include "internal.h"
+#include "modarith.h"
+
+namespace fl {
+
+constexpr int MAX_BABY = 64;
+
+// ---------------------------------------------------------------------------
+// plans
+// ---------------------------------------------------------------------------
+static bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+int plan_create(Ctx *c, const fhelin_layer_desc *d, Plan **out) {
+    FL_CHECK(c && d && out, FHELIN_E_INVALID_ARG, "plan_create: null argument");
+    const int S = c->N / 2;
+    std::unique_ptr<Plan> p(new Plan());
+    p->kind = d->kind;
+    p->desc = *d;
+    if (d->kind == FHELIN_LAYER_FC) {
+        FL_CHECK(pow2(d->fc_n) && S % d->fc_n == 0, FHELIN_E_UNSUPPORTED_PARAM, "fc_n must be a power of two dividing N/2");
+        FL_CHECK(d->fc_out >= 1 && d->fc_out <= d->fc_n && d->fc_in >= 1 && d->fc_in <= d->fc_n,
+                 FHELIN_E_INVALID_ARG, "fc_out / fc_in must be in [1, fc_n]");
+        FL_CHECK(pow2(d->n1) && d->fc_n % d->n1 == 0 && d->n1 <= MAX_BABY, FHELIN_E_UNSUPPORTED_PARAM,
+                 "n1 must be a power of two dividing fc_n, at most 64");
+        p->n_in = p->n_out = 1;
+        for (int b = 0; b < d->n1; ++b) p->rb.push_back(b);
+        for (int j = 0; j < d->fc_n / d->n1; ++j) p->gk.push_back(d->n1 * j);
+    } else if (d->kind == FHELIN_LAYER_CONV) {
+        FL_CHECK(d->k == 1 || d->k == 3, FHELIN_E_UNSUPPORTED_PARAM, "conv kernel must be 1 or 3");
+        FL_CHECK(d->c_in >= 1 && d->c_out >= 1 && d->h >= 1 && d->w >= 1, FHELIN_E_INVALID_ARG, "bad conv shape");
+        const int hw = d->h * d->w;
+        FL_CHECK(S % hw == 0, FHELIN_E_UNSUPPORTED_PARAM, "h*w must divide N/2");
+        const int cct = S / hw;
+        p->n_in = (d->c_in + cct - 1) / cct;
+        p->n_out = (d->c_out + cct - 1) / cct;
+        FL_CHECK(p->n_in <= MAX_BATCH && p->n_out <= MAX_BATCH, FHELIN_E_UNSUPPORTED_PARAM, "too many ciphertexts per layer");
+        if (d->k == 1) {
+            p->rb.push_back(0);
+        } else {
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) p->rb.push_back(dy * d->w + dx);
+        }
+        for (int j = 0; j < cct; ++j) p->gk.push_back(j * hw);
+    } else {
+        return set_error(FHELIN_E_INVALID_ARG, "unknown layer kind");
+    }
+    std::vector<uint32_t> gal;
+    for (int r : p->rb)
+        if (galois_of_rotation(r, c->log_n) != 1) gal.push_back(galois_of_rotation(r, c->log_n));
+    for (int r : p->gk)
+        if (galois_of_rotation(r, c->log_n) != 1) gal.push_back(galois_of_rotation(r, c->log_n));
+    std::sort(gal.begin(), gal.end());
+    gal.erase(std::unique(gal.begin(), gal.end()), gal.end());
+    p->galois = gal;
+    *out = p.release();
+    return FHELIN_OK;
+}
+
+// ---------------------------------------------------------------------------
+// pt x ct multiply-accumulate: A[e][j] = sum_i sum_b pt[o][i][j][b] * R[i][b]
+// grid (entries, N/256, l_max): consecutive workgroups share a plaintext tile
+// ---------------------------------------------------------------------------
+struct MacArgs {
+    const uint64_t *x;    // inputs, NTT domain [2][L] per input entry
+    const uint64_t *rb;   // baby rotations [B'][2][L] per input entry
+    const uint64_t *pts;  // [n_pt][pt_level][N], Montgomery form
+    uint64_t *acc;        // [G][2][L] per output entry
+    int n_in, n_out, B, Bp, G, pt_level;
+    int8_t bmap[MAX_BABY];  // baby index -> slot in rb, -1 = identity (use x)
+};
+
+__global__ void __launch_bounds__(256) k_mac(MacArgs a, Batch b, const ModConst *__restrict__ mods, int log_n,
+                                             int L) {
+    const int e = blockIdx.x;
+    const int i = blockIdx.z;
+    const int l = b.level[e];
+    if (i >= l) return;
+    const int64_t N = (int64_t)1 << log_n;
+    const int k = blockIdx.y * 256 + threadIdx.x;
+    const int req = e / a.n_out, o = e % a.n_out;
+    const ModConst mc = mods[i];
+    const int64_t ct = (int64_t)2 * L * N;
+    for (int j = 0; j < a.G; ++j) {
+        Acc128 s0{0, 0}, s1{0, 0};
+        uint64_t r0 = 0, r1 = 0;
+        int cnt = 0;
+        for (int ii = 0; ii < a.n_in; ++ii) {
+            const int64_t xin = (int64_t)req * a.n_in + ii;
+            for (int bb = 0; bb < a.B; ++bb) {
+                const int64_t pidx = ((int64_t)(o * a.n_in + ii) * a.G + j) * a.B + bb;
+                const uint64_t pv = a.pts[(pidx * a.pt_level + i) * N + k];
+                const int m = a.bmap[bb];
+                const uint64_t *src = m < 0 ? a.x + xin * ct : a.rb + (xin * a.Bp + m) * ct;
+                mac128(s0, src[(int64_t)i * N + k], pv);
+                mac128(s1, src[(int64_t)(L + i) * N + k], pv);
+                if (++cnt == 16) {
+                    r0 = add_mod(r0, redc(s0, mc.q, mc.mont_neg_inv), mc.q);
+                    r1 = add_mod(r1, redc(s1, mc.q, mc.mont_neg_inv), mc.q);
+                    s0 = Acc128{0, 0};
+                    s1 = Acc128{0, 0};
+                    cnt = 0;
+                }
+            }
+        }
+        r0 = add_mod(r0, redc(s0, mc.q, mc.mont_neg_inv), mc.q);
+        r1 = add_mod(r1, redc(s1, mc.q, mc.mont_neg_inv), mc.q);
+        uint64_t *dst = a.acc + ((int64_t)e * a.G + j) * ct;
+        dst[(int64_t)i * N + k] = r0;
+        dst[(int64_t)(L + i) * N + k] = r1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// workspace
+// ---------------------------------------------------------------------------
+int workspace_get(Ctx *c, hipStream_t s, size_t bytes, uint64_t **out) {
+    Workspace *w;
+    {
+        std::lock_guard<std::mutex> g(c->mu);
+        auto &slot = c->ws[(void *)s];
+        if (!slot) {
+            slot.reset(new Workspace());
+            slot->ctx = c;
+        }
+        w = slot.get();
+    }
+    if (w->bytes < bytes) {
+        if (w->buf) {
+            FL_TRY_HIP(hipStreamSynchronize(s));
+            dev_free(c, w->buf, w->bytes);
+            w->buf = nullptr;
+            w->bytes = 0;
+        }
+        FL_RET(dev_alloc(c, &w->buf, bytes));
+        w->bytes = bytes;
+    }
+    *out = (uint64_t *)w->buf;
+    return FHELIN_OK;
+}
+
+// ---------------------------------------------------------------------------
+// helpers building row maps
+// ---------------------------------------------------------------------------
+static RowMap rows_ct(const Ctx *c, const Batch &b, uint64_t *base, int64_t es, int stride, int poly_lo,
+                      int poly_cnt) {
+    RowMap m{};
+    m.base = base;
+    m.ct_stride = es;
+    m.kind = ROWS_CT;
+    m.n_ct = b.n;
+    m.stride = stride;
+    m.poly_lo = poly_lo;
+    m.poly_cnt = poly_cnt;
+    m.L = c->L;
+    m.K = c->K;
+    m.alpha = c->alpha;
+    m.log_n = c->log_n;
+    for (int t = 0; t < b.n; ++t) m.level[t] = b.level[t];
+    return m;
+}
+
+static RowMap rows_kind(const Ctx *c, const Batch &b, uint64_t *base, int64_t es, int kind, int n_part) {
+    RowMap m = rows_ct(c, b, base, es, 0, 0, 0);
+    m.kind = kind;
+    m.n_part = n_part;
+    return m;
+}
+
+// One full key switch of the batch entries: given c1 (NTT, ct layout) and the
+// automorphism/key per entry in `b`, accumulate (sigma_g(c0) + out0, out1) into dst.
+struct KsScratch {
+    uint64_t *tc;  int64_t tc_es;   // [L] coefficient temp
+    uint64_t *dg;  int64_t dg_es;   // [dnum][L+K] digits
+    uint64_t *u;   int64_t u_es;    // [2][L+K]
+    uint64_t *md;  int64_t md_es;   // [2][L]
+};
+
+// ModUp of the c1 polynomial of ct entries (NTT domain in, digits NTT domain out)
+static int modup_ct(const Ctx *c, const Batch &b, const uint64_t *ct, int64_t ct_es, int ct_stride,
+                    const KsScratch &w, hipStream_t s) {
+    const int64_t N = c->N;
+    RowMap src = rows_ct(c, b, (uint64_t *)ct, ct_es, ct_stride, 1, 1);
+    RowMap dst = rows_ct(c, b, w.tc, w.tc_es, c->L, 0, 1);
+    FL_RET(launch_copy_rows(c, dst, src, s));
+    FL_RET(launch_ntt(c, dst, 1, s));
+    FL_RET(launch_modup(c, b, w.tc, w.tc_es, ct + (int64_t)ct_stride * N, ct_es, w.dg, w.dg_es, s));
+    FL_RET(launch_ntt(c, rows_kind(c, b, w.dg, w.dg_es, ROWS_MODUP, 0), 0, s));
+    return FHELIN_OK;
+}
+
+// inner product + ModDown + combine, digits already in w.dg
+static int ks_finish(const Ctx *c, const Batch &b, const KeySet *ks, const KsScratch &w, uint64_t *dst,
+                     int64_t dst_es, int dst_stride, const uint64_t *c0, int64_t c0_es, int c0_stride, int accumulate,
+                     hipStream_t s) {
+    FL_RET(launch_ks_inner(c, b, ks, w.dg, w.dg_es, w.u, w.u_es, s));
+    FL_RET(launch_ntt(c, rows_kind(c, b, w.u, w.u_es, ROWS_EXT_P, 2), 1, s));
+    FL_RET(launch_moddown_fbc(c, b, w.u, w.u_es, w.md, w.md_es, s));
+    FL_RET(launch_ntt(c, rows_ct(c, b, w.md, w.md_es, c->L, 0, 2), 0, s));
+    FL_RET(launch_moddown_combine(c, b, w.u, w.u_es, w.md, w.md_es, dst, dst_es, dst_stride, c0, c0_es, c0_stride,
+                                  accumulate, s));
+    return FHELIN_OK;
+}
+
+static int check_batch(const Ctx *c, const fhelin_ct_batch *bt, const char *what) {
+    FL_CHECK(bt && bt->data && bt->levels && bt->n_ct >= 0, FHELIN_E_INVALID_ARG, std::string(what) + ": null batch");
+    FL_CHECK(bt->stride >= 1 && bt->stride <= c->L, FHELIN_E_INVALID_ARG, std::string(what) + ": stride out of range");
+    for (int t = 0; t < bt->n_ct; ++t)
+        FL_CHECK(bt->levels[t] >= 1 && bt->levels[t] <= bt->stride, FHELIN_E_LEVEL_MISMATCH,
+                 std::string(what) + ": level out of range");
+    return FHELIN_OK;
+}
+
+// ---------------------------------------------------------------------------
+// linear layer over a batch of requests
+// ---------------------------------------------------------------------------
+static size_t limbs_per_request(const Ctx *c, const Plan *p, int Bp) {
+    const size_t L = c->L, K = c->K, D = c->dnum;
+    const size_t ni = p->n_in, no = p->n_out, G = p->gk.size();
+    const size_t emax = std::max(ni, no);
+    return ni * 2 * L             // X
+           + ni * D * (L + K)      // hoisted digits
+           + ni * Bp * 2 * L       // baby rotations
+           + no * G * 2 * L        // accumulators
+           + no * 2 * L            // Y
+           + emax * L              // coefficient temp
+           + emax * D * (L + K)    // giant digits
+           + emax * 2 * (L + K)    // u
+           + emax * 2 * L;         // md
+}
+
+int linear_apply(Ctx *c, const Plan *p, const KeySet *ks, const PtSet *pts, const fhelin_ct_batch *in,
+                 const fhelin_ct_batch *out, int flags, hipStream_t s, int max_chunk) {
+    FL_CHECK(c && p && pts && in && out, FHELIN_E_INVALID_ARG, "linear_apply: null argument");
+    FL_RET(check_batch(c, in, "linear_apply input"));
+    FL_RET(check_batch(c, out, "linear_apply output"));
+    FL_CHECK(in->n_ct % p->n_in == 0, FHELIN_E_INVALID_ARG, "input count is not a multiple of the plan's n_in");
+    const int R = in->n_ct / p->n_in;
+    FL_CHECK(out->n_ct == R * p->n_out, FHELIN_E_INVALID_ARG, "output count must be requests * n_out");
+    FL_CHECK(pts->n_pt == p->n_pt(), FHELIN_E_INVALID_ARG, "plaintext set does not match the plan");
+    const bool rescale = flags & FHELIN_APPLY_RESCALE;
+    for (int r = 0; r < R; ++r) {
+        int l = in->levels[r * p->n_in];
+        for (int i = 1; i < p->n_in; ++i)
+            FL_CHECK(in->levels[r * p->n_in + i] == l, FHELIN_E_LEVEL_MISMATCH, "inputs of a request differ in level");
+        FL_CHECK(l <= pts->level, FHELIN_E_LEVEL_MISMATCH, "plaintexts encoded below the request level");
+        FL_CHECK(!rescale || l >= 2, FHELIN_E_LEVEL_MISMATCH, "rescale needs level >= 2");
+        for (int o = 0; o < p->n_out; ++o)
+            FL_CHECK(out->levels[r * p->n_out + o] == (rescale ? l - 1 : l), FHELIN_E_LEVEL_MISMATCH,
+                     "output levels must equal the input level (minus one when rescaling)");
+        if (!p->galois.empty()) {
+            FL_CHECK(ks != nullptr, FHELIN_E_MISSING_GALOIS_KEY, "layer needs Galois keys");
+            FL_CHECK(l <= ks->level, FHELIN_E_LEVEL_MISMATCH, "keys loaded below the request level");
+        }
+    }
+    for (uint32_t g : p->galois)
+        FL_CHECK(ks->find(g) >= 0, FHELIN_E_MISSING_GALOIS_KEY, "keyset lacks Galois element " + std::to_string(g));
+    if (R == 0) return FHELIN_OK;
+
+    const int64_t N = c->N, L = c->L, K = c->K;
+    const int B = (int)p->rb.size(), G = (int)p->gk.size();
+    MacArgs ma{};
+    int Bp = 0;
+    for (int b = 0; b < B; ++b) ma.bmap[b] = galois_of_rotation(p->rb[b], c->log_n) == 1 ? -1 : Bp++;
+    int chunk = std::max(1, std::min(max_chunk, MAX_BATCH / std::max(p->n_in, p->n_out)));
+    chunk = std::min(chunk, R);
+    uint64_t *ws;
+    FL_RET(workspace_get(c, s, limbs_per_request(c, p, Bp) * chunk * N * sizeof(uint64_t), &ws));
+
+    const int64_t ct = 2 * L * N, dg = (int64_t)c->dnum * (L + K) * N;
+    for (int r0 = 0; r0 < R; r0 += chunk) {
+        const int Rc = std::min(chunk, R - r0);
+        const int Ein = Rc * p->n_in, Eout = Rc * p->n_out, Emax = std::max(Ein, Eout);
+        // carve the workspace
+        uint64_t *X = ws, *D = X + Ein * ct, *RB = D + Ein * dg, *A = RB + (int64_t)Ein * Bp * ct;
+        uint64_t *Y = A + (int64_t)Eout * G * ct, *TC = Y + Eout * ct, *DG = TC + Emax * L * N;
+        uint64_t *U = DG + Emax * dg, *MD = U + Emax * 2 * (L + K) * N;
+        Batch bin{}, bout{};
+        bin.n = Ein;
+        bout.n = Eout;
+        for (int e = 0; e < Ein; ++e) {
+            bin.level[e] = (uint8_t)in->levels[(r0 * p->n_in) + e];
+            bin.g[e] = 1;
+        }
+        for (int e = 0; e < Eout; ++e) {
+            bout.level[e] = (uint8_t)in->levels[(r0 + e / p->n_out) * p->n_in];
+            bout.g[e] = 1;
+        }
+        KsScratch w{TC, L * N, DG, dg, U, 2 * (L + K) * N, MD, 2 * L * N};
+        // 1. import inputs to the NTT domain
+        const int64_t in_es = (int64_t)2 * in->stride * N;
+        RowMap src = rows_ct(c, bin, in->data + (int64_t)r0 * p->n_in * in_es, in_es, in->stride, 0, 2);
+        RowMap dx = rows_ct(c, bin, X, ct, (int)L, 0, 2);
+        FL_RET(launch_copy_rows(c, dx, src, s));
+        FL_RET(launch_ntt(c, dx, 0, s));
+        // 2-3. hoisted ModUp and baby rotations
+        if (Bp > 0) {
+            KsScratch wb = w;
+            wb.dg = D;
+            FL_RET(modup_ct(c, bin, X, ct, (int)L, wb, s));
+            for (int b = 0; b < B; ++b) {
+                if (ma.bmap[b] < 0) continue;
+                uint32_t g = galois_of_rotation(p->rb[b], c->log_n);
+                int key = ks->find(g);
+                for (int e = 0; e < Ein; ++e) {
+                    bin.g[e] = g;
+                    bin.key[e] = (int16_t)key;
+                }
+                FL_RET(ks_finish(c, bin, ks, wb, RB + ma.bmap[b] * ct, (int64_t)Bp * ct, (int)L, X, ct, (int)L, 0, s));
+            }
+            for (int e = 0; e < Ein; ++e) bin.g[e] = 1;
+        }
+        // 4. multiply-accumulate
+        ma.x = X;
+        ma.rb = RB;
+        ma.pts = pts->data;
+        ma.acc = A;
+        ma.n_in = p->n_in;
+        ma.n_out = p->n_out;
+        ma.B = B;
+        ma.Bp = Bp;
+        ma.G = G;
+        ma.pt_level = pts->level;
+        {
+            int lmax = 0;
+            for (int e = 0; e < Eout; ++e) lmax = std::max<int>(lmax, bout.level[e]);
+            hipLaunchKernelGGL(k_mac, dim3(Eout, c->N / 256, lmax), dim3(256), 0, s, ma, bout, c->d_mods, c->log_n,
+                               c->L);
+            FL_TRY_HIP(hipGetLastError());
+        }
+        // 5. giant steps, summed into Y
+        bool first = true;
+        for (int j = 0; j < G; ++j) {
+            if (galois_of_rotation(p->gk[j], c->log_n) != 1) continue;
+            RowMap ys = rows_ct(c, bout, A + j * ct, (int64_t)G * ct, (int)L, 0, 2);
+            RowMap yd = rows_ct(c, bout, Y, ct, (int)L, 0, 2);
+            FL_RET(launch_copy_rows(c, yd, ys, s));
+            first = false;
+            break;
+        }
+        for (int j = 0; j < G; ++j) {
+            uint32_t g = galois_of_rotation(p->gk[j], c->log_n);
+            if (g == 1) continue;
+            int key = ks->find(g);
+            for (int e = 0; e < Eout; ++e) {
+                bout.g[e] = g;
+                bout.key[e] = (int16_t)key;
+            }
+            uint64_t *Aj = A + j * ct;
+            FL_RET(modup_ct(c, bout, Aj, (int64_t)G * ct, (int)L, w, s));
+            FL_RET(ks_finish(c, bout, ks, w, Y, ct, (int)L, Aj, (int64_t)G * ct, (int)L, first ? 0 : 1, s));
+            first = false;
+        }
+        for (int e = 0; e < Eout; ++e) bout.g[e] = 1;
+        // 6. export (and rescale) in the coefficient domain
+        RowMap yr = rows_ct(c, bout, Y, ct, (int)L, 0, 2);
+        FL_RET(launch_ntt(c, yr, 1, s));
+        const int64_t out_es = (int64_t)2 * out->stride * N;
+        uint64_t *ob = out->data + (int64_t)r0 * p->n_out * out_es;
+        if (rescale) {
+            FL_RET(launch_rescale(c, bout, Y, ct, (int)L, ob, out_es, out->stride, s));
+        } else {
+            FL_RET(launch_copy_rows(c, rows_ct(c, bout, ob, out_es, out->stride, 0, 2), yr, s));
+        }
+    }
+    return FHELIN_OK;
+}
+
+// ---------------------------------------------------------------------------
+// rotation of every ciphertext of a batch (one key switch each)
+// ---------------------------------------------------------------------------
+int rotate_batch(Ctx *c, const KeySet *ks, const fhelin_ct_batch *in, const int32_t *steps, const fhelin_ct_batch *out,
+                 hipStream_t s) {
+    FL_CHECK(c && in && out && steps, FHELIN_E_INVALID_ARG, "rotate: null argument");
+    FL_RET(check_batch(c, in, "rotate input"));
+    FL_RET(check_batch(c, out, "rotate output"));
+    FL_CHECK(in->n_ct == out->n_ct, FHELIN_E_INVALID_ARG, "rotate: batch sizes differ");
+    for (int t = 0; t < in->n_ct; ++t) {
+        FL_CHECK(in->levels[t] == out->levels[t], FHELIN_E_LEVEL_MISMATCH, "rotate: levels differ");
+        uint32_t g = galois_of_rotation(steps[t], c->log_n);
+        if (g == 1) continue;
+        FL_CHECK(ks != nullptr && ks->find(g) >= 0, FHELIN_E_MISSING_GALOIS_KEY,
+                 "keyset lacks Galois element " + std::to_string(g));
+        FL_CHECK(in->levels[t] <= ks->level, FHELIN_E_LEVEL_MISMATCH, "keys loaded below the ciphertext level");
+    }
+    const int64_t N = c->N, L = c->L, K = c->K;
+    const int64_t ct = 2 * L * N, dg = (int64_t)c->dnum * (L + K) * N;
+    const int64_t per = ct * 2 + L * N + dg + 2 * (L + K) * N + 2 * L * N;
+    const int chunk = std::min(in->n_ct, MAX_BATCH);
+    if (chunk == 0) return FHELIN_OK;
+    uint64_t *ws;
+    FL_RET(workspace_get(c, s, (size_t)per * chunk * sizeof(uint64_t), &ws));
+    const int64_t in_es = (int64_t)2 * in->stride * N, out_es = (int64_t)2 * out->stride * N;
+    for (int t0 = 0; t0 < in->n_ct; t0 += chunk) {
+        const int n = std::min(chunk, in->n_ct - t0);
+        uint64_t *X = ws, *Y = X + n * ct, *TC = Y + n * ct, *DG = TC + n * L * N, *U = DG + n * dg;
+        uint64_t *MD = U + n * 2 * (L + K) * N;
+        // entries that really rotate
+        Batch b{};
+        std::vector<int> idx;
+        for (int t = 0; t < n; ++t) {
+            uint32_t g = galois_of_rotation(steps[t0 + t], c->log_n);
+            if (g == 1) {  // identity: plain copy
+                Batch one{};
+                one.n = 1;
+                one.level[0] = (uint8_t)in->levels[t0 + t];
+                FL_RET(launch_copy_rows(c, rows_ct(c, one, out->data + (t0 + t) * out_es, out_es, out->stride, 0, 2),
+                                        rows_ct(c, one, in->data + (t0 + t) * in_es, in_es, in->stride, 0, 2), s));
+                continue;
+            }
+            b.level[b.n] = (uint8_t)in->levels[t0 + t];
+            b.g[b.n] = g;
+            b.key[b.n] = (int16_t)ks->find(g);
+            idx.push_back(t0 + t);
+            ++b.n;
+        }
+        if (b.n == 0) continue;
+        // gather inputs (entries may be non-contiguous after skipping identities)
+        for (int e = 0; e < b.n; ++e) {
+            Batch one{};
+            one.n = 1;
+            one.level[0] = b.level[e];
+            FL_RET(launch_copy_rows(c, rows_ct(c, one, X + e * ct, ct, (int)L, 0, 2),
+                                    rows_ct(c, one, in->data + idx[e] * in_es, in_es, in->stride, 0, 2), s));
+        }
+        FL_RET(launch_ntt(c, rows_ct(c, b, X, ct, (int)L, 0, 2), 0, s));
+        KsScratch w{TC, L * N, DG, dg, U, 2 * (L + K) * N, MD, 2 * L * N};
+        FL_RET(modup_ct(c, b, X, ct, (int)L, w, s));
+        FL_RET(ks_finish(c, b, ks, w, Y, ct, (int)L, X, ct, (int)L, 0, s));
+        FL_RET(launch_ntt(c, rows_ct(c, b, Y, ct, (int)L, 0, 2), 1, s));
+        for (int e = 0; e < b.n; ++e) {
+            Batch one{};
+            one.n = 1;
+            one.level[0] = b.level[e];
+            FL_RET(launch_copy_rows(c, rows_ct(c, one, out->data + idx[e] * out_es, out_es, out->stride, 0, 2),
+                                    rows_ct(c, one, Y + e * ct, ct, (int)L, 0, 2), s));
+        }
+    }
+    return FHELIN_OK;
+}
+
+// ---------------------------------------------------------------------------
+// standalone rescale of a coefficient-domain batch
+// ---------------------------------------------------------------------------
+int rescale_batch(Ctx *c, const fhelin_ct_batch *in, const fhelin_ct_batch *out, hipStream_t s) {
+    FL_CHECK(c && in && out, FHELIN_E_INVALID_ARG, "rescale: null argument");
+    FL_RET(check_batch(c, in, "rescale input"));
+    FL_RET(check_batch(c, out, "rescale output"));
+    FL_CHECK(in->n_ct == out->n_ct, FHELIN_E_INVALID_ARG, "rescale: batch sizes differ");
+    if (in->data == out->data)
+        FL_CHECK(in->stride == out->stride, FHELIN_E_INVALID_ARG, "rescale: in-place needs equal strides");
+    for (int t = 0; t < in->n_ct; ++t) {
+        FL_CHECK(in->levels[t] >= 2, FHELIN_E_LEVEL_MISMATCH, "rescale needs level >= 2");
+        FL_CHECK(out->levels[t] == in->levels[t] - 1, FHELIN_E_LEVEL_MISMATCH, "rescale: output level must be input - 1");
+    }
+    const int64_t N = c->N;
+    const int64_t in_es = (int64_t)2 * in->stride * N, out_es = (int64_t)2 * out->stride * N;
+    for (int t0 = 0; t0 < in->n_ct; t0 += MAX_BATCH) {
+        Batch b{};
+        b.n = std::min(MAX_BATCH, in->n_ct - t0);
+        for (int e = 0; e < b.n; ++e) b.level[e] = (uint8_t)in->levels[t0 + e];
+        // in place is safe: limb i < l-1 of entry t reads limb i and limb l-1 of the same
+        // entry; limb l-1 is never written.
+        FL_RET(launch_rescale(c, b, in->data + t0 * in_es, in_es, in->stride, out->data + t0 * out_es, out_es,
+                              out->stride, s));
+    }
+    return FHELIN_OK;
+}
+
+}  // namespace fl

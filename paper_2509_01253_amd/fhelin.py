@@ -1,0 +1,302 @@
+"""Python binding of the fhelin C ABI (``include/fhelin.h``).
+
+Argument marshalling only: every step of the encrypted path runs in the HIP
+kernels of ``libfhelin.so``.  PyTorch provides device memory (tensors) and
+streams; ``torch`` is imported before the library is loaded so both share one
+HIP runtime.  Functions carry the C names; handles are opaque ``c_void_p``.
+A non-zero status raises :class:`FhelinError`.  If the library has not been
+built the import fails: there is no fallback.
+
+Ciphertext batches are 8-byte integer tensors (int64 or uint64) on the GPU
+shaped ``[n_ct][2][stride][N]`` (coefficient domain), with a host list of
+levels.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # noqa: F401  (must precede the library: shared HIP runtime)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfhelin.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2509_01253_amd.build`")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+_i32, _u32, _u64, _dbl, _vp = ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double, ctypes.c_void_p
+_pvp = ctypes.POINTER(ctypes.c_void_p)
+
+FHELIN_LAYER_FC = 1
+FHELIN_LAYER_CONV = 2
+FHELIN_APPLY_RESCALE = 1
+
+STATUS = {
+    0: "FHELIN_OK", -1: "FHELIN_E_INVALID_ARG", -2: "FHELIN_E_UNSUPPORTED_PARAM", -3: "FHELIN_E_LEVEL_MISMATCH",
+    -4: "FHELIN_E_MISSING_GALOIS_KEY", -5: "FHELIN_E_OOM", -6: "FHELIN_E_BUDGET", -7: "FHELIN_E_HIP",
+    -8: "FHELIN_E_UNIMPLEMENTED",
+}
+
+
+class fhelin_params(ctypes.Structure):
+    _fields_ = [("log_n", _i32), ("n_q", _i32), ("n_p", _i32), ("dnum", _i32),
+                ("q", ctypes.POINTER(_u64)), ("p", ctypes.POINTER(_u64))]
+
+
+class fhelin_layer_desc(ctypes.Structure):
+    _fields_ = [("kind", _i32), ("fc_n", _i32), ("fc_out", _i32), ("fc_in", _i32), ("n1", _i32),
+                ("c_in", _i32), ("c_out", _i32), ("h", _i32), ("w", _i32), ("k", _i32)]
+
+
+class fhelin_ct_batch(ctypes.Structure):
+    _fields_ = [("data", _vp), ("n_ct", _i32), ("stride", _i32), ("levels", ctypes.POINTER(_i32))]
+
+
+_SIGS = {
+    "fhelin_primes_generate": [_i32, _i32, _i32, _vp],
+    "fhelin_ctx_create": [ctypes.POINTER(fhelin_params), _pvp],
+    "fhelin_ctx_destroy": [_vp],
+    "fhelin_ctx_set_budget": [_vp, _u64],
+    "fhelin_ctx_memory": [_vp, ctypes.POINTER(_u64)],
+    "fhelin_ctx_trim": [_vp],
+    "fhelin_ctx_root": [_vp, _i32, ctypes.POINTER(_u64)],
+    "fhelin_keyset_load": [_vp, _vp, _i32, _i32, _vp, _i32, _vp, _pvp],
+    "fhelin_keyset_release": [_vp],
+    "fhelin_pt_import": [_vp, _vp, _i32, _i32, _i32, _vp, _pvp],
+    "fhelin_pt_encode": [_vp, _vp, _i32, _i32, _dbl, _vp, _pvp],
+    "fhelin_pt_export": [_vp, _vp, _i32, _vp, _vp],
+    "fhelin_ptset_info": [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32)],
+    "fhelin_ptset_release": [_vp],
+    "fhelin_plan_create": [_vp, ctypes.POINTER(fhelin_layer_desc), _pvp],
+    "fhelin_plan_destroy": [_vp],
+    "fhelin_plan_info": [_vp] + [ctypes.POINTER(_i32)] * 5,
+    "fhelin_plan_rotations": [_vp, _vp, _vp],
+    "fhelin_plan_galois": [_vp, _vp, _i32, ctypes.POINTER(_i32)],
+    "fhelin_plan_encode_weights": [_vp, _vp, _vp, _vp, _vp, _i32, _dbl, _vp, _pvp],
+    "fhelin_linear_apply": [_vp, _vp, _vp, _vp, ctypes.POINTER(fhelin_ct_batch), ctypes.POINTER(fhelin_ct_batch),
+                            _i32, _vp],
+    "fhelin_rescale": [_vp, ctypes.POINTER(fhelin_ct_batch), ctypes.POINTER(fhelin_ct_batch), _vp],
+    "fhelin_rotate": [_vp, _vp, ctypes.POINTER(fhelin_ct_batch), _vp, ctypes.POINTER(fhelin_ct_batch), _vp],
+    "fhelin_ntt": [_vp, _vp, _vp, _i32, _i32, _vp],
+}
+for _name, _args in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = _i32
+_lib.fhelin_last_error.restype = ctypes.c_char_p
+_lib.fhelin_last_error.argtypes = []
+_lib.fhelin_status_string.restype = ctypes.c_char_p
+_lib.fhelin_status_string.argtypes = [ctypes.c_int]
+
+
+class FhelinError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+def fhelin_last_error() -> str:
+    return _lib.fhelin_last_error().decode()
+
+
+def fhelin_status_string(status: int) -> str:
+    return _lib.fhelin_status_string(status).decode()
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise FhelinError(rc, fhelin_last_error())
+
+
+def _stream(stream):
+    if stream is None:
+        return _vp(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, torch.cuda.Stream):
+        return _vp(stream.cuda_stream)
+    return _vp(int(stream))
+
+
+def _dev_ptr(t: torch.Tensor, dtypes, what: str):
+    if not t.is_cuda:
+        raise ValueError(f"{what} must be a GPU tensor")
+    if t.dtype not in dtypes:
+        raise ValueError(f"{what} has dtype {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    return _vp(t.data_ptr())
+
+
+_W64 = (torch.int64, torch.uint64)
+
+
+def _i32_array(vals):
+    vals = [int(v) for v in vals]
+    return (_i32 * max(1, len(vals)))(*vals)
+
+
+# --------------------------------------------------------------------------
+def fhelin_primes_generate(log_n: int, bits: int, count: int) -> list:
+    out = (_u64 * count)()
+    _check(_lib.fhelin_primes_generate(log_n, bits, count, ctypes.cast(out, _vp)))
+    return [int(v) for v in out]
+
+
+def fhelin_ctx_create(log_n: int, q, p, dnum: int):
+    qa = (_u64 * len(q))(*[int(v) for v in q])
+    pa = (_u64 * len(p))(*[int(v) for v in p])
+    prm = fhelin_params(log_n, len(q), len(p), dnum, qa, pa)
+    out = _vp()
+    _check(_lib.fhelin_ctx_create(ctypes.byref(prm), ctypes.byref(out)))
+    return out
+
+
+def fhelin_ctx_destroy(ctx):
+    _check(_lib.fhelin_ctx_destroy(ctx))
+
+
+def fhelin_ctx_set_budget(ctx, nbytes: int):
+    _check(_lib.fhelin_ctx_set_budget(ctx, int(nbytes)))
+
+
+def fhelin_ctx_memory(ctx) -> int:
+    v = _u64()
+    _check(_lib.fhelin_ctx_memory(ctx, ctypes.byref(v)))
+    return int(v.value)
+
+
+def fhelin_ctx_trim(ctx):
+    _check(_lib.fhelin_ctx_trim(ctx))
+
+
+def fhelin_ctx_root(ctx, mod_index: int) -> int:
+    v = _u64()
+    _check(_lib.fhelin_ctx_root(ctx, mod_index, ctypes.byref(v)))
+    return int(v.value)
+
+
+def fhelin_keyset_load(ctx, galois, level: int, evk: torch.Tensor, stream=None):
+    """evk: [n_keys][beta][2][level+K][N] 8-byte integers, GPU or CPU tensor."""
+    gal = (_u32 * len(galois))(*[int(g) for g in galois])
+    if evk.dtype not in _W64 or not evk.is_contiguous():
+        raise ValueError("evk must be a contiguous 8-byte integer tensor")
+    out = _vp()
+    _check(_lib.fhelin_keyset_load(ctx, ctypes.cast(gal, _vp), len(galois), level, _vp(evk.data_ptr()),
+                                   1 if evk.is_cuda else 0, _stream(stream), ctypes.byref(out)))
+    return out
+
+
+def fhelin_keyset_release(ks):
+    _check(_lib.fhelin_keyset_release(ks))
+
+
+def fhelin_pt_import(ctx, pt: torch.Tensor, stream=None):
+    """pt: [n_pt][level][N] 8-byte integers (GPU or CPU)."""
+    if pt.dtype not in _W64 or not pt.is_contiguous() or pt.dim() != 3:
+        raise ValueError("pt must be a contiguous [n_pt][level][N] 8-byte integer tensor")
+    out = _vp()
+    _check(_lib.fhelin_pt_import(ctx, _vp(pt.data_ptr()), pt.shape[0], pt.shape[1], 1 if pt.is_cuda else 0,
+                                 _stream(stream), ctypes.byref(out)))
+    return out
+
+
+def fhelin_pt_encode(ctx, slots: torch.Tensor, level: int, scale: float, stream=None):
+    """slots: GPU float64 [n_pt][N/2] (real slot values)."""
+    out = _vp()
+    _check(_lib.fhelin_pt_encode(ctx, _dev_ptr(slots, (torch.float64,), "slots"), slots.shape[0], level,
+                                 float(scale), _stream(stream), ctypes.byref(out)))
+    return out
+
+
+def fhelin_pt_export(ctx, pts, level: int, out: torch.Tensor, stream=None):
+    _check(_lib.fhelin_pt_export(ctx, pts, level, _dev_ptr(out, _W64, "out"), _stream(stream)))
+
+
+def fhelin_ptset_info(pts):
+    n, l = _i32(), _i32()
+    _check(_lib.fhelin_ptset_info(pts, ctypes.byref(n), ctypes.byref(l)))
+    return int(n.value), int(l.value)
+
+
+def fhelin_ptset_release(pts):
+    _check(_lib.fhelin_ptset_release(pts))
+
+
+def fhelin_plan_create(ctx, kind: int, fc_n=0, fc_out=0, fc_in=0, n1=0, c_in=0, c_out=0, h=0, w=0, k=0):
+    d = fhelin_layer_desc(kind, fc_n, fc_out, fc_in, n1, c_in, c_out, h, w, k)
+    out = _vp()
+    _check(_lib.fhelin_plan_create(ctx, ctypes.byref(d), ctypes.byref(out)))
+    return out
+
+
+def fhelin_plan_destroy(plan):
+    _check(_lib.fhelin_plan_destroy(plan))
+
+
+def fhelin_plan_info(plan) -> dict:
+    v = [_i32() for _ in range(5)]
+    _check(_lib.fhelin_plan_info(plan, *[ctypes.byref(x) for x in v]))
+    return dict(zip(["n_in", "n_out", "n_baby", "n_giant", "n_pt"], [int(x.value) for x in v]))
+
+
+def fhelin_plan_rotations(plan):
+    info = fhelin_plan_info(plan)
+    b = (_i32 * info["n_baby"])()
+    g = (_i32 * info["n_giant"])()
+    _check(_lib.fhelin_plan_rotations(plan, ctypes.cast(b, _vp), ctypes.cast(g, _vp)))
+    return list(b), list(g)
+
+
+def fhelin_plan_galois(plan) -> list:
+    n = _i32()
+    _check(_lib.fhelin_plan_galois(plan, None, 0, ctypes.byref(n)))
+    out = (_u32 * max(1, n.value))()
+    _check(_lib.fhelin_plan_galois(plan, ctypes.cast(out, _vp), n.value, ctypes.byref(n)))
+    return [int(v) for v in out][: n.value]
+
+
+def fhelin_plan_encode_weights(ctx, plan, weights: torch.Tensor, perm_out, perm_in, level: int, scale: float,
+                               stream=None):
+    po = _dev_ptr(perm_out, (torch.int32,), "perm_out") if perm_out is not None else None
+    pi = _dev_ptr(perm_in, (torch.int32,), "perm_in") if perm_in is not None else None
+    out = _vp()
+    _check(_lib.fhelin_plan_encode_weights(ctx, plan, _dev_ptr(weights, (torch.float64,), "weights"), po, pi,
+                                           level, float(scale), _stream(stream), ctypes.byref(out)))
+    return out
+
+
+def ct_batch(data: torch.Tensor, levels) -> fhelin_ct_batch:
+    """Describe a GPU tensor [n_ct][2][stride][N] with per-ciphertext levels."""
+    if data.dim() != 4 or data.shape[1] != 2:
+        raise ValueError("ciphertext tensor must be [n_ct][2][stride][N]")
+    lv = _i32_array(levels)
+    b = fhelin_ct_batch(_dev_ptr(data, _W64, "ciphertexts"), data.shape[0], data.shape[2],
+                        ctypes.cast(lv, ctypes.POINTER(_i32)))
+    b._keep = lv  # keep the level array alive with the struct
+    return b
+
+
+def fhelin_linear_apply(ctx, plan, ks, pts, x: torch.Tensor, x_levels, y: torch.Tensor, y_levels, flags=0,
+                        stream=None):
+    bi, bo = ct_batch(x, x_levels), ct_batch(y, y_levels)
+    _check(_lib.fhelin_linear_apply(ctx, plan, ks, pts, ctypes.byref(bi), ctypes.byref(bo), flags, _stream(stream)))
+
+
+def fhelin_rescale(ctx, x: torch.Tensor, x_levels, y: torch.Tensor, y_levels, stream=None):
+    bi, bo = ct_batch(x, x_levels), ct_batch(y, y_levels)
+    _check(_lib.fhelin_rescale(ctx, ctypes.byref(bi), ctypes.byref(bo), _stream(stream)))
+
+
+def fhelin_rotate(ctx, ks, x: torch.Tensor, levels, steps, y: torch.Tensor, stream=None):
+    bi, bo = ct_batch(x, levels), ct_batch(y, levels)
+    st = _i32_array(steps)
+    _check(_lib.fhelin_rotate(ctx, ks, ctypes.byref(bi), ctypes.cast(st, _vp), ctypes.byref(bo), _stream(stream)))
+
+
+def fhelin_ntt(ctx, rows: torch.Tensor, mod_index, inverse: bool, stream=None):
+    mi = _i32_array(mod_index)
+    if rows.dim() != 2 or rows.shape[0] != len(mod_index):
+        raise ValueError("rows must be [n_rows][N] with one modulus index per row")
+    _check(_lib.fhelin_ntt(ctx, _dev_ptr(rows, _W64, "rows"), ctypes.cast(mi, _vp), rows.shape[0],
+                           1 if inverse else 0, _stream(stream)))

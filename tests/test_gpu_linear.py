@@ -1,0 +1,265 @@
+"""GPU parity of whole linear layers against the oracle: bit-exact output
+ciphertexts (coefficient domain) from shared integer plaintexts, decryptions
+within 1e-3 of the FP64 layer, batches of uneven levels, and the library's own
+weight encoding (within one unit per coefficient of the oracle's encoding)."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2509_01253_amd import synth
+from tests.gpu_util import ctx_for, dev, host, keys_at, pad_cts
+from tests.helpers import Client, encode_pts
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def F():
+    from paper_2509_01253_amd import fhelin
+    return fhelin
+
+
+def _rel(got, ref):
+    return np.abs(got - ref).max() / np.abs(ref).max()
+
+
+class Layer:
+    """A layer evaluated on the GPU through the C ABI."""
+
+    def __init__(self, F, prm, keys, pts, level_keys, **desc):
+        self.F, self.prm = F, prm
+        self.ctx = ctx_for(F, prm)
+        kind = F.FHELIN_LAYER_FC if "fc_n" in desc else F.FHELIN_LAYER_CONV
+        self.plan = F.fhelin_plan_create(self.ctx, kind, **desc)
+        self.info = F.fhelin_plan_info(self.plan)
+        self.ks = None
+        if keys.galois:
+            assert F.fhelin_plan_galois(self.plan) == keys.galois
+            self.ks = F.fhelin_keyset_load(self.ctx, keys.galois, level_keys, dev(keys_at(prm, keys, level_keys)))
+        self.pset = None
+        if pts is not None:
+            self.pset = F.fhelin_pt_import(self.ctx, dev(pts.reshape(-1, pts.shape[-2], prm.N)))
+
+    def apply(self, cts, levels, rescale=True, stride=None):
+        prm, F = self.prm, self.F
+        stride = stride or max(levels)
+        x = dev(pad_cts(cts, stride, prm.N))
+        n_out = len(cts) // self.info["n_in"] * self.info["n_out"]
+        req_levels = [levels[r * self.info["n_in"]] for r in range(len(cts) // self.info["n_in"])]
+        out_levels = [l - 1 if rescale else l for l in req_levels for _ in range(self.info["n_out"])]
+        y = dev(np.zeros((n_out, 2, stride, prm.N), np.uint64))
+        F.fhelin_linear_apply(self.ctx, self.plan, self.ks, self.pset, x, levels, y, out_levels,
+                              F.FHELIN_APPLY_RESCALE if rescale else 0)
+        got = host(y)
+        return [got[t, :, : out_levels[t]] for t in range(n_out)]
+
+    def close(self):
+        F = self.F
+        if self.pset is not None:
+            F.fhelin_ptset_release(self.pset)
+        if self.ks is not None:
+            F.fhelin_keyset_release(self.ks)
+        F.fhelin_plan_destroy(self.plan)
+        F.fhelin_ctx_destroy(self.ctx)
+
+
+def test_fc_plain_c1_bit_exact(F):
+    """N=2^12, 3 x 36-bit q + 1 special, dnum 3, scale 2^30, FC 64x64 U[-1,1],
+    plain diagonal method (63 hoisted rotations), one rescale."""
+    print("c1 plain FC", flush=True)
+    prm = O.make_params(12, 3, 1, 3, 36, 2.0 ** 30)
+    st = synth.Stream(synth.master_seed(1))
+    W = st.sub(synth.TAG_W).uniform(64 * 64, -1, 1).reshape(64, 64)
+    x = st.sub(synth.TAG_X).uniform(64, -1, 1)
+    cl = Client(prm, synth.master_seed(1))
+    sched = O.fc_schedule(64, 64)
+    pts = encode_pts(prm, O.fc_slots(W, 64, 64, prm.S), 3, prm.scale)
+    keys = cl.keyset(sched.rotations())
+    ct = cl.encrypt_slots(O.fc_input_slots(x, 64, prm.S), 3, prm.scale)
+    want = O.rescale(prm, O.linear(prm, ct[None], 3, sched, pts, keys)[0], 3)
+    lay = Layer(F, prm, keys, pts, 3, fc_n=64, fc_out=64, fc_in=64, n1=64)
+    try:
+        got = lay.apply([ct], [3])[0]
+        assert np.array_equal(got, want)
+        z = cl.decrypt_slots(got, 2, prm.scale ** 2 / prm.q[2]).real
+        assert _rel(z[:64], W @ x) < 1e-3
+    finally:
+        lay.close()
+
+
+def test_fc_bsgs_uneven_levels_batch(F):
+    """A batch of requests at different levels in one call: each output equals the
+    oracle's, and equals the same request evaluated alone."""
+    print("bsgs uneven batch", flush=True)
+    prm = O.make_params(12, 6, 2, 3, 50, 2.0 ** 40)
+    st = synth.Stream(4000)
+    n, n1 = 64, 8
+    W = st.he_normal((n, n), n)
+    sched = O.fc_schedule(n, n1)
+    pts = encode_pts(prm, O.fc_slots(W, n, n1, prm.S), prm.L, prm.scale)
+    cl = Client(prm, 4001)
+    keys = cl.keyset(sched.rotations())
+    levels = [6, 2, 4, 5, 3, 6, 2]
+    xs = [st.uniform(n, 0, 1) for _ in levels]
+    cts = [cl.encrypt_slots(O.fc_input_slots(x, n, prm.S), l, prm.scale) for x, l in zip(xs, levels)]
+    lay = Layer(F, prm, keys, pts, prm.L, fc_n=n, fc_out=n, fc_in=n, n1=n1)
+    try:
+        got = lay.apply(cts, levels, stride=prm.L)
+        for t, l in enumerate(levels):
+            want = O.rescale(prm, O.linear(prm, cts[t][None], l, sched, pts, keys)[0], l)
+            assert np.array_equal(got[t], want), t
+            z = cl.decrypt_slots(got[t], l - 1, prm.scale ** 2 / prm.q[l - 1]).real
+            assert _rel(z[:n], W @ xs[t]) < 1e-3, t
+        alone = lay.apply([cts[3]], [levels[3]], stride=prm.L)[0]
+        assert np.array_equal(alone, got[3])
+        # no rescale: outputs at the input level
+        norsc = lay.apply(cts[:2], levels[:2], rescale=False, stride=prm.L)
+        for t in range(2):
+            assert np.array_equal(norsc[t], O.linear(prm, cts[t][None], levels[t], sched, pts, keys)[0])
+    finally:
+        lay.close()
+
+
+@pytest.mark.parametrize("c_in,c_out,k", [(16, 16, 3), (3, 16, 3), (16, 8, 1)])
+def test_conv_multi_ct_bit_exact(F, c_in, c_out, k):
+    print(f"conv {c_in}->{c_out} k{k}", flush=True)
+    prm = O.make_params(10, 4, 2, 2, 50, 2.0 ** 40)
+    cs = O.ConvShape(c_in, c_out, 8, 8, k)
+    st = synth.Stream(4100 + c_in + k)
+    W = st.he_normal((c_out, c_in, k, k), c_in * k * k)
+    sched = O.conv_schedule(cs, prm.S)
+    level = 3
+    pts = encode_pts(prm, O.conv_slots(W, cs, prm.S), level, prm.scale)
+    cl = Client(prm, 4200 + c_in)
+    keys = cl.keyset(sched.rotations())
+    reqs = 2
+    xs = [st.uniform(c_in * 64, 0, 1).reshape(c_in, 8, 8) for _ in range(reqs)]
+    cts = []
+    for x in xs:
+        slots = O.conv_input_slots(x, cs, prm.S)
+        cts += [cl.encrypt_slots(slots[i], level, prm.scale) for i in range(sched.n_in)]
+    lay = Layer(F, prm, keys, pts, level, c_in=c_in, c_out=c_out, h=8, w=8, k=k)
+    try:
+        assert lay.info["n_in"] == sched.n_in and lay.info["n_out"] == sched.n_out
+        got = lay.apply(cts, [level] * len(cts))
+        for r in range(reqs):
+            want = O.linear(prm, np.stack(cts[r * sched.n_in:(r + 1) * sched.n_in]), level, sched, pts, keys)
+            for o in range(sched.n_out):
+                assert np.array_equal(got[r * sched.n_out + o], O.rescale(prm, want[o], level)), (r, o)
+            dec = np.stack([cl.decrypt_slots(got[r * sched.n_out + o], level - 1,
+                                             prm.scale ** 2 / prm.q[level - 1]).real for o in range(sched.n_out)])
+            assert _rel(O.conv_output_from_slots(dec, cs, prm.S), O.conv_ref(W, xs[r])) < 1e-3
+    finally:
+        lay.close()
+
+
+def test_conv_c2_full(F):
+    """ResNet-20-block conv 3x3 16->16 on 32x32, N=2^15, 8 + 2 primes (50-bit),
+    dnum 4, scale 2^40, channel shuffle folded: bit-exact + decrypt 1e-3."""
+    print("c2 conv full", flush=True)
+    prm = O.make_params(15, 8, 2, 4, 50, 2.0 ** 40)
+    cs = O.ConvShape(16, 16, 32, 32, 3)
+    st = synth.Stream(synth.master_seed(2))
+    W = st.sub(synth.TAG_W).he_normal((16, 16, 3, 3), 144)
+    perm = st.sub(synth.TAG_PERM).permutation(16)
+    Wp = O.fold_permutations(W, perm, None)
+    x = st.sub(synth.TAG_X).uniform(16 * 32 * 32, 0, 1).reshape(16, 32, 32)
+    sched = O.conv_schedule(cs, prm.S)
+    pts = encode_pts(prm, O.conv_slots(Wp, cs, prm.S), 8, prm.scale)
+    cl = Client(prm, synth.master_seed(2))
+    keys = cl.keyset(sched.rotations())
+    ct = cl.encrypt_slots(O.conv_input_slots(x, cs, prm.S)[0], 8, prm.scale)
+    want = O.rescale(prm, O.linear(prm, ct[None], 8, sched, pts, keys)[0], 8)
+    lay = Layer(F, prm, keys, pts, 8, c_in=16, c_out=16, h=32, w=32, k=3)
+    try:
+        got = lay.apply([ct], [8])[0]
+        assert np.array_equal(got, want)
+        z = cl.decrypt_slots(got, 7, prm.scale ** 2 / prm.q[7]).real
+        assert _rel(O.conv_output_from_slots(z[None], cs, prm.S), O.conv_ref(Wp, x)) < 1e-3
+    finally:
+        lay.close()
+
+
+def test_encode_within_one_unit(F):
+    import torch
+    print("encode", flush=True)
+    for log_n in (12, 16):
+        prm = O.make_params(log_n, 3, 1, 3, 50, 2.0 ** 40)
+        ctx = ctx_for(F, prm)
+        try:
+            st = synth.Stream(4300 + log_n)
+            z = np.stack([st.uniform(prm.S, -1, 1), st.he_normal(prm.S, 16), np.full(prm.S, 0.25)])
+            pset = F.fhelin_pt_encode(ctx, torch.from_numpy(z).cuda(), 3, prm.scale)
+            out = dev(np.zeros((3, 3, prm.N), np.uint64))
+            F.fhelin_pt_export(ctx, pset, 3, out)
+            got = host(out)
+            for i in range(3):
+                m = O.encode(z[i], log_n, prm.scale)
+                for j, q in enumerate(prm.q[:3]):
+                    d = (got[i, j].astype(object) - O.to_rns(m, [q])[0].astype(object)) % q
+                    d = np.array([v if v <= q // 2 else v - q for v in d], dtype=np.int64)
+                    assert np.abs(d).max() <= 1, (log_n, i, j)
+                    assert np.mean(d != 0) < 1e-3
+            # the constant vector encodes exactly
+            assert np.array_equal(got[2, 0], O.to_rns(O.encode(z[2], log_n, prm.scale), [prm.q[0]])[0])
+            F.fhelin_ptset_release(pset)
+        finally:
+            F.fhelin_ctx_destroy(ctx)
+
+
+@pytest.mark.parametrize("kind", ["fc", "conv"])
+def test_encode_weights_with_shuffle(F, kind):
+    """Weights -> folded diagonals -> encode on the GPU, against the oracle's slot
+    vectors and encoding (one unit per coefficient), then decrypt(layer) vs FP64."""
+    import torch
+    print(f"encode weights {kind}", flush=True)
+    prm = O.make_params(11, 4, 2, 2, 50, 2.0 ** 40)
+    st = synth.Stream(4400)
+    cl = Client(prm, 4401)
+    level = 4
+    if kind == "fc":
+        n, n1, fo, fi = 128, 16, 100, 128
+        W = st.he_normal((fo, fi), fi)
+        po, pi = st.permutation(fo), st.permutation(fi)
+        Wp = O.fold_permutations(W, po, pi)
+        sched = O.fc_schedule(n, n1)
+        slots = O.fc_slots(Wp, n, n1, prm.S)
+        desc = dict(fc_n=n, fc_out=fo, fc_in=fi, n1=n1)
+        x = st.uniform(fi, 0, 1)
+        xs = [O.fc_input_slots(x, n, prm.S)]
+        ref = (Wp @ x)
+    else:
+        cs = O.ConvShape(8, 16, 8, 8, 3)
+        W = st.he_normal((16, 8, 3, 3), 72)
+        po, pi = st.permutation(16), st.permutation(8)
+        Wp = O.fold_permutations(W, po, pi)
+        sched = O.conv_schedule(cs, prm.S)
+        slots = O.conv_slots(Wp, cs, prm.S)
+        desc = dict(c_in=8, c_out=16, h=8, w=8, k=3)
+        x = st.uniform(8 * 64, 0, 1).reshape(8, 8, 8)
+        xs = list(O.conv_input_slots(x, cs, prm.S))
+        ref = O.conv_ref(Wp, x)
+    keys = cl.keyset(sched.rotations())
+    lay = Layer(F, prm, keys, None, level, **desc)
+    try:
+        lay.pset = F.fhelin_plan_encode_weights(
+            lay.ctx, lay.plan, torch.from_numpy(np.ascontiguousarray(W)).cuda(),
+            torch.from_numpy(po).cuda(), torch.from_numpy(pi).cuda(), level, prm.scale)
+        n_pt = lay.info["n_pt"]
+        out = dev(np.zeros((n_pt, level, prm.N), np.uint64))
+        F.fhelin_pt_export(lay.ctx, lay.pset, level, out)
+        got = host(out)
+        want = encode_pts(prm, slots, level, prm.scale).reshape(n_pt, level, prm.N)
+        q0 = prm.q[0]
+        d = (got[:, 0].astype(np.int64) - want[:, 0].astype(np.int64))
+        d = np.where(d > q0 // 2, d - q0, np.where(d < -(q0 // 2), d + q0, d))
+        assert np.abs(d).max() <= 1
+        cts = [cl.encrypt_slots(s, level, prm.scale) for s in xs]
+        res = lay.apply(cts, [level] * len(cts))
+        dec = np.stack([cl.decrypt_slots(r, level - 1, prm.scale ** 2 / prm.q[level - 1]).real for r in res])
+        if kind == "fc":
+            assert _rel(dec[0][:100], ref) < 1e-3
+        else:
+            assert _rel(O.conv_output_from_slots(dec, cs, prm.S), ref) < 1e-3
+    finally:
+        lay.close()
