@@ -44,6 +44,16 @@ def parse():
 
 WORKLOAD = dict(log_n=16, L=12, K=3, dnum=4, bits=50, scale=2.0 ** 40, fc=256, n1=16, lmin=4, lmax=12)
 
+# Integer-ALU ceiling of the NTT butterfly on MI355X: a lazy Shoup butterfly is 24
+# VALU instructions on gfx950 (64-bit products from v_mad_u64_u32 / v_mul_lo_u32 /
+# v_mul_hi_u32, which issue at the full VALU rate), and the chip issues one VALU
+# instruction per lane per clock on 256 CUs x 64 lanes at 2.4 GHz.
+ALU_LANE_OPS = 256 * 64 * 2.4e9
+BFLY_VALU_OPS = 24
+PEAK_BFLY = ALU_LANE_OPS / BFLY_VALU_OPS / 1e12  # T butterflies (= modular multiplies) per second
+KERNELS = ["ntt_fwd_cols", "ntt_fwd_rows", "ntt_inv_rows", "ntt_inv_cols", "mac", "ks_inner", "modup",
+           "moddown_fbc", "combine", "rescale", "copy", "mont", "encode"]
+
 
 def cpu_baseline(level: int) -> dict:
     """The oracle (plain C + numpy, OpenMP over limbs) on one request of the same
@@ -145,6 +155,7 @@ def main():
     release((ks, pts))
 
     torch.cuda.synchronize()
+    F.fhelin_profile_enable(ctx, True)
     lat = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -156,6 +167,23 @@ def main():
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
     ms = float(np.mean(lat))
+    prof = {}
+    for kname in KERNELS:
+        n, kms, units = F.fhelin_profile_read(ctx, kname)
+        if n:
+            prof[kname] = {"launches": n, "ms_per_step": round(kms / args.steps, 3), "units": units}
+    F.fhelin_profile_enable(ctx, False)
+    busy = sum(v["ms_per_step"] for v in prof.values())
+    for v in prof.values():
+        v["share"] = round(v["ms_per_step"] / busy, 4) if busy else 0.0
+    dom = max((k for k in prof if k.startswith("ntt_")), key=lambda k: prof[k]["ms_per_step"])
+    d = prof[dom]
+    avg_s = d["ms_per_step"] * args.steps / d["launches"] / 1e3
+    achieved = d["units"] / d["launches"] / avg_s / 1e12
+    roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 4), "peak": round(PEAK_BFLY, 4),
+                "unit": "T modmul-butterflies/s", "frac": round(achieved / PEAK_BFLY, 4), "traffic": None,
+                "avg_launch_ms": round(avg_s * 1e3, 4),
+                "units_per_launch": d["units"] / d["launches"]}
     layers_per_s = args.batch / (ms / 1e3)
     res = {
         "metric": "encrypted linear layers/s (N=2^16, 256x256 FC, batch of 64 at levels 4..12)",
@@ -180,6 +208,9 @@ def main():
         "ctx_setup_ms": round(t_ctx * 1e3, 1),
         "plan": info,
         "timed_wall_s": round(total, 3),
+        "roofline": roofline,
+        "kernels": {k: {"ms_per_step": v["ms_per_step"], "share": v["share"], "launches": v["launches"]}
+                    for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["ms_per_step"])},
     }
     F.fhelin_plan_destroy(plan)
     F.fhelin_ctx_destroy(ctx)

@@ -51,6 +51,7 @@ typedef struct fhelin_ctx fhelin_ctx;
 typedef struct fhelin_keyset fhelin_keyset;
 typedef struct fhelin_ptset fhelin_ptset;
 typedef struct fhelin_plan fhelin_plan;
+typedef struct fhelin_graph fhelin_graph;
 
 /* ---- parameters and context ------------------------------------------ */
 
@@ -206,6 +207,21 @@ typedef struct {
 int fhelin_linear_apply(fhelin_ctx *ctx, const fhelin_plan *plan, const fhelin_keyset *ks, const fhelin_ptset *pts,
                         const fhelin_ct_batch *in, const fhelin_ct_batch *out, int32_t flags, void *stream);
 
+/* Capture the kernels of one fhelin_linear_apply call (same arguments) into a
+ * HIP graph and instantiate it; nothing runs at capture time.  The device
+ * buffers, levels, keys and plaintexts are baked in: each fhelin_graph_launch
+ * reads the current contents of in->data and overwrites out->data with the
+ * same result an eager call would produce.  `stream` must be non-NULL; the
+ * graph uses that stream's workspace, so replays of one graph, and eager calls
+ * on the capture stream, must not overlap in time.  The handles and buffers
+ * must outlive the graph.  The schedule holds kernels only (no memset or
+ * copy nodes). */
+int fhelin_graph_capture_linear(fhelin_ctx *ctx, const fhelin_plan *plan, const fhelin_keyset *ks,
+                                const fhelin_ptset *pts, const fhelin_ct_batch *in, const fhelin_ct_batch *out,
+                                int32_t flags, void *stream, fhelin_graph **graph);
+int fhelin_graph_launch(fhelin_graph *graph, void *stream);
+int fhelin_graph_destroy(fhelin_graph *graph);
+
 /* Rescale (full-RNS CKKS): drop the top prime q_{l-1} with rounding,
  * c'_i = (c_i - [c]_{q_{l-1}}) * q_{l-1}^{-1} mod q_i with the centred
  * representative of the top limb.  out levels = in levels - 1 (each >= 1).
@@ -225,6 +241,20 @@ int fhelin_ntt(fhelin_ctx *ctx, uint64_t *rows, const int32_t *mod_index, int32_
                void *stream);
 
 /* ---- diagnostics ------------------------------------------------------- */
+
+/* Per-kernel timing: when enabled, each kernel launch of the context is
+ * bracketed by two HIP events recorded on its launching stream (not while the
+ * stream is being captured into a graph).  enable != 0 also discards earlier
+ * records.  Kernel classes: ntt_fwd_cols, ntt_fwd_rows, ntt_inv_rows,
+ * ntt_inv_cols, ntt_fwd_1, ntt_inv_1, mac, ks_inner, modup, moddown_fbc,
+ * combine, rescale, copy, mont, encode. */
+int fhelin_profile_enable(fhelin_ctx *ctx, int32_t enable);
+/* Totals of one kernel class since enabling: launches, summed event time (ms)
+ * and summed algorithmic work units (butterflies for NTT passes, 64-bit
+ * multiply-adds for mac / ks_inner, output elements otherwise).  Waits for the
+ * recorded events.  Output pointers may be NULL. */
+int fhelin_profile_read(fhelin_ctx *ctx, const char *kernel, int64_t *launches, double *total_ms, double *units);
+
 const char *fhelin_last_error(void);
 const char *fhelin_status_string(int status);
 

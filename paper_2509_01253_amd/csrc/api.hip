@@ -10,6 +10,43 @@ const char *last_error();
 int plan_create(Ctx *c, const fhelin_layer_desc *d, Plan **out);
 int linear_apply(Ctx *c, const Plan *p, const KeySet *ks, const PtSet *pts, const fhelin_ct_batch *in,
                  const fhelin_ct_batch *out, int flags, hipStream_t s, int max_chunk);
+size_t linear_workspace_bytes(const Ctx *c, const Plan *p, int n_requests, int max_chunk);
+
+// A captured linear-layer schedule: the kernels of one fhelin_linear_apply with fixed
+// buffers, replayed with hipGraphLaunch.
+struct Graph {
+    Ctx *ctx = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~Graph() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+};
+
+static int graph_capture_linear(Ctx *c, const Plan *p, const KeySet *ks, const PtSet *pts, const fhelin_ct_batch *in,
+                                const fhelin_ct_batch *out, int flags, hipStream_t s, Graph **g) {
+    FL_CHECK(p && in && g, FHELIN_E_INVALID_ARG, "graph_capture: null argument");
+    FL_CHECK(s != nullptr, FHELIN_E_INVALID_ARG, "graph capture needs a non-null stream");
+    // size the stream's workspace before capture (no allocation may happen inside it)
+    uint64_t *ws;
+    FL_RET(workspace_get(c, s, linear_workspace_bytes(c, p, in->n_ct / std::max(1, p->n_in), MAX_BATCH), &ws));
+    std::unique_ptr<Graph> gr(new Graph());
+    gr->ctx = c;
+    FL_TRY_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    int rc = linear_apply(c, p, ks, pts, in, out, flags, s, MAX_BATCH);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(s, &graph);
+    if (rc != FHELIN_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e != hipSuccess) return set_error(FHELIN_E_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+    gr->graph = graph;
+    FL_TRY_HIP(hipGraphInstantiate(&gr->exec, graph, nullptr, nullptr, 0));
+    *g = gr.release();
+    return FHELIN_OK;
+}
 int rotate_batch(Ctx *c, const KeySet *ks, const fhelin_ct_batch *in, const int32_t *steps, const fhelin_ct_batch *out,
                  hipStream_t s);
 int rescale_batch(Ctx *c, const fhelin_ct_batch *in, const fhelin_ct_batch *out, hipStream_t s);
@@ -371,6 +408,86 @@ FHELIN_EXPORT int fhelin_ntt(fhelin_ctx *ctx, uint64_t *rows, const int32_t *mod
     Ctx *c = (Ctx *)ctx;
     DeviceGuard g(c);
     return ntt_rows(c, rows, mod_index, n_rows, inverse ? 1 : 0, (hipStream_t)stream);
+    API_END
+}
+
+FHELIN_EXPORT int fhelin_graph_capture_linear(fhelin_ctx *ctx, const fhelin_plan *plan, const fhelin_keyset *ks,
+                                              const fhelin_ptset *pts, const fhelin_ct_batch *in,
+                                              const fhelin_ct_batch *out, int32_t flags, void *stream,
+                                              fhelin_graph **graph) {
+    API_BEGIN FL_CHECK(ctx && graph, FHELIN_E_INVALID_ARG, "null argument");
+    Ctx *c = (Ctx *)ctx;
+    DeviceGuard g(c);
+    Graph *gr = nullptr;
+    int rc = graph_capture_linear(c, (const Plan *)plan, (const KeySet *)ks, (const PtSet *)pts, in, out, flags,
+                                  (hipStream_t)stream, &gr);
+    if (rc == FHELIN_OK) *graph = (fhelin_graph *)gr;
+    return rc;
+    API_END
+}
+
+FHELIN_EXPORT int fhelin_graph_launch(fhelin_graph *graph, void *stream) {
+    API_BEGIN FL_CHECK(graph, FHELIN_E_INVALID_ARG, "null graph");
+    Graph *gr = (Graph *)graph;
+    DeviceGuard g(gr->ctx);
+    FL_TRY_HIP(hipGraphLaunch(gr->exec, (hipStream_t)stream));
+    return FHELIN_OK;
+    API_END
+}
+
+FHELIN_EXPORT int fhelin_graph_destroy(fhelin_graph *graph) {
+    API_BEGIN FL_CHECK(graph, FHELIN_E_INVALID_ARG, "null graph");
+    Graph *gr = (Graph *)graph;
+    DeviceGuard g(gr->ctx);
+    (void)hipDeviceSynchronize();
+    delete gr;
+    return FHELIN_OK;
+    API_END
+}
+
+FHELIN_EXPORT int fhelin_profile_enable(fhelin_ctx *ctx, int32_t enable) {
+    API_BEGIN FL_CHECK(ctx, FHELIN_E_INVALID_ARG, "null context");
+    Ctx *c = (Ctx *)ctx;
+    DeviceGuard g(c);
+    Profiler *p = c->prof.get();
+    FL_TRY_HIP(hipDeviceSynchronize());
+    std::lock_guard<std::mutex> lk(p->mu);
+    for (auto &r : p->recs) {
+        p->pool.push_back(r.a);
+        p->pool.push_back(r.b);
+    }
+    p->recs.clear();
+    p->on = enable != 0;
+    return FHELIN_OK;
+    API_END
+}
+
+FHELIN_EXPORT int fhelin_profile_read(fhelin_ctx *ctx, const char *kernel, int64_t *launches, double *total_ms,
+                                      double *units) {
+    API_BEGIN FL_CHECK(ctx && kernel, FHELIN_E_INVALID_ARG, "null argument");
+    Ctx *c = (Ctx *)ctx;
+    DeviceGuard g(c);
+    int kind = -1;
+    for (int k = 0; k < PK_COUNT; ++k)
+        if (std::string(PROF_NAMES[k]) == kernel) kind = k;
+    FL_CHECK(kind >= 0, FHELIN_E_INVALID_ARG, std::string("unknown kernel class ") + kernel);
+    Profiler *p = c->prof.get();
+    std::lock_guard<std::mutex> lk(p->mu);
+    int64_t n = 0;
+    double ms = 0, u = 0;
+    for (auto &r : p->recs) {
+        if (r.kind != kind) continue;
+        FL_TRY_HIP(hipEventSynchronize(r.b));
+        float t = 0;
+        FL_TRY_HIP(hipEventElapsedTime(&t, r.a, r.b));
+        ++n;
+        ms += t;
+        u += r.units;
+    }
+    if (launches) *launches = n;
+    if (total_ms) *total_ms = ms;
+    if (units) *units = u;
+    return FHELIN_OK;
     API_END
 }
 

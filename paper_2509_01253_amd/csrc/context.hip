@@ -314,8 +314,51 @@ int ctx_create(const fhelin_params *prm, Ctx **out) {
     return FHELIN_OK;
 }
 
+const char *const PROF_NAMES[PK_COUNT] = {"ntt_fwd_cols", "ntt_fwd_rows", "ntt_inv_rows", "ntt_inv_cols",
+                                          "ntt_fwd_1",    "ntt_inv_1",    "mac",          "ks_inner",
+                                          "modup",        "moddown_fbc",  "combine",      "rescale",
+                                          "copy",         "mont",         "encode"};
+
+hipEvent_t Profiler::get() {
+    if (!pool.empty()) {
+        hipEvent_t e = pool.back();
+        pool.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+ProfScope::ProfScope(const Ctx *c, hipStream_t st, int k, double u) : s(st), kind(k), units(u) {
+    Profiler *pr = c->prof.get();
+    if (!pr->on) return;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
+    std::lock_guard<std::mutex> g(pr->mu);
+    a = pr->get();
+    if (!a) return;
+    if (hipEventRecord(a, st) != hipSuccess) return;
+    p = pr;
+}
+
+ProfScope::~ProfScope() {
+    if (!p) return;
+    std::lock_guard<std::mutex> g(p->mu);
+    hipEvent_t b = p->get();
+    if (!b || hipEventRecord(b, s) != hipSuccess) return;
+    p->recs.push_back({kind, a, b, units});
+}
+
 Ctx::~Ctx() {
     ws.clear();
+    if (prof) {
+        for (auto &r : prof->recs) {
+            (void)hipEventDestroy(r.a);
+            (void)hipEventDestroy(r.b);
+        }
+        for (auto e : prof->pool) (void)hipEventDestroy(e);
+    }
     (void)hipFree(d_mods);
     (void)hipFree(d_tw);
     (void)hipFree(d_twp);

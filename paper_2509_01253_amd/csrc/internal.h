@@ -85,6 +85,26 @@ struct ModDownTab {
 // ---------------------------------------------------------------------------
 struct Workspace;
 
+// Optional per-kernel timing with HIP events on the launching stream (diagnostics).
+enum ProfKind : int {
+    PK_NTT_FWD_COLS = 0, PK_NTT_FWD_ROWS, PK_NTT_INV_ROWS, PK_NTT_INV_COLS, PK_NTT_FWD_1, PK_NTT_INV_1,
+    PK_MAC, PK_KS_INNER, PK_MODUP, PK_MODDOWN_FBC, PK_COMBINE, PK_RESCALE, PK_COPY, PK_MONT, PK_ENCODE, PK_COUNT
+};
+extern const char *const PROF_NAMES[PK_COUNT];
+
+struct Profiler {
+    bool on = false;
+    std::mutex mu;
+    struct Rec {
+        int kind;
+        hipEvent_t a, b;
+        double units;  // algorithmic work of the launch (butterflies, multiply-adds, elements)
+    };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
+    hipEvent_t get();
+};
+
 struct Ctx {
     int device = 0;
     int log_n = 0, N = 0, L = 0, K = 0, dnum = 0, alpha = 0;
@@ -106,6 +126,7 @@ struct Ctx {
     uint64_t used = 0;
     std::mutex mu;
     std::map<void *, std::unique_ptr<Workspace>> ws;  // per stream
+    std::unique_ptr<Profiler> prof{new Profiler()};
     ~Ctx();
 };
 
@@ -278,6 +299,17 @@ struct Workspace {
 int workspace_get(Ctx *c, hipStream_t s, size_t bytes, uint64_t **out);
 
 uint32_t galois_of_rotation(int64_t r, int log_n);
+
+// Bracket one launch with profiling events when enabled and the stream is not capturing.
+struct ProfScope {
+    Profiler *p = nullptr;
+    hipStream_t s;
+    int kind;
+    double units;
+    hipEvent_t a{};
+    ProfScope(const Ctx *c, hipStream_t st, int k, double u);
+    ~ProfScope();
+};
 
 // ---------------------------------------------------------------------------
 // kernel launchers (each .hip file owns its kernels)

@@ -13,6 +13,8 @@
 // Layout of per-entry workspace buffers (slot = modulus index):
 //   digits [dnum][L+K][N], u [2][L+K][N], md [2][L][N] (stride L), cts [2][stride][N].
 // Every kernel maps one thread to one coefficient; grid.z is the batch entry.
+#include <cmath>
+
 #include "internal.h"
 #include "modarith.h"
 
@@ -78,6 +80,12 @@ int launch_modup(const Ctx *c, const Batch &b, const uint64_t *coef, int64_t coe
     int lmax = 0;
     for (int t = 0; t < b.n; ++t) lmax = b.level[t] > lmax ? b.level[t] : lmax;
     int beta = (lmax + c->alpha - 1) / c->alpha;
+    double units = 0;
+    for (int t = 0; t < b.n; ++t) {
+        const double l = b.level[t];
+        units += std::ceil(l / c->alpha) * (l + c->K) * c->N;
+    }
+    ProfScope ps(c, s, PK_MODUP, units);
     hipLaunchKernelGGL(k_modup, dim3(c->N / 256, beta, b.n), dim3(256), 0, s, b, c->d_mods, c->d_modup, coef, coef_es,
                        ntt, ntt_es, digits, digits_es, c->log_n, c->L, c->K, c->alpha, c->dnum);
     FL_TRY_HIP(hipGetLastError());
@@ -131,6 +139,12 @@ int launch_ks_inner(const Ctx *c, const Batch &b, const KeySet *ks, const uint64
     if (b.n == 0) return FHELIN_OK;
     int lmax = 0;
     for (int t = 0; t < b.n; ++t) lmax = b.level[t] > lmax ? b.level[t] : lmax;
+    double units = 0;
+    for (int t = 0; t < b.n; ++t) {
+        const double l = b.level[t];
+        units += 2.0 * std::ceil(l / c->alpha) * (l + c->K) * c->N;
+    }
+    ProfScope ps(c, s, PK_KS_INNER, units);
     hipLaunchKernelGGL(k_ks_inner, dim3(c->N / 256, lmax + c->K, b.n), dim3(256), 0, s, b, c->d_mods, ks->evk,
                        ks->key_stride(), ks->level, digits, digits_es, u, u_es, c->log_n, c->L, c->K, c->alpha);
     FL_TRY_HIP(hipGetLastError());
@@ -177,6 +191,12 @@ __global__ void __launch_bounds__(256) k_moddown_fbc(Batch b, const ModConst *__
 int launch_moddown_fbc(const Ctx *c, const Batch &b, const uint64_t *u, int64_t u_es, uint64_t *md, int64_t md_es,
                        hipStream_t s) {
     if (b.n == 0) return FHELIN_OK;
+    double units = 0;
+    for (int t = 0; t < b.n; ++t) {
+        const double l = b.level[t];
+        units += 2.0 * l * c->N;
+    }
+    ProfScope ps(c, s, PK_MODDOWN_FBC, units);
     hipLaunchKernelGGL(k_moddown_fbc, dim3(c->N / 256, 2, b.n), dim3(256), 0, s, b, c->d_mods, c->d_moddown, u, u_es,
                        md, md_es, c->log_n, c->L, c->K);
     FL_TRY_HIP(hipGetLastError());
@@ -216,6 +236,12 @@ int launch_moddown_combine(const Ctx *c, const Batch &b, const uint64_t *u, int6
     if (b.n == 0) return FHELIN_OK;
     int lmax = 0;
     for (int t = 0; t < b.n; ++t) lmax = b.level[t] > lmax ? b.level[t] : lmax;
+    double units = 0;
+    for (int t = 0; t < b.n; ++t) {
+        const double l = b.level[t];
+        units += 2.0 * l * c->N;
+    }
+    ProfScope ps(c, s, PK_COMBINE, units);
     hipLaunchKernelGGL(k_moddown_combine, dim3(c->N / 256, 2 * lmax, b.n), dim3(256), 0, s, b, c->d_mods,
                        c->d_moddown, u, u_es, md, md_es, dst, dst_es, dst_stride, c0, c0_es, c0_stride, accumulate,
                        c->log_n, c->L, c->K);
@@ -260,6 +286,12 @@ int launch_rescale(const Ctx *c, const Batch &b, const uint64_t *in, int64_t in_
     int lmax = 0;
     for (int t = 0; t < b.n; ++t) lmax = b.level[t] > lmax ? b.level[t] : lmax;
     if (lmax < 2) return FHELIN_OK;
+    double units = 0;
+    for (int t = 0; t < b.n; ++t) {
+        const double l = b.level[t];
+        units += 2.0 * (l - 1) * c->N;
+    }
+    ProfScope ps(c, s, PK_RESCALE, units);
     hipLaunchKernelGGL(k_rescale, dim3(c->N / 256, 2 * (lmax - 1), b.n), dim3(256), 0, s, b, c->d_mods, c->d_rs_inv,
                        c->d_rs_inv_sh, in, in_es, in_stride, out, out_es, out_stride, c->log_n, c->L);
     FL_TRY_HIP(hipGetLastError());
@@ -286,6 +318,9 @@ int launch_copy_rows(const Ctx *c, const RowMap &dst, const RowMap &src, hipStre
     int rows = rowmap_max_rows(dst);
     if (rows == 0 || dst.n_ct == 0) return FHELIN_OK;
     int bx = c->N / 256 < 32 ? c->N / 256 : 32;
+    double units = 0;
+    for (int t = 0; t < dst.n_ct; ++t) units += (double)rowmap_rows(dst, t) * c->N;
+    ProfScope ps(c, s, PK_COPY, units);
     hipLaunchKernelGGL(k_copy_rows, dim3(bx, rows, dst.n_ct), dim3(256), 0, s, dst, src);
     FL_TRY_HIP(hipGetLastError());
     return FHELIN_OK;

@@ -75,7 +75,7 @@ int plan_create(Ctx *c, const fhelin_layer_desc *d, Plan **out) {
 
 // ---------------------------------------------------------------------------
 // pt x ct multiply-accumulate: A[e][j] = sum_i sum_b pt[o][i][j][b] * R[i][b]
-// grid (entries, N/256, l_max): consecutive workgroups share a plaintext tile
+// grid (N/256, l_max, entry groups)
 // ---------------------------------------------------------------------------
 struct MacArgs {
     const uint64_t *x;    // inputs, NTT domain [2][L] per input entry
@@ -86,44 +86,68 @@ struct MacArgs {
     int8_t bmap[MAX_BABY];  // baby index -> slot in rb, -1 = identity (use x)
 };
 
+// One thread per (coefficient, limb); it walks the entries of its group and, per entry,
+// loads up to 16 rotated-input values once and reuses them for every giant step
+// (the plaintext tile of the group is shared by all its entries through L1/L2).
+constexpr int MAC_GROUP = 8;  // output entries per workgroup
+
 __global__ void __launch_bounds__(256) k_mac(MacArgs a, Batch b, const ModConst *__restrict__ mods, int log_n,
                                              int L) {
-    const int e = blockIdx.x;
-    const int i = blockIdx.z;
-    const int l = b.level[e];
-    if (i >= l) return;
+    const int i = blockIdx.y;
     const int64_t N = (int64_t)1 << log_n;
-    const int k = blockIdx.y * 256 + threadIdx.x;
-    const int req = e / a.n_out, o = e % a.n_out;
+    const int k = blockIdx.x * 256 + threadIdx.x;
     const ModConst mc = mods[i];
     const int64_t ct = (int64_t)2 * L * N;
-    for (int j = 0; j < a.G; ++j) {
-        Acc128 s0{0, 0}, s1{0, 0};
-        uint64_t r0 = 0, r1 = 0;
-        int cnt = 0;
-        for (int ii = 0; ii < a.n_in; ++ii) {
-            const int64_t xin = (int64_t)req * a.n_in + ii;
-            for (int bb = 0; bb < a.B; ++bb) {
-                const int64_t pidx = ((int64_t)(o * a.n_in + ii) * a.G + j) * a.B + bb;
-                const uint64_t pv = a.pts[(pidx * a.pt_level + i) * N + k];
-                const int m = a.bmap[bb];
-                const uint64_t *src = m < 0 ? a.x + xin * ct : a.rb + (xin * a.Bp + m) * ct;
-                mac128(s0, src[(int64_t)i * N + k], pv);
-                mac128(s1, src[(int64_t)(L + i) * N + k], pv);
-                if (++cnt == 16) {
-                    r0 = add_mod(r0, redc(s0, mc.q, mc.mont_neg_inv), mc.q);
-                    r1 = add_mod(r1, redc(s1, mc.q, mc.mont_neg_inv), mc.q);
-                    s0 = Acc128{0, 0};
-                    s1 = Acc128{0, 0};
-                    cnt = 0;
+    const int terms = a.n_in * a.B;
+    const int e_end = min(b.n, (int)(blockIdx.z + 1) * MAC_GROUP);
+    for (int e = blockIdx.z * MAC_GROUP; e < e_end; ++e) {
+        if (i >= b.level[e]) continue;
+        const int req = e / a.n_out, o = e % a.n_out;
+        uint64_t *acc = a.acc + (int64_t)e * a.G * ct + (int64_t)i * N + k;
+        for (int t0 = 0; t0 < terms; t0 += 16) {  // 16 products stay below q 2^64 for q < 2^60
+            const int nt = min(16, terms - t0);
+            uint64_t x0[16], x1[16];
+            int64_t poff[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                if (u < nt) {
+                    const int t = t0 + u;
+                    const int ii = t / a.B, bb = t % a.B;
+                    const int64_t xin = (int64_t)req * a.n_in + ii;
+                    const int m = a.bmap[bb];
+                    const uint64_t *src = m < 0 ? a.x + xin * ct : a.rb + (xin * a.Bp + m) * ct;
+                    x0[u] = src[(int64_t)i * N + k];
+                    x1[u] = src[(int64_t)(L + i) * N + k];
+                    // plaintext (o, ii, j, bb) of giant step j is at poff + j * B * pt_level * N
+                    poff[u] = ((((int64_t)(o * a.n_in + ii) * a.G) * a.B + bb) * a.pt_level + i) * N + k;
+                } else {
+                    x0[u] = 0;
+                    x1[u] = 0;
+                    poff[u] = -1;
                 }
             }
+            const int64_t jstride = (int64_t)a.B * a.pt_level * N;
+            for (int j = 0; j < a.G; ++j) {
+                Acc128 s0{0, 0}, s1{0, 0};
+#pragma unroll
+                for (int u = 0; u < 16; ++u) {
+                    if (u < nt) {
+                        const uint64_t pv = a.pts[poff[u] + j * jstride];
+                        mac128(s0, x0[u], pv);
+                        mac128(s1, x1[u], pv);
+                    }
+                }
+                uint64_t r0 = redc(s0, mc.q, mc.mont_neg_inv);
+                uint64_t r1 = redc(s1, mc.q, mc.mont_neg_inv);
+                uint64_t *dst = acc + (int64_t)j * ct;
+                if (t0) {
+                    r0 = add_mod(r0, dst[0], mc.q);
+                    r1 = add_mod(r1, dst[(int64_t)L * N], mc.q);
+                }
+                dst[0] = r0;
+                dst[(int64_t)L * N] = r1;
+            }
         }
-        r0 = add_mod(r0, redc(s0, mc.q, mc.mont_neg_inv), mc.q);
-        r1 = add_mod(r1, redc(s1, mc.q, mc.mont_neg_inv), mc.q);
-        uint64_t *dst = a.acc + ((int64_t)e * a.G + j) * ct;
-        dst[(int64_t)i * N + k] = r0;
-        dst[(int64_t)(L + i) * N + k] = r1;
     }
 }
 
@@ -245,6 +269,14 @@ static size_t limbs_per_request(const Ctx *c, const Plan *p, int Bp) {
            + emax * 2 * L;         // md
 }
 
+size_t linear_workspace_bytes(const Ctx *c, const Plan *p, int n_requests, int max_chunk) {
+    int Bp = 0;
+    for (int r : p->rb) Bp += galois_of_rotation(r, c->log_n) == 1 ? 0 : 1;
+    int chunk = std::max(1, std::min(max_chunk, MAX_BATCH / std::max(p->n_in, p->n_out)));
+    chunk = std::min(chunk, std::max(1, n_requests));
+    return limbs_per_request(c, p, Bp) * chunk * (size_t)c->N * sizeof(uint64_t);
+}
+
 int linear_apply(Ctx *c, const Plan *p, const KeySet *ks, const PtSet *pts, const fhelin_ct_batch *in,
                  const fhelin_ct_batch *out, int flags, hipStream_t s, int max_chunk) {
     FL_CHECK(c && p && pts && in && out, FHELIN_E_INVALID_ARG, "linear_apply: null argument");
@@ -339,9 +371,14 @@ int linear_apply(Ctx *c, const Plan *p, const KeySet *ks, const PtSet *pts, cons
         ma.pt_level = pts->level;
         {
             int lmax = 0;
-            for (int e = 0; e < Eout; ++e) lmax = std::max<int>(lmax, bout.level[e]);
-            hipLaunchKernelGGL(k_mac, dim3(Eout, c->N / 256, lmax), dim3(256), 0, s, ma, bout, c->d_mods, c->log_n,
-                               c->L);
+            double macs = 0;
+            for (int e = 0; e < Eout; ++e) {
+                lmax = std::max<int>(lmax, bout.level[e]);
+                macs += 2.0 * bout.level[e] * (double)c->N * G * B * p->n_in;
+            }
+            ProfScope ps(c, s, PK_MAC, macs);
+            hipLaunchKernelGGL(k_mac, dim3(c->N / 256, lmax, (Eout + MAC_GROUP - 1) / MAC_GROUP), dim3(256), 0, s, ma,
+                               bout, c->d_mods, c->log_n, c->L);
             FL_TRY_HIP(hipGetLastError());
         }
         // 5. giant steps, summed into Y

@@ -7,12 +7,14 @@
 // in [0, 4q) (forward) or [0, 2q) (inverse) between stages; rows are canonical
 // [0, q) on entry and exit.
 //
-// Blocking for gfx950 (64 KiB LDS per workgroup here, 256 threads):
+// Blocking for gfx950 (256 threads per workgroup, 16 elements per thread):
 //   N <= 2^12: one workgroup holds a whole limb in LDS and runs every stage.
 //   N >= 2^13: two passes through HBM.  N = N1 * 256.  The first forward pass
 //   runs the log2(N1) stages with distance >= 256 on tiles of 4096/N1 adjacent
 //   columns (element c + 256 r, r < N1); the second runs the last 8 stages on
 //   tiles of 16 contiguous 256-element blocks.  The inverse runs them mirrored.
+//   Inside a pass, butterflies run on registers in two rounds (radix 16 x 2^(S-4))
+//   with one LDS exchange; global accesses are 128-byte contiguous per 16 lanes.
 // Grid: x = tile within the limb, y = row within a batch entry, z = batch entry.
 #include "internal.h"
 #include "modarith.h"
@@ -116,111 +118,181 @@ __global__ void __launch_bounds__(NTT_THREADS) k_ntt_inv_1(RowMap rm, const ModC
 }
 
 // ---------------------------------------------------------------------------
-// two passes (N >= 8192), N = N1 * 256
+// two passes (N >= 8192), N = N1 * 256, register-blocked
+//
+// Each pass runs the stages of 2^S-point sub-transforms (columns of N1 = 2^S
+// elements with stride 256 in pass 1, contiguous 256-blocks in pass 2).  A thread
+// holds 16 elements of one sub-transform in registers, T = 2^(S-4) threads per
+// sub-transform.  Round A: element u sits at local index rho = r + T u and the
+// four stages with distances 8T, 4T, 2T, T pair u with u + 8, 4, 2, 1.  Round B:
+// rho = 16 r + u and the S-4 remaining stages (distances 2^(S-5) .. 1) pair u
+// with u + h inside the thread.  One LDS exchange separates the rounds.
+// The twiddle of stage distance t for the pair at rho is psi^brv(idx),
+// idx = (M + gb 2^S + rho) / 2t, with M = 2^S in pass 1 (first stages of the
+// transform, gb = 0) and M = N in pass 2 (gb = global 256-block index).
 // ---------------------------------------------------------------------------
-// forward pass 1: stages m = 1 .. N1/2 on columns
+template <int S>
+__device__ __forceinline__ void fwd_round_a(uint64_t (&X)[16], int64_t base, const uint64_t *__restrict__ w,
+                                            const uint64_t *__restrict__ wp, uint64_t q) {
+    constexpr int T = 1 << (S - 4);
+#pragma unroll
+    for (int lh = 3; lh >= 0; --lh) {
+        const int h = 1 << lh;
+        const int lt = lh + (S - 4);  // log2 of the distance t = h T
+#pragma unroll
+        for (int g = 0; g < 8 / h; ++g) {  // groups of 2h consecutive u
+            const int64_t idx = (base + (int64_t)T * (g * 2 * h)) >> (lt + 1);
+            const uint64_t W = w[idx], Wp = wp[idx];
+#pragma unroll
+            for (int v = 0; v < h; ++v) ct_bfly(X[g * 2 * h + v], X[g * 2 * h + v + h], W, Wp, q);
+        }
+    }
+}
+
+template <int S>
+__device__ __forceinline__ void fwd_round_b(uint64_t (&X)[16], int64_t base, const uint64_t *__restrict__ w,
+                                            const uint64_t *__restrict__ wp, uint64_t q) {
+    // base = M + gb 2^S + 16 r
+#pragma unroll
+    for (int lh = S - 5; lh >= 0; --lh) {
+        const int h = 1 << lh;
+#pragma unroll
+        for (int g = 0; g < 8 / h; ++g) {
+            const int64_t idx = (base + g * 2 * h) >> (lh + 1);
+            const uint64_t W = w[idx], Wp = wp[idx];
+#pragma unroll
+            for (int v = 0; v < h; ++v) ct_bfly(X[g * 2 * h + v], X[g * 2 * h + v + h], W, Wp, q);
+        }
+    }
+}
+
+// inverse rounds: stages in increasing distance
+template <int S>
+__device__ __forceinline__ void inv_round_b(uint64_t (&X)[16], int64_t base, const uint64_t *__restrict__ w,
+                                            const uint64_t *__restrict__ wp, uint64_t q) {
+#pragma unroll
+    for (int lh = 0; lh <= S - 5; ++lh) {
+        const int h = 1 << lh;
+#pragma unroll
+        for (int g = 0; g < 8 / h; ++g) {
+            const int64_t idx = (base + g * 2 * h) >> (lh + 1);
+            const uint64_t W = w[idx], Wp = wp[idx];
+#pragma unroll
+            for (int v = 0; v < h; ++v) gs_bfly(X[g * 2 * h + v], X[g * 2 * h + v + h], W, Wp, q);
+        }
+    }
+}
+
+template <int S>
+__device__ __forceinline__ void inv_round_a(uint64_t (&X)[16], int64_t base, const uint64_t *__restrict__ w,
+                                            const uint64_t *__restrict__ wp, uint64_t q) {
+    constexpr int T = 1 << (S - 4);
+#pragma unroll
+    for (int lh = 0; lh <= 3; ++lh) {
+        const int h = 1 << lh;
+        const int lt = lh + (S - 4);
+#pragma unroll
+        for (int g = 0; g < 8 / h; ++g) {
+            const int64_t idx = (base + (int64_t)T * (g * 2 * h)) >> (lt + 1);
+            const uint64_t W = w[idx], Wp = wp[idx];
+#pragma unroll
+            for (int v = 0; v < h; ++v) gs_bfly(X[g * 2 * h + v], X[g * 2 * h + v + h], W, Wp, q);
+        }
+    }
+}
+
+// forward pass 1: stages with distance >= 256 on columns c + 256 rho, rho < N1 = 2^S
 template <int LOGN>
 __global__ void __launch_bounds__(NTT_THREADS) k_ntt_fwd_cols(RowMap rm, const ModConst *__restrict__ mods,
                                                               const uint64_t *__restrict__ tw,
                                                               const uint64_t *__restrict__ twp) {
-    constexpr int N = 1 << LOGN, LOGN1 = LOGN - 8, N1 = 1 << LOGN1, C = TILE / N1, LOGC = 12 - LOGN1;
-    __shared__ uint64_t s[TILE];
+    constexpr int N = 1 << LOGN, S = LOGN - 8, T = 1 << (S - 4), C = NTT_THREADS / T, CP = C + 1;
+    __shared__ uint64_t s[(1 << S) * CP];
     uint64_t *x;
     int mi;
     if (!row_of(rm, x, mi)) return;
     const uint64_t q = mods[mi].q;
     const uint64_t *w = tw + (size_t)mi * N, *wp = twp + (size_t)mi * N;
-    const int col0 = blockIdx.x * C;
-    for (int e = threadIdx.x; e < TILE; e += NTT_THREADS) {
-        int c = e & (C - 1), r = e >> LOGC;
-        s[e] = x[col0 + c + 256 * r];
-    }
+    const int c = threadIdx.x % C, r = threadIdx.x / C;
+    uint64_t *xc = x + blockIdx.x * C + c;
+    uint64_t X[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) X[u] = xc[256 * (r + T * u)];
+    fwd_round_a<S>(X, 1 << S, w, wp, q);
+#pragma unroll
+    for (int u = 0; u < 16; ++u) s[(r + T * u) * CP + c] = X[u];
     __syncthreads();
-    for (int lt = LOGN1 - 1, m = 1; lt >= 0; --lt, m <<= 1) {
-        const int t = 1 << lt;  // column-local distance
-        for (int b = threadIdx.x; b < TILE / 2; b += NTT_THREADS) {
-            int c = b & (C - 1), pb = b >> LOGC;
-            int i = pb >> lt;
-            int r = (i << (lt + 1)) + (pb & (t - 1));
-            uint64_t X = s[(r << LOGC) + c], Y = s[((r + t) << LOGC) + c];
-            ct_bfly(X, Y, w[m + i], wp[m + i], q);
-            s[(r << LOGC) + c] = X;
-            s[((r + t) << LOGC) + c] = Y;
-        }
-        __syncthreads();
-    }
-    for (int e = threadIdx.x; e < TILE; e += NTT_THREADS) {
-        int c = e & (C - 1), r = e >> LOGC;
-        x[col0 + c + 256 * r] = s[e];  // lazy [0, 4q)
-    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) X[u] = s[(16 * r + u) * CP + c];
+    fwd_round_b<S>(X, (1 << S) + 16 * r, w, wp, q);
+#pragma unroll
+    for (int u = 0; u < 16; ++u) xc[256 * (16 * r + u)] = X[u];  // lazy [0, 4q)
 }
 
-// forward pass 2: stages m = N1 .. N/2 inside contiguous 256-blocks
+// forward pass 2: the last 8 stages inside contiguous 256-blocks; 16 blocks per workgroup
 template <int LOGN>
 __global__ void __launch_bounds__(NTT_THREADS) k_ntt_fwd_rows(RowMap rm, const ModConst *__restrict__ mods,
                                                               const uint64_t *__restrict__ tw,
                                                               const uint64_t *__restrict__ twp) {
-    constexpr int N = 1 << LOGN, N1 = N >> 8;
-    __shared__ uint64_t s[TILE];
+    constexpr int N = 1 << LOGN, BS = 272;  // padded block stride in LDS (one pad word per 16)
+    __shared__ uint64_t s[16 * BS];
     uint64_t *x;
     int mi;
     if (!row_of(rm, x, mi)) return;
     const uint64_t q = mods[mi].q;
     const uint64_t *w = tw + (size_t)mi * N, *wp = twp + (size_t)mi * N;
+    const int blk = threadIdx.x >> 4, r = threadIdx.x & 15;
+    const int gb = blockIdx.x * 16 + blk;
     uint64_t *xt = x + (size_t)blockIdx.x * TILE;
-    const int blk0 = blockIdx.x * (TILE / 256);
-    for (int e = threadIdx.x; e < TILE; e += NTT_THREADS) s[e] = xt[e];
+    uint64_t X[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) X[u] = xt[blk * 256 + r + 16 * u];
+    const int64_t base = N + (int64_t)gb * 256;
+    fwd_round_a<8>(X, base, w, wp, q);
+    uint64_t *sb = s + blk * BS;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) sb[r + 17 * u] = X[u];
     __syncthreads();
-    for (int lt = 7, m = N1; lt >= 0; --lt, m <<= 1) {
-        const int t = 1 << lt;
-        for (int b = threadIdx.x; b < TILE / 2; b += NTT_THREADS) {
-            int blk = b >> 7, pb = b & 127;
-            int il = pb >> lt;
-            int l = (il << (lt + 1)) + (pb & (t - 1));
-            int i = (blk0 + blk) * (128 >> lt) + il;
-            int j = (blk << 8) + l;
-            uint64_t X = s[j], Y = s[j + t];
-            ct_bfly(X, Y, w[m + i], wp[m + i], q);
-            s[j] = X;
-            s[j + t] = Y;
-        }
-        __syncthreads();
-    }
-    for (int e = threadIdx.x; e < TILE; e += NTT_THREADS) xt[e] = reduce4q(s[e], q);
+#pragma unroll
+    for (int u = 0; u < 16; ++u) X[u] = sb[17 * r + u];
+    fwd_round_b<8>(X, base + 16 * r, w, wp, q);
+#pragma unroll
+    for (int u = 0; u < 16; ++u) sb[17 * r + u] = reduce4q(X[u], q);
+    __syncthreads();
+    for (int e = threadIdx.x; e < TILE; e += NTT_THREADS) xt[e] = s[(e >> 8) * BS + (e & 255) + ((e & 255) >> 4)];
 }
 
-// inverse pass 1: stages t = 1 .. 128 inside contiguous 256-blocks
+// inverse pass 1: the first 8 stages (distance 1 .. 128) inside contiguous 256-blocks
 template <int LOGN>
 __global__ void __launch_bounds__(NTT_THREADS) k_ntt_inv_rows(RowMap rm, const ModConst *__restrict__ mods,
                                                               const uint64_t *__restrict__ itw,
                                                               const uint64_t *__restrict__ itwp) {
-    constexpr int N = 1 << LOGN;
-    __shared__ uint64_t s[TILE];
+    constexpr int N = 1 << LOGN, BS = 272;
+    __shared__ uint64_t s[16 * BS];
     uint64_t *x;
     int mi;
     if (!row_of(rm, x, mi)) return;
     const uint64_t q = mods[mi].q;
     const uint64_t *w = itw + (size_t)mi * N, *wp = itwp + (size_t)mi * N;
+    const int blk = threadIdx.x >> 4, r = threadIdx.x & 15;
+    const int gb = blockIdx.x * 16 + blk;
     uint64_t *xt = x + (size_t)blockIdx.x * TILE;
-    const int blk0 = blockIdx.x * (TILE / 256);
-    for (int e = threadIdx.x; e < TILE; e += NTT_THREADS) s[e] = xt[e];
+    for (int e = threadIdx.x; e < TILE; e += NTT_THREADS) s[(e >> 8) * BS + (e & 255) + ((e & 255) >> 4)] = xt[e];
     __syncthreads();
-    for (int lt = 0, m = N / 2; lt < 8; ++lt, m >>= 1) {
-        const int t = 1 << lt;
-        for (int b = threadIdx.x; b < TILE / 2; b += NTT_THREADS) {
-            int blk = b >> 7, pb = b & 127;
-            int il = pb >> lt;
-            int l = (il << (lt + 1)) + (pb & (t - 1));
-            int i = (blk0 + blk) * (128 >> lt) + il;
-            int j = (blk << 8) + l;
-            uint64_t U = s[j], V = s[j + t];
-            gs_bfly(U, V, w[m + i], wp[m + i], q);
-            s[j] = U;
-            s[j + t] = V;
-        }
-        __syncthreads();
-    }
-    for (int e = threadIdx.x; e < TILE; e += NTT_THREADS) xt[e] = s[e];  // lazy [0, 2q)
+    uint64_t *sb = s + blk * BS;
+    uint64_t X[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) X[u] = sb[17 * r + u];
+    const int64_t base = N + (int64_t)gb * 256;
+    inv_round_b<8>(X, base + 16 * r, w, wp, q);
+#pragma unroll
+    for (int u = 0; u < 16; ++u) sb[17 * r + u] = X[u];
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 16; ++u) X[u] = sb[r + 17 * u];
+    inv_round_a<8>(X, base, w, wp, q);
+#pragma unroll
+    for (int u = 0; u < 16; ++u) xt[blk * 256 + r + 16 * u] = X[u];  // lazy [0, 2q)
 }
 
 // inverse pass 2: stages with distance >= 256 on columns, then N^{-1}
@@ -228,37 +300,28 @@ template <int LOGN>
 __global__ void __launch_bounds__(NTT_THREADS) k_ntt_inv_cols(RowMap rm, const ModConst *__restrict__ mods,
                                                               const uint64_t *__restrict__ itw,
                                                               const uint64_t *__restrict__ itwp) {
-    constexpr int N = 1 << LOGN, LOGN1 = LOGN - 8, N1 = 1 << LOGN1, C = TILE / N1, LOGC = 12 - LOGN1;
-    __shared__ uint64_t s[TILE];
+    constexpr int N = 1 << LOGN, S = LOGN - 8, T = 1 << (S - 4), C = NTT_THREADS / T, CP = C + 1;
+    __shared__ uint64_t s[(1 << S) * CP];
     uint64_t *x;
     int mi;
     if (!row_of(rm, x, mi)) return;
     const ModConst mc = mods[mi];
     const uint64_t q = mc.q;
     const uint64_t *w = itw + (size_t)mi * N, *wp = itwp + (size_t)mi * N;
-    const int col0 = blockIdx.x * C;
-    for (int e = threadIdx.x; e < TILE; e += NTT_THREADS) {
-        int c = e & (C - 1), r = e >> LOGC;
-        s[e] = x[col0 + c + 256 * r];
-    }
+    const int c = threadIdx.x % C, r = threadIdx.x / C;
+    uint64_t *xc = x + blockIdx.x * C + c;
+    uint64_t X[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) X[u] = xc[256 * (16 * r + u)];
+    inv_round_b<S>(X, (1 << S) + 16 * r, w, wp, q);
+#pragma unroll
+    for (int u = 0; u < 16; ++u) s[(16 * r + u) * CP + c] = X[u];
     __syncthreads();
-    for (int lt = 0, m = N1 / 2; lt < LOGN1; ++lt, m >>= 1) {
-        const int t = 1 << lt;
-        for (int b = threadIdx.x; b < TILE / 2; b += NTT_THREADS) {
-            int c = b & (C - 1), pb = b >> LOGC;
-            int i = pb >> lt;
-            int r = (i << (lt + 1)) + (pb & (t - 1));
-            uint64_t U = s[(r << LOGC) + c], V = s[((r + t) << LOGC) + c];
-            gs_bfly(U, V, w[m + i], wp[m + i], q);
-            s[(r << LOGC) + c] = U;
-            s[((r + t) << LOGC) + c] = V;
-        }
-        __syncthreads();
-    }
-    for (int e = threadIdx.x; e < TILE; e += NTT_THREADS) {
-        int c = e & (C - 1), r = e >> LOGC;
-        x[col0 + c + 256 * r] = shoup(s[e], mc.ninv, mc.ninv_sh, q);
-    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) X[u] = s[(r + T * u) * CP + c];
+    inv_round_a<S>(X, 1 << S, w, wp, q);
+#pragma unroll
+    for (int u = 0; u < 16; ++u) xc[256 * (r + T * u)] = shoup(X[u], mc.ninv, mc.ninv_sh, q);
 }
 
 // ---------------------------------------------------------------------------
@@ -279,22 +342,36 @@ __global__ void __launch_bounds__(256) k_to_mont(RowMap rm, const ModConst *__re
 template <int LOGN>
 static void launch_ntt_t(const Ctx *c, const RowMap &rm, int rows, int inverse, hipStream_t s) {
     const int M = 1 << LOGN;
+    double total_rows = 0;
+    for (int t = 0; t < rm.n_ct; ++t) total_rows += rowmap_rows(rm, t);
+    const double bfly_per_stage = total_rows * (M / 2);
     if (LOGN <= 12) {
         dim3 g(1, rows, rm.n_ct);
-        if (!inverse)
+        if (!inverse) {
+            ProfScope ps(c, s, PK_NTT_FWD_1, bfly_per_stage * LOGN);
             hipLaunchKernelGGL(k_ntt_fwd_1<(LOGN <= 12 ? LOGN : 12)>, g, dim3(NTT_THREADS), 0, s, rm, c->d_mods, c->d_tw,
                                c->d_twp);
-        else
+        } else {
+            ProfScope ps(c, s, PK_NTT_INV_1, bfly_per_stage * LOGN);
             hipLaunchKernelGGL(k_ntt_inv_1<(LOGN <= 12 ? LOGN : 12)>, g, dim3(NTT_THREADS), 0, s, rm, c->d_mods, c->d_itw,
                                c->d_itwp);
+        }
     } else {
         constexpr int L2 = LOGN > 12 ? LOGN : 13;
         dim3 g(M / TILE, rows, rm.n_ct);
         if (!inverse) {
-            hipLaunchKernelGGL(k_ntt_fwd_cols<L2>, g, dim3(NTT_THREADS), 0, s, rm, c->d_mods, c->d_tw, c->d_twp);
+            {
+                ProfScope ps(c, s, PK_NTT_FWD_COLS, bfly_per_stage * (LOGN - 8));
+                hipLaunchKernelGGL(k_ntt_fwd_cols<L2>, g, dim3(NTT_THREADS), 0, s, rm, c->d_mods, c->d_tw, c->d_twp);
+            }
+            ProfScope ps(c, s, PK_NTT_FWD_ROWS, bfly_per_stage * 8);
             hipLaunchKernelGGL(k_ntt_fwd_rows<L2>, g, dim3(NTT_THREADS), 0, s, rm, c->d_mods, c->d_tw, c->d_twp);
         } else {
-            hipLaunchKernelGGL(k_ntt_inv_rows<L2>, g, dim3(NTT_THREADS), 0, s, rm, c->d_mods, c->d_itw, c->d_itwp);
+            {
+                ProfScope ps(c, s, PK_NTT_INV_ROWS, bfly_per_stage * 8);
+                hipLaunchKernelGGL(k_ntt_inv_rows<L2>, g, dim3(NTT_THREADS), 0, s, rm, c->d_mods, c->d_itw, c->d_itwp);
+            }
+            ProfScope ps(c, s, PK_NTT_INV_COLS, bfly_per_stage * (LOGN - 8));
             hipLaunchKernelGGL(k_ntt_inv_cols<L2>, g, dim3(NTT_THREADS), 0, s, rm, c->d_mods, c->d_itw, c->d_itwp);
         }
     }
@@ -321,6 +398,9 @@ static int launch_mont(const Ctx *c, const RowMap &rm, int to, hipStream_t s) {
     int rows = rowmap_max_rows(rm);
     if (rows == 0 || rm.n_ct == 0) return FHELIN_OK;
     int bx = c->N / 256 < 64 ? c->N / 256 : 64;
+    double units = 0;
+    for (int t = 0; t < rm.n_ct; ++t) units += (double)rowmap_rows(rm, t) * c->N;
+    ProfScope ps(c, s, PK_MONT, units);
     hipLaunchKernelGGL(k_to_mont, dim3(bx, rows, rm.n_ct), dim3(256), 0, s, rm, c->d_mods, to);
     FL_TRY_HIP(hipGetLastError());
     return FHELIN_OK;

@@ -80,6 +80,13 @@ _SIGS = {
     "fhelin_rescale": [_vp, ctypes.POINTER(fhelin_ct_batch), ctypes.POINTER(fhelin_ct_batch), _vp],
     "fhelin_rotate": [_vp, _vp, ctypes.POINTER(fhelin_ct_batch), _vp, ctypes.POINTER(fhelin_ct_batch), _vp],
     "fhelin_ntt": [_vp, _vp, _vp, _i32, _i32, _vp],
+    "fhelin_graph_capture_linear": [_vp, _vp, _vp, _vp, ctypes.POINTER(fhelin_ct_batch),
+                                    ctypes.POINTER(fhelin_ct_batch), _i32, _vp, _pvp],
+    "fhelin_graph_launch": [_vp, _vp],
+    "fhelin_graph_destroy": [_vp],
+    "fhelin_profile_enable": [_vp, _i32],
+    "fhelin_profile_read": [_vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
+                            ctypes.POINTER(ctypes.c_double)],
 }
 for _name, _args in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -283,6 +290,24 @@ def fhelin_linear_apply(ctx, plan, ks, pts, x: torch.Tensor, x_levels, y: torch.
     _check(_lib.fhelin_linear_apply(ctx, plan, ks, pts, ctypes.byref(bi), ctypes.byref(bo), flags, _stream(stream)))
 
 
+def fhelin_graph_capture_linear(ctx, plan, ks, pts, x: torch.Tensor, x_levels, y: torch.Tensor, y_levels, flags=0,
+                                stream=None):
+    """Capture one linear_apply into a graph (stream must not be the null stream)."""
+    bi, bo = ct_batch(x, x_levels), ct_batch(y, y_levels)
+    out = _vp()
+    _check(_lib.fhelin_graph_capture_linear(ctx, plan, ks, pts, ctypes.byref(bi), ctypes.byref(bo), flags,
+                                            _stream(stream), ctypes.byref(out)))
+    return out
+
+
+def fhelin_graph_launch(graph, stream=None):
+    _check(_lib.fhelin_graph_launch(graph, _stream(stream)))
+
+
+def fhelin_graph_destroy(graph):
+    _check(_lib.fhelin_graph_destroy(graph))
+
+
 def fhelin_rescale(ctx, x: torch.Tensor, x_levels, y: torch.Tensor, y_levels, stream=None):
     bi, bo = ct_batch(x, x_levels), ct_batch(y, y_levels)
     _check(_lib.fhelin_rescale(ctx, ctypes.byref(bi), ctypes.byref(bo), _stream(stream)))
@@ -300,3 +325,14 @@ def fhelin_ntt(ctx, rows: torch.Tensor, mod_index, inverse: bool, stream=None):
         raise ValueError("rows must be [n_rows][N] with one modulus index per row")
     _check(_lib.fhelin_ntt(ctx, _dev_ptr(rows, _W64, "rows"), ctypes.cast(mi, _vp), rows.shape[0],
                            1 if inverse else 0, _stream(stream)))
+
+
+def fhelin_profile_enable(ctx, enable: bool = True):
+    _check(_lib.fhelin_profile_enable(ctx, 1 if enable else 0))
+
+
+def fhelin_profile_read(ctx, kernel: str):
+    """(launches, total_ms, units) for one kernel class."""
+    n, ms, u = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+    _check(_lib.fhelin_profile_read(ctx, kernel.encode(), ctypes.byref(n), ctypes.byref(ms), ctypes.byref(u)))
+    return int(n.value), float(ms.value), float(u.value)
