@@ -39,6 +39,9 @@ def parse():
     ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-level", type=int, default=8, help="level of the oracle's sampled request")
+    ap.add_argument("--schedule", choices=["rotation", "hoisted"], default="hoisted",
+                    help="per-rotation ModDown, or the double-hoisted schedule")
+    ap.add_argument("--n1", type=int, default=16, help="baby steps of the 256x256 FC (power of two)")
     return ap.parse_args()
 
 
@@ -55,31 +58,31 @@ KERNELS = ["ntt_fwd_cols", "ntt_fwd_rows", "ntt_inv_rows", "ntt_inv_cols", "mac"
            "moddown_fbc", "combine", "rescale", "copy", "mont", "encode"]
 
 
-def cpu_baseline(level: int) -> dict:
+def cpu_baseline(level: int, n1: int, hoisted: bool) -> dict:
     """The oracle (plain C + numpy, OpenMP over limbs) on one request of the same
-    workload at a single level; layers/s = 1 / time."""
+    workload and schedule at a single level; layers/s = 1 / time."""
     from oracle import oracle as O
     from paper_2509_01253_amd import synth
 
     w = WORKLOAD
     prm = O.make_params(w["log_n"], w["L"], w["K"], w["dnum"], w["bits"], w["scale"])
     st = synth.Stream(synth.master_seed(3)).sub(99)
-    sched = O.fc_schedule(w["fc"], w["n1"])
+    sched = O.fc_schedule(w["fc"], n1)
     gal = [O.galois_of(r, prm.log_n) for r in sched.rotations()]
     evk = np.stack([np.stack([np.stack([synth.uniform_limbs(st, prm.mods, prm.N) for _ in range(2)])
                               for _ in range(prm.dnum)]) for _ in gal])
     keys = O.KeySet(gal, evk)
-    pts = np.stack([synth.uniform_limbs(st, prm.q[:level], prm.N) for _ in range(w["fc"])])
-    pts = pts.reshape(1, 1, sched.G, sched.B, level, prm.N)
+    pts = np.stack([synth.uniform_limbs(st, prm.q[:level] + prm.p, prm.N) for _ in range(w["fc"])])
+    pts = pts.reshape(1, 1, sched.G, sched.B, level + prm.K, prm.N)
     ct = np.stack([synth.uniform_limbs(st, prm.q[:level], prm.N) for _ in range(2)])
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     t0 = time.perf_counter()
-    y = O.linear(prm, ct[None], level, sched, pts, keys)
+    y = O.linear(prm, ct[None], level, sched, pts, keys, hoist_moddown=hoisted)
     O.rescale(prm, y[0], level)
     dt = time.perf_counter() - t0
     return {"value": 1.0 / dt, "unit": "layers/s", "cores": threads, "kind": "oracle",
-            "sample": f"one request (FC 256x256, 30 rotations, 256 pt-MACs, rescale) at level {level} of "
-                      f"the N=2^16 workload; {dt:.1f} s"}
+            "sample": f"one request (FC 256x256, n1={n1}, {'double-hoisted' if hoisted else 'per-rotation'} "
+                      f"schedule, 256 pt-MACs, rescale) at level {level} of the N=2^16 workload; {dt:.1f} s"}
 
 
 def main():
@@ -103,7 +106,8 @@ def main():
     t_setup = time.perf_counter()
     ctx = F.fhelin_ctx_create(w["log_n"], q, p, dnum)
     t_ctx = time.perf_counter() - t_setup
-    plan = F.fhelin_plan_create(ctx, F.FHELIN_LAYER_FC, fc_n=w["fc"], fc_out=w["fc"], fc_in=w["fc"], n1=w["n1"])
+    plan = F.fhelin_plan_create(ctx, F.FHELIN_LAYER_FC, fc_n=w["fc"], fc_out=w["fc"], fc_in=w["fc"], n1=args.n1)
+    flags = F.FHELIN_APPLY_RESCALE | (F.FHELIN_APPLY_HOIST_MODDOWN if args.schedule == "hoisted" else 0)
     galois = F.fhelin_plan_galois(plan)
     info = F.fhelin_plan_info(plan)
     n_rot = sum(1 for r in F.fhelin_plan_rotations(plan)[0] if r) + sum(1 for r in F.fhelin_plan_rotations(plan)[1] if r)
@@ -133,7 +137,7 @@ def main():
     def step():
         ks = F.fhelin_keyset_load(ctx, galois, L, evk)
         pts = F.fhelin_plan_encode_weights(ctx, plan, W, perm_out, perm_in, L, w["scale"])
-        F.fhelin_linear_apply(ctx, plan, ks, pts, x, levels, y, out_levels, F.FHELIN_APPLY_RESCALE)
+        F.fhelin_linear_apply(ctx, plan, ks, pts, x, levels, y, out_levels, flags)
         return ks, pts
 
     def release(h):
@@ -148,7 +152,7 @@ def main():
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record()
-    F.fhelin_linear_apply(ctx, plan, ks, pts, x, levels, y, out_levels, F.FHELIN_APPLY_RESCALE)
+    F.fhelin_linear_apply(ctx, plan, ks, pts, x, levels, y, out_levels, flags)
     ev1.record()
     torch.cuda.synchronize()
     apply_ms = ev0.elapsed_time(ev1)
@@ -199,8 +203,9 @@ def main():
         "dtype": "u64",
         "data": "synthetic",
         "config": {"workload": "batched FC 256x256, 64 RNS-CKKS ciphertexts, N=2^16, levels U{4..12}, "
-                               "12+3 primes of 50 bits, dnum 4, BSGS 16x16, rescale",
-                   "batch": args.batch, "levels": levels},
+                               "12+3 primes of 50 bits, dnum 4, baby-step giant-step, rescale",
+                   "batch": args.batch, "levels": levels, "n1": args.n1, "n2": w["fc"] // args.n1,
+                   "schedule": args.schedule},
         "ks_rotations_per_s": round(args.batch * n_rot / (ms / 1e3), 1),
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3), "p99": round(float(np.percentile(lat, 99)), 3)},
         "apply_only_ms": round(apply_ms, 3),
@@ -215,7 +220,7 @@ def main():
     F.fhelin_plan_destroy(plan)
     F.fhelin_ctx_destroy(ctx)
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(args.cpu_level)
+        res["cpu_baseline"] = cpu_baseline(args.cpu_level, args.n1, args.schedule == "hoisted")
     print(json.dumps(res), flush=True)
 
 

@@ -113,20 +113,21 @@ int fhelin_keyset_release(fhelin_keyset *ks);
 
 /* ---- plaintexts -------------------------------------------------------- */
 
-/* Import integer plaintexts [n_pt][level][N] (coefficient domain, residues
- * mod q_0..q_{level-1}); host or device source. */
+/* Import integer plaintexts [n_pt][level + n_p][N] (coefficient domain,
+ * residues mod q_0..q_{level-1} then p_0..p_{n_p-1}; the special-prime rows
+ * serve the double-hoisted schedule); host or device source. */
 int fhelin_pt_import(fhelin_ctx *ctx, const uint64_t *pt, int32_t n_pt, int32_t level, int32_t src_on_device,
                      void *stream, fhelin_ptset **out);
 
 /* CKKS encode (canonical embedding, slot j at zeta^(5^j), zeta = exp(i pi/N);
  * Cheon-Kim-Kim-Song 2017): real slot vectors slots[n_pt][N/2] (device, FP64)
  * -> m_k = round(scale * (2/N) * sum_j z_j Re(zeta^(-5^j k))), ties to even,
- * reduced mod q_0..q_{level-1}.  |m_k| must stay below 2^62. */
+ * reduced mod q_0..q_{level-1} and p_0..p_{n_p-1}.  |m_k| must stay below 2^62. */
 int fhelin_pt_encode(fhelin_ctx *ctx, const double *slots, int32_t n_pt, int32_t level, double scale, void *stream,
                      fhelin_ptset **out);
 
-/* Write a plaintext set back in the coefficient domain: out[n_pt][level][N]
- * (device), level <= the set's level. */
+/* Write a plaintext set back in the coefficient domain: out[n_pt][level + n_p][N]
+ * (device; q rows 0..level-1 then the special rows), level <= the set's level. */
 int fhelin_pt_export(fhelin_ctx *ctx, const fhelin_ptset *pts, int32_t level, uint64_t *out, void *stream);
 int fhelin_ptset_info(const fhelin_ptset *pts, int32_t *n_pt, int32_t *level);
 int fhelin_ptset_release(fhelin_ptset *pts);
@@ -195,6 +196,16 @@ typedef struct {
 } fhelin_ct_batch;
 
 #define FHELIN_APPLY_RESCALE 1
+/* Double-hoisted schedule (Bossuat-Mouchet-Troncoso-Pastoriza-Hubaux, Eurocrypt
+ * 2021): baby rotations, the plaintext multiply-accumulate and the giant-step
+ * sum are kept in the extended basis Q*P; each giant step ModDowns only c1
+ * before its ModUp and one ModDown per output ends the layer:
+ *   R~_b = (P sigma_b(x0) + u0_b, u1_b) (r_b = 0: P x),  A~_j = sum pt (.) R~_b,
+ *   Y~ = sum_j [A~_j if G_j = 0 else (sigma_j(A~_j.c0) + v0, v1)],
+ *   v = KS_j(ModDown(A~_j.c1)),  y = ModDown(Y~).
+ * The result decrypts to the same layer with different rounding than the
+ * default per-rotation schedule; both are exact functions of their inputs. */
+#define FHELIN_APPLY_HOIST_MODDOWN 2
 
 /* Apply a linear layer to a batch of requests.  in->n_ct = R * n_in (request
  * r owns input ciphertexts r*n_in .. r*n_in+n_in-1, all at the same level);

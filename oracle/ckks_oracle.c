@@ -578,6 +578,151 @@ int or_linear(const uint64_t *x, int n_in, int n_out, int B, const int64_t *rb, 
 }
 
 /* ------------------------------------------------------------------ */
+/* baby-step / giant-step transform with hoisted ModDown ("double       */
+/* hoisting", Bossuat-Mouchet-Troncoso-Pastoriza-Hubaux, Eurocrypt 2021) */
+/* Same layer as or_linear; the key-switch outputs stay in the extended */
+/* basis B = {q_0..q_{l-1}, p_0..p_{K-1}} (carrying a factor P):        */
+/*   R~_b = (P sigma_b(x0) + u0_b, u1_b),  u_b = sum_j ModUp_j(sigma_b(x1)) evk_b[j] */
+/*          (r_b = 0: R~ = (P x0, P x1));                                 */
+/*   A~_k = sum_i sum_b pt[o][i][k][b] * R~_b   over B                    */
+/*          (pt has residues mod every modulus of B);                     */
+/*   Y~ = sum_k T_k with T_k = A~_k when G_k = 0, else                      */
+/*        T_k = (sigma_k(A~_k.c0) + v0, v1),                                */
+/*        v = sum_j ModUp_j(sigma_k(ModDown(A~_k.c1))) evk_k[j];            */
+/*   y = (ModDown(Y~.c0), ModDown(Y~.c1)).                                 */
+/* pt layout: [n_out][n_in][G][B][pt_l + K][N]: rows 0..pt_l-1 are mod      */
+/* q_0..q_{pt_l-1}, rows pt_l.. are mod p_0..p_{K-1}.                       */
+/* ------------------------------------------------------------------ */
+/* IP over B (no ModDown): d [l][N] under s(X^g) -> u [2][l+K][N] */
+static void ks_inner_ext(const octx *c, int l, const uint64_t *d, const uint64_t *evk, uint64_t *u) {
+    size_t n = c->n;
+    int beta = (l + c->alpha - 1) / c->alpha, m = l + c->K;
+    uint64_t *y = (uint64_t *)malloc((size_t)m * n * sizeof(uint64_t));
+    memset(u, 0, (size_t)2 * m * n * sizeof(uint64_t));
+    for (int j = 0; j < beta; j++) {
+        modup_digit(c, l, j, d, y);
+        #pragma omp parallel for schedule(dynamic)
+        for (int pr = 0; pr < 2 * m; pr++) {
+            int part = pr / m, r = pr % m;
+            uint64_t q = c->mod[ext_index(c, l, r)];
+            uint64_t *tt = (uint64_t *)malloc(n * sizeof(uint64_t));
+            ring_mul(c, ext_index(c, l, r), y + (size_t)r * n, evk_limb(c, evk, l, j, part, r), tt);
+            uint64_t *ur = u + ((size_t)part * m + r) * n;
+            for (size_t k = 0; k < n; k++) ur[k] = addmod(ur[k], tt[k], q);
+            free(tt);
+        }
+    }
+    free(y);
+}
+
+/* P mod each modulus of B: q_i -> [P]_{q_i}, p_k -> 0 */
+static uint64_t P_mod(const octx *c, int mi) {
+    uint64_t q = c->mod[mi], r = 1;
+    for (int k = 0; k < c->K; k++) r = mulmod(r, c->mod[c->L + k] % q, q);
+    return r;
+}
+
+/* (P x) over B for a level-l Q polynomial x [l][N] -> [l+K][N] */
+static void lift_P(const octx *c, int l, const uint64_t *x, uint64_t *out) {
+    size_t n = c->n;
+    for (int r = 0; r < l + c->K; r++) {
+        int mi = ext_index(c, l, r);
+        uint64_t f = P_mod(c, mi);
+        for (size_t k = 0; k < n; k++) out[(size_t)r * n + k] = r < l ? mulmod(x[(size_t)r * n + k], f, c->mod[mi]) : 0;
+    }
+}
+
+int or_linear_dh(const uint64_t *x, int n_in, int n_out, int B, const int64_t *rb, int G, const int64_t *gk,
+                 const uint64_t *pt, int pt_l, int l, const uint32_t *galois, int n_keys, const uint64_t *evk,
+                 int log_n, int L, int K, int dnum, const uint64_t *mod, uint64_t *out) {
+    octx c; octx_init(&c, log_n, L, K, dnum, mod);
+    size_t n = c.n, ctsz = (size_t)2 * l * n;
+    int m = l + K;
+    size_t ext = (size_t)2 * m * n;
+    int rc = 0;
+    uint64_t *R = (uint64_t *)malloc((size_t)n_in * B * ext * sizeof(uint64_t));
+    uint64_t *A = (uint64_t *)malloc(ext * sizeof(uint64_t));
+    uint64_t *Y = (uint64_t *)malloc(ext * sizeof(uint64_t));
+    uint64_t *tmp = (uint64_t *)malloc(ext * sizeof(uint64_t));
+    uint64_t *sx = (uint64_t *)malloc(ctsz * sizeof(uint64_t));
+    uint64_t *c1 = (uint64_t *)malloc((size_t)l * n * sizeof(uint64_t));
+    uint64_t *sc1 = (uint64_t *)malloc((size_t)l * n * sizeof(uint64_t));
+    /* baby steps in B */
+    for (int i = 0; i < n_in && !rc; i++)
+        for (int b = 0; b < B; b++) {
+            uint64_t *Rib = R + ((size_t)i * B + b) * ext;
+            const uint64_t *xi = x + (size_t)i * ctsz;
+            uint64_t g = galois_of(rb[b], log_n);
+            if (g == 1) {
+                lift_P(&c, l, xi, Rib);
+                lift_P(&c, l, xi + (size_t)l * n, Rib + (size_t)m * n);
+                continue;
+            }
+            const uint64_t *key = find_key(&c, g, galois, n_keys, evk);
+            if (!key) { rc = -1; break; }
+            for (int p = 0; p < 2; p++)
+                for (int li = 0; li < l; li++)
+                    or_automorph(xi + ((size_t)p * l + li) * n, sx + ((size_t)p * l + li) * n, log_n, g, mod[li]);
+            ks_inner_ext(&c, l, sx + (size_t)l * n, key, Rib);
+            lift_P(&c, l, sx, tmp);
+            for (int r = 0; r < m; r++) {
+                uint64_t q = mod[ext_index(&c, l, r)];
+                for (size_t k = 0; k < n; k++) Rib[(size_t)r * n + k] = addmod(Rib[(size_t)r * n + k], tmp[(size_t)r * n + k], q);
+            }
+        }
+    for (int o = 0; o < n_out && !rc; o++) {
+        memset(Y, 0, ext * sizeof(uint64_t));
+        for (int k = 0; k < G && !rc; k++) {
+            memset(A, 0, ext * sizeof(uint64_t));
+            #pragma omp parallel for schedule(dynamic)
+            for (int pr = 0; pr < 2 * m; pr++) {
+                int part = pr / m, r = pr % m;
+                int mi = ext_index(&c, l, r);
+                int prow = r < l ? r : pt_l + (r - l);
+                uint64_t *pp = (uint64_t *)malloc(n * sizeof(uint64_t));
+                uint64_t *a = A + ((size_t)part * m + r) * n;
+                for (int i = 0; i < n_in; i++)
+                    for (int b = 0; b < B; b++) {
+                        const uint64_t *p = pt + ((((size_t)o * n_in + i) * G + k) * B + b) * (size_t)(pt_l + K) * n;
+                        const uint64_t *Rib = R + ((size_t)i * B + b) * ext;
+                        ring_mul(&c, mi, Rib + ((size_t)part * m + r) * n, p + (size_t)prow * n, pp);
+                        for (size_t t = 0; t < n; t++) a[t] = addmod(a[t], pp[t], mod[mi]);
+                    }
+                free(pp);
+            }
+            uint64_t g = galois_of(gk[k], log_n);
+            const uint64_t *T = A;
+            if (g != 1) {
+                const uint64_t *key = find_key(&c, g, galois, n_keys, evk);
+                if (!key) { rc = -1; break; }
+                moddown(&c, l, A + (size_t)m * n, c1);                 /* c1' = ModDown(A~.c1) */
+                for (int li = 0; li < l; li++) or_automorph(c1 + (size_t)li * n, sc1 + (size_t)li * n, log_n, g, mod[li]);
+                ks_inner_ext(&c, l, sc1, key, tmp);                    /* v over B */
+                for (int r = 0; r < m; r++) {                          /* + sigma(A~.c0) on every limb of B */
+                    int mi = ext_index(&c, l, r);
+                    uint64_t *t0 = (uint64_t *)malloc(n * sizeof(uint64_t));
+                    or_automorph(A + (size_t)r * n, t0, log_n, g, mod[mi]);
+                    for (size_t t = 0; t < n; t++) tmp[(size_t)r * n + t] = addmod(tmp[(size_t)r * n + t], t0[t], mod[mi]);
+                    free(t0);
+                }
+                T = tmp;
+            }
+            for (int r = 0; r < 2 * m; r++) {
+                uint64_t q = mod[ext_index(&c, l, r % m)];
+                for (size_t t = 0; t < n; t++) Y[(size_t)r * n + t] = addmod(Y[(size_t)r * n + t], T[(size_t)r * n + t], q);
+            }
+        }
+        if (rc) break;
+        uint64_t *yo = out + (size_t)o * ctsz;
+        moddown(&c, l, Y, yo);
+        moddown(&c, l, Y + (size_t)m * n, yo + (size_t)l * n);
+    }
+    free(R); free(A); free(Y); free(tmp); free(sx); free(c1); free(sc1);
+    octx_free(&c);
+    return rc;
+}
+
+/* ------------------------------------------------------------------ */
 /* client side (test-input construction and decryption checks only)    */
 /* ------------------------------------------------------------------ */
 

@@ -76,6 +76,7 @@ def lib():
             "or_mul_pt": (None, [p, p, i32, i32, p, p]),
             "or_galois_of": (u64, [i64, i32]),
             "or_linear": (i32, [p, i32, i32, i32, p, i32, p, p, i32, i32, p, i32, p, i32, i32, i32, i32, p, p]),
+            "or_linear_dh": (i32, [p, i32, i32, i32, p, i32, p, p, i32, i32, p, i32, p, i32, i32, i32, i32, p, p]),
             "or_encrypt": (None, [p, p, p, p, i32, i32, p, p]),
             "or_decrypt": (None, [p, p, i32, i32, p, p]),
             "or_keygen_galois": (None, [p, u64, p, p, i32, i32, i32, i32, p, p]),
@@ -288,20 +289,29 @@ def mul_pt(prm: Params, ct, pt, level):
     return out
 
 
-def linear(prm: Params, x, level, sched: "Schedule", pts, keys: "KeySet"):
-    """Generic BSGS transform; x [n_in][2][level][N]; pts [n_out][n_in][G][B][pt_l][N]."""
+def linear(prm: Params, x, level, sched: "Schedule", pts, keys: "KeySet", hoist_moddown: bool = False):
+    """Generic BSGS transform; x [n_in][2][level][N]; pts [n_out][n_in][G][B][pt_l + K][N]
+    (rows: q_0..q_{pt_l-1} then p_0..p_{K-1}).  hoist_moddown selects the double-hoisted
+    schedule (key-switch outputs kept in the extended basis)."""
     x = _u64(x)
     pts = _u64(pts)
-    pt_l = pts.shape[-2]
+    pt_l = pts.shape[-2] - prm.K
     assert pts.shape[:4] == (sched.n_out, sched.n_in, sched.G, sched.B) and pt_l >= level
     rb = np.ascontiguousarray(sched.rb, np.int64)
     gk = np.ascontiguousarray(sched.gk, np.int64)
     gal = np.ascontiguousarray(keys.galois, np.uint32)
     evk = keys.evk
     out = np.zeros((sched.n_out, 2, level, prm.N), np.uint64)
-    rc = lib().or_linear(_ptr(x), sched.n_in, sched.n_out, sched.B, _ptr(rb), sched.G, _ptr(gk), _ptr(pts), pt_l,
-                         level, _ptr(gal), len(keys.galois), _ptr(evk), prm.log_n, prm.L, prm.K, prm.dnum,
-                         _ptr(prm.mods_arr), _ptr(out))
+    if hoist_moddown:
+        rc = lib().or_linear_dh(_ptr(x), sched.n_in, sched.n_out, sched.B, _ptr(rb), sched.G, _ptr(gk), _ptr(pts),
+                                pt_l, level, _ptr(gal), len(keys.galois), _ptr(evk), prm.log_n, prm.L, prm.K,
+                                prm.dnum, _ptr(prm.mods_arr), _ptr(out))
+    else:
+        # the per-rotation schedule reads the q rows only
+        pq = np.ascontiguousarray(pts[..., :pt_l, :])
+        rc = lib().or_linear(_ptr(x), sched.n_in, sched.n_out, sched.B, _ptr(rb), sched.G, _ptr(gk), _ptr(pq),
+                             pt_l, level, _ptr(gal), len(keys.galois), _ptr(evk), prm.log_n, prm.L, prm.K,
+                             prm.dnum, _ptr(prm.mods_arr), _ptr(out))
     if rc != 0:
         raise KeyError("missing Galois key")
     return out
@@ -422,8 +432,10 @@ def to_rns(m_int: np.ndarray, mods) -> np.ndarray:
     return np.stack(rows)
 
 
-def encode_rns(prm: Params, z, level: int, delta: float) -> np.ndarray:
-    return to_rns(encode(z, prm.log_n, delta), prm.q[:level])
+def encode_rns(prm: Params, z, level: int, delta: float, ext: bool = False) -> np.ndarray:
+    """Encoded slots as residues mod q_0..q_{level-1} (and p_0..p_{K-1} when ext)."""
+    mods = prm.q[:level] + (prm.p if ext else [])
+    return to_rns(encode(z, prm.log_n, delta), mods)
 
 
 def decrypt_decode(prm: Params, ct, s, level: int, delta: float) -> np.ndarray:

@@ -10,7 +10,7 @@ const char *last_error();
 int plan_create(Ctx *c, const fhelin_layer_desc *d, Plan **out);
 int linear_apply(Ctx *c, const Plan *p, const KeySet *ks, const PtSet *pts, const fhelin_ct_batch *in,
                  const fhelin_ct_batch *out, int flags, hipStream_t s, int max_chunk);
-size_t linear_workspace_bytes(const Ctx *c, const Plan *p, int n_requests, int max_chunk);
+size_t linear_workspace_bytes(const Ctx *c, const Plan *p, int n_requests, int max_chunk, int flags);
 
 // A captured linear-layer schedule: the kernels of one fhelin_linear_apply with fixed
 // buffers, replayed with hipGraphLaunch.
@@ -30,7 +30,7 @@ static int graph_capture_linear(Ctx *c, const Plan *p, const KeySet *ks, const P
     FL_CHECK(s != nullptr, FHELIN_E_INVALID_ARG, "graph capture needs a non-null stream");
     // size the stream's workspace before capture (no allocation may happen inside it)
     uint64_t *ws;
-    FL_RET(workspace_get(c, s, linear_workspace_bytes(c, p, in->n_ct / std::max(1, p->n_in), MAX_BATCH), &ws));
+    FL_RET(workspace_get(c, s, linear_workspace_bytes(c, p, in->n_ct / std::max(1, p->n_in), MAX_BATCH, flags), &ws));
     std::unique_ptr<Graph> gr(new Graph());
     gr->ctx = c;
     FL_TRY_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));

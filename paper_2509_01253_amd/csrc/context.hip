@@ -144,6 +144,7 @@ int ctx_create(const fhelin_params *prm, Ctx **out) {
     FL_CHECK(prm->dnum >= 1 && prm->dnum <= prm->n_q, FHELIN_E_UNSUPPORTED_PARAM, "dnum must be in [1, n_q]");
     const int L = prm->n_q, K = prm->n_p, alpha = (L + prm->dnum - 1) / prm->dnum;
     FL_CHECK(alpha <= MAX_ALPHA, FHELIN_E_UNSUPPORTED_PARAM, "digits hold at most 8 primes (raise dnum)");
+    FL_CHECK((L + alpha - 1) / alpha <= 16, FHELIN_E_UNSUPPORTED_PARAM, "at most 16 key-switch digits (lower dnum)");
     const uint64_t two_n = (uint64_t)2 << prm->log_n;
     std::vector<uint64_t> mods(prm->q, prm->q + L);
     mods.insert(mods.end(), prm->p, prm->p + K);
@@ -174,6 +175,8 @@ int ctx_create(const fhelin_params *prm, Ctx **out) {
     c->dnum = prm->dnum;
     c->alpha = alpha;
     c->mods = mods;
+    c->small = true;
+    for (uint64_t q : mods) c->small = c->small && q < ((uint64_t)1 << 56);
     const int M = L + K, N = c->N;
 
     // per-modulus constants, roots and twiddles

@@ -46,11 +46,12 @@ __global__ void __launch_bounds__(256) k_fft_stage(const double2 *__restrict__ i
     y[o + ns] = make_double2(a.x - br, a.y - bi);
 }
 
-// m_k = rint(scale/N * Re(X_k zeta^-k)); residues mod q_i -> pt[p][i][k] (coefficient domain)
+// m_k = rint(scale/N * Re(X_k zeta^-k)); residues mod q_0..q_{level-1}, p_0..p_{K-1}
+// -> pt[p][row][k] (coefficient domain)
 __global__ void __launch_bounds__(256) k_encode_finish(const double2 *__restrict__ X, uint64_t *__restrict__ pt,
                                                        const ModConst *__restrict__ mods,
-                                                       const double *__restrict__ zeta, int level, double scale,
-                                                       int log_n) {
+                                                       const double *__restrict__ zeta, int level, int L, int K,
+                                                       double scale, int log_n) {
     const int64_t N = (int64_t)1 << log_n;
     const int p = blockIdx.y;
     const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -61,11 +62,11 @@ __global__ void __launch_bounds__(256) k_encode_finish(const double2 *__restrict
     const int64_t mi = (int64_t)m;
     const bool neg = mi < 0;
     const uint64_t mag = neg ? (uint64_t)(-mi) : (uint64_t)mi;
-    uint64_t *o = pt + (int64_t)p * level * N + k;
-    for (int i = 0; i < level; ++i) {
-        const ModConst mc = mods[i];
-        uint64_t r = csub(shoup_lazy(mag, 1, mc.one_sh, mc.q), mc.q);
-        o[(int64_t)i * N] = (neg && r) ? mc.q - r : r;
+    uint64_t *o = pt + (int64_t)p * (level + K) * N + k;
+    for (int r = 0; r < level + K; ++r) {
+        const ModConst mc = mods[r < level ? r : L + (r - level)];
+        uint64_t v = csub(shoup_lazy(mag, 1, mc.one_sh, mc.q), mc.q);
+        o[(int64_t)r * N] = (neg && v) ? mc.q - v : v;
     }
 }
 
@@ -124,7 +125,7 @@ int ptset_new(Ctx *c, int n_pt, int level, PtSet **out) {
     p->ctx = c;
     p->n_pt = n_pt;
     p->level = level;
-    p->bytes = (size_t)n_pt * level * c->N * sizeof(uint64_t);
+    p->bytes = (size_t)n_pt * (level + c->K) * c->N * sizeof(uint64_t);
     FL_RET(dev_alloc(c, (void **)&p->data, p->bytes));
     *out = p.release();
     return FHELIN_OK;
@@ -136,14 +137,13 @@ void ptset_free(PtSet *p) {
     delete p;
 }
 
-// rows of plaintexts p0 .. p0+n-1 of a [n_pt][level][N] buffer as one batch entry
+// rows of plaintexts p0 .. p0+n-1 of a [n_pt][level+K][N] buffer: row e < level -> q_e,
+// else p_{e-level}
 static RowMap pt_rows(const Ctx *c, uint64_t *data, int n, int level) {
     RowMap m{};
     m.base = data;
-    m.kind = ROWS_CT;
-    m.stride = level;
-    m.poly_lo = 0;
-    m.poly_cnt = n;
+    m.kind = ROWS_KEY;
+    m.n_part = n;
     m.n_ct = 1;
     m.L = c->L;
     m.K = c->K;
@@ -155,8 +155,9 @@ static RowMap pt_rows(const Ctx *c, uint64_t *data, int n, int level) {
 
 // coefficient domain -> NTT domain, Montgomery form, in place
 static int pt_to_internal(Ctx *c, PtSet *p, hipStream_t s) {
+    const int64_t rows = p->level + c->K;
     for (int p0 = 0; p0 < p->n_pt; p0 += 64) {
-        RowMap e = pt_rows(c, p->data + (int64_t)p0 * p->level * c->N, std::min(64, p->n_pt - p0), p->level);
+        RowMap e = pt_rows(c, p->data + (int64_t)p0 * rows * c->N, std::min(64, p->n_pt - p0), p->level);
         FL_RET(launch_ntt(c, e, 0, s));
         FL_RET(launch_to_mont(c, e, s));
     }
@@ -191,19 +192,22 @@ int pt_import(Ctx *c, const uint64_t *src, int n_pt, int level, int on_device, h
 int pt_export(Ctx *c, const PtSet *p, int level, uint64_t *dst, hipStream_t s) {
     FL_CHECK(c && p && dst, FHELIN_E_INVALID_ARG, "pt_export: null argument");
     FL_CHECK(level >= 1 && level <= p->level, FHELIN_E_LEVEL_MISMATCH, "pt_export: level above the set's level");
-    const int64_t N = c->N;
-    FL_TRY_HIP(hipMemcpy2DAsync(dst, (size_t)level * N * sizeof(uint64_t), p->data,
-                                (size_t)p->level * N * sizeof(uint64_t), (size_t)level * N * sizeof(uint64_t),
-                                p->n_pt, hipMemcpyDeviceToDevice, s));
+    const int64_t N = c->N, K = c->K;
+    const size_t row = (size_t)N * sizeof(uint64_t);
+    // q rows 0..level-1, then the K special rows
+    FL_TRY_HIP(hipMemcpy2DAsync(dst, (level + K) * row, p->data, (p->level + K) * row, level * row, p->n_pt,
+                                hipMemcpyDeviceToDevice, s));
+    FL_TRY_HIP(hipMemcpy2DAsync(dst + level * N, (level + K) * row, p->data + (int64_t)p->level * N,
+                                (p->level + K) * row, K * row, p->n_pt, hipMemcpyDeviceToDevice, s));
     for (int p0 = 0; p0 < p->n_pt; p0 += 64) {
-        RowMap e = pt_rows(c, dst + (int64_t)p0 * level * N, std::min(64, p->n_pt - p0), level);
+        RowMap e = pt_rows(c, dst + (int64_t)p0 * (level + K) * N, std::min(64, p->n_pt - p0), level);
         FL_RET(launch_from_mont(c, e, s));
         FL_RET(launch_ntt(c, e, 1, s));
     }
     return FHELIN_OK;
 }
 
-// encode n real slot vectors (device [n][S]) into coefficient-domain rows dst[n][level][N]
+// encode n real slot vectors (device [n][S]) into coefficient-domain rows dst[n][level+K][N]
 static int encode_into(Ctx *c, const double *slots, int n, int level, double scale, uint64_t *dst, hipStream_t s) {
     const int64_t N = c->N;
     uint64_t *ws;
@@ -217,7 +221,7 @@ static int encode_into(Ctx *c, const double *slots, int n, int level, double sca
         std::swap(a, b);
     }
     hipLaunchKernelGGL(k_encode_finish, dim3((unsigned)N / 256, n), dim3(256), 0, s, a, dst, c->d_mods, c->d_zeta,
-                       level, scale, c->log_n);
+                       level, c->L, c->K, scale, c->log_n);
     FL_TRY_HIP(hipGetLastError());
     return FHELIN_OK;
 }
@@ -231,7 +235,8 @@ int pt_encode(Ctx *c, const double *slots, int n_pt, int level, double scale, hi
     int rc = FHELIN_OK;
     for (int p0 = 0; p0 < n_pt && rc == FHELIN_OK; p0 += 64) {
         const int n = std::min(64, n_pt - p0);
-        rc = encode_into(c, slots + (int64_t)p0 * (N / 2), n, level, scale, p->data + (int64_t)p0 * level * N, s);
+        rc = encode_into(c, slots + (int64_t)p0 * (N / 2), n, level, scale,
+                         p->data + (int64_t)p0 * (level + c->K) * N, s);
     }
     if (rc == FHELIN_OK) rc = pt_to_internal(c, p, s);
     if (rc) {
@@ -264,7 +269,8 @@ int plan_encode_weights(Ctx *c, const Plan *pl, const double *W, const int32_t *
                                d.c_in, d.h, d.w, d.k, pl->n_in, S, p0, slots);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) rc = set_error(FHELIN_E_HIP, std::string("encode_weights: ") + hipGetErrorString(e));
-        if (rc == FHELIN_OK) rc = encode_into(c, slots, n, level, scale, p->data + (int64_t)p0 * level * N, s);
+        if (rc == FHELIN_OK)
+            rc = encode_into(c, slots, n, level, scale, p->data + (int64_t)p0 * (level + c->K) * N, s);
     }
     if (rc == FHELIN_OK) rc = pt_to_internal(c, p, s);
     (void)hipStreamSynchronize(s);  // the slot buffer is read by queued kernels

@@ -108,6 +108,7 @@ struct Profiler {
 struct Ctx {
     int device = 0;
     int log_n = 0, N = 0, L = 0, K = 0, dnum = 0, alpha = 0;
+    bool small = false;              // every modulus < 2^56: cheaper lazy accumulation
     std::vector<uint64_t> mods;      // q_0..q_{L-1}, p_0..p_{K-1}
     std::vector<uint64_t> psi;       // minimal primitive 2N-th root per modulus
     std::vector<ModConst> h_mods;
@@ -329,11 +330,19 @@ int launch_modup(const Ctx *c, const Batch &b, const uint64_t *coef, int64_t coe
 int launch_ks_inner(const Ctx *c, const Batch &b, const KeySet *ks, const uint64_t *digits, int64_t digits_es,
                     uint64_t *u, int64_t u_es, hipStream_t s);
 int launch_moddown_fbc(const Ctx *c, const Batch &b, const uint64_t *u, int64_t u_es, uint64_t *md, int64_t md_es,
-                       hipStream_t s);
+                       hipStream_t s, int n_parts = 2);
+// inner product with an addend: add_ext = 0 adds P * sigma_g(c0) of a Q ciphertext [2][L] on the
+// q slots, add_ext = 1 adds sigma_g(c0) of an extended ciphertext [2][L+K]; accumulate adds into u
+int launch_ks_inner_add(const Ctx *c, const Batch &b, const KeySet *ks, const uint64_t *digits, int64_t digits_es,
+                        uint64_t *u, int64_t u_es, const uint64_t *add, int64_t add_es, int add_ext, int accumulate,
+                        hipStream_t s);
+// extended ciphertexts [2][L+K]: dst (+)= P * src (lift, src a Q ciphertext [2][src_stride]) or dst (+)= src
+int launch_ext_lift_add(const Ctx *c, const Batch &b, const uint64_t *src, int64_t src_es, int src_stride, int lift,
+                        int accumulate, uint64_t *dst, int64_t dst_es, hipStream_t s);
 // dst[p][i] (+)= (u[p][i] - md[p][i]) P^-1 (+ sigma_g(c0)[i] for p = 0); dst/c0 are [2][stride] ct buffers
 int launch_moddown_combine(const Ctx *c, const Batch &b, const uint64_t *u, int64_t u_es, const uint64_t *md,
                            int64_t md_es, uint64_t *dst, int64_t dst_es, int dst_stride, const uint64_t *c0,
-                           int64_t c0_es, int c0_stride, int accumulate, hipStream_t s);
+                           int64_t c0_es, int c0_stride, int accumulate, hipStream_t s, int n_parts = 2);
 // coefficient-domain rescale of [2][in_stride] -> [2][out_stride]
 int launch_rescale(const Ctx *c, const Batch &b, const uint64_t *in, int64_t in_es, int in_stride, uint64_t *out,
                    int64_t out_es, int out_stride, hipStream_t s);

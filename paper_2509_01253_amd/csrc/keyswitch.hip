@@ -94,59 +94,167 @@ int launch_modup(const Ctx *c, const Batch &b, const uint64_t *coef, int64_t coe
 
 // ---------------------------------------------------------------------------
 // inner product with the evaluation key: grid (N/256, l_max + K, n)
+//   u_p[slot] (+)= sum_j sigma_g(y_j)[slot] * evk_g[j].p[slot]  (+ addend for p = 0)
+// addend (optional, NTT domain, automorphism applied):
+//   add_ext = 0: a Q ciphertext [2][add_stride]; adds P * sigma_g(c0) on the q slots
+//   add_ext = 1: an extended ciphertext [2][L+K]; adds sigma_g(c0) on every slot
 // ---------------------------------------------------------------------------
+struct KsAdd {
+    const uint64_t *src;  // null: no addend
+    int64_t es;
+    int ext;
+    int accumulate;
+};
+
+// grid (N/256, L + K slots, entry groups of KS_EG): slot s is q_s (entries with s < l)
+// or p_{s-L}; the key rows of slot s are the same for every entry of the group, so a
+// thread loads them once per key and reuses them.
+constexpr int KS_EG = 8;
+
+template <bool SMALL>
 __global__ void __launch_bounds__(256) k_ks_inner(Batch b, const ModConst *__restrict__ mods,
+                                                  const ModDownTab *__restrict__ mdt,
                                                   const uint64_t *__restrict__ evk, int64_t key_stride, int key_level,
-                                                  const uint64_t *__restrict__ digits, int64_t digits_es,
-                                                  uint64_t *__restrict__ u, int64_t u_es, int log_n, int L, int K,
-                                                  int alpha) {
-    const int t = blockIdx.z, e = blockIdx.y;
-    const int l = b.level[t];
-    if (e >= l + K) return;
+                                                  int key_beta, const uint64_t *__restrict__ digits,
+                                                  int64_t digits_es, uint64_t *__restrict__ u, int64_t u_es,
+                                                  KsAdd add, int log_n, int L, int K, int alpha) {
+    const int s = blockIdx.y;
     const int64_t N = (int64_t)1 << log_n;
     const int k = blockIdx.x * 256 + threadIdx.x;
-    const int slot = e < l ? e : L + (e - l);
-    const int kp = e < l ? e : key_level + (e - l);
-    const int beta = (l + alpha - 1) / alpha;
-    const ModConst mc = mods[slot];
-    const int src = auto_index(k, b.g[t], log_n);
-    const uint64_t *key = evk + (int64_t)b.key[t] * key_stride;
-    const uint64_t *d = digits + t * digits_es + (int64_t)slot * N + src;
+    const ModConst mc = mods[s];
+    const int kp = s < L ? s : key_level + (s - L);
     const int64_t kpart = (int64_t)(key_level + K) * N;
-    const uint64_t *kb = key + (int64_t)kp * N + k;
-    Acc128 a0{0, 0}, a1{0, 0};
-    uint64_t r0 = 0, r1 = 0;
-    for (int j = 0; j < beta; ++j) {
-        uint64_t dv = d[(int64_t)j * (L + K) * N];
-        mac128(a0, dv, kb[(2 * j) * kpart]);
-        mac128(a1, dv, kb[(2 * j + 1) * kpart]);
-        if ((j & 15) == 15) {  // keep the Montgomery input below q 2^64 (q < 2^60)
-            r0 = add_mod(r0, redc(a0, mc.q, mc.mont_neg_inv), mc.q);
-            r1 = add_mod(r1, redc(a1, mc.q, mc.mont_neg_inv), mc.q);
-            a0 = Acc128{0, 0};
-            a1 = Acc128{0, 0};
+    constexpr int MAXB = 16;
+    uint64_t kb[MAXB], ka[MAXB];
+    int cur_key = -1;
+    const int e_end = min(b.n, (int)(blockIdx.z + 1) * KS_EG);
+    for (int t = blockIdx.z * KS_EG; t < e_end; ++t) {
+        const int l = b.level[t];
+        if (s < L && s >= l) continue;
+        const int beta = (l + alpha - 1) / alpha;
+        if (b.key[t] != cur_key) {
+            cur_key = b.key[t];
+            const uint64_t *key = evk + (int64_t)cur_key * key_stride + (int64_t)kp * N + k;
+#pragma unroll
+            for (int j = 0; j < MAXB; ++j) {
+                if (j < key_beta) {
+                    kb[j] = key[(2 * j) * kpart];
+                    ka[j] = key[(2 * j + 1) * kpart];
+                }
+            }
         }
+        const int src = auto_index(k, b.g[t], log_n);
+        const uint64_t *d = digits + t * digits_es + (int64_t)s * N + src;
+        LazyAcc<SMALL> a0, a1;
+        a0.zero();
+        a1.zero();
+#pragma unroll
+        for (int j = 0; j < MAXB; ++j) {
+            if (j < beta) {
+                const uint64_t dv = d[(int64_t)j * (L + K) * N];
+                a0.mac(dv, kb[j]);
+                a1.mac(dv, ka[j]);
+            }
+        }
+        uint64_t r0 = a0.reduce(mc.q, mc.mont_neg_inv), r1 = a1.reduce(mc.q, mc.mont_neg_inv);
+        if (add.src) {
+            if (add.ext) {
+                r0 = add_mod(r0, add.src[t * add.es + (int64_t)s * N + src], mc.q);
+            } else if (s < L) {
+                uint64_t v = add.src[t * add.es + (int64_t)s * N + src];
+                r0 = add_mod(r0, mont_mul(v, mdt->p_mont[s], mc.q, mc.mont_neg_inv), mc.q);
+            }
+        }
+        uint64_t *ut = u + t * u_es;
+        uint64_t *o0 = ut + (int64_t)s * N + k, *o1 = ut + ((int64_t)(L + K) + s) * N + k;
+        if (add.accumulate) {
+            r0 = add_mod(r0, *o0, mc.q);
+            r1 = add_mod(r1, *o1, mc.q);
+        }
+        *o0 = r0;
+        *o1 = r1;
     }
-    r0 = add_mod(r0, redc(a0, mc.q, mc.mont_neg_inv), mc.q);
-    r1 = add_mod(r1, redc(a1, mc.q, mc.mont_neg_inv), mc.q);
-    uint64_t *ut = u + t * u_es;
-    ut[(int64_t)slot * N + k] = r0;
-    ut[((int64_t)(L + K) + slot) * N + k] = r1;
 }
 
-int launch_ks_inner(const Ctx *c, const Batch &b, const KeySet *ks, const uint64_t *digits, int64_t digits_es,
-                    uint64_t *u, int64_t u_es, hipStream_t s) {
+static int launch_ks_inner_impl(const Ctx *c, const Batch &b, const KeySet *ks, const uint64_t *digits,
+                                int64_t digits_es, uint64_t *u, int64_t u_es, KsAdd add, hipStream_t s) {
     if (b.n == 0) return FHELIN_OK;
-    int lmax = 0;
-    for (int t = 0; t < b.n; ++t) lmax = b.level[t] > lmax ? b.level[t] : lmax;
     double units = 0;
     for (int t = 0; t < b.n; ++t) {
         const double l = b.level[t];
         units += 2.0 * std::ceil(l / c->alpha) * (l + c->K) * c->N;
     }
     ProfScope ps(c, s, PK_KS_INNER, units);
-    hipLaunchKernelGGL(k_ks_inner, dim3(c->N / 256, lmax + c->K, b.n), dim3(256), 0, s, b, c->d_mods, ks->evk,
-                       ks->key_stride(), ks->level, digits, digits_es, u, u_es, c->log_n, c->L, c->K, c->alpha);
+    dim3 grid(c->N / 256, c->L + c->K, (b.n + KS_EG - 1) / KS_EG);
+    if (c->small)
+        hipLaunchKernelGGL(k_ks_inner<true>, grid, dim3(256), 0, s, b, c->d_mods, c->d_moddown, ks->evk,
+                           ks->key_stride(), ks->level, ks->beta, digits, digits_es, u, u_es, add, c->log_n, c->L,
+                           c->K, c->alpha);
+    else
+        hipLaunchKernelGGL(k_ks_inner<false>, grid, dim3(256), 0, s, b, c->d_mods, c->d_moddown, ks->evk,
+                           ks->key_stride(), ks->level, ks->beta, digits, digits_es, u, u_es, add, c->log_n, c->L,
+                           c->K, c->alpha);
+    FL_TRY_HIP(hipGetLastError());
+    return FHELIN_OK;
+}
+
+int launch_ks_inner(const Ctx *c, const Batch &b, const KeySet *ks, const uint64_t *digits, int64_t digits_es,
+                    uint64_t *u, int64_t u_es, hipStream_t s) {
+    return launch_ks_inner_impl(c, b, ks, digits, digits_es, u, u_es, KsAdd{nullptr, 0, 0, 0}, s);
+}
+
+int launch_ks_inner_add(const Ctx *c, const Batch &b, const KeySet *ks, const uint64_t *digits, int64_t digits_es,
+                        uint64_t *u, int64_t u_es, const uint64_t *add, int64_t add_es, int add_ext, int accumulate,
+                        hipStream_t s) {
+    return launch_ks_inner_impl(c, b, ks, digits, digits_es, u, u_es, KsAdd{add, add_es, add_ext, accumulate}, s);
+}
+
+// ---------------------------------------------------------------------------
+// extended-basis helpers (NTT domain): dst[p][slot] over slots of B_l
+//   lift:  dst = P * src for a Q ciphertext src [2][src_stride] (0 on the p slots)
+//   add:   dst (+)= src for extended ciphertexts [2][L+K]
+// grid (N/256, 2 (l_max + K), n)
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_ext_lift_add(Batch b, const ModConst *__restrict__ mods,
+                                                      const ModDownTab *__restrict__ mdt,
+                                                      const uint64_t *__restrict__ src, int64_t src_es,
+                                                      int src_stride, int lift, int accumulate,
+                                                      uint64_t *__restrict__ dst, int64_t dst_es, int log_n, int L,
+                                                      int K) {
+    const int t = blockIdx.z;
+    const int l = b.level[t];
+    const int r = blockIdx.y;
+    if (r >= 2 * (l + K)) return;
+    const int p = r / (l + K), e = r % (l + K);
+    const int slot = e < l ? e : L + (e - l);
+    const int64_t N = (int64_t)1 << log_n;
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    const ModConst mc = mods[slot];
+    uint64_t v;
+    if (lift) {
+        v = e < l ? mont_mul(src[t * src_es + ((int64_t)p * src_stride + e) * N + k], mdt->p_mont[e], mc.q,
+                             mc.mont_neg_inv)
+                  : 0;
+    } else {
+        v = src[t * src_es + ((int64_t)p * (L + K) + slot) * N + k];
+    }
+    uint64_t *o = dst + t * dst_es + ((int64_t)p * (L + K) + slot) * N + k;
+    if (accumulate) v = add_mod(v, *o, mc.q);
+    *o = v;
+}
+
+int launch_ext_lift_add(const Ctx *c, const Batch &b, const uint64_t *src, int64_t src_es, int src_stride, int lift,
+                        int accumulate, uint64_t *dst, int64_t dst_es, hipStream_t s) {
+    if (b.n == 0) return FHELIN_OK;
+    int lmax = 0;
+    double units = 0;
+    for (int t = 0; t < b.n; ++t) {
+        lmax = b.level[t] > lmax ? b.level[t] : lmax;
+        units += 2.0 * (b.level[t] + c->K) * c->N;
+    }
+    ProfScope ps(c, s, PK_COPY, units);
+    hipLaunchKernelGGL(k_ext_lift_add, dim3(c->N / 256, 2 * (lmax + c->K), b.n), dim3(256), 0, s, b, c->d_mods,
+                       c->d_moddown, src, src_es, src_stride, lift, accumulate, dst, dst_es, c->log_n, c->L, c->K);
     FL_TRY_HIP(hipGetLastError());
     return FHELIN_OK;
 }
@@ -189,16 +297,16 @@ __global__ void __launch_bounds__(256) k_moddown_fbc(Batch b, const ModConst *__
 }
 
 int launch_moddown_fbc(const Ctx *c, const Batch &b, const uint64_t *u, int64_t u_es, uint64_t *md, int64_t md_es,
-                       hipStream_t s) {
+                       hipStream_t s, int n_parts) {
     if (b.n == 0) return FHELIN_OK;
     double units = 0;
     for (int t = 0; t < b.n; ++t) {
         const double l = b.level[t];
         units += 2.0 * l * c->N;
     }
-    ProfScope ps(c, s, PK_MODDOWN_FBC, units);
-    hipLaunchKernelGGL(k_moddown_fbc, dim3(c->N / 256, 2, b.n), dim3(256), 0, s, b, c->d_mods, c->d_moddown, u, u_es,
-                       md, md_es, c->log_n, c->L, c->K);
+    ProfScope ps(c, s, PK_MODDOWN_FBC, units * n_parts / 2);
+    hipLaunchKernelGGL(k_moddown_fbc, dim3(c->N / 256, n_parts, b.n), dim3(256), 0, s, b, c->d_mods, c->d_moddown, u,
+                       u_es, md, md_es, c->log_n, c->L, c->K);
     FL_TRY_HIP(hipGetLastError());
     return FHELIN_OK;
 }
@@ -212,11 +320,12 @@ __global__ void __launch_bounds__(256) k_moddown_combine(Batch b, const ModConst
                                                          const uint64_t *__restrict__ md, int64_t md_es,
                                                          uint64_t *__restrict__ dst, int64_t dst_es, int dst_stride,
                                                          const uint64_t *__restrict__ c0, int64_t c0_es,
-                                                         int c0_stride, int accumulate, int log_n, int L, int K) {
+                                                         int c0_stride, int accumulate, int n_parts, int log_n, int L,
+                                                         int K) {
     const int t = blockIdx.z;
     const int l = b.level[t];
     const int r = blockIdx.y;
-    if (r >= 2 * l) return;
+    if (r >= n_parts * l) return;
     const int p = r / l, i = r % l;
     const int64_t N = (int64_t)1 << log_n;
     const int k = blockIdx.x * 256 + threadIdx.x;
@@ -232,7 +341,7 @@ __global__ void __launch_bounds__(256) k_moddown_combine(Batch b, const ModConst
 
 int launch_moddown_combine(const Ctx *c, const Batch &b, const uint64_t *u, int64_t u_es, const uint64_t *md,
                            int64_t md_es, uint64_t *dst, int64_t dst_es, int dst_stride, const uint64_t *c0,
-                           int64_t c0_es, int c0_stride, int accumulate, hipStream_t s) {
+                           int64_t c0_es, int c0_stride, int accumulate, hipStream_t s, int n_parts) {
     if (b.n == 0) return FHELIN_OK;
     int lmax = 0;
     for (int t = 0; t < b.n; ++t) lmax = b.level[t] > lmax ? b.level[t] : lmax;
@@ -241,10 +350,10 @@ int launch_moddown_combine(const Ctx *c, const Batch &b, const uint64_t *u, int6
         const double l = b.level[t];
         units += 2.0 * l * c->N;
     }
-    ProfScope ps(c, s, PK_COMBINE, units);
-    hipLaunchKernelGGL(k_moddown_combine, dim3(c->N / 256, 2 * lmax, b.n), dim3(256), 0, s, b, c->d_mods,
+    ProfScope ps(c, s, PK_COMBINE, units * n_parts / 2);
+    hipLaunchKernelGGL(k_moddown_combine, dim3(c->N / 256, n_parts * lmax, b.n), dim3(256), 0, s, b, c->d_mods,
                        c->d_moddown, u, u_es, md, md_es, dst, dst_es, dst_stride, c0, c0_es, c0_stride, accumulate,
-                       c->log_n, c->L, c->K);
+                       n_parts, c->log_n, c->L, c->K);
     FL_TRY_HIP(hipGetLastError());
     return FHELIN_OK;
 }

@@ -78,77 +78,152 @@ int plan_create(Ctx *c, const fhelin_layer_desc *d, Plan **out) {
 // grid (N/256, l_max, entry groups)
 // ---------------------------------------------------------------------------
 struct MacArgs {
-    const uint64_t *x;    // inputs, NTT domain [2][L] per input entry
-    const uint64_t *rb;   // baby rotations [B'][2][L] per input entry
-    const uint64_t *pts;  // [n_pt][pt_level][N], Montgomery form
-    uint64_t *acc;        // [G][2][L] per output entry
+    const uint64_t *x;    // inputs, NTT domain [2][ls] per input entry
+    const uint64_t *rb;   // baby rotations [B'][2][ls] per input entry
+    const uint64_t *pts;  // [n_pt][pt_level + K][N], Montgomery form
+    uint64_t *acc;        // [G][2][ls] per output entry
     int n_in, n_out, B, Bp, G, pt_level;
+    int ext;              // 0: Q limbs, ls = L; 1: extended basis, ls = L + K
     int8_t bmap[MAX_BABY];  // baby index -> slot in rb, -1 = identity (use x)
 };
 
-// One thread per (coefficient, limb); it walks the entries of its group and, per entry,
-// loads up to 16 rotated-input values once and reuses them for every giant step
-// (the plaintext tile of the group is shared by all its entries through L1/L2).
-constexpr int MAC_GROUP = 8;  // output entries per workgroup
+// For one limb (slot s) and coefficient k the multiply-accumulate is a small matrix
+// product over the requests r of a group: A[r][j] = sum_t pt[o][j][t] * R[r][t]
+// (t = (input i, baby b)).  A workgroup takes 16 coefficients, one slot, one output
+// index o and a group of ET requests; plaintext and rotated-input tiles of MTB terms
+// are staged in LDS, so each plaintext value is read from memory once per group and
+// each rotated input once per chunk of JT giant steps.  Thread (kl, jj): coefficient
+// kl, giant step jj mod JT, and every ES-th request of the group starting at jj / JT.
+// Products are accumulated lazily in 128 bits, 16 terms per Montgomery reduction
+// (below q 2^64 for q < 2^60).
+constexpr int MAC_K = 16;   // coefficients per workgroup
+constexpr int MAC_TB = 4;   // terms per LDS chunk
+constexpr int MAC_MY = 8;   // requests per thread
+constexpr int MAC_ET = 32;  // requests per workgroup at most
 
+template <bool SMALL>
 __global__ void __launch_bounds__(256) k_mac(MacArgs a, Batch b, const ModConst *__restrict__ mods, int log_n,
-                                             int L) {
-    const int i = blockIdx.y;
+                                             int L, int K, int R, int JT, int ES, int ET) {
+    __shared__ uint64_t Ps[16][MAC_TB][MAC_K];
+    __shared__ uint64_t Rs[MAC_ET][MAC_TB][2][MAC_K];
+    const int s = blockIdx.y;  // slot = modulus index (q_s for s < L, p_{s-L} otherwise)
     const int64_t N = (int64_t)1 << log_n;
-    const int k = blockIdx.x * 256 + threadIdx.x;
-    const ModConst mc = mods[i];
-    const int64_t ct = (int64_t)2 * L * N;
+    const int k0 = blockIdx.x * MAC_K;
+    const int o = blockIdx.z % a.n_out, r0 = (blockIdx.z / a.n_out) * ET;
+    const int kl = threadIdx.x & 15, jj = threadIdx.x >> 4;
+    const int jloc = jj % JT, es = jj / JT;
+    const int ls = a.ext ? L + K : L;
+    const int64_t ct = (int64_t)2 * ls * N;
     const int terms = a.n_in * a.B;
-    const int e_end = min(b.n, (int)(blockIdx.z + 1) * MAC_GROUP);
-    for (int e = blockIdx.z * MAC_GROUP; e < e_end; ++e) {
-        if (i >= b.level[e]) continue;
-        const int req = e / a.n_out, o = e % a.n_out;
-        uint64_t *acc = a.acc + (int64_t)e * a.G * ct + (int64_t)i * N + k;
-        for (int t0 = 0; t0 < terms; t0 += 16) {  // 16 products stay below q 2^64 for q < 2^60
-            const int nt = min(16, terms - t0);
-            uint64_t x0[16], x1[16];
-            int64_t poff[16];
+    const int prows = a.pt_level + K;
+    const int prow = s < L ? s : a.pt_level + (s - L);
+    const int nr = min(ET, R - r0);
+    const ModConst mc = mods[s];
+    // active(r): the slot exists at the request's level
+    auto active = [&](int rr) -> bool {
+        const int l = b.level[(r0 + rr) * a.n_out + o];
+        return s < L ? s < l : a.ext != 0;
+    };
+    for (int jc = 0; jc < a.G; jc += JT) {
+        const int j = jc + jloc;
+        LazyAcc<SMALL> acc[MAC_MY][2];
+        uint64_t red[MAC_MY][2];
 #pragma unroll
-            for (int u = 0; u < 16; ++u) {
-                if (u < nt) {
-                    const int t = t0 + u;
+        for (int m = 0; m < MAC_MY; ++m) {
+            acc[m][0].zero();
+            acc[m][1].zero();
+            red[m][0] = red[m][1] = 0;
+        }
+        for (int t0 = 0; t0 < terms; t0 += MAC_TB) {
+            // stage plaintexts: JT x MAC_TB x 16
+            for (int v = threadIdx.x; v < JT * MAC_TB * MAC_K; v += 256) {
+                const int kk = v % MAC_K, tt = (v / MAC_K) % MAC_TB, jl = v / (MAC_K * MAC_TB);
+                const int t = t0 + tt, jg = jc + jl;
+                uint64_t pv = 0;
+                if (t < terms && jg < a.G) {
                     const int ii = t / a.B, bb = t % a.B;
-                    const int64_t xin = (int64_t)req * a.n_in + ii;
+                    const int64_t pidx = ((int64_t)(o * a.n_in + ii) * a.G + jg) * a.B + bb;
+                    pv = a.pts[(pidx * prows + prow) * N + k0 + kk];
+                }
+                Ps[jl][tt][kk] = pv;
+            }
+            // stage rotated inputs: nr x MAC_TB x 2 x 16
+            for (int v = threadIdx.x; v < nr * MAC_TB * 2 * MAC_K; v += 256) {
+                const int kk = v % MAC_K, p = (v / MAC_K) % 2, tt = (v / (2 * MAC_K)) % MAC_TB,
+                          rr = v / (2 * MAC_K * MAC_TB);
+                const int t = t0 + tt;
+                uint64_t xv = 0;
+                if (t < terms && active(rr)) {
+                    const int ii = t / a.B, bb = t % a.B;
+                    const int64_t xin = (int64_t)(r0 + rr) * a.n_in + ii;
                     const int m = a.bmap[bb];
                     const uint64_t *src = m < 0 ? a.x + xin * ct : a.rb + (xin * a.Bp + m) * ct;
-                    x0[u] = src[(int64_t)i * N + k];
-                    x1[u] = src[(int64_t)(L + i) * N + k];
-                    // plaintext (o, ii, j, bb) of giant step j is at poff + j * B * pt_level * N
-                    poff[u] = ((((int64_t)(o * a.n_in + ii) * a.G) * a.B + bb) * a.pt_level + i) * N + k;
-                } else {
-                    x0[u] = 0;
-                    x1[u] = 0;
-                    poff[u] = -1;
+                    xv = src[((int64_t)p * ls + s) * N + k0 + kk];
                 }
+                Rs[rr][tt][p][kk] = xv;
             }
-            const int64_t jstride = (int64_t)a.B * a.pt_level * N;
-            for (int j = 0; j < a.G; ++j) {
-                Acc128 s0{0, 0}, s1{0, 0};
+            __syncthreads();
+            if (j < a.G) {
 #pragma unroll
-                for (int u = 0; u < 16; ++u) {
-                    if (u < nt) {
-                        const uint64_t pv = a.pts[poff[u] + j * jstride];
-                        mac128(s0, x0[u], pv);
-                        mac128(s1, x1[u], pv);
+                for (int tt = 0; tt < MAC_TB; ++tt) {
+                    const uint64_t pv = Ps[jloc][tt][kl];
+#pragma unroll
+                    for (int m = 0; m < MAC_MY; ++m) {
+                        const int rr = es + m * ES;
+                        if (rr < nr) {
+                            acc[m][0].mac(Rs[rr][tt][0][kl], pv);
+                            acc[m][1].mac(Rs[rr][tt][1][kl], pv);
+                        }
                     }
                 }
-                uint64_t r0 = redc(s0, mc.q, mc.mont_neg_inv);
-                uint64_t r1 = redc(s1, mc.q, mc.mont_neg_inv);
-                uint64_t *dst = acc + (int64_t)j * ct;
-                if (t0) {
-                    r0 = add_mod(r0, dst[0], mc.q);
-                    r1 = add_mod(r1, dst[(int64_t)L * N], mc.q);
+            }
+            __syncthreads();
+            if (((t0 + MAC_TB) % 16) == 0 || t0 + MAC_TB >= terms) {
+#pragma unroll
+                for (int m = 0; m < MAC_MY; ++m)
+#pragma unroll
+                    for (int p = 0; p < 2; ++p) {
+                        red[m][p] = add_mod(red[m][p], acc[m][p].reduce(mc.q, mc.mont_neg_inv), mc.q);
+                        acc[m][p].zero();
+                    }
+            }
+        }
+        if (j < a.G) {
+#pragma unroll
+            for (int m = 0; m < MAC_MY; ++m) {
+                const int rr = es + m * ES;
+                if (rr < nr && active(rr)) {
+                    const int64_t e = (int64_t)(r0 + rr) * a.n_out + o;
+                    uint64_t *dst = a.acc + (e * a.G + j) * ct + (int64_t)s * N + k0 + kl;
+                    dst[0] = red[m][0];
+                    dst[(int64_t)ls * N] = red[m][1];
                 }
-                dst[0] = r0;
-                dst[(int64_t)L * N] = r1;
             }
         }
     }
+}
+
+static int launch_mac(const Ctx *c, const Plan *p, MacArgs &ma, const Batch &bout, hipStream_t s) {
+    const int R = bout.n / p->n_out;
+    double macs = 0;
+    int lmax = 0;
+    for (int e = 0; e < bout.n; ++e) {
+        lmax = std::max<int>(lmax, bout.level[e]);
+        macs += 2.0 * (bout.level[e] + (ma.ext ? c->K : 0)) * (double)c->N * ma.G * ma.B * p->n_in;
+    }
+    const int JT = std::min(ma.G, 16);
+    const int ES = 16 / JT;
+    const int ET = std::min(MAC_MY * ES, MAC_ET);
+    const int slots = ma.ext ? c->L + c->K : lmax;
+    ProfScope ps(c, s, PK_MAC, macs);
+    dim3 grid(c->N / MAC_K, slots, p->n_out * ((R + ET - 1) / ET));
+    if (c->small)
+        hipLaunchKernelGGL(k_mac<true>, grid, dim3(256), 0, s, ma, bout, c->d_mods, c->log_n, c->L, c->K, R, JT, ES, ET);
+    else
+        hipLaunchKernelGGL(k_mac<false>, grid, dim3(256), 0, s, ma, bout, c->d_mods, c->log_n, c->L, c->K, R, JT, ES,
+                           ET);
+    FL_TRY_HIP(hipGetLastError());
+    return FHELIN_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -269,12 +344,144 @@ static size_t limbs_per_request(const Ctx *c, const Plan *p, int Bp) {
            + emax * 2 * L;         // md
 }
 
-size_t linear_workspace_bytes(const Ctx *c, const Plan *p, int n_requests, int max_chunk) {
+static size_t limbs_per_request_dh(const Ctx *c, const Plan *p, int Bp) {
+    const size_t L = c->L, K = c->K, D = c->dnum, E = L + K;
+    const size_t ni = p->n_in, no = p->n_out, G = p->gk.size();
+    const size_t emax = std::max(ni, no);
+    return ni * 2 * L         // X
+           + ni * 2 * E        // P * X
+           + ni * D * E        // hoisted digits
+           + ni * Bp * 2 * E   // baby rotations (extended basis)
+           + no * G * 2 * E    // accumulators (extended basis)
+           + no * 2 * E        // giant-step sum (extended basis)
+           + no * 2 * L        // Y
+           + emax * 2 * L      // Q temp for ModDown(c1)
+           + emax * L          // coefficient temp
+           + emax * D * E      // giant digits
+           + emax * 2 * L;     // md
+}
+
+size_t linear_workspace_bytes(const Ctx *c, const Plan *p, int n_requests, int max_chunk, int flags) {
     int Bp = 0;
     for (int r : p->rb) Bp += galois_of_rotation(r, c->log_n) == 1 ? 0 : 1;
     int chunk = std::max(1, std::min(max_chunk, MAX_BATCH / std::max(p->n_in, p->n_out)));
     chunk = std::min(chunk, std::max(1, n_requests));
-    return limbs_per_request(c, p, Bp) * chunk * (size_t)c->N * sizeof(uint64_t);
+    size_t per = (flags & FHELIN_APPLY_HOIST_MODDOWN) ? limbs_per_request_dh(c, p, Bp) : limbs_per_request(c, p, Bp);
+    return per * chunk * (size_t)c->N * sizeof(uint64_t);
+}
+
+// Export Y (NTT, [2][L] per entry) to the caller's batch, with or without rescale.
+static int export_out(Ctx *c, const Batch &bout, uint64_t *Y, const fhelin_ct_batch *out, int64_t first_ct,
+                      bool rescale, hipStream_t s) {
+    const int64_t N = c->N, ct = 2 * (int64_t)c->L * N;
+    RowMap yr = rows_ct(c, bout, Y, ct, c->L, 0, 2);
+    FL_RET(launch_ntt(c, yr, 1, s));
+    const int64_t out_es = (int64_t)2 * out->stride * N;
+    uint64_t *ob = out->data + first_ct * out_es;
+    if (rescale) return launch_rescale(c, bout, Y, ct, c->L, ob, out_es, out->stride, s);
+    return launch_copy_rows(c, rows_ct(c, bout, ob, out_es, out->stride, 0, 2), yr, s);
+}
+
+// One chunk of requests with the double-hoisted schedule (Bossuat et al. 2021): baby
+// rotations, the multiply-accumulate and the giant-step sum stay in the extended basis
+// (carrying a factor P); each giant step ModDowns only c1 before its ModUp, and one
+// ModDown per output ends the layer.
+static int apply_chunk_dh(Ctx *c, const Plan *p, const KeySet *ks, const PtSet *pts, const fhelin_ct_batch *in,
+                          const fhelin_ct_batch *out, bool rescale, hipStream_t s, uint64_t *ws, int r0, int Rc,
+                          MacArgs ma, int Bp) {
+    const int64_t N = c->N, L = c->L, K = c->K, E = L + K;
+    const int B = (int)p->rb.size(), G = (int)p->gk.size();
+    const int64_t ct = 2 * L * N, ext = 2 * E * N, dg = (int64_t)c->dnum * E * N;
+    const int Ein = Rc * p->n_in, Eout = Rc * p->n_out, Emax = std::max(Ein, Eout);
+    uint64_t *X = ws, *XL = X + Ein * ct, *D = XL + Ein * ext, *RB = D + Ein * dg;
+    uint64_t *A = RB + (int64_t)Ein * Bp * ext, *YE = A + (int64_t)Eout * G * ext, *Y = YE + Eout * ext;
+    uint64_t *TQ = Y + Eout * ct, *TC = TQ + Emax * ct, *DG = TC + Emax * L * N, *MD = DG + Emax * dg;
+    Batch bin{}, bout{};
+    bin.n = Ein;
+    bout.n = Eout;
+    for (int e = 0; e < Ein; ++e) {
+        bin.level[e] = (uint8_t)in->levels[(r0 * p->n_in) + e];
+        bin.g[e] = 1;
+    }
+    for (int e = 0; e < Eout; ++e) {
+        bout.level[e] = (uint8_t)in->levels[(r0 + e / p->n_out) * p->n_in];
+        bout.g[e] = 1;
+    }
+    // 1. import
+    const int64_t in_es = (int64_t)2 * in->stride * N;
+    RowMap src = rows_ct(c, bin, in->data + (int64_t)r0 * p->n_in * in_es, in_es, in->stride, 0, 2);
+    RowMap dx = rows_ct(c, bin, X, ct, (int)L, 0, 2);
+    FL_RET(launch_copy_rows(c, dx, src, s));
+    FL_RET(launch_ntt(c, dx, 0, s));
+    // 2. P * x for the identity baby step
+    bool has_identity = false;
+    for (int b = 0; b < B; ++b) has_identity |= ma.bmap[b] < 0;
+    if (has_identity) FL_RET(launch_ext_lift_add(c, bin, X, ct, (int)L, 1, 0, XL, ext, s));
+    // 3. baby rotations in the extended basis: (P sigma(c0) + u0, u1)
+    if (Bp > 0) {
+        KsScratch wb{TC, L * N, D, dg, nullptr, 0, MD, ct};
+        FL_RET(modup_ct(c, bin, X, ct, (int)L, wb, s));
+        for (int b = 0; b < B; ++b) {
+            if (ma.bmap[b] < 0) continue;
+            uint32_t g = galois_of_rotation(p->rb[b], c->log_n);
+            int key = ks->find(g);
+            for (int e = 0; e < Ein; ++e) {
+                bin.g[e] = g;
+                bin.key[e] = (int16_t)key;
+            }
+            FL_RET(launch_ks_inner_add(c, bin, ks, D, dg, RB + ma.bmap[b] * ext, (int64_t)Bp * ext, X, ct, 0, 0, s));
+        }
+        for (int e = 0; e < Ein; ++e) bin.g[e] = 1;
+    }
+    // 4. multiply-accumulate over the extended basis
+    ma.x = XL;
+    ma.rb = RB;
+    ma.pts = pts->data;
+    ma.acc = A;
+    ma.n_in = p->n_in;
+    ma.n_out = p->n_out;
+    ma.B = B;
+    ma.Bp = Bp;
+    ma.G = G;
+    ma.pt_level = pts->level;
+    ma.ext = 1;
+    FL_RET(launch_mac(c, p, ma, bout, s));
+    // 5. giant steps summed in the extended basis
+    bool first = true;
+    KsScratch w{TC, L * N, DG, dg, nullptr, 0, MD, ct};
+    for (int j = 0; j < G; ++j) {
+        uint32_t g = galois_of_rotation(p->gk[j], c->log_n);
+        uint64_t *Aj = A + j * ext;
+        const int64_t a_es = (int64_t)G * ext;
+        if (g == 1) {
+            FL_RET(launch_ext_lift_add(c, bout, Aj, a_es, 0, 0, first ? 0 : 1, YE, ext, s));
+            first = false;
+            continue;
+        }
+        int key = ks->find(g);
+        for (int e = 0; e < Eout; ++e) {
+            bout.g[e] = g;
+            bout.key[e] = (int16_t)key;
+        }
+        // c1' = ModDown(A~_j.c1) -> poly 1 of TQ (NTT domain)
+        uint64_t *Aj1 = Aj + E * N;
+        FL_RET(launch_ntt(c, rows_kind(c, bout, Aj1, a_es, ROWS_EXT_P, 1), 1, s));
+        FL_RET(launch_moddown_fbc(c, bout, Aj1, a_es, MD, ct, s, 1));
+        FL_RET(launch_ntt(c, rows_ct(c, bout, MD, ct, (int)L, 0, 1), 0, s));
+        FL_RET(launch_moddown_combine(c, bout, Aj1, a_es, MD, ct, TQ + L * N, ct, (int)L, nullptr, 0, 0, 0, s, 1));
+        // ModUp(c1') and the inner product, plus sigma(A~_j.c0), summed into YE
+        FL_RET(modup_ct(c, bout, TQ, ct, (int)L, w, s));
+        FL_RET(launch_ks_inner_add(c, bout, ks, DG, dg, YE, ext, Aj, a_es, 1, first ? 0 : 1, s));
+        first = false;
+    }
+    for (int e = 0; e < Eout; ++e) bout.g[e] = 1;
+    // 6. final ModDown of both polynomials
+    FL_RET(launch_ntt(c, rows_kind(c, bout, YE, ext, ROWS_EXT_P, 2), 1, s));
+    FL_RET(launch_moddown_fbc(c, bout, YE, ext, MD, ct, s, 2));
+    FL_RET(launch_ntt(c, rows_ct(c, bout, MD, ct, (int)L, 0, 2), 0, s));
+    FL_RET(launch_moddown_combine(c, bout, YE, ext, MD, ct, Y, ct, (int)L, nullptr, 0, 0, 0, s, 2));
+    // 7. export
+    return export_out(c, bout, Y, out, (int64_t)r0 * p->n_out, rescale, s);
 }
 
 int linear_apply(Ctx *c, const Plan *p, const KeySet *ks, const PtSet *pts, const fhelin_ct_batch *in,
@@ -313,9 +520,17 @@ int linear_apply(Ctx *c, const Plan *p, const KeySet *ks, const PtSet *pts, cons
     int chunk = std::max(1, std::min(max_chunk, MAX_BATCH / std::max(p->n_in, p->n_out)));
     chunk = std::min(chunk, R);
     uint64_t *ws;
-    FL_RET(workspace_get(c, s, limbs_per_request(c, p, Bp) * chunk * N * sizeof(uint64_t), &ws));
+    const bool dh = flags & FHELIN_APPLY_HOIST_MODDOWN;
+    FL_RET(workspace_get(c, s, (dh ? limbs_per_request_dh(c, p, Bp) : limbs_per_request(c, p, Bp)) * chunk * N *
+                                   sizeof(uint64_t),
+                         &ws));
 
     const int64_t ct = 2 * L * N, dg = (int64_t)c->dnum * (L + K) * N;
+    if (dh) {
+        for (int r0 = 0; r0 < R; r0 += chunk)
+            FL_RET(apply_chunk_dh(c, p, ks, pts, in, out, rescale, s, ws, r0, std::min(chunk, R - r0), ma, Bp));
+        return FHELIN_OK;
+    }
     for (int r0 = 0; r0 < R; r0 += chunk) {
         const int Rc = std::min(chunk, R - r0);
         const int Ein = Rc * p->n_in, Eout = Rc * p->n_out, Emax = std::max(Ein, Eout);
@@ -369,18 +584,8 @@ int linear_apply(Ctx *c, const Plan *p, const KeySet *ks, const PtSet *pts, cons
         ma.Bp = Bp;
         ma.G = G;
         ma.pt_level = pts->level;
-        {
-            int lmax = 0;
-            double macs = 0;
-            for (int e = 0; e < Eout; ++e) {
-                lmax = std::max<int>(lmax, bout.level[e]);
-                macs += 2.0 * bout.level[e] * (double)c->N * G * B * p->n_in;
-            }
-            ProfScope ps(c, s, PK_MAC, macs);
-            hipLaunchKernelGGL(k_mac, dim3(c->N / 256, lmax, (Eout + MAC_GROUP - 1) / MAC_GROUP), dim3(256), 0, s, ma,
-                               bout, c->d_mods, c->log_n, c->L);
-            FL_TRY_HIP(hipGetLastError());
-        }
+        ma.ext = 0;
+        FL_RET(launch_mac(c, p, ma, bout, s));
         // 5. giant steps, summed into Y
         bool first = true;
         for (int j = 0; j < G; ++j) {

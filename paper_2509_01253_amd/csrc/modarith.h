@@ -57,9 +57,63 @@ __device__ __forceinline__ uint64_t redc(uint64_t lo, uint64_t hi, uint64_t q, u
 
 __device__ __forceinline__ uint64_t redc(const Acc128 &a, uint64_t q, uint64_t ninv) { return redc(a.lo, a.hi, q, ninv); }
 
+// Lazy sum of up to 16 products a*b with a, b < 2^56, split on 32-bit halves:
+// a b = a0 b0 + (a0 b1 + a1 b0) 2^32 + a1 b1 2^64 with a1, b1 < 2^24, so the middle and
+// high sums cannot overflow 64 bits in 16 terms and the low sum only needs a carry count.
+// Four 32x32->64 multiply-adds per product instead of a full 64x64->128 product.
+struct Acc56 {
+    uint64_t s0, s1, s2;
+    uint32_t c0;
+};
+
+__device__ __forceinline__ void acc56_zero(Acc56 &A) {
+    A.s0 = A.s1 = A.s2 = 0;
+    A.c0 = 0;
+}
+
+__device__ __forceinline__ void mac56(Acc56 &A, uint64_t a, uint64_t b) {
+    const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32), b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
+    const uint64_t t = A.s0 + (uint64_t)a0 * b0;
+    A.c0 += t < A.s0 ? 1u : 0u;
+    A.s0 = t;
+    A.s1 += (uint64_t)a0 * b1;
+    A.s1 += (uint64_t)a1 * b0;
+    A.s2 += (uint64_t)a1 * b1;
+}
+
+// Montgomery reduction of the accumulated sum (requires sum < q 2^64: 16 q < 2^64)
+__device__ __forceinline__ uint64_t redc56(const Acc56 &A, uint64_t q, uint64_t ninv);
+
 __device__ __forceinline__ uint64_t mont_mul(uint64_t a, uint64_t b_mont, uint64_t q, uint64_t ninv) {
     return redc(a * b_mont, mulhi64(a, b_mont), q, ninv);
 }
+
+__device__ __forceinline__ uint64_t redc56(const Acc56 &A, uint64_t q, uint64_t ninv) {
+    const uint64_t lo = A.s0 + (A.s1 << 32);
+    const uint64_t hi = (uint64_t)A.c0 + A.s2 + (A.s1 >> 32) + (lo < A.s0 ? 1 : 0);
+    return redc(lo, hi, q, ninv);
+}
+
+// A 16-term lazy accumulator over either representation: SMALL (all moduli < 2^56)
+// uses Acc56, otherwise full 128-bit products.
+template <bool SMALL>
+struct LazyAcc;
+
+template <>
+struct LazyAcc<true> {
+    Acc56 a;
+    __device__ __forceinline__ void zero() { acc56_zero(a); }
+    __device__ __forceinline__ void mac(uint64_t x, uint64_t y) { mac56(a, x, y); }
+    __device__ __forceinline__ uint64_t reduce(uint64_t q, uint64_t ninv) const { return redc56(a, q, ninv); }
+};
+
+template <>
+struct LazyAcc<false> {
+    Acc128 a;
+    __device__ __forceinline__ void zero() { a = Acc128{0, 0}; }
+    __device__ __forceinline__ void mac(uint64_t x, uint64_t y) { mac128(a, x, y); }
+    __device__ __forceinline__ uint64_t reduce(uint64_t q, uint64_t ninv) const { return redc(a, q, ninv); }
+};
 
 // ---------------------------------------------------------------------------
 // host helpers (context setup only)

@@ -32,6 +32,7 @@ _pvp = ctypes.POINTER(ctypes.c_void_p)
 FHELIN_LAYER_FC = 1
 FHELIN_LAYER_CONV = 2
 FHELIN_APPLY_RESCALE = 1
+FHELIN_APPLY_HOIST_MODDOWN = 2
 
 STATUS = {
     0: "FHELIN_OK", -1: "FHELIN_E_INVALID_ARG", -2: "FHELIN_E_UNSUPPORTED_PARAM", -3: "FHELIN_E_LEVEL_MISMATCH",
@@ -198,12 +199,14 @@ def fhelin_keyset_release(ks):
     _check(_lib.fhelin_keyset_release(ks))
 
 
-def fhelin_pt_import(ctx, pt: torch.Tensor, stream=None):
-    """pt: [n_pt][level][N] 8-byte integers (GPU or CPU)."""
+def fhelin_pt_import(ctx, pt: torch.Tensor, level=None, stream=None):
+    """pt: [n_pt][level + K][N] 8-byte integers (GPU or CPU); K = number of special primes."""
     if pt.dtype not in _W64 or not pt.is_contiguous() or pt.dim() != 3:
-        raise ValueError("pt must be a contiguous [n_pt][level][N] 8-byte integer tensor")
+        raise ValueError("pt must be a contiguous [n_pt][level + K][N] 8-byte integer tensor")
+    if level is None:
+        raise ValueError("level is required")
     out = _vp()
-    _check(_lib.fhelin_pt_import(ctx, _vp(pt.data_ptr()), pt.shape[0], pt.shape[1], 1 if pt.is_cuda else 0,
+    _check(_lib.fhelin_pt_import(ctx, _vp(pt.data_ptr()), pt.shape[0], level, 1 if pt.is_cuda else 0,
                                  _stream(stream), ctypes.byref(out)))
     return out
 

@@ -53,7 +53,8 @@ def random_ct(prm: O.Params, stream, level: int) -> np.ndarray:
 
 
 def encode_pts(prm: O.Params, slots: np.ndarray, level: int, delta: float) -> np.ndarray:
-    """Slot vectors [..., S] -> integer plaintexts [..., level, N] (coefficient domain)."""
+    """Slot vectors [..., S] -> integer plaintexts [..., level + K, N] (coefficient domain,
+    residues mod q_0..q_{level-1} then p_0..p_{K-1})."""
     flat = slots.reshape(-1, slots.shape[-1])
-    out = np.stack([O.encode_rns(prm, z, level, delta) for z in flat])
-    return out.reshape(slots.shape[:-1] + (level, prm.N))
+    out = np.stack([O.encode_rns(prm, z, level, delta, ext=True) for z in flat])
+    return out.reshape(slots.shape[:-1] + (level + prm.K, prm.N))

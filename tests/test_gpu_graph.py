@@ -31,7 +31,7 @@ def test_graph_replays_match_eager():
     try:
         plan = F.fhelin_plan_create(ctx, F.FHELIN_LAYER_FC, fc_n=n, fc_out=n, fc_in=n, n1=n1)
         ks = F.fhelin_keyset_load(ctx, keys.galois, prm.L, dev(keys_at(prm, keys, prm.L)))
-        pset = F.fhelin_pt_import(ctx, dev(pts.reshape(-1, prm.L, prm.N)))
+        pset = F.fhelin_pt_import(ctx, dev(pts.reshape(-1, prm.L + prm.K, prm.N)), level=prm.L)
         torch.cuda.synchronize()
         inputs = []
         for rep in range(3):
@@ -41,9 +41,9 @@ def test_graph_replays_match_eager():
         x = dev(inputs[0])
         y = dev(np.zeros_like(inputs[0]))
         out_levels = [l - 1 for l in levels]
+        flags = F.FHELIN_APPLY_RESCALE | F.FHELIN_APPLY_HOIST_MODDOWN
         with torch.cuda.stream(stream):
-            g = F.fhelin_graph_capture_linear(ctx, plan, ks, pset, x, levels, y, out_levels,
-                                              F.FHELIN_APPLY_RESCALE, stream=stream)
+            g = F.fhelin_graph_capture_linear(ctx, plan, ks, pset, x, levels, y, out_levels, flags, stream=stream)
         y_eager = dev(np.zeros_like(inputs[0]))
         for rep in range(3):
             x.copy_(dev(inputs[rep]))
@@ -52,7 +52,7 @@ def test_graph_replays_match_eager():
             stream.synchronize()
             got = host(y)
             # eager reference on the default stream, then some unrelated eager work
-            F.fhelin_linear_apply(ctx, plan, ks, pset, x, levels, y_eager, out_levels, F.FHELIN_APPLY_RESCALE)
+            F.fhelin_linear_apply(ctx, plan, ks, pset, x, levels, y_eager, out_levels, flags)
             torch.cuda.synchronize()
             want = host(y_eager)
             assert np.array_equal(got, want), rep
@@ -62,7 +62,8 @@ def test_graph_replays_match_eager():
             # and against the oracle for one request
             t = rep % len(levels)
             l = levels[t]
-            ref = O.rescale(prm, O.linear(prm, inputs[rep][t, :, :l][None], l, sched, pts, keys)[0], l)
+            ref = O.rescale(prm, O.linear(prm, inputs[rep][t, :, :l][None], l, sched, pts, keys,
+                                          hoist_moddown=True)[0], l)
             assert np.array_equal(got[t, :, : l - 1], ref), rep
         F.fhelin_graph_destroy(g)
         F.fhelin_ptset_release(pset)

@@ -38,9 +38,10 @@ class Layer:
             self.ks = F.fhelin_keyset_load(self.ctx, keys.galois, level_keys, dev(keys_at(prm, keys, level_keys)))
         self.pset = None
         if pts is not None:
-            self.pset = F.fhelin_pt_import(self.ctx, dev(pts.reshape(-1, pts.shape[-2], prm.N)))
+            self.pset = F.fhelin_pt_import(self.ctx, dev(pts.reshape(-1, pts.shape[-2], prm.N)),
+                                           level=pts.shape[-2] - prm.K)
 
-    def apply(self, cts, levels, rescale=True, stride=None):
+    def apply(self, cts, levels, rescale=True, stride=None, dh=False):
         prm, F = self.prm, self.F
         stride = stride or max(levels)
         x = dev(pad_cts(cts, stride, prm.N))
@@ -48,8 +49,8 @@ class Layer:
         req_levels = [levels[r * self.info["n_in"]] for r in range(len(cts) // self.info["n_in"])]
         out_levels = [l - 1 if rescale else l for l in req_levels for _ in range(self.info["n_out"])]
         y = dev(np.zeros((n_out, 2, stride, prm.N), np.uint64))
-        F.fhelin_linear_apply(self.ctx, self.plan, self.ks, self.pset, x, levels, y, out_levels,
-                              F.FHELIN_APPLY_RESCALE if rescale else 0)
+        flags = (F.FHELIN_APPLY_RESCALE if rescale else 0) | (F.FHELIN_APPLY_HOIST_MODDOWN if dh else 0)
+        F.fhelin_linear_apply(self.ctx, self.plan, self.ks, self.pset, x, levels, y, out_levels, flags)
         got = host(y)
         return [got[t, :, : out_levels[t]] for t in range(n_out)]
 
@@ -190,12 +191,12 @@ def test_encode_within_one_unit(F):
             st = synth.Stream(4300 + log_n)
             z = np.stack([st.uniform(prm.S, -1, 1), st.he_normal(prm.S, 16), np.full(prm.S, 0.25)])
             pset = F.fhelin_pt_encode(ctx, torch.from_numpy(z).cuda(), 3, prm.scale)
-            out = dev(np.zeros((3, 3, prm.N), np.uint64))
+            out = dev(np.zeros((3, 3 + prm.K, prm.N), np.uint64))
             F.fhelin_pt_export(ctx, pset, 3, out)
             got = host(out)
             for i in range(3):
                 m = O.encode(z[i], log_n, prm.scale)
-                for j, q in enumerate(prm.q[:3]):
+                for j, q in enumerate(prm.q[:3] + prm.p):
                     d = (got[i, j].astype(object) - O.to_rns(m, [q])[0].astype(object)) % q
                     d = np.array([v if v <= q // 2 else v - q for v in d], dtype=np.int64)
                     assert np.abs(d).max() <= 1, (log_n, i, j)
@@ -246,10 +247,10 @@ def test_encode_weights_with_shuffle(F, kind):
             lay.ctx, lay.plan, torch.from_numpy(np.ascontiguousarray(W)).cuda(),
             torch.from_numpy(po).cuda(), torch.from_numpy(pi).cuda(), level, prm.scale)
         n_pt = lay.info["n_pt"]
-        out = dev(np.zeros((n_pt, level, prm.N), np.uint64))
+        out = dev(np.zeros((n_pt, level + prm.K, prm.N), np.uint64))
         F.fhelin_pt_export(lay.ctx, lay.pset, level, out)
         got = host(out)
-        want = encode_pts(prm, slots, level, prm.scale).reshape(n_pt, level, prm.N)
+        want = encode_pts(prm, slots, level, prm.scale).reshape(n_pt, level + prm.K, prm.N)
         q0 = prm.q[0]
         d = (got[:, 0].astype(np.int64) - want[:, 0].astype(np.int64))
         d = np.where(d > q0 // 2, d - q0, np.where(d < -(q0 // 2), d + q0, d))
@@ -261,5 +262,61 @@ def test_encode_weights_with_shuffle(F, kind):
             assert _rel(dec[0][:100], ref) < 1e-3
         else:
             assert _rel(O.conv_output_from_slots(dec, cs, prm.S), ref) < 1e-3
+    finally:
+        lay.close()
+
+
+# ---------------------------------------------------------------------------
+# the double-hoisted schedule
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n1", [8, 64, 1])
+def test_fc_double_hoisted_bit_exact(F, n1):
+    print(f"dh fc n1={n1}", flush=True)
+    prm = O.make_params(12, 6, 2, 3, 50, 2.0 ** 40)
+    st = synth.Stream(4500 + n1)
+    n = 64
+    W = st.he_normal((n, n), n)
+    sched = O.fc_schedule(n, n1)
+    pts = encode_pts(prm, O.fc_slots(W, n, n1, prm.S), prm.L, prm.scale)
+    cl = Client(prm, 4501)
+    keys = cl.keyset(sched.rotations())
+    levels = [6, 2, 5, 3]
+    xs = [st.uniform(n, 0, 1) for _ in levels]
+    cts = [cl.encrypt_slots(O.fc_input_slots(x, n, prm.S), l, prm.scale) for x, l in zip(xs, levels)]
+    lay = Layer(F, prm, keys, pts, prm.L, fc_n=n, fc_out=n, fc_in=n, n1=n1)
+    try:
+        got = lay.apply(cts, levels, stride=prm.L, dh=True)
+        for t, l in enumerate(levels):
+            want = O.rescale(prm, O.linear(prm, cts[t][None], l, sched, pts, keys, hoist_moddown=True)[0], l)
+            assert np.array_equal(got[t], want), t
+            z = cl.decrypt_slots(got[t], l - 1, prm.scale ** 2 / prm.q[l - 1]).real
+            assert _rel(z[:n], W @ xs[t]) < 1e-3, t
+        nr = lay.apply(cts[:1], levels[:1], rescale=False, stride=prm.L, dh=True)[0]
+        assert np.array_equal(nr, O.linear(prm, cts[0][None], levels[0], sched, pts, keys, hoist_moddown=True)[0])
+    finally:
+        lay.close()
+
+
+@pytest.mark.parametrize("c_in,c_out,k", [(16, 16, 3), (16, 8, 1)])
+def test_conv_double_hoisted_bit_exact(F, c_in, c_out, k):
+    print(f"dh conv {c_in}->{c_out} k{k}", flush=True)
+    prm = O.make_params(10, 4, 2, 2, 50, 2.0 ** 40)
+    cs = O.ConvShape(c_in, c_out, 8, 8, k)
+    st = synth.Stream(4600 + k)
+    W = st.he_normal((c_out, c_in, k, k), c_in * k * k)
+    sched = O.conv_schedule(cs, prm.S)
+    level = 3
+    pts = encode_pts(prm, O.conv_slots(W, cs, prm.S), level, prm.scale)
+    cl = Client(prm, 4601)
+    keys = cl.keyset(sched.rotations())
+    x = st.uniform(c_in * 64, 0, 1).reshape(c_in, 8, 8)
+    slots = O.conv_input_slots(x, cs, prm.S)
+    cts = [cl.encrypt_slots(slots[i], level, prm.scale) for i in range(sched.n_in)]
+    lay = Layer(F, prm, keys, pts, level, c_in=c_in, c_out=c_out, h=8, w=8, k=k)
+    try:
+        got = lay.apply(cts, [level] * len(cts), dh=True)
+        want = O.linear(prm, np.stack(cts), level, sched, pts, keys, hoist_moddown=True)
+        for o in range(sched.n_out):
+            assert np.array_equal(got[o], O.rescale(prm, want[o], level)), o
     finally:
         lay.close()

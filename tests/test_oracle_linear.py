@@ -174,8 +174,84 @@ def test_missing_key_reported(small):
     prm = small
     cl = Client(prm, 400)
     sched = O.fc_schedule(64, 8)
-    pts = np.zeros((1, 1, sched.G, sched.B, 3, prm.N), np.uint64)
+    pts = np.zeros((1, 1, sched.G, sched.B, 3 + prm.K, prm.N), np.uint64)
     ct = np.zeros((1, 2, 3, prm.N), np.uint64)
     keys = cl.keyset([1, 2])
     with pytest.raises(KeyError):
         O.linear(prm, ct, 3, sched, pts, keys)
+    with pytest.raises(KeyError):
+        O.linear(prm, ct, 3, sched, pts, keys, hoist_moddown=True)
+
+
+# ---------------------------------------------------------------------------
+# the double-hoisted schedule (ModDown hoisted out of baby and giant steps)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n,n1", [(64, 8), (64, 64), (64, 1)])
+def test_fc_double_hoisted_decrypts(small, n, n1):
+    prm = small
+    st = synth.Stream(500 + n1)
+    W = st.he_normal((n, n), n)
+    x = st.uniform(n, 0, 1)
+    cl = Client(prm, 501)
+    sched = O.fc_schedule(n, n1)
+    pts = encode_pts(prm, O.fc_slots(W, n, n1, prm.S), 4, prm.scale)
+    ct = cl.encrypt_slots(O.fc_input_slots(x, n, prm.S), 4, prm.scale)
+    keys = cl.keyset(sched.rotations())
+    y_dh = O.linear(prm, ct[None], 4, sched, pts, keys, hoist_moddown=True)[0]
+    y_std = O.linear(prm, ct[None], 4, sched, pts, keys)[0]
+    z_dh = cl.decrypt_slots(O.rescale(prm, y_dh, 4), 3, prm.scale ** 2 / prm.q[3]).real
+    z_std = cl.decrypt_slots(O.rescale(prm, y_std, 4), 3, prm.scale ** 2 / prm.q[3]).real
+    assert _rel_err(z_dh[:n], W @ x) < 1e-3
+    # both schedules compute the same layer; they differ only in rounding noise
+    assert np.abs(z_dh - z_std).max() < 1e-6 * np.abs(W @ x).max() * 1e3
+    if n1 > 1:
+        assert not np.array_equal(y_dh, y_std)
+
+
+def test_conv_double_hoisted_decrypts(small):
+    prm = small
+    cs = O.ConvShape(16, 16, 8, 8, 3)
+    st = synth.Stream(510)
+    W = st.he_normal((16, 16, 3, 3), 144)
+    x = st.uniform(16 * 64, 0, 1).reshape(16, 8, 8)
+    sched = O.conv_schedule(cs, prm.S)
+    pts = encode_pts(prm, O.conv_slots(W, cs, prm.S), 3, prm.scale)
+    cl = Client(prm, 511)
+    xs = O.conv_input_slots(x, cs, prm.S)
+    cts = np.stack([cl.encrypt_slots(xs[i], 3, prm.scale) for i in range(sched.n_in)])
+    y = O.linear(prm, cts, 3, sched, pts, cl.keyset(sched.rotations()), hoist_moddown=True)
+    dec = np.stack([cl.decrypt_slots(O.rescale(prm, y[o], 3), 2, prm.scale ** 2 / prm.q[2]).real
+                    for o in range(sched.n_out)])
+    assert _rel_err(O.conv_output_from_slots(dec, cs, prm.S), O.conv_ref(W, x)) < 1e-3
+
+
+def test_double_hoisted_identity_exact_division():
+    """W = I with n1 = n: only the r=0 baby step and G=0 giant step contribute, so the
+    result is exactly ModDown((P x0, P x1) * pt) = x * pt (the P factor divides out with
+    no rounding: P*v has zero residues mod every p_k)."""
+    prm = O.make_params(8, 3, 2, 3, 40, 2.0 ** 30)
+    cl = Client(prm, 520)
+    n = 16
+    sched = O.fc_schedule(n, n)
+    pts = encode_pts(prm, O.fc_slots(np.eye(n), n, n, prm.S), 3, prm.scale)
+    ct = cl.encrypt_slots(O.fc_input_slots(synth.Stream(521).uniform(n, -1, 1), n, prm.S), 3, prm.scale)
+    y = O.linear(prm, ct[None], 3, sched, pts, cl.keyset(sched.rotations()), hoist_moddown=True)[0]
+    assert np.array_equal(y, O.mul_pt(prm, ct, pts[0, 0, 0, 0, :3], 3))
+
+
+def test_double_hoisted_schoolbook_identical():
+    prm = O.make_params(7, 3, 1, 3, 40, 2.0 ** 30)
+    cl = Client(prm, 530)
+    st = synth.Stream(531)
+    W = st.uniform(16 * 16, -1, 1).reshape(16, 16)
+    sched = O.fc_schedule(16, 4)
+    pts = encode_pts(prm, O.fc_slots(W, 16, 4, prm.S), 3, prm.scale)
+    ct = cl.encrypt_slots(O.fc_input_slots(st.uniform(16, -1, 1), 16, prm.S), 3, prm.scale)
+    keys = cl.keyset(sched.rotations())
+    a = O.linear(prm, ct[None], 3, sched, pts, keys, hoist_moddown=True)
+    O.set_schoolbook(True)
+    try:
+        b = O.linear(prm, ct[None], 3, sched, pts, keys, hoist_moddown=True)
+    finally:
+        O.set_schoolbook(False)
+    assert np.array_equal(a, b)
