@@ -42,6 +42,13 @@ def parse():
     ap.add_argument("--schedule", choices=["rotation", "hoisted"], default="hoisted",
                     help="per-rotation ModDown, or the double-hoisted schedule")
     ap.add_argument("--n1", type=int, default=16, help="baby steps of the 256x256 FC (power of two)")
+    ap.add_argument("--serve-requests", type=int, default=0,
+                    help="requests per arrival rate in an extra serving run (default 0 = no serving run)")
+    ap.add_argument("--serve-rates", type=str, default="20,100", help="Poisson arrival rates (req/s)")
+    ap.add_argument("--serve-clients", type=int, default=32)
+    ap.add_argument("--calib-copy", type=float, default=0.0,
+                    help="instead of the benchmark: copy this many GiB device-to-device 3 times (traffic-counter "
+                         "calibration)")
     return ap.parse_args()
 
 
@@ -85,10 +92,104 @@ def cpu_baseline(level: int, n1: int, hoisted: bool) -> dict:
                       f"schedule, 256 pt-MACs, rescale) at level {level} of the N=2^16 workload; {dt:.1f} s"}
 
 
+def serve_bench(args) -> dict:
+    """Serving run: Poisson arrivals mixing an N=2^15 job (ResNet-20-block conv 3x3
+    16->16 on 32x32, 8 + 2 primes, levels 2..8) and an N=2^16 job (ResNet-18 stage-1
+    conv 3x3 64->64 on 64x64, 8 input and 8 output ciphertexts, 12 + 3 primes, levels
+    2..12), up to 32 clients with their own key sets, admitted by an HBM budget, with
+    continuous batching on 4 streams; compared with the same requests served one at a
+    time on one stream."""
+    import torch
+
+    from paper_2509_01253_amd import fhelin as F
+    from paper_2509_01253_amd import synth
+    from paper_2509_01253_amd.serving import GpuExecutor, Request, Server, poisson_timeline
+
+    root = synth.Stream(synth.master_seed(5))
+    dev = torch.device("cuda:0")
+    jobs = {
+        "conv16": dict(params="N15", log_n=15, L=8, K=2, dnum=4, c=16, hw=32, lmin=2),
+        "conv64": dict(params="N16", log_n=16, L=12, K=3, dnum=4, c=64, hw=64, lmin=2),
+    }
+    ex = GpuExecutor(n_streams=4)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(int(root.sub(synth.TAG_KEYS).u64(1)[0] & 0x7FFFFFFFFFFFFFFF))
+    info = {}
+    for name, j in jobs.items():
+        pr = F.fhelin_primes_generate(j["log_n"], 50, j["K"] + j["L"])
+        p, q = pr[: j["K"]], pr[j["K"]:]
+        ex.add_params(j["params"], j["log_n"], q, p, j["dnum"])
+        ctx = ex.params[j["params"]]["ctx"]
+        kw = dict(c_in=j["c"], c_out=j["c"], h=j["hw"], w=j["hw"], k=3)
+        plan = F.fhelin_plan_create(ctx, F.FHELIN_LAYER_CONV, **kw)
+        W = torch.from_numpy(root.sub(synth.TAG_W).sub(j["c"]).he_normal((j["c"], j["c"], 3, 3), 9 * j["c"])).to(dev)
+        pts = F.fhelin_plan_encode_weights(ctx, plan, W, None, None, j["L"], 2.0 ** 40)
+        F.fhelin_plan_destroy(plan)
+        ex.add_layer(name, j["params"], kw, F.FHELIN_LAYER_CONV, pts)
+        gal = ex.layers[name]["galois"]
+        N, L, K = 1 << j["log_n"], j["L"], j["K"]
+        beta = -(-L // -(-L // j["dnum"]))
+        mods = q + p
+
+        def source(stream, gal=gal, N=N, L=L, K=K, beta=beta, mods=mods):
+            evk = torch.empty((len(gal), beta, 2, L + K, N), dtype=torch.int64, device=dev)
+            for m, qm in enumerate(mods):
+                evk[:, :, :, m].random_(0, qm, generator=gen)
+            return gal, L, evk
+
+        nbytes = len(gal) * beta * 2 * (L + K) * N * 8
+        for ci in range(args.serve_clients):
+            ex.add_client_keys(f"c{ci}", j["params"], source, nbytes)
+        info[name] = dict(n_in=ex.layers[name]["n_in"], N=N, L=L, q=q)
+    torch.cuda.synchronize()
+
+    def make_requests(rate, seed):
+        st = root.sub(synth.TAG_ARRIVAL).sub(seed)
+        times = poisson_timeline(rate, args.serve_requests, st)
+        lv = root.sub(synth.TAG_LEVEL).sub(seed)
+        reqs, rounds = [], {}
+        for i in range(args.serve_requests):
+            name = "conv16" if i % 2 == 0 else "conv64"
+            j, I = jobs[name], info[name]
+            ci = int(st.integers(1, 0, args.serve_clients - 1)[0])
+            level = int(lv.integers(1, j["lmin"], I["L"])[0])
+            x = torch.empty((I["n_in"], 2, level, I["N"]), dtype=torch.int64, device=dev)
+            for li in range(level):
+                x[:, :, li].random_(0, I["q"][li], generator=gen)
+            sess = f"s{ci}"
+            rounds[sess] = rounds.get(sess, 0) + 1
+            reqs.append((float(times[i]), Request(i, f"c{ci}", sess, rounds[sess], name, level, x)))
+        torch.cuda.synchronize()
+        return reqs
+
+    out = {"workload": "Poisson mix of conv 16->16 @32x32 (N=2^15, levels 2..8) and conv 64->64 @64x64 "
+                       "(N=2^16, 8 in / 8 out ciphertexts, levels 2..12), "
+                       f"{args.serve_clients} clients with their own keys, HBM budget 200 GiB",
+           "rates": {}}
+    for ri, rate in enumerate(float(r) for r in args.serve_rates.split(",")):
+        row = {}
+        for mode, streams, mb in (("continuous", 4, 64), ("one_at_a_time", 1, 1)):
+            reqs = make_requests(rate, ri)
+            srv = Server(ex, hbm_budget=200 << 30, streams=streams, max_batch=mb)
+            for ci in range(args.serve_clients):
+                srv.open_session(f"s{ci}", f"c{ci}")
+            res = srv.run(reqs)
+            st = srv.stats(res)
+            row[mode] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items()}
+            for k in list(srv.keys):
+                ex.release_keys(srv.keys.pop(k).handle)
+            del reqs, res
+            torch.cuda.synchronize()
+        out["rates"][str(int(rate))] = row
+    ex.close()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "one GPU only: requests scale out by routing clients to GPUs, not by splitting a "
+                                   "layer; --gpus must be 1"}))
         sys.exit(2)
     import torch
 
@@ -96,6 +197,16 @@ def main():
     from paper_2509_01253_amd import synth
 
     assert torch.cuda.is_available(), "bench needs a GPU"
+    if args.calib_copy > 0:
+        n = int(args.calib_copy * (1 << 30)) // 8
+        a = torch.ones(n, dtype=torch.int64, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calib_copy_bytes_read": n * 8, "calib_copy_bytes_written": n * 8, "copies": 3}))
+        return
     dev = torch.device("cuda:0")
     w = WORKLOAD
     primes = F.fhelin_primes_generate(w["log_n"], w["bits"], w["K"] + w["L"])
@@ -219,6 +330,8 @@ def main():
     }
     F.fhelin_plan_destroy(plan)
     F.fhelin_ctx_destroy(ctx)
+    if args.serve_requests > 0:
+        res["serving"] = serve_bench(args)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(args.cpu_level, args.n1, args.schedule == "hoisted")
     print(json.dumps(res), flush=True)

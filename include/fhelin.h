@@ -218,6 +218,21 @@ typedef struct {
 int fhelin_linear_apply(fhelin_ctx *ctx, const fhelin_plan *plan, const fhelin_keyset *ks, const fhelin_ptset *pts,
                         const fhelin_ct_batch *in, const fhelin_ct_batch *out, int32_t flags, void *stream);
 
+/* Workspace (bytes of device memory) that fhelin_linear_apply needs on a
+ * stream for n_requests requests of this plan with these flags; the stream's
+ * workspace grows to it on first use and is charged to the budget.  Lets a
+ * scheduler admit work by memory before launching it. */
+int fhelin_plan_workspace_bytes(fhelin_ctx *ctx, const fhelin_plan *plan, int32_t n_requests, int32_t flags,
+                                uint64_t *bytes);
+
+/* fhelin_linear_apply with one key set per request (ks_per_request[R], host
+ * array; requests from different clients batched in one call).  Every key set
+ * must belong to ctx and cover the plan's Galois elements at the request's
+ * level.  Results equal per-request fhelin_linear_apply calls bit for bit. */
+int fhelin_linear_apply_multi(fhelin_ctx *ctx, const fhelin_plan *plan, const fhelin_keyset *const *ks_per_request,
+                              const fhelin_ptset *pts, const fhelin_ct_batch *in, const fhelin_ct_batch *out,
+                              int32_t flags, void *stream);
+
 /* Capture the kernels of one fhelin_linear_apply call (same arguments) into a
  * HIP graph and instantiate it; nothing runs at capture time.  The device
  * buffers, levels, keys and plaintexts are baked in: each fhelin_graph_launch

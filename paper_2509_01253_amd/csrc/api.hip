@@ -8,7 +8,7 @@ namespace fl {
 int primes_generate(int log_n, int bits, int count, uint64_t *out);
 const char *last_error();
 int plan_create(Ctx *c, const fhelin_layer_desc *d, Plan **out);
-int linear_apply(Ctx *c, const Plan *p, const KeySet *ks, const PtSet *pts, const fhelin_ct_batch *in,
+int linear_apply(Ctx *c, const Plan *p, const KeySet *const *kss, const PtSet *pts, const fhelin_ct_batch *in,
                  const fhelin_ct_batch *out, int flags, hipStream_t s, int max_chunk);
 size_t linear_workspace_bytes(const Ctx *c, const Plan *p, int n_requests, int max_chunk, int flags);
 
@@ -16,6 +16,7 @@ size_t linear_workspace_bytes(const Ctx *c, const Plan *p, int n_requests, int m
 // buffers, replayed with hipGraphLaunch.
 struct Graph {
     Ctx *ctx = nullptr;
+    std::shared_ptr<WsBuf> ws;  // the workspace the captured kernels use
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     ~Graph() {
@@ -30,11 +31,17 @@ static int graph_capture_linear(Ctx *c, const Plan *p, const KeySet *ks, const P
     FL_CHECK(s != nullptr, FHELIN_E_INVALID_ARG, "graph capture needs a non-null stream");
     // size the stream's workspace before capture (no allocation may happen inside it)
     uint64_t *ws;
-    FL_RET(workspace_get(c, s, linear_workspace_bytes(c, p, in->n_ct / std::max(1, p->n_in), MAX_BATCH, flags), &ws));
     std::unique_ptr<Graph> gr(new Graph());
     gr->ctx = c;
+    FL_RET(workspace_get(c, s, linear_workspace_bytes(c, p, in->n_ct / std::max(1, p->n_in), MAX_BATCH, flags), &ws,
+                         &gr->ws));
+    const int R = in->n_ct / std::max(1, p->n_in);
+    std::vector<const KeySet *> kss((size_t)std::max(1, R), ks);
+    // loads still in flight on other streams finish before the capture (no cross-capture waits)
+    if (ks) FL_RET(ks->ready.host_wait());
+    if (pts) FL_RET(pts->ready.host_wait());
     FL_TRY_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    int rc = linear_apply(c, p, ks, pts, in, out, flags, s, MAX_BATCH);
+    int rc = linear_apply(c, p, kss.data(), pts, in, out, flags, s, MAX_BATCH);
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(s, &graph);
     if (rc != FHELIN_OK) {
@@ -112,6 +119,7 @@ static int keyset_load(Ctx *c, const uint32_t *galois, int n_keys, int level, co
         rc = launch_ntt(c, e2, 0, s);
         if (rc == FHELIN_OK) rc = launch_to_mont(c, e2, s);
     }
+    if (rc == FHELIN_OK) rc = k->ready.record(s);
     if (rc) {
         dev_free(c, k->evk, k->bytes);
         return rc;
@@ -379,8 +387,31 @@ FHELIN_EXPORT int fhelin_linear_apply(fhelin_ctx *ctx, const fhelin_plan *plan, 
     API_BEGIN FL_CHECK(ctx, FHELIN_E_INVALID_ARG, "null context");
     Ctx *c = (Ctx *)ctx;
     DeviceGuard g(c);
-    return linear_apply(c, (const Plan *)plan, (const KeySet *)ks, (const PtSet *)pts, in, out, flags,
-                        (hipStream_t)stream, MAX_BATCH);
+    FL_CHECK(plan && in, FHELIN_E_INVALID_ARG, "null argument");
+    const Plan *p = (const Plan *)plan;
+    const int R = in->n_ct / std::max(1, p->n_in);
+    std::vector<const KeySet *> kss((size_t)std::max(1, R), (const KeySet *)ks);
+    return linear_apply(c, p, kss.data(), (const PtSet *)pts, in, out, flags, (hipStream_t)stream, MAX_BATCH);
+    API_END
+}
+
+FHELIN_EXPORT int fhelin_plan_workspace_bytes(fhelin_ctx *ctx, const fhelin_plan *plan, int32_t n_requests,
+                                              int32_t flags, uint64_t *bytes) {
+    API_BEGIN FL_CHECK(ctx && plan && bytes && n_requests >= 0, FHELIN_E_INVALID_ARG, "null argument");
+    *bytes = linear_workspace_bytes((Ctx *)ctx, (const Plan *)plan, n_requests, MAX_BATCH, flags);
+    return FHELIN_OK;
+    API_END
+}
+
+FHELIN_EXPORT int fhelin_linear_apply_multi(fhelin_ctx *ctx, const fhelin_plan *plan,
+                                            const fhelin_keyset *const *ks_per_request, const fhelin_ptset *pts,
+                                            const fhelin_ct_batch *in, const fhelin_ct_batch *out, int32_t flags,
+                                            void *stream) {
+    API_BEGIN FL_CHECK(ctx && ks_per_request, FHELIN_E_INVALID_ARG, "null argument");
+    Ctx *c = (Ctx *)ctx;
+    DeviceGuard g(c);
+    return linear_apply(c, (const Plan *)plan, (const KeySet *const *)ks_per_request, (const PtSet *)pts, in, out,
+                        flags, (hipStream_t)stream, MAX_BATCH);
     API_END
 }
 

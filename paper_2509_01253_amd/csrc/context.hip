@@ -353,6 +353,30 @@ ProfScope::~ProfScope() {
     p->recs.push_back({kind, a, b, units});
 }
 
+int Ready::record(hipStream_t s) {
+    if (!ev) FL_TRY_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    FL_TRY_HIP(hipEventRecord(ev, s));
+    return FHELIN_OK;
+}
+
+int Ready::wait(hipStream_t s) const {
+    if (!ev) return FHELIN_OK;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    FL_TRY_HIP(hipStreamIsCapturing(s, &cs));
+    if (cs != hipStreamCaptureStatusNone) return FHELIN_OK;  // the capture call waited on the host
+    FL_TRY_HIP(hipStreamWaitEvent(s, ev, 0));
+    return FHELIN_OK;
+}
+
+int Ready::host_wait() const {
+    if (ev) FL_TRY_HIP(hipEventSynchronize(ev));
+    return FHELIN_OK;
+}
+
+Ready::~Ready() {
+    if (ev) (void)hipEventDestroy(ev);
+}
+
 Ctx::~Ctx() {
     ws.clear();
     if (prof) {

@@ -161,7 +161,7 @@ static int pt_to_internal(Ctx *c, PtSet *p, hipStream_t s) {
         FL_RET(launch_ntt(c, e, 0, s));
         FL_RET(launch_to_mont(c, e, s));
     }
-    return FHELIN_OK;
+    return p->ready.record(s);
 }
 
 int pt_import(Ctx *c, const uint64_t *src, int n_pt, int level, int on_device, hipStream_t s, PtSet **out) {
@@ -194,6 +194,7 @@ int pt_export(Ctx *c, const PtSet *p, int level, uint64_t *dst, hipStream_t s) {
     FL_CHECK(level >= 1 && level <= p->level, FHELIN_E_LEVEL_MISMATCH, "pt_export: level above the set's level");
     const int64_t N = c->N, K = c->K;
     const size_t row = (size_t)N * sizeof(uint64_t);
+    FL_RET(p->ready.wait(s));
     // q rows 0..level-1, then the K special rows
     FL_TRY_HIP(hipMemcpy2DAsync(dst, (level + K) * row, p->data, (p->level + K) * row, level * row, p->n_pt,
                                 hipMemcpyDeviceToDevice, s));

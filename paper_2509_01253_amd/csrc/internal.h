@@ -251,20 +251,36 @@ inline int rowmap_max_rows(const RowMap &m) {
 struct Batch {
     int32_t n;
     uint8_t level[MAX_BATCH];
-    uint32_t g[MAX_BATCH];    // Galois element (1 = none)
-    int16_t key[MAX_BATCH];   // key index inside the keyset
+    uint8_t key_level[MAX_BATCH];  // level the entry's key set was loaded at
+    uint32_t g[MAX_BATCH];         // Galois element (1 = none)
+    const uint64_t *key[MAX_BATCH];// the entry's evaluation key for g (digit 0, part 0, row 0)
 };
 
 // device buffers of a loaded key set (compact layout, Montgomery form, NTT domain):
 // key t, digit j, part p, position e: evk + ((t*beta + j)*2 + p)*(level+K)*N + e*N,
 // position e < level -> q_e, else p_{e-level}
+// Completion of an asynchronous load (key set, plaintext set): recorded on the loading
+// stream; a call on another stream waits for it before its first kernel.
+struct Ready {
+    hipEvent_t ev = nullptr;
+    int record(hipStream_t s);           // create on first use, record on s
+    int wait(hipStream_t s) const;       // stream wait (skipped while s is capturing)
+    int host_wait() const;               // host-side wait
+    Ready() = default;
+    Ready(const Ready &) = delete;
+    Ready &operator=(const Ready &) = delete;
+    ~Ready();
+};
+
 struct KeySet {
     Ctx *ctx = nullptr;
     int level = 0, beta = 0, n_keys = 0;
     std::vector<uint32_t> galois;
     uint64_t *evk = nullptr;
     size_t bytes = 0;
+    Ready ready;
     int64_t key_stride() const { return (int64_t)beta * 2 * (level + ctx->K) * ctx->N; }
+    const uint64_t *key_ptr(int idx) const { return evk + (int64_t)idx * key_stride(); }
     int find(uint32_t g) const {
         for (int i = 0; i < n_keys; ++i)
             if (galois[i] == g) return i;
@@ -277,6 +293,7 @@ struct PtSet {
     int n_pt = 0, level = 0;
     uint64_t *data = nullptr;  // [n_pt][level][N], NTT domain, Montgomery form
     size_t bytes = 0;
+    Ready ready;
 };
 
 struct Plan {
@@ -288,16 +305,23 @@ struct Plan {
     int n_pt() const { return n_out * n_in * (int)gk.size() * (int)rb.size(); }
 };
 
-struct Workspace {
+// A workspace buffer.  Shared: the stream's workspace slot holds one reference and every
+// graph captured against it holds another, so a regrow of the slot never frees memory a
+// captured graph still points at.
+struct WsBuf {
     Ctx *ctx = nullptr;
     void *buf = nullptr;
     size_t bytes = 0;
-    ~Workspace() {
+    ~WsBuf() {
         if (buf) dev_free(ctx, buf, bytes);
     }
 };
-// workspace of at least `bytes` for `stream` (grows; synchronises the stream before a regrow)
-int workspace_get(Ctx *c, hipStream_t s, size_t bytes, uint64_t **out);
+struct Workspace {
+    std::shared_ptr<WsBuf> cur;
+};
+// workspace of at least `bytes` for `stream` (grows; synchronises the stream before a regrow
+// that frees the old buffer); `hold`, if given, receives a reference that keeps it alive
+int workspace_get(Ctx *c, hipStream_t s, size_t bytes, uint64_t **out, std::shared_ptr<WsBuf> *hold = nullptr);
 
 uint32_t galois_of_rotation(int64_t r, int log_n);
 
@@ -327,15 +351,14 @@ int launch_copy_rows(const Ctx *c, const RowMap &dst, const RowMap &src, hipStre
 // key switching (keyswitch.hip); all pointers are bases of batch entry 0, *_es = elements per entry
 int launch_modup(const Ctx *c, const Batch &b, const uint64_t *coef, int64_t coef_es, const uint64_t *ntt,
                  int64_t ntt_es, uint64_t *digits, int64_t digits_es, hipStream_t s);
-int launch_ks_inner(const Ctx *c, const Batch &b, const KeySet *ks, const uint64_t *digits, int64_t digits_es,
-                    uint64_t *u, int64_t u_es, hipStream_t s);
+int launch_ks_inner(const Ctx *c, const Batch &b, const uint64_t *digits, int64_t digits_es, uint64_t *u, int64_t u_es,
+                    hipStream_t s);
 int launch_moddown_fbc(const Ctx *c, const Batch &b, const uint64_t *u, int64_t u_es, uint64_t *md, int64_t md_es,
                        hipStream_t s, int n_parts = 2);
 // inner product with an addend: add_ext = 0 adds P * sigma_g(c0) of a Q ciphertext [2][L] on the
 // q slots, add_ext = 1 adds sigma_g(c0) of an extended ciphertext [2][L+K]; accumulate adds into u
-int launch_ks_inner_add(const Ctx *c, const Batch &b, const KeySet *ks, const uint64_t *digits, int64_t digits_es,
-                        uint64_t *u, int64_t u_es, const uint64_t *add, int64_t add_es, int add_ext, int accumulate,
-                        hipStream_t s);
+int launch_ks_inner_add(const Ctx *c, const Batch &b, const uint64_t *digits, int64_t digits_es, uint64_t *u,
+                        int64_t u_es, const uint64_t *add, int64_t add_es, int add_ext, int accumulate, hipStream_t s);
 // extended ciphertexts [2][L+K]: dst (+)= P * src (lift, src a Q ciphertext [2][src_stride]) or dst (+)= src
 int launch_ext_lift_add(const Ctx *c, const Batch &b, const uint64_t *src, int64_t src_es, int src_stride, int lift,
                         int accumulate, uint64_t *dst, int64_t dst_es, hipStream_t s);

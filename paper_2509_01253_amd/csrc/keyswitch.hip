@@ -114,30 +114,33 @@ constexpr int KS_EG = 8;
 template <bool SMALL>
 __global__ void __launch_bounds__(256) k_ks_inner(Batch b, const ModConst *__restrict__ mods,
                                                   const ModDownTab *__restrict__ mdt,
-                                                  const uint64_t *__restrict__ evk, int64_t key_stride, int key_level,
-                                                  int key_beta, const uint64_t *__restrict__ digits,
-                                                  int64_t digits_es, uint64_t *__restrict__ u, int64_t u_es,
-                                                  KsAdd add, int log_n, int L, int K, int alpha) {
+                                                  const uint64_t *__restrict__ digits, int64_t digits_es,
+                                                  uint64_t *__restrict__ u, int64_t u_es, KsAdd add, int log_n, int L,
+                                                  int K, int alpha) {
     const int s = blockIdx.y;
     const int64_t N = (int64_t)1 << log_n;
     const int k = blockIdx.x * 256 + threadIdx.x;
     const ModConst mc = mods[s];
-    const int kp = s < L ? s : key_level + (s - L);
-    const int64_t kpart = (int64_t)(key_level + K) * N;
     constexpr int MAXB = 16;
     uint64_t kb[MAXB], ka[MAXB];
-    int cur_key = -1;
+    const uint64_t *cur_key = nullptr;
+    int cur_beta = 0;
     const int e_end = min(b.n, (int)(blockIdx.z + 1) * KS_EG);
     for (int t = blockIdx.z * KS_EG; t < e_end; ++t) {
         const int l = b.level[t];
         if (s < L && s >= l) continue;
         const int beta = (l + alpha - 1) / alpha;
-        if (b.key[t] != cur_key) {
+        if (b.key[t] != cur_key || beta > cur_beta) {
+            // key rows of slot s: position s (q) or key_level + (s - L) (p) of each digit/part
             cur_key = b.key[t];
-            const uint64_t *key = evk + (int64_t)cur_key * key_stride + (int64_t)kp * N + k;
+            const int kl = b.key_level[t];
+            cur_beta = (kl + alpha - 1) / alpha;
+            const int kp = s < L ? s : kl + (s - L);
+            const int64_t kpart = (int64_t)(kl + K) * N;
+            const uint64_t *key = cur_key + (int64_t)kp * N + k;
 #pragma unroll
             for (int j = 0; j < MAXB; ++j) {
-                if (j < key_beta) {
+                if (j < cur_beta) {
                     kb[j] = key[(2 * j) * kpart];
                     ka[j] = key[(2 * j + 1) * kpart];
                 }
@@ -176,8 +179,8 @@ __global__ void __launch_bounds__(256) k_ks_inner(Batch b, const ModConst *__res
     }
 }
 
-static int launch_ks_inner_impl(const Ctx *c, const Batch &b, const KeySet *ks, const uint64_t *digits,
-                                int64_t digits_es, uint64_t *u, int64_t u_es, KsAdd add, hipStream_t s) {
+static int launch_ks_inner_impl(const Ctx *c, const Batch &b, const uint64_t *digits, int64_t digits_es, uint64_t *u,
+                                int64_t u_es, KsAdd add, hipStream_t s) {
     if (b.n == 0) return FHELIN_OK;
     double units = 0;
     for (int t = 0; t < b.n; ++t) {
@@ -187,26 +190,23 @@ static int launch_ks_inner_impl(const Ctx *c, const Batch &b, const KeySet *ks, 
     ProfScope ps(c, s, PK_KS_INNER, units);
     dim3 grid(c->N / 256, c->L + c->K, (b.n + KS_EG - 1) / KS_EG);
     if (c->small)
-        hipLaunchKernelGGL(k_ks_inner<true>, grid, dim3(256), 0, s, b, c->d_mods, c->d_moddown, ks->evk,
-                           ks->key_stride(), ks->level, ks->beta, digits, digits_es, u, u_es, add, c->log_n, c->L,
-                           c->K, c->alpha);
+        hipLaunchKernelGGL(k_ks_inner<true>, grid, dim3(256), 0, s, b, c->d_mods, c->d_moddown, digits, digits_es, u,
+                           u_es, add, c->log_n, c->L, c->K, c->alpha);
     else
-        hipLaunchKernelGGL(k_ks_inner<false>, grid, dim3(256), 0, s, b, c->d_mods, c->d_moddown, ks->evk,
-                           ks->key_stride(), ks->level, ks->beta, digits, digits_es, u, u_es, add, c->log_n, c->L,
-                           c->K, c->alpha);
+        hipLaunchKernelGGL(k_ks_inner<false>, grid, dim3(256), 0, s, b, c->d_mods, c->d_moddown, digits, digits_es, u,
+                           u_es, add, c->log_n, c->L, c->K, c->alpha);
     FL_TRY_HIP(hipGetLastError());
     return FHELIN_OK;
 }
 
-int launch_ks_inner(const Ctx *c, const Batch &b, const KeySet *ks, const uint64_t *digits, int64_t digits_es,
-                    uint64_t *u, int64_t u_es, hipStream_t s) {
-    return launch_ks_inner_impl(c, b, ks, digits, digits_es, u, u_es, KsAdd{nullptr, 0, 0, 0}, s);
+int launch_ks_inner(const Ctx *c, const Batch &b, const uint64_t *digits, int64_t digits_es, uint64_t *u, int64_t u_es,
+                    hipStream_t s) {
+    return launch_ks_inner_impl(c, b, digits, digits_es, u, u_es, KsAdd{nullptr, 0, 0, 0}, s);
 }
 
-int launch_ks_inner_add(const Ctx *c, const Batch &b, const KeySet *ks, const uint64_t *digits, int64_t digits_es,
-                        uint64_t *u, int64_t u_es, const uint64_t *add, int64_t add_es, int add_ext, int accumulate,
-                        hipStream_t s) {
-    return launch_ks_inner_impl(c, b, ks, digits, digits_es, u, u_es, KsAdd{add, add_es, add_ext, accumulate}, s);
+int launch_ks_inner_add(const Ctx *c, const Batch &b, const uint64_t *digits, int64_t digits_es, uint64_t *u,
+                        int64_t u_es, const uint64_t *add, int64_t add_es, int add_ext, int accumulate, hipStream_t s) {
+    return launch_ks_inner_impl(c, b, digits, digits_es, u, u_es, KsAdd{add, add_es, add_ext, accumulate}, s);
 }
 
 // ---------------------------------------------------------------------------

@@ -75,7 +75,7 @@ int plan_create(Ctx *c, const fhelin_layer_desc *d, Plan **out) {
 
 // ---------------------------------------------------------------------------
 // pt x ct multiply-accumulate: A[e][j] = sum_i sum_b pt[o][i][j][b] * R[i][b]
-// grid (N/256, l_max, entry groups)
+// grid (N/16, slots, n_out x request groups)
 // ---------------------------------------------------------------------------
 struct MacArgs {
     const uint64_t *x;    // inputs, NTT domain [2][ls] per input entry
@@ -94,8 +94,8 @@ struct MacArgs {
 // are staged in LDS, so each plaintext value is read from memory once per group and
 // each rotated input once per chunk of JT giant steps.  Thread (kl, jj): coefficient
 // kl, giant step jj mod JT, and every ES-th request of the group starting at jj / JT.
-// Products are accumulated lazily in 128 bits, 16 terms per Montgomery reduction
-// (below q 2^64 for q < 2^60).
+// Products are accumulated lazily (split 56-bit sums when every modulus is below 2^56,
+// else 128 bits), 16 terms per Montgomery reduction (below q 2^64 for q < 2^60).
 constexpr int MAC_K = 16;   // coefficients per workgroup
 constexpr int MAC_TB = 4;   // terms per LDS chunk
 constexpr int MAC_MY = 8;   // requests per thread
@@ -117,6 +117,8 @@ __global__ void __launch_bounds__(256) k_mac(MacArgs a, Batch b, const ModConst 
     const int terms = a.n_in * a.B;
     const int prows = a.pt_level + K;
     const int prow = s < L ? s : a.pt_level + (s - L);
+    // a q slot above the plaintexts' level is active for no request (levels <= pt_level)
+    if (s < L && s >= a.pt_level) return;
     const int nr = min(ET, R - r0);
     const ModConst mc = mods[s];
     // active(r): the slot exists at the request's level
@@ -229,28 +231,28 @@ static int launch_mac(const Ctx *c, const Plan *p, MacArgs &ma, const Batch &bou
 // ---------------------------------------------------------------------------
 // workspace
 // ---------------------------------------------------------------------------
-int workspace_get(Ctx *c, hipStream_t s, size_t bytes, uint64_t **out) {
+int workspace_get(Ctx *c, hipStream_t s, size_t bytes, uint64_t **out, std::shared_ptr<WsBuf> *hold) {
     Workspace *w;
     {
         std::lock_guard<std::mutex> g(c->mu);
         auto &slot = c->ws[(void *)s];
-        if (!slot) {
-            slot.reset(new Workspace());
-            slot->ctx = c;
-        }
+        if (!slot) slot.reset(new Workspace());
         w = slot.get();
     }
-    if (w->bytes < bytes) {
-        if (w->buf) {
-            FL_TRY_HIP(hipStreamSynchronize(s));
-            dev_free(c, w->buf, w->bytes);
-            w->buf = nullptr;
-            w->bytes = 0;
+    if (!w->cur || w->cur->bytes < bytes) {
+        if (w->cur) {
+            // the old buffer is freed here unless a captured graph still holds it
+            if (w->cur.use_count() == 1) FL_TRY_HIP(hipStreamSynchronize(s));
+            w->cur.reset();
         }
-        FL_RET(dev_alloc(c, &w->buf, bytes));
-        w->bytes = bytes;
+        std::shared_ptr<WsBuf> nb(new WsBuf());
+        nb->ctx = c;
+        FL_RET(dev_alloc(c, &nb->buf, bytes));
+        nb->bytes = bytes;
+        w->cur = std::move(nb);
     }
-    *out = (uint64_t *)w->buf;
+    *out = (uint64_t *)w->cur->buf;
+    if (hold) *hold = w->cur;
     return FHELIN_OK;
 }
 
@@ -305,16 +307,25 @@ static int modup_ct(const Ctx *c, const Batch &b, const uint64_t *ct, int64_t ct
 }
 
 // inner product + ModDown + combine, digits already in w.dg
-static int ks_finish(const Ctx *c, const Batch &b, const KeySet *ks, const KsScratch &w, uint64_t *dst,
-                     int64_t dst_es, int dst_stride, const uint64_t *c0, int64_t c0_es, int c0_stride, int accumulate,
-                     hipStream_t s) {
-    FL_RET(launch_ks_inner(c, b, ks, w.dg, w.dg_es, w.u, w.u_es, s));
+static int ks_finish(const Ctx *c, const Batch &b, const KsScratch &w, uint64_t *dst, int64_t dst_es, int dst_stride,
+                     const uint64_t *c0, int64_t c0_es, int c0_stride, int accumulate, hipStream_t s) {
+    FL_RET(launch_ks_inner(c, b, w.dg, w.dg_es, w.u, w.u_es, s));
     FL_RET(launch_ntt(c, rows_kind(c, b, w.u, w.u_es, ROWS_EXT_P, 2), 1, s));
     FL_RET(launch_moddown_fbc(c, b, w.u, w.u_es, w.md, w.md_es, s));
     FL_RET(launch_ntt(c, rows_ct(c, b, w.md, w.md_es, c->L, 0, 2), 0, s));
     FL_RET(launch_moddown_combine(c, b, w.u, w.u_es, w.md, w.md_es, dst, dst_es, dst_stride, c0, c0_es, c0_stride,
                                   accumulate, s));
     return FHELIN_OK;
+}
+
+// entries e of a batch belong to request e / per_req; each gets that request's key for g
+static void set_keys(Batch &b, int per_req, const KeySet *const *kss, uint32_t g) {
+    for (int e = 0; e < b.n; ++e) {
+        const KeySet *ks = kss[e / per_req];
+        b.g[e] = g;
+        b.key[e] = ks->key_ptr(ks->find(g));
+        b.key_level[e] = (uint8_t)ks->level;
+    }
 }
 
 static int check_batch(const Ctx *c, const fhelin_ct_batch *bt, const char *what) {
@@ -386,9 +397,9 @@ static int export_out(Ctx *c, const Batch &bout, uint64_t *Y, const fhelin_ct_ba
 // rotations, the multiply-accumulate and the giant-step sum stay in the extended basis
 // (carrying a factor P); each giant step ModDowns only c1 before its ModUp, and one
 // ModDown per output ends the layer.
-static int apply_chunk_dh(Ctx *c, const Plan *p, const KeySet *ks, const PtSet *pts, const fhelin_ct_batch *in,
-                          const fhelin_ct_batch *out, bool rescale, hipStream_t s, uint64_t *ws, int r0, int Rc,
-                          MacArgs ma, int Bp) {
+static int apply_chunk_dh(Ctx *c, const Plan *p, const KeySet *const *kss, const PtSet *pts,
+                          const fhelin_ct_batch *in, const fhelin_ct_batch *out, bool rescale, hipStream_t s,
+                          uint64_t *ws, int r0, int Rc, MacArgs ma, int Bp) {
     const int64_t N = c->N, L = c->L, K = c->K, E = L + K;
     const int B = (int)p->rb.size(), G = (int)p->gk.size();
     const int64_t ct = 2 * L * N, ext = 2 * E * N, dg = (int64_t)c->dnum * E * N;
@@ -423,13 +434,8 @@ static int apply_chunk_dh(Ctx *c, const Plan *p, const KeySet *ks, const PtSet *
         FL_RET(modup_ct(c, bin, X, ct, (int)L, wb, s));
         for (int b = 0; b < B; ++b) {
             if (ma.bmap[b] < 0) continue;
-            uint32_t g = galois_of_rotation(p->rb[b], c->log_n);
-            int key = ks->find(g);
-            for (int e = 0; e < Ein; ++e) {
-                bin.g[e] = g;
-                bin.key[e] = (int16_t)key;
-            }
-            FL_RET(launch_ks_inner_add(c, bin, ks, D, dg, RB + ma.bmap[b] * ext, (int64_t)Bp * ext, X, ct, 0, 0, s));
+            set_keys(bin, p->n_in, kss + r0, galois_of_rotation(p->rb[b], c->log_n));
+            FL_RET(launch_ks_inner_add(c, bin, D, dg, RB + ma.bmap[b] * ext, (int64_t)Bp * ext, X, ct, 0, 0, s));
         }
         for (int e = 0; e < Ein; ++e) bin.g[e] = 1;
     }
@@ -458,11 +464,7 @@ static int apply_chunk_dh(Ctx *c, const Plan *p, const KeySet *ks, const PtSet *
             first = false;
             continue;
         }
-        int key = ks->find(g);
-        for (int e = 0; e < Eout; ++e) {
-            bout.g[e] = g;
-            bout.key[e] = (int16_t)key;
-        }
+        set_keys(bout, p->n_out, kss + r0, g);
         // c1' = ModDown(A~_j.c1) -> poly 1 of TQ (NTT domain)
         uint64_t *Aj1 = Aj + E * N;
         FL_RET(launch_ntt(c, rows_kind(c, bout, Aj1, a_es, ROWS_EXT_P, 1), 1, s));
@@ -471,7 +473,7 @@ static int apply_chunk_dh(Ctx *c, const Plan *p, const KeySet *ks, const PtSet *
         FL_RET(launch_moddown_combine(c, bout, Aj1, a_es, MD, ct, TQ + L * N, ct, (int)L, nullptr, 0, 0, 0, s, 1));
         // ModUp(c1') and the inner product, plus sigma(A~_j.c0), summed into YE
         FL_RET(modup_ct(c, bout, TQ, ct, (int)L, w, s));
-        FL_RET(launch_ks_inner_add(c, bout, ks, DG, dg, YE, ext, Aj, a_es, 1, first ? 0 : 1, s));
+        FL_RET(launch_ks_inner_add(c, bout, DG, dg, YE, ext, Aj, a_es, 1, first ? 0 : 1, s));
         first = false;
     }
     for (int e = 0; e < Eout; ++e) bout.g[e] = 1;
@@ -484,7 +486,7 @@ static int apply_chunk_dh(Ctx *c, const Plan *p, const KeySet *ks, const PtSet *
     return export_out(c, bout, Y, out, (int64_t)r0 * p->n_out, rescale, s);
 }
 
-int linear_apply(Ctx *c, const Plan *p, const KeySet *ks, const PtSet *pts, const fhelin_ct_batch *in,
+int linear_apply(Ctx *c, const Plan *p, const KeySet *const *kss, const PtSet *pts, const fhelin_ct_batch *in,
                  const fhelin_ct_batch *out, int flags, hipStream_t s, int max_chunk) {
     FL_CHECK(c && p && pts && in && out, FHELIN_E_INVALID_ARG, "linear_apply: null argument");
     FL_RET(check_batch(c, in, "linear_apply input"));
@@ -504,13 +506,23 @@ int linear_apply(Ctx *c, const Plan *p, const KeySet *ks, const PtSet *pts, cons
             FL_CHECK(out->levels[r * p->n_out + o] == (rescale ? l - 1 : l), FHELIN_E_LEVEL_MISMATCH,
                      "output levels must equal the input level (minus one when rescaling)");
         if (!p->galois.empty()) {
+            const KeySet *ks = kss ? kss[r] : nullptr;
             FL_CHECK(ks != nullptr, FHELIN_E_MISSING_GALOIS_KEY, "layer needs Galois keys");
+            FL_CHECK(ks->ctx == c, FHELIN_E_INVALID_ARG, "keyset belongs to another context");
             FL_CHECK(l <= ks->level, FHELIN_E_LEVEL_MISMATCH, "keys loaded below the request level");
+            for (uint32_t g : p->galois)
+                FL_CHECK(ks->find(g) >= 0, FHELIN_E_MISSING_GALOIS_KEY,
+                         "keyset lacks Galois element " + std::to_string(g));
         }
     }
-    for (uint32_t g : p->galois)
-        FL_CHECK(ks->find(g) >= 0, FHELIN_E_MISSING_GALOIS_KEY, "keyset lacks Galois element " + std::to_string(g));
     if (R == 0) return FHELIN_OK;
+    // key and plaintext sets loaded on another stream
+    FL_RET(pts->ready.wait(s));
+    if (!p->galois.empty()) {
+        const KeySet *prev = nullptr;
+        for (int r = 0; r < R; ++r)
+            if (kss[r] != prev) FL_RET((prev = kss[r])->ready.wait(s));
+    }
 
     const int64_t N = c->N, L = c->L, K = c->K;
     const int B = (int)p->rb.size(), G = (int)p->gk.size();
@@ -528,7 +540,7 @@ int linear_apply(Ctx *c, const Plan *p, const KeySet *ks, const PtSet *pts, cons
     const int64_t ct = 2 * L * N, dg = (int64_t)c->dnum * (L + K) * N;
     if (dh) {
         for (int r0 = 0; r0 < R; r0 += chunk)
-            FL_RET(apply_chunk_dh(c, p, ks, pts, in, out, rescale, s, ws, r0, std::min(chunk, R - r0), ma, Bp));
+            FL_RET(apply_chunk_dh(c, p, kss, pts, in, out, rescale, s, ws, r0, std::min(chunk, R - r0), ma, Bp));
         return FHELIN_OK;
     }
     for (int r0 = 0; r0 < R; r0 += chunk) {
@@ -563,13 +575,8 @@ int linear_apply(Ctx *c, const Plan *p, const KeySet *ks, const PtSet *pts, cons
             FL_RET(modup_ct(c, bin, X, ct, (int)L, wb, s));
             for (int b = 0; b < B; ++b) {
                 if (ma.bmap[b] < 0) continue;
-                uint32_t g = galois_of_rotation(p->rb[b], c->log_n);
-                int key = ks->find(g);
-                for (int e = 0; e < Ein; ++e) {
-                    bin.g[e] = g;
-                    bin.key[e] = (int16_t)key;
-                }
-                FL_RET(ks_finish(c, bin, ks, wb, RB + ma.bmap[b] * ct, (int64_t)Bp * ct, (int)L, X, ct, (int)L, 0, s));
+                set_keys(bin, p->n_in, kss + r0, galois_of_rotation(p->rb[b], c->log_n));
+                FL_RET(ks_finish(c, bin, wb, RB + ma.bmap[b] * ct, (int64_t)Bp * ct, (int)L, X, ct, (int)L, 0, s));
             }
             for (int e = 0; e < Ein; ++e) bin.g[e] = 1;
         }
@@ -599,14 +606,10 @@ int linear_apply(Ctx *c, const Plan *p, const KeySet *ks, const PtSet *pts, cons
         for (int j = 0; j < G; ++j) {
             uint32_t g = galois_of_rotation(p->gk[j], c->log_n);
             if (g == 1) continue;
-            int key = ks->find(g);
-            for (int e = 0; e < Eout; ++e) {
-                bout.g[e] = g;
-                bout.key[e] = (int16_t)key;
-            }
+            set_keys(bout, p->n_out, kss + r0, g);
             uint64_t *Aj = A + j * ct;
             FL_RET(modup_ct(c, bout, Aj, (int64_t)G * ct, (int)L, w, s));
-            FL_RET(ks_finish(c, bout, ks, w, Y, ct, (int)L, Aj, (int64_t)G * ct, (int)L, first ? 0 : 1, s));
+            FL_RET(ks_finish(c, bout, w, Y, ct, (int)L, Aj, (int64_t)G * ct, (int)L, first ? 0 : 1, s));
             first = false;
         }
         for (int e = 0; e < Eout; ++e) bout.g[e] = 1;
@@ -641,6 +644,7 @@ int rotate_batch(Ctx *c, const KeySet *ks, const fhelin_ct_batch *in, const int3
                  "keyset lacks Galois element " + std::to_string(g));
         FL_CHECK(in->levels[t] <= ks->level, FHELIN_E_LEVEL_MISMATCH, "keys loaded below the ciphertext level");
     }
+    if (ks) FL_RET(ks->ready.wait(s));
     const int64_t N = c->N, L = c->L, K = c->K;
     const int64_t ct = 2 * L * N, dg = (int64_t)c->dnum * (L + K) * N;
     const int64_t per = ct * 2 + L * N + dg + 2 * (L + K) * N + 2 * L * N;
@@ -668,7 +672,8 @@ int rotate_batch(Ctx *c, const KeySet *ks, const fhelin_ct_batch *in, const int3
             }
             b.level[b.n] = (uint8_t)in->levels[t0 + t];
             b.g[b.n] = g;
-            b.key[b.n] = (int16_t)ks->find(g);
+            b.key[b.n] = ks->key_ptr(ks->find(g));
+            b.key_level[b.n] = (uint8_t)ks->level;
             idx.push_back(t0 + t);
             ++b.n;
         }
@@ -684,7 +689,7 @@ int rotate_batch(Ctx *c, const KeySet *ks, const fhelin_ct_batch *in, const int3
         FL_RET(launch_ntt(c, rows_ct(c, b, X, ct, (int)L, 0, 2), 0, s));
         KsScratch w{TC, L * N, DG, dg, U, 2 * (L + K) * N, MD, 2 * L * N};
         FL_RET(modup_ct(c, b, X, ct, (int)L, w, s));
-        FL_RET(ks_finish(c, b, ks, w, Y, ct, (int)L, X, ct, (int)L, 0, s));
+        FL_RET(ks_finish(c, b, w, Y, ct, (int)L, X, ct, (int)L, 0, s));
         FL_RET(launch_ntt(c, rows_ct(c, b, Y, ct, (int)L, 0, 2), 1, s));
         for (int e = 0; e < b.n; ++e) {
             Batch one{};

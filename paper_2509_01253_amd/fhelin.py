@@ -78,6 +78,9 @@ _SIGS = {
     "fhelin_plan_encode_weights": [_vp, _vp, _vp, _vp, _vp, _i32, _dbl, _vp, _pvp],
     "fhelin_linear_apply": [_vp, _vp, _vp, _vp, ctypes.POINTER(fhelin_ct_batch), ctypes.POINTER(fhelin_ct_batch),
                             _i32, _vp],
+    "fhelin_plan_workspace_bytes": [_vp, _vp, _i32, _i32, ctypes.POINTER(_u64)],
+    "fhelin_linear_apply_multi": [_vp, _vp, _vp, _vp, ctypes.POINTER(fhelin_ct_batch),
+                                  ctypes.POINTER(fhelin_ct_batch), _i32, _vp],
     "fhelin_rescale": [_vp, ctypes.POINTER(fhelin_ct_batch), ctypes.POINTER(fhelin_ct_batch), _vp],
     "fhelin_rotate": [_vp, _vp, ctypes.POINTER(fhelin_ct_batch), _vp, ctypes.POINTER(fhelin_ct_batch), _vp],
     "fhelin_ntt": [_vp, _vp, _vp, _i32, _i32, _vp],
@@ -291,6 +294,21 @@ def fhelin_linear_apply(ctx, plan, ks, pts, x: torch.Tensor, x_levels, y: torch.
                         stream=None):
     bi, bo = ct_batch(x, x_levels), ct_batch(y, y_levels)
     _check(_lib.fhelin_linear_apply(ctx, plan, ks, pts, ctypes.byref(bi), ctypes.byref(bo), flags, _stream(stream)))
+
+
+def fhelin_plan_workspace_bytes(ctx, plan, n_requests: int, flags: int) -> int:
+    v = _u64()
+    _check(_lib.fhelin_plan_workspace_bytes(ctx, plan, n_requests, flags, ctypes.byref(v)))
+    return int(v.value)
+
+
+def fhelin_linear_apply_multi(ctx, plan, ks_per_request, pts, x: torch.Tensor, x_levels, y: torch.Tensor, y_levels,
+                              flags=0, stream=None):
+    """linear_apply with one key set per request (requests of different clients)."""
+    bi, bo = ct_batch(x, x_levels), ct_batch(y, y_levels)
+    arr = (_vp * max(1, len(ks_per_request)))(*[k.value if isinstance(k, _vp) else k for k in ks_per_request])
+    _check(_lib.fhelin_linear_apply_multi(ctx, plan, ctypes.cast(arr, _vp), pts, ctypes.byref(bi), ctypes.byref(bo),
+                                          flags, _stream(stream)))
 
 
 def fhelin_graph_capture_linear(ctx, plan, ks, pts, x: torch.Tensor, x_levels, y: torch.Tensor, y_levels, flags=0,

@@ -71,3 +71,58 @@ def test_graph_replays_match_eager():
         F.fhelin_plan_destroy(plan)
     finally:
         F.fhelin_ctx_destroy(ctx)
+
+
+def test_graph_keeps_its_workspace_when_the_stream_regrows():
+    """A graph captured on a stream keeps the workspace it was captured with: a later,
+    larger call on the same stream regrows the stream's workspace, and the graph
+    still replays to the eager result (its buffer is not freed under it)."""
+    import torch
+
+    from paper_2509_01253_amd import fhelin as F
+    print("graph workspace regrow", flush=True)
+    prm = O.make_params(12, 4, 2, 2, 50, 2.0 ** 40)
+    st = synth.Stream(5100)
+    n, n1 = 32, 8
+    W = st.he_normal((n, n), n)
+    sched = O.fc_schedule(n, n1)
+    pts = encode_pts(prm, O.fc_slots(W, n, n1, prm.S), prm.L, prm.scale)
+    cl = Client(prm, 5101)
+    keys = cl.keyset(sched.rotations())
+    ctx = ctx_for(F, prm)
+    stream = torch.cuda.Stream()
+    try:
+        plan = F.fhelin_plan_create(ctx, F.FHELIN_LAYER_FC, fc_n=n, fc_out=n, fc_in=n, n1=n1)
+        ks = F.fhelin_keyset_load(ctx, keys.galois, prm.L, dev(keys_at(prm, keys, prm.L)))
+        pset = F.fhelin_pt_import(ctx, dev(pts.reshape(-1, prm.L + prm.K, prm.N)), level=prm.L)
+        flags = F.FHELIN_APPLY_RESCALE | F.FHELIN_APPLY_HOIST_MODDOWN
+        one = pad_cts([cl.encrypt_slots(O.fc_input_slots(st.uniform(n, 0, 1), n, prm.S), 4, prm.scale)], prm.L,
+                      prm.N)
+        x1, y1 = dev(one), dev(np.zeros_like(one))
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            g = F.fhelin_graph_capture_linear(ctx, plan, ks, pset, x1, [4], y1, [3], flags, stream=stream)
+        # a larger batch on the same stream: the stream's workspace grows
+        levels = [4, 3, 2, 4, 3, 2]
+        many = pad_cts([cl.encrypt_slots(O.fc_input_slots(st.uniform(n, 0, 1), n, prm.S), l, prm.scale)
+                        for l in levels], prm.L, prm.N)
+        xm, ym = dev(many), dev(np.zeros_like(many))
+        F.fhelin_linear_apply(ctx, plan, ks, pset, xm, levels, ym, [l - 1 for l in levels], flags, stream=stream)
+        stream.synchronize()
+        F.fhelin_graph_launch(g, stream=stream)
+        stream.synchronize()
+        got = host(y1)
+        y_eager = dev(np.zeros_like(one))
+        F.fhelin_linear_apply(ctx, plan, ks, pset, x1, [4], y_eager, [3], flags)
+        assert np.array_equal(got, host(y_eager))
+        ref = O.rescale(prm, O.linear(prm, one[0, :, :4][None], 4, sched, pts, keys, hoist_moddown=True)[0], 4)
+        assert np.array_equal(got[0, :, :3], ref)
+        for t, l in enumerate(levels):
+            ref = O.rescale(prm, O.linear(prm, many[t, :, :l][None], l, sched, pts, keys, hoist_moddown=True)[0], l)
+            assert np.array_equal(host(ym)[t, :, : l - 1], ref), t
+        F.fhelin_graph_destroy(g)
+        F.fhelin_ptset_release(pset)
+        F.fhelin_keyset_release(ks)
+        F.fhelin_plan_destroy(plan)
+    finally:
+        F.fhelin_ctx_destroy(ctx)
