@@ -42,6 +42,10 @@ def parse():
     ap.add_argument("--schedule", choices=["rotation", "hoisted"], default="hoisted",
                     help="per-rotation ModDown, or the double-hoisted schedule")
     ap.add_argument("--n1", type=int, default=16, help="baby steps of the 256x256 FC (power of two)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="autotune the plan on the batch before warmup (default: the plan's default tune)")
+    ap.add_argument("--no-one-at-a-time", action="store_true",
+                    help="skip the extra one-request-at-a-time comparison after the timed steps")
     ap.add_argument("--serve-requests", type=int, default=0,
                     help="requests per arrival rate in an extra serving run (default 0 = no serving run)")
     ap.add_argument("--serve-rates", type=str, default="20,100", help="Poisson arrival rates (req/s)")
@@ -63,6 +67,15 @@ BFLY_VALU_OPS = 24
 PEAK_BFLY = ALU_LANE_OPS / BFLY_VALU_OPS / 1e12  # T butterflies (= modular multiplies) per second
 KERNELS = ["ntt_fwd_cols", "ntt_fwd_rows", "ntt_inv_rows", "ntt_inv_cols", "mac", "ks_inner", "modup",
            "moddown_fbc", "combine", "rescale", "copy", "mont", "encode"]
+
+
+def algo_bytes(level: int, n_ks: int, n_mac: int, K: int, alpha: int, N: int) -> int:
+    """Algorithmic HBM bytes of one request at `level`: each key switch reads its
+    evaluation key (2 beta (level + K) limbs) and a ciphertext in and out (2 level limbs
+    each); each pt-ct MAC reads its plaintext (level limbs)."""
+    beta = -(-level // alpha)
+    limbs = n_ks * (2 * beta * (level + K) + 4 * level) + n_mac * level
+    return limbs * N * 8
 
 
 def cpu_baseline(level: int, n1: int, hoisted: bool) -> dict:
@@ -255,6 +268,13 @@ def main():
         F.fhelin_ptset_release(h[1])
         F.fhelin_keyset_release(h[0])
 
+    tune_info = {"autotuned": False, "tune": F.fhelin_plan_get_tune(plan)}
+    if args.autotune:
+        ks, pts = step()
+        best, best_ms = F.fhelin_plan_autotune(ctx, plan, [ks] * args.batch, pts, x, levels, y, out_levels, flags)
+        torch.cuda.synchronize()
+        release((ks, pts))
+        tune_info = {"autotuned": True, "tune": best, "apply_ms_at_tune": round(best_ms, 3)}
     for _ in range(args.warmup):
         release(step())
         torch.cuda.synchronize()
@@ -328,6 +348,32 @@ def main():
         "kernels": {k: {"ms_per_step": v["ms_per_step"], "share": v["share"], "launches": v["launches"]}
                     for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["ms_per_step"])},
     }
+    res["tune"] = tune_info
+    if not args.no_one_at_a_time:
+        # the same requests one at a time (keys and weights resident): the unbatched GPU path
+        ks, pts = step()
+        torch.cuda.synchronize()
+        one_lat = []
+        for r in range(args.batch):
+            s0 = time.perf_counter()
+            F.fhelin_linear_apply(ctx, plan, ks, pts, x[r:r + 1], levels[r:r + 1], y[r:r + 1], out_levels[r:r + 1],
+                                  flags)
+            torch.cuda.synchronize()
+            one_lat.append((time.perf_counter() - s0) * 1e3)
+        release((ks, pts))
+        res["one_at_a_time"] = {
+            "layers_per_s": round(args.batch / (sum(one_lat) / 1e3), 3),
+            "latency_ms": {"p50": round(float(np.percentile(one_lat, 50)), 3),
+                           "p99": round(float(np.percentile(one_lat, 99)), 3)},
+            "batched_speedup_apply_only": round((sum(one_lat) / 1e3) / (apply_ms / 1e3), 3),
+        }
+    # effective HBM fraction: algorithmic bytes of the batch per step (per ciphertext: every
+    # key switch reads its evaluation key once and its ciphertext in and out, every pt-MAC
+    # reads its plaintext once) over the step time at 8 TB/s
+    n_mac = info["n_pt"] // max(1, info["n_out"])
+    byts = sum(algo_bytes(l, n_rot, n_mac, K, alpha, N) for l in levels)
+    res["hbm_effective"] = {"bytes_per_step": byts, "achieved_GBps": round(byts / (ms / 1e3) / 1e9, 1),
+                            "peak_GBps": 8000.0, "frac": round(byts / (ms / 1e3) / 8e12, 4)}
     F.fhelin_plan_destroy(plan)
     F.fhelin_ctx_destroy(ctx)
     if args.serve_requests > 0:

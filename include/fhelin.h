@@ -21,7 +21,9 @@
  *     stream).  Work is enqueued on it and ordered by it; a call returns once
  *     the work is enqueued.  Inputs must stay valid until the stream reaches
  *     the work.  Calls on different streams that share a handle may run
- *     concurrently: each stream gets its own workspace.
+ *     concurrently: each stream gets its own workspace.  A key set or
+ *     plaintext set may be used on a stream other than the one that loaded
+ *     it: the using call waits for the load to finish.
  *   - Ciphertext and plaintext data cross the ABI in the COEFFICIENT domain:
  *     uint64 residues in [0, q_i), limb-major, N values per limb.
  *   - The modulus list of a context is q_0..q_{L-1} followed by p_0..p_{K-1}
@@ -232,6 +234,34 @@ int fhelin_plan_workspace_bytes(fhelin_ctx *ctx, const fhelin_plan *plan, int32_
 int fhelin_linear_apply_multi(fhelin_ctx *ctx, const fhelin_plan *plan, const fhelin_keyset *const *ks_per_request,
                               const fhelin_ptset *pts, const fhelin_ct_batch *in, const fhelin_ct_batch *out,
                               int32_t flags, void *stream);
+
+/* Tile and chunk choices of a plan's schedule.  They change speed only: every
+ * choice gives bit-identical results.
+ *   chunk   requests per chunk, 0 = as many as 64 ciphertexts allow (a smaller
+ *           chunk keeps the working set of a chunk in the GPU's caches)
+ *   ks_eg   batch entries per workgroup of the key-switch inner product (each
+ *           workgroup reuses an evaluation-key tile across its entries), 1..64
+ *   mac_my  requests per thread in the plaintext multiply-accumulate: 2, 4, 8 */
+typedef struct fhelin_tune {
+    int32_t chunk;
+    int32_t ks_eg;
+    int32_t mac_my;
+} fhelin_tune;
+
+int fhelin_plan_get_tune(const fhelin_plan *plan, fhelin_tune *out);
+/* FHELIN_E_INVALID_ARG if a field is out of range; the plan is unchanged then. */
+int fhelin_plan_set_tune(fhelin_plan *plan, const fhelin_tune *tune);
+
+/* Autotuner: times the plan's schedule on the caller's batch (the arguments of
+ * fhelin_linear_apply_multi) for candidate tunes, one field at a time starting
+ * from the plan's current tune (chunk in {all, 32, 16, 8, 4} up to the request
+ * count, ks_eg in {4, 8, 16}, mac_my in {2, 4, 8}), with HIP events on
+ * `stream`, and keeps the fastest in the plan.  Every timed run computes the
+ * layer, so `out` holds the layer's result on return.  Synchronises `stream`.
+ * best (optional) receives the chosen tune, best_ms (optional) its time in ms. */
+int fhelin_plan_autotune(fhelin_ctx *ctx, fhelin_plan *plan, const fhelin_keyset *const *ks_per_request,
+                         const fhelin_ptset *pts, const fhelin_ct_batch *in, const fhelin_ct_batch *out,
+                         int32_t flags, void *stream, fhelin_tune *best, double *best_ms);
 
 /* Capture the kernels of one fhelin_linear_apply call (same arguments) into a
  * HIP graph and instantiate it; nothing runs at capture time.  The device

@@ -11,6 +11,8 @@ int plan_create(Ctx *c, const fhelin_layer_desc *d, Plan **out);
 int linear_apply(Ctx *c, const Plan *p, const KeySet *const *kss, const PtSet *pts, const fhelin_ct_batch *in,
                  const fhelin_ct_batch *out, int flags, hipStream_t s, int max_chunk);
 size_t linear_workspace_bytes(const Ctx *c, const Plan *p, int n_requests, int max_chunk, int flags);
+int plan_autotune(Ctx *c, Plan *p, const KeySet *const *kss, const PtSet *pts, const fhelin_ct_batch *in,
+                  const fhelin_ct_batch *out, int flags, hipStream_t s, Tune *best_out, double *best_ms);
 
 // A captured linear-layer schedule: the kernels of one fhelin_linear_apply with fixed
 // buffers, replayed with hipGraphLaunch.
@@ -399,6 +401,50 @@ FHELIN_EXPORT int fhelin_plan_workspace_bytes(fhelin_ctx *ctx, const fhelin_plan
                                               int32_t flags, uint64_t *bytes) {
     API_BEGIN FL_CHECK(ctx && plan && bytes && n_requests >= 0, FHELIN_E_INVALID_ARG, "null argument");
     *bytes = linear_workspace_bytes((Ctx *)ctx, (const Plan *)plan, n_requests, MAX_BATCH, flags);
+    return FHELIN_OK;
+    API_END
+}
+
+FHELIN_EXPORT int fhelin_plan_get_tune(const fhelin_plan *plan, fhelin_tune *out) {
+    API_BEGIN FL_CHECK(plan && out, FHELIN_E_INVALID_ARG, "null argument");
+    const Tune &t = ((const Plan *)plan)->tune;
+    out->chunk = t.chunk;
+    out->ks_eg = t.ks_eg;
+    out->mac_my = t.mac_my;
+    return FHELIN_OK;
+    API_END
+}
+
+FHELIN_EXPORT int fhelin_plan_set_tune(fhelin_plan *plan, const fhelin_tune *tune) {
+    API_BEGIN FL_CHECK(plan && tune, FHELIN_E_INVALID_ARG, "null argument");
+    Tune t;
+    t.chunk = tune->chunk;
+    t.ks_eg = tune->ks_eg;
+    t.mac_my = tune->mac_my;
+    FL_CHECK(tune_valid(t), FHELIN_E_INVALID_ARG,
+             "tune out of range (chunk 0..64, ks_eg 1..64, mac_my 2, 4 or 8)");
+    ((Plan *)plan)->tune = t;
+    return FHELIN_OK;
+    API_END
+}
+
+FHELIN_EXPORT int fhelin_plan_autotune(fhelin_ctx *ctx, fhelin_plan *plan, const fhelin_keyset *const *ks_per_request,
+                                       const fhelin_ptset *pts, const fhelin_ct_batch *in,
+                                       const fhelin_ct_batch *out, int32_t flags, void *stream, fhelin_tune *best,
+                                       double *best_ms) {
+    API_BEGIN FL_CHECK(ctx && plan, FHELIN_E_INVALID_ARG, "null argument");
+    Ctx *c = (Ctx *)ctx;
+    DeviceGuard g(c);
+    Tune t;
+    double ms = 0;
+    FL_RET(plan_autotune(c, (Plan *)plan, (const KeySet *const *)ks_per_request, (const PtSet *)pts, in, out, flags,
+                         (hipStream_t)stream, &t, &ms));
+    if (best) {
+        best->chunk = t.chunk;
+        best->ks_eg = t.ks_eg;
+        best->mac_my = t.mac_my;
+    }
+    if (best_ms) *best_ms = ms;
     return FHELIN_OK;
     API_END
 }

@@ -176,7 +176,7 @@ int ctx_create(const fhelin_params *prm, Ctx **out) {
     c->alpha = alpha;
     c->mods = mods;
     c->small = true;
-    for (uint64_t q : mods) c->small = c->small && q < ((uint64_t)1 << 56);
+    for (uint64_t q : mods) c->small = c->small && q < ((uint64_t)1 << 55);
     const int M = L + K, N = c->N;
 
     // per-modulus constants, roots and twiddles

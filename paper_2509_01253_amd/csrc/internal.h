@@ -108,7 +108,7 @@ struct Profiler {
 struct Ctx {
     int device = 0;
     int log_n = 0, N = 0, L = 0, K = 0, dnum = 0, alpha = 0;
-    bool small = false;              // every modulus < 2^56: cheaper lazy accumulation
+    bool small = false;              // every modulus < 2^55: cheaper lazy accumulation
     std::vector<uint64_t> mods;      // q_0..q_{L-1}, p_0..p_{K-1}
     std::vector<uint64_t> psi;       // minimal primitive 2N-th root per modulus
     std::vector<ModConst> h_mods;
@@ -296,12 +296,21 @@ struct PtSet {
     Ready ready;
 };
 
+// Tile and chunk choices of a layer schedule (results do not depend on them).
+struct Tune {
+    int chunk = 0;    // requests per chunk (0: as many as fit MAX_BATCH ciphertexts)
+    int ks_eg = 8;    // batch entries per key-switch inner-product workgroup
+    int mac_my = 8;   // requests per thread in the multiply-accumulate
+};
+bool tune_valid(const Tune &t);
+
 struct Plan {
     int kind = 0;
     fhelin_layer_desc desc{};
     int n_in = 0, n_out = 0;
     std::vector<int32_t> rb, gk;  // baby / giant rotation amounts
     std::vector<uint32_t> galois; // distinct Galois elements needed
+    Tune tune;
     int n_pt() const { return n_out * n_in * (int)gk.size() * (int)rb.size(); }
 };
 
@@ -352,13 +361,14 @@ int launch_copy_rows(const Ctx *c, const RowMap &dst, const RowMap &src, hipStre
 int launch_modup(const Ctx *c, const Batch &b, const uint64_t *coef, int64_t coef_es, const uint64_t *ntt,
                  int64_t ntt_es, uint64_t *digits, int64_t digits_es, hipStream_t s);
 int launch_ks_inner(const Ctx *c, const Batch &b, const uint64_t *digits, int64_t digits_es, uint64_t *u, int64_t u_es,
-                    hipStream_t s);
+                    hipStream_t s, int eg = 8);
 int launch_moddown_fbc(const Ctx *c, const Batch &b, const uint64_t *u, int64_t u_es, uint64_t *md, int64_t md_es,
                        hipStream_t s, int n_parts = 2);
 // inner product with an addend: add_ext = 0 adds P * sigma_g(c0) of a Q ciphertext [2][L] on the
 // q slots, add_ext = 1 adds sigma_g(c0) of an extended ciphertext [2][L+K]; accumulate adds into u
 int launch_ks_inner_add(const Ctx *c, const Batch &b, const uint64_t *digits, int64_t digits_es, uint64_t *u,
-                        int64_t u_es, const uint64_t *add, int64_t add_es, int add_ext, int accumulate, hipStream_t s);
+                        int64_t u_es, const uint64_t *add, int64_t add_es, int add_ext, int accumulate, hipStream_t s,
+                        int eg = 8);
 // extended ciphertexts [2][L+K]: dst (+)= P * src (lift, src a Q ciphertext [2][src_stride]) or dst (+)= src
 int launch_ext_lift_add(const Ctx *c, const Batch &b, const uint64_t *src, int64_t src_es, int src_stride, int lift,
                         int accumulate, uint64_t *dst, int64_t dst_es, hipStream_t s);

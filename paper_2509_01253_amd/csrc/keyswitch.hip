@@ -106,17 +106,16 @@ struct KsAdd {
     int accumulate;
 };
 
-// grid (N/256, L + K slots, entry groups of KS_EG): slot s is q_s (entries with s < l)
+// grid (N/256, L + K slots, entry groups of eg): slot s is q_s (entries with s < l)
 // or p_{s-L}; the key rows of slot s are the same for every entry of the group, so a
 // thread loads them once per key and reuses them.
-constexpr int KS_EG = 8;
 
 template <bool SMALL>
 __global__ void __launch_bounds__(256) k_ks_inner(Batch b, const ModConst *__restrict__ mods,
                                                   const ModDownTab *__restrict__ mdt,
                                                   const uint64_t *__restrict__ digits, int64_t digits_es,
                                                   uint64_t *__restrict__ u, int64_t u_es, KsAdd add, int log_n, int L,
-                                                  int K, int alpha) {
+                                                  int K, int alpha, int eg) {
     const int s = blockIdx.y;
     const int64_t N = (int64_t)1 << log_n;
     const int k = blockIdx.x * 256 + threadIdx.x;
@@ -125,8 +124,8 @@ __global__ void __launch_bounds__(256) k_ks_inner(Batch b, const ModConst *__res
     uint64_t kb[MAXB], ka[MAXB];
     const uint64_t *cur_key = nullptr;
     int cur_beta = 0;
-    const int e_end = min(b.n, (int)(blockIdx.z + 1) * KS_EG);
-    for (int t = blockIdx.z * KS_EG; t < e_end; ++t) {
+    const int e_end = min(b.n, (int)(blockIdx.z + 1) * eg);
+    for (int t = blockIdx.z * eg; t < e_end; ++t) {
         const int l = b.level[t];
         if (s < L && s >= l) continue;
         const int beta = (l + alpha - 1) / alpha;
@@ -141,8 +140,8 @@ __global__ void __launch_bounds__(256) k_ks_inner(Batch b, const ModConst *__res
 #pragma unroll
             for (int j = 0; j < MAXB; ++j) {
                 if (j < cur_beta) {
-                    kb[j] = key[(2 * j) * kpart];
-                    ka[j] = key[(2 * j + 1) * kpart];
+                    kb[j] = LazyAcc<SMALL>::prep(key[(2 * j) * kpart]);
+                    ka[j] = LazyAcc<SMALL>::prep(key[(2 * j + 1) * kpart]);
                 }
             }
         }
@@ -154,7 +153,7 @@ __global__ void __launch_bounds__(256) k_ks_inner(Batch b, const ModConst *__res
 #pragma unroll
         for (int j = 0; j < MAXB; ++j) {
             if (j < beta) {
-                const uint64_t dv = d[(int64_t)j * (L + K) * N];
+                const uint64_t dv = LazyAcc<SMALL>::prep(d[(int64_t)j * (L + K) * N]);
                 a0.mac(dv, kb[j]);
                 a1.mac(dv, ka[j]);
             }
@@ -180,7 +179,7 @@ __global__ void __launch_bounds__(256) k_ks_inner(Batch b, const ModConst *__res
 }
 
 static int launch_ks_inner_impl(const Ctx *c, const Batch &b, const uint64_t *digits, int64_t digits_es, uint64_t *u,
-                                int64_t u_es, KsAdd add, hipStream_t s) {
+                                int64_t u_es, KsAdd add, hipStream_t s, int eg) {
     if (b.n == 0) return FHELIN_OK;
     double units = 0;
     for (int t = 0; t < b.n; ++t) {
@@ -188,25 +187,27 @@ static int launch_ks_inner_impl(const Ctx *c, const Batch &b, const uint64_t *di
         units += 2.0 * std::ceil(l / c->alpha) * (l + c->K) * c->N;
     }
     ProfScope ps(c, s, PK_KS_INNER, units);
-    dim3 grid(c->N / 256, c->L + c->K, (b.n + KS_EG - 1) / KS_EG);
+    if (eg < 1) eg = 1;
+    dim3 grid(c->N / 256, c->L + c->K, (b.n + eg - 1) / eg);
     if (c->small)
         hipLaunchKernelGGL(k_ks_inner<true>, grid, dim3(256), 0, s, b, c->d_mods, c->d_moddown, digits, digits_es, u,
-                           u_es, add, c->log_n, c->L, c->K, c->alpha);
+                           u_es, add, c->log_n, c->L, c->K, c->alpha, eg);
     else
         hipLaunchKernelGGL(k_ks_inner<false>, grid, dim3(256), 0, s, b, c->d_mods, c->d_moddown, digits, digits_es, u,
-                           u_es, add, c->log_n, c->L, c->K, c->alpha);
+                           u_es, add, c->log_n, c->L, c->K, c->alpha, eg);
     FL_TRY_HIP(hipGetLastError());
     return FHELIN_OK;
 }
 
 int launch_ks_inner(const Ctx *c, const Batch &b, const uint64_t *digits, int64_t digits_es, uint64_t *u, int64_t u_es,
-                    hipStream_t s) {
-    return launch_ks_inner_impl(c, b, digits, digits_es, u, u_es, KsAdd{nullptr, 0, 0, 0}, s);
+                    hipStream_t s, int eg) {
+    return launch_ks_inner_impl(c, b, digits, digits_es, u, u_es, KsAdd{nullptr, 0, 0, 0}, s, eg);
 }
 
 int launch_ks_inner_add(const Ctx *c, const Batch &b, const uint64_t *digits, int64_t digits_es, uint64_t *u,
-                        int64_t u_es, const uint64_t *add, int64_t add_es, int add_ext, int accumulate, hipStream_t s) {
-    return launch_ks_inner_impl(c, b, digits, digits_es, u, u_es, KsAdd{add, add_es, add_ext, accumulate}, s);
+                        int64_t u_es, const uint64_t *add, int64_t add_es, int add_ext, int accumulate, hipStream_t s,
+                        int eg) {
+    return launch_ks_inner_impl(c, b, digits, digits_es, u, u_es, KsAdd{add, add_es, add_ext, accumulate}, s, eg);
 }
 
 // ---------------------------------------------------------------------------

@@ -90,51 +90,53 @@ struct MacArgs {
 // For one limb (slot s) and coefficient k the multiply-accumulate is a small matrix
 // product over the requests r of a group: A[r][j] = sum_t pt[o][j][t] * R[r][t]
 // (t = (input i, baby b)).  A workgroup takes 16 coefficients, one slot, one output
-// index o and a group of ET requests; plaintext and rotated-input tiles of MTB terms
-// are staged in LDS, so each plaintext value is read from memory once per group and
-// each rotated input once per chunk of JT giant steps.  Thread (kl, jj): coefficient
-// kl, giant step jj mod JT, and every ES-th request of the group starting at jj / JT.
-// Products are accumulated lazily (split 56-bit sums when every modulus is below 2^56,
-// else 128 bits), 16 terms per Montgomery reduction (below q 2^64 for q < 2^60).
+// index o and a group of ET = MY * ES requests; plaintext and rotated-input tiles of
+// MAC_TB terms are staged in LDS, so each plaintext value is read from memory once per
+// group and each rotated input once per chunk of JT giant steps.  Thread (kl, jj):
+// coefficient kl, giant step jj mod JT, and the MY requests jj / JT + m ES of the group.
+// Rows of the request tile past the group or inactive at this slot are staged as zeros,
+// so the inner loop has no branches; only the stores are guarded.  Operands are staged
+// in the accumulator's form (28-bit halves when every modulus is below 2^55, else plain)
+// and products are summed lazily; every 16 terms the sum is Montgomery-reduced and
+// seeds the next 16.
 constexpr int MAC_K = 16;   // coefficients per workgroup
 constexpr int MAC_TB = 4;   // terms per LDS chunk
-constexpr int MAC_MY = 8;   // requests per thread
 constexpr int MAC_ET = 32;  // requests per workgroup at most
 
-template <bool SMALL>
+// MY = requests per thread (a tile choice); ES * MY = ET <= MAC_ET
+template <bool SMALL, int MY>
 __global__ void __launch_bounds__(256) k_mac(MacArgs a, Batch b, const ModConst *__restrict__ mods, int log_n,
                                              int L, int K, int R, int JT, int ES, int ET) {
     __shared__ uint64_t Ps[16][MAC_TB][MAC_K];
     __shared__ uint64_t Rs[MAC_ET][MAC_TB][2][MAC_K];
     const int s = blockIdx.y;  // slot = modulus index (q_s for s < L, p_{s-L} otherwise)
+    // a q slot above the plaintexts' level is active for no request (levels <= pt_level)
+    if (s < L && s >= a.pt_level) return;
     const int64_t N = (int64_t)1 << log_n;
     const int k0 = blockIdx.x * MAC_K;
     const int o = blockIdx.z % a.n_out, r0 = (blockIdx.z / a.n_out) * ET;
     const int kl = threadIdx.x & 15, jj = threadIdx.x >> 4;
-    const int jloc = jj % JT, es = jj / JT;
+    const int jloc = jj % JT, es = min(jj / JT, ES - 1);  // es < ES keeps es + m ES < ET
     const int ls = a.ext ? L + K : L;
     const int64_t ct = (int64_t)2 * ls * N;
     const int terms = a.n_in * a.B;
     const int prows = a.pt_level + K;
     const int prow = s < L ? s : a.pt_level + (s - L);
-    // a q slot above the plaintexts' level is active for no request (levels <= pt_level)
-    if (s < L && s >= a.pt_level) return;
     const int nr = min(ET, R - r0);
     const ModConst mc = mods[s];
-    // active(r): the slot exists at the request's level
+    // active(r): the group holds request rr and the slot exists at its level
     auto active = [&](int rr) -> bool {
+        if (rr >= nr) return false;
         const int l = b.level[(r0 + rr) * a.n_out + o];
         return s < L ? s < l : a.ext != 0;
     };
     for (int jc = 0; jc < a.G; jc += JT) {
         const int j = jc + jloc;
-        LazyAcc<SMALL> acc[MAC_MY][2];
-        uint64_t red[MAC_MY][2];
+        LazyAcc<SMALL> acc[MY][2];
 #pragma unroll
-        for (int m = 0; m < MAC_MY; ++m) {
+        for (int m = 0; m < MY; ++m) {
             acc[m][0].zero();
             acc[m][1].zero();
-            red[m][0] = red[m][1] = 0;
         }
         for (int t0 = 0; t0 < terms; t0 += MAC_TB) {
             // stage plaintexts: JT x MAC_TB x 16
@@ -145,12 +147,12 @@ __global__ void __launch_bounds__(256) k_mac(MacArgs a, Batch b, const ModConst 
                 if (t < terms && jg < a.G) {
                     const int ii = t / a.B, bb = t % a.B;
                     const int64_t pidx = ((int64_t)(o * a.n_in + ii) * a.G + jg) * a.B + bb;
-                    pv = a.pts[(pidx * prows + prow) * N + k0 + kk];
+                    pv = LazyAcc<SMALL>::prep(a.pts[(pidx * prows + prow) * N + k0 + kk]);
                 }
                 Ps[jl][tt][kk] = pv;
             }
-            // stage rotated inputs: nr x MAC_TB x 2 x 16
-            for (int v = threadIdx.x; v < nr * MAC_TB * 2 * MAC_K; v += 256) {
+            // stage rotated inputs: ET x MAC_TB x 2 x 16 (zeros past the group / inactive)
+            for (int v = threadIdx.x; v < ET * MAC_TB * 2 * MAC_K; v += 256) {
                 const int kk = v % MAC_K, p = (v / MAC_K) % 2, tt = (v / (2 * MAC_K)) % MAC_TB,
                           rr = v / (2 * MAC_K * MAC_TB);
                 const int t = t0 + tt;
@@ -160,45 +162,38 @@ __global__ void __launch_bounds__(256) k_mac(MacArgs a, Batch b, const ModConst 
                     const int64_t xin = (int64_t)(r0 + rr) * a.n_in + ii;
                     const int m = a.bmap[bb];
                     const uint64_t *src = m < 0 ? a.x + xin * ct : a.rb + (xin * a.Bp + m) * ct;
-                    xv = src[((int64_t)p * ls + s) * N + k0 + kk];
+                    xv = LazyAcc<SMALL>::prep(src[((int64_t)p * ls + s) * N + k0 + kk]);
                 }
                 Rs[rr][tt][p][kk] = xv;
             }
             __syncthreads();
-            if (j < a.G) {
 #pragma unroll
-                for (int tt = 0; tt < MAC_TB; ++tt) {
-                    const uint64_t pv = Ps[jloc][tt][kl];
+            for (int tt = 0; tt < MAC_TB; ++tt) {
+                const uint64_t pv = Ps[jloc][tt][kl];
 #pragma unroll
-                    for (int m = 0; m < MAC_MY; ++m) {
-                        const int rr = es + m * ES;
-                        if (rr < nr) {
-                            acc[m][0].mac(Rs[rr][tt][0][kl], pv);
-                            acc[m][1].mac(Rs[rr][tt][1][kl], pv);
-                        }
-                    }
+                for (int m = 0; m < MY; ++m) {
+                    const int rr = es + m * ES;
+                    acc[m][0].mac(Rs[rr][tt][0][kl], pv);
+                    acc[m][1].mac(Rs[rr][tt][1][kl], pv);
                 }
             }
             __syncthreads();
             if (((t0 + MAC_TB) % 16) == 0 || t0 + MAC_TB >= terms) {
 #pragma unroll
-                for (int m = 0; m < MAC_MY; ++m)
+                for (int m = 0; m < MY; ++m)
 #pragma unroll
-                    for (int p = 0; p < 2; ++p) {
-                        red[m][p] = add_mod(red[m][p], acc[m][p].reduce(mc.q, mc.mont_neg_inv), mc.q);
-                        acc[m][p].zero();
-                    }
+                    for (int p = 0; p < 2; ++p) acc[m][p].set(acc[m][p].reduce(mc.q, mc.mont_neg_inv));
             }
         }
-        if (j < a.G) {
+        if (j < a.G && jj / JT < ES) {
 #pragma unroll
-            for (int m = 0; m < MAC_MY; ++m) {
+            for (int m = 0; m < MY; ++m) {
                 const int rr = es + m * ES;
-                if (rr < nr && active(rr)) {
+                if (active(rr)) {
                     const int64_t e = (int64_t)(r0 + rr) * a.n_out + o;
                     uint64_t *dst = a.acc + (e * a.G + j) * ct + (int64_t)s * N + k0 + kl;
-                    dst[0] = red[m][0];
-                    dst[(int64_t)ls * N] = red[m][1];
+                    dst[0] = acc[m][0].value();
+                    dst[(int64_t)ls * N] = acc[m][1].value();
                 }
             }
         }
@@ -215,17 +210,31 @@ static int launch_mac(const Ctx *c, const Plan *p, MacArgs &ma, const Batch &bou
     }
     const int JT = std::min(ma.G, 16);
     const int ES = 16 / JT;
-    const int ET = std::min(MAC_MY * ES, MAC_ET);
+    int MY = p->tune.mac_my;
+    while (MY > 2 && MY * ES > MAC_ET) MY /= 2;  // ES <= 16, so MY = 2 always fits
+    const int ET = MY * ES;
     const int slots = ma.ext ? c->L + c->K : lmax;
     ProfScope ps(c, s, PK_MAC, macs);
     dim3 grid(c->N / MAC_K, slots, p->n_out * ((R + ET - 1) / ET));
-    if (c->small)
-        hipLaunchKernelGGL(k_mac<true>, grid, dim3(256), 0, s, ma, bout, c->d_mods, c->log_n, c->L, c->K, R, JT, ES, ET);
-    else
-        hipLaunchKernelGGL(k_mac<false>, grid, dim3(256), 0, s, ma, bout, c->d_mods, c->log_n, c->L, c->K, R, JT, ES,
-                           ET);
+#define FL_MAC(SM, Y) hipLaunchKernelGGL((k_mac<SM, Y>), grid, dim3(256), 0, s, ma, bout, c->d_mods, c->log_n, c->L, \
+                                         c->K, R, JT, ES, ET)
+    if (c->small) {
+        if (MY == 2) FL_MAC(true, 2);
+        else if (MY == 4) FL_MAC(true, 4);
+        else FL_MAC(true, 8);
+    } else {
+        if (MY == 2) FL_MAC(false, 2);
+        else if (MY == 4) FL_MAC(false, 4);
+        else FL_MAC(false, 8);
+    }
+#undef FL_MAC
     FL_TRY_HIP(hipGetLastError());
     return FHELIN_OK;
+}
+
+bool tune_valid(const Tune &t) {
+    return t.chunk >= 0 && t.chunk <= MAX_BATCH && t.ks_eg >= 1 && t.ks_eg <= MAX_BATCH &&
+           (t.mac_my == 2 || t.mac_my == 4 || t.mac_my == 8);
 }
 
 // ---------------------------------------------------------------------------
@@ -308,8 +317,8 @@ static int modup_ct(const Ctx *c, const Batch &b, const uint64_t *ct, int64_t ct
 
 // inner product + ModDown + combine, digits already in w.dg
 static int ks_finish(const Ctx *c, const Batch &b, const KsScratch &w, uint64_t *dst, int64_t dst_es, int dst_stride,
-                     const uint64_t *c0, int64_t c0_es, int c0_stride, int accumulate, hipStream_t s) {
-    FL_RET(launch_ks_inner(c, b, w.dg, w.dg_es, w.u, w.u_es, s));
+                     const uint64_t *c0, int64_t c0_es, int c0_stride, int accumulate, hipStream_t s, int eg = 8) {
+    FL_RET(launch_ks_inner(c, b, w.dg, w.dg_es, w.u, w.u_es, s, eg));
     FL_RET(launch_ntt(c, rows_kind(c, b, w.u, w.u_es, ROWS_EXT_P, 2), 1, s));
     FL_RET(launch_moddown_fbc(c, b, w.u, w.u_es, w.md, w.md_es, s));
     FL_RET(launch_ntt(c, rows_ct(c, b, w.md, w.md_es, c->L, 0, 2), 0, s));
@@ -372,11 +381,18 @@ static size_t limbs_per_request_dh(const Ctx *c, const Plan *p, int Bp) {
            + emax * 2 * L;     // md
 }
 
+// requests per chunk: at most MAX_BATCH ciphertexts on either side, the plan's tuned
+// chunk if set, and no more than the requests present
+static int chunk_of(const Plan *p, int n_requests, int max_chunk) {
+    int chunk = std::max(1, std::min(max_chunk, MAX_BATCH / std::max(p->n_in, p->n_out)));
+    if (p->tune.chunk > 0) chunk = std::min(chunk, p->tune.chunk);
+    return std::min(chunk, std::max(1, n_requests));
+}
+
 size_t linear_workspace_bytes(const Ctx *c, const Plan *p, int n_requests, int max_chunk, int flags) {
     int Bp = 0;
     for (int r : p->rb) Bp += galois_of_rotation(r, c->log_n) == 1 ? 0 : 1;
-    int chunk = std::max(1, std::min(max_chunk, MAX_BATCH / std::max(p->n_in, p->n_out)));
-    chunk = std::min(chunk, std::max(1, n_requests));
+    const int chunk = chunk_of(p, n_requests, max_chunk);
     size_t per = (flags & FHELIN_APPLY_HOIST_MODDOWN) ? limbs_per_request_dh(c, p, Bp) : limbs_per_request(c, p, Bp);
     return per * chunk * (size_t)c->N * sizeof(uint64_t);
 }
@@ -435,7 +451,8 @@ static int apply_chunk_dh(Ctx *c, const Plan *p, const KeySet *const *kss, const
         for (int b = 0; b < B; ++b) {
             if (ma.bmap[b] < 0) continue;
             set_keys(bin, p->n_in, kss + r0, galois_of_rotation(p->rb[b], c->log_n));
-            FL_RET(launch_ks_inner_add(c, bin, D, dg, RB + ma.bmap[b] * ext, (int64_t)Bp * ext, X, ct, 0, 0, s));
+            FL_RET(launch_ks_inner_add(c, bin, D, dg, RB + ma.bmap[b] * ext, (int64_t)Bp * ext, X, ct, 0, 0, s,
+                                       p->tune.ks_eg));
         }
         for (int e = 0; e < Ein; ++e) bin.g[e] = 1;
     }
@@ -473,7 +490,7 @@ static int apply_chunk_dh(Ctx *c, const Plan *p, const KeySet *const *kss, const
         FL_RET(launch_moddown_combine(c, bout, Aj1, a_es, MD, ct, TQ + L * N, ct, (int)L, nullptr, 0, 0, 0, s, 1));
         // ModUp(c1') and the inner product, plus sigma(A~_j.c0), summed into YE
         FL_RET(modup_ct(c, bout, TQ, ct, (int)L, w, s));
-        FL_RET(launch_ks_inner_add(c, bout, DG, dg, YE, ext, Aj, a_es, 1, first ? 0 : 1, s));
+        FL_RET(launch_ks_inner_add(c, bout, DG, dg, YE, ext, Aj, a_es, 1, first ? 0 : 1, s, p->tune.ks_eg));
         first = false;
     }
     for (int e = 0; e < Eout; ++e) bout.g[e] = 1;
@@ -529,8 +546,7 @@ int linear_apply(Ctx *c, const Plan *p, const KeySet *const *kss, const PtSet *p
     MacArgs ma{};
     int Bp = 0;
     for (int b = 0; b < B; ++b) ma.bmap[b] = galois_of_rotation(p->rb[b], c->log_n) == 1 ? -1 : Bp++;
-    int chunk = std::max(1, std::min(max_chunk, MAX_BATCH / std::max(p->n_in, p->n_out)));
-    chunk = std::min(chunk, R);
+    const int chunk = chunk_of(p, R, max_chunk);
     uint64_t *ws;
     const bool dh = flags & FHELIN_APPLY_HOIST_MODDOWN;
     FL_RET(workspace_get(c, s, (dh ? limbs_per_request_dh(c, p, Bp) : limbs_per_request(c, p, Bp)) * chunk * N *
@@ -576,7 +592,8 @@ int linear_apply(Ctx *c, const Plan *p, const KeySet *const *kss, const PtSet *p
             for (int b = 0; b < B; ++b) {
                 if (ma.bmap[b] < 0) continue;
                 set_keys(bin, p->n_in, kss + r0, galois_of_rotation(p->rb[b], c->log_n));
-                FL_RET(ks_finish(c, bin, wb, RB + ma.bmap[b] * ct, (int64_t)Bp * ct, (int)L, X, ct, (int)L, 0, s));
+                FL_RET(ks_finish(c, bin, wb, RB + ma.bmap[b] * ct, (int64_t)Bp * ct, (int)L, X, ct, (int)L, 0, s,
+                                 p->tune.ks_eg));
             }
             for (int e = 0; e < Ein; ++e) bin.g[e] = 1;
         }
@@ -609,7 +626,7 @@ int linear_apply(Ctx *c, const Plan *p, const KeySet *const *kss, const PtSet *p
             set_keys(bout, p->n_out, kss + r0, g);
             uint64_t *Aj = A + j * ct;
             FL_RET(modup_ct(c, bout, Aj, (int64_t)G * ct, (int)L, w, s));
-            FL_RET(ks_finish(c, bout, w, Y, ct, (int)L, Aj, (int64_t)G * ct, (int)L, first ? 0 : 1, s));
+            FL_RET(ks_finish(c, bout, w, Y, ct, (int)L, Aj, (int64_t)G * ct, (int)L, first ? 0 : 1, s, p->tune.ks_eg));
             first = false;
         }
         for (int e = 0; e < Eout; ++e) bout.g[e] = 1;
@@ -624,6 +641,76 @@ int linear_apply(Ctx *c, const Plan *p, const KeySet *const *kss, const PtSet *p
             FL_RET(launch_copy_rows(c, rows_ct(c, bout, ob, out_es, out->stride, 0, 2), yr, s));
         }
     }
+    return FHELIN_OK;
+}
+
+// ---------------------------------------------------------------------------
+// autotuner: coordinate descent over the tune fields, timing whole layers
+// ---------------------------------------------------------------------------
+static int time_apply(Ctx *c, const Plan *p, const KeySet *const *kss, const PtSet *pts, const fhelin_ct_batch *in,
+                      const fhelin_ct_batch *out, int flags, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
+                      double *ms) {
+    FL_RET(linear_apply(c, p, kss, pts, in, out, flags, s, MAX_BATCH));  // warm (workspace, caches)
+    float best = 0;
+    for (int rep = 0; rep < 2; ++rep) {
+        FL_TRY_HIP(hipEventRecord(e0, s));
+        FL_RET(linear_apply(c, p, kss, pts, in, out, flags, s, MAX_BATCH));
+        FL_TRY_HIP(hipEventRecord(e1, s));
+        FL_TRY_HIP(hipEventSynchronize(e1));
+        float t = 0;
+        FL_TRY_HIP(hipEventElapsedTime(&t, e0, e1));
+        if (rep == 0 || t < best) best = t;
+    }
+    *ms = best;
+    return FHELIN_OK;
+}
+
+int plan_autotune(Ctx *c, Plan *p, const KeySet *const *kss, const PtSet *pts, const fhelin_ct_batch *in,
+                  const fhelin_ct_batch *out, int flags, hipStream_t s, Tune *best_out, double *best_ms) {
+    FL_CHECK(c && p && in, FHELIN_E_INVALID_ARG, "autotune: null argument");
+    FL_CHECK(in->n_ct % std::max(1, p->n_in) == 0, FHELIN_E_INVALID_ARG, "input count is not a multiple of n_in");
+    const int R = in->n_ct / std::max(1, p->n_in);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    FL_TRY_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return set_error(FHELIN_E_HIP, "autotune: event creation failed");
+    }
+    const Tune start = p->tune;
+    Tune best = start;
+    double best_t = 0;
+    int rc = time_apply(c, p, kss, pts, in, out, flags, s, e0, e1, &best_t);
+    const int chunks[] = {0, 32, 16, 8, 4}, egs[] = {4, 8, 16}, mys[] = {2, 4, 8};
+    for (int field = 0; field < 3 && rc == FHELIN_OK; ++field) {
+        const int *vals = field == 0 ? chunks : field == 1 ? egs : mys;
+        const int nv = field == 0 ? 5 : 3;
+        for (int i = 0; i < nv && rc == FHELIN_OK; ++i) {
+            Tune t = best;
+            int &f = field == 0 ? t.chunk : field == 1 ? t.ks_eg : t.mac_my;
+            if (f == vals[i]) continue;
+            if (field == 0 && vals[i] >= R) continue;  // same as "all" for this batch
+            f = vals[i];
+            p->tune = t;
+            double ms = 0;
+            rc = time_apply(c, p, kss, pts, in, out, flags, s, e0, e1, &ms);
+            if (rc == FHELIN_OK && ms < best_t) {
+                best_t = ms;
+                best = t;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != FHELIN_OK) {
+        p->tune = start;
+        return rc;
+    }
+    p->tune = best;
+    // leave `out` holding the layer computed with the chosen tune
+    FL_RET(linear_apply(c, p, kss, pts, in, out, flags, s, MAX_BATCH));
+    FL_TRY_HIP(hipStreamSynchronize(s));
+    if (best_out) *best_out = best;
+    if (best_ms) *best_ms = best_t;
     return FHELIN_OK;
 }
 

@@ -57,62 +57,85 @@ __device__ __forceinline__ uint64_t redc(uint64_t lo, uint64_t hi, uint64_t q, u
 
 __device__ __forceinline__ uint64_t redc(const Acc128 &a, uint64_t q, uint64_t ninv) { return redc(a.lo, a.hi, q, ninv); }
 
-// Lazy sum of up to 16 products a*b with a, b < 2^56, split on 32-bit halves:
-// a b = a0 b0 + (a0 b1 + a1 b0) 2^32 + a1 b1 2^64 with a1, b1 < 2^24, so the middle and
-// high sums cannot overflow 64 bits in 16 terms and the low sum only needs a carry count.
-// Four 32x32->64 multiply-adds per product instead of a full 64x64->128 product.
-struct Acc56 {
-    uint64_t s0, s1, s2;
-    uint32_t c0;
-};
-
-__device__ __forceinline__ void acc56_zero(Acc56 &A) {
-    A.s0 = A.s1 = A.s2 = 0;
-    A.c0 = 0;
+// Montgomery reduction of T = hi*2^64 + lo < 2q*2^64 -> T*2^-64 mod q in [0, q):
+// (T + m q) / 2^64 < 3q, two conditional subtractions.
+__device__ __forceinline__ uint64_t redc_wide(uint64_t lo, uint64_t hi, uint64_t q, uint64_t ninv) {
+    uint64_t m = lo * ninv;
+    uint64_t mq_lo = m * q;
+    uint64_t mq_hi = mulhi64(m, q);
+    uint64_t carry = (lo + mq_lo < lo) ? 1 : 0;
+    uint64_t t = hi + mq_hi + carry;    // < 3q
+    return csub(csub(t, 2 * q), q);
 }
 
-__device__ __forceinline__ void mac56(Acc56 &A, uint64_t a, uint64_t b) {
-    const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32), b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
-    const uint64_t t = A.s0 + (uint64_t)a0 * b0;
-    A.c0 += t < A.s0 ? 1u : 0u;
-    A.s0 = t;
+// Lazy sums of up to 16 products a*b, Montgomery-reduced at the end.
+//
+// Small moduli (every q < 2^55): operands are split once into 28-bit halves packed in
+// one word, pack28(a) = a0 | a1 << 32 with a = a0 + a1 2^28.  Then
+//   a b = a0 b0 + (a0 b1 + a1 b0) 2^28 + a1 b1 2^56
+// and every partial product is below 2^55, so three 64-bit sums take 16 products
+// without carries: four 32x32->64 multiply-adds per product and nothing else.
+// A reduced value v < q restarts a sum at v 2^64 (v 2^8 in the 2^56 sum; below 2^63).
+__device__ __forceinline__ uint64_t pack28(uint64_t a) {
+    return (a & 0xFFFFFFFull) | ((a >> 28) << 32);
+}
+
+struct Acc28 {
+    uint64_t s0, s1, s2;  // weights 1, 2^28, 2^56
+};
+
+__device__ __forceinline__ void mac28(Acc28 &A, uint64_t pa, uint64_t pb) {
+    const uint32_t a0 = (uint32_t)pa, a1 = (uint32_t)(pa >> 32), b0 = (uint32_t)pb, b1 = (uint32_t)(pb >> 32);
+    A.s0 += (uint64_t)a0 * b0;
     A.s1 += (uint64_t)a0 * b1;
     A.s1 += (uint64_t)a1 * b0;
     A.s2 += (uint64_t)a1 * b1;
 }
 
-// Montgomery reduction of the accumulated sum (requires sum < q 2^64: 16 q < 2^64)
-__device__ __forceinline__ uint64_t redc56(const Acc56 &A, uint64_t q, uint64_t ninv);
-
 __device__ __forceinline__ uint64_t mont_mul(uint64_t a, uint64_t b_mont, uint64_t q, uint64_t ninv) {
     return redc(a * b_mont, mulhi64(a, b_mont), q, ninv);
 }
 
-__device__ __forceinline__ uint64_t redc56(const Acc56 &A, uint64_t q, uint64_t ninv) {
-    const uint64_t lo = A.s0 + (A.s1 << 32);
-    const uint64_t hi = (uint64_t)A.c0 + A.s2 + (A.s1 >> 32) + (lo < A.s0 ? 1 : 0);
-    return redc(lo, hi, q, ninv);
+// T = s0 + s1 2^28 + s2 2^56 < 2q 2^64 -> T 2^-64 mod q
+__device__ __forceinline__ uint64_t redc28(const Acc28 &A, uint64_t q, uint64_t ninv) {
+    const uint64_t m1 = A.s1 << 28, m2 = A.s2 << 56;
+    uint64_t lo = A.s0 + m1;
+    uint64_t hi = (A.s1 >> 36) + (A.s2 >> 8) + (lo < m1 ? 1 : 0);
+    const uint64_t lo2 = lo + m2;
+    hi += lo2 < m2 ? 1 : 0;
+    return redc_wide(lo2, hi, q, ninv);
 }
 
-// A 16-term lazy accumulator over either representation: SMALL (all moduli < 2^56)
-// uses Acc56, otherwise full 128-bit products.
+// A 16-term lazy accumulator over either representation: SMALL (all moduli < 2^55)
+// uses Acc28 on packed operands, otherwise full 128-bit products on plain operands.
+// prep(x) puts an operand in the form mac() takes.  set(v) restarts the sum at v 2^64
+// for a reduced v < q, so the Montgomery reduction of (v 2^64 + 16 products) < 2q 2^64
+// (16 q < 2^64) returns v + (products) 2^-64 mod q; value() reads v back after set().
 template <bool SMALL>
 struct LazyAcc;
 
 template <>
 struct LazyAcc<true> {
-    Acc56 a;
-    __device__ __forceinline__ void zero() { acc56_zero(a); }
-    __device__ __forceinline__ void mac(uint64_t x, uint64_t y) { mac56(a, x, y); }
-    __device__ __forceinline__ uint64_t reduce(uint64_t q, uint64_t ninv) const { return redc56(a, q, ninv); }
+    Acc28 a;
+    __device__ __forceinline__ static uint64_t prep(uint64_t x) { return pack28(x); }
+    __device__ __forceinline__ void zero() { a = Acc28{0, 0, 0}; }
+    __device__ __forceinline__ void set(uint64_t v) { a = Acc28{0, 0, v << 8}; }
+    __device__ __forceinline__ uint64_t value() const { return a.s2 >> 8; }
+    __device__ __forceinline__ void mac(uint64_t px, uint64_t py) { mac28(a, px, py); }
+    __device__ __forceinline__ uint64_t reduce(uint64_t q, uint64_t ninv) const { return redc28(a, q, ninv); }
 };
 
 template <>
 struct LazyAcc<false> {
     Acc128 a;
+    __device__ __forceinline__ static uint64_t prep(uint64_t x) { return x; }
     __device__ __forceinline__ void zero() { a = Acc128{0, 0}; }
+    __device__ __forceinline__ void set(uint64_t v) { a = Acc128{0, v}; }
+    __device__ __forceinline__ uint64_t value() const { return a.hi; }
     __device__ __forceinline__ void mac(uint64_t x, uint64_t y) { mac128(a, x, y); }
-    __device__ __forceinline__ uint64_t reduce(uint64_t q, uint64_t ninv) const { return redc(a, q, ninv); }
+    __device__ __forceinline__ uint64_t reduce(uint64_t q, uint64_t ninv) const {
+        return redc_wide(a.lo, a.hi, q, ninv);
+    }
 };
 
 // ---------------------------------------------------------------------------

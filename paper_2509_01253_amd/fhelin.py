@@ -55,6 +55,10 @@ class fhelin_ct_batch(ctypes.Structure):
     _fields_ = [("data", _vp), ("n_ct", _i32), ("stride", _i32), ("levels", ctypes.POINTER(_i32))]
 
 
+class fhelin_tune(ctypes.Structure):
+    _fields_ = [("chunk", _i32), ("ks_eg", _i32), ("mac_my", _i32)]
+
+
 _SIGS = {
     "fhelin_primes_generate": [_i32, _i32, _i32, _vp],
     "fhelin_ctx_create": [ctypes.POINTER(fhelin_params), _pvp],
@@ -84,6 +88,10 @@ _SIGS = {
     "fhelin_rescale": [_vp, ctypes.POINTER(fhelin_ct_batch), ctypes.POINTER(fhelin_ct_batch), _vp],
     "fhelin_rotate": [_vp, _vp, ctypes.POINTER(fhelin_ct_batch), _vp, ctypes.POINTER(fhelin_ct_batch), _vp],
     "fhelin_ntt": [_vp, _vp, _vp, _i32, _i32, _vp],
+    "fhelin_plan_get_tune": [_vp, _vp],
+    "fhelin_plan_set_tune": [_vp, _vp],
+    "fhelin_plan_autotune": [_vp, _vp, _vp, _vp, ctypes.POINTER(fhelin_ct_batch), ctypes.POINTER(fhelin_ct_batch),
+                             _i32, _vp, _vp, ctypes.POINTER(_dbl)],
     "fhelin_graph_capture_linear": [_vp, _vp, _vp, _vp, ctypes.POINTER(fhelin_ct_batch),
                                     ctypes.POINTER(fhelin_ct_batch), _i32, _vp, _pvp],
     "fhelin_graph_launch": [_vp, _vp],
@@ -309,6 +317,29 @@ def fhelin_linear_apply_multi(ctx, plan, ks_per_request, pts, x: torch.Tensor, x
     arr = (_vp * max(1, len(ks_per_request)))(*[k.value if isinstance(k, _vp) else k for k in ks_per_request])
     _check(_lib.fhelin_linear_apply_multi(ctx, plan, ctypes.cast(arr, _vp), pts, ctypes.byref(bi), ctypes.byref(bo),
                                           flags, _stream(stream)))
+
+
+def fhelin_plan_get_tune(plan) -> dict:
+    t = fhelin_tune()
+    _check(_lib.fhelin_plan_get_tune(plan, ctypes.byref(t)))
+    return {"chunk": t.chunk, "ks_eg": t.ks_eg, "mac_my": t.mac_my}
+
+
+def fhelin_plan_set_tune(plan, chunk: int = 0, ks_eg: int = 8, mac_my: int = 8):
+    t = fhelin_tune(chunk, ks_eg, mac_my)
+    _check(_lib.fhelin_plan_set_tune(plan, ctypes.byref(t)))
+
+
+def fhelin_plan_autotune(ctx, plan, ks_per_request, pts, x: torch.Tensor, x_levels, y: torch.Tensor, y_levels,
+                         flags=0, stream=None):
+    """Time candidate tunes on this batch, keep the fastest in the plan; y holds the layer's
+    result on return.  Returns (tune dict, best time in ms)."""
+    bi, bo = ct_batch(x, x_levels), ct_batch(y, y_levels)
+    arr = (_vp * max(1, len(ks_per_request)))(*[k.value if isinstance(k, _vp) else k for k in ks_per_request])
+    t, ms = fhelin_tune(), _dbl()
+    _check(_lib.fhelin_plan_autotune(ctx, plan, ctypes.cast(arr, _vp), pts, ctypes.byref(bi), ctypes.byref(bo),
+                                     flags, _stream(stream), ctypes.byref(t), ctypes.byref(ms)))
+    return {"chunk": t.chunk, "ks_eg": t.ks_eg, "mac_my": t.mac_my}, float(ms.value)
 
 
 def fhelin_graph_capture_linear(ctx, plan, ks, pts, x: torch.Tensor, x_levels, y: torch.Tensor, y_levels, flags=0,

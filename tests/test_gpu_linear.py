@@ -320,3 +320,54 @@ def test_conv_double_hoisted_bit_exact(F, c_in, c_out, k):
             assert np.array_equal(got[o], O.rescale(prm, want[o], level)), o
     finally:
         lay.close()
+
+
+# ---------------------------------------------------------------------------
+# tile / chunk choices and the autotuner
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("dh", [False, True])
+def test_tunes_bit_identical_and_autotune(F, dh):
+    """Every tune (chunk, key-switch entry group, MAC requests per thread) gives the
+    oracle's ciphertexts bit for bit on a batch of uneven levels; the autotuner keeps
+    a valid tune and leaves the layer's result in the output."""
+    print(f"tunes dh={dh}", flush=True)
+    prm = O.make_params(12, 5, 2, 3, 50, 2.0 ** 40)
+    st = synth.Stream(4700 + dh)
+    n, n1 = 64, 8
+    W = st.he_normal((n, n), n)
+    sched = O.fc_schedule(n, n1)
+    pts = encode_pts(prm, O.fc_slots(W, n, n1, prm.S), prm.L, prm.scale)
+    cl = Client(prm, 4701)
+    keys = cl.keyset(sched.rotations())
+    levels = [5, 2, 4, 3, 5, 2, 3, 4, 5, 3, 2]
+    cts = [cl.encrypt_slots(O.fc_input_slots(st.uniform(n, 0, 1), n, prm.S), l, prm.scale) for l in levels]
+    want = [O.rescale(prm, O.linear(prm, c[None], l, sched, pts, keys, hoist_moddown=dh)[0], l)
+            for c, l in zip(cts, levels)]
+    lay = Layer(F, prm, keys, pts, prm.L, fc_n=n, fc_out=n, fc_in=n, n1=n1)
+    try:
+        assert F.fhelin_plan_get_tune(lay.plan) == {"chunk": 0, "ks_eg": 8, "mac_my": 8}
+        for tune in [dict(chunk=0, ks_eg=8, mac_my=2), dict(chunk=4, ks_eg=3, mac_my=4),
+                     dict(chunk=1, ks_eg=16, mac_my=8), dict(chunk=5, ks_eg=1, mac_my=2)]:
+            F.fhelin_plan_set_tune(lay.plan, **tune)
+            got = lay.apply(cts, levels, stride=prm.L, dh=dh)
+            for t in range(len(levels)):
+                assert np.array_equal(got[t], want[t]), (tune, t)
+        with pytest.raises(F.FhelinError):
+            F.fhelin_plan_set_tune(lay.plan, chunk=0, ks_eg=8, mac_my=3)
+        with pytest.raises(F.FhelinError):
+            F.fhelin_plan_set_tune(lay.plan, chunk=65, ks_eg=8, mac_my=8)
+        F.fhelin_plan_set_tune(lay.plan)
+        x = dev(pad_cts(cts, prm.L, prm.N))
+        y = dev(np.zeros((len(cts), 2, prm.L, prm.N), np.uint64))
+        flags = F.FHELIN_APPLY_RESCALE | (F.FHELIN_APPLY_HOIST_MODDOWN if dh else 0)
+        best, ms = F.fhelin_plan_autotune(lay.ctx, lay.plan, [lay.ks] * len(cts), lay.pset, x, levels, y,
+                                          [l - 1 for l in levels], flags)
+        print("autotune", best, f"{ms:.3f} ms", flush=True)
+        assert best == F.fhelin_plan_get_tune(lay.plan)
+        assert best["mac_my"] in (2, 4, 8) and best["ks_eg"] in (4, 8, 16) and best["chunk"] in (0, 32, 16, 8, 4)
+        assert ms >= 0
+        got = host(y)
+        for t, l in enumerate(levels):
+            assert np.array_equal(got[t, :, : l - 1], want[t]), t
+    finally:
+        lay.close()
