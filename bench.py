@@ -50,6 +50,9 @@ def parse():
                     help="requests per arrival rate in an extra serving run (default 0 = no serving run)")
     ap.add_argument("--serve-rates", type=str, default="20,100", help="Poisson arrival rates (req/s)")
     ap.add_argument("--serve-clients", type=int, default=32)
+    ap.add_argument("--pmc-summary", type=str, default="",
+                    help="instead of the benchmark: FETCH,WRITE,CALIB_FETCH,CALIB_WRITE rocprofv3 --pmc output "
+                         "directories -> the measured-traffic file used for roofline.traffic")
     ap.add_argument("--calib-copy", type=float, default=0.0,
                     help="instead of the benchmark: copy this many GiB device-to-device 3 times (traffic-counter "
                          "calibration)")
@@ -65,8 +68,86 @@ WORKLOAD = dict(log_n=16, L=12, K=3, dnum=4, bits=50, scale=2.0 ** 40, fc=256, n
 ALU_LANE_OPS = 256 * 64 * 2.4e9
 BFLY_VALU_OPS = 24
 PEAK_BFLY = ALU_LANE_OPS / BFLY_VALU_OPS / 1e12  # T butterflies (= modular multiplies) per second
+# A product of the packed multiply-accumulate is four v_mad_u64_u32 plus one add, and
+# every 16 products end in one ~16-instruction-per-product-share Montgomery reduction
+# of the three partial sums (about 30 instructions): 6 VALU instructions per product.
+MAC_VALU_OPS = 6
+PEAK_MAC = ALU_LANE_OPS / MAC_VALU_OPS / 1e12  # T modular products per second
+HBM_PEAK_GBPS = 8000.0
+# roofline of each kernel class: (bound, unit of `achieved`, peak)
+ROOF = {k: ("alu", "T modmul-butterflies/s", PEAK_BFLY) for k in
+        ("ntt_fwd_cols", "ntt_fwd_rows", "ntt_inv_rows", "ntt_inv_cols")}
+ROOF["mac"] = ("alu", "T modular products/s", PEAK_MAC)
+for _k in ("ks_inner", "modup", "moddown_fbc", "combine", "copy", "rescale", "mont"):
+    ROOF[_k] = ("hbm", "GB/s", HBM_PEAK_GBPS)
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic.json")
 KERNELS = ["ntt_fwd_cols", "ntt_fwd_rows", "ntt_inv_rows", "ntt_inv_cols", "mac", "ks_inner", "modup",
            "moddown_fbc", "combine", "rescale", "copy", "mont", "encode"]
+
+
+def _lib_digest() -> str:
+    import hashlib
+    with open(os.path.join(ROOT, "paper_2509_01253_amd", "libfhelin.so"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic(kernel: str, launches: int, args):
+    """HBM bytes per launch of `kernel` measured with rocprofv3 FETCH_SIZE / WRITE_SIZE on
+    this workload and tune (calibrated against a copy kernel), if the stored measurement
+    was taken with the library that is loaded now; else None."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("library_sha256") != _lib_digest() or t.get("bench_args") != traffic_args(args):
+        return None
+    k = t.get("kernels", {}).get(kernel)
+    return None if k is None else k["bytes_per_dispatch"]
+
+
+def traffic_args(args) -> dict:
+    return {"batch": args.batch, "n1": args.n1, "schedule": args.schedule, "autotune": bool(args.autotune)}
+
+
+def pmc_summary(dirs: str, args) -> None:
+    """Write the traffic file from four rocprofv3 --pmc output directories: FETCH_SIZE
+    and WRITE_SIZE of this benchmark run with the same workload flags, then of the
+    --calib-copy 1 run (a 1 GiB device copy: the scale of each counter)."""
+    import csv
+    import glob
+    fetch, write, cfetch, cwrite = dirs.split(",")
+
+    def per_kernel(d):
+        files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+        acc = {}
+        for r in csv.DictReader(open(files[0])):
+            name = r["Kernel_Name"].split("(")[0].replace("void ", "").replace("fl::", "")
+            name = name.split("<")[0]
+            acc.setdefault(name, []).append(float(r["Counter_Value"]))
+        return acc
+
+    def copy_kib(d):
+        return max(per_kernel(d)["__amd_rocclr_copyBuffer"])
+
+    gib = 1 << 20  # KiB in 1 GiB: the calibration copy moves 1 GiB each way
+    f_scale, w_scale = gib / copy_kib(cfetch), gib / copy_kib(cwrite)
+    fk, wk = per_kernel(fetch), per_kernel(write)
+    names = {"k_mac": "mac", "k_ks_inner": "ks_inner", "k_ntt_fwd_rows": "ntt_fwd_rows",
+             "k_ntt_fwd_cols": "ntt_fwd_cols", "k_ntt_inv_rows": "ntt_inv_rows", "k_ntt_inv_cols": "ntt_inv_cols",
+             "k_modup": "modup", "k_moddown_fbc": "moddown_fbc", "k_moddown_combine": "combine",
+             "k_copy_rows": "copy", "k_rescale": "rescale", "k_to_mont": "mont"}
+    out = {"library_sha256": _lib_digest(), "bench_args": traffic_args(args), "fetch_scale": f_scale,
+           "write_scale": w_scale, "kernels": {}}
+    for raw, cls in names.items():
+        if raw in fk and raw in wk:
+            fb = sum(fk[raw]) / len(fk[raw]) * 1024 * f_scale
+            wb = sum(wk[raw]) / len(wk[raw]) * 1024 * w_scale
+            out["kernels"][cls] = {"dispatches": len(fk[raw]), "fetch_bytes_per_dispatch": fb,
+                                   "write_bytes_per_dispatch": wb, "bytes_per_dispatch": fb + wb}
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps({k: round(v["bytes_per_dispatch"] / 2**30, 3) for k, v in out["kernels"].items()}))
 
 
 def algo_bytes(level: int, n_ks: int, n_mac: int, K: int, alpha: int, N: int) -> int:
@@ -200,6 +281,9 @@ def serve_bench(args) -> dict:
 
 def main():
     args = parse()
+    if args.pmc_summary:
+        pmc_summary(args.pmc_summary, args)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "one GPU only: requests scale out by routing clients to GPUs, not by splitting a "
                                    "layer; --gpus must be 1"}))
@@ -304,21 +388,27 @@ def main():
     ms = float(np.mean(lat))
     prof = {}
     for kname in KERNELS:
-        n, kms, units = F.fhelin_profile_read(ctx, kname)
+        n, kms, units, byts = F.fhelin_profile_read(ctx, kname)
         if n:
-            prof[kname] = {"launches": n, "ms_per_step": round(kms / args.steps, 3), "units": units}
+            prof[kname] = {"launches": n, "ms_per_step": round(kms / args.steps, 3), "units": units, "bytes": byts}
     F.fhelin_profile_enable(ctx, False)
     busy = sum(v["ms_per_step"] for v in prof.values())
     for v in prof.values():
         v["share"] = round(v["ms_per_step"] / busy, 4) if busy else 0.0
-    dom = max((k for k in prof if k.startswith("ntt_")), key=lambda k: prof[k]["ms_per_step"])
-    d = prof[dom]
-    avg_s = d["ms_per_step"] * args.steps / d["launches"] / 1e3
-    achieved = d["units"] / d["launches"] / avg_s / 1e12
-    roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 4), "peak": round(PEAK_BFLY, 4),
-                "unit": "T modmul-butterflies/s", "frac": round(achieved / PEAK_BFLY, 4), "traffic": None,
-                "avg_launch_ms": round(avg_s * 1e3, 4),
-                "units_per_launch": d["units"] / d["launches"]}
+    rooflines = {}
+    for kname, d in prof.items():
+        if kname not in ROOF:
+            continue
+        bound, unit, peak = ROOF[kname]
+        avg_s = d["ms_per_step"] * args.steps / d["launches"] / 1e3
+        per_launch = (d["bytes"] if bound == "hbm" else d["units"]) / d["launches"]
+        achieved = per_launch / avg_s / (1e9 if bound == "hbm" else 1e12)
+        rooflines[kname] = {"bound": bound, "achieved": round(achieved, 4), "peak": round(peak, 4), "unit": unit,
+                            "frac": round(achieved / peak, 4), "avg_launch_ms": round(avg_s * 1e3, 4),
+                            "per_launch": per_launch,
+                            "hbm_frac": round(d["bytes"] / d["launches"] / avg_s / 1e9 / HBM_PEAK_GBPS, 4)}
+    dom = max(rooflines, key=lambda k: prof[k]["ms_per_step"])
+    roofline = dict(rooflines[dom], kernel=dom, traffic=measured_traffic(dom, prof[dom]["launches"], args))
     layers_per_s = args.batch / (ms / 1e3)
     res = {
         "metric": "encrypted linear layers/s (N=2^16, 256x256 FC, batch of 64 at levels 4..12)",
@@ -345,6 +435,8 @@ def main():
         "plan": info,
         "timed_wall_s": round(total, 3),
         "roofline": roofline,
+        "rooflines": {k: {kk: v[kk] for kk in ("bound", "achieved", "unit", "frac", "hbm_frac", "avg_launch_ms")}
+                      for k, v in sorted(rooflines.items(), key=lambda kv: -prof[kv[0]]["ms_per_step"])[:4]},
         "kernels": {k: {"ms_per_step": v["ms_per_step"], "share": v["share"], "launches": v["launches"]}
                     for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["ms_per_step"])},
     }

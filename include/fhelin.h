@@ -241,7 +241,8 @@ int fhelin_linear_apply_multi(fhelin_ctx *ctx, const fhelin_plan *plan, const fh
  *           chunk keeps the working set of a chunk in the GPU's caches)
  *   ks_eg   batch entries per workgroup of the key-switch inner product (each
  *           workgroup reuses an evaluation-key tile across its entries), 1..64
- *   mac_my  requests per thread in the plaintext multiply-accumulate: 2, 4, 8 */
+ *   mac_my  requests per thread in the plaintext multiply-accumulate: 2, 4, 8
+ * A new plan starts at chunk 0, ks_eg 16, mac_my 2. */
 typedef struct fhelin_tune {
     int32_t chunk;
     int32_t ks_eg;
@@ -305,11 +306,14 @@ int fhelin_ntt(fhelin_ctx *ctx, uint64_t *rows, const int32_t *mod_index, int32_
  * ntt_inv_cols, ntt_fwd_1, ntt_inv_1, mac, ks_inner, modup, moddown_fbc,
  * combine, rescale, copy, mont, encode. */
 int fhelin_profile_enable(fhelin_ctx *ctx, int32_t enable);
-/* Totals of one kernel class since enabling: launches, summed event time (ms)
- * and summed algorithmic work units (butterflies for NTT passes, 64-bit
- * multiply-adds for mac / ks_inner, output elements otherwise).  Waits for the
- * recorded events.  Output pointers may be NULL. */
-int fhelin_profile_read(fhelin_ctx *ctx, const char *kernel, int64_t *launches, double *total_ms, double *units);
+/* Totals of one kernel class since enabling: launches, summed event time (ms),
+ * summed algorithmic work units (butterflies for NTT passes, 64-bit
+ * multiply-adds for mac / ks_inner, output elements otherwise) and summed
+ * algorithmic HBM bytes (every input and output stream of the launch counted
+ * once; distinct evaluation keys once per launch; 0 for classes without a byte
+ * model).  Waits for the recorded events.  Output pointers may be NULL. */
+int fhelin_profile_read(fhelin_ctx *ctx, const char *kernel, int64_t *launches, double *total_ms, double *units,
+                        double *bytes);
 
 const char *fhelin_last_error(void);
 const char *fhelin_status_string(int status);

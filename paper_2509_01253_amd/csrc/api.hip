@@ -540,7 +540,7 @@ FHELIN_EXPORT int fhelin_profile_enable(fhelin_ctx *ctx, int32_t enable) {
 }
 
 FHELIN_EXPORT int fhelin_profile_read(fhelin_ctx *ctx, const char *kernel, int64_t *launches, double *total_ms,
-                                      double *units) {
+                                      double *units, double *bytes) {
     API_BEGIN FL_CHECK(ctx && kernel, FHELIN_E_INVALID_ARG, "null argument");
     Ctx *c = (Ctx *)ctx;
     DeviceGuard g(c);
@@ -551,7 +551,7 @@ FHELIN_EXPORT int fhelin_profile_read(fhelin_ctx *ctx, const char *kernel, int64
     Profiler *p = c->prof.get();
     std::lock_guard<std::mutex> lk(p->mu);
     int64_t n = 0;
-    double ms = 0, u = 0;
+    double ms = 0, u = 0, by = 0;
     for (auto &r : p->recs) {
         if (r.kind != kind) continue;
         FL_TRY_HIP(hipEventSynchronize(r.b));
@@ -560,10 +560,12 @@ FHELIN_EXPORT int fhelin_profile_read(fhelin_ctx *ctx, const char *kernel, int64
         ++n;
         ms += t;
         u += r.units;
+        by += r.bytes;
     }
     if (launches) *launches = n;
     if (total_ms) *total_ms = ms;
     if (units) *units = u;
+    if (bytes) *bytes = by;
     return FHELIN_OK;
     API_END
 }

@@ -333,7 +333,8 @@ hipEvent_t Profiler::get() {
     return e;
 }
 
-ProfScope::ProfScope(const Ctx *c, hipStream_t st, int k, double u) : s(st), kind(k), units(u) {
+ProfScope::ProfScope(const Ctx *c, hipStream_t st, int k, double u, double by)
+    : s(st), kind(k), units(u), bytes(by) {
     Profiler *pr = c->prof.get();
     if (!pr->on) return;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
@@ -350,7 +351,7 @@ ProfScope::~ProfScope() {
     std::lock_guard<std::mutex> g(p->mu);
     hipEvent_t b = p->get();
     if (!b || hipEventRecord(b, s) != hipSuccess) return;
-    p->recs.push_back({kind, a, b, units});
+    p->recs.push_back({kind, a, b, units, bytes});
 }
 
 int Ready::record(hipStream_t s) {

@@ -99,6 +99,7 @@ struct Profiler {
         int kind;
         hipEvent_t a, b;
         double units;  // algorithmic work of the launch (butterflies, multiply-adds, elements)
+        double bytes;  // algorithmic HBM bytes of the launch (each stream read or written once)
     };
     std::vector<Rec> recs;
     std::vector<hipEvent_t> pool;
@@ -296,11 +297,12 @@ struct PtSet {
     Ready ready;
 };
 
-// Tile and chunk choices of a layer schedule (results do not depend on them).
+// Tile and chunk choices of a layer schedule (results do not depend on them).  The
+// defaults are the autotuner's choice on the batched N = 2^16 FC workload.
 struct Tune {
     int chunk = 0;    // requests per chunk (0: as many as fit MAX_BATCH ciphertexts)
-    int ks_eg = 8;    // batch entries per key-switch inner-product workgroup
-    int mac_my = 8;   // requests per thread in the multiply-accumulate
+    int ks_eg = 16;   // batch entries per key-switch inner-product workgroup
+    int mac_my = 2;   // requests per thread in the multiply-accumulate
 };
 bool tune_valid(const Tune &t);
 
@@ -339,9 +341,9 @@ struct ProfScope {
     Profiler *p = nullptr;
     hipStream_t s;
     int kind;
-    double units;
+    double units, bytes;
     hipEvent_t a{};
-    ProfScope(const Ctx *c, hipStream_t st, int k, double u);
+    ProfScope(const Ctx *c, hipStream_t st, int k, double u, double by = 0);
     ~ProfScope();
 };
 

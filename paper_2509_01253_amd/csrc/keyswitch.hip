@@ -80,12 +80,13 @@ int launch_modup(const Ctx *c, const Batch &b, const uint64_t *coef, int64_t coe
     int lmax = 0;
     for (int t = 0; t < b.n; ++t) lmax = b.level[t] > lmax ? b.level[t] : lmax;
     int beta = (lmax + c->alpha - 1) / c->alpha;
-    double units = 0;
+    double units = 0, bytes = 0;
     for (int t = 0; t < b.n; ++t) {
         const double l = b.level[t];
         units += std::ceil(l / c->alpha) * (l + c->K) * c->N;
+        bytes += 8.0 * c->N * (l + std::ceil(l / c->alpha) * (l + c->K));  // read l limbs, write the digits
     }
-    ProfScope ps(c, s, PK_MODUP, units);
+    ProfScope ps(c, s, PK_MODUP, units, bytes);
     hipLaunchKernelGGL(k_modup, dim3(c->N / 256, beta, b.n), dim3(256), 0, s, b, c->d_mods, c->d_modup, coef, coef_es,
                        ntt, ntt_es, digits, digits_es, c->log_n, c->L, c->K, c->alpha, c->dnum);
     FL_TRY_HIP(hipGetLastError());
@@ -181,12 +182,28 @@ __global__ void __launch_bounds__(256) k_ks_inner(Batch b, const ModConst *__res
 static int launch_ks_inner_impl(const Ctx *c, const Batch &b, const uint64_t *digits, int64_t digits_es, uint64_t *u,
                                 int64_t u_es, KsAdd add, hipStream_t s, int eg) {
     if (b.n == 0) return FHELIN_OK;
-    double units = 0;
+    // work: 2 beta (l + K) N products per entry; bytes: digits beta (l + K) limbs, the
+    // addend (l + K limbs extended, l limbs lifted), the accumulated sum read back, two
+    // output polynomials, and each distinct key once (2 beta_k (l_k + K) limbs)
+    double units = 0, bytes = 0;
+    const double limb = 8.0 * c->N;
+    const uint64_t *seen[MAX_BATCH];
+    int n_seen = 0;
     for (int t = 0; t < b.n; ++t) {
-        const double l = b.level[t];
-        units += 2.0 * std::ceil(l / c->alpha) * (l + c->K) * c->N;
+        const double l = b.level[t], beta = std::ceil(l / c->alpha), e = l + c->K;
+        units += 2.0 * beta * e * c->N;
+        bytes += limb * (beta * e + 2 * e);
+        if (add.src) bytes += limb * (add.ext ? e : l);
+        if (add.accumulate) bytes += limb * 2 * e;
+        bool dup = false;
+        for (int i = 0; i < n_seen; ++i) dup |= seen[i] == b.key[t];
+        if (!dup) {
+            seen[n_seen++] = b.key[t];
+            const double kl = b.key_level[t];
+            bytes += limb * 2 * std::ceil(kl / c->alpha) * (kl + c->K);
+        }
     }
-    ProfScope ps(c, s, PK_KS_INNER, units);
+    ProfScope ps(c, s, PK_KS_INNER, units, bytes);
     if (eg < 1) eg = 1;
     dim3 grid(c->N / 256, c->L + c->K, (b.n + eg - 1) / eg);
     if (c->small)
@@ -305,7 +322,10 @@ int launch_moddown_fbc(const Ctx *c, const Batch &b, const uint64_t *u, int64_t 
         const double l = b.level[t];
         units += 2.0 * l * c->N;
     }
-    ProfScope ps(c, s, PK_MODDOWN_FBC, units * n_parts / 2);
+    // reads K limbs per part per entry, writes l limbs per part: (K + l) N 8 bytes per part
+    double bytes = 0;
+    for (int t = 0; t < b.n; ++t) bytes += 8.0 * c->N * (c->K + b.level[t]) * n_parts;
+    ProfScope ps(c, s, PK_MODDOWN_FBC, units * n_parts / 2, bytes);
     hipLaunchKernelGGL(k_moddown_fbc, dim3(c->N / 256, n_parts, b.n), dim3(256), 0, s, b, c->d_mods, c->d_moddown, u,
                        u_es, md, md_es, c->log_n, c->L, c->K);
     FL_TRY_HIP(hipGetLastError());
@@ -351,7 +371,7 @@ int launch_moddown_combine(const Ctx *c, const Batch &b, const uint64_t *u, int6
         const double l = b.level[t];
         units += 2.0 * l * c->N;
     }
-    ProfScope ps(c, s, PK_COMBINE, units * n_parts / 2);
+    ProfScope ps(c, s, PK_COMBINE, units * n_parts / 2, 8.0 * units * n_parts / 2 * (c0 ? 4 : 3));
     hipLaunchKernelGGL(k_moddown_combine, dim3(c->N / 256, n_parts * lmax, b.n), dim3(256), 0, s, b, c->d_mods,
                        c->d_moddown, u, u_es, md, md_es, dst, dst_es, dst_stride, c0, c0_es, c0_stride, accumulate,
                        n_parts, c->log_n, c->L, c->K);
@@ -401,7 +421,7 @@ int launch_rescale(const Ctx *c, const Batch &b, const uint64_t *in, int64_t in_
         const double l = b.level[t];
         units += 2.0 * (l - 1) * c->N;
     }
-    ProfScope ps(c, s, PK_RESCALE, units);
+    ProfScope ps(c, s, PK_RESCALE, units, 16.0 * units);
     hipLaunchKernelGGL(k_rescale, dim3(c->N / 256, 2 * (lmax - 1), b.n), dim3(256), 0, s, b, c->d_mods, c->d_rs_inv,
                        c->d_rs_inv_sh, in, in_es, in_stride, out, out_es, out_stride, c->log_n, c->L);
     FL_TRY_HIP(hipGetLastError());
@@ -430,7 +450,7 @@ int launch_copy_rows(const Ctx *c, const RowMap &dst, const RowMap &src, hipStre
     int bx = c->N / 256 < 32 ? c->N / 256 : 32;
     double units = 0;
     for (int t = 0; t < dst.n_ct; ++t) units += (double)rowmap_rows(dst, t) * c->N;
-    ProfScope ps(c, s, PK_COPY, units);
+    ProfScope ps(c, s, PK_COPY, units, 16.0 * units);
     hipLaunchKernelGGL(k_copy_rows, dim3(bx, rows, dst.n_ct), dim3(256), 0, s, dst, src);
     FL_TRY_HIP(hipGetLastError());
     return FHELIN_OK;

@@ -75,7 +75,7 @@ int plan_create(Ctx *c, const fhelin_layer_desc *d, Plan **out) {
 
 // ---------------------------------------------------------------------------
 // pt x ct multiply-accumulate: A[e][j] = sum_i sum_b pt[o][i][j][b] * R[i][b]
-// grid (N/16, slots, n_out x request groups)
+// grid (N/16, slots, n_out)
 // ---------------------------------------------------------------------------
 struct MacArgs {
     const uint64_t *x;    // inputs, NTT domain [2][ls] per input entry
@@ -85,115 +85,117 @@ struct MacArgs {
     int n_in, n_out, B, Bp, G, pt_level;
     int ext;              // 0: Q limbs, ls = L; 1: extended basis, ls = L + K
     int8_t bmap[MAX_BABY];  // baby index -> slot in rb, -1 = identity (use x)
+    uint8_t order[MAX_BATCH];  // requests by descending level (a slot's active requests: a prefix)
 };
 
 // For one limb (slot s) and coefficient k the multiply-accumulate is a small matrix
-// product over the requests r of a group: A[r][j] = sum_t pt[o][j][t] * R[r][t]
-// (t = (input i, baby b)).  A workgroup takes 16 coefficients, one slot, one output
-// index o and a group of ET = MY * ES requests; plaintext and rotated-input tiles of
-// MAC_TB terms are staged in LDS, so each plaintext value is read from memory once per
-// group and each rotated input once per chunk of JT giant steps.  Thread (kl, jj):
-// coefficient kl, giant step jj mod JT, and the MY requests jj / JT + m ES of the group.
-// Rows of the request tile past the group or inactive at this slot are staged as zeros,
-// so the inner loop has no branches; only the stores are guarded.  Operands are staged
-// in the accumulator's form (28-bit halves when every modulus is below 2^55, else plain)
-// and products are summed lazily; every 16 terms the sum is Montgomery-reduced and
-// seeds the next 16.
+// product over the requests: A[r][j] = sum_t pt[o][j][t] * R[r][t] (t = (input i,
+// baby b)).  A workgroup takes 16 coefficients, one slot and one output index and runs
+// every request: thread (kl, jj) owns coefficient kl and giant step jj mod JT, keeps
+// its 16-term plaintext column in registers (read from memory once per workgroup),
+// and walks the requests in groups of ET = MY * ES, taking requests jj / JT + m ES of
+// each group.  The groups' rotated inputs are staged in LDS, 16 terms at a time
+// (zero past the last request), so the inner loop has no branches.  Requests go in
+// descending level order, so the requests a q slot exists for are a prefix and
+// the rest are skipped.  Operands are in the accumulator's form (28-bit halves
+// when every modulus is below 2^55, else plain); each 16-term chunk ends in one
+// Montgomery reduction that seeds the next chunk.
 constexpr int MAC_K = 16;   // coefficients per workgroup
-constexpr int MAC_TB = 4;   // terms per LDS chunk
-constexpr int MAC_ET = 32;  // requests per workgroup at most
+constexpr int MAC_TB = 16;  // terms per chunk
+constexpr int MAC_ET = 8;   // requests per group at most
 
-// MY = requests per thread (a tile choice); ES * MY = ET <= MAC_ET
+// MY = requests per thread (a tile choice); ES thread rows per giant step, ES * MY <= MAC_ET
 template <bool SMALL, int MY>
 __global__ void __launch_bounds__(256) k_mac(MacArgs a, Batch b, const ModConst *__restrict__ mods, int log_n,
-                                             int L, int K, int R, int JT, int ES, int ET) {
-    __shared__ uint64_t Ps[16][MAC_TB][MAC_K];
+                                             int L, int K, int R, int JT, int ES) {
     __shared__ uint64_t Rs[MAC_ET][MAC_TB][2][MAC_K];
     const int s = blockIdx.y;  // slot = modulus index (q_s for s < L, p_{s-L} otherwise)
     // a q slot above the plaintexts' level is active for no request (levels <= pt_level)
     if (s < L && s >= a.pt_level) return;
     const int64_t N = (int64_t)1 << log_n;
-    const int k0 = blockIdx.x * MAC_K;
-    const int o = blockIdx.z % a.n_out, r0 = (blockIdx.z / a.n_out) * ET;
+    const int k0 = blockIdx.x * MAC_K, o = blockIdx.z;
     const int kl = threadIdx.x & 15, jj = threadIdx.x >> 4;
-    const int jloc = jj % JT, es = min(jj / JT, ES - 1);  // es < ES keeps es + m ES < ET
+    const int jloc = jj % JT, es = jj / JT;
+    const bool computes = es < ES;  // other thread rows only help staging
+    const int esc = computes ? es : 0;
+    const int ET = MY * ES;
     const int ls = a.ext ? L + K : L;
     const int64_t ct = (int64_t)2 * ls * N;
     const int terms = a.n_in * a.B;
     const int prows = a.pt_level + K;
     const int prow = s < L ? s : a.pt_level + (s - L);
-    const int nr = min(ET, R - r0);
     const ModConst mc = mods[s];
-    // active(r): the group holds request rr and the slot exists at its level
-    auto active = [&](int rr) -> bool {
-        if (rr >= nr) return false;
-        const int l = b.level[(r0 + rr) * a.n_out + o];
-        return s < L ? s < l : a.ext != 0;
-    };
+    int n_act = R;  // requests this slot exists for
+    if (s < L) {
+        n_act = 0;
+        while (n_act < R && s < b.level[a.order[n_act] * a.n_out + o]) ++n_act;
+    }
+    const bool one_chunk = terms <= MAC_TB;
     for (int jc = 0; jc < a.G; jc += JT) {
         const int j = jc + jloc;
-        LazyAcc<SMALL> acc[MY][2];
-#pragma unroll
-        for (int m = 0; m < MY; ++m) {
-            acc[m][0].zero();
-            acc[m][1].zero();
-        }
-        for (int t0 = 0; t0 < terms; t0 += MAC_TB) {
-            // stage plaintexts: JT x MAC_TB x 16
-            for (int v = threadIdx.x; v < JT * MAC_TB * MAC_K; v += 256) {
-                const int kk = v % MAC_K, tt = (v / MAC_K) % MAC_TB, jl = v / (MAC_K * MAC_TB);
-                const int t = t0 + tt, jg = jc + jl;
-                uint64_t pv = 0;
-                if (t < terms && jg < a.G) {
-                    const int ii = t / a.B, bb = t % a.B;
-                    const int64_t pidx = ((int64_t)(o * a.n_in + ii) * a.G + jg) * a.B + bb;
-                    pv = LazyAcc<SMALL>::prep(a.pts[(pidx * prows + prow) * N + k0 + kk]);
-                }
-                Ps[jl][tt][kk] = pv;
-            }
-            // stage rotated inputs: ET x MAC_TB x 2 x 16 (zeros past the group / inactive)
-            for (int v = threadIdx.x; v < ET * MAC_TB * 2 * MAC_K; v += 256) {
-                const int kk = v % MAC_K, p = (v / MAC_K) % 2, tt = (v / (2 * MAC_K)) % MAC_TB,
-                          rr = v / (2 * MAC_K * MAC_TB);
-                const int t = t0 + tt;
-                uint64_t xv = 0;
-                if (t < terms && active(rr)) {
-                    const int ii = t / a.B, bb = t % a.B;
-                    const int64_t xin = (int64_t)(r0 + rr) * a.n_in + ii;
-                    const int m = a.bmap[bb];
-                    const uint64_t *src = m < 0 ? a.x + xin * ct : a.rb + (xin * a.Bp + m) * ct;
-                    xv = LazyAcc<SMALL>::prep(src[((int64_t)p * ls + s) * N + k0 + kk]);
-                }
-                Rs[rr][tt][p][kk] = xv;
-            }
-            __syncthreads();
+        uint64_t pv[MAC_TB];
+        auto load_pv = [&](int t0) {
 #pragma unroll
             for (int tt = 0; tt < MAC_TB; ++tt) {
-                const uint64_t pv = Ps[jloc][tt][kl];
-#pragma unroll
-                for (int m = 0; m < MY; ++m) {
-                    const int rr = es + m * ES;
-                    acc[m][0].mac(Rs[rr][tt][0][kl], pv);
-                    acc[m][1].mac(Rs[rr][tt][1][kl], pv);
+                const int t = t0 + tt;
+                pv[tt] = 0;
+                if (t < terms && j < a.G) {
+                    const int ii = t / a.B, bb = t % a.B;
+                    const int64_t pidx = ((int64_t)(o * a.n_in + ii) * a.G + j) * a.B + bb;
+                    pv[tt] = LazyAcc<SMALL>::prep(a.pts[(pidx * prows + prow) * N + k0 + kl]);
                 }
             }
-            __syncthreads();
-            if (((t0 + MAC_TB) % 16) == 0 || t0 + MAC_TB >= terms) {
+        };
+        if (one_chunk) load_pv(0);
+        for (int g0 = 0; g0 < n_act; g0 += ET) {
+            LazyAcc<SMALL> acc[MY][2];
+#pragma unroll
+            for (int m = 0; m < MY; ++m) {
+                acc[m][0].zero();
+                acc[m][1].zero();
+            }
+            for (int t0 = 0; t0 < terms; t0 += MAC_TB) {
+                if (!one_chunk) load_pv(t0);
+                __syncthreads();  // readers of the previous tile are done
+                for (int v = threadIdx.x; v < ET * MAC_TB * 2 * MAC_K; v += 256) {
+                    const int kk = v % MAC_K, p = (v / MAC_K) % 2, tt = (v / (2 * MAC_K)) % MAC_TB,
+                              rr = v / (2 * MAC_K * MAC_TB);
+                    const int t = t0 + tt, r = g0 + rr;
+                    uint64_t xv = 0;
+                    if (t < terms && r < n_act) {
+                        const int ii = t / a.B, bb = t % a.B;
+                        const int64_t xin = (int64_t)a.order[r] * a.n_in + ii;
+                        const int m = a.bmap[bb];
+                        const uint64_t *src = m < 0 ? a.x + xin * ct : a.rb + (xin * a.Bp + m) * ct;
+                        xv = LazyAcc<SMALL>::prep(src[((int64_t)p * ls + s) * N + k0 + kk]);
+                    }
+                    Rs[rr][tt][p][kk] = xv;
+                }
+                __syncthreads();
+#pragma unroll
+                for (int tt = 0; tt < MAC_TB; ++tt) {
+#pragma unroll
+                    for (int m = 0; m < MY; ++m) {
+                        const int rr = esc + m * ES;
+                        acc[m][0].mac(Rs[rr][tt][0][kl], pv[tt]);
+                        acc[m][1].mac(Rs[rr][tt][1][kl], pv[tt]);
+                    }
+                }
 #pragma unroll
                 for (int m = 0; m < MY; ++m)
 #pragma unroll
                     for (int p = 0; p < 2; ++p) acc[m][p].set(acc[m][p].reduce(mc.q, mc.mont_neg_inv));
             }
-        }
-        if (j < a.G && jj / JT < ES) {
+            if (computes && j < a.G) {
 #pragma unroll
-            for (int m = 0; m < MY; ++m) {
-                const int rr = es + m * ES;
-                if (active(rr)) {
-                    const int64_t e = (int64_t)(r0 + rr) * a.n_out + o;
-                    uint64_t *dst = a.acc + (e * a.G + j) * ct + (int64_t)s * N + k0 + kl;
-                    dst[0] = acc[m][0].value();
-                    dst[(int64_t)ls * N] = acc[m][1].value();
+                for (int m = 0; m < MY; ++m) {
+                    const int r = g0 + esc + m * ES;
+                    if (r < n_act) {
+                        const int64_t e = (int64_t)a.order[r] * a.n_out + o;
+                        uint64_t *dst = a.acc + (e * a.G + j) * ct + (int64_t)s * N + k0 + kl;
+                        dst[0] = acc[m][0].value();
+                        dst[(int64_t)ls * N] = acc[m][1].value();
+                    }
                 }
             }
         }
@@ -202,22 +204,34 @@ __global__ void __launch_bounds__(256) k_mac(MacArgs a, Batch b, const ModConst 
 
 static int launch_mac(const Ctx *c, const Plan *p, MacArgs &ma, const Batch &bout, hipStream_t s) {
     const int R = bout.n / p->n_out;
-    double macs = 0;
+    // work: 2 (active limbs) N G B n_in products per output entry; bytes: the rotated
+    // inputs (n_in B terms x 2 polys x active limbs per request), the accumulators
+    // (G x 2 x active limbs per output entry) and the plaintexts once (slots x n_pt limbs)
+    double macs = 0, bytes = 0;
     int lmax = 0;
+    const double limb = 8.0 * c->N;
     for (int e = 0; e < bout.n; ++e) {
         lmax = std::max<int>(lmax, bout.level[e]);
-        macs += 2.0 * (bout.level[e] + (ma.ext ? c->K : 0)) * (double)c->N * ma.G * ma.B * p->n_in;
+        const double act = bout.level[e] + (ma.ext ? c->K : 0);
+        macs += 2.0 * act * (double)c->N * ma.G * ma.B * p->n_in;
+        bytes += limb * 2 * act * ma.G;
+        if (e % p->n_out == 0) bytes += limb * 2 * act * ma.B * p->n_in;
     }
+    bytes += limb * (double)p->n_pt() * ((ma.ext ? c->K : 0) + std::min(lmax, ma.pt_level));
+    // requests by descending level (stable)
+    int idx[MAX_BATCH];
+    for (int r = 0; r < R; ++r) idx[r] = r;
+    std::stable_sort(idx, idx + R, [&](int x, int y) { return bout.level[x * p->n_out] > bout.level[y * p->n_out]; });
+    for (int r = 0; r < R; ++r) ma.order[r] = (uint8_t)idx[r];
     const int JT = std::min(ma.G, 16);
-    const int ES = 16 / JT;
     int MY = p->tune.mac_my;
-    while (MY > 2 && MY * ES > MAC_ET) MY /= 2;  // ES <= 16, so MY = 2 always fits
-    const int ET = MY * ES;
+    while (MY > 2 && MY > MAC_ET) MY /= 2;
+    const int ES = std::max(1, std::min(16 / JT, MAC_ET / MY));
     const int slots = ma.ext ? c->L + c->K : lmax;
-    ProfScope ps(c, s, PK_MAC, macs);
-    dim3 grid(c->N / MAC_K, slots, p->n_out * ((R + ET - 1) / ET));
+    ProfScope ps(c, s, PK_MAC, macs, bytes);
+    dim3 grid(c->N / MAC_K, slots, p->n_out);
 #define FL_MAC(SM, Y) hipLaunchKernelGGL((k_mac<SM, Y>), grid, dim3(256), 0, s, ma, bout, c->d_mods, c->log_n, c->L, \
-                                         c->K, R, JT, ES, ET)
+                                         c->K, R, JT, ES)
     if (c->small) {
         if (MY == 2) FL_MAC(true, 2);
         else if (MY == 4) FL_MAC(true, 4);

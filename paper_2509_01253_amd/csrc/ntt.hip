@@ -345,14 +345,15 @@ static void launch_ntt_t(const Ctx *c, const RowMap &rm, int rows, int inverse, 
     double total_rows = 0;
     for (int t = 0; t < rm.n_ct; ++t) total_rows += rowmap_rows(rm, t);
     const double bfly_per_stage = total_rows * (M / 2);
+    const double row_bytes = total_rows * 16.0 * M;  // each row read and written once per pass
     if (LOGN <= 12) {
         dim3 g(1, rows, rm.n_ct);
         if (!inverse) {
-            ProfScope ps(c, s, PK_NTT_FWD_1, bfly_per_stage * LOGN);
+            ProfScope ps(c, s, PK_NTT_FWD_1, bfly_per_stage * LOGN, row_bytes);
             hipLaunchKernelGGL(k_ntt_fwd_1<(LOGN <= 12 ? LOGN : 12)>, g, dim3(NTT_THREADS), 0, s, rm, c->d_mods, c->d_tw,
                                c->d_twp);
         } else {
-            ProfScope ps(c, s, PK_NTT_INV_1, bfly_per_stage * LOGN);
+            ProfScope ps(c, s, PK_NTT_INV_1, bfly_per_stage * LOGN, row_bytes);
             hipLaunchKernelGGL(k_ntt_inv_1<(LOGN <= 12 ? LOGN : 12)>, g, dim3(NTT_THREADS), 0, s, rm, c->d_mods, c->d_itw,
                                c->d_itwp);
         }
@@ -361,17 +362,17 @@ static void launch_ntt_t(const Ctx *c, const RowMap &rm, int rows, int inverse, 
         dim3 g(M / TILE, rows, rm.n_ct);
         if (!inverse) {
             {
-                ProfScope ps(c, s, PK_NTT_FWD_COLS, bfly_per_stage * (LOGN - 8));
+                ProfScope ps(c, s, PK_NTT_FWD_COLS, bfly_per_stage * (LOGN - 8), row_bytes);
                 hipLaunchKernelGGL(k_ntt_fwd_cols<L2>, g, dim3(NTT_THREADS), 0, s, rm, c->d_mods, c->d_tw, c->d_twp);
             }
-            ProfScope ps(c, s, PK_NTT_FWD_ROWS, bfly_per_stage * 8);
+            ProfScope ps(c, s, PK_NTT_FWD_ROWS, bfly_per_stage * 8, row_bytes);
             hipLaunchKernelGGL(k_ntt_fwd_rows<L2>, g, dim3(NTT_THREADS), 0, s, rm, c->d_mods, c->d_tw, c->d_twp);
         } else {
             {
-                ProfScope ps(c, s, PK_NTT_INV_ROWS, bfly_per_stage * 8);
+                ProfScope ps(c, s, PK_NTT_INV_ROWS, bfly_per_stage * 8, row_bytes);
                 hipLaunchKernelGGL(k_ntt_inv_rows<L2>, g, dim3(NTT_THREADS), 0, s, rm, c->d_mods, c->d_itw, c->d_itwp);
             }
-            ProfScope ps(c, s, PK_NTT_INV_COLS, bfly_per_stage * (LOGN - 8));
+            ProfScope ps(c, s, PK_NTT_INV_COLS, bfly_per_stage * (LOGN - 8), row_bytes);
             hipLaunchKernelGGL(k_ntt_inv_cols<L2>, g, dim3(NTT_THREADS), 0, s, rm, c->d_mods, c->d_itw, c->d_itwp);
         }
     }
@@ -400,7 +401,7 @@ static int launch_mont(const Ctx *c, const RowMap &rm, int to, hipStream_t s) {
     int bx = c->N / 256 < 64 ? c->N / 256 : 64;
     double units = 0;
     for (int t = 0; t < rm.n_ct; ++t) units += (double)rowmap_rows(rm, t) * c->N;
-    ProfScope ps(c, s, PK_MONT, units);
+    ProfScope ps(c, s, PK_MONT, units, 16.0 * units);
     hipLaunchKernelGGL(k_to_mont, dim3(bx, rows, rm.n_ct), dim3(256), 0, s, rm, c->d_mods, to);
     FL_TRY_HIP(hipGetLastError());
     return FHELIN_OK;

@@ -98,7 +98,7 @@ _SIGS = {
     "fhelin_graph_destroy": [_vp],
     "fhelin_profile_enable": [_vp, _i32],
     "fhelin_profile_read": [_vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
-                            ctypes.POINTER(ctypes.c_double)],
+                            ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)],
 }
 for _name, _args in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -325,7 +325,7 @@ def fhelin_plan_get_tune(plan) -> dict:
     return {"chunk": t.chunk, "ks_eg": t.ks_eg, "mac_my": t.mac_my}
 
 
-def fhelin_plan_set_tune(plan, chunk: int = 0, ks_eg: int = 8, mac_my: int = 8):
+def fhelin_plan_set_tune(plan, chunk: int = 0, ks_eg: int = 16, mac_my: int = 2):
     t = fhelin_tune(chunk, ks_eg, mac_my)
     _check(_lib.fhelin_plan_set_tune(plan, ctypes.byref(t)))
 
@@ -384,7 +384,8 @@ def fhelin_profile_enable(ctx, enable: bool = True):
 
 
 def fhelin_profile_read(ctx, kernel: str):
-    """(launches, total_ms, units) for one kernel class."""
-    n, ms, u = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
-    _check(_lib.fhelin_profile_read(ctx, kernel.encode(), ctypes.byref(n), ctypes.byref(ms), ctypes.byref(u)))
-    return int(n.value), float(ms.value), float(u.value)
+    """(launches, total_ms, units, bytes) for one kernel class."""
+    n, ms, u, by = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _check(_lib.fhelin_profile_read(ctx, kernel.encode(), ctypes.byref(n), ctypes.byref(ms), ctypes.byref(u),
+                                    ctypes.byref(by)))
+    return int(n.value), float(ms.value), float(u.value), float(by.value)

@@ -345,7 +345,7 @@ def test_tunes_bit_identical_and_autotune(F, dh):
             for c, l in zip(cts, levels)]
     lay = Layer(F, prm, keys, pts, prm.L, fc_n=n, fc_out=n, fc_in=n, n1=n1)
     try:
-        assert F.fhelin_plan_get_tune(lay.plan) == {"chunk": 0, "ks_eg": 8, "mac_my": 8}
+        assert F.fhelin_plan_get_tune(lay.plan) == {"chunk": 0, "ks_eg": 16, "mac_my": 2}
         for tune in [dict(chunk=0, ks_eg=8, mac_my=2), dict(chunk=4, ks_eg=3, mac_my=4),
                      dict(chunk=1, ks_eg=16, mac_my=8), dict(chunk=5, ks_eg=1, mac_my=2)]:
             F.fhelin_plan_set_tune(lay.plan, **tune)
@@ -356,7 +356,7 @@ def test_tunes_bit_identical_and_autotune(F, dh):
             F.fhelin_plan_set_tune(lay.plan, chunk=0, ks_eg=8, mac_my=3)
         with pytest.raises(F.FhelinError):
             F.fhelin_plan_set_tune(lay.plan, chunk=65, ks_eg=8, mac_my=8)
-        F.fhelin_plan_set_tune(lay.plan)
+        F.fhelin_plan_set_tune(lay.plan, chunk=0, ks_eg=8, mac_my=8)
         x = dev(pad_cts(cts, prm.L, prm.N))
         y = dev(np.zeros((len(cts), 2, prm.L, prm.N), np.uint64))
         flags = F.FHELIN_APPLY_RESCALE | (F.FHELIN_APPLY_HOIST_MODDOWN if dh else 0)
