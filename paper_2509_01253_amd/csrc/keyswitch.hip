@@ -111,7 +111,8 @@ struct KsAdd {
 // or p_{s-L}; the key rows of slot s are the same for every entry of the group, so a
 // thread loads them once per key and reuses them.
 
-template <bool SMALL>
+// MAXB >= dnum bounds the digits (the key rows a thread keeps in registers).
+template <bool SMALL, int MAXB>
 __global__ void __launch_bounds__(256) k_ks_inner(Batch b, const ModConst *__restrict__ mods,
                                                   const ModDownTab *__restrict__ mdt,
                                                   const uint64_t *__restrict__ digits, int64_t digits_es,
@@ -121,11 +122,11 @@ __global__ void __launch_bounds__(256) k_ks_inner(Batch b, const ModConst *__res
     const int64_t N = (int64_t)1 << log_n;
     const int k = blockIdx.x * 256 + threadIdx.x;
     const ModConst mc = mods[s];
-    constexpr int MAXB = 16;
     uint64_t kb[MAXB], ka[MAXB];
     const uint64_t *cur_key = nullptr;
     int cur_beta = 0;
     const int e_end = min(b.n, (int)(blockIdx.z + 1) * eg);
+#pragma unroll 2
     for (int t = blockIdx.z * eg; t < e_end; ++t) {
         const int l = b.level[t];
         if (s < L && s >= l) continue;
@@ -206,12 +207,19 @@ static int launch_ks_inner_impl(const Ctx *c, const Batch &b, const uint64_t *di
     ProfScope ps(c, s, PK_KS_INNER, units, bytes);
     if (eg < 1) eg = 1;
     dim3 grid(c->N / 256, c->L + c->K, (b.n + eg - 1) / eg);
-    if (c->small)
-        hipLaunchKernelGGL(k_ks_inner<true>, grid, dim3(256), 0, s, b, c->d_mods, c->d_moddown, digits, digits_es, u,
-                           u_es, add, c->log_n, c->L, c->K, c->alpha, eg);
-    else
-        hipLaunchKernelGGL(k_ks_inner<false>, grid, dim3(256), 0, s, b, c->d_mods, c->d_moddown, digits, digits_es, u,
-                           u_es, add, c->log_n, c->L, c->K, c->alpha, eg);
+#define FL_KS(SM, MB) hipLaunchKernelGGL((k_ks_inner<SM, MB>), grid, dim3(256), 0, s, b, c->d_mods, c->d_moddown, \
+                                         digits, digits_es, u, u_es, add, c->log_n, c->L, c->K, c->alpha, eg)
+    const int n_digits = (c->L + c->alpha - 1) / c->alpha;  // at most 16 (checked at context creation)
+    if (c->small) {
+        if (n_digits <= 4) FL_KS(true, 4);
+        else if (n_digits <= 8) FL_KS(true, 8);
+        else FL_KS(true, 16);
+    } else {
+        if (n_digits <= 4) FL_KS(false, 4);
+        else if (n_digits <= 8) FL_KS(false, 8);
+        else FL_KS(false, 16);
+    }
+#undef FL_KS
     FL_TRY_HIP(hipGetLastError());
     return FHELIN_OK;
 }

@@ -1,0 +1,135 @@
+"""Parity at the workloads' full sizes, in the launch configuration the benchmark
+times (double-hoisted schedule, default tune, N = 2^16, 12 + 3 primes of 50 bits,
+dnum 4).  Key material, plaintexts and ciphertexts are uniform residues: the
+kernels' results are exact integer functions of them, so bit-exactness needs no
+valid encryption (decryption error is covered at smaller N).  The oracle computes
+sampled requests one by one; every other output is checked against the same
+request evaluated alone."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2509_01253_amd import synth
+from tests.gpu_util import dev, host, keys_at, pad_cts
+
+pytestmark = pytest.mark.gpu
+
+
+def _params():
+    return O.make_params(16, 12, 3, 4, 50, 2.0 ** 40)
+
+
+def _uniform_keys(prm, galois, st):
+    evk = np.stack([np.stack([np.stack([synth.uniform_limbs(st, prm.mods, prm.N) for _ in range(2)])
+                              for _ in range(prm.dnum)]) for _ in galois])
+    return O.KeySet(list(galois), evk)
+
+
+def _uniform_pts(prm, n_pt, level, st):
+    return np.stack([synth.uniform_limbs(st, prm.q[:level] + prm.p, prm.N) for _ in range(n_pt)])
+
+
+def _uniform_ct(prm, level, st):
+    return np.stack([synth.uniform_limbs(st, prm.q[:level], prm.N) for _ in range(2)])
+
+
+def test_fc256_batch64_full_size():
+    """Batched FC 256x256 (n1 = 16): 64 requests at levels 4..12 in one call; the two
+    lowest-level requests bit-exact against the oracle, four others equal to the same
+    request evaluated alone."""
+    import torch
+
+    from paper_2509_01253_amd import fhelin as F
+    print("full size: FC 256x256, batch 64, N=2^16", flush=True)
+    prm = _params()
+    st = synth.Stream(synth.master_seed(3)).sub(1001)
+    sched = O.fc_schedule(256, 16)
+    ctx = F.fhelin_ctx_create(prm.log_n, prm.q, prm.p, prm.dnum)
+    try:
+        plan = F.fhelin_plan_create(ctx, F.FHELIN_LAYER_FC, fc_n=256, fc_out=256, fc_in=256, n1=16)
+        galois = F.fhelin_plan_galois(plan)
+        assert galois == sorted({O.galois_of(r, prm.log_n) for r in sched.rotations()} - {1})
+        keys = _uniform_keys(prm, galois, st.sub(1))
+        pts = _uniform_pts(prm, 256, prm.L, st.sub(2))
+        levels = [int(v) for v in st.sub(3).integers(64, 4, 12)]
+        cts = [_uniform_ct(prm, l, st.sub(100 + i)) for i, l in enumerate(levels)]
+        print("inputs ready", flush=True)
+        ks = F.fhelin_keyset_load(ctx, galois, prm.L, dev(keys_at(prm, keys, prm.L)))
+        pset = F.fhelin_pt_import(ctx, dev(pts), level=prm.L)
+        x = dev(pad_cts(cts, prm.L, prm.N))
+        y = dev(np.zeros((64, 2, prm.L, prm.N), np.uint64))
+        flags = F.FHELIN_APPLY_RESCALE | F.FHELIN_APPLY_HOIST_MODDOWN
+        F.fhelin_linear_apply(ctx, plan, ks, pset, x, levels, y, [l - 1 for l in levels], flags)
+        got = host(y)
+        print("gpu done", flush=True)
+        # four requests alone
+        for t in (0, 17, 40, 63):
+            y1 = dev(np.zeros((1, 2, prm.L, prm.N), np.uint64))
+            F.fhelin_linear_apply(ctx, plan, ks, pset, dev(pad_cts([cts[t]], prm.L, prm.N)), [levels[t]], y1,
+                                  [levels[t] - 1], flags)
+            assert np.array_equal(host(y1)[0, :, : levels[t] - 1], got[t, :, : levels[t] - 1]), t
+        # the oracle on the two lowest-level requests
+        pts6 = pts.reshape(1, 1, sched.G, sched.B, prm.L + prm.K, prm.N)
+        for t in sorted(range(64), key=lambda i: levels[i])[:2]:
+            l = levels[t]
+            want = O.rescale(prm, O.linear(prm, cts[t][None], l, sched, pts6, keys, hoist_moddown=True)[0], l)
+            assert np.array_equal(got[t, :, : l - 1], want), (t, l)
+            print(f"oracle request {t} (level {l}) bit-exact", flush=True)
+        F.fhelin_ptset_release(pset)
+        F.fhelin_keyset_release(ks)
+        F.fhelin_plan_destroy(plan)
+    finally:
+        F.fhelin_ctx_destroy(ctx)
+        torch.cuda.synchronize()
+
+
+def test_resnet18_stem_conv_full_size():
+    """The ResNet-18 stem on 64x64x3 inputs at N = 2^16 and level 3 (one input
+    ciphertext, 64 output channels in 8 ciphertexts, 3x3 kernel): every output
+    ciphertext bit-exact against the oracle, through a captured graph as the layer
+    stack replays it."""
+    import torch
+
+    from paper_2509_01253_amd import fhelin as F
+    print("full size: stem conv 3->64 @64x64, N=2^16, level 3", flush=True)
+    prm = _params()
+    level = 3
+    st = synth.Stream(synth.master_seed(4)).sub(1002)
+    cs = O.ConvShape(3, 64, 64, 64, 3)
+    sched = O.conv_schedule(cs, prm.S)
+    ctx = F.fhelin_ctx_create(prm.log_n, prm.q, prm.p, prm.dnum)
+    stream = torch.cuda.Stream()
+    try:
+        plan = F.fhelin_plan_create(ctx, F.FHELIN_LAYER_CONV, c_in=3, c_out=64, h=64, w=64, k=3)
+        info = F.fhelin_plan_info(plan)
+        assert (info["n_in"], info["n_out"]) == (sched.n_in, sched.n_out) == (1, 8)
+        galois = F.fhelin_plan_galois(plan)
+        keys = _uniform_keys(prm, galois, st.sub(1))
+        n_pt = info["n_pt"]
+        pts = _uniform_pts(prm, n_pt, level, st.sub(2))
+        ct = _uniform_ct(prm, level, st.sub(3))
+        print("inputs ready", flush=True)
+        ks = F.fhelin_keyset_load(ctx, galois, level, dev(keys_at(prm, keys, level)))
+        pset = F.fhelin_pt_import(ctx, dev(pts), level=level)
+        x = dev(pad_cts([ct], level, prm.N))
+        y = dev(np.zeros((8, 2, level, prm.N), np.uint64))
+        flags = F.FHELIN_APPLY_RESCALE | F.FHELIN_APPLY_HOIST_MODDOWN
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            g = F.fhelin_graph_capture_linear(ctx, plan, ks, pset, x, [level], y, [level - 1] * 8, flags,
+                                              stream=stream)
+        F.fhelin_graph_launch(g, stream=stream)
+        stream.synchronize()
+        got = host(y)
+        print("gpu done", flush=True)
+        want = O.linear(prm, ct[None], level, sched, pts.reshape(sched.n_out, sched.n_in, sched.G, sched.B,
+                                                                level + prm.K, prm.N), keys, hoist_moddown=True)
+        for o in range(8):
+            assert np.array_equal(got[o, :, : level - 1], O.rescale(prm, want[o], level)), o
+        F.fhelin_graph_destroy(g)
+        F.fhelin_ptset_release(pset)
+        F.fhelin_keyset_release(ks)
+        F.fhelin_plan_destroy(plan)
+    finally:
+        F.fhelin_ctx_destroy(ctx)
+        torch.cuda.synchronize()
