@@ -371,6 +371,18 @@ int launch_moddown_fbc(const Ctx *c, const Batch &b, const uint64_t *u, int64_t 
 int launch_ks_inner_add(const Ctx *c, const Batch &b, const uint64_t *digits, int64_t digits_es, uint64_t *u,
                         int64_t u_es, const uint64_t *add, int64_t add_es, int add_ext, int accumulate, hipStream_t s,
                         int eg = 8);
+// a list of rotations run by one inner-product launch (see k_ks_inner)
+constexpr int MAX_ROT = 64;
+struct KsRot {
+    int32_t n;               // 0: one rotation per entry from Batch.g / Batch.key
+    uint32_t g[MAX_ROT];     // Galois element of rotation i
+    int32_t key[MAX_ROT];    // its key index in every entry's key set
+    int64_t out[MAX_ROT];    // element offset of its output from the entry's output
+};
+// every rotation of `rot` for every entry of b (b.key[t] = base of the entry's key set)
+int launch_ks_inner_rot(const Ctx *c, const Batch &b, const KsRot &rot, const uint64_t *digits, int64_t digits_es,
+                        uint64_t *u, int64_t u_es, const uint64_t *add, int64_t add_es, int add_ext, hipStream_t s,
+                        int eg);
 // extended ciphertexts [2][L+K]: dst (+)= P * src (lift, src a Q ciphertext [2][src_stride]) or dst (+)= src
 int launch_ext_lift_add(const Ctx *c, const Batch &b, const uint64_t *src, int64_t src_es, int src_stride, int lift,
                         int accumulate, uint64_t *dst, int64_t dst_es, hipStream_t s);

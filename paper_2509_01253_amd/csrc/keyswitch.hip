@@ -109,32 +109,60 @@ struct KsAdd {
 
 // grid (N/256, L + K slots, entry groups of eg): slot s is q_s (entries with s < l)
 // or p_{s-L}; the key rows of slot s are the same for every entry of the group, so a
-// thread loads them once per key and reuses them.
+// thread loads them once per key and reuses them.  With a rotation list (rot.n > 0)
+// one launch runs every listed rotation of every entry: b.key[t] is then the base of
+// the entry's key set, rotation i uses the key at index rot.key[i] of it and writes
+// at element offset rot.out[i] of the entry's output; the entries' digits are
+// gathered once per rotation while they are still in the caches.
+
+// The digit count of an entry (its beta) is a run-time value; the loads of one entry's
+// digits are issued together by dispatching to code compiled for exactly that count
+// (no per-digit branches between the loads).
+template <bool SMALL, int NB, int MAXB>
+__device__ __forceinline__ void ks_dot(int nb, LazyAcc<SMALL> &a0, LazyAcc<SMALL> &a1, const uint64_t *d,
+                                       int64_t dstride, const uint64_t (&kb)[MAXB], const uint64_t (&ka)[MAXB]) {
+    if (nb == NB || NB == MAXB) {
+        uint64_t v[NB];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) v[j] = d[j * dstride];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const uint64_t dv = LazyAcc<SMALL>::prep(v[j]);
+            a0.mac(dv, kb[j]);
+            a1.mac(dv, ka[j]);
+        }
+        return;
+    }
+    if constexpr (NB < MAXB) ks_dot<SMALL, NB + 1, MAXB>(nb, a0, a1, d, dstride, kb, ka);
+}
 
 // MAXB >= dnum bounds the digits (the key rows a thread keeps in registers).
 template <bool SMALL, int MAXB>
 __global__ void __launch_bounds__(256) k_ks_inner(Batch b, const ModConst *__restrict__ mods,
                                                   const ModDownTab *__restrict__ mdt,
                                                   const uint64_t *__restrict__ digits, int64_t digits_es,
-                                                  uint64_t *__restrict__ u, int64_t u_es, KsAdd add, int log_n, int L,
-                                                  int K, int alpha, int eg) {
+                                                  uint64_t *__restrict__ u, int64_t u_es, KsAdd add, KsRot rot,
+                                                  int log_n, int L, int K, int alpha, int eg) {
     const int s = blockIdx.y;
     const int64_t N = (int64_t)1 << log_n;
     const int k = blockIdx.x * 256 + threadIdx.x;
     const ModConst mc = mods[s];
     uint64_t kb[MAXB], ka[MAXB];
+    const int e_end = min(b.n, (int)(blockIdx.z + 1) * eg);
+    const int n_rot = rot.n > 0 ? rot.n : 1;
+    for (int ri = 0; ri < n_rot; ++ri) {
     const uint64_t *cur_key = nullptr;
     int cur_beta = 0;
-    const int e_end = min(b.n, (int)(blockIdx.z + 1) * eg);
-#pragma unroll 2
     for (int t = blockIdx.z * eg; t < e_end; ++t) {
         const int l = b.level[t];
         if (s < L && s >= l) continue;
         const int beta = (l + alpha - 1) / alpha;
-        if (b.key[t] != cur_key || beta > cur_beta) {
+        const int kl = b.key_level[t];
+        const uint64_t *kt = b.key[t];
+        if (rot.n > 0) kt += (int64_t)rot.key[ri] * 2 * ((kl + alpha - 1) / alpha) * (kl + K) * N;
+        if (kt != cur_key || beta > cur_beta) {
             // key rows of slot s: position s (q) or key_level + (s - L) (p) of each digit/part
-            cur_key = b.key[t];
-            const int kl = b.key_level[t];
+            cur_key = kt;
             cur_beta = (kl + alpha - 1) / alpha;
             const int kp = s < L ? s : kl + (s - L);
             const int64_t kpart = (int64_t)(kl + K) * N;
@@ -147,19 +175,12 @@ __global__ void __launch_bounds__(256) k_ks_inner(Batch b, const ModConst *__res
                 }
             }
         }
-        const int src = auto_index(k, b.g[t], log_n);
+        const int src = auto_index(k, rot.n > 0 ? rot.g[ri] : b.g[t], log_n);
         const uint64_t *d = digits + t * digits_es + (int64_t)s * N + src;
         LazyAcc<SMALL> a0, a1;
         a0.zero();
         a1.zero();
-#pragma unroll
-        for (int j = 0; j < MAXB; ++j) {
-            if (j < beta) {
-                const uint64_t dv = LazyAcc<SMALL>::prep(d[(int64_t)j * (L + K) * N]);
-                a0.mac(dv, kb[j]);
-                a1.mac(dv, ka[j]);
-            }
-        }
+        ks_dot<SMALL, 1, MAXB>(beta, a0, a1, d, (int64_t)(L + K) * N, kb, ka);
         uint64_t r0 = a0.reduce(mc.q, mc.mont_neg_inv), r1 = a1.reduce(mc.q, mc.mont_neg_inv);
         if (add.src) {
             if (add.ext) {
@@ -169,7 +190,7 @@ __global__ void __launch_bounds__(256) k_ks_inner(Batch b, const ModConst *__res
                 r0 = add_mod(r0, mont_mul(v, mdt->p_mont[s], mc.q, mc.mont_neg_inv), mc.q);
             }
         }
-        uint64_t *ut = u + t * u_es;
+        uint64_t *ut = u + t * u_es + (rot.n > 0 ? rot.out[ri] : 0);
         uint64_t *o0 = ut + (int64_t)s * N + k, *o1 = ut + ((int64_t)(L + K) + s) * N + k;
         if (add.accumulate) {
             r0 = add_mod(r0, *o0, mc.q);
@@ -178,11 +199,13 @@ __global__ void __launch_bounds__(256) k_ks_inner(Batch b, const ModConst *__res
         *o0 = r0;
         *o1 = r1;
     }
+    }
 }
 
 static int launch_ks_inner_impl(const Ctx *c, const Batch &b, const uint64_t *digits, int64_t digits_es, uint64_t *u,
-                                int64_t u_es, KsAdd add, hipStream_t s, int eg) {
+                                int64_t u_es, KsAdd add, hipStream_t s, int eg, const KsRot &rot) {
     if (b.n == 0) return FHELIN_OK;
+    const int n_rot = rot.n > 0 ? rot.n : 1;
     // work: 2 beta (l + K) N products per entry; bytes: digits beta (l + K) limbs, the
     // addend (l + K limbs extended, l limbs lifted), the accumulated sum read back, two
     // output polynomials, and each distinct key once (2 beta_k (l_k + K) limbs)
@@ -192,23 +215,24 @@ static int launch_ks_inner_impl(const Ctx *c, const Batch &b, const uint64_t *di
     int n_seen = 0;
     for (int t = 0; t < b.n; ++t) {
         const double l = b.level[t], beta = std::ceil(l / c->alpha), e = l + c->K;
-        units += 2.0 * beta * e * c->N;
-        bytes += limb * (beta * e + 2 * e);
+        units += n_rot * 2.0 * beta * e * c->N;
+        // the digits are read once per launch (rotations of one launch re-read them from cache)
+        bytes += limb * (beta * e + n_rot * 2 * e);
         if (add.src) bytes += limb * (add.ext ? e : l);
-        if (add.accumulate) bytes += limb * 2 * e;
+        if (add.accumulate) bytes += n_rot * limb * 2 * e;
         bool dup = false;
         for (int i = 0; i < n_seen; ++i) dup |= seen[i] == b.key[t];
         if (!dup) {
             seen[n_seen++] = b.key[t];
             const double kl = b.key_level[t];
-            bytes += limb * 2 * std::ceil(kl / c->alpha) * (kl + c->K);
+            bytes += n_rot * limb * 2 * std::ceil(kl / c->alpha) * (kl + c->K);
         }
     }
     ProfScope ps(c, s, PK_KS_INNER, units, bytes);
     if (eg < 1) eg = 1;
     dim3 grid(c->N / 256, c->L + c->K, (b.n + eg - 1) / eg);
 #define FL_KS(SM, MB) hipLaunchKernelGGL((k_ks_inner<SM, MB>), grid, dim3(256), 0, s, b, c->d_mods, c->d_moddown, \
-                                         digits, digits_es, u, u_es, add, c->log_n, c->L, c->K, c->alpha, eg)
+                                         digits, digits_es, u, u_es, add, rot, c->log_n, c->L, c->K, c->alpha, eg)
     const int n_digits = (c->L + c->alpha - 1) / c->alpha;  // at most 16 (checked at context creation)
     if (c->small) {
         if (n_digits <= 4) FL_KS(true, 4);
@@ -226,13 +250,20 @@ static int launch_ks_inner_impl(const Ctx *c, const Batch &b, const uint64_t *di
 
 int launch_ks_inner(const Ctx *c, const Batch &b, const uint64_t *digits, int64_t digits_es, uint64_t *u, int64_t u_es,
                     hipStream_t s, int eg) {
-    return launch_ks_inner_impl(c, b, digits, digits_es, u, u_es, KsAdd{nullptr, 0, 0, 0}, s, eg);
+    return launch_ks_inner_impl(c, b, digits, digits_es, u, u_es, KsAdd{nullptr, 0, 0, 0}, s, eg, KsRot{});
 }
 
 int launch_ks_inner_add(const Ctx *c, const Batch &b, const uint64_t *digits, int64_t digits_es, uint64_t *u,
                         int64_t u_es, const uint64_t *add, int64_t add_es, int add_ext, int accumulate, hipStream_t s,
                         int eg) {
-    return launch_ks_inner_impl(c, b, digits, digits_es, u, u_es, KsAdd{add, add_es, add_ext, accumulate}, s, eg);
+    return launch_ks_inner_impl(c, b, digits, digits_es, u, u_es, KsAdd{add, add_es, add_ext, accumulate}, s, eg,
+                                KsRot{});
+}
+
+int launch_ks_inner_rot(const Ctx *c, const Batch &b, const KsRot &rot, const uint64_t *digits, int64_t digits_es,
+                        uint64_t *u, int64_t u_es, const uint64_t *add, int64_t add_es, int add_ext, hipStream_t s,
+                        int eg) {
+    return launch_ks_inner_impl(c, b, digits, digits_es, u, u_es, KsAdd{add, add_es, add_ext, 0}, s, eg, rot);
 }
 
 // ---------------------------------------------------------------------------

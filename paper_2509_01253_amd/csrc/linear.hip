@@ -104,8 +104,10 @@ constexpr int MAC_K = 16;   // coefficients per workgroup
 constexpr int MAC_TB = 16;  // terms per chunk
 constexpr int MAC_ET = 8;   // requests per group at most
 
-// MY = requests per thread (a tile choice); ES thread rows per giant step, ES * MY <= MAC_ET
-template <bool SMALL, int MY>
+// MY = requests per thread (a tile choice); ES thread rows per giant step, ES * MY <= MAC_ET;
+// NC = 16-term chunks of the plaintext column kept in registers (terms <= 16 NC), else
+// NC = 1 and the column is reloaded per chunk
+template <bool SMALL, int MY, int NC>
 __global__ void __launch_bounds__(256) k_mac(MacArgs a, Batch b, const ModConst *__restrict__ mods, int log_n,
                                              int L, int K, int R, int JT, int ES) {
     __shared__ uint64_t Rs[MAC_ET][MAC_TB][2][MAC_K];
@@ -130,23 +132,26 @@ __global__ void __launch_bounds__(256) k_mac(MacArgs a, Batch b, const ModConst 
         n_act = 0;
         while (n_act < R && s < b.level[a.order[n_act] * a.n_out + o]) ++n_act;
     }
-    const bool one_chunk = terms <= MAC_TB;
+    const bool resident = terms <= NC * MAC_TB;
     for (int jc = 0; jc < a.G; jc += JT) {
         const int j = jc + jloc;
-        uint64_t pv[MAC_TB];
-        auto load_pv = [&](int t0) {
+        uint64_t pv[NC][MAC_TB];
+        auto load_pv = [&](uint64_t(&col)[MAC_TB], int t0) {
 #pragma unroll
             for (int tt = 0; tt < MAC_TB; ++tt) {
                 const int t = t0 + tt;
-                pv[tt] = 0;
+                col[tt] = 0;
                 if (t < terms && j < a.G) {
                     const int ii = t / a.B, bb = t % a.B;
                     const int64_t pidx = ((int64_t)(o * a.n_in + ii) * a.G + j) * a.B + bb;
-                    pv[tt] = LazyAcc<SMALL>::prep(a.pts[(pidx * prows + prow) * N + k0 + kl]);
+                    col[tt] = LazyAcc<SMALL>::prep(a.pts[(pidx * prows + prow) * N + k0 + kl]);
                 }
             }
         };
-        if (one_chunk) load_pv(0);
+        if (resident) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) load_pv(pv[c], c * MAC_TB);
+        }
         for (int g0 = 0; g0 < n_act; g0 += ET) {
             LazyAcc<SMALL> acc[MY][2];
 #pragma unroll
@@ -155,7 +160,7 @@ __global__ void __launch_bounds__(256) k_mac(MacArgs a, Batch b, const ModConst 
                 acc[m][1].zero();
             }
             for (int t0 = 0; t0 < terms; t0 += MAC_TB) {
-                if (!one_chunk) load_pv(t0);
+                if (!resident) load_pv(pv[0], t0);
                 __syncthreads();  // readers of the previous tile are done
                 for (int v = threadIdx.x; v < ET * MAC_TB * 2 * MAC_K; v += 256) {
                     const int kk = v % MAC_K, p = (v / MAC_K) % 2, tt = (v / (2 * MAC_K)) % MAC_TB,
@@ -172,14 +177,22 @@ __global__ void __launch_bounds__(256) k_mac(MacArgs a, Batch b, const ModConst 
                     Rs[rr][tt][p][kk] = xv;
                 }
                 __syncthreads();
+                auto compute = [&](const uint64_t(&col)[MAC_TB]) {
 #pragma unroll
-                for (int tt = 0; tt < MAC_TB; ++tt) {
+                    for (int tt = 0; tt < MAC_TB; ++tt) {
 #pragma unroll
-                    for (int m = 0; m < MY; ++m) {
-                        const int rr = esc + m * ES;
-                        acc[m][0].mac(Rs[rr][tt][0][kl], pv[tt]);
-                        acc[m][1].mac(Rs[rr][tt][1][kl], pv[tt]);
+                        for (int m = 0; m < MY; ++m) {
+                            const int rr = esc + m * ES;
+                            acc[m][0].mac(Rs[rr][tt][0][kl], col[tt]);
+                            acc[m][1].mac(Rs[rr][tt][1][kl], col[tt]);
+                        }
                     }
+                };
+                if constexpr (NC > 1) {
+                    if (resident && t0 >= MAC_TB) compute(pv[1]);
+                    else compute(pv[0]);
+                } else {
+                    compute(pv[0]);
                 }
 #pragma unroll
                 for (int m = 0; m < MY; ++m)
@@ -230,17 +243,22 @@ static int launch_mac(const Ctx *c, const Plan *p, MacArgs &ma, const Batch &bou
     const int slots = ma.ext ? c->L + c->K : lmax;
     ProfScope ps(c, s, PK_MAC, macs, bytes);
     dim3 grid(c->N / MAC_K, slots, p->n_out);
-#define FL_MAC(SM, Y) hipLaunchKernelGGL((k_mac<SM, Y>), grid, dim3(256), 0, s, ma, bout, c->d_mods, c->log_n, c->L, \
-                                         c->K, R, JT, ES)
+    const int terms = p->n_in * ma.B, NC = terms > MAC_TB && terms <= 2 * MAC_TB ? 2 : 1;
+#define FL_MAC(SM, Y, C) hipLaunchKernelGGL((k_mac<SM, Y, C>), grid, dim3(256), 0, s, ma, bout, c->d_mods, c->log_n, \
+                                            c->L, c->K, R, JT, ES)
+#define FL_MAC_NC(SM, Y) \
+    if (NC == 2) FL_MAC(SM, Y, 2); \
+    else FL_MAC(SM, Y, 1)
     if (c->small) {
-        if (MY == 2) FL_MAC(true, 2);
-        else if (MY == 4) FL_MAC(true, 4);
-        else FL_MAC(true, 8);
+        if (MY == 2) FL_MAC_NC(true, 2);
+        else if (MY == 4) FL_MAC_NC(true, 4);
+        else FL_MAC_NC(true, 8);
     } else {
-        if (MY == 2) FL_MAC(false, 2);
-        else if (MY == 4) FL_MAC(false, 4);
-        else FL_MAC(false, 8);
+        if (MY == 2) FL_MAC_NC(false, 2);
+        else if (MY == 4) FL_MAC_NC(false, 4);
+        else FL_MAC_NC(false, 8);
     }
+#undef FL_MAC_NC
 #undef FL_MAC
     FL_TRY_HIP(hipGetLastError());
     return FHELIN_OK;
@@ -462,11 +480,34 @@ static int apply_chunk_dh(Ctx *c, const Plan *p, const KeySet *const *kss, const
     if (Bp > 0) {
         KsScratch wb{TC, L * N, D, dg, nullptr, 0, MD, ct};
         FL_RET(modup_ct(c, bin, X, ct, (int)L, wb, s));
+        // one launch for every baby rotation when all key sets of the chunk hold the
+        // rotations' keys at the same indices (always, for one client)
+        KsRot rot{};
+        bool same = true;
         for (int b = 0; b < B; ++b) {
             if (ma.bmap[b] < 0) continue;
-            set_keys(bin, p->n_in, kss + r0, galois_of_rotation(p->rb[b], c->log_n));
-            FL_RET(launch_ks_inner_add(c, bin, D, dg, RB + ma.bmap[b] * ext, (int64_t)Bp * ext, X, ct, 0, 0, s,
-                                       p->tune.ks_eg));
+            const uint32_t g = galois_of_rotation(p->rb[b], c->log_n);
+            const int idx = kss[r0]->find(g);
+            for (int r = 1; r < Rc; ++r) same = same && kss[r0 + r]->find(g) == idx;
+            rot.g[rot.n] = g;
+            rot.key[rot.n] = idx;
+            rot.out[rot.n] = (int64_t)ma.bmap[b] * ext;
+            ++rot.n;
+        }
+        if (same) {
+            for (int e = 0; e < Ein; ++e) {
+                const KeySet *ks = kss[r0 + e / p->n_in];
+                bin.key[e] = ks->evk;
+                bin.key_level[e] = (uint8_t)ks->level;
+            }
+            FL_RET(launch_ks_inner_rot(c, bin, rot, D, dg, RB, (int64_t)Bp * ext, X, ct, 0, s, p->tune.ks_eg));
+        } else {
+            for (int b = 0; b < B; ++b) {
+                if (ma.bmap[b] < 0) continue;
+                set_keys(bin, p->n_in, kss + r0, galois_of_rotation(p->rb[b], c->log_n));
+                FL_RET(launch_ks_inner_add(c, bin, D, dg, RB + ma.bmap[b] * ext, (int64_t)Bp * ext, X, ct, 0, 0, s,
+                                           p->tune.ks_eg));
+            }
         }
         for (int e = 0; e < Ein; ++e) bin.g[e] = 1;
     }

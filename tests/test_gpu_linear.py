@@ -371,3 +371,104 @@ def test_tunes_bit_identical_and_autotune(F, dh):
             assert np.array_equal(got[t, :, : l - 1], want[t]), t
     finally:
         lay.close()
+
+
+# ---------------------------------------------------------------------------
+# requests of several clients in one call
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("dh,extra", [(False, True), (True, False), (True, True)])
+def test_multi_client_batch(F, dh, extra):
+    """Requests of three clients with their own secret and Galois keys share one call
+    (fhelin_linear_apply_multi): every output equals the oracle evaluated with that
+    client's keys and decrypts under that client's secret.  With `extra` one client's
+    key set holds an additional key, so its keys sit at other indices than the
+    others' (the double-hoisted schedule then runs the baby rotations one launch each
+    instead of all in one)."""
+    print(f"multi-client dh={dh} extra={extra}", flush=True)
+    prm = O.make_params(12, 5, 2, 3, 50, 2.0 ** 40)
+    st = synth.Stream(4800 + dh)
+    n, n1 = 64, 8
+    W = st.he_normal((n, n), n)
+    sched = O.fc_schedule(n, n1)
+    pts = encode_pts(prm, O.fc_slots(W, n, n1, prm.S), prm.L, prm.scale)
+    clients = [Client(prm, 4810 + i) for i in range(3)]
+    rots = sched.rotations()
+    keysets = [cl.keyset(rots) for cl in clients[:2]] + [clients[2].keyset(list(rots) + ([10] if extra else []))]
+    assert len(keysets[2].galois) == len(keysets[0].galois) + int(extra)
+    owner = [0, 1, 2, 0, 2, 1, 2]
+    levels = [5, 3, 4, 2, 5, 4, 3]
+    xs = [st.uniform(n, 0, 1) for _ in owner]
+    cts = [clients[o].encrypt_slots(O.fc_input_slots(x, n, prm.S), l, prm.scale) for o, x, l in zip(owner, xs, levels)]
+    ctx = ctx_for(F, prm)
+    try:
+        plan = F.fhelin_plan_create(ctx, F.FHELIN_LAYER_FC, fc_n=n, fc_out=n, fc_in=n, n1=n1)
+        handles = [F.fhelin_keyset_load(ctx, ks.galois, prm.L, dev(keys_at(prm, ks, prm.L))) for ks in keysets]
+        pset = F.fhelin_pt_import(ctx, dev(pts.reshape(-1, prm.L + prm.K, prm.N)), level=prm.L)
+        x = dev(pad_cts(cts, prm.L, prm.N))
+        y = dev(np.zeros((len(cts), 2, prm.L, prm.N), np.uint64))
+        flags = F.FHELIN_APPLY_RESCALE | (F.FHELIN_APPLY_HOIST_MODDOWN if dh else 0)
+        F.fhelin_linear_apply_multi(ctx, plan, [handles[o] for o in owner], pset, x, levels, y,
+                                    [l - 1 for l in levels], flags)
+        got = host(y)
+        for t, (o, l) in enumerate(zip(owner, levels)):
+            want = O.rescale(prm, O.linear(prm, cts[t][None], l, sched, pts, keysets[o], hoist_moddown=dh)[0], l)
+            assert np.array_equal(got[t, :, : l - 1], want), t
+            z = clients[o].decrypt_slots(got[t, :, : l - 1], l - 1, prm.scale ** 2 / prm.q[l - 1]).real
+            assert _rel(z[:n], W @ xs[t]) < 1e-3, t
+        F.fhelin_ptset_release(pset)
+        for h in handles:
+            F.fhelin_keyset_release(h)
+        F.fhelin_plan_destroy(plan)
+    finally:
+        F.fhelin_ctx_destroy(ctx)
+
+
+def test_errors_reported(F):
+    """Invalid calls are rejected on the host with their status before any kernel
+    runs: a key set missing a Galois element, keys loaded below the request level,
+    plaintexts encoded below it, rescale at level 1, mismatched output counts or
+    levels, and an out-of-range tune."""
+    print("error paths", flush=True)
+    prm = O.make_params(12, 4, 2, 2, 50, 2.0 ** 40)
+    st = synth.Stream(4900)
+    n, n1 = 32, 8
+    sched = O.fc_schedule(n, n1)
+    pts = encode_pts(prm, O.fc_slots(st.he_normal((n, n), n), n, n1, prm.S), 3, prm.scale)
+    cl = Client(prm, 4901)
+    keys = cl.keyset(sched.rotations())
+    partial = O.KeySet(keys.galois[:-1], keys.evk[:-1])
+    ctx = ctx_for(F, prm)
+    try:
+        plan = F.fhelin_plan_create(ctx, F.FHELIN_LAYER_FC, fc_n=n, fc_out=n, fc_in=n, n1=n1)
+        ks_full = F.fhelin_keyset_load(ctx, keys.galois, prm.L, dev(keys_at(prm, keys, prm.L)))
+        ks_low = F.fhelin_keyset_load(ctx, keys.galois, 2, dev(keys_at(prm, keys, 2)))
+        ks_part = F.fhelin_keyset_load(ctx, partial.galois, prm.L, dev(keys_at(prm, partial, prm.L)))
+        pset = F.fhelin_pt_import(ctx, dev(pts.reshape(-1, 3 + prm.K, prm.N)), level=3)
+        ct = lambda l: dev(pad_cts([cl.encrypt_slots(O.fc_input_slots(st.uniform(n, 0, 1), n, prm.S), l,
+                                                     prm.scale)], prm.L, prm.N))
+        y = dev(np.zeros((1, 2, prm.L, prm.N), np.uint64))
+        R = F.FHELIN_APPLY_RESCALE
+
+        def status(fn):
+            with pytest.raises(F.FhelinError) as ei:
+                fn()
+            return ei.value.status
+
+        assert status(lambda: F.fhelin_linear_apply(ctx, plan, ks_part, pset, ct(3), [3], y, [2], R)) == -4
+        assert status(lambda: F.fhelin_linear_apply(ctx, plan, None, pset, ct(3), [3], y, [2], R)) == -4
+        assert status(lambda: F.fhelin_linear_apply(ctx, plan, ks_low, pset, ct(3), [3], y, [2], R)) == -3
+        assert status(lambda: F.fhelin_linear_apply(ctx, plan, ks_full, pset, ct(4), [4], y, [3], R)) == -3
+        assert status(lambda: F.fhelin_linear_apply(ctx, plan, ks_full, pset, ct(1), [1], y, [0], R)) == -3
+        assert status(lambda: F.fhelin_linear_apply(ctx, plan, ks_full, pset, ct(3), [3], y, [3], R)) == -3
+        y2 = dev(np.zeros((2, 2, prm.L, prm.N), np.uint64))
+        assert status(lambda: F.fhelin_linear_apply(ctx, plan, ks_full, pset, ct(3), [3], y2, [2, 2], R)) == -1
+        assert status(lambda: F.fhelin_plan_set_tune(plan, chunk=0, ks_eg=0, mac_my=2)) == -1
+        # a valid call still works afterwards
+        F.fhelin_linear_apply(ctx, plan, ks_full, pset, ct(3), [3], y, [2], R)
+        host(y)
+        for h in (ks_full, ks_low, ks_part):
+            F.fhelin_keyset_release(h)
+        F.fhelin_ptset_release(pset)
+        F.fhelin_plan_destroy(plan)
+    finally:
+        F.fhelin_ctx_destroy(ctx)
