@@ -104,12 +104,15 @@ constexpr int MAC_K = 16;   // coefficients per workgroup
 constexpr int MAC_TB = 16;  // terms per chunk
 constexpr int MAC_ET = 8;   // requests per group at most
 
-// MY = requests per thread (a tile choice); ES thread rows per giant step, ES * MY <= MAC_ET;
-// NC = 16-term chunks of the plaintext column kept in registers (terms <= 16 NC), else
-// NC = 1 and the column is reloaded per chunk
-template <bool SMALL, int MY, int NC>
+// MY = requests per thread (a tile choice); ET = requests per group (2, 4 or 8), so
+// ES = ET / MY thread rows share a giant step; NC = 16-term chunks of the plaintext
+// column kept in registers (terms <= 16 NC), else NC = 1 and the column is reloaded
+// per chunk
+template <bool SMALL, int MY, int NC, int ET>
 __global__ void __launch_bounds__(256) k_mac(MacArgs a, Batch b, const ModConst *__restrict__ mods, int log_n,
-                                             int L, int K, int R, int JT, int ES) {
+                                             int L, int K, int R, int JT) {
+    static_assert(ET % MY == 0 && ET <= 8, "bad request group");
+    constexpr int ES = ET / MY;
     __shared__ uint64_t Rs[MAC_ET][MAC_TB][2][MAC_K];
     const int s = blockIdx.y;  // slot = modulus index (q_s for s < L, p_{s-L} otherwise)
     // a q slot above the plaintexts' level is active for no request (levels <= pt_level)
@@ -120,7 +123,6 @@ __global__ void __launch_bounds__(256) k_mac(MacArgs a, Batch b, const ModConst 
     const int jloc = jj % JT, es = jj / JT;
     const bool computes = es < ES;  // other thread rows only help staging
     const int esc = computes ? es : 0;
-    const int ET = MY * ES;
     const int ls = a.ext ? L + K : L;
     const int64_t ct = (int64_t)2 * ls * N;
     const int terms = a.n_in * a.B;
@@ -133,6 +135,32 @@ __global__ void __launch_bounds__(256) k_mac(MacArgs a, Batch b, const ModConst 
         while (n_act < R && s < b.level[a.order[n_act] * a.n_out + o]) ++n_act;
     }
     const bool resident = terms <= NC * MAC_TB;
+    // the request tile of a (group, chunk): thread holds values i < 2 ET, value i at
+    // request row i / 2, term row tid / 32 + 8 (i & 1), polynomial (tid / 16) & 1,
+    // coefficient tid & 15; the next tile's values are loaded before the current
+    // tile's multiply-accumulate so their latency overlaps it
+    const int kk = threadIdx.x & 15, pp = (threadIdx.x >> 4) & 1, tr = threadIdx.x >> 5;
+    uint64_t pre[2 * ET];
+    auto fetch = [&](int g0, int t0) {
+#pragma unroll
+        for (int i = 0; i < 2 * ET; ++i) {
+            const int rr = i >> 1, t = t0 + tr + 8 * (i & 1), r = g0 + rr;
+            uint64_t xv = 0;
+            if (t < terms && r < n_act) {
+                const int ii = t / a.B, bb = t % a.B;
+                const int64_t xin = (int64_t)a.order[r] * a.n_in + ii;
+                const int m = a.bmap[bb];
+                const uint64_t *src = m < 0 ? a.x + xin * ct : a.rb + (xin * a.Bp + m) * ct;
+                xv = src[((int64_t)pp * ls + s) * N + k0 + kk];
+            }
+            pre[i] = xv;
+        }
+    };
+    auto stash = [&]() {
+#pragma unroll
+        for (int i = 0; i < 2 * ET; ++i) Rs[i >> 1][tr + 8 * (i & 1)][pp][kk] = LazyAcc<SMALL>::prep(pre[i]);
+    };
+    if (n_act > 0) fetch(0, 0);
     for (int jc = 0; jc < a.G; jc += JT) {
         const int j = jc + jloc;
         uint64_t pv[NC][MAC_TB];
@@ -162,21 +190,12 @@ __global__ void __launch_bounds__(256) k_mac(MacArgs a, Batch b, const ModConst 
             for (int t0 = 0; t0 < terms; t0 += MAC_TB) {
                 if (!resident) load_pv(pv[0], t0);
                 __syncthreads();  // readers of the previous tile are done
-                for (int v = threadIdx.x; v < ET * MAC_TB * 2 * MAC_K; v += 256) {
-                    const int kk = v % MAC_K, p = (v / MAC_K) % 2, tt = (v / (2 * MAC_K)) % MAC_TB,
-                              rr = v / (2 * MAC_K * MAC_TB);
-                    const int t = t0 + tt, r = g0 + rr;
-                    uint64_t xv = 0;
-                    if (t < terms && r < n_act) {
-                        const int ii = t / a.B, bb = t % a.B;
-                        const int64_t xin = (int64_t)a.order[r] * a.n_in + ii;
-                        const int m = a.bmap[bb];
-                        const uint64_t *src = m < 0 ? a.x + xin * ct : a.rb + (xin * a.Bp + m) * ct;
-                        xv = LazyAcc<SMALL>::prep(src[((int64_t)p * ls + s) * N + k0 + kk]);
-                    }
-                    Rs[rr][tt][p][kk] = xv;
-                }
+                stash();
                 __syncthreads();
+                // prefetch the next tile: next chunk, next group, or the first of the next giant-step chunk
+                if (t0 + MAC_TB < terms) fetch(g0, t0 + MAC_TB);
+                else if (g0 + ET < n_act) fetch(g0 + ET, 0);
+                else if (jc + JT < a.G) fetch(0, 0);
                 auto compute = [&](const uint64_t(&col)[MAC_TB]) {
 #pragma unroll
                     for (int tt = 0; tt < MAC_TB; ++tt) {
@@ -237,28 +256,31 @@ static int launch_mac(const Ctx *c, const Plan *p, MacArgs &ma, const Batch &bou
     std::stable_sort(idx, idx + R, [&](int x, int y) { return bout.level[x * p->n_out] > bout.level[y * p->n_out]; });
     for (int r = 0; r < R; ++r) ma.order[r] = (uint8_t)idx[r];
     const int JT = std::min(ma.G, 16);
-    int MY = p->tune.mac_my;
-    while (MY > 2 && MY > MAC_ET) MY /= 2;
-    const int ES = std::max(1, std::min(16 / JT, MAC_ET / MY));
+    const int MY = p->tune.mac_my;
+    // requests per group: MY times the thread rows per giant step (at most 16 / JT), a power of two <= 8
+    int ET = MY;
+    while (ET * 2 <= MAC_ET && (ET * 2) / MY <= 16 / JT) ET *= 2;
     const int slots = ma.ext ? c->L + c->K : lmax;
     ProfScope ps(c, s, PK_MAC, macs, bytes);
     dim3 grid(c->N / MAC_K, slots, p->n_out);
     const int terms = p->n_in * ma.B, NC = terms > MAC_TB && terms <= 2 * MAC_TB ? 2 : 1;
-#define FL_MAC(SM, Y, C) hipLaunchKernelGGL((k_mac<SM, Y, C>), grid, dim3(256), 0, s, ma, bout, c->d_mods, c->log_n, \
-                                            c->L, c->K, R, JT, ES)
-#define FL_MAC_NC(SM, Y) \
-    if (NC == 2) FL_MAC(SM, Y, 2); \
-    else FL_MAC(SM, Y, 1)
+#define FL_MAC(SM, Y, C, E) hipLaunchKernelGGL((k_mac<SM, Y, C, E>), grid, dim3(256), 0, s, ma, bout, c->d_mods, \
+                                               c->log_n, c->L, c->K, R, JT)
+#define FL_MAC_E(SM, Y, C) \
+    if (ET == 2) FL_MAC(SM, 2, C, 2); \
+    else if (ET == 4 && Y <= 4) FL_MAC(SM, (Y <= 4 ? Y : 4), C, 4); \
+    else FL_MAC(SM, Y, C, 8)
+#define FL_MAC_Y(SM, C) \
+    if (MY == 2) { FL_MAC_E(SM, 2, C); } \
+    else if (MY == 4) { FL_MAC_E(SM, 4, C); } \
+    else { FL_MAC(SM, 8, C, 8); }
     if (c->small) {
-        if (MY == 2) FL_MAC_NC(true, 2);
-        else if (MY == 4) FL_MAC_NC(true, 4);
-        else FL_MAC_NC(true, 8);
+        if (NC == 2) { FL_MAC_Y(true, 2) } else { FL_MAC_Y(true, 1) }
     } else {
-        if (MY == 2) FL_MAC_NC(false, 2);
-        else if (MY == 4) FL_MAC_NC(false, 4);
-        else FL_MAC_NC(false, 8);
+        if (NC == 2) { FL_MAC_Y(false, 2) } else { FL_MAC_Y(false, 1) }
     }
-#undef FL_MAC_NC
+#undef FL_MAC_Y
+#undef FL_MAC_E
 #undef FL_MAC
     FL_TRY_HIP(hipGetLastError());
     return FHELIN_OK;

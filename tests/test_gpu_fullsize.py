@@ -34,19 +34,19 @@ def _uniform_ct(prm, level, st):
 
 
 def test_fc256_batch64_full_size():
-    """Batched FC 256x256 (n1 = 16): 64 requests at levels 4..12 in one call; the two
-    lowest-level requests bit-exact against the oracle, four others equal to the same
-    request evaluated alone."""
+    """Batched FC 256x256 with the benchmark's split (n1 = 32): 64 requests at levels
+    4..12 in one call; the two lowest-level requests bit-exact against the oracle,
+    four others equal to the same request evaluated alone."""
     import torch
 
     from paper_2509_01253_amd import fhelin as F
     print("full size: FC 256x256, batch 64, N=2^16", flush=True)
     prm = _params()
     st = synth.Stream(synth.master_seed(3)).sub(1001)
-    sched = O.fc_schedule(256, 16)
+    sched = O.fc_schedule(256, 32)
     ctx = F.fhelin_ctx_create(prm.log_n, prm.q, prm.p, prm.dnum)
     try:
-        plan = F.fhelin_plan_create(ctx, F.FHELIN_LAYER_FC, fc_n=256, fc_out=256, fc_in=256, n1=16)
+        plan = F.fhelin_plan_create(ctx, F.FHELIN_LAYER_FC, fc_n=256, fc_out=256, fc_in=256, n1=32)
         galois = F.fhelin_plan_galois(plan)
         assert galois == sorted({O.galois_of(r, prm.log_n) for r in sched.rotations()} - {1})
         keys = _uniform_keys(prm, galois, st.sub(1))
