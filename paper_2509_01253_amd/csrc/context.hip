@@ -312,6 +312,7 @@ int ctx_create(const fhelin_params *prm, Ctx **out) {
         }
     }
     FL_RET(upload(c.get(), &c->d_slot_idx, si));
+    FL_RET(upload(c.get(), &c->d_zero, std::vector<uint64_t>(32, 0)));
 
     *out = c.release();
     return FHELIN_OK;
@@ -399,6 +400,7 @@ Ctx::~Ctx() {
     (void)hipFree(d_fft_tw);
     (void)hipFree(d_zeta);
     (void)hipFree(d_slot_idx);
+    (void)hipFree(d_zero);
 }
 
 void ctx_destroy(Ctx *c) { delete c; }

@@ -123,6 +123,7 @@ struct Ctx {
     double *d_fft_tw = nullptr;                    // encode FFT twiddles exp(-2 pi i k/N): [N/2] (re, im)
     double *d_zeta = nullptr;                      // exp(i pi k / N), k < N: [N] (re, im)
     int32_t *d_slot_idx = nullptr;                 // (5^j mod 2N - 1) / 2, j < N/2
+    uint64_t *d_zero = nullptr;                    // 256 zero bytes (padding source of tile loads)
     // memory accounting
     uint64_t budget = 0;
     uint64_t used = 0;
@@ -161,7 +162,7 @@ struct RowMap {
     int32_t L, K, alpha;
     int32_t n_list;
     int32_t log_n;
-    uint8_t level[MAX_BATCH];
+    int32_t level[MAX_BATCH];  // 32-bit: a uniform index then reads it with a scalar load
 };
 
 // Number of rows of batch entry t.
@@ -251,8 +252,10 @@ inline int rowmap_max_rows(const RowMap &m) {
 // per-entry metadata of a batched key-switch / combine launch
 struct Batch {
     int32_t n;
-    uint8_t level[MAX_BATCH];
-    uint8_t key_level[MAX_BATCH];  // level the entry's key set was loaded at
+    // 32-bit entries: a byte read at a run-time index is a vector load, which waits
+    // for every store and load the wave still has in flight
+    int32_t level[MAX_BATCH];
+    int32_t key_level[MAX_BATCH];  // level the entry's key set was loaded at
     uint32_t g[MAX_BATCH];         // Galois element (1 = none)
     const uint64_t *key[MAX_BATCH];// the entry's evaluation key for g (digit 0, part 0, row 0)
 };

@@ -118,22 +118,25 @@ struct KsAdd {
 // The digit count of an entry (its beta) is a run-time value; the loads of one entry's
 // digits are issued together by dispatching to code compiled for exactly that count
 // (no per-digit branches between the loads).
-template <bool SMALL, int NB, int MAXB>
+// sum_j d_j kb_j and sum_j d_j ka_j over the nb digits: every digit load is issued
+// before the first product
+template <bool SMALL, int MAXB>
 __device__ __forceinline__ void ks_dot(int nb, LazyAcc<SMALL> &a0, LazyAcc<SMALL> &a1, const uint64_t *d,
                                        int64_t dstride, const uint64_t (&kb)[MAXB], const uint64_t (&ka)[MAXB]) {
-    if (nb == NB || NB == MAXB) {
-        uint64_t v[NB];
+    uint64_t v[MAXB];
 #pragma unroll
-        for (int j = 0; j < NB; ++j) v[j] = d[j * dstride];
+    for (int j = 0; j < MAXB; ++j) {
+        v[j] = 0;
+        if (j < nb) v[j] = d[j * dstride];
+    }
 #pragma unroll
-        for (int j = 0; j < NB; ++j) {
+    for (int j = 0; j < MAXB; ++j) {
+        if (j < nb) {
             const uint64_t dv = LazyAcc<SMALL>::prep(v[j]);
             a0.mac(dv, kb[j]);
             a1.mac(dv, ka[j]);
         }
-        return;
     }
-    if constexpr (NB < MAXB) ks_dot<SMALL, NB + 1, MAXB>(nb, a0, a1, d, dstride, kb, ka);
 }
 
 // MAXB >= dnum bounds the digits (the key rows a thread keeps in registers).
@@ -167,34 +170,45 @@ __global__ void __launch_bounds__(256) k_ks_inner(Batch b, const ModConst *__res
             const int kp = s < L ? s : kl + (s - L);
             const int64_t kpart = (int64_t)(kl + K) * N;
             const uint64_t *key = cur_key + (int64_t)kp * N + k;
+            // rows past the key's digits repeat its last one (never used), so every
+            // load is unconditional and the loads go out together
 #pragma unroll
             for (int j = 0; j < MAXB; ++j) {
-                if (j < cur_beta) {
-                    kb[j] = LazyAcc<SMALL>::prep(key[(2 * j) * kpart]);
-                    ka[j] = LazyAcc<SMALL>::prep(key[(2 * j + 1) * kpart]);
-                }
+                const int jr = j < cur_beta ? j : cur_beta - 1;
+                kb[j] = key[(2 * jr) * kpart];
+                ka[j] = key[(2 * jr + 1) * kpart];
+            }
+#pragma unroll
+            for (int j = 0; j < MAXB; ++j) {
+                kb[j] = LazyAcc<SMALL>::prep(kb[j]);
+                ka[j] = LazyAcc<SMALL>::prep(ka[j]);
             }
         }
         const int src = auto_index(k, rot.n > 0 ? rot.g[ri] : b.g[t], log_n);
         const uint64_t *d = digits + t * digits_es + (int64_t)s * N + src;
+        uint64_t *ut = u + t * u_es + (rot.n > 0 ? rot.out[ri] : 0);
+        uint64_t *o0 = ut + (int64_t)s * N + k, *o1 = ut + ((int64_t)(L + K) + s) * N + k;
+        // the addend and the running sum are read before the products so that their
+        // loads are in flight together with the digits'
+        const bool has_add = add.src && (add.ext || s < L);
+        uint64_t addv = 0, prev0 = 0, prev1 = 0;
+        if (has_add) addv = add.src[t * add.es + (int64_t)s * N + src];
+        if (add.accumulate) {
+            prev0 = *o0;
+            prev1 = *o1;
+        }
         LazyAcc<SMALL> a0, a1;
         a0.zero();
         a1.zero();
-        ks_dot<SMALL, 1, MAXB>(beta, a0, a1, d, (int64_t)(L + K) * N, kb, ka);
+        ks_dot<SMALL, MAXB>(beta, a0, a1, d, (int64_t)(L + K) * N, kb, ka);
         uint64_t r0 = a0.reduce(mc.q, mc.mont_neg_inv), r1 = a1.reduce(mc.q, mc.mont_neg_inv);
-        if (add.src) {
-            if (add.ext) {
-                r0 = add_mod(r0, add.src[t * add.es + (int64_t)s * N + src], mc.q);
-            } else if (s < L) {
-                uint64_t v = add.src[t * add.es + (int64_t)s * N + src];
-                r0 = add_mod(r0, mont_mul(v, mdt->p_mont[s], mc.q, mc.mont_neg_inv), mc.q);
-            }
+        if (has_add) {
+            if (add.ext) r0 = add_mod(r0, addv, mc.q);
+            else r0 = add_mod(r0, mont_mul(addv, mdt->p_mont[s], mc.q, mc.mont_neg_inv), mc.q);
         }
-        uint64_t *ut = u + t * u_es + (rot.n > 0 ? rot.out[ri] : 0);
-        uint64_t *o0 = ut + (int64_t)s * N + k, *o1 = ut + ((int64_t)(L + K) + s) * N + k;
         if (add.accumulate) {
-            r0 = add_mod(r0, *o0, mc.q);
-            r1 = add_mod(r1, *o1, mc.q);
+            r0 = add_mod(r0, prev0, mc.q);
+            r1 = add_mod(r1, prev1, mc.q);
         }
         *o0 = r0;
         *o1 = r1;

@@ -85,7 +85,9 @@ struct MacArgs {
     int n_in, n_out, B, Bp, G, pt_level;
     int ext;              // 0: Q limbs, ls = L; 1: extended basis, ls = L + K
     int8_t bmap[MAX_BABY];  // baby index -> slot in rb, -1 = identity (use x)
-    uint8_t order[MAX_BATCH];  // requests by descending level (a slot's active requests: a prefix)
+    int32_t order[MAX_BATCH];  // requests by descending level (a slot's active requests: a prefix)
+    const uint64_t *zero;      // a zero word: the source of padding loads
+    uint32_t b_magic;          // ceil(2^20 / B): t / B = (t b_magic) >> 20 for t < 4096
 };
 
 // For one limb (slot s) and coefficient k the multiply-accumulate is a small matrix
@@ -134,26 +136,43 @@ __global__ void __launch_bounds__(256) k_mac(MacArgs a, Batch b, const ModConst 
         n_act = 0;
         while (n_act < R && s < b.level[a.order[n_act] * a.n_out + o]) ++n_act;
     }
-    const bool resident = terms <= NC * MAC_TB;
+    // NC = 2 is launched only for terms <= 32
+    const bool resident = NC > 1 || terms <= MAC_TB;
     // the request tile of a (group, chunk): thread holds values i < 2 ET, value i at
     // request row i / 2, term row tid / 32 + 8 (i & 1), polynomial (tid / 16) & 1,
     // coefficient tid & 15; the next tile's values are loaded before the current
     // tile's multiply-accumulate so their latency overlaps it
+    // every load address below comes from registers and LDS only: an address read
+    // from memory would make each load wait for all loads issued before it
+    __shared__ int8_t bmap[MAX_BABY];
+    __shared__ int32_t order[MAX_BATCH];
+    if (threadIdx.x < MAX_BABY) bmap[threadIdx.x] = a.bmap[threadIdx.x];
+    if (threadIdx.x < MAX_BATCH) order[threadIdx.x] = a.order[threadIdx.x];
+    __syncthreads();
     const int kk = threadIdx.x & 15, pp = (threadIdx.x >> 4) & 1, tr = threadIdx.x >> 5;
+    const int64_t lane_off = ((int64_t)pp * ls + s) * N + k0 + kk;
     uint64_t pre[2 * ET];
     auto fetch = [&](int g0, int t0) {
+        // the thread's two terms of the chunk: source row of request order 0 and the
+        // stride between request entries
+        const uint64_t *tb[2];
+        int64_t tstride[2];
+        bool tv[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int t = t0 + tr + 8 * h;
+            tv[h] = t < terms;
+            const int ii = (int)(((uint32_t)t * a.b_magic) >> 20), bb = t - ii * a.B;
+            const int m = tv[h] ? bmap[bb] : -1;
+            tb[h] = (m < 0 ? a.x + (int64_t)ii * ct : a.rb + ((int64_t)ii * a.Bp + m) * ct) + lane_off;
+            tstride[h] = (m < 0 ? (int64_t)a.n_in : (int64_t)a.n_in * a.Bp) * ct;
+        }
 #pragma unroll
         for (int i = 0; i < 2 * ET; ++i) {
-            const int rr = i >> 1, t = t0 + tr + 8 * (i & 1), r = g0 + rr;
-            uint64_t xv = 0;
-            if (t < terms && r < n_act) {
-                const int ii = t / a.B, bb = t % a.B;
-                const int64_t xin = (int64_t)a.order[r] * a.n_in + ii;
-                const int m = a.bmap[bb];
-                const uint64_t *src = m < 0 ? a.x + xin * ct : a.rb + (xin * a.Bp + m) * ct;
-                xv = src[((int64_t)pp * ls + s) * N + k0 + kk];
-            }
-            pre[i] = xv;
+            const int h = i & 1, r = g0 + (i >> 1);
+            const bool live = tv[h] && r < n_act;
+            const uint64_t *src = live ? tb[h] + a.order[r < n_act ? r : 0] * tstride[h] : a.zero;
+            pre[i] = *src;
         }
     };
     auto stash = [&]() {
@@ -168,13 +187,16 @@ __global__ void __launch_bounds__(256) k_mac(MacArgs a, Batch b, const ModConst 
 #pragma unroll
             for (int tt = 0; tt < MAC_TB; ++tt) {
                 const int t = t0 + tt;
-                col[tt] = 0;
+                const uint64_t *src = a.zero;
                 if (t < terms && j < a.G) {
                     const int ii = t / a.B, bb = t % a.B;
                     const int64_t pidx = ((int64_t)(o * a.n_in + ii) * a.G + j) * a.B + bb;
-                    col[tt] = LazyAcc<SMALL>::prep(a.pts[(pidx * prows + prow) * N + k0 + kl]);
+                    src = a.pts + (pidx * prows + prow) * N + k0 + kl;
                 }
+                col[tt] = *src;
             }
+#pragma unroll
+            for (int tt = 0; tt < MAC_TB; ++tt) col[tt] = LazyAcc<SMALL>::prep(col[tt]);
         };
         if (resident) {
 #pragma unroll
@@ -223,7 +245,7 @@ __global__ void __launch_bounds__(256) k_mac(MacArgs a, Batch b, const ModConst 
                 for (int m = 0; m < MY; ++m) {
                     const int r = g0 + esc + m * ES;
                     if (r < n_act) {
-                        const int64_t e = (int64_t)a.order[r] * a.n_out + o;
+                        const int64_t e = (int64_t)order[r] * a.n_out + o;
                         uint64_t *dst = a.acc + (e * a.G + j) * ct + (int64_t)s * N + k0 + kl;
                         dst[0] = acc[m][0].value();
                         dst[(int64_t)ls * N] = acc[m][1].value();
@@ -254,7 +276,9 @@ static int launch_mac(const Ctx *c, const Plan *p, MacArgs &ma, const Batch &bou
     int idx[MAX_BATCH];
     for (int r = 0; r < R; ++r) idx[r] = r;
     std::stable_sort(idx, idx + R, [&](int x, int y) { return bout.level[x * p->n_out] > bout.level[y * p->n_out]; });
-    for (int r = 0; r < R; ++r) ma.order[r] = (uint8_t)idx[r];
+    for (int r = 0; r < R; ++r) ma.order[r] = idx[r];
+    ma.zero = c->d_zero;
+    ma.b_magic = (uint32_t)(((1u << 20) + ma.B - 1) / ma.B);
     const int JT = std::min(ma.G, 16);
     const int MY = p->tune.mac_my;
     // requests per group: MY times the thread rows per giant step (at most 16 / JT), a power of two <= 8
