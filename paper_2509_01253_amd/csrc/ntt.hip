@@ -131,73 +131,100 @@ __global__ void __launch_bounds__(NTT_THREADS) k_ntt_inv_1(RowMap rm, const ModC
 // idx = (M + gb 2^S + rho) / 2t, with M = 2^S in pass 1 (first stages of the
 // transform, gb = 0) and M = N in pass 2 (gb = global 256-block index).
 // ---------------------------------------------------------------------------
-template <int S>
-__device__ __forceinline__ void fwd_round_a(uint64_t (&X)[16], int64_t base, const uint64_t *__restrict__ w,
-                                            const uint64_t *__restrict__ wp, uint64_t q) {
+// The twiddles of a round are loaded before its butterflies, in the order they are
+// used, so that their loads are in flight together (and with the data's) rather
+// than one stage at a time.
+struct Tw {
+    uint64_t w[15], wp[15];  // at most 1 + 2 + 4 + 8 pairs
+};
+
+// round A twiddles: stages lh = 3..0 (forward) or 0..3 (inverse), groups g < 8 / 2^lh
+template <int S, bool FWD>
+__device__ __forceinline__ void tw_load_a(Tw &t, int64_t base, const uint64_t *__restrict__ w,
+                                          const uint64_t *__restrict__ wp) {
     constexpr int T = 1 << (S - 4);
+    int k = 0;
 #pragma unroll
-    for (int lh = 3; lh >= 0; --lh) {
-        const int h = 1 << lh;
-        const int lt = lh + (S - 4);  // log2 of the distance t = h T
+    for (int i = 0; i < 4; ++i) {
+        const int lh = FWD ? 3 - i : i;
+        const int h = 1 << lh, lt = lh + (S - 4);  // log2 of the distance t = h T
 #pragma unroll
-        for (int g = 0; g < 8 / h; ++g) {  // groups of 2h consecutive u
+        for (int g = 0; g < 8 / h; ++g, ++k) {
             const int64_t idx = (base + (int64_t)T * (g * 2 * h)) >> (lt + 1);
-            const uint64_t W = w[idx], Wp = wp[idx];
+            t.w[k] = w[idx];
+            t.wp[k] = wp[idx];
+        }
+    }
+}
+
+// round B twiddles: stages lh = S-5..0 (forward) or 0..S-5 (inverse)
+template <int S, bool FWD>
+__device__ __forceinline__ void tw_load_b(Tw &t, int64_t base, const uint64_t *__restrict__ w,
+                                          const uint64_t *__restrict__ wp) {
+    int k = 0;
 #pragma unroll
-            for (int v = 0; v < h; ++v) ct_bfly(X[g * 2 * h + v], X[g * 2 * h + v + h], W, Wp, q);
+    for (int i = 0; i <= S - 5; ++i) {
+        const int lh = FWD ? S - 5 - i : i;
+        const int h = 1 << lh;
+#pragma unroll
+        for (int g = 0; g < 8 / h; ++g, ++k) {
+            const int64_t idx = (base + g * 2 * h) >> (lh + 1);
+            t.w[k] = w[idx];
+            t.wp[k] = wp[idx];
         }
     }
 }
 
 template <int S>
-__device__ __forceinline__ void fwd_round_b(uint64_t (&X)[16], int64_t base, const uint64_t *__restrict__ w,
-                                            const uint64_t *__restrict__ wp, uint64_t q) {
-    // base = M + gb 2^S + 16 r
+__device__ __forceinline__ void fwd_round_a(uint64_t (&X)[16], const Tw &t, uint64_t q) {
+    int k = 0;
+#pragma unroll
+    for (int lh = 3; lh >= 0; --lh) {
+        const int h = 1 << lh;
+#pragma unroll
+        for (int g = 0; g < 8 / h; ++g, ++k)
+#pragma unroll
+            for (int v = 0; v < h; ++v) ct_bfly(X[g * 2 * h + v], X[g * 2 * h + v + h], t.w[k], t.wp[k], q);
+    }
+}
+
+template <int S>
+__device__ __forceinline__ void fwd_round_b(uint64_t (&X)[16], const Tw &t, uint64_t q) {
+    int k = 0;
 #pragma unroll
     for (int lh = S - 5; lh >= 0; --lh) {
         const int h = 1 << lh;
 #pragma unroll
-        for (int g = 0; g < 8 / h; ++g) {
-            const int64_t idx = (base + g * 2 * h) >> (lh + 1);
-            const uint64_t W = w[idx], Wp = wp[idx];
+        for (int g = 0; g < 8 / h; ++g, ++k)
 #pragma unroll
-            for (int v = 0; v < h; ++v) ct_bfly(X[g * 2 * h + v], X[g * 2 * h + v + h], W, Wp, q);
-        }
+            for (int v = 0; v < h; ++v) ct_bfly(X[g * 2 * h + v], X[g * 2 * h + v + h], t.w[k], t.wp[k], q);
     }
 }
 
 // inverse rounds: stages in increasing distance
 template <int S>
-__device__ __forceinline__ void inv_round_b(uint64_t (&X)[16], int64_t base, const uint64_t *__restrict__ w,
-                                            const uint64_t *__restrict__ wp, uint64_t q) {
+__device__ __forceinline__ void inv_round_b(uint64_t (&X)[16], const Tw &t, uint64_t q) {
+    int k = 0;
 #pragma unroll
     for (int lh = 0; lh <= S - 5; ++lh) {
         const int h = 1 << lh;
 #pragma unroll
-        for (int g = 0; g < 8 / h; ++g) {
-            const int64_t idx = (base + g * 2 * h) >> (lh + 1);
-            const uint64_t W = w[idx], Wp = wp[idx];
+        for (int g = 0; g < 8 / h; ++g, ++k)
 #pragma unroll
-            for (int v = 0; v < h; ++v) gs_bfly(X[g * 2 * h + v], X[g * 2 * h + v + h], W, Wp, q);
-        }
+            for (int v = 0; v < h; ++v) gs_bfly(X[g * 2 * h + v], X[g * 2 * h + v + h], t.w[k], t.wp[k], q);
     }
 }
 
 template <int S>
-__device__ __forceinline__ void inv_round_a(uint64_t (&X)[16], int64_t base, const uint64_t *__restrict__ w,
-                                            const uint64_t *__restrict__ wp, uint64_t q) {
-    constexpr int T = 1 << (S - 4);
+__device__ __forceinline__ void inv_round_a(uint64_t (&X)[16], const Tw &t, uint64_t q) {
+    int k = 0;
 #pragma unroll
     for (int lh = 0; lh <= 3; ++lh) {
         const int h = 1 << lh;
-        const int lt = lh + (S - 4);
 #pragma unroll
-        for (int g = 0; g < 8 / h; ++g) {
-            const int64_t idx = (base + (int64_t)T * (g * 2 * h)) >> (lt + 1);
-            const uint64_t W = w[idx], Wp = wp[idx];
+        for (int g = 0; g < 8 / h; ++g, ++k)
 #pragma unroll
-            for (int v = 0; v < h; ++v) gs_bfly(X[g * 2 * h + v], X[g * 2 * h + v + h], W, Wp, q);
-        }
+            for (int v = 0; v < h; ++v) gs_bfly(X[g * 2 * h + v], X[g * 2 * h + v + h], t.w[k], t.wp[k], q);
     }
 }
 
@@ -218,13 +245,19 @@ __global__ void __launch_bounds__(NTT_THREADS) k_ntt_fwd_cols(RowMap rm, const M
     uint64_t X[16];
 #pragma unroll
     for (int u = 0; u < 16; ++u) X[u] = xc[256 * (r + T * u)];
-    fwd_round_a<S>(X, 1 << S, w, wp, q);
+    {
+        Tw ta;
+        tw_load_a<S, true>(ta, 1 << S, w, wp);
+        fwd_round_a<S>(X, ta, q);
+    }
+    Tw tb;
+    tw_load_b<S, true>(tb, (1 << S) + 16 * r, w, wp);
 #pragma unroll
     for (int u = 0; u < 16; ++u) s[(r + T * u) * CP + c] = X[u];
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < 16; ++u) X[u] = s[(16 * r + u) * CP + c];
-    fwd_round_b<S>(X, (1 << S) + 16 * r, w, wp, q);
+    fwd_round_b<S>(X, tb, q);
 #pragma unroll
     for (int u = 0; u < 16; ++u) xc[256 * (16 * r + u)] = X[u];  // lazy [0, 4q)
 }
@@ -248,14 +281,20 @@ __global__ void __launch_bounds__(NTT_THREADS) k_ntt_fwd_rows(RowMap rm, const M
 #pragma unroll
     for (int u = 0; u < 16; ++u) X[u] = xt[blk * 256 + r + 16 * u];
     const int64_t base = N + (int64_t)gb * 256;
-    fwd_round_a<8>(X, base, w, wp, q);
+    {
+        Tw ta;
+        tw_load_a<8, true>(ta, base, w, wp);
+        fwd_round_a<8>(X, ta, q);
+    }
+    Tw tb;
+    tw_load_b<8, true>(tb, base + 16 * r, w, wp);
     uint64_t *sb = s + blk * BS;
 #pragma unroll
     for (int u = 0; u < 16; ++u) sb[r + 17 * u] = X[u];
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < 16; ++u) X[u] = sb[17 * r + u];
-    fwd_round_b<8>(X, base + 16 * r, w, wp, q);
+    fwd_round_b<8>(X, tb, q);
 #pragma unroll
     for (int u = 0; u < 16; ++u) sb[17 * r + u] = reduce4q(X[u], q);
     __syncthreads();
@@ -277,20 +316,27 @@ __global__ void __launch_bounds__(NTT_THREADS) k_ntt_inv_rows(RowMap rm, const M
     const int blk = threadIdx.x >> 4, r = threadIdx.x & 15;
     const int gb = blockIdx.x * 16 + blk;
     uint64_t *xt = x + (size_t)blockIdx.x * TILE;
-    for (int e = threadIdx.x; e < TILE; e += NTT_THREADS) s[(e >> 8) * BS + (e & 255) + ((e & 255) >> 4)] = xt[e];
-    __syncthreads();
-    uint64_t *sb = s + blk * BS;
-    uint64_t X[16];
-#pragma unroll
-    for (int u = 0; u < 16; ++u) X[u] = sb[17 * r + u];
     const int64_t base = N + (int64_t)gb * 256;
-    inv_round_b<8>(X, base + 16 * r, w, wp, q);
+    uint64_t X[16];
+    {
+        Tw tb;
+        tw_load_b<8, false>(tb, base + 16 * r, w, wp);
+        for (int e = threadIdx.x; e < TILE; e += NTT_THREADS)
+            s[(e >> 8) * BS + (e & 255) + ((e & 255) >> 4)] = xt[e];
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < 16; ++u) X[u] = s[blk * BS + 17 * r + u];
+        inv_round_b<8>(X, tb, q);
+    }
+    Tw ta;
+    tw_load_a<8, false>(ta, base, w, wp);
+    uint64_t *sb = s + blk * BS;
 #pragma unroll
     for (int u = 0; u < 16; ++u) sb[17 * r + u] = X[u];
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < 16; ++u) X[u] = sb[r + 17 * u];
-    inv_round_a<8>(X, base, w, wp, q);
+    inv_round_a<8>(X, ta, q);
 #pragma unroll
     for (int u = 0; u < 16; ++u) xt[blk * 256 + r + 16 * u] = X[u];  // lazy [0, 2q)
 }
@@ -313,13 +359,19 @@ __global__ void __launch_bounds__(NTT_THREADS) k_ntt_inv_cols(RowMap rm, const M
     uint64_t X[16];
 #pragma unroll
     for (int u = 0; u < 16; ++u) X[u] = xc[256 * (16 * r + u)];
-    inv_round_b<S>(X, (1 << S) + 16 * r, w, wp, q);
+    {
+        Tw tb;
+        tw_load_b<S, false>(tb, (1 << S) + 16 * r, w, wp);
+        inv_round_b<S>(X, tb, q);
+    }
+    Tw ta;
+    tw_load_a<S, false>(ta, 1 << S, w, wp);
 #pragma unroll
     for (int u = 0; u < 16; ++u) s[(16 * r + u) * CP + c] = X[u];
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < 16; ++u) X[u] = s[(r + T * u) * CP + c];
-    inv_round_a<S>(X, 1 << S, w, wp, q);
+    inv_round_a<S>(X, ta, q);
 #pragma unroll
     for (int u = 0; u < 16; ++u) xc[256 * (r + T * u)] = shoup(X[u], mc.ninv, mc.ninv_sh, q);
 }
