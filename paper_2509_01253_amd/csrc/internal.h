@@ -381,6 +381,7 @@ struct KsRot {
     uint32_t g[MAX_ROT];     // Galois element of rotation i
     int32_t key[MAX_ROT];    // its key index in every entry's key set
     int64_t out[MAX_ROT];    // element offset of its output from the entry's output
+    uint32_t ginv[MAX_ROT];  // g^-1 mod 2N (filled by the launcher)
 };
 // every rotation of `rot` for every entry of b (b.key[t] = base of the entry's key set)
 int launch_ks_inner_rot(const Ctx *c, const Batch &b, const KsRot &rot, const uint64_t *digits, int64_t digits_es,

@@ -216,6 +216,133 @@ __global__ void __launch_bounds__(256) k_ks_inner(Batch b, const ModConst *__res
     }
 }
 
+// Every rotation of a list for every entry (hoisted baby steps): for rotation g and
+// entry t, u = (P c0 + <D, evk_g>_0, <D, evk_g>_1) with the digits D and c0 taken at
+// sigma_g.  sigma_g(a) at slot k is a at auto_index(k, g), so the value at slot m
+// lands at k = auto_index(m, g^-1).  A thread owns one source slot m and EPT entries:
+// their digits and addends at m stay in registers across all rotations, while keys
+// are read, and outputs written, at k -- a permutation inside m's 64-slot block, so
+// each wave still covers whole cache lines.  Each digit is read from memory once
+// per launch instead of once per rotation.  The next rotation's key rows are
+// loaded while the current one is multiplied.
+// Block: 64 slots x 4 entry rows (wave w takes entries w, w + 4, ...); grid (N/64,
+// slots, ceil(n / 4 EPT)).
+template <bool SMALL, int MAXB, int EPT>
+__global__ void __launch_bounds__(256) k_ks_rot(Batch b, const ModConst *__restrict__ mods,
+                                                const ModDownTab *__restrict__ mdt,
+                                                const uint64_t *__restrict__ digits, int64_t digits_es,
+                                                uint64_t *__restrict__ u, int64_t u_es, KsAdd add, KsRot rot,
+                                                int log_n, int L, int K, int alpha) {
+    const int s = blockIdx.y;
+    const int64_t N = (int64_t)1 << log_n;
+    const int m = blockIdx.x * 64 + (threadIdx.x & 63);
+    // the wave index, known to be uniform: entry metadata is then read with scalar loads
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const ModConst mc = mods[s];
+    const int64_t dstride = (int64_t)(L + K) * N;
+    const bool has_add = add.src && (add.ext || s < L);
+    bool live[EPT];
+    int beta[EPT];
+    uint64_t dv[EPT][MAXB], pa[EPT];
+    int first = -1;
+#pragma unroll
+    for (int v = 0; v < EPT; ++v) {
+        const int t = blockIdx.z * 4 * EPT + w + 4 * v;
+        live[v] = t < b.n && !(s < L && s >= b.level[t]);
+        beta[v] = live[v] ? (b.level[t] + alpha - 1) / alpha : 0;
+        pa[v] = 0;
+#pragma unroll
+        for (int j = 0; j < MAXB; ++j) dv[v][j] = 0;
+        if (!live[v]) continue;
+        if (first < 0) first = v;
+        const uint64_t *d = digits + t * digits_es + (int64_t)s * N + m;
+#pragma unroll
+        for (int j = 0; j < MAXB; ++j)
+            if (j < beta[v]) dv[v][j] = d[j * dstride];
+        if (has_add) pa[v] = add.src[t * add.es + (int64_t)s * N + m];
+    }
+    if (first < 0) return;
+#pragma unroll
+    for (int v = 0; v < EPT; ++v) {
+#pragma unroll
+        for (int j = 0; j < MAXB; ++j) dv[v][j] = LazyAcc<SMALL>::prep(dv[v][j]);
+        if (has_add && !add.ext) pa[v] = mont_mul(pa[v], mdt->p_mont[s], mc.q, mc.mont_neg_inv);
+    }
+    // key rows of slot s: position s (q) or key_level + (s - L) (p) of each digit/part;
+    // rows past the key's digits repeat its last one (never used)
+    auto key_rows = [&](int v, int ri, int k, uint64_t(&kb)[MAXB], uint64_t(&ka)[MAXB]) {
+        const int t = blockIdx.z * 4 * EPT + w + 4 * v;
+        const int kl = b.key_level[t];
+        const int kbeta = (kl + alpha - 1) / alpha;
+        const int64_t kpart = (int64_t)(kl + K) * N;
+        const uint64_t *key = b.key[t] + (int64_t)rot.key[ri] * 2 * kbeta * kpart +
+                              (int64_t)(s < L ? s : kl + (s - L)) * N + k;
+#pragma unroll
+        for (int j = 0; j < MAXB; ++j) {
+            const int jr = j < kbeta ? j : kbeta - 1;
+            kb[j] = key[(2 * jr) * kpart];
+            ka[j] = key[(2 * jr + 1) * kpart];
+        }
+    };
+    const int t_first = blockIdx.z * 4 * EPT + w + 4 * first;
+    uint64_t nb[MAXB], na[MAXB];
+    int k_next = auto_index(m, rot.ginv[0], log_n);
+    key_rows(first, 0, k_next, nb, na);
+    for (int ri = 0; ri < rot.n; ++ri) {
+        const int k = k_next;
+        uint64_t kb[MAXB], ka[MAXB];
+#pragma unroll
+        for (int j = 0; j < MAXB; ++j) {
+            kb[j] = LazyAcc<SMALL>::prep(nb[j]);
+            ka[j] = LazyAcc<SMALL>::prep(na[j]);
+        }
+        // the next rotation's keys are in flight during this one's products
+        const int rn = ri + 1 < rot.n ? ri + 1 : ri;
+        k_next = auto_index(m, rot.ginv[rn], log_n);
+        key_rows(first, rn, k_next, nb, na);
+        const uint64_t *kt_first = b.key[t_first];
+#pragma unroll
+        for (int v = 0; v < EPT; ++v) {
+            if (!live[v]) continue;
+            const int t = blockIdx.z * 4 * EPT + w + 4 * v;
+            LazyAcc<SMALL> a0, a1;
+            a0.zero();
+            a1.zero();
+            if (b.key[t] == kt_first && b.key_level[t] == b.key_level[t_first]) {
+#pragma unroll
+                for (int j = 0; j < MAXB; ++j) {
+                    if (j < beta[v]) {
+                        a0.mac(dv[v][j], kb[j]);
+                        a1.mac(dv[v][j], ka[j]);
+                    }
+                }
+            } else {  // an entry of another key set (several clients in one batch)
+                uint64_t ob[MAXB], oa[MAXB];
+                key_rows(v, ri, k, ob, oa);
+#pragma unroll
+                for (int j = 0; j < MAXB; ++j) {
+                    if (j < beta[v]) {
+                        a0.mac(dv[v][j], LazyAcc<SMALL>::prep(ob[j]));
+                        a1.mac(dv[v][j], LazyAcc<SMALL>::prep(oa[j]));
+                    }
+                }
+            }
+            uint64_t r0 = a0.reduce(mc.q, mc.mont_neg_inv), r1 = a1.reduce(mc.q, mc.mont_neg_inv);
+            if (has_add) r0 = add_mod(r0, pa[v], mc.q);
+            uint64_t *ut = u + t * u_es + rot.out[ri];
+            ut[(int64_t)s * N + k] = r0;
+            ut[((int64_t)(L + K) + s) * N + k] = r1;
+        }
+    }
+}
+
+static uint32_t galois_inverse(uint32_t g, int log_n) {
+    // g is odd: Newton's iteration x <- x (2 - g x) doubles the correct low bits
+    uint32_t x = g;
+    for (int i = 0; i < 5; ++i) x *= 2u - g * x;
+    return x & ((2u << log_n) - 1u);
+}
+
 static int launch_ks_inner_impl(const Ctx *c, const Batch &b, const uint64_t *digits, int64_t digits_es, uint64_t *u,
                                 int64_t u_es, KsAdd add, hipStream_t s, int eg, const KsRot &rot) {
     if (b.n == 0) return FHELIN_OK;
@@ -243,11 +370,30 @@ static int launch_ks_inner_impl(const Ctx *c, const Batch &b, const uint64_t *di
         }
     }
     ProfScope ps(c, s, PK_KS_INNER, units, bytes);
+    const int n_digits = (c->L + c->alpha - 1) / c->alpha;  // at most 16 (checked at context creation)
+    if (rot.n > 0) {
+        KsRot r = rot;
+        for (int i = 0; i < r.n; ++i) r.ginv[i] = galois_inverse(r.g[i], c->log_n);
+#define FL_KR(SM, MB, E) hipLaunchKernelGGL((k_ks_rot<SM, MB, E>), dim3(c->N / 64, c->L + c->K, (b.n + 4 * E - 1) / (4 * E)), \
+                                            dim3(256), 0, s, b, c->d_mods, c->d_moddown, digits, digits_es, u, u_es, add, \
+                                            r, c->log_n, c->L, c->K, c->alpha)
+        if (c->small) {
+            if (n_digits <= 4) FL_KR(true, 4, 4);
+            else if (n_digits <= 8) FL_KR(true, 8, 2);
+            else FL_KR(true, 16, 1);
+        } else {
+            if (n_digits <= 4) FL_KR(false, 4, 4);
+            else if (n_digits <= 8) FL_KR(false, 8, 2);
+            else FL_KR(false, 16, 1);
+        }
+#undef FL_KR
+        FL_TRY_HIP(hipGetLastError());
+        return FHELIN_OK;
+    }
     if (eg < 1) eg = 1;
     dim3 grid(c->N / 256, c->L + c->K, (b.n + eg - 1) / eg);
 #define FL_KS(SM, MB) hipLaunchKernelGGL((k_ks_inner<SM, MB>), grid, dim3(256), 0, s, b, c->d_mods, c->d_moddown, \
                                          digits, digits_es, u, u_es, add, rot, c->log_n, c->L, c->K, c->alpha, eg)
-    const int n_digits = (c->L + c->alpha - 1) / c->alpha;  // at most 16 (checked at context creation)
     if (c->small) {
         if (n_digits <= 4) FL_KS(true, 4);
         else if (n_digits <= 8) FL_KS(true, 8);
