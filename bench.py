@@ -80,10 +80,10 @@ HBM_PEAK_GBPS = 8000.0
 ROOF = {k: ("alu", "T modmul-butterflies/s", PEAK_BFLY) for k in
         ("ntt_fwd_cols", "ntt_fwd_rows", "ntt_inv_rows", "ntt_inv_cols")}
 ROOF["mac"] = ("alu", "T modular products/s", PEAK_MAC)
-for _k in ("ks_inner", "modup", "moddown_fbc", "combine", "copy", "rescale", "mont"):
+for _k in ("ks_inner", "ks_rot", "ks_sum", "modup", "moddown_fbc", "combine", "copy", "rescale", "mont"):
     ROOF[_k] = ("hbm", "GB/s", HBM_PEAK_GBPS)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic.json")
-KERNELS = ["ntt_fwd_cols", "ntt_fwd_rows", "ntt_inv_rows", "ntt_inv_cols", "mac", "ks_inner", "modup",
+KERNELS = ["ntt_fwd_cols", "ntt_fwd_rows", "ntt_inv_rows", "ntt_inv_cols", "mac", "ks_inner", "ks_rot", "ks_sum", "modup",
            "moddown_fbc", "combine", "rescale", "copy", "mont", "encode"]
 
 
@@ -135,7 +135,7 @@ def pmc_summary(dirs: str, args) -> None:
     gib = 1 << 20  # KiB in 1 GiB: the calibration copy moves 1 GiB each way
     f_scale, w_scale = gib / copy_kib(cfetch), gib / copy_kib(cwrite)
     fk, wk = per_kernel(fetch), per_kernel(write)
-    names = {"k_mac": "mac", "k_ks_inner": "ks_inner", "k_ntt_fwd_rows": "ntt_fwd_rows",
+    names = {"k_mac": "mac", "k_ks_inner": "ks_inner", "k_ks_rot": "ks_rot", "k_ks_sum": "ks_sum", "k_ntt_fwd_rows": "ntt_fwd_rows",
              "k_ntt_fwd_cols": "ntt_fwd_cols", "k_ntt_inv_rows": "ntt_inv_rows", "k_ntt_inv_cols": "ntt_inv_cols",
              "k_modup": "modup", "k_moddown_fbc": "moddown_fbc", "k_moddown_combine": "combine",
              "k_copy_rows": "copy", "k_rescale": "rescale", "k_to_mont": "mont"}

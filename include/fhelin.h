@@ -303,12 +303,14 @@ int fhelin_ntt(fhelin_ctx *ctx, uint64_t *rows, const int32_t *mod_index, int32_
  * bracketed by two HIP events recorded on its launching stream (not while the
  * stream is being captured into a graph).  enable != 0 also discards earlier
  * records.  Kernel classes: ntt_fwd_cols, ntt_fwd_rows, ntt_inv_rows,
- * ntt_inv_cols, ntt_fwd_1, ntt_inv_1, mac, ks_inner, modup, moddown_fbc,
+ * ntt_inv_cols, ntt_fwd_1, ntt_inv_1, mac, ks_inner (one rotation per
+ * entry), ks_rot (a list of rotations for every entry: hoisted baby steps),
+ * ks_sum (a sum of key switches per entry: giant steps), modup, moddown_fbc,
  * combine, rescale, copy, mont, encode. */
 int fhelin_profile_enable(fhelin_ctx *ctx, int32_t enable);
 /* Totals of one kernel class since enabling: launches, summed event time (ms),
  * summed algorithmic work units (butterflies for NTT passes, 64-bit
- * multiply-adds for mac / ks_inner, output elements otherwise) and summed
+ * multiply-adds for mac / ks_inner / ks_rot / ks_sum, output elements otherwise) and summed
  * algorithmic HBM bytes (every input and output stream of the launch counted
  * once; distinct evaluation keys once per launch; 0 for classes without a byte
  * model).  Waits for the recorded events.  Output pointers may be NULL. */

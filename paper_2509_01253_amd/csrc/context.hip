@@ -321,7 +321,8 @@ int ctx_create(const fhelin_params *prm, Ctx **out) {
 const char *const PROF_NAMES[PK_COUNT] = {"ntt_fwd_cols", "ntt_fwd_rows", "ntt_inv_rows", "ntt_inv_cols",
                                           "ntt_fwd_1",    "ntt_inv_1",    "mac",          "ks_inner",
                                           "modup",        "moddown_fbc",  "combine",      "rescale",
-                                          "copy",         "mont",         "encode"};
+                                          "copy",         "mont",         "encode",       "ks_rot",
+                                          "ks_sum"};
 
 hipEvent_t Profiler::get() {
     if (!pool.empty()) {

@@ -88,7 +88,8 @@ struct Workspace;
 // Optional per-kernel timing with HIP events on the launching stream (diagnostics).
 enum ProfKind : int {
     PK_NTT_FWD_COLS = 0, PK_NTT_FWD_ROWS, PK_NTT_INV_ROWS, PK_NTT_INV_COLS, PK_NTT_FWD_1, PK_NTT_INV_1,
-    PK_MAC, PK_KS_INNER, PK_MODUP, PK_MODDOWN_FBC, PK_COMBINE, PK_RESCALE, PK_COPY, PK_MONT, PK_ENCODE, PK_COUNT
+    PK_MAC, PK_KS_INNER, PK_MODUP, PK_MODDOWN_FBC, PK_COMBINE, PK_RESCALE, PK_COPY, PK_MONT, PK_ENCODE, PK_KS_ROT,
+    PK_KS_SUM, PK_COUNT
 };
 extern const char *const PROF_NAMES[PK_COUNT];
 
@@ -383,6 +384,20 @@ struct KsRot {
     int64_t out[MAX_ROT];    // element offset of its output from the entry's output
     uint32_t ginv[MAX_ROT];  // g^-1 mod 2N (filled by the launcher)
 };
+// A sum of key switches per entry (giant steps): entry t gets
+//   init_t + sum_i (add_i,t(sigma_i) + <D_i,t(sigma_i), evk_i>_0, <D_i,t(sigma_i), evk_i>_1)
+// on the extended basis, each rotation with its own digits and addend.
+constexpr int MAX_SUM = 16;
+struct KsSum {
+    int32_t n;
+    uint32_t g[MAX_SUM];        // Galois element of term i
+    int32_t key[MAX_SUM];       // its key index in every entry's key set
+    int64_t dig_off[MAX_SUM];   // element offset of term i's digits from `digits`
+    int64_t add_off[MAX_SUM];   // element offset of term i's addend from `add`
+};
+int launch_ks_sum(const Ctx *c, const Batch &b, const KsSum &sum, const uint64_t *digits, int64_t digits_es,
+                  const uint64_t *add, int64_t add_es, const uint64_t *init, int64_t init_es, uint64_t *u,
+                  int64_t u_es, hipStream_t s);
 // every rotation of `rot` for every entry of b (b.key[t] = base of the entry's key set)
 int launch_ks_inner_rot(const Ctx *c, const Batch &b, const KsRot &rot, const uint64_t *digits, int64_t digits_es,
                         uint64_t *u, int64_t u_es, const uint64_t *add, int64_t add_es, int add_ext, hipStream_t s,

@@ -336,6 +336,163 @@ __global__ void __launch_bounds__(256) k_ks_rot(Batch b, const ModConst *__restr
     }
 }
 
+// Giant-step sum: see KsSum.  Thread = slot k of limb s; a block takes EG entries and
+// keeps their two running sums in registers across the terms, so the sum is written
+// once instead of read and rewritten per term.  Within a term, every entry's digit
+// and addend loads are issued before the first product.
+template <bool SMALL, int MAXB, int EG>
+__global__ void __launch_bounds__(256) k_ks_sum(Batch b, const ModConst *__restrict__ mods,
+                                                const uint64_t *__restrict__ digits, int64_t digits_es,
+                                                const uint64_t *__restrict__ add, int64_t add_es,
+                                                const uint64_t *__restrict__ init, int64_t init_es,
+                                                uint64_t *__restrict__ u, int64_t u_es, KsSum sum, int log_n, int L,
+                                                int K, int alpha) {
+    const int s = blockIdx.y;
+    const int64_t N = (int64_t)1 << log_n, E = L + K;
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    const ModConst mc = mods[s];
+    const int t0 = blockIdx.z * EG;
+    bool live[EG];
+    int beta[EG];
+    uint64_t acc[EG][2];
+    int first = -1;
+#pragma unroll
+    for (int v = 0; v < EG; ++v) {
+        const int t = t0 + v;
+        live[v] = t < b.n && !(s < L && s >= b.level[t]);
+        beta[v] = live[v] ? (b.level[t] + alpha - 1) / alpha : 0;
+        acc[v][0] = acc[v][1] = 0;
+        if (live[v] && init) {
+            acc[v][0] = init[t * init_es + (int64_t)s * N + k];
+            acc[v][1] = init[t * init_es + (E + s) * N + k];
+        }
+        if (live[v] && first < 0) first = v;
+    }
+    if (first < 0) return;
+    auto key_rows = [&](int t, int ti, uint64_t(&kb)[MAXB], uint64_t(&ka)[MAXB]) {
+        const int kl = b.key_level[t];
+        const int kbeta = (kl + alpha - 1) / alpha;
+        const int64_t kpart = (int64_t)(kl + K) * N;
+        const uint64_t *key = b.key[t] + (int64_t)sum.key[ti] * 2 * kbeta * kpart +
+                              (int64_t)(s < L ? s : kl + (s - L)) * N + k;
+#pragma unroll
+        for (int j = 0; j < MAXB; ++j) {
+            const int jr = j < kbeta ? j : kbeta - 1;
+            kb[j] = key[(2 * jr) * kpart];
+            ka[j] = key[(2 * jr + 1) * kpart];
+        }
+    };
+    const int t_first = t0 + first;
+    for (int ti = 0; ti < sum.n; ++ti) {
+        const int src = auto_index(k, sum.g[ti], log_n);
+        uint64_t kb[MAXB], ka[MAXB];
+        key_rows(t_first, ti, kb, ka);
+        uint64_t dv[EG][MAXB], addv[EG];
+#pragma unroll
+        for (int v = 0; v < EG; ++v) {
+            addv[v] = 0;
+#pragma unroll
+            for (int j = 0; j < MAXB; ++j) dv[v][j] = 0;
+            if (!live[v]) continue;
+            const int t = t0 + v;
+            const uint64_t *d = digits + sum.dig_off[ti] + t * digits_es + (int64_t)s * N + src;
+#pragma unroll
+            for (int j = 0; j < MAXB; ++j)
+                if (j < beta[v]) dv[v][j] = d[j * E * N];
+            addv[v] = add[sum.add_off[ti] + t * add_es + (int64_t)s * N + src];
+        }
+#pragma unroll
+        for (int j = 0; j < MAXB; ++j) {
+            kb[j] = LazyAcc<SMALL>::prep(kb[j]);
+            ka[j] = LazyAcc<SMALL>::prep(ka[j]);
+        }
+#pragma unroll
+        for (int v = 0; v < EG; ++v) {
+            if (!live[v]) continue;
+            const int t = t0 + v;
+            LazyAcc<SMALL> a0, a1;
+            a0.zero();
+            a1.zero();
+            if (b.key[t] == b.key[t_first] && b.key_level[t] == b.key_level[t_first]) {
+#pragma unroll
+                for (int j = 0; j < MAXB; ++j) {
+                    if (j < beta[v]) {
+                        const uint64_t x = LazyAcc<SMALL>::prep(dv[v][j]);
+                        a0.mac(x, kb[j]);
+                        a1.mac(x, ka[j]);
+                    }
+                }
+            } else {  // an entry of another key set (several clients in one batch)
+                uint64_t ob[MAXB], oa[MAXB];
+                key_rows(t, ti, ob, oa);
+#pragma unroll
+                for (int j = 0; j < MAXB; ++j) {
+                    if (j < beta[v]) {
+                        const uint64_t x = LazyAcc<SMALL>::prep(dv[v][j]);
+                        a0.mac(x, LazyAcc<SMALL>::prep(ob[j]));
+                        a1.mac(x, LazyAcc<SMALL>::prep(oa[j]));
+                    }
+                }
+            }
+            const uint64_t r0 = add_mod(a0.reduce(mc.q, mc.mont_neg_inv), addv[v], mc.q);
+            acc[v][0] = add_mod(acc[v][0], r0, mc.q);
+            acc[v][1] = add_mod(acc[v][1], a1.reduce(mc.q, mc.mont_neg_inv), mc.q);
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < EG; ++v) {
+        if (!live[v]) continue;
+        const int t = t0 + v;
+        u[t * u_es + (int64_t)s * N + k] = acc[v][0];
+        u[t * u_es + (E + s) * N + k] = acc[v][1];
+    }
+}
+
+int launch_ks_sum(const Ctx *c, const Batch &b, const KsSum &sum, const uint64_t *digits, int64_t digits_es,
+                  const uint64_t *add, int64_t add_es, const uint64_t *init, int64_t init_es, uint64_t *u,
+                  int64_t u_es, hipStream_t s) {
+    if (b.n == 0) return FHELIN_OK;
+    // work: 2 beta (l + K) N products per entry and term; bytes: per term the digits
+    // (beta (l + K) limbs) and the addend (l + K), each distinct key once; the initial
+    // value and the sum (2 (l + K) each) once
+    double units = 0, bytes = 0;
+    const double limb = 8.0 * c->N;
+    for (int t = 0; t < b.n; ++t) {
+        const double l = b.level[t], beta = std::ceil(l / c->alpha), e = l + c->K;
+        units += sum.n * 2.0 * beta * e * c->N;
+        bytes += limb * (sum.n * (beta * e + e) + (init ? 2 * e : 0) + 2 * e);
+    }
+    {
+        const uint64_t *seen[MAX_BATCH];
+        int n_seen = 0;
+        for (int t = 0; t < b.n; ++t) {
+            bool dup = false;
+            for (int i = 0; i < n_seen; ++i) dup |= seen[i] == b.key[t];
+            if (dup) continue;
+            seen[n_seen++] = b.key[t];
+            const double kl = b.key_level[t];
+            bytes += sum.n * limb * 2 * std::ceil(kl / c->alpha) * (kl + c->K);
+        }
+    }
+    ProfScope ps(c, s, PK_KS_SUM, units, bytes);
+    const int n_digits = (c->L + c->alpha - 1) / c->alpha;
+#define FL_KSUM(SM, MB, EG) hipLaunchKernelGGL((k_ks_sum<SM, MB, EG>), dim3(c->N / 256, c->L + c->K, (b.n + EG - 1) / EG), \
+                                               dim3(256), 0, s, b, c->d_mods, digits, digits_es, add, add_es, init, \
+                                               init_es, u, u_es, sum, c->log_n, c->L, c->K, c->alpha)
+    if (c->small) {
+        if (n_digits <= 4) FL_KSUM(true, 4, 8);
+        else if (n_digits <= 8) FL_KSUM(true, 8, 4);
+        else FL_KSUM(true, 16, 2);
+    } else {
+        if (n_digits <= 4) FL_KSUM(false, 4, 8);
+        else if (n_digits <= 8) FL_KSUM(false, 8, 4);
+        else FL_KSUM(false, 16, 2);
+    }
+#undef FL_KSUM
+    FL_TRY_HIP(hipGetLastError());
+    return FHELIN_OK;
+}
+
 static uint32_t galois_inverse(uint32_t g, int log_n) {
     // g is odd: Newton's iteration x <- x (2 - g x) doubles the correct low bits
     uint32_t x = g;
@@ -369,7 +526,7 @@ static int launch_ks_inner_impl(const Ctx *c, const Batch &b, const uint64_t *di
             bytes += n_rot * limb * 2 * std::ceil(kl / c->alpha) * (kl + c->K);
         }
     }
-    ProfScope ps(c, s, PK_KS_INNER, units, bytes);
+    ProfScope ps(c, s, rot.n > 0 ? PK_KS_ROT : PK_KS_INNER, units, bytes);
     const int n_digits = (c->L + c->alpha - 1) / c->alpha;  // at most 16 (checked at context creation)
     if (rot.n > 0) {
         KsRot r = rot;

@@ -442,10 +442,23 @@ static size_t limbs_per_request(const Ctx *c, const Plan *p, int Bp) {
            + emax * 2 * L;         // md
 }
 
+// giant steps other than the identity
+static int giant_nonid(const Ctx *c, const Plan *p) {
+    int n = 0;
+    for (int r : p->gk) n += galois_of_rotation(r, c->log_n) == 1 ? 0 : 1;
+    return n;
+}
+
+// digit buffers of the giant steps: one per step when they are summed in one launch
+static int giant_digit_sets(const Ctx *c, const Plan *p) {
+    const int n = giant_nonid(c, p);
+    return n >= 1 && n <= MAX_SUM ? n : 1;
+}
+
 static size_t limbs_per_request_dh(const Ctx *c, const Plan *p, int Bp) {
     const size_t L = c->L, K = c->K, D = c->dnum, E = L + K;
     const size_t ni = p->n_in, no = p->n_out, G = p->gk.size();
-    const size_t emax = std::max(ni, no);
+    const size_t emax = std::max(ni, no), nd = giant_digit_sets(c, p);
     return ni * 2 * L         // X
            + ni * 2 * E        // P * X
            + ni * D * E        // hoisted digits
@@ -455,7 +468,7 @@ static size_t limbs_per_request_dh(const Ctx *c, const Plan *p, int Bp) {
            + no * 2 * L        // Y
            + emax * 2 * L      // Q temp for ModDown(c1)
            + emax * L          // coefficient temp
-           + emax * D * E      // giant digits
+           + emax * D * E * nd // giant digits
            + emax * 2 * L;     // md
 }
 
@@ -500,7 +513,8 @@ static int apply_chunk_dh(Ctx *c, const Plan *p, const KeySet *const *kss, const
     const int Ein = Rc * p->n_in, Eout = Rc * p->n_out, Emax = std::max(Ein, Eout);
     uint64_t *X = ws, *XL = X + Ein * ct, *D = XL + Ein * ext, *RB = D + Ein * dg;
     uint64_t *A = RB + (int64_t)Ein * Bp * ext, *YE = A + (int64_t)Eout * G * ext, *Y = YE + Eout * ext;
-    uint64_t *TQ = Y + Eout * ct, *TC = TQ + Emax * ct, *DG = TC + Emax * L * N, *MD = DG + Emax * dg;
+    const int n_dg = giant_digit_sets(c, p);
+    uint64_t *TQ = Y + Eout * ct, *TC = TQ + Emax * ct, *DG = TC + Emax * L * N, *MD = DG + Emax * dg * n_dg;
     Batch bin{}, bout{};
     bin.n = Ein;
     bout.n = Eout;
@@ -570,13 +584,55 @@ static int apply_chunk_dh(Ctx *c, const Plan *p, const KeySet *const *kss, const
     ma.pt_level = pts->level;
     ma.ext = 1;
     FL_RET(launch_mac(c, p, ma, bout, s));
-    // 5. giant steps summed in the extended basis
+    // 5. giant steps summed in the extended basis.  When every giant step has its own
+    // digit buffer and the chunk's key sets hold the giant keys at the same indices,
+    // the key switches of all steps (and the identity step) go to one launch that
+    // writes the sum once.
+    const int64_t a_es = (int64_t)G * ext;
+    bool fuse = n_dg == giant_nonid(c, p) && n_dg >= 1;
+    for (int j = 0; fuse && j < G; ++j) {
+        const uint32_t g = galois_of_rotation(p->gk[j], c->log_n);
+        if (g == 1) continue;
+        const int idx = kss[r0]->find(g);
+        for (int r = 1; r < Rc; ++r) fuse = fuse && kss[r0 + r]->find(g) == idx;
+    }
+    if (fuse) {
+        KsSum sum{};
+        const uint64_t *init = nullptr;
+        for (int j = 0; j < G; ++j) {
+            const uint32_t g = galois_of_rotation(p->gk[j], c->log_n);
+            uint64_t *Aj = A + j * ext;
+            if (g == 1) {
+                init = Aj;
+                continue;
+            }
+            set_keys(bout, p->n_out, kss + r0, g);
+            uint64_t *Aj1 = Aj + E * N;
+            FL_RET(launch_ntt(c, rows_kind(c, bout, Aj1, a_es, ROWS_EXT_P, 1), 1, s));
+            FL_RET(launch_moddown_fbc(c, bout, Aj1, a_es, MD, ct, s, 1));
+            FL_RET(launch_ntt(c, rows_ct(c, bout, MD, ct, (int)L, 0, 1), 0, s));
+            FL_RET(launch_moddown_combine(c, bout, Aj1, a_es, MD, ct, TQ + L * N, ct, (int)L, nullptr, 0, 0, 0, s, 1));
+            KsScratch wj{TC, L * N, DG + (int64_t)sum.n * Emax * dg, dg, nullptr, 0, MD, ct};
+            FL_RET(modup_ct(c, bout, TQ, ct, (int)L, wj, s));
+            sum.g[sum.n] = g;
+            sum.key[sum.n] = kss[r0]->find(g);
+            sum.dig_off[sum.n] = (int64_t)sum.n * Emax * dg;
+            sum.add_off[sum.n] = j * ext;
+            ++sum.n;
+        }
+        for (int e = 0; e < Eout; ++e) {
+            const KeySet *ks = kss[r0 + e / p->n_out];
+            bout.key[e] = ks->evk;
+            bout.key_level[e] = ks->level;
+            bout.g[e] = 1;
+        }
+        FL_RET(launch_ks_sum(c, bout, sum, DG, dg, A, a_es, init, a_es, YE, ext, s));
+    }
     bool first = true;
     KsScratch w{TC, L * N, DG, dg, nullptr, 0, MD, ct};
-    for (int j = 0; j < G; ++j) {
+    for (int j = 0; !fuse && j < G; ++j) {
         uint32_t g = galois_of_rotation(p->gk[j], c->log_n);
         uint64_t *Aj = A + j * ext;
-        const int64_t a_es = (int64_t)G * ext;
         if (g == 1) {
             FL_RET(launch_ext_lift_add(c, bout, Aj, a_es, 0, 0, first ? 0 : 1, YE, ext, s));
             first = false;
