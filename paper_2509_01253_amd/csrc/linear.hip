@@ -167,13 +167,20 @@ __global__ void __launch_bounds__(256) k_mac(MacArgs a, Batch b, const ModConst 
             tb[h] = (m < 0 ? a.x + (int64_t)ii * ct : a.rb + ((int64_t)ii * a.Bp + m) * ct) + lane_off;
             tstride[h] = (m < 0 ? (int64_t)a.n_in : (int64_t)a.n_in * a.Bp) * ct;
         }
+        // the group's request entries, read once (scalar loads issued together)
+        int ord[ET];
+#pragma unroll
+        for (int rr = 0; rr < ET; ++rr) ord[rr] = a.order[g0 + rr < n_act ? g0 + rr : 0];
+        // every address first, then the loads: no branch separates them
+        const uint64_t *src[2 * ET];
 #pragma unroll
         for (int i = 0; i < 2 * ET; ++i) {
-            const int h = i & 1, r = g0 + (i >> 1);
-            const bool live = tv[h] && r < n_act;
-            const uint64_t *src = live ? tb[h] + a.order[r < n_act ? r : 0] * tstride[h] : a.zero;
-            pre[i] = *src;
+            const int h = i & 1, rr = i >> 1;
+            const uint64_t *cand = tb[h] + ord[rr] * tstride[h];
+            src[i] = tv[h] && g0 + rr < n_act ? cand : a.zero;
         }
+#pragma unroll
+        for (int i = 0; i < 2 * ET; ++i) pre[i] = *src[i];
     };
     auto stash = [&]() {
 #pragma unroll
@@ -214,10 +221,19 @@ __global__ void __launch_bounds__(256) k_mac(MacArgs a, Batch b, const ModConst 
                 __syncthreads();  // readers of the previous tile are done
                 stash();
                 __syncthreads();
-                // prefetch the next tile: next chunk, next group, or the first of the next giant-step chunk
-                if (t0 + MAC_TB < terms) fetch(g0, t0 + MAC_TB);
-                else if (g0 + ET < n_act) fetch(g0 + ET, 0);
-                else if (jc + JT < a.G) fetch(0, 0);
+                // prefetch the next tile: next chunk, next group, or the first of the next
+                // giant-step chunk (one call site: one inlined copy of the loads)
+                int gn = g0, tn = t0 + MAC_TB;
+                bool more = true;
+                if (tn >= terms) {
+                    tn = 0;
+                    gn = g0 + ET;
+                    if (gn >= n_act) {
+                        gn = 0;
+                        more = jc + JT < a.G;
+                    }
+                }
+                if (more) fetch(gn, tn);
                 auto compute = [&](const uint64_t(&col)[MAC_TB]) {
 #pragma unroll
                     for (int tt = 0; tt < MAC_TB; ++tt) {
