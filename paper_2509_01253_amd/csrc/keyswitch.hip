@@ -216,6 +216,21 @@ __global__ void __launch_bounds__(256) k_ks_inner(Batch b, const ModConst *__res
     }
 }
 
+// Block coordinates of a 1-D grid of nx * ny * nz blocks in which the nz blocks of
+// one (x, y) tile -- they read the same key rows for different entry groups -- are
+// dispatched 8 apart: blocks go to the 8 XCDs round-robin, so these share an XCD
+// and its L2 and run close together.  Needs nx * ny % 8 == 0 (else plain order).
+struct BlockXYZ {
+    int x, y, z;
+};
+__device__ __forceinline__ BlockXYZ xcd_block(int nx, int ny, int nz, bool swizzle) {
+    const int lin = blockIdx.x;
+    if (!swizzle) return {lin % nx, (lin / nx) % ny, lin / (nx * ny)};
+    const int span = 8 * nz, q = lin / span, w = lin % span;
+    const int xy = q * 8 + (w & 7);
+    return {xy % nx, xy / nx, w >> 3};
+}
+
 // Every rotation of a list for every entry (hoisted baby steps): for rotation g and
 // entry t, u = (P c0 + <D, evk_g>_0, <D, evk_g>_1) with the digits D and c0 taken at
 // sigma_g.  sigma_g(a) at slot k is a at auto_index(k, g), so the value at slot m
@@ -225,17 +240,18 @@ __global__ void __launch_bounds__(256) k_ks_inner(Batch b, const ModConst *__res
 // each wave still covers whole cache lines.  Each digit is read from memory once
 // per launch instead of once per rotation.  The next rotation's key rows are
 // loaded while the current one is multiplied.
-// Block: 64 slots x 4 entry rows (wave w takes entries w, w + 4, ...); grid (N/64,
-// slots, ceil(n / 4 EPT)).
+// Block: 64 slots x 4 entry rows (wave w takes entries w, w + 4, ...); blocks (N/64,
+// slots, ceil(n / 4 EPT)) on a 1-D grid (xcd_block).
 template <bool SMALL, int MAXB, int EPT>
 __global__ void __launch_bounds__(256) k_ks_rot(Batch b, const ModConst *__restrict__ mods,
                                                 const ModDownTab *__restrict__ mdt,
                                                 const uint64_t *__restrict__ digits, int64_t digits_es,
                                                 uint64_t *__restrict__ u, int64_t u_es, KsAdd add, KsRot rot,
-                                                int log_n, int L, int K, int alpha) {
-    const int s = blockIdx.y;
+                                                int log_n, int L, int K, int alpha, int nz, bool swizzle) {
+    const BlockXYZ bk = xcd_block((1 << log_n) / 64, L + K, nz, swizzle);
+    const int s = bk.y;
     const int64_t N = (int64_t)1 << log_n;
-    const int m = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int m = bk.x * 64 + (threadIdx.x & 63);
     // the wave index, known to be uniform: entry metadata is then read with scalar loads
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const ModConst mc = mods[s];
@@ -247,7 +263,7 @@ __global__ void __launch_bounds__(256) k_ks_rot(Batch b, const ModConst *__restr
     int first = -1;
 #pragma unroll
     for (int v = 0; v < EPT; ++v) {
-        const int t = blockIdx.z * 4 * EPT + w + 4 * v;
+        const int t = bk.z * 4 * EPT + w + 4 * v;
         live[v] = t < b.n && !(s < L && s >= b.level[t]);
         beta[v] = live[v] ? (b.level[t] + alpha - 1) / alpha : 0;
         pa[v] = 0;
@@ -271,7 +287,7 @@ __global__ void __launch_bounds__(256) k_ks_rot(Batch b, const ModConst *__restr
     // key rows of slot s: position s (q) or key_level + (s - L) (p) of each digit/part;
     // rows past the key's digits repeat its last one (never used)
     auto key_rows = [&](int v, int ri, int k, uint64_t(&kb)[MAXB], uint64_t(&ka)[MAXB]) {
-        const int t = blockIdx.z * 4 * EPT + w + 4 * v;
+        const int t = bk.z * 4 * EPT + w + 4 * v;
         const int kl = b.key_level[t];
         const int kbeta = (kl + alpha - 1) / alpha;
         const int64_t kpart = (int64_t)(kl + K) * N;
@@ -284,7 +300,7 @@ __global__ void __launch_bounds__(256) k_ks_rot(Batch b, const ModConst *__restr
             ka[j] = key[(2 * jr + 1) * kpart];
         }
     };
-    const int t_first = blockIdx.z * 4 * EPT + w + 4 * first;
+    const int t_first = bk.z * 4 * EPT + w + 4 * first;
     uint64_t nb[MAXB], na[MAXB];
     int k_next = auto_index(m, rot.ginv[0], log_n);
     key_rows(first, 0, k_next, nb, na);
@@ -304,7 +320,7 @@ __global__ void __launch_bounds__(256) k_ks_rot(Batch b, const ModConst *__restr
 #pragma unroll
         for (int v = 0; v < EPT; ++v) {
             if (!live[v]) continue;
-            const int t = blockIdx.z * 4 * EPT + w + 4 * v;
+            const int t = bk.z * 4 * EPT + w + 4 * v;
             LazyAcc<SMALL> a0, a1;
             a0.zero();
             a1.zero();
@@ -346,12 +362,13 @@ __global__ void __launch_bounds__(256) k_ks_sum(Batch b, const ModConst *__restr
                                                 const uint64_t *__restrict__ add, int64_t add_es,
                                                 const uint64_t *__restrict__ init, int64_t init_es,
                                                 uint64_t *__restrict__ u, int64_t u_es, KsSum sum, int log_n, int L,
-                                                int K, int alpha) {
-    const int s = blockIdx.y;
+                                                int K, int alpha, int nz, bool swizzle) {
+    const BlockXYZ bk = xcd_block((1 << log_n) / 256, L + K, nz, swizzle);
+    const int s = bk.y;
     const int64_t N = (int64_t)1 << log_n, E = L + K;
-    const int k = blockIdx.x * 256 + threadIdx.x;
+    const int k = bk.x * 256 + threadIdx.x;
     const ModConst mc = mods[s];
-    const int t0 = blockIdx.z * EG;
+    const int t0 = bk.z * EG;
     bool live[EG];
     int beta[EG];
     uint64_t acc[EG][2];
@@ -476,9 +493,10 @@ int launch_ks_sum(const Ctx *c, const Batch &b, const KsSum &sum, const uint64_t
     }
     ProfScope ps(c, s, PK_KS_SUM, units, bytes);
     const int n_digits = (c->L + c->alpha - 1) / c->alpha;
-#define FL_KSUM(SM, MB, EG) hipLaunchKernelGGL((k_ks_sum<SM, MB, EG>), dim3(c->N / 256, c->L + c->K, (b.n + EG - 1) / EG), \
-                                               dim3(256), 0, s, b, c->d_mods, digits, digits_es, add, add_es, init, \
-                                               init_es, u, u_es, sum, c->log_n, c->L, c->K, c->alpha)
+    const int nxy = c->N / 256 * (c->L + c->K);
+#define FL_KSUM(SM, MB, EG) hipLaunchKernelGGL((k_ks_sum<SM, MB, EG>), dim3(nxy * ((b.n + EG - 1) / EG)), dim3(256), 0, s, \
+                                               b, c->d_mods, digits, digits_es, add, add_es, init, init_es, u, u_es, sum, \
+                                               c->log_n, c->L, c->K, c->alpha, (b.n + EG - 1) / EG, nxy % 8 == 0)
     if (c->small) {
         if (n_digits <= 4) FL_KSUM(true, 4, 8);
         else if (n_digits <= 8) FL_KSUM(true, 8, 4);
@@ -531,9 +549,10 @@ static int launch_ks_inner_impl(const Ctx *c, const Batch &b, const uint64_t *di
     if (rot.n > 0) {
         KsRot r = rot;
         for (int i = 0; i < r.n; ++i) r.ginv[i] = galois_inverse(r.g[i], c->log_n);
-#define FL_KR(SM, MB, E) hipLaunchKernelGGL((k_ks_rot<SM, MB, E>), dim3(c->N / 64, c->L + c->K, (b.n + 4 * E - 1) / (4 * E)), \
-                                            dim3(256), 0, s, b, c->d_mods, c->d_moddown, digits, digits_es, u, u_es, add, \
-                                            r, c->log_n, c->L, c->K, c->alpha)
+        const int nxy = c->N / 64 * (c->L + c->K);
+#define FL_KR(SM, MB, E) hipLaunchKernelGGL((k_ks_rot<SM, MB, E>), dim3(nxy * ((b.n + 4 * E - 1) / (4 * E))), dim3(256), \
+                                            0, s, b, c->d_mods, c->d_moddown, digits, digits_es, u, u_es, add, r, c->log_n, \
+                                            c->L, c->K, c->alpha, (b.n + 4 * E - 1) / (4 * E), nxy % 8 == 0)
         if (c->small) {
             if (n_digits <= 4) FL_KR(true, 4, 4);
             else if (n_digits <= 8) FL_KR(true, 8, 2);
