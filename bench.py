@@ -52,6 +52,9 @@ def parse():
                     help="requests per arrival rate in an extra serving run (default 0 = no serving run)")
     ap.add_argument("--serve-rates", type=str, default="20,100", help="Poisson arrival rates (req/s)")
     ap.add_argument("--serve-clients", type=int, default=32)
+    ap.add_argument("--serve-streams", type=str, default="4",
+                    help="streams (batches in flight at once) of the continuous-batching server; a comma list "
+                         "runs one server per value")
     ap.add_argument("--pmc-summary", type=str, default="",
                     help="instead of the benchmark: FETCH,WRITE,CALIB_FETCH,CALIB_WRITE rocprofv3 --pmc output "
                          "directories -> the measured-traffic file used for roofline.traffic")
@@ -207,7 +210,7 @@ def serve_bench(args) -> dict:
         "conv16": dict(params="N15", log_n=15, L=8, K=2, dnum=4, c=16, hw=32, lmin=2),
         "conv64": dict(params="N16", log_n=16, L=12, K=3, dnum=4, c=64, hw=64, lmin=2),
     }
-    ex = GpuExecutor(n_streams=4)
+    ex = GpuExecutor(n_streams=max(int(k) for k in args.serve_streams.split(",")))
     gen = torch.Generator(device=dev)
     gen.manual_seed(int(root.sub(synth.TAG_KEYS).u64(1)[0] & 0x7FFFFFFFFFFFFFFF))
     info = {}
@@ -264,7 +267,9 @@ def serve_bench(args) -> dict:
            "rates": {}}
     for ri, rate in enumerate(float(r) for r in args.serve_rates.split(",")):
         row = {}
-        for mode, streams, mb in (("continuous", 4, 64), ("one_at_a_time", 1, 1)):
+        modes = [(f"continuous_s{k}" if "," in args.serve_streams else "continuous", int(k), 64)
+                 for k in args.serve_streams.split(",")] + [("one_at_a_time", 1, 1)]
+        for mode, streams, mb in modes:
             reqs = make_requests(rate, ri)
             srv = Server(ex, hbm_budget=200 << 30, streams=streams, max_batch=mb)
             for ci in range(args.serve_clients):
@@ -272,6 +277,7 @@ def serve_bench(args) -> dict:
             res = srv.run(reqs)
             st = srv.stats(res)
             row[mode] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items()}
+            print(f"serving rate {rate:g} req/s, {mode}: {row[mode]}", file=sys.stderr, flush=True)
             for k in list(srv.keys):
                 ex.release_keys(srv.keys.pop(k).handle)
             del reqs, res

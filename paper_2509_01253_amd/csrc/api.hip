@@ -96,11 +96,14 @@ static int keyset_load(Ctx *c, const uint32_t *galois, int n_keys, int level, co
     k->galois.assign(galois, galois + n_keys);
     k->bytes = (size_t)n_keys * k->key_stride() * sizeof(uint64_t);
     FL_RET(dev_alloc(c, (void **)&k->evk, k->bytes));
-    hipError_t e = hipMemcpyAsync(k->evk, evk, k->bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s);
-    if (e == hipSuccess && !on_device) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) {
-        dev_free(c, k->evk, k->bytes);
-        return set_error(FHELIN_E_HIP, std::string("keyset_load copy: ") + hipGetErrorString(e));
+    // a host source is copied in first; a device source is read by the NTT's first pass
+    if (!on_device) {
+        hipError_t e = hipMemcpyAsync(k->evk, evk, k->bytes, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            dev_free(c, k->evk, k->bytes);
+            return set_error(FHELIN_E_HIP, std::string("keyset_load copy: ") + hipGetErrorString(e));
+        }
     }
     // every row: NTT then Montgomery form; rows grouped per (key, digit, part)
     RowMap m{};
@@ -118,8 +121,12 @@ static int keyset_load(Ctx *c, const uint32_t *galois, int n_keys, int level, co
         e2.n_ct = 1;
         e2.n_part = std::min(per, parts - p0);
         e2.level[0] = (uint8_t)level;
-        rc = launch_ntt(c, e2, 0, s);
-        if (rc == FHELIN_OK) rc = launch_to_mont(c, e2, s);
+        RowMap src{};
+        if (on_device) {
+            src = e2;
+            src.base = const_cast<uint64_t *>(evk) + (int64_t)p0 * (level + c->K) * c->N;
+        }
+        rc = launch_ntt_from(c, e2, src, 0, s, true);
     }
     if (rc == FHELIN_OK) rc = k->ready.record(s);
     if (rc) {

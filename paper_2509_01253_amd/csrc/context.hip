@@ -194,6 +194,8 @@ int ctx_create(const fhelin_params *prm, Ctx **out) {
         mc.ninv_sh = h_shoup(mc.ninv, q);
         mc.half = (q - 1) / 2;
         mc.one_sh = h_shoup(1, q);
+        mc.r1 = (uint64_t)((((u128)1) << 64) % q);
+        mc.r1_sh = h_shoup(mc.r1, q);
         c->h_mods.push_back(mc);
         uint64_t psi_inv = h_invmod(psi, q);
         std::vector<uint64_t> pw(N), ipw(N);

@@ -158,8 +158,7 @@ static int pt_to_internal(Ctx *c, PtSet *p, hipStream_t s) {
     const int64_t rows = p->level + c->K;
     for (int p0 = 0; p0 < p->n_pt; p0 += 64) {
         RowMap e = pt_rows(c, p->data + (int64_t)p0 * rows * c->N, std::min(64, p->n_pt - p0), p->level);
-        FL_RET(launch_ntt(c, e, 0, s));
-        FL_RET(launch_to_mont(c, e, s));
+        FL_RET(launch_ntt(c, e, 0, s, true));
     }
     return p->ready.record(s);
 }

@@ -58,6 +58,7 @@ struct ModConst {
     uint64_t ninv, ninv_sh; // N^{-1} mod q and its Shoup companion
     uint64_t half;          // (q - 1) / 2: largest non-negative centred residue
     uint64_t one_sh;        // floor(2^64 / q): x mod q = csub(shoup_lazy(x, 1, one_sh, q))
+    uint64_t r1, r1_sh;     // 2^64 mod q and its Shoup companion: Montgomery form in one Shoup product
 };
 
 // Base conversion constants of ModUp for (level l, digit j): digit primes
@@ -149,6 +150,8 @@ enum RowKind : int32_t {
     ROWS_MODUP = 3, // digit buffer [dnum][L+K]: every slot of each digit except the digit's own q's
     ROWS_EXT_Q = 4, // extended buffer [n_part][L+K]: Q slots 0..l-1 of each part
     ROWS_KEY = 5,   // compact key rows [n_part][l+K]: position e < l -> q_e, else p_{e-l}
+    ROWS_EXT = 6,   // extended buffer [n_part][L+K]: Q slots 0..l-1 and the K special slots of each part
+    ROWS_DIGITS = 7,// digit buffer [dnum][L+K]: Q slots 0..l-1 and the special slots of each of the beta digits
 };
 
 struct RowMap {
@@ -175,6 +178,8 @@ __host__ __device__ inline int rowmap_rows(const RowMap &m, int t) {
     case ROWS_EXT_P: return m.n_part * m.K;
     case ROWS_EXT_Q: return m.n_part * l;
     case ROWS_KEY: return m.n_part * (l + m.K);
+    case ROWS_EXT: return m.n_part * (l + m.K);
+    case ROWS_DIGITS: return (l + m.alpha - 1) / m.alpha * (l + m.K);
     case ROWS_MODUP: {
         int beta = (l + m.alpha - 1) / m.alpha;
         return beta * (l + m.K) - l;
@@ -215,6 +220,15 @@ __host__ __device__ inline void rowmap_get(const RowMap &m, int t, int r, int64_
         int e = r % (l + m.K);
         *off = base + (int64_t)r * N;
         *mod = e < l ? e : m.L + (e - l);
+        return;
+    }
+    case ROWS_EXT:
+    case ROWS_DIGITS: {
+        // part (or digit) r / (l + K), position e < l -> q_e, else p_{e-l}; slot-indexed layout
+        int p = r / (l + m.K), e = r % (l + m.K);
+        int slot = e < l ? e : m.L + (e - l);
+        *off = base + ((int64_t)p * (m.L + m.K) + slot) * N;
+        *mod = slot;
         return;
     }
     case ROWS_MODUP: {
@@ -356,12 +370,20 @@ struct ProfScope {
 // ---------------------------------------------------------------------------
 // NTT over the rows of a RowMap; inverse = 0 forward (natural -> bit-reversed),
 // 1 inverse.  Rows hold canonical residues on entry and exit.
-int launch_ntt(const Ctx *c, const RowMap &rows, int inverse, hipStream_t s);
+// to_mont (forward only): the outputs leave in Montgomery form (x 2^64 mod q)
+int launch_ntt(const Ctx *c, const RowMap &rows, int inverse, hipStream_t s, bool to_mont = false);
+// out of place: rows of `src` (same row enumeration as `rows`, its own layout) transformed into `rows`
+int launch_ntt_from(const Ctx *c, const RowMap &rows, const RowMap &src, int inverse, hipStream_t s,
+                    bool to_mont = false);
 // to/from Montgomery form over the rows (canonical in, canonical out)
 int launch_to_mont(const Ctx *c, const RowMap &rows, hipStream_t s);
 int launch_from_mont(const Ctx *c, const RowMap &rows, hipStream_t s);
 // copy rows between two row maps of the same shape
 int launch_copy_rows(const Ctx *c, const RowMap &dst, const RowMap &src, hipStream_t s);
+// ModDown of one polynomial of extended entries in the coefficient domain:
+// out[i] = (u[i] - conv_P->q_i(u[P])) * P^{-1} mod q_i, i < level
+int launch_moddown_coef(const Ctx *c, const Batch &b, const uint64_t *u, int64_t u_es, uint64_t *out, int64_t out_es,
+                        hipStream_t s);
 
 // key switching (keyswitch.hip); all pointers are bases of batch entry 0, *_es = elements per entry
 int launch_modup(const Ctx *c, const Batch &b, const uint64_t *coef, int64_t coef_es, const uint64_t *ntt,

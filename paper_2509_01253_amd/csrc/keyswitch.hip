@@ -708,6 +708,61 @@ int launch_moddown_fbc(const Ctx *c, const Batch &b, const uint64_t *u, int64_t 
 }
 
 // ---------------------------------------------------------------------------
+// ModDown in the coefficient domain, conversion and combination in one pass:
+// grid (N/256, 1, n); u is one polynomial [L+K] (slot-indexed) per entry
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_moddown_coef(Batch b, const ModConst *__restrict__ mods,
+                                                      const ModDownTab *__restrict__ tab,
+                                                      const uint64_t *__restrict__ u, int64_t u_es,
+                                                      uint64_t *__restrict__ out, int64_t out_es, int log_n, int L,
+                                                      int K) {
+    const int t = blockIdx.z;
+    const int l = b.level[t];
+    const int64_t N = (int64_t)1 << log_n;
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    const uint64_t *up = u + t * u_es;
+    uint64_t *o = out + t * out_es;
+    uint64_t v[MAX_P];
+    uint64_t nneg = 0;
+#pragma unroll
+    for (int a = 0; a < MAX_P; ++a) {
+        if (a < K) {
+            const ModConst mc = mods[L + a];
+            uint64_t w = shoup(up[(int64_t)(L + a) * N + k], tab->inv_hat[a], tab->inv_hat_sh[a], mc.q);
+            v[a] = w;
+            nneg += w > mc.half ? 1 : 0;
+        }
+    }
+    for (int i = 0; i < l; ++i) {
+        const ModConst mc = mods[i];
+        Acc128 acc{0, 0};
+#pragma unroll
+        for (int a = 0; a < MAX_P; ++a)
+            if (a < K) mac128(acc, v[a], tab->hat_mont[a][i]);
+        uint64_t r = redc(acc, mc.q, mc.mont_neg_inv);
+        if (nneg) r = sub_mod(r, mont_mul(nneg, tab->p_mont[i], mc.q, mc.mont_neg_inv), mc.q);
+        const uint64_t x = up[(int64_t)i * N + k];
+        o[(int64_t)i * N + k] = shoup(sub_mod(x, r, mc.q), tab->pinv[i], tab->pinv_sh[i], mc.q);
+    }
+}
+
+int launch_moddown_coef(const Ctx *c, const Batch &b, const uint64_t *u, int64_t u_es, uint64_t *out, int64_t out_es,
+                        hipStream_t s) {
+    if (b.n == 0) return FHELIN_OK;
+    double units = 0, bytes = 0;
+    for (int t = 0; t < b.n; ++t) {
+        const double l = b.level[t];
+        units += l * c->N;
+        bytes += 8.0 * c->N * (c->K + 2 * l);  // reads K + l limbs, writes l
+    }
+    ProfScope ps(c, s, PK_MODDOWN_FBC, units, bytes);
+    hipLaunchKernelGGL(k_moddown_coef, dim3(c->N / 256, 1, b.n), dim3(256), 0, s, b, c->d_mods, c->d_moddown, u, u_es,
+                       out, out_es, c->log_n, c->L, c->K);
+    FL_TRY_HIP(hipGetLastError());
+    return FHELIN_OK;
+}
+
+// ---------------------------------------------------------------------------
 // ModDown combine (NTT domain): grid (N/256, 2*l_max, n)
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_moddown_combine(Batch b, const ModConst *__restrict__ mods,

@@ -115,7 +115,7 @@ __global__ void __launch_bounds__(256) k_mac(MacArgs a, Batch b, const ModConst 
                                              int L, int K, int R, int JT) {
     static_assert(ET % MY == 0 && ET <= 8, "bad request group");
     constexpr int ES = ET / MY;
-    __shared__ uint64_t Rs[MAC_ET][MAC_TB][2][MAC_K];
+    __shared__ uint64_t Rs[ET][MAC_TB][2][MAC_K];
     const int s = blockIdx.y;  // slot = modulus index (q_s for s < L, p_{s-L} otherwise)
     // a q slot above the plaintexts' level is active for no request (levels <= pt_level)
     if (s < L && s >= a.pt_level) return;
@@ -402,8 +402,7 @@ static int modup_ct(const Ctx *c, const Batch &b, const uint64_t *ct, int64_t ct
     const int64_t N = c->N;
     RowMap src = rows_ct(c, b, (uint64_t *)ct, ct_es, ct_stride, 1, 1);
     RowMap dst = rows_ct(c, b, w.tc, w.tc_es, c->L, 0, 1);
-    FL_RET(launch_copy_rows(c, dst, src, s));
-    FL_RET(launch_ntt(c, dst, 1, s));
+    FL_RET(launch_ntt_from(c, dst, src, 1, s));  // c1 to the coefficient domain, out of place
     FL_RET(launch_modup(c, b, w.tc, w.tc_es, ct + (int64_t)ct_stride * N, ct_es, w.dg, w.dg_es, s));
     FL_RET(launch_ntt(c, rows_kind(c, b, w.dg, w.dg_es, ROWS_MODUP, 0), 0, s));
     return FHELIN_OK;
@@ -516,6 +515,20 @@ static int export_out(Ctx *c, const Batch &bout, uint64_t *Y, const fhelin_ct_ba
     return launch_copy_rows(c, rows_ct(c, bout, ob, out_es, out->stride, 0, 2), yr, s);
 }
 
+// Giant step of the double-hoisted schedule: ModDown of A~_j.c1 (extended basis, NTT
+// domain, consumed) to the Q basis, then ModUp of the result into the digits dg.  The
+// ModDown runs in the coefficient domain (one inverse transform of all l + K limbs,
+// conversion and combination in one pass), which is where ModUp needs its input; the
+// digits' own limbs are copied there and transformed with the rest.
+static int giant_moddown_modup(const Ctx *c, const Batch &b, uint64_t *a1, int64_t a_es, uint64_t *tc,
+                               uint64_t *dg, int64_t dg_es, hipStream_t s) {
+    const int64_t LN = (int64_t)c->L * c->N;
+    FL_RET(launch_ntt(c, rows_kind(c, b, a1, a_es, ROWS_EXT, 1), 1, s));
+    FL_RET(launch_moddown_coef(c, b, a1, a_es, tc, LN, s));
+    FL_RET(launch_modup(c, b, tc, LN, tc, LN, dg, dg_es, s));
+    return launch_ntt(c, rows_kind(c, b, dg, dg_es, ROWS_DIGITS, 0), 0, s);
+}
+
 // One chunk of requests with the double-hoisted schedule (Bossuat et al. 2021): baby
 // rotations, the multiply-accumulate and the giant-step sum stay in the extended basis
 // (carrying a factor P); each giant step ModDowns only c1 before its ModUp, and one
@@ -546,8 +559,7 @@ static int apply_chunk_dh(Ctx *c, const Plan *p, const KeySet *const *kss, const
     const int64_t in_es = (int64_t)2 * in->stride * N;
     RowMap src = rows_ct(c, bin, in->data + (int64_t)r0 * p->n_in * in_es, in_es, in->stride, 0, 2);
     RowMap dx = rows_ct(c, bin, X, ct, (int)L, 0, 2);
-    FL_RET(launch_copy_rows(c, dx, src, s));
-    FL_RET(launch_ntt(c, dx, 0, s));
+    FL_RET(launch_ntt_from(c, dx, src, 0, s));
     // 2. P * x for the identity baby step
     bool has_identity = false;
     for (int b = 0; b < B; ++b) has_identity |= ma.bmap[b] < 0;
@@ -623,13 +635,7 @@ static int apply_chunk_dh(Ctx *c, const Plan *p, const KeySet *const *kss, const
                 continue;
             }
             set_keys(bout, p->n_out, kss + r0, g);
-            uint64_t *Aj1 = Aj + E * N;
-            FL_RET(launch_ntt(c, rows_kind(c, bout, Aj1, a_es, ROWS_EXT_P, 1), 1, s));
-            FL_RET(launch_moddown_fbc(c, bout, Aj1, a_es, MD, ct, s, 1));
-            FL_RET(launch_ntt(c, rows_ct(c, bout, MD, ct, (int)L, 0, 1), 0, s));
-            FL_RET(launch_moddown_combine(c, bout, Aj1, a_es, MD, ct, TQ + L * N, ct, (int)L, nullptr, 0, 0, 0, s, 1));
-            KsScratch wj{TC, L * N, DG + (int64_t)sum.n * Emax * dg, dg, nullptr, 0, MD, ct};
-            FL_RET(modup_ct(c, bout, TQ, ct, (int)L, wj, s));
+            FL_RET(giant_moddown_modup(c, bout, Aj + E * N, a_es, TC, DG + (int64_t)sum.n * Emax * dg, dg, s));
             sum.g[sum.n] = g;
             sum.key[sum.n] = kss[r0]->find(g);
             sum.dig_off[sum.n] = (int64_t)sum.n * Emax * dg;
@@ -645,7 +651,6 @@ static int apply_chunk_dh(Ctx *c, const Plan *p, const KeySet *const *kss, const
         FL_RET(launch_ks_sum(c, bout, sum, DG, dg, A, a_es, init, a_es, YE, ext, s));
     }
     bool first = true;
-    KsScratch w{TC, L * N, DG, dg, nullptr, 0, MD, ct};
     for (int j = 0; !fuse && j < G; ++j) {
         uint32_t g = galois_of_rotation(p->gk[j], c->log_n);
         uint64_t *Aj = A + j * ext;
@@ -655,14 +660,8 @@ static int apply_chunk_dh(Ctx *c, const Plan *p, const KeySet *const *kss, const
             continue;
         }
         set_keys(bout, p->n_out, kss + r0, g);
-        // c1' = ModDown(A~_j.c1) -> poly 1 of TQ (NTT domain)
-        uint64_t *Aj1 = Aj + E * N;
-        FL_RET(launch_ntt(c, rows_kind(c, bout, Aj1, a_es, ROWS_EXT_P, 1), 1, s));
-        FL_RET(launch_moddown_fbc(c, bout, Aj1, a_es, MD, ct, s, 1));
-        FL_RET(launch_ntt(c, rows_ct(c, bout, MD, ct, (int)L, 0, 1), 0, s));
-        FL_RET(launch_moddown_combine(c, bout, Aj1, a_es, MD, ct, TQ + L * N, ct, (int)L, nullptr, 0, 0, 0, s, 1));
-        // ModUp(c1') and the inner product, plus sigma(A~_j.c0), summed into YE
-        FL_RET(modup_ct(c, bout, TQ, ct, (int)L, w, s));
+        // ModUp(ModDown(A~_j.c1)) and the inner product, plus sigma(A~_j.c0), summed into YE
+        FL_RET(giant_moddown_modup(c, bout, Aj + E * N, a_es, TC, DG, dg, s));
         FL_RET(launch_ks_inner_add(c, bout, DG, dg, YE, ext, Aj, a_es, 1, first ? 0 : 1, s, p->tune.ks_eg));
         first = false;
     }
@@ -755,8 +754,7 @@ int linear_apply(Ctx *c, const Plan *p, const KeySet *const *kss, const PtSet *p
         const int64_t in_es = (int64_t)2 * in->stride * N;
         RowMap src = rows_ct(c, bin, in->data + (int64_t)r0 * p->n_in * in_es, in_es, in->stride, 0, 2);
         RowMap dx = rows_ct(c, bin, X, ct, (int)L, 0, 2);
-        FL_RET(launch_copy_rows(c, dx, src, s));
-        FL_RET(launch_ntt(c, dx, 0, s));
+        FL_RET(launch_ntt_from(c, dx, src, 0, s));
         // 2-3. hoisted ModUp and baby rotations
         if (Bp > 0) {
             KsScratch wb = w;

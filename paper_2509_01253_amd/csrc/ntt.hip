@@ -33,6 +33,16 @@ __device__ __forceinline__ bool row_of(const RowMap &m, uint64_t *&ptr, int &mod
     return true;
 }
 
+// out-of-place first pass: the same row of the source map (same row enumeration,
+// its own layout), or the destination itself when the map is empty
+__device__ __forceinline__ const uint64_t *src_row(const RowMap &src, const uint64_t *dst) {
+    if (!src.base) return dst;
+    int64_t off;
+    int mod;
+    rowmap_get(src, blockIdx.z, blockIdx.y, &off, &mod);
+    return src.base + off;
+}
+
 // forward CT butterfly, lazy: X, Y in [0, 4q) -> [0, 4q)
 __device__ __forceinline__ void ct_bfly(uint64_t &X, uint64_t &Y, uint64_t w, uint64_t wp, uint64_t q) {
     uint64_t q2 = 2 * q;
@@ -230,7 +240,8 @@ __device__ __forceinline__ void inv_round_a(uint64_t (&X)[16], const Tw &t, uint
 
 // forward pass 1: stages with distance >= 256 on columns c + 256 rho, rho < N1 = 2^S
 template <int LOGN>
-__global__ void __launch_bounds__(NTT_THREADS) k_ntt_fwd_cols(RowMap rm, const ModConst *__restrict__ mods,
+__global__ void __launch_bounds__(NTT_THREADS) k_ntt_fwd_cols(RowMap rm, RowMap src,
+                                                              const ModConst *__restrict__ mods,
                                                               const uint64_t *__restrict__ tw,
                                                               const uint64_t *__restrict__ twp) {
     constexpr int N = 1 << LOGN, S = LOGN - 8, T = 1 << (S - 4), C = NTT_THREADS / T, CP = C + 1;
@@ -238,13 +249,15 @@ __global__ void __launch_bounds__(NTT_THREADS) k_ntt_fwd_cols(RowMap rm, const M
     uint64_t *x;
     int mi;
     if (!row_of(rm, x, mi)) return;
+    const uint64_t *xs = src_row(src, x);
     const uint64_t q = mods[mi].q;
     const uint64_t *w = tw + (size_t)mi * N, *wp = twp + (size_t)mi * N;
     const int c = threadIdx.x % C, r = threadIdx.x / C;
     uint64_t *xc = x + blockIdx.x * C + c;
+    const uint64_t *xsc = xs + blockIdx.x * C + c;
     uint64_t X[16];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) X[u] = xc[256 * (r + T * u)];
+    for (int u = 0; u < 16; ++u) X[u] = xsc[256 * (r + T * u)];
     {
         Tw ta;
         tw_load_a<S, true>(ta, 1 << S, w, wp);
@@ -262,8 +275,9 @@ __global__ void __launch_bounds__(NTT_THREADS) k_ntt_fwd_cols(RowMap rm, const M
     for (int u = 0; u < 16; ++u) xc[256 * (16 * r + u)] = X[u];  // lazy [0, 4q)
 }
 
-// forward pass 2: the last 8 stages inside contiguous 256-blocks; 16 blocks per workgroup
-template <int LOGN>
+// forward pass 2: the last 8 stages inside contiguous 256-blocks; 16 blocks per workgroup;
+// MONT: outputs in Montgomery form (one Shoup product by 2^64 mod q replaces the final reduction)
+template <int LOGN, bool MONT>
 __global__ void __launch_bounds__(NTT_THREADS) k_ntt_fwd_rows(RowMap rm, const ModConst *__restrict__ mods,
                                                               const uint64_t *__restrict__ tw,
                                                               const uint64_t *__restrict__ twp) {
@@ -296,14 +310,18 @@ __global__ void __launch_bounds__(NTT_THREADS) k_ntt_fwd_rows(RowMap rm, const M
     for (int u = 0; u < 16; ++u) X[u] = sb[17 * r + u];
     fwd_round_b<8>(X, tb, q);
 #pragma unroll
-    for (int u = 0; u < 16; ++u) sb[17 * r + u] = reduce4q(X[u], q);
+    for (int u = 0; u < 16; ++u) {
+        if constexpr (MONT) sb[17 * r + u] = shoup(X[u], mods[mi].r1, mods[mi].r1_sh, q);
+        else sb[17 * r + u] = reduce4q(X[u], q);
+    }
     __syncthreads();
     for (int e = threadIdx.x; e < TILE; e += NTT_THREADS) xt[e] = s[(e >> 8) * BS + (e & 255) + ((e & 255) >> 4)];
 }
 
 // inverse pass 1: the first 8 stages (distance 1 .. 128) inside contiguous 256-blocks
 template <int LOGN>
-__global__ void __launch_bounds__(NTT_THREADS) k_ntt_inv_rows(RowMap rm, const ModConst *__restrict__ mods,
+__global__ void __launch_bounds__(NTT_THREADS) k_ntt_inv_rows(RowMap rm, RowMap src,
+                                                              const ModConst *__restrict__ mods,
                                                               const uint64_t *__restrict__ itw,
                                                               const uint64_t *__restrict__ itwp) {
     constexpr int N = 1 << LOGN, BS = 272;
@@ -311,6 +329,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_ntt_inv_rows(RowMap rm, const M
     uint64_t *x;
     int mi;
     if (!row_of(rm, x, mi)) return;
+    const uint64_t *xst = src_row(src, x) + (size_t)blockIdx.x * TILE;
     const uint64_t q = mods[mi].q;
     const uint64_t *w = itw + (size_t)mi * N, *wp = itwp + (size_t)mi * N;
     const int blk = threadIdx.x >> 4, r = threadIdx.x & 15;
@@ -322,7 +341,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_ntt_inv_rows(RowMap rm, const M
         Tw tb;
         tw_load_b<8, false>(tb, base + 16 * r, w, wp);
         for (int e = threadIdx.x; e < TILE; e += NTT_THREADS)
-            s[(e >> 8) * BS + (e & 255) + ((e & 255) >> 4)] = xt[e];
+            s[(e >> 8) * BS + (e & 255) + ((e & 255) >> 4)] = xst[e];
         __syncthreads();
 #pragma unroll
         for (int u = 0; u < 16; ++u) X[u] = s[blk * BS + 17 * r + u];
@@ -392,7 +411,8 @@ __global__ void __launch_bounds__(256) k_to_mont(RowMap rm, const ModConst *__re
 }
 
 template <int LOGN>
-static void launch_ntt_t(const Ctx *c, const RowMap &rm, int rows, int inverse, hipStream_t s) {
+static void launch_ntt_t(const Ctx *c, const RowMap &rm, const RowMap &src, int rows, int inverse, bool to_mont,
+                         hipStream_t s) {
     const int M = 1 << LOGN;
     double total_rows = 0;
     for (int t = 0; t < rm.n_ct; ++t) total_rows += rowmap_rows(rm, t);
@@ -415,14 +435,20 @@ static void launch_ntt_t(const Ctx *c, const RowMap &rm, int rows, int inverse, 
         if (!inverse) {
             {
                 ProfScope ps(c, s, PK_NTT_FWD_COLS, bfly_per_stage * (LOGN - 8), row_bytes);
-                hipLaunchKernelGGL(k_ntt_fwd_cols<L2>, g, dim3(NTT_THREADS), 0, s, rm, c->d_mods, c->d_tw, c->d_twp);
+                hipLaunchKernelGGL(k_ntt_fwd_cols<L2>, g, dim3(NTT_THREADS), 0, s, rm, src, c->d_mods, c->d_tw,
+                                   c->d_twp);
             }
             ProfScope ps(c, s, PK_NTT_FWD_ROWS, bfly_per_stage * 8, row_bytes);
-            hipLaunchKernelGGL(k_ntt_fwd_rows<L2>, g, dim3(NTT_THREADS), 0, s, rm, c->d_mods, c->d_tw, c->d_twp);
+            if (to_mont)
+                hipLaunchKernelGGL((k_ntt_fwd_rows<L2, true>), g, dim3(NTT_THREADS), 0, s, rm, c->d_mods, c->d_tw, c->d_twp);
+            else
+                hipLaunchKernelGGL((k_ntt_fwd_rows<L2, false>), g, dim3(NTT_THREADS), 0, s, rm, c->d_mods, c->d_tw,
+                                   c->d_twp);
         } else {
             {
                 ProfScope ps(c, s, PK_NTT_INV_ROWS, bfly_per_stage * 8, row_bytes);
-                hipLaunchKernelGGL(k_ntt_inv_rows<L2>, g, dim3(NTT_THREADS), 0, s, rm, c->d_mods, c->d_itw, c->d_itwp);
+                hipLaunchKernelGGL(k_ntt_inv_rows<L2>, g, dim3(NTT_THREADS), 0, s, rm, src, c->d_mods, c->d_itw,
+                                   c->d_itwp);
             }
             ProfScope ps(c, s, PK_NTT_INV_COLS, bfly_per_stage * (LOGN - 8), row_bytes);
             hipLaunchKernelGGL(k_ntt_inv_cols<L2>, g, dim3(NTT_THREADS), 0, s, rm, c->d_mods, c->d_itw, c->d_itwp);
@@ -430,20 +456,36 @@ static void launch_ntt_t(const Ctx *c, const RowMap &rm, int rows, int inverse, 
     }
 }
 
-int launch_ntt(const Ctx *c, const RowMap &rm, int inverse, hipStream_t s) {
+static int launch_mont(const Ctx *c, const RowMap &rm, int to, hipStream_t s);
+
+int launch_ntt(const Ctx *c, const RowMap &rm, int inverse, hipStream_t s, bool to_mont) {
+    RowMap none{};
+    return launch_ntt_from(c, rm, none, inverse, s, to_mont);
+}
+
+int launch_ntt_from(const Ctx *c, const RowMap &rm, const RowMap &src, int inverse, hipStream_t s, bool to_mont) {
     int rows = rowmap_max_rows(rm);
     if (rows == 0 || rm.n_ct == 0) return FHELIN_OK;
+    if (src.base && c->log_n <= 12) {
+        // one-pass sizes: copy, then transform in place
+        FL_RET(launch_copy_rows(c, rm, src, s));
+        RowMap none{};
+        return launch_ntt_from(c, rm, none, inverse, s, to_mont);
+    }
+    // the two-pass forward transform converts in its last pass; the one-pass one is followed by a conversion
+    const bool fused = to_mont && !inverse && c->log_n > 12;
     switch (c->log_n) {
-    case 10: launch_ntt_t<10>(c, rm, rows, inverse, s); break;
-    case 11: launch_ntt_t<11>(c, rm, rows, inverse, s); break;
-    case 12: launch_ntt_t<12>(c, rm, rows, inverse, s); break;
-    case 13: launch_ntt_t<13>(c, rm, rows, inverse, s); break;
-    case 14: launch_ntt_t<14>(c, rm, rows, inverse, s); break;
-    case 15: launch_ntt_t<15>(c, rm, rows, inverse, s); break;
-    case 16: launch_ntt_t<16>(c, rm, rows, inverse, s); break;
+    case 10: launch_ntt_t<10>(c, rm, src, rows, inverse, fused, s); break;
+    case 11: launch_ntt_t<11>(c, rm, src, rows, inverse, fused, s); break;
+    case 12: launch_ntt_t<12>(c, rm, src, rows, inverse, fused, s); break;
+    case 13: launch_ntt_t<13>(c, rm, src, rows, inverse, fused, s); break;
+    case 14: launch_ntt_t<14>(c, rm, src, rows, inverse, fused, s); break;
+    case 15: launch_ntt_t<15>(c, rm, src, rows, inverse, fused, s); break;
+    case 16: launch_ntt_t<16>(c, rm, src, rows, inverse, fused, s); break;
     default: return set_error(FHELIN_E_UNSUPPORTED_PARAM, "unsupported ring degree");
     }
     FL_TRY_HIP(hipGetLastError());
+    if (to_mont && !fused) return launch_mont(c, rm, 1, s);
     return FHELIN_OK;
 }
 

@@ -101,6 +101,7 @@ class Server:
         self.rejected = 0
         self.batches = 0
         self.evictions = 0
+        self.max_inflight = 0               # most batches on the device at once
 
     # -- protocol ----------------------------------------------------------
     def open_session(self, session: str, client: str):
@@ -192,6 +193,7 @@ class Server:
         self.live_bytes += nbytes
         self.inflight[stream] = _Slot(token, batch, out, nbytes, now, [(r.client, params) for r in batch])
         self.batches += 1
+        self.max_inflight = max(self.max_inflight, len(self.inflight))
         return True
 
     def _poll(self) -> int:
@@ -256,6 +258,7 @@ class Server:
             "p99_ms": float(np.percentile(lat, 99)),
             "mean_batch": float(np.mean([r.batch for r in ok])),
             "batches": self.batches,
+            "max_inflight": self.max_inflight,
             "key_evictions": self.evictions,
         }
 
