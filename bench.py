@@ -52,7 +52,7 @@ def parse():
                     help="requests per arrival rate in an extra serving run (default 0 = no serving run)")
     ap.add_argument("--serve-rates", type=str, default="20,100", help="Poisson arrival rates (req/s)")
     ap.add_argument("--serve-clients", type=int, default=32)
-    ap.add_argument("--serve-streams", type=str, default="4",
+    ap.add_argument("--serve-streams", type=str, default="2",
                     help="streams (batches in flight at once) of the continuous-batching server; a comma list "
                          "runs one server per value")
     ap.add_argument("--pmc-summary", type=str, default="",

@@ -465,6 +465,15 @@ __global__ void __launch_bounds__(256) k_ks_sum(Batch b, const ModConst *__restr
     }
 }
 
+// entries of more than one key set (several clients in one batch): the kernels then
+// give every wave / block a single entry, so each entry's key rows are prefetched like
+// a shared key set's instead of loaded one after another inside the loop
+static bool mixed_keys(const Batch &b) {
+    for (int t = 1; t < b.n; ++t)
+        if (b.key[t] != b.key[0] || b.key_level[t] != b.key_level[0]) return true;
+    return false;
+}
+
 int launch_ks_sum(const Ctx *c, const Batch &b, const KsSum &sum, const uint64_t *digits, int64_t digits_es,
                   const uint64_t *add, int64_t add_es, const uint64_t *init, int64_t init_es, uint64_t *u,
                   int64_t u_es, hipStream_t s) {
@@ -497,7 +506,17 @@ int launch_ks_sum(const Ctx *c, const Batch &b, const KsSum &sum, const uint64_t
 #define FL_KSUM(SM, MB, EG) hipLaunchKernelGGL((k_ks_sum<SM, MB, EG>), dim3(nxy * ((b.n + EG - 1) / EG)), dim3(256), 0, s, \
                                                b, c->d_mods, digits, digits_es, add, add_es, init, init_es, u, u_es, sum, \
                                                c->log_n, c->L, c->K, c->alpha, (b.n + EG - 1) / EG, nxy % 8 == 0)
-    if (c->small) {
+    if (mixed_keys(b)) {
+        if (c->small) {
+            if (n_digits <= 4) FL_KSUM(true, 4, 1);
+            else if (n_digits <= 8) FL_KSUM(true, 8, 1);
+            else FL_KSUM(true, 16, 1);
+        } else {
+            if (n_digits <= 4) FL_KSUM(false, 4, 1);
+            else if (n_digits <= 8) FL_KSUM(false, 8, 1);
+            else FL_KSUM(false, 16, 1);
+        }
+    } else if (c->small) {
         if (n_digits <= 4) FL_KSUM(true, 4, 8);
         else if (n_digits <= 8) FL_KSUM(true, 8, 4);
         else FL_KSUM(true, 16, 2);
@@ -553,20 +572,21 @@ static int launch_ks_inner_impl(const Ctx *c, const Batch &b, const uint64_t *di
 #define FL_KR(SM, MB, E) hipLaunchKernelGGL((k_ks_rot<SM, MB, E>), dim3(nxy * ((b.n + 4 * E - 1) / (4 * E))), dim3(256), \
                                             0, s, b, c->d_mods, c->d_moddown, digits, digits_es, u, u_es, add, r, c->log_n, \
                                             c->L, c->K, c->alpha, (b.n + 4 * E - 1) / (4 * E), nxy % 8 == 0)
+        const bool one = mixed_keys(b);
         if (c->small) {
-            if (n_digits <= 4) FL_KR(true, 4, 4);
-            else if (n_digits <= 8) FL_KR(true, 8, 2);
+            if (n_digits <= 4) { if (one) FL_KR(true, 4, 1); else FL_KR(true, 4, 4); }
+            else if (n_digits <= 8) { if (one) FL_KR(true, 8, 1); else FL_KR(true, 8, 2); }
             else FL_KR(true, 16, 1);
         } else {
-            if (n_digits <= 4) FL_KR(false, 4, 4);
-            else if (n_digits <= 8) FL_KR(false, 8, 2);
+            if (n_digits <= 4) { if (one) FL_KR(false, 4, 1); else FL_KR(false, 4, 4); }
+            else if (n_digits <= 8) { if (one) FL_KR(false, 8, 1); else FL_KR(false, 8, 2); }
             else FL_KR(false, 16, 1);
         }
 #undef FL_KR
         FL_TRY_HIP(hipGetLastError());
         return FHELIN_OK;
     }
-    if (eg < 1) eg = 1;
+    if (eg < 1 || mixed_keys(b)) eg = 1;
     dim3 grid(c->N / 256, c->L + c->K, (b.n + eg - 1) / eg);
 #define FL_KS(SM, MB) hipLaunchKernelGGL((k_ks_inner<SM, MB>), grid, dim3(256), 0, s, b, c->d_mods, c->d_moddown, \
                                          digits, digits_es, u, u_es, add, rot, c->log_n, c->L, c->K, c->alpha, eg)

@@ -13,7 +13,9 @@ The server side of the hybrid protocol (paper Sec. 3-4) as a serving system:
   workspace growth and missing key sets fit the HBM budget; otherwise the
   requests wait until in-flight work completes and frees memory.
 * Continuous batching.  Up to `streams` batches are in flight on separate
-  HIP streams.  Whenever a slot frees up, the oldest waiting request and every
+  HIP streams (two by default: one batch runs while the next is admitted and
+  launched; on MI355X four concurrent batches of N=2^16 convolutions ran at
+  less than half the throughput of two, each launch already filling the GPU).  Whenever a slot frees up, the oldest waiting request and every
   other waiting request for the same layer (any client, any level) form the
   next batch (at most `max_batch` requests), so requests that arrive while
   others run join the next launch and their work overlaps on the device.
@@ -85,7 +87,7 @@ class _Slot:
 class Server:
     """Request loop; see the module docstring."""
 
-    def __init__(self, executor, hbm_budget: int, streams: int = 4, max_batch: int = 64, clock=time.perf_counter):
+    def __init__(self, executor, hbm_budget: int, streams: int = 2, max_batch: int = 64, clock=time.perf_counter):
         self.ex = executor
         self.budget = int(hbm_budget)
         self.n_streams = streams
@@ -271,7 +273,7 @@ def poisson_timeline(rate: float, n: int, stream) -> np.ndarray:
 class GpuExecutor:
     """Executor over the fhelin C ABI (one context per parameter set)."""
 
-    def __init__(self, n_streams: int = 4, flags=None):
+    def __init__(self, n_streams: int = 2, flags=None):
         import torch
 
         from paper_2509_01253_amd import fhelin as F
