@@ -177,6 +177,8 @@ int ctx_create(const fhelin_params *prm, Ctx **out) {
     c->mods = mods;
     c->small = true;
     for (uint64_t q : mods) c->small = c->small && q < ((uint64_t)1 << 55);
+    c->ntt53 = true;
+    for (uint64_t q : mods) c->ntt53 = c->ntt53 && q < ((uint64_t)1 << 50);
     const int M = L + K, N = c->N;
 
     // per-modulus constants, roots and twiddles
@@ -208,9 +210,9 @@ int ctx_create(const fhelin_params *prm, Ctx **out) {
             uint32_t b = brv((uint32_t)k, c->log_n);
             size_t o = (size_t)m * N + k;
             tw[o] = pw[b];
-            twp[o] = h_shoup(pw[b], q);
+            twp[o] = c->ntt53 ? h_shoup53(pw[b], q) : h_shoup(pw[b], q);
             itw[o] = ipw[b];
-            itwp[o] = h_shoup(ipw[b], q);
+            itwp[o] = c->ntt53 ? h_shoup53(ipw[b], q) : h_shoup(ipw[b], q);
         }
     }
     FL_RET(upload(c.get(), &c->d_mods, c->h_mods));

@@ -4,14 +4,17 @@
 // Encoding (Cheon-Kim-Kim-Song 2017): m_k = round(Delta (2/N) Re sum_j z_j zeta^(-5^j k)),
 // zeta = exp(i pi / N).  Over all odd exponents e (z_j at 5^j, conj z_j at -5^j)
 // this is (Delta/N) Re(zeta^(-k) sum_t Z_t w^(-tk)) with e = 2t+1, w = exp(2 pi i/N):
-// one forward complex FFT of length N per plaintext (radix-2 Stockham, natural
-// order in and out).  Rounding is rint (ties to even).
+// one forward complex FFT of length N per plaintext: radix-2 decimation in time
+// (Cooley-Tukey 1965) on bit-reversed input, natural-order output, in two passes
+// through HBM with the butterflies of each pass in LDS (the stages inside 256-element
+// blocks, then the stages across them, column-wise).  Rounding is rint (ties to even).
 #include "internal.h"
 #include "modarith.h"
 
 namespace fl {
 
-// Z[p][(5^j-1)/2] = z_j, Z[p][(2N-5^j-1)/2] = z_j (real slots: conj z = z); every index once
+// Z[p][(5^j-1)/2] = z_j, Z[p][(2N-5^j-1)/2] = z_j (real slots: conj z = z); every index
+// once, stored at its bit-reversed position (the FFT's input order)
 __global__ void __launch_bounds__(256) k_encode_scatter(const double *__restrict__ slots, double2 *__restrict__ Z,
                                                         const int32_t *__restrict__ slot_idx, int log_n) {
     const int64_t N = (int64_t)1 << log_n, S = N / 2;
@@ -19,31 +22,72 @@ __global__ void __launch_bounds__(256) k_encode_scatter(const double *__restrict
     const int j = blockIdx.x * 256 + threadIdx.x;
     if (j >= S) return;
     double z = slots[(int64_t)p * S + j];
-    int t = slot_idx[j];
+    const uint32_t t = (uint32_t)slot_idx[j];
     double2 *zp = Z + (int64_t)p * N;
-    zp[t] = make_double2(z, 0.0);
-    zp[N - 1 - t] = make_double2(z, 0.0);
+    zp[__brev(t) >> (32 - log_n)] = make_double2(z, 0.0);
+    zp[__brev((uint32_t)(N - 1) - t) >> (32 - log_n)] = make_double2(z, 0.0);
 }
 
-// one radix-2 Stockham stage (Govindaraju et al. 2008 form), forward sign
-__global__ void __launch_bounds__(256) k_fft_stage(const double2 *__restrict__ in, double2 *__restrict__ out,
-                                                   const double *__restrict__ tw, int log_n, int log_ns) {
-    const int64_t N = (int64_t)1 << log_n, H = N / 2;
-    const int p = blockIdx.y;
-    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (j >= H) return;
-    const double2 *x = in + (int64_t)p * N;
-    double2 *y = out + (int64_t)p * N;
-    const int64_t ns = (int64_t)1 << log_ns;
-    const int64_t k = j & (ns - 1);
-    const double2 a = x[j], b = x[j + H];
-    // w = exp(-2 pi i k / (2 ns)) = table[k * N / (2 ns)]
-    const int64_t ti = k << (log_n - 1 - log_ns);
-    const double wr = tw[2 * ti], wi = tw[2 * ti + 1];
+// one decimation-in-time butterfly: (u, v) -> (u + w v, u - w v), w = exp(-2 pi i idx / N)
+__device__ __forceinline__ void dit_bfly(double2 *x, int i0, int i1, const double *__restrict__ tw, int64_t idx) {
+    const double wr = tw[2 * idx], wi = tw[2 * idx + 1];
+    const double2 a = x[i0], b = x[i1];
     const double br = b.x * wr - b.y * wi, bi = b.x * wi + b.y * wr;
-    const int64_t o = ((j >> log_ns) << (log_ns + 1)) + k;
-    y[o] = make_double2(a.x + br, a.y + bi);
-    y[o + ns] = make_double2(a.x - br, a.y - bi);
+    x[i0] = make_double2(a.x + br, a.y + bi);
+    x[i1] = make_double2(a.x - br, a.y - bi);
+}
+
+constexpr int FFT_TILE = 1024;   // complex elements per workgroup of the first pass (16 KiB of LDS)
+constexpr int FFT_CTILE = 2048;  // at most, of the second (32 KiB): 8 columns of 128 bytes at N = 2^16
+
+// columns per workgroup of the second pass
+__host__ __device__ inline int fft_cols(int log_n) {
+    const int c = FFT_CTILE >> (log_n - 8);
+    return c < 256 ? c : 256;
+}
+
+// pass 1: stages m = 2 .. 256 inside each contiguous 256-element block; grid (N / 1024, n)
+__global__ void __launch_bounds__(256) k_fft_rows(double2 *__restrict__ A, const double *__restrict__ tw, int log_n) {
+    __shared__ double2 x[FFT_TILE];
+    const int64_t N = (int64_t)1 << log_n;
+    double2 *a = A + (int64_t)blockIdx.y * N + (int64_t)blockIdx.x * FFT_TILE;
+    for (int e = threadIdx.x; e < FFT_TILE; e += 256) x[e] = a[e];
+    __syncthreads();
+    for (int lm = 1; lm <= 8; ++lm) {
+        const int half = 1 << (lm - 1);
+        for (int b = threadIdx.x; b < FFT_TILE / 2; b += 256) {
+            const int jj = b & (half - 1), i0 = ((b >> (lm - 1)) << lm) + jj;
+            dit_bfly(x, i0, i0 + half, tw, (int64_t)jj << (log_n - lm));
+        }
+        __syncthreads();
+    }
+    for (int e = threadIdx.x; e < FFT_TILE; e += 256) a[e] = x[e];
+}
+
+// pass 2: stages m = 512 .. N across the blocks: element c + 256 r is row r of column
+// c; a workgroup transforms fft_cols adjacent columns of N1 = N / 256 rows, each a
+// DIT FFT over r whose twiddles also depend on c; grid (256 / columns, n)
+__global__ void __launch_bounds__(256) k_fft_cols(double2 *__restrict__ A, const double *__restrict__ tw, int log_n) {
+    __shared__ double2 x[FFT_CTILE];
+    const int64_t N = (int64_t)1 << log_n;
+    const int log_n1 = log_n - 8, cols = fft_cols(log_n), tile = cols << log_n1;
+    const int c0 = blockIdx.x * cols;
+    double2 *a = A + (int64_t)blockIdx.y * N + c0;
+    // LDS element (r, cc) at r * cols + cc: consecutive threads read consecutive columns
+    for (int e = threadIdx.x; e < tile; e += 256) x[e] = a[(int64_t)(e / cols) * 256 + e % cols];
+    __syncthreads();
+    for (int lm = 1; lm <= log_n1; ++lm) {
+        const int half = 1 << (lm - 1);
+        for (int b = threadIdx.x; b < tile / 2; b += 256) {
+            const int cc = b % cols, rb = b / cols;
+            const int jj = rb & (half - 1), r0 = ((rb >> (lm - 1)) << lm) + jj;
+            // exp(-2 pi i (c + 256 jj) / (256 m)), m = 2^lm
+            const int64_t idx = ((int64_t)(c0 + cc) + 256 * (int64_t)jj) << (log_n1 - lm);
+            dit_bfly(x, r0 * cols + cc, (r0 + half) * cols + cc, tw, idx);
+        }
+        __syncthreads();
+    }
+    for (int e = threadIdx.x; e < tile; e += 256) a[(int64_t)(e / cols) * 256 + e % cols] = x[e];
 }
 
 // m_k = rint(scale/N * Re(X_k zeta^-k)); residues mod q_0..q_{level-1}, p_0..p_{K-1}
@@ -211,15 +255,14 @@ int pt_export(Ctx *c, const PtSet *p, int level, uint64_t *dst, hipStream_t s) {
 static int encode_into(Ctx *c, const double *slots, int n, int level, double scale, uint64_t *dst, hipStream_t s) {
     const int64_t N = c->N;
     uint64_t *ws;
-    FL_RET(workspace_get(c, s, (size_t)n * N * 2 * sizeof(double2), &ws));
-    double2 *a = (double2 *)ws, *b = a + (int64_t)n * N;
+    FL_RET(workspace_get(c, s, (size_t)n * N * sizeof(double2), &ws));
+    double2 *a = (double2 *)ws;
     hipLaunchKernelGGL(k_encode_scatter, dim3((unsigned)(N / 2 + 255) / 256, n), dim3(256), 0, s, slots, a,
                        c->d_slot_idx, c->log_n);
-    for (int ls = 0; ls < c->log_n; ++ls) {
-        hipLaunchKernelGGL(k_fft_stage, dim3((unsigned)(N / 2 + 255) / 256, n), dim3(256), 0, s, a, b, c->d_fft_tw,
-                           c->log_n, ls);
-        std::swap(a, b);
-    }
+    // N >= 2^10: 256-element blocks, then the 256 columns of N / 256 rows
+    hipLaunchKernelGGL(k_fft_rows, dim3((unsigned)(N / FFT_TILE), n), dim3(256), 0, s, a, c->d_fft_tw, c->log_n);
+    hipLaunchKernelGGL(k_fft_cols, dim3((unsigned)(256 / fft_cols(c->log_n)), n), dim3(256), 0, s, a, c->d_fft_tw,
+                       c->log_n);
     hipLaunchKernelGGL(k_encode_finish, dim3((unsigned)N / 256, n), dim3(256), 0, s, a, dst, c->d_mods, c->d_zeta,
                        level, c->L, c->K, scale, c->log_n);
     FL_TRY_HIP(hipGetLastError());

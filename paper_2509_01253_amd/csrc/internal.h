@@ -112,6 +112,7 @@ struct Ctx {
     int device = 0;
     int log_n = 0, N = 0, L = 0, K = 0, dnum = 0, alpha = 0;
     bool small = false;              // every modulus < 2^55: cheaper lazy accumulation
+    bool ntt53 = false;              // every modulus < 2^50: NTT twiddle companions floor(w 2^53 / q)
     std::vector<uint64_t> mods;      // q_0..q_{L-1}, p_0..p_{K-1}
     std::vector<uint64_t> psi;       // minimal primitive 2N-th root per modulus
     std::vector<ModConst> h_mods;

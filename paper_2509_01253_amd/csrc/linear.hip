@@ -100,8 +100,8 @@ struct MacArgs {
 // (zero past the last request), so the inner loop has no branches.  Requests go in
 // descending level order, so the requests a q slot exists for are a prefix and
 // the rest are skipped.  Operands are in the accumulator's form (28-bit halves
-// when every modulus is below 2^55, else plain); each 16-term chunk ends in one
-// Montgomery reduction that seeds the next chunk.
+// when every modulus is below 2^55, else plain); every 32 terms (16 with larger
+// moduli) end in one Montgomery reduction that seeds the next ones.
 constexpr int MAC_K = 16;   // coefficients per workgroup
 constexpr int MAC_TB = 16;  // terms per chunk
 constexpr int MAC_ET = 8;   // requests per group at most
@@ -251,10 +251,14 @@ __global__ void __launch_bounds__(256) k_mac(MacArgs a, Batch b, const ModConst 
                 } else {
                     compute(pv[0]);
                 }
+                // reduce after every LazyAcc<SMALL>::TERMS products and at the end
+                if ((t0 / MAC_TB) % (LazyAcc<SMALL>::TERMS / MAC_TB) == LazyAcc<SMALL>::TERMS / MAC_TB - 1 ||
+                    t0 + MAC_TB >= terms) {
 #pragma unroll
-                for (int m = 0; m < MY; ++m)
+                    for (int m = 0; m < MY; ++m)
 #pragma unroll
-                    for (int p = 0; p < 2; ++p) acc[m][p].set(acc[m][p].reduce(mc.q, mc.mont_neg_inv));
+                        for (int p = 0; p < 2; ++p) acc[m][p].set(acc[m][p].reduce(mc.q, mc.mont_neg_inv));
+                }
             }
             if (computes && j < a.G) {
 #pragma unroll

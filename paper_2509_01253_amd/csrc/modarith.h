@@ -23,6 +23,24 @@ __device__ __forceinline__ uint64_t shoup_lazy(uint64_t a, uint64_t w, uint64_t 
     return a * w - h * q;
 }
 
+// a * w mod q in [0, 2q) for a < 2^52 and w < q < 2^50, with the companion of
+// v = floor(w 2^53 / q) < 2^53 stored as (ph << 11) 2^32 + pl (v = ph 2^32 + pl, ph < 2^21).
+// With a = ah 2^32 + al (ah < 2^20) and m = hi32(al pl) + ah pl + al ph < 2^54, the
+// estimate (ah ph) 2^11 + floor(m / 2^21) drops only the low word of al pl, so it is
+// floor(a v / 2^53) or one less; floor(a v / 2^53) is floor(a w / q) or one less since
+// a / 2^53 < 1/2.  The estimate is floor(a w / q) or one less -- the 64-bit form's
+// [0, 2q) -- from four 32-bit multiplies (the pre-shifted ph makes the last one a
+// multiply-add).
+__device__ __forceinline__ uint64_t shoup53_lazy(uint64_t a, uint64_t w, uint64_t wp, uint64_t q) {
+    const uint32_t al = (uint32_t)a, ah = (uint32_t)(a >> 32);
+    const uint32_t pl = (uint32_t)wp, ph11 = (uint32_t)(wp >> 32), ph = ph11 >> 11;
+    uint64_t m = __umulhi(al, pl);
+    m += (uint64_t)ah * pl;
+    m += (uint64_t)al * ph;
+    const uint64_t qe = (uint64_t)ah * ph11 + (m >> 21);
+    return a * w - qe * q;
+}
+
 __device__ __forceinline__ uint64_t csub(uint64_t a, uint64_t q) { return a >= q ? a - q : a; }
 
 __device__ __forceinline__ uint64_t shoup(uint64_t a, uint64_t w, uint64_t wp, uint64_t q) {
@@ -68,13 +86,14 @@ __device__ __forceinline__ uint64_t redc_wide(uint64_t lo, uint64_t hi, uint64_t
     return csub(csub(t, 2 * q), q);
 }
 
-// Lazy sums of up to 16 products a*b, Montgomery-reduced at the end.
+// Lazy sums of up to TERMS products a*b, Montgomery-reduced at the end.
 //
 // Small moduli (every q < 2^55): operands are split once into 28-bit halves packed in
 // one word, pack28(a) = a0 | a1 << 32 with a = a0 + a1 2^28.  Then
 //   a b = a0 b0 + (a0 b1 + a1 b0) 2^28 + a1 b1 2^56
-// and every partial product is below 2^55, so three 64-bit sums take 16 products
-// without carries: four 32x32->64 multiply-adds per product and nothing else.
+// and every partial product is below 2^56 (a1 b1 below 2^54), so three 64-bit sums
+// take 32 products without carries (s0 < 2^61, s1 < 2^62, s2 < 2^59 plus a restart
+// value below 2^63): four 32x32->64 multiply-adds per product and nothing else.
 // A reduced value v < q restarts a sum at v 2^64 (v 2^8 in the 2^56 sum; below 2^63).
 __device__ __forceinline__ uint64_t pack28(uint64_t a) {
     return (a & 0xFFFFFFFull) | ((a >> 28) << 32);
@@ -106,16 +125,18 @@ __device__ __forceinline__ uint64_t redc28(const Acc28 &A, uint64_t q, uint64_t 
     return redc_wide(lo2, hi, q, ninv);
 }
 
-// A 16-term lazy accumulator over either representation: SMALL (all moduli < 2^55)
-// uses Acc28 on packed operands, otherwise full 128-bit products on plain operands.
-// prep(x) puts an operand in the form mac() takes.  set(v) restarts the sum at v 2^64
-// for a reduced v < q, so the Montgomery reduction of (v 2^64 + 16 products) < 2q 2^64
-// (16 q < 2^64) returns v + (products) 2^-64 mod q; value() reads v back after set().
+// A TERMS-term lazy accumulator over either representation: SMALL (all moduli < 2^55)
+// uses Acc28 on packed operands (32 terms), otherwise full 128-bit products on plain
+// operands (16 terms, moduli < 2^60).  prep(x) puts an operand in the form mac()
+// takes.  set(v) restarts the sum at v 2^64 for a reduced v < q, so the Montgomery
+// reduction of (v 2^64 + TERMS products) < 2q 2^64 (TERMS q < 2^64) returns
+// v + (products) 2^-64 mod q; value() reads v back after set().
 template <bool SMALL>
 struct LazyAcc;
 
 template <>
 struct LazyAcc<true> {
+    static constexpr int TERMS = 32;
     Acc28 a;
     __device__ __forceinline__ static uint64_t prep(uint64_t x) { return pack28(x); }
     __device__ __forceinline__ void zero() { a = Acc28{0, 0, 0}; }
@@ -127,6 +148,7 @@ struct LazyAcc<true> {
 
 template <>
 struct LazyAcc<false> {
+    static constexpr int TERMS = 16;
     Acc128 a;
     __device__ __forceinline__ static uint64_t prep(uint64_t x) { return x; }
     __device__ __forceinline__ void zero() { a = Acc128{0, 0}; }
@@ -154,6 +176,10 @@ inline uint64_t h_powmod(uint64_t a, uint64_t e, uint64_t q) {
 }
 inline uint64_t h_invmod(uint64_t a, uint64_t q) { return h_powmod(a % q, q - 2, q); }  // q prime
 inline uint64_t h_shoup(uint64_t w, uint64_t q) { return (uint64_t)(((u128)w << 64) / q); }
+inline uint64_t h_shoup53(uint64_t w, uint64_t q) {
+    const uint64_t v = (uint64_t)(((u128)w << 53) / q);  // < 2^53 for w < q
+    return ((v >> 32) << 43) | (v & 0xffffffffu);         // high word pre-shifted by 11
+}
 inline uint64_t h_to_mont(uint64_t a, uint64_t q) { return (uint64_t)(((u128)(a % q) << 64) % q); }
 inline uint64_t h_neg_inv64(uint64_t q) {
     // Newton iteration for q^-1 mod 2^64 (q odd), then negate

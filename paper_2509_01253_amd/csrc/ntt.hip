@@ -43,22 +43,31 @@ __device__ __forceinline__ const uint64_t *src_row(const RowMap &src, const uint
     return src.base + off;
 }
 
+// twiddle products: F53 (every modulus < 2^50) takes the 53-bit companions
+template <bool F53>
+__device__ __forceinline__ uint64_t tw_mul(uint64_t a, uint64_t w, uint64_t wp, uint64_t q) {
+    if constexpr (F53) return shoup53_lazy(a, w, wp, q);
+    else return shoup_lazy(a, w, wp, q);
+}
+
 // forward CT butterfly, lazy: X, Y in [0, 4q) -> [0, 4q)
+template <bool F53>
 __device__ __forceinline__ void ct_bfly(uint64_t &X, uint64_t &Y, uint64_t w, uint64_t wp, uint64_t q) {
     uint64_t q2 = 2 * q;
     uint64_t x = X >= q2 ? X - q2 : X;
-    uint64_t t = shoup_lazy(Y, w, wp, q);
+    uint64_t t = tw_mul<F53>(Y, w, wp, q);
     X = x + t;
     Y = x - t + q2;
 }
 
 // inverse GS butterfly, lazy: U, V in [0, 2q) -> [0, 2q)
+template <bool F53>
 __device__ __forceinline__ void gs_bfly(uint64_t &U, uint64_t &V, uint64_t w, uint64_t wp, uint64_t q) {
     uint64_t q2 = 2 * q;
     uint64_t u = U, v = V;
     uint64_t s = u + v;
     U = s >= q2 ? s - q2 : s;
-    V = shoup_lazy(u - v + q2, w, wp, q);
+    V = tw_mul<F53>(u - v + q2, w, wp, q);
 }
 
 __device__ __forceinline__ uint64_t reduce4q(uint64_t x, uint64_t q) {
@@ -70,7 +79,7 @@ __device__ __forceinline__ uint64_t reduce4q(uint64_t x, uint64_t q) {
 // ---------------------------------------------------------------------------
 // single pass (N <= 4096)
 // ---------------------------------------------------------------------------
-template <int LOGN>
+template <int LOGN, bool F53>
 __global__ void __launch_bounds__(NTT_THREADS) k_ntt_fwd_1(RowMap rm, const ModConst *__restrict__ mods,
                                                            const uint64_t *__restrict__ tw,
                                                            const uint64_t *__restrict__ twp) {
@@ -89,7 +98,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_ntt_fwd_1(RowMap rm, const ModC
             int i = b >> lt;
             int j = (i << (lt + 1)) + (b & (t - 1));
             uint64_t X = s[j], Y = s[j + t];
-            ct_bfly(X, Y, w[m + i], wp[m + i], q);
+            ct_bfly<F53>(X, Y, w[m + i], wp[m + i], q);
             s[j] = X;
             s[j + t] = Y;
         }
@@ -98,7 +107,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_ntt_fwd_1(RowMap rm, const ModC
     for (int e = threadIdx.x; e < N; e += NTT_THREADS) x[e] = reduce4q(s[e], q);
 }
 
-template <int LOGN>
+template <int LOGN, bool F53>
 __global__ void __launch_bounds__(NTT_THREADS) k_ntt_inv_1(RowMap rm, const ModConst *__restrict__ mods,
                                                            const uint64_t *__restrict__ itw,
                                                            const uint64_t *__restrict__ itwp) {
@@ -118,7 +127,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_ntt_inv_1(RowMap rm, const ModC
             int i = b >> lt;
             int j = (i << (lt + 1)) + (b & (t - 1));
             uint64_t U = s[j], V = s[j + t];
-            gs_bfly(U, V, w[m + i], wp[m + i], q);
+            gs_bfly<F53>(U, V, w[m + i], wp[m + i], q);
             s[j] = U;
             s[j + t] = V;
         }
@@ -185,7 +194,7 @@ __device__ __forceinline__ void tw_load_b(Tw &t, int64_t base, const uint64_t *_
     }
 }
 
-template <int S>
+template <int S, bool F53>
 __device__ __forceinline__ void fwd_round_a(uint64_t (&X)[16], const Tw &t, uint64_t q) {
     int k = 0;
 #pragma unroll
@@ -194,11 +203,11 @@ __device__ __forceinline__ void fwd_round_a(uint64_t (&X)[16], const Tw &t, uint
 #pragma unroll
         for (int g = 0; g < 8 / h; ++g, ++k)
 #pragma unroll
-            for (int v = 0; v < h; ++v) ct_bfly(X[g * 2 * h + v], X[g * 2 * h + v + h], t.w[k], t.wp[k], q);
+            for (int v = 0; v < h; ++v) ct_bfly<F53>(X[g * 2 * h + v], X[g * 2 * h + v + h], t.w[k], t.wp[k], q);
     }
 }
 
-template <int S>
+template <int S, bool F53>
 __device__ __forceinline__ void fwd_round_b(uint64_t (&X)[16], const Tw &t, uint64_t q) {
     int k = 0;
 #pragma unroll
@@ -207,12 +216,12 @@ __device__ __forceinline__ void fwd_round_b(uint64_t (&X)[16], const Tw &t, uint
 #pragma unroll
         for (int g = 0; g < 8 / h; ++g, ++k)
 #pragma unroll
-            for (int v = 0; v < h; ++v) ct_bfly(X[g * 2 * h + v], X[g * 2 * h + v + h], t.w[k], t.wp[k], q);
+            for (int v = 0; v < h; ++v) ct_bfly<F53>(X[g * 2 * h + v], X[g * 2 * h + v + h], t.w[k], t.wp[k], q);
     }
 }
 
 // inverse rounds: stages in increasing distance
-template <int S>
+template <int S, bool F53>
 __device__ __forceinline__ void inv_round_b(uint64_t (&X)[16], const Tw &t, uint64_t q) {
     int k = 0;
 #pragma unroll
@@ -221,11 +230,11 @@ __device__ __forceinline__ void inv_round_b(uint64_t (&X)[16], const Tw &t, uint
 #pragma unroll
         for (int g = 0; g < 8 / h; ++g, ++k)
 #pragma unroll
-            for (int v = 0; v < h; ++v) gs_bfly(X[g * 2 * h + v], X[g * 2 * h + v + h], t.w[k], t.wp[k], q);
+            for (int v = 0; v < h; ++v) gs_bfly<F53>(X[g * 2 * h + v], X[g * 2 * h + v + h], t.w[k], t.wp[k], q);
     }
 }
 
-template <int S>
+template <int S, bool F53>
 __device__ __forceinline__ void inv_round_a(uint64_t (&X)[16], const Tw &t, uint64_t q) {
     int k = 0;
 #pragma unroll
@@ -234,12 +243,12 @@ __device__ __forceinline__ void inv_round_a(uint64_t (&X)[16], const Tw &t, uint
 #pragma unroll
         for (int g = 0; g < 8 / h; ++g, ++k)
 #pragma unroll
-            for (int v = 0; v < h; ++v) gs_bfly(X[g * 2 * h + v], X[g * 2 * h + v + h], t.w[k], t.wp[k], q);
+            for (int v = 0; v < h; ++v) gs_bfly<F53>(X[g * 2 * h + v], X[g * 2 * h + v + h], t.w[k], t.wp[k], q);
     }
 }
 
 // forward pass 1: stages with distance >= 256 on columns c + 256 rho, rho < N1 = 2^S
-template <int LOGN>
+template <int LOGN, bool F53>
 __global__ void __launch_bounds__(NTT_THREADS) k_ntt_fwd_cols(RowMap rm, RowMap src,
                                                               const ModConst *__restrict__ mods,
                                                               const uint64_t *__restrict__ tw,
@@ -261,7 +270,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_ntt_fwd_cols(RowMap rm, RowMap 
     {
         Tw ta;
         tw_load_a<S, true>(ta, 1 << S, w, wp);
-        fwd_round_a<S>(X, ta, q);
+        fwd_round_a<S, F53>(X, ta, q);
     }
     Tw tb;
     tw_load_b<S, true>(tb, (1 << S) + 16 * r, w, wp);
@@ -270,14 +279,14 @@ __global__ void __launch_bounds__(NTT_THREADS) k_ntt_fwd_cols(RowMap rm, RowMap 
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < 16; ++u) X[u] = s[(16 * r + u) * CP + c];
-    fwd_round_b<S>(X, tb, q);
+    fwd_round_b<S, F53>(X, tb, q);
 #pragma unroll
     for (int u = 0; u < 16; ++u) xc[256 * (16 * r + u)] = X[u];  // lazy [0, 4q)
 }
 
 // forward pass 2: the last 8 stages inside contiguous 256-blocks; 16 blocks per workgroup;
 // MONT: outputs in Montgomery form (one Shoup product by 2^64 mod q replaces the final reduction)
-template <int LOGN, bool MONT>
+template <int LOGN, bool MONT, bool F53>
 __global__ void __launch_bounds__(NTT_THREADS) k_ntt_fwd_rows(RowMap rm, const ModConst *__restrict__ mods,
                                                               const uint64_t *__restrict__ tw,
                                                               const uint64_t *__restrict__ twp) {
@@ -298,7 +307,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_ntt_fwd_rows(RowMap rm, const M
     {
         Tw ta;
         tw_load_a<8, true>(ta, base, w, wp);
-        fwd_round_a<8>(X, ta, q);
+        fwd_round_a<8, F53>(X, ta, q);
     }
     Tw tb;
     tw_load_b<8, true>(tb, base + 16 * r, w, wp);
@@ -308,7 +317,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_ntt_fwd_rows(RowMap rm, const M
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < 16; ++u) X[u] = sb[17 * r + u];
-    fwd_round_b<8>(X, tb, q);
+    fwd_round_b<8, F53>(X, tb, q);
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
         if constexpr (MONT) sb[17 * r + u] = shoup(X[u], mods[mi].r1, mods[mi].r1_sh, q);
@@ -319,7 +328,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_ntt_fwd_rows(RowMap rm, const M
 }
 
 // inverse pass 1: the first 8 stages (distance 1 .. 128) inside contiguous 256-blocks
-template <int LOGN>
+template <int LOGN, bool F53>
 __global__ void __launch_bounds__(NTT_THREADS) k_ntt_inv_rows(RowMap rm, RowMap src,
                                                               const ModConst *__restrict__ mods,
                                                               const uint64_t *__restrict__ itw,
@@ -345,7 +354,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_ntt_inv_rows(RowMap rm, RowMap 
         __syncthreads();
 #pragma unroll
         for (int u = 0; u < 16; ++u) X[u] = s[blk * BS + 17 * r + u];
-        inv_round_b<8>(X, tb, q);
+        inv_round_b<8, F53>(X, tb, q);
     }
     Tw ta;
     tw_load_a<8, false>(ta, base, w, wp);
@@ -355,13 +364,13 @@ __global__ void __launch_bounds__(NTT_THREADS) k_ntt_inv_rows(RowMap rm, RowMap 
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < 16; ++u) X[u] = sb[r + 17 * u];
-    inv_round_a<8>(X, ta, q);
+    inv_round_a<8, F53>(X, ta, q);
 #pragma unroll
     for (int u = 0; u < 16; ++u) xt[blk * 256 + r + 16 * u] = X[u];  // lazy [0, 2q)
 }
 
 // inverse pass 2: stages with distance >= 256 on columns, then N^{-1}
-template <int LOGN>
+template <int LOGN, bool F53>
 __global__ void __launch_bounds__(NTT_THREADS) k_ntt_inv_cols(RowMap rm, const ModConst *__restrict__ mods,
                                                               const uint64_t *__restrict__ itw,
                                                               const uint64_t *__restrict__ itwp) {
@@ -381,7 +390,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_ntt_inv_cols(RowMap rm, const M
     {
         Tw tb;
         tw_load_b<S, false>(tb, (1 << S) + 16 * r, w, wp);
-        inv_round_b<S>(X, tb, q);
+        inv_round_b<S, F53>(X, tb, q);
     }
     Tw ta;
     tw_load_a<S, false>(ta, 1 << S, w, wp);
@@ -390,7 +399,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_ntt_inv_cols(RowMap rm, const M
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < 16; ++u) X[u] = s[(r + T * u) * CP + c];
-    inv_round_a<S>(X, ta, q);
+    inv_round_a<S, F53>(X, ta, q);
 #pragma unroll
     for (int u = 0; u < 16; ++u) xc[256 * (r + T * u)] = shoup(X[u], mc.ninv, mc.ninv_sh, q);
 }
@@ -410,7 +419,7 @@ __global__ void __launch_bounds__(256) k_to_mont(RowMap rm, const ModConst *__re
     }
 }
 
-template <int LOGN>
+template <int LOGN, bool F53>
 static void launch_ntt_t(const Ctx *c, const RowMap &rm, const RowMap &src, int rows, int inverse, bool to_mont,
                          hipStream_t s) {
     const int M = 1 << LOGN;
@@ -422,11 +431,11 @@ static void launch_ntt_t(const Ctx *c, const RowMap &rm, const RowMap &src, int 
         dim3 g(1, rows, rm.n_ct);
         if (!inverse) {
             ProfScope ps(c, s, PK_NTT_FWD_1, bfly_per_stage * LOGN, row_bytes);
-            hipLaunchKernelGGL(k_ntt_fwd_1<(LOGN <= 12 ? LOGN : 12)>, g, dim3(NTT_THREADS), 0, s, rm, c->d_mods, c->d_tw,
+            hipLaunchKernelGGL((k_ntt_fwd_1<(LOGN <= 12 ? LOGN : 12), F53>), g, dim3(NTT_THREADS), 0, s, rm, c->d_mods, c->d_tw,
                                c->d_twp);
         } else {
             ProfScope ps(c, s, PK_NTT_INV_1, bfly_per_stage * LOGN, row_bytes);
-            hipLaunchKernelGGL(k_ntt_inv_1<(LOGN <= 12 ? LOGN : 12)>, g, dim3(NTT_THREADS), 0, s, rm, c->d_mods, c->d_itw,
+            hipLaunchKernelGGL((k_ntt_inv_1<(LOGN <= 12 ? LOGN : 12), F53>), g, dim3(NTT_THREADS), 0, s, rm, c->d_mods, c->d_itw,
                                c->d_itwp);
         }
     } else {
@@ -435,23 +444,23 @@ static void launch_ntt_t(const Ctx *c, const RowMap &rm, const RowMap &src, int 
         if (!inverse) {
             {
                 ProfScope ps(c, s, PK_NTT_FWD_COLS, bfly_per_stage * (LOGN - 8), row_bytes);
-                hipLaunchKernelGGL(k_ntt_fwd_cols<L2>, g, dim3(NTT_THREADS), 0, s, rm, src, c->d_mods, c->d_tw,
+                hipLaunchKernelGGL((k_ntt_fwd_cols<L2, F53>), g, dim3(NTT_THREADS), 0, s, rm, src, c->d_mods, c->d_tw,
                                    c->d_twp);
             }
             ProfScope ps(c, s, PK_NTT_FWD_ROWS, bfly_per_stage * 8, row_bytes);
             if (to_mont)
-                hipLaunchKernelGGL((k_ntt_fwd_rows<L2, true>), g, dim3(NTT_THREADS), 0, s, rm, c->d_mods, c->d_tw, c->d_twp);
+                hipLaunchKernelGGL((k_ntt_fwd_rows<L2, true, F53>), g, dim3(NTT_THREADS), 0, s, rm, c->d_mods, c->d_tw, c->d_twp);
             else
-                hipLaunchKernelGGL((k_ntt_fwd_rows<L2, false>), g, dim3(NTT_THREADS), 0, s, rm, c->d_mods, c->d_tw,
+                hipLaunchKernelGGL((k_ntt_fwd_rows<L2, false, F53>), g, dim3(NTT_THREADS), 0, s, rm, c->d_mods, c->d_tw,
                                    c->d_twp);
         } else {
             {
                 ProfScope ps(c, s, PK_NTT_INV_ROWS, bfly_per_stage * 8, row_bytes);
-                hipLaunchKernelGGL(k_ntt_inv_rows<L2>, g, dim3(NTT_THREADS), 0, s, rm, src, c->d_mods, c->d_itw,
+                hipLaunchKernelGGL((k_ntt_inv_rows<L2, F53>), g, dim3(NTT_THREADS), 0, s, rm, src, c->d_mods, c->d_itw,
                                    c->d_itwp);
             }
             ProfScope ps(c, s, PK_NTT_INV_COLS, bfly_per_stage * (LOGN - 8), row_bytes);
-            hipLaunchKernelGGL(k_ntt_inv_cols<L2>, g, dim3(NTT_THREADS), 0, s, rm, c->d_mods, c->d_itw, c->d_itwp);
+            hipLaunchKernelGGL((k_ntt_inv_cols<L2, F53>), g, dim3(NTT_THREADS), 0, s, rm, c->d_mods, c->d_itw, c->d_itwp);
         }
     }
 }
@@ -475,13 +484,20 @@ int launch_ntt_from(const Ctx *c, const RowMap &rm, const RowMap &src, int inver
     // the two-pass forward transform converts in its last pass; the one-pass one is followed by a conversion
     const bool fused = to_mont && !inverse && c->log_n > 12;
     switch (c->log_n) {
-    case 10: launch_ntt_t<10>(c, rm, src, rows, inverse, fused, s); break;
-    case 11: launch_ntt_t<11>(c, rm, src, rows, inverse, fused, s); break;
-    case 12: launch_ntt_t<12>(c, rm, src, rows, inverse, fused, s); break;
-    case 13: launch_ntt_t<13>(c, rm, src, rows, inverse, fused, s); break;
-    case 14: launch_ntt_t<14>(c, rm, src, rows, inverse, fused, s); break;
-    case 15: launch_ntt_t<15>(c, rm, src, rows, inverse, fused, s); break;
-    case 16: launch_ntt_t<16>(c, rm, src, rows, inverse, fused, s); break;
+    case 10: c->ntt53 ? launch_ntt_t<10, true>(c, rm, src, rows, inverse, fused, s)
+                      : launch_ntt_t<10, false>(c, rm, src, rows, inverse, fused, s); break;
+    case 11: c->ntt53 ? launch_ntt_t<11, true>(c, rm, src, rows, inverse, fused, s)
+                      : launch_ntt_t<11, false>(c, rm, src, rows, inverse, fused, s); break;
+    case 12: c->ntt53 ? launch_ntt_t<12, true>(c, rm, src, rows, inverse, fused, s)
+                      : launch_ntt_t<12, false>(c, rm, src, rows, inverse, fused, s); break;
+    case 13: c->ntt53 ? launch_ntt_t<13, true>(c, rm, src, rows, inverse, fused, s)
+                      : launch_ntt_t<13, false>(c, rm, src, rows, inverse, fused, s); break;
+    case 14: c->ntt53 ? launch_ntt_t<14, true>(c, rm, src, rows, inverse, fused, s)
+                      : launch_ntt_t<14, false>(c, rm, src, rows, inverse, fused, s); break;
+    case 15: c->ntt53 ? launch_ntt_t<15, true>(c, rm, src, rows, inverse, fused, s)
+                      : launch_ntt_t<15, false>(c, rm, src, rows, inverse, fused, s); break;
+    case 16: c->ntt53 ? launch_ntt_t<16, true>(c, rm, src, rows, inverse, fused, s)
+                      : launch_ntt_t<16, false>(c, rm, src, rows, inverse, fused, s); break;
     default: return set_error(FHELIN_E_UNSUPPORTED_PARAM, "unsupported ring degree");
     }
     FL_TRY_HIP(hipGetLastError());

@@ -1,6 +1,6 @@
 """The library's device modular arithmetic (modarith.h) compiled for the host with
 g++ and checked against 128-bit integer arithmetic: Montgomery reduction of lazy
-sums of up to 16 products, restarted at a reduced value, for the packed 28-bit
+sums of up to 32 (packed) or 16 products, restarted at a reduced value, for the packed 28-bit
 accumulator (moduli below 2^55) and the 128-bit one, including operands next to q."""
 import os
 import subprocess
