@@ -52,6 +52,9 @@ def parse():
                     help="requests per arrival rate in an extra serving run (default 0 = no serving run)")
     ap.add_argument("--serve-rates", type=str, default="20,100", help="Poisson arrival rates (req/s)")
     ap.add_argument("--serve-clients", type=int, default=32)
+    ap.add_argument("--serve-reserve", type=int, default=64,
+                    help="requests per batch the serving executor sizes every stream's workspace for at start-up "
+                         "(0: grow on demand when a larger batch arrives)")
     ap.add_argument("--serve-streams", type=str, default="2",
                     help="streams (batches in flight at once) of the continuous-batching server; a comma list "
                          "runs one server per value")
@@ -210,7 +213,7 @@ def serve_bench(args) -> dict:
         "conv16": dict(params="N15", log_n=15, L=8, K=2, dnum=4, c=16, hw=32, lmin=2),
         "conv64": dict(params="N16", log_n=16, L=12, K=3, dnum=4, c=64, hw=64, lmin=2),
     }
-    ex = GpuExecutor(n_streams=max(int(k) for k in args.serve_streams.split(",")))
+    ex = GpuExecutor(n_streams=max(int(k) for k in args.serve_streams.split(",")), reserve_requests=args.serve_reserve)
     gen = torch.Generator(device=dev)
     gen.manual_seed(int(root.sub(synth.TAG_KEYS).u64(1)[0] & 0x7FFFFFFFFFFFFFFF))
     info = {}

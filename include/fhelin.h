@@ -227,6 +227,15 @@ int fhelin_linear_apply(fhelin_ctx *ctx, const fhelin_plan *plan, const fhelin_k
 int fhelin_plan_workspace_bytes(fhelin_ctx *ctx, const fhelin_plan *plan, int32_t n_requests, int32_t flags,
                                 uint64_t *bytes);
 
+/* Grow the stream's workspace now to what fhelin_linear_apply needs for
+ * n_requests requests of this plan with these flags (never shrinks it), so that
+ * later calls on the stream allocate nothing.  A grow synchronises the stream
+ * first; the memory is charged to the budget (FHELIN_E_BUDGET / FHELIN_E_OOM if it
+ * does not fit) and released by fhelin_ctx_trim or fhelin_ctx_destroy.  For
+ * schedulers that size memory up front instead of on the first large batch. */
+int fhelin_plan_reserve_workspace(fhelin_ctx *ctx, const fhelin_plan *plan, int32_t n_requests, int32_t flags,
+                                  void *stream);
+
 /* fhelin_linear_apply with one key set per request (ks_per_request[R], host
  * array; requests from different clients batched in one call).  Every key set
  * must belong to ctx and cover the plan's Galois elements at the request's

@@ -412,6 +412,17 @@ FHELIN_EXPORT int fhelin_plan_workspace_bytes(fhelin_ctx *ctx, const fhelin_plan
     API_END
 }
 
+FHELIN_EXPORT int fhelin_plan_reserve_workspace(fhelin_ctx *ctx, const fhelin_plan *plan, int32_t n_requests,
+                                                int32_t flags, void *stream) {
+    API_BEGIN FL_CHECK(ctx && plan && n_requests >= 0, FHELIN_E_INVALID_ARG, "null argument");
+    Ctx *c = (Ctx *)ctx;
+    DeviceGuard g(c);
+    uint64_t *ws = nullptr;
+    return workspace_get(c, (hipStream_t)stream,
+                         linear_workspace_bytes(c, (const Plan *)plan, n_requests, MAX_BATCH, flags), &ws);
+    API_END
+}
+
 FHELIN_EXPORT int fhelin_plan_get_tune(const fhelin_plan *plan, fhelin_tune *out) {
     API_BEGIN FL_CHECK(plan && out, FHELIN_E_INVALID_ARG, "null argument");
     const Tune &t = ((const Plan *)plan)->tune;

@@ -83,6 +83,7 @@ _SIGS = {
     "fhelin_linear_apply": [_vp, _vp, _vp, _vp, ctypes.POINTER(fhelin_ct_batch), ctypes.POINTER(fhelin_ct_batch),
                             _i32, _vp],
     "fhelin_plan_workspace_bytes": [_vp, _vp, _i32, _i32, ctypes.POINTER(_u64)],
+    "fhelin_plan_reserve_workspace": [_vp, _vp, _i32, _i32, _vp],
     "fhelin_linear_apply_multi": [_vp, _vp, _vp, _vp, ctypes.POINTER(fhelin_ct_batch),
                                   ctypes.POINTER(fhelin_ct_batch), _i32, _vp],
     "fhelin_rescale": [_vp, ctypes.POINTER(fhelin_ct_batch), ctypes.POINTER(fhelin_ct_batch), _vp],
@@ -308,6 +309,11 @@ def fhelin_plan_workspace_bytes(ctx, plan, n_requests: int, flags: int) -> int:
     v = _u64()
     _check(_lib.fhelin_plan_workspace_bytes(ctx, plan, n_requests, flags, ctypes.byref(v)))
     return int(v.value)
+
+
+def fhelin_plan_reserve_workspace(ctx, plan, n_requests: int, flags: int, stream=None) -> None:
+    """Grow the stream's workspace now for n_requests requests (no allocation later)."""
+    _check(_lib.fhelin_plan_reserve_workspace(ctx, plan, n_requests, flags, _stream(stream)))
 
 
 def fhelin_linear_apply_multi(ctx, plan, ks_per_request, pts, x: torch.Tensor, x_levels, y: torch.Tensor, y_levels,

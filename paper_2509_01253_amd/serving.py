@@ -104,6 +104,7 @@ class Server:
         self.batches = 0
         self.evictions = 0
         self.max_inflight = 0               # most batches on the device at once
+        self.batch_s = []                   # dispatch-to-completion time of every batch
 
     # -- protocol ----------------------------------------------------------
     def open_session(self, session: str, client: str):
@@ -204,6 +205,7 @@ class Server:
             if not self.ex.done(slot.token):
                 continue
             end = self.clock()
+            self.batch_s.append(end - slot.start)
             outs = self.ex.collect(slot.token, slot.out, slot.reqs)
             for r, (y, lvl) in zip(slot.reqs, outs):
                 self.results[r.rid] = Result(r.rid, "ok", y, lvl, r.arrival, slot.start, end, len(slot.reqs))
@@ -261,6 +263,8 @@ class Server:
             "mean_batch": float(np.mean([r.batch for r in ok])),
             "batches": self.batches,
             "max_inflight": self.max_inflight,
+            "batch_ms_p50": float(np.percentile(self.batch_s, 50) * 1e3) if self.batch_s else 0.0,
+            "batch_ms_max": float(max(self.batch_s) * 1e3) if self.batch_s else 0.0,
             "key_evictions": self.evictions,
         }
 
@@ -273,7 +277,7 @@ def poisson_timeline(rate: float, n: int, stream) -> np.ndarray:
 class GpuExecutor:
     """Executor over the fhelin C ABI (one context per parameter set)."""
 
-    def __init__(self, n_streams: int = 2, flags=None):
+    def __init__(self, n_streams: int = 2, flags=None, reserve_requests: int = 0):
         import torch
 
         from paper_2509_01253_amd import fhelin as F
@@ -286,6 +290,10 @@ class GpuExecutor:
         self.key_size = {}
         self.streams = [torch.cuda.Stream() for _ in range(n_streams)]
         self.ws = {}          # (params, stream) -> workspace bytes reserved so far
+        # > 0: every stream's workspace is grown at registration to a batch of this
+        # many requests of each layer, so no batch grows it (a grow synchronises the
+        # stream and allocates while requests wait)
+        self.reserve_requests = reserve_requests
 
     # registration
     def add_params(self, name, log_n, q, p, dnum):
@@ -298,6 +306,11 @@ class GpuExecutor:
         info = self.F.fhelin_plan_info(plan)
         self.layers[name] = dict(params=params, plan=plan, pts=pts, n_in=info["n_in"], n_out=info["n_out"],
                                  galois=self.F.fhelin_plan_galois(plan))
+        if self.reserve_requests > 0:
+            need = self.F.fhelin_plan_workspace_bytes(P["ctx"], plan, self.reserve_requests, self.flags)
+            for i, st in enumerate(self.streams):
+                self.F.fhelin_plan_reserve_workspace(P["ctx"], plan, self.reserve_requests, self.flags, stream=st)
+                self.ws[(params, i)] = max(self.ws.get((params, i), 0), need)
 
     def add_client_keys(self, client, params, source, nbytes):
         """source(stream) -> (galois list, level, evk tensor); nbytes = resident size."""

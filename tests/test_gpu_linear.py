@@ -472,3 +472,37 @@ def test_errors_reported(F):
         F.fhelin_plan_destroy(plan)
     finally:
         F.fhelin_ctx_destroy(ctx)
+
+
+def test_reserved_workspace_then_apply_allocates_nothing(F):
+    """fhelin_plan_reserve_workspace grows the stream's workspace to the plan's need
+    for a batch, after which a layer call of that size on the stream allocates
+    nothing and gives the same bits as the oracle."""
+    print("reserve workspace", flush=True)
+    prm = O.make_params(12, 6, 2, 3, 50, 2.0 ** 40)
+    st = synth.Stream(4600)
+    n, n1 = 64, 8
+    W = st.he_normal((n, n), n)
+    sched = O.fc_schedule(n, n1)
+    pts = encode_pts(prm, O.fc_slots(W, n, n1, prm.S), prm.L, prm.scale)
+    cl = Client(prm, 4601)
+    keys = cl.keyset(sched.rotations())
+    levels = [6, 3, 5]
+    cts = [cl.encrypt_slots(O.fc_input_slots(st.uniform(n, 0, 1), n, prm.S), l, prm.scale) for l in levels]
+    lay = Layer(F, prm, keys, pts, prm.L, fc_n=n, fc_out=n, fc_in=n, n1=n1)
+    try:
+        flags = F.FHELIN_APPLY_RESCALE | F.FHELIN_APPLY_HOIST_MODDOWN
+        need = F.fhelin_plan_workspace_bytes(lay.ctx, lay.plan, len(levels), flags)
+        m0 = F.fhelin_ctx_memory(lay.ctx)
+        F.fhelin_plan_reserve_workspace(lay.ctx, lay.plan, len(levels), flags)
+        m1 = F.fhelin_ctx_memory(lay.ctx)
+        assert m1 - m0 >= need > 0
+        F.fhelin_plan_reserve_workspace(lay.ctx, lay.plan, 1, flags)  # never shrinks
+        assert F.fhelin_ctx_memory(lay.ctx) == m1
+        got = lay.apply(cts, levels, stride=prm.L, dh=True)
+        assert F.fhelin_ctx_memory(lay.ctx) == m1
+        for t, l in enumerate(levels):
+            want = O.rescale(prm, O.linear(prm, cts[t][None], l, sched, pts, keys, hoist_moddown=True)[0], l)
+            assert np.array_equal(got[t], want), t
+    finally:
+        lay.close()
