@@ -349,11 +349,16 @@ __global__ void __launch_bounds__(NTT_THREADS) k_ntt_inv_rows(RowMap rm, RowMap 
     {
         Tw tb;
         tw_load_b<8, false>(tb, base + 16 * r, w, wp);
-        for (int e = threadIdx.x; e < TILE; e += NTT_THREADS)
-            s[(e >> 8) * BS + (e & 255) + ((e & 255) >> 4)] = xst[e];
-        __syncthreads();
+        // the thread's 16 contiguous inputs as eight 16-byte loads (measured faster
+        // than staging the tile through LDS; the forward pass's outputs, by contrast,
+        // are faster staged)
+        const ulonglong2 *in = reinterpret_cast<const ulonglong2 *>(xst + blk * 256 + 16 * r);
 #pragma unroll
-        for (int u = 0; u < 16; ++u) X[u] = s[blk * BS + 17 * r + u];
+        for (int u = 0; u < 8; ++u) {
+            const ulonglong2 v = in[u];
+            X[2 * u] = v.x;
+            X[2 * u + 1] = v.y;
+        }
         inv_round_b<8, F53>(X, tb, q);
     }
     Tw ta;
