@@ -536,30 +536,36 @@ class ConvShape:
         return -(-self.c_out // self.per_ct(S))
 
 
-def conv_schedule(cs: ConvShape, S: int) -> Schedule:
+def conv_schedule(cs: ConvShape, S: int, n1: int = 1) -> Schedule:
     """Multiplexed (channel-major) packing: slot s = c*H*W + h*W + w, c_ct = S/(H*W)
-    channels per ciphertext.  Baby steps: the k*k spatial offsets (dy, dx) in
-    row-major order, rotation dy*W + dx.  Giant steps: channel offsets k,
-    rotation k*H*W."""
+    channels per ciphertext.  The channel offsets k < c_ct split as k = k1 + n1 k2
+    (baby-step giant-step over the channel rotation; n1 = 1: every channel offset a
+    giant step).  Baby steps: channel offset k1 < n1 with each of the k*k spatial
+    offsets (dy, dx) in row-major order, rotation k1*H*W + dy*W + dx.  Giant steps:
+    rotation n1 k2 H*W."""
     c_ct = cs.per_ct(S)
-    if cs.k == 1:
-        rb = [0]
-    else:
-        r = cs.k // 2
-        rb = [dy * cs.w + dx for dy in range(-r, r + 1) for dx in range(-r, r + 1)]
-    gk = [k * cs.h * cs.w for k in range(c_ct)]
+    assert n1 >= 1 and c_ct % n1 == 0
+    hw = cs.h * cs.w
+    r = cs.k // 2
+    offs = [0] if cs.k == 1 else [dy * cs.w + dx for dy in range(-r, r + 1) for dx in range(-r, r + 1)]
+    rb = [k1 * hw + o for k1 in range(n1) for o in offs]
+    gk = [n1 * k2 * hw for k2 in range(c_ct // n1)]
     return Schedule(cs.n_in(S), cs.n_out(S), rb, gk)
 
 
-def conv_slots(Wp: np.ndarray, cs: ConvShape, S: int) -> np.ndarray:
-    """Plaintext slot vectors [n_out][n_in][c_ct][k*k][S].
+def conv_slots(Wp: np.ndarray, cs: ConvShape, S: int, n1: int = 1) -> np.ndarray:
+    """Plaintext slot vectors [n_out][n_in][c_ct / n1][n1 k*k][S] for conv_schedule(cs, S, n1).
 
-    Entry (o, i, k, b) with offset (dy, dx) is rot_{-k H W}(d) where, at output
-    slot s = co*HW + h*W + w of output ciphertext o,
+    With d_{k,(dy,dx)} the diagonal of channel offset k and spatial offset (dy, dx),
+    at output slot s = co*HW + h*W + w of output ciphertext o,
     d[s] = W'[o c_ct + co, i c_ct + (co + k) mod c_ct, dy + r, dx + r]
            * [0 <= h + dy < H] * [0 <= w + dx < W]
-    (zero where a channel index is past C_out / C_in)."""
+    (zero where a channel index is past C_out / C_in), entry (o, i, k2, (k1, b)) is
+    rot_{-n1 k2 H W}(d_{k1 + n1 k2, b}): the giant rotation by n1 k2 H W brings it back
+    in place, and rot_{n1 k2 HW}(rot_{-n1 k2 HW}(d) * rot_{k1 HW + off}(x)) =
+    d * rot_{k HW + off}(x)."""
     c_ct = cs.per_ct(S)
+    assert n1 >= 1 and c_ct % n1 == 0
     hw = cs.h * cs.w
     n_in, n_out = cs.n_in(S), cs.n_out(S)
     r = cs.k // 2
@@ -568,18 +574,21 @@ def conv_slots(Wp: np.ndarray, cs: ConvShape, S: int) -> np.ndarray:
     co = s // hw
     hh = (s % hw) // cs.w
     ww = s % cs.w
-    out = np.zeros((n_out, n_in, c_ct, len(offs), S))
+    n2 = c_ct // n1
+    out = np.zeros((n_out, n_in, n2, n1 * len(offs), S))
     for o in range(n_out):
         co_g = o * c_ct + co
         for i in range(n_in):
-            for k in range(c_ct):
-                ci_g = i * c_ct + (co + k) % c_ct
-                valid_c = (co_g < cs.c_out) & (ci_g < cs.c_in)
-                for b, (dy, dx) in enumerate(offs):
-                    valid = valid_c & (hh + dy >= 0) & (hh + dy < cs.h) & (ww + dx >= 0) & (ww + dx < cs.w)
-                    d = np.zeros(S)
-                    d[valid] = Wp[co_g[valid], ci_g[valid], dy + r, dx + r]
-                    out[o, i, k, b] = np.roll(d, k * hw)
+            for k2 in range(n2):
+                for k1 in range(n1):
+                    k = k1 + n1 * k2
+                    ci_g = i * c_ct + (co + k) % c_ct
+                    valid_c = (co_g < cs.c_out) & (ci_g < cs.c_in)
+                    for b, (dy, dx) in enumerate(offs):
+                        valid = valid_c & (hh + dy >= 0) & (hh + dy < cs.h) & (ww + dx >= 0) & (ww + dx < cs.w)
+                        d = np.zeros(S)
+                        d[valid] = Wp[co_g[valid], ci_g[valid], dy + r, dx + r]
+                        out[o, i, k2, k1 * len(offs) + b] = np.roll(d, n1 * k2 * hw)
     return out
 
 

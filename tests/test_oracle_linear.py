@@ -126,8 +126,9 @@ def test_shuffle_folding_probes(small):
     assert _rel_err(z[:n], (W @ x_orig)[p_out]) < 1e-3
 
 
-@pytest.mark.parametrize("c_in,c_out,k", [(8, 8, 3), (16, 16, 3), (3, 16, 3), (16, 8, 1)])
-def test_conv_multiplexed(small, c_in, c_out, k):
+@pytest.mark.parametrize("c_in,c_out,k,n1", [(8, 8, 3, 1), (16, 16, 3, 1), (3, 16, 3, 1), (16, 8, 1, 1),
+                                             (16, 16, 3, 4), (16, 8, 1, 2), (3, 16, 3, 2)])
+def test_conv_multiplexed(small, c_in, c_out, k, n1):
     prm = small
     cs = O.ConvShape(c_in, c_out, 8, 8, k)
     st = synth.Stream(100 + c_in + c_out + k)
@@ -135,9 +136,9 @@ def test_conv_multiplexed(small, c_in, c_out, k):
     perm = st.permutation(c_out)
     Wp = O.fold_permutations(W, perm, None)
     x = st.uniform(c_in * 64, 0, 1).reshape(c_in, 8, 8)
-    sched = O.conv_schedule(cs, prm.S)
+    sched = O.conv_schedule(cs, prm.S, n1)
     level = 3
-    pts = encode_pts(prm, O.conv_slots(Wp, cs, prm.S), level, prm.scale)
+    pts = encode_pts(prm, O.conv_slots(Wp, cs, prm.S, n1), level, prm.scale)
     cl = Client(prm, 200 + c_in)
     xs = O.conv_input_slots(x, cs, prm.S)
     cts = np.stack([cl.encrypt_slots(xs[i], level, prm.scale) for i in range(sched.n_in)])
@@ -148,8 +149,8 @@ def test_conv_multiplexed(small, c_in, c_out, k):
     ref = O.conv_ref(Wp, x)
     assert _rel_err(got, ref) < 1e-3
     # counts: hoisted baby key switches per input ct, giant ones per output ct
-    assert len([r for r in sched.rb if r]) == (8 if k == 3 else 0)
-    assert sched.G == cs.per_ct(prm.S)
+    assert len([r for r in sched.rb if r]) == n1 * k * k - 1
+    assert sched.G == cs.per_ct(prm.S) // n1
 
 
 def test_linear_schoolbook_mode_identical():
@@ -208,14 +209,15 @@ def test_fc_double_hoisted_decrypts(small, n, n1):
         assert not np.array_equal(y_dh, y_std)
 
 
-def test_conv_double_hoisted_decrypts(small):
+@pytest.mark.parametrize("n1", [1, 4])
+def test_conv_double_hoisted_decrypts(small, n1):
     prm = small
     cs = O.ConvShape(16, 16, 8, 8, 3)
     st = synth.Stream(510)
     W = st.he_normal((16, 16, 3, 3), 144)
     x = st.uniform(16 * 64, 0, 1).reshape(16, 8, 8)
-    sched = O.conv_schedule(cs, prm.S)
-    pts = encode_pts(prm, O.conv_slots(W, cs, prm.S), 3, prm.scale)
+    sched = O.conv_schedule(cs, prm.S, n1)
+    pts = encode_pts(prm, O.conv_slots(W, cs, prm.S, n1), 3, prm.scale)
     cl = Client(prm, 511)
     xs = O.conv_input_slots(x, cs, prm.S)
     cts = np.stack([cl.encrypt_slots(xs[i], 3, prm.scale) for i in range(sched.n_in)])
