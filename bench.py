@@ -58,6 +58,12 @@ def parse():
     ap.add_argument("--serve-streams", type=str, default="2",
                     help="streams (batches in flight at once) of the continuous-batching server; a comma list "
                          "runs one server per value")
+    ap.add_argument("--resnet18", type=int, default=0,
+                    help="instead of the FC benchmark: time every linear layer of the ResNet-18-shaped stack on "
+                         "64x64x3 inputs at N=2^16, level 3, for this many inferences per batch")
+    ap.add_argument("--conv-n1", type=int, default=1,
+                    help="convolutions (ResNet-18 stack, serving) split their channel rotations into baby and giant "
+                         "steps (1, default) or run every channel offset as a giant step (0)")
     ap.add_argument("--pmc-summary", type=str, default="",
                     help="instead of the benchmark: FETCH,WRITE,CALIB_FETCH,CALIB_WRITE rocprofv3 --pmc output "
                          "directories -> the measured-traffic file used for roofline.traffic")
@@ -204,7 +210,7 @@ def serve_bench(args) -> dict:
     import torch
 
     from paper_2509_01253_amd import fhelin as F
-    from paper_2509_01253_amd import synth
+    from paper_2509_01253_amd import resnet, synth
     from paper_2509_01253_amd.serving import GpuExecutor, Request, Server, poisson_timeline
 
     root = synth.Stream(synth.master_seed(5))
@@ -223,6 +229,9 @@ def serve_bench(args) -> dict:
         ex.add_params(j["params"], j["log_n"], q, p, j["dnum"])
         ctx = ex.params[j["params"]]["ctx"]
         kw = dict(c_in=j["c"], c_out=j["c"], h=j["hw"], w=j["hw"], k=3)
+        if args.conv_n1:
+            kw["n1"] = resnet.conv_channel_babies(resnet.LayerSpec("", "conv", j["c"], j["c"], j["hw"], j["hw"]),
+                                                  1 << (j["log_n"] - 1))
         plan = F.fhelin_plan_create(ctx, F.FHELIN_LAYER_CONV, **kw)
         W = torch.from_numpy(root.sub(synth.TAG_W).sub(j["c"]).he_normal((j["c"], j["c"], 3, 3), 9 * j["c"])).to(dev)
         pts = F.fhelin_plan_encode_weights(ctx, plan, W, None, None, j["L"], 2.0 ** 40)
@@ -290,6 +299,94 @@ def serve_bench(args) -> dict:
     return out
 
 
+def resnet18_bench(args) -> dict:
+    """The linear layers of a ResNet-18-shaped network on 64x64x3 inputs (3x3 stride-1
+    stem, four stages of widths 64..512, 1x1 downsampling convolutions, FC 512 -> 200;
+    paper Sec. 4 rounds, one per layer), each a fresh ciphertext set at level 3 of the
+    N = 2^16 context (12 + 3 primes of 50 bits, dnum 4).  Per layer: weights encoded on
+    the GPU and a key set for the layer's rotations loaded (untimed), the layer captured
+    into a graph for a batch of `args.resnet18` inferences, and the graph replayed; the
+    time is the median replay (HIP events on the replay stream).  The stack time is the
+    sum over the layers.  Keys and inputs are uniform residues (RLWE samples are
+    indistinguishable from uniform, so the cost is the same)."""
+    import torch
+
+    from paper_2509_01253_amd import fhelin as F
+    from paper_2509_01253_amd import resnet, synth
+
+    w = WORKLOAD
+    dev = torch.device("cuda:0")
+    primes = F.fhelin_primes_generate(w["log_n"], w["bits"], w["K"] + w["L"])
+    p, q = primes[: w["K"]], primes[w["K"]:]
+    N, K, level, B = 1 << w["log_n"], w["K"], 3, args.resnet18
+    mods = q[:level] + p
+    ctx = F.fhelin_ctx_create(w["log_n"], q, p, w["dnum"])
+    flags = F.FHELIN_APPLY_RESCALE | F.FHELIN_APPLY_HOIST_MODDOWN
+    root = synth.Stream(synth.master_seed(4))
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(int(root.sub(synth.TAG_KEYS).u64(1)[0] & 0x7FFFFFFFFFFFFFFF))
+    stream = torch.cuda.Stream()
+    specs = resnet.resnet18_layers(64, 64)
+    weights = resnet.init_weights(specs, root.sub(synth.TAG_W))
+    rows, total = [], 0.0
+    for sp in specs:
+        if sp.kind == "conv":
+            n1 = resnet.conv_channel_babies(sp, N // 2) if args.conv_n1 else 1
+            plan = F.fhelin_plan_create(ctx, F.FHELIN_LAYER_CONV, c_in=sp.c_in, c_out=sp.c_out, h=sp.h, w=sp.w, k=sp.k,
+                                        n1=n1)
+        else:
+            plan = F.fhelin_plan_create(ctx, F.FHELIN_LAYER_FC, fc_n=sp.fc_n, fc_out=sp.c_out, fc_in=sp.c_in,
+                                        n1=min(16, sp.fc_n))
+        info = F.fhelin_plan_info(plan)
+        gal = F.fhelin_plan_galois(plan)
+        Wd = torch.from_numpy(np.ascontiguousarray(weights[sp.name])).to(dev)
+        pts = F.fhelin_plan_encode_weights(ctx, plan, Wd, None, None, level, w["scale"])
+        ks = None
+        if gal:
+            evk = torch.empty((len(gal), 1, 2, level + K, N), dtype=torch.int64, device=dev)
+            for m, qm in enumerate(mods):
+                evk[:, :, :, m].random_(0, qm, generator=gen)
+            ks = F.fhelin_keyset_load(ctx, gal, level, evk)
+            del evk
+        x = torch.empty((B * info["n_in"], 2, level, N), dtype=torch.int64, device=dev)
+        for m in range(level):
+            x[:, :, m].random_(0, q[m], generator=gen)
+        y = torch.zeros((B * info["n_out"], 2, level, N), dtype=torch.int64, device=dev)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            graph = F.fhelin_graph_capture_linear(ctx, plan, ks, pts, x, [level] * (B * info["n_in"]), y,
+                                                  [level - 1] * (B * info["n_out"]), flags, stream=stream)
+        F.fhelin_graph_launch(graph, stream=stream)  # warm-up replay
+        times = []
+        for _ in range(3):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            F.fhelin_graph_launch(graph, stream=stream)
+            e1.record(stream)
+            e1.synchronize()
+            times.append(e0.elapsed_time(e1))
+        ms = float(np.median(times))
+        total += ms
+        rot = F.fhelin_plan_rotations(plan)
+        row = {"layer": sp.name, "ms": round(ms, 3), "n_in": info["n_in"], "n_out": info["n_out"],
+               "baby": len(rot[0]), "giant": len(rot[1]), "keys": len(gal), "pts": info["n_pt"]}
+        rows.append(row)
+        print(f"resnet18 layer {row}", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        F.fhelin_graph_destroy(graph)
+        F.fhelin_ptset_release(pts)
+        if ks is not None:
+            F.fhelin_keyset_release(ks)
+        F.fhelin_plan_destroy(plan)
+        F.fhelin_ctx_trim(ctx)
+        del x, y
+    F.fhelin_ctx_destroy(ctx)
+    return {"workload": "ResNet-18-shaped linear layers on 64x64x3 inputs, N=2^16, level 3, 12+3 primes of 50 bits, "
+                        "dnum 4, double-hoisted schedule, rescale, one graph per layer",
+            "inferences_per_batch": B, "stack_ms": round(total, 3),
+            "inferences_per_s": round(B / (total / 1e3), 3), "layers": rows}
+
+
 def main():
     args = parse()
     if args.pmc_summary:
@@ -305,6 +402,9 @@ def main():
     from paper_2509_01253_amd import synth
 
     assert torch.cuda.is_available(), "bench needs a GPU"
+    if args.resnet18 > 0:
+        print(json.dumps({"resnet18": resnet18_bench(args)}))
+        return
     if args.calib_copy > 0:
         n = int(args.calib_copy * (1 << 30)) // 8
         a = torch.ones(n, dtype=torch.int64, device="cuda")

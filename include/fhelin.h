@@ -150,8 +150,10 @@ int fhelin_ptset_release(fhelin_ptset *pts);
  *    spatial, kernel k in {1, 3}, stride 1, zero padding k/2 ("same").  Slot
  *    s = c*h*w + y*w + x with c_ct = N/(2hw) channels per ciphertext, so a
  *    layer maps ceil(c_in/c_ct) input ciphertexts to ceil(c_out/c_ct) outputs.
- *    Baby steps are the k*k spatial offsets (dy, dx), row-major, rotation
- *    dy*w + dx; giant steps are channel offsets j < c_ct, rotation j*h*w.
+ *    The channel offsets k < c_ct split as k = k1 + n1*k2 (n1 a power of two
+ *    dividing c_ct with n1*k*k <= 64; n1 = 0 or 1: no split).  Baby steps are
+ *    (k1, (dy, dx)), k1-major then the k*k spatial offsets row-major, rotation
+ *    k1*h*w + dy*w + dx; giant steps are k2 < c_ct/n1, rotation n1*k2*h*w.
  * Every layer is evaluated as
  *    y_o = sum_j rot_{G_j}( sum_i sum_b pt[o][i][j][b] * rot_{r_b}(x_i) )
  * (rot_0 = identity, no key switch), with plaintext index

@@ -136,21 +136,23 @@ __global__ void __launch_bounds__(256) k_diag_fc(const double *__restrict__ W, c
     out[(int64_t)blockIdx.y * S + s] = v;
 }
 
-// conv: entry (o, i, j, b) holds rot_{-j h w}(d) with
-// d[s] = W'[o c + co(s)][i c + (co(s) + j) mod c][dy + r][dx + r] * [inside]
+// conv: with n1 channel baby steps, entry (o, i, j, b), b = k1 k^2 + (spatial offset),
+// holds rot_{-n1 j h w}(d) for channel offset kc = k1 + n1 j, where
+// d[s] = W'[o c + co(s)][i c + (co(s) + kc) mod c][dy + r][dx + r] * [inside]
 __global__ void __launch_bounds__(256) k_diag_conv(const double *__restrict__ W, const int32_t *__restrict__ perm_out,
                                                    const int32_t *__restrict__ perm_in, int c_out, int c_in, int h,
-                                                   int w, int ks, int n_in, int S, int p0,
+                                                   int w, int ks, int n_in, int n1, int S, int p0,
                                                    double *__restrict__ out) {
     const int pidx = p0 + blockIdx.y;
     const int s = blockIdx.x * 256 + threadIdx.x;
     if (s >= S) return;
-    const int hw = h * w, cct = S / hw, B = ks * ks, r = ks / 2;
-    const int b = pidx % B, j = (pidx / B) % cct, ii = (pidx / B / cct) % n_in, o = pidx / B / cct / n_in;
-    const int dy = b / ks - r, dx = b % ks - r;
-    const int sp = ((s - j * hw) % S + S) % S;
+    const int hw = h * w, cct = S / hw, KK = ks * ks, B = n1 * KK, G = cct / n1, r = ks / 2;
+    const int b = pidx % B, j = (pidx / B) % G, ii = (pidx / B / G) % n_in, o = pidx / B / G / n_in;
+    const int k1 = b / KK, bo = b % KK, kc = k1 + n1 * j;
+    const int dy = bo / ks - r, dx = bo % ks - r;
+    const int sp = ((s - n1 * j * hw) % S + S) % S;
     const int co = sp / hw, y = (sp % hw) / w, x = sp % w;
-    const int cog = o * cct + co, cig = ii * cct + (co + j) % cct;
+    const int cog = o * cct + co, cig = ii * cct + (co + kc) % cct;
     double v = 0.0;
     if (cog < c_out && cig < c_in && y + dy >= 0 && y + dy < h && x + dx >= 0 && x + dx < w) {
         int a = perm_out ? perm_out[cog] : cog;
@@ -309,7 +311,7 @@ int plan_encode_weights(Ctx *c, const Plan *pl, const double *W, const int32_t *
                                d.fc_in, d.fc_n, d.n1, S, p0, slots);
         else
             hipLaunchKernelGGL(k_diag_conv, dim3((S + 255) / 256, n), dim3(256), 0, s, W, perm_out, perm_in, d.c_out,
-                               d.c_in, d.h, d.w, d.k, pl->n_in, S, p0, slots);
+                               d.c_in, d.h, d.w, d.k, pl->n_in, d.n1 > 1 ? d.n1 : 1, S, p0, slots);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) rc = set_error(FHELIN_E_HIP, std::string("encode_weights: ") + hipGetErrorString(e));
         if (rc == FHELIN_OK)

@@ -48,16 +48,21 @@ int plan_create(Ctx *c, const fhelin_layer_desc *d, Plan **out) {
         const int hw = d->h * d->w;
         FL_CHECK(S % hw == 0, FHELIN_E_UNSUPPORTED_PARAM, "h*w must divide N/2");
         const int cct = S / hw;
+        const int n1 = d->n1 > 1 ? d->n1 : 1;  // channel baby steps
+        FL_CHECK(pow2(n1) && cct % n1 == 0 && n1 * d->k * d->k <= MAX_BABY, FHELIN_E_UNSUPPORTED_PARAM,
+                 "conv n1 must be a power of two dividing the channels per ciphertext, n1 k^2 <= 64");
         p->n_in = (d->c_in + cct - 1) / cct;
         p->n_out = (d->c_out + cct - 1) / cct;
         FL_CHECK(p->n_in <= MAX_BATCH && p->n_out <= MAX_BATCH, FHELIN_E_UNSUPPORTED_PARAM, "too many ciphertexts per layer");
-        if (d->k == 1) {
-            p->rb.push_back(0);
-        } else {
-            for (int dy = -1; dy <= 1; ++dy)
-                for (int dx = -1; dx <= 1; ++dx) p->rb.push_back(dy * d->w + dx);
+        for (int k1 = 0; k1 < n1; ++k1) {
+            if (d->k == 1) {
+                p->rb.push_back(k1 * hw);
+            } else {
+                for (int dy = -1; dy <= 1; ++dy)
+                    for (int dx = -1; dx <= 1; ++dx) p->rb.push_back(k1 * hw + dy * d->w + dx);
+            }
         }
-        for (int j = 0; j < cct; ++j) p->gk.push_back(j * hw);
+        for (int j = 0; j < cct / n1; ++j) p->gk.push_back(n1 * j * hw);
     } else {
         return set_error(FHELIN_E_INVALID_ARG, "unknown layer kind");
     }

@@ -54,6 +54,18 @@ def resnet18_layers(h: int = 64, w: int = 64, c0: int = 3, widths=(64, 128, 256,
     return L
 
 
+def conv_channel_babies(spec: LayerSpec, slots: int) -> int:
+    """Channel baby steps for a conv layer's plan: the largest power of two n1
+    dividing the channels per ciphertext with n1 k^2 <= 64 (the plan's limit).  Each
+    channel offset that becomes a baby step trades a giant-step key switch (ModDown,
+    ModUp, their transforms) for a hoisted rotation (an inner product only)."""
+    cct = slots // (spec.h * spec.w)
+    n1 = 1
+    while cct % (2 * n1) == 0 and 2 * n1 * spec.k * spec.k <= 64:
+        n1 *= 2
+    return n1
+
+
 def init_weights(specs, stream) -> dict:
     """He-normal weights (batch norm folded), seeded."""
     W = {}

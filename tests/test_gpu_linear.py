@@ -121,16 +121,16 @@ def test_fc_bsgs_uneven_levels_batch(F):
         lay.close()
 
 
-@pytest.mark.parametrize("c_in,c_out,k", [(16, 16, 3), (3, 16, 3), (16, 8, 1)])
-def test_conv_multi_ct_bit_exact(F, c_in, c_out, k):
-    print(f"conv {c_in}->{c_out} k{k}", flush=True)
+@pytest.mark.parametrize("c_in,c_out,k,n1", [(16, 16, 3, 1), (3, 16, 3, 1), (16, 8, 1, 1), (16, 16, 3, 4), (16, 8, 1, 8)])
+def test_conv_multi_ct_bit_exact(F, c_in, c_out, k, n1):
+    print(f"conv {c_in}->{c_out} k{k} n1={n1}", flush=True)
     prm = O.make_params(10, 4, 2, 2, 50, 2.0 ** 40)
     cs = O.ConvShape(c_in, c_out, 8, 8, k)
     st = synth.Stream(4100 + c_in + k)
     W = st.he_normal((c_out, c_in, k, k), c_in * k * k)
-    sched = O.conv_schedule(cs, prm.S)
+    sched = O.conv_schedule(cs, prm.S, n1)
     level = 3
-    pts = encode_pts(prm, O.conv_slots(W, cs, prm.S), level, prm.scale)
+    pts = encode_pts(prm, O.conv_slots(W, cs, prm.S, n1), level, prm.scale)
     cl = Client(prm, 4200 + c_in)
     keys = cl.keyset(sched.rotations())
     reqs = 2
@@ -139,9 +139,10 @@ def test_conv_multi_ct_bit_exact(F, c_in, c_out, k):
     for x in xs:
         slots = O.conv_input_slots(x, cs, prm.S)
         cts += [cl.encrypt_slots(slots[i], level, prm.scale) for i in range(sched.n_in)]
-    lay = Layer(F, prm, keys, pts, level, c_in=c_in, c_out=c_out, h=8, w=8, k=k)
+    lay = Layer(F, prm, keys, pts, level, c_in=c_in, c_out=c_out, h=8, w=8, k=k, n1=n1)
     try:
         assert lay.info["n_in"] == sched.n_in and lay.info["n_out"] == sched.n_out
+        assert F.fhelin_plan_rotations(lay.plan) == (sched.rb, sched.gk)
         got = lay.apply(cts, [level] * len(cts))
         for r in range(reqs):
             want = O.linear(prm, np.stack(cts[r * sched.n_in:(r + 1) * sched.n_in]), level, sched, pts, keys)
@@ -208,7 +209,7 @@ def test_encode_within_one_unit(F):
             F.fhelin_ctx_destroy(ctx)
 
 
-@pytest.mark.parametrize("kind", ["fc", "conv"])
+@pytest.mark.parametrize("kind", ["fc", "conv", "conv_n1"])
 def test_encode_weights_with_shuffle(F, kind):
     """Weights -> folded diagonals -> encode on the GPU, against the oracle's slot
     vectors and encoding (one unit per coefficient), then decrypt(layer) vs FP64."""
@@ -230,13 +231,14 @@ def test_encode_weights_with_shuffle(F, kind):
         xs = [O.fc_input_slots(x, n, prm.S)]
         ref = (Wp @ x)
     else:
+        n1 = 4 if kind == "conv_n1" else 1
         cs = O.ConvShape(8, 16, 8, 8, 3)
         W = st.he_normal((16, 8, 3, 3), 72)
         po, pi = st.permutation(16), st.permutation(8)
         Wp = O.fold_permutations(W, po, pi)
-        sched = O.conv_schedule(cs, prm.S)
-        slots = O.conv_slots(Wp, cs, prm.S)
-        desc = dict(c_in=8, c_out=16, h=8, w=8, k=3)
+        sched = O.conv_schedule(cs, prm.S, n1)
+        slots = O.conv_slots(Wp, cs, prm.S, n1)
+        desc = dict(c_in=8, c_out=16, h=8, w=8, k=3, n1=n1)
         x = st.uniform(8 * 64, 0, 1).reshape(8, 8, 8)
         xs = list(O.conv_input_slots(x, cs, prm.S))
         ref = O.conv_ref(Wp, x)
@@ -297,22 +299,22 @@ def test_fc_double_hoisted_bit_exact(F, n1):
         lay.close()
 
 
-@pytest.mark.parametrize("c_in,c_out,k", [(16, 16, 3), (16, 8, 1)])
-def test_conv_double_hoisted_bit_exact(F, c_in, c_out, k):
-    print(f"dh conv {c_in}->{c_out} k{k}", flush=True)
+@pytest.mark.parametrize("c_in,c_out,k,n1", [(16, 16, 3, 1), (16, 8, 1, 1), (16, 16, 3, 4), (16, 16, 3, 2)])
+def test_conv_double_hoisted_bit_exact(F, c_in, c_out, k, n1):
+    print(f"dh conv {c_in}->{c_out} k{k} n1={n1}", flush=True)
     prm = O.make_params(10, 4, 2, 2, 50, 2.0 ** 40)
     cs = O.ConvShape(c_in, c_out, 8, 8, k)
     st = synth.Stream(4600 + k)
     W = st.he_normal((c_out, c_in, k, k), c_in * k * k)
-    sched = O.conv_schedule(cs, prm.S)
+    sched = O.conv_schedule(cs, prm.S, n1)
     level = 3
-    pts = encode_pts(prm, O.conv_slots(W, cs, prm.S), level, prm.scale)
+    pts = encode_pts(prm, O.conv_slots(W, cs, prm.S, n1), level, prm.scale)
     cl = Client(prm, 4601)
     keys = cl.keyset(sched.rotations())
     x = st.uniform(c_in * 64, 0, 1).reshape(c_in, 8, 8)
     slots = O.conv_input_slots(x, cs, prm.S)
     cts = [cl.encrypt_slots(slots[i], level, prm.scale) for i in range(sched.n_in)]
-    lay = Layer(F, prm, keys, pts, level, c_in=c_in, c_out=c_out, h=8, w=8, k=k)
+    lay = Layer(F, prm, keys, pts, level, c_in=c_in, c_out=c_out, h=8, w=8, k=k, n1=n1)
     try:
         got = lay.apply(cts, [level] * len(cts), dh=True)
         want = O.linear(prm, np.stack(cts), level, sched, pts, keys, hoist_moddown=True)
