@@ -55,12 +55,18 @@ def resnet18_layers(h: int = 64, w: int = 64, c0: int = 3, widths=(64, 128, 256,
 
 
 def conv_channel_babies(spec: LayerSpec, slots: int) -> int:
-    """Channel baby steps for a conv layer's plan: the largest power of two n1
-    dividing the channels per ciphertext with n1 k^2 <= 64 (the plan's limit).  Each
-    channel offset that becomes a baby step trades a giant-step key switch (ModDown,
-    ModUp, their transforms) for a hoisted rotation (an inner product only)."""
+    """Channel baby steps for a conv layer's plan.  Each channel offset that becomes a
+    baby step trades a giant-step key switch (ModDown, ModUp, their transforms) for a
+    hoisted rotation (an inner product), but the multiply-accumulate then reads
+    n1 times as many rotated inputs for every output ciphertext.  Measured on the
+    ResNet-18 stack at N = 2^16: with 8 or 32 channels per ciphertext the split was
+    slower or even (up to 3.5x slower for 8 in / 8 out ciphertexts), with 128 or 512
+    it was 2-3x faster.  So: no split below 64 channels per ciphertext, else the
+    largest power of two n1 dividing them with n1 k^2 <= 64 (the plan's limit)."""
     cct = slots // (spec.h * spec.w)
     n1 = 1
+    if cct < 64:
+        return n1
     while cct % (2 * n1) == 0 and 2 * n1 * spec.k * spec.k <= 64:
         n1 *= 2
     return n1
