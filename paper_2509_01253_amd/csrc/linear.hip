@@ -4,8 +4,9 @@
 // A layer is the baby-step / giant-step form
 //     y_o = sum_j rot_{G_j}( sum_i sum_b pt[o][i][j][b] * rot_{r_b}(x_i) ),
 // which covers the Halevi-Shoup diagonal method for FC layers (baby steps b < n1,
-// giant steps n1*j) and multiplexed convolutions (baby = spatial offsets, giant =
-// channel offsets).  The baby rotations of each input share one ModUp (hoisting);
+// giant steps n1*j) and multiplexed convolutions (baby = spatial offsets, with the
+// low part k1 of the channel offset k = k1 + n1 k2 when the plan splits it; giant =
+// the rest of the channel offset).  The baby rotations of each input share one ModUp (hoisting);
 // each giant rotation is a full key switch.  The paper's server round (Sec. 4.4)
 // folds the unshuffle of the previous round and the shuffle of this round into
 // the plaintexts, so they cost nothing here.
