@@ -474,10 +474,11 @@ static int giant_nonid(const Ctx *c, const Plan *p) {
     return n;
 }
 
-// digit buffers of the giant steps: one per step when they are summed in one launch
+// digit buffers of the giant steps: one per step of a group summed in one launch
+// (groups of at most MAX_SUM steps)
 static int giant_digit_sets(const Ctx *c, const Plan *p) {
     const int n = giant_nonid(c, p);
-    return n >= 1 && n <= MAX_SUM ? n : 1;
+    return n < 1 ? 1 : std::min(n, MAX_SUM);
 }
 
 static size_t limbs_per_request_dh(const Ctx *c, const Plan *p, int Bp) {
@@ -489,7 +490,7 @@ static size_t limbs_per_request_dh(const Ctx *c, const Plan *p, int Bp) {
            + ni * D * E        // hoisted digits
            + ni * Bp * 2 * E   // baby rotations (extended basis)
            + no * G * 2 * E    // accumulators (extended basis)
-           + no * 2 * E        // giant-step sum (extended basis)
+           + no * 4 * E        // giant-step sums (extended basis; two, alternating between groups)
            + no * 2 * L        // Y
            + emax * 2 * L      // Q temp for ModDown(c1)
            + emax * L          // coefficient temp
@@ -551,7 +552,8 @@ static int apply_chunk_dh(Ctx *c, const Plan *p, const KeySet *const *kss, const
     const int64_t ct = 2 * L * N, ext = 2 * E * N, dg = (int64_t)c->dnum * E * N;
     const int Ein = Rc * p->n_in, Eout = Rc * p->n_out, Emax = std::max(Ein, Eout);
     uint64_t *X = ws, *XL = X + Ein * ct, *D = XL + Ein * ext, *RB = D + Ein * dg;
-    uint64_t *A = RB + (int64_t)Ein * Bp * ext, *YE = A + (int64_t)Eout * G * ext, *Y = YE + Eout * ext;
+    uint64_t *A = RB + (int64_t)Ein * Bp * ext, *YE = A + (int64_t)Eout * G * ext, *YE2 = YE + Eout * ext;
+    uint64_t *Y = YE2 + Eout * ext;
     const int n_dg = giant_digit_sets(c, p);
     uint64_t *TQ = Y + Eout * ct, *TC = TQ + Emax * ct, *DG = TC + Emax * L * N, *MD = DG + Emax * dg * n_dg;
     Batch bin{}, bout{};
@@ -622,43 +624,84 @@ static int apply_chunk_dh(Ctx *c, const Plan *p, const KeySet *const *kss, const
     ma.pt_level = pts->level;
     ma.ext = 1;
     FL_RET(launch_mac(c, p, ma, bout, s));
-    // 5. giant steps summed in the extended basis.  When every giant step has its own
-    // digit buffer and the chunk's key sets hold the giant keys at the same indices,
-    // the key switches of all steps (and the identity step) go to one launch that
-    // writes the sum once.
+    // 5. giant steps summed in the extended basis.  When the chunk's key sets hold the
+    // giant keys at the same indices, the key switches of a group of up to MAX_SUM
+    // steps (each with its own digit buffer) go to one launch that adds them to the
+    // running sum (the identity step's accumulator, then the previous group's sum;
+    // two sum buffers alternate) and writes it once.  A single output entry takes a
+    // group's ModDown/ModUp in one launch per stage, the group's steps as entries.
     const int64_t a_es = (int64_t)G * ext;
-    bool fuse = n_dg == giant_nonid(c, p) && n_dg >= 1;
+    const int nonid = giant_nonid(c, p);
+    bool fuse = nonid >= 1;
     for (int j = 0; fuse && j < G; ++j) {
         const uint32_t g = galois_of_rotation(p->gk[j], c->log_n);
         if (g == 1) continue;
         const int idx = kss[r0]->find(g);
         for (int r = 1; r < Rc; ++r) fuse = fuse && kss[r0 + r]->find(g) == idx;
     }
+    uint64_t *Ysum = YE;
     if (fuse) {
-        KsSum sum{};
         const uint64_t *init = nullptr;
-        for (int j = 0; j < G; ++j) {
-            const uint32_t g = galois_of_rotation(p->gk[j], c->log_n);
-            uint64_t *Aj = A + j * ext;
-            if (g == 1) {
-                init = Aj;
-                continue;
-            }
-            set_keys(bout, p->n_out, kss + r0, g);
-            FL_RET(giant_moddown_modup(c, bout, Aj + E * N, a_es, TC, DG + (int64_t)sum.n * Emax * dg, dg, s));
-            sum.g[sum.n] = g;
-            sum.key[sum.n] = kss[r0]->find(g);
-            sum.dig_off[sum.n] = (int64_t)sum.n * Emax * dg;
-            sum.add_off[sum.n] = j * ext;
-            ++sum.n;
-        }
+        int64_t init_es = a_es;
+        for (int j = 0; j < G; ++j)
+            if (galois_of_rotation(p->gk[j], c->log_n) == 1) init = A + j * ext;
+        Batch bsum = bout;
         for (int e = 0; e < Eout; ++e) {
             const KeySet *ks = kss[r0 + e / p->n_out];
-            bout.key[e] = ks->evk;
-            bout.key_level[e] = ks->level;
-            bout.g[e] = 1;
+            bsum.key[e] = ks->evk;
+            bsum.key_level[e] = ks->level;
+            bsum.g[e] = 1;
         }
-        FL_RET(launch_ks_sum(c, bout, sum, DG, dg, A, a_es, init, a_es, YE, ext, s));
+        uint64_t *bufs[2] = {YE, YE2};
+        int which = 0;
+        KsSum sum{};
+        int jg[MAX_SUM];  // giant index of each term of the group
+        for (int j = 0; j < G; ++j) {
+            const uint32_t g = galois_of_rotation(p->gk[j], c->log_n);
+            if (g != 1) {
+                jg[sum.n] = j;
+                sum.g[sum.n] = g;
+                sum.key[sum.n] = kss[r0]->find(g);
+                sum.dig_off[sum.n] = (int64_t)sum.n * Emax * dg;
+                sum.add_off[sum.n] = j * ext;
+                ++sum.n;
+            }
+            bool last = true;
+            for (int jj = j + 1; jj < G; ++jj) last = last && galois_of_rotation(p->gk[jj], c->log_n) == 1;
+            if (sum.n == 0 || (sum.n < MAX_SUM && !last)) continue;
+            // the group's ModDown / ModUp into its digit buffers
+            if (Eout == 1 && sum.n > 1) {
+                // entries = the group's steps: accumulators ext apart when the steps are
+                // consecutive (every non-identity step of the group), digits Emax dg apart;
+                // their coefficient-domain temporaries go to the baby-rotation buffer, which
+                // the multiply-accumulate has consumed
+                bool consecutive = true;
+                for (int i = 1; i < sum.n; ++i) consecutive = consecutive && jg[i] == jg[0] + i;
+                if (consecutive && (int64_t)sum.n * L * N <= (int64_t)Ein * Bp * ext) {
+                    Batch bg{};
+                    bg.n = sum.n;
+                    for (int i = 0; i < sum.n; ++i) {
+                        bg.level[i] = bout.level[0];
+                        bg.g[i] = 1;
+                    }
+                    FL_RET(giant_moddown_modup(c, bg, A + jg[0] * ext + E * N, ext, RB, DG, (int64_t)Emax * dg, s));
+                } else {
+                    for (int i = 0; i < sum.n; ++i)
+                        FL_RET(giant_moddown_modup(c, bout, A + jg[i] * ext + E * N, a_es, TC, DG + sum.dig_off[i], dg,
+                                                   s));
+                }
+            } else {
+                for (int i = 0; i < sum.n; ++i)
+                    FL_RET(giant_moddown_modup(c, bout, A + jg[i] * ext + E * N, a_es, TC, DG + sum.dig_off[i], dg, s));
+            }
+            uint64_t *dst = bufs[which];
+            FL_RET(launch_ks_sum(c, bsum, sum, DG, dg, A, a_es, init, init_es, dst, ext, s));
+            init = dst;
+            init_es = ext;
+            Ysum = dst;
+            which ^= 1;
+            sum = KsSum{};
+        }
     }
     bool first = true;
     for (int j = 0; !fuse && j < G; ++j) {
@@ -677,10 +720,10 @@ static int apply_chunk_dh(Ctx *c, const Plan *p, const KeySet *const *kss, const
     }
     for (int e = 0; e < Eout; ++e) bout.g[e] = 1;
     // 6. final ModDown of both polynomials
-    FL_RET(launch_ntt(c, rows_kind(c, bout, YE, ext, ROWS_EXT_P, 2), 1, s));
-    FL_RET(launch_moddown_fbc(c, bout, YE, ext, MD, ct, s, 2));
+    FL_RET(launch_ntt(c, rows_kind(c, bout, Ysum, ext, ROWS_EXT_P, 2), 1, s));
+    FL_RET(launch_moddown_fbc(c, bout, Ysum, ext, MD, ct, s, 2));
     FL_RET(launch_ntt(c, rows_ct(c, bout, MD, ct, (int)L, 0, 2), 0, s));
-    FL_RET(launch_moddown_combine(c, bout, YE, ext, MD, ct, Y, ct, (int)L, nullptr, 0, 0, 0, s, 2));
+    FL_RET(launch_moddown_combine(c, bout, Ysum, ext, MD, ct, Y, ct, (int)L, nullptr, 0, 0, 0, s, 2));
     // 7. export
     return export_out(c, bout, Y, out, (int64_t)r0 * p->n_out, rescale, s);
 }
