@@ -41,7 +41,11 @@ __device__ __forceinline__ uint64_t shoup53_lazy(uint64_t a, uint64_t w, uint64_
     return a * w - qe * q;
 }
 
-__device__ __forceinline__ uint64_t csub(uint64_t a, uint64_t q) { return a >= q ? a - q : a; }
+// a - q unless that borrows (the borrow of the subtraction selects, no separate compare)
+__device__ __forceinline__ uint64_t csub(uint64_t a, uint64_t q) {
+    uint64_t r;
+    return __builtin_sub_overflow(a, q, &r) ? a : r;
+}
 
 __device__ __forceinline__ uint64_t shoup(uint64_t a, uint64_t w, uint64_t wp, uint64_t q) {
     return csub(shoup_lazy(a, w, wp, q), q);

@@ -54,7 +54,8 @@ __device__ __forceinline__ uint64_t tw_mul(uint64_t a, uint64_t w, uint64_t wp, 
 template <bool F53>
 __device__ __forceinline__ void ct_bfly(uint64_t &X, uint64_t &Y, uint64_t w, uint64_t wp, uint64_t q) {
     uint64_t q2 = 2 * q;
-    uint64_t x = X >= q2 ? X - q2 : X;
+    uint64_t x;  // X - 2q unless that borrows
+    if (__builtin_sub_overflow(X, q2, &x)) x = X;
     uint64_t t = tw_mul<F53>(Y, w, wp, q);
     X = x + t;
     Y = x - t + q2;
@@ -65,16 +66,12 @@ template <bool F53>
 __device__ __forceinline__ void gs_bfly(uint64_t &U, uint64_t &V, uint64_t w, uint64_t wp, uint64_t q) {
     uint64_t q2 = 2 * q;
     uint64_t u = U, v = V;
-    uint64_t s = u + v;
-    U = s >= q2 ? s - q2 : s;
+    uint64_t s = u + v, r;
+    U = __builtin_sub_overflow(s, q2, &r) ? s : r;
     V = tw_mul<F53>(u - v + q2, w, wp, q);
 }
 
-__device__ __forceinline__ uint64_t reduce4q(uint64_t x, uint64_t q) {
-    uint64_t q2 = 2 * q;
-    x = x >= q2 ? x - q2 : x;
-    return x >= q ? x - q : x;
-}
+__device__ __forceinline__ uint64_t reduce4q(uint64_t x, uint64_t q) { return csub(csub(x, 2 * q), q); }
 
 // ---------------------------------------------------------------------------
 // single pass (N <= 4096)
