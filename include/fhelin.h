@@ -87,9 +87,13 @@ int fhelin_ctx_destroy(fhelin_ctx *ctx);
  * and per-stream workspaces.  0 = unlimited (the default).  Allocations that
  * would exceed it fail with FHELIN_E_BUDGET. */
 int fhelin_ctx_set_budget(fhelin_ctx *ctx, uint64_t bytes);
-/* Bytes currently allocated by the context (keys + plaintexts + workspaces). */
+/* Bytes currently allocated by the context (keys + plaintexts + workspaces).
+ * Released blocks (at most 32 GiB) are kept for reuse by a later allocation of
+ * the same size instead of being returned to HIP; they are not counted here.
+ * A release waits for the device to be idle, as hipFree does. */
 int fhelin_ctx_memory(const fhelin_ctx *ctx, uint64_t *used_bytes);
-/* Release the per-stream workspaces (they are re-created on demand). */
+/* Release the per-stream workspaces (they are re-created on demand) and return
+ * the kept released blocks to HIP. */
 int fhelin_ctx_trim(fhelin_ctx *ctx);
 
 /* The minimal primitive 2N-th root of unity the context uses for modulus

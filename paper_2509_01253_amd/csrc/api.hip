@@ -242,6 +242,7 @@ FHELIN_EXPORT int fhelin_ctx_trim(fhelin_ctx *ctx) {
         old.swap(c->ws);
     }
     old.clear();
+    cache_flush(c);
     return FHELIN_OK;
     API_END
 }

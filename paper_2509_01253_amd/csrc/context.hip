@@ -96,14 +96,38 @@ static uint64_t minimal_root(uint64_t q, int log_n) {
 
 static inline uint32_t brv(uint32_t x, int bits) { return __builtin_bitreverse32(x) >> (32 - bits); }
 
+constexpr uint64_t CACHE_CAP = 32ull << 30;  // most bytes of freed blocks kept for reuse
+
+void cache_flush(Ctx *c) {
+    std::multimap<size_t, void *> blocks;
+    {
+        std::lock_guard<std::mutex> g(c->mu);
+        blocks.swap(c->cache);
+        c->cached = 0;
+    }
+    for (auto &b : blocks) (void)hipFree(b.second);
+}
+
 int dev_alloc(Ctx *c, void **p, size_t bytes) {
     {
         std::lock_guard<std::mutex> g(c->mu);
         if (c->budget && c->used + bytes > c->budget)
             return set_error(FHELIN_E_BUDGET, "allocation of " + std::to_string(bytes) + " bytes exceeds the HBM budget");
         c->used += bytes;
+        auto it = c->cache.find(bytes);
+        if (it != c->cache.end()) {
+            *p = it->second;
+            c->cache.erase(it);
+            c->cached -= bytes;
+            return FHELIN_OK;
+        }
     }
     hipError_t e = hipMalloc(p, bytes ? bytes : 256);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        cache_flush(c);  // blocks of other sizes may be what is missing
+        e = hipMalloc(p, bytes ? bytes : 256);
+    }
     if (e != hipSuccess) {
         std::lock_guard<std::mutex> g(c->mu);
         c->used -= bytes;
@@ -115,9 +139,19 @@ int dev_alloc(Ctx *c, void **p, size_t bytes) {
 
 void dev_free(Ctx *c, void *p, size_t bytes) {
     if (!p) return;
-    (void)hipFree(p);
-    std::lock_guard<std::mutex> g(c->mu);
-    c->used -= bytes;
+    // like hipFree: no queued work may still use the block once it is handed out again
+    (void)hipDeviceSynchronize();
+    bool keep;
+    {
+        std::lock_guard<std::mutex> g(c->mu);
+        c->used -= bytes;
+        keep = c->cached + bytes <= CACHE_CAP;
+        if (keep) {
+            c->cache.emplace(bytes, p);
+            c->cached += bytes;
+        }
+    }
+    if (!keep) (void)hipFree(p);
 }
 
 template <class T>
@@ -386,6 +420,8 @@ Ready::~Ready() {
 
 Ctx::~Ctx() {
     ws.clear();
+    for (auto &b : cache) (void)hipFree(b.second);
+    cache.clear();
     if (prof) {
         for (auto &r : prof->recs) {
             (void)hipEventDestroy(r.a);

@@ -130,6 +130,11 @@ struct Ctx {
     // memory accounting
     uint64_t budget = 0;
     uint64_t used = 0;
+    // freed device blocks kept for reuse by an allocation of the same size (not
+    // charged to `used`), so steady-state loads and releases call neither hipMalloc
+    // nor hipFree; flushed on an allocation failure, by fhelin_ctx_trim and on destroy
+    std::multimap<size_t, void *> cache;
+    uint64_t cached = 0;
     std::mutex mu;
     std::map<void *, std::unique_ptr<Workspace>> ws;  // per stream
     std::unique_ptr<Profiler> prof{new Profiler()};
@@ -139,6 +144,7 @@ struct Ctx {
 int ctx_create(const fhelin_params *prm, Ctx **out);
 void ctx_destroy(Ctx *c);
 int dev_alloc(Ctx *c, void **p, size_t bytes);    // charged to the budget
+void cache_flush(Ctx *c);                         // return the cached free blocks to HIP
 void dev_free(Ctx *c, void *p, size_t bytes);
 
 // ---------------------------------------------------------------------------
