@@ -15,7 +15,9 @@ The server side of the hybrid protocol (paper Sec. 3-4) as a serving system:
 * Continuous batching.  Up to `streams` batches are in flight on separate
   HIP streams (two by default: one batch runs while the next is admitted and
   launched; on MI355X four concurrent batches of N=2^16 convolutions ran at
-  less than half the throughput of two, each launch already filling the GPU).  Whenever a slot frees up, the oldest waiting request and every
+  less than half the throughput of two, each launch already filling the GPU).
+  A second batch starts beside a running one only when at least
+  `overlap_min_queue` requests wait (two by default).  Whenever a slot frees up, the oldest waiting request and every
   other waiting request for the same layer (any client, any level) form the
   next batch (at most `max_batch` requests), so requests that arrive while
   others run join the next launch and their work overlaps on the device.
@@ -87,11 +89,17 @@ class _Slot:
 class Server:
     """Request loop; see the module docstring."""
 
-    def __init__(self, executor, hbm_budget: int, streams: int = 2, max_batch: int = 64, clock=time.perf_counter):
+    def __init__(self, executor, hbm_budget: int, streams: int = 2, max_batch: int = 64, clock=time.perf_counter,
+                 overlap_min_queue: int = 2):
         self.ex = executor
         self.budget = int(hbm_budget)
         self.n_streams = streams
         self.max_batch = max_batch
+        # a batch starts beside one already in flight only when at least this many
+        # requests wait: a lone request waits for the running batch instead of
+        # sharing the GPU with it (both would run slower, raising the tail latency at
+        # light load), while a queue that has built up gets the overlap
+        self.overlap_min_queue = overlap_min_queue
         self.clock = clock
         self.sessions = {}                  # session -> next expected round
         self.session_client = {}
@@ -222,6 +230,8 @@ class Server:
         self._poll()
         for st in range(self.n_streams):
             if st not in self.inflight:
+                if self.inflight and len(self.queue) < self.overlap_min_queue:
+                    break
                 if not self._try_dispatch(st):
                     break
 

@@ -110,7 +110,7 @@ def test_batches_across_clients_and_levels():
 def test_continuous_batching_admits_arrivals_while_running():
     clk = FakeClock()
     ex = FakeExecutor(clk, dur=1.0)
-    srv = Server(ex, hbm_budget=10 ** 6, streams=2, clock=clk)
+    srv = Server(ex, hbm_budget=10 ** 6, streams=2, clock=clk, overlap_min_queue=1)
     for c in "abc":
         srv.open_session(f"s-{c}", c)
     srv.submit(_req(0, "a"))
@@ -130,6 +130,33 @@ def test_continuous_batching_admits_arrivals_while_running():
     clk.t = 2.0
     srv.pump()
     assert srv.results[2].latency == 1.5
+
+
+def test_lone_request_waits_instead_of_overlapping():
+    """With the default overlap threshold a single waiting request does not start a
+    second batch beside a running one; two waiting requests do."""
+    clk = FakeClock()
+    ex = FakeExecutor(clk, dur=1.0)
+    srv = Server(ex, hbm_budget=10 ** 6, streams=2, clock=clk)
+    for c in "abcd":
+        srv.open_session(f"s-{c}", c)
+    srv.submit(_req(0, "a"))
+    srv.pump()                      # batch 1 on stream 0
+    clk.t = 0.3
+    srv.submit(_req(1, "b"))
+    srv.pump()                      # alone in the queue: waits for stream 0
+    assert [l[1] for l in ex.launches] == [[0]]
+    clk.t = 0.4
+    srv.submit(_req(2, "c", layer="conv"))
+    srv.pump()                      # two waiting: a second batch starts on stream 1
+    assert [l[1] for l in ex.launches] == [[0], [1]]
+    assert srv.max_inflight == 2
+    clk.t = 1.0
+    srv.pump()                      # stream 0 frees, stream 1 still runs: the lone conv request waits
+    assert len(ex.launches) == 2
+    clk.t = 1.4
+    srv.pump()                      # nothing in flight -> it starts
+    assert ex.launches[2] == ("conv", [2], 1.4)
 
 
 def test_admission_by_budget_and_lru_eviction():
