@@ -124,6 +124,26 @@ def traffic_args(args) -> dict:
     return {"batch": args.batch, "n1": args.n1, "schedule": args.schedule, "autotune": bool(args.autotune)}
 
 
+def stream_rates(a, b) -> dict:
+    """Attainable streaming rates of plain library kernels over two equal device
+    buffers (context for the kernels' HBM fractions): device copy (read + write),
+    write-only fill, read-mostly sum; GB/s over 10 back-to-back launches each."""
+    import torch
+    nb = a.numel() * a.element_size()
+    rates = {}
+    for name, fn, nbytes in (("copy", lambda: b.copy_(a), 2 * nb), ("fill", lambda: b.fill_(3), nb),
+                             ("sum", lambda: a.sum(), nb)):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        rates[name + "_GBps"] = round(10 * nbytes / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
+    return rates
+
+
 def pmc_summary(dirs: str, args) -> None:
     """Write the traffic file from four rocprofv3 --pmc output directories: FETCH_SIZE
     and WRITE_SIZE of this benchmark run with the same workload flags, then of the
@@ -413,7 +433,8 @@ def main():
         for _ in range(3):
             b.copy_(a)
         torch.cuda.synchronize()
-        print(json.dumps({"calib_copy_bytes_read": n * 8, "calib_copy_bytes_written": n * 8, "copies": 3}))
+        print(json.dumps({"calib_copy_bytes_read": n * 8, "calib_copy_bytes_written": n * 8, "copies": 3,
+                          **stream_rates(a, b)}))
         return
     dev = torch.device("cuda:0")
     w = WORKLOAD
@@ -579,6 +600,12 @@ def main():
                             "peak_GBps": 8000.0, "frac": round(byts / (ms / 1e3) / 8e12, 4)}
     F.fhelin_plan_destroy(plan)
     F.fhelin_ctx_destroy(ctx)
+    # what a plain 1 GiB device copy attains on this GPU, measured after the timed region
+    ca = torch.ones(1 << 27, dtype=torch.int64, device=dev)
+    copy_gbps = stream_rates(ca, torch.empty_like(ca))["copy_GBps"]
+    del ca
+    res["hbm_effective"]["copy_GBps"] = copy_gbps
+    res["hbm_effective"]["frac_of_copy"] = round(res["hbm_effective"]["achieved_GBps"] / copy_gbps, 4)
     if args.serve_requests > 0:
         res["serving"] = serve_bench(args)
     if not args.no_cpu_baseline:
