@@ -52,6 +52,10 @@ def parse():
                     help="requests per arrival rate in an extra serving run (default 0 = no serving run)")
     ap.add_argument("--serve-rates", type=str, default="20,100", help="Poisson arrival rates (req/s)")
     ap.add_argument("--serve-clients", type=int, default=32)
+    ap.add_argument("--serve-schedule", choices=["fastest", "hoisted", "rotation"], default="fastest",
+                    help="schedule of each served layer: the faster of the double-hoisted and the per-rotation "
+                         "ModDown schedule timed at the layer's middle level for single requests (used for batches "
+                         "of 1) and for batches of 4 (used for larger batches) (default), or one of them")
     ap.add_argument("--serve-reserve", type=int, default=64,
                     help="requests per batch the serving executor sizes every stream's workspace for at start-up "
                          "(0: grow on demand when a larger batch arrives)")
@@ -223,6 +227,60 @@ def cpu_baseline(level: int, n1: int, hoisted: bool) -> dict:
                       f"schedule, 256 pt-MACs, rescale) at level {level} of the N=2^16 workload; {dt:.1f} s"}
 
 
+def fastest_schedule(F, ctx, plan, pts, sched_flags, N, L, K, beta, mods, level, dev, batches=(1, 4)) -> dict:
+    """The faster schedule of a layer for batches of each size in `batches`, requests at
+    `level`: a key set of uniform residues is loaded, every schedule is applied once to
+    warm up and then three times (HIP events, median); the key set is released
+    afterwards and the context trimmed (call it before the context has reserved
+    workspaces that must stay).  Returns the choice per batch size and the
+    (max_batch, schedule) pairs for the executor: a batch up to the first size takes
+    the first choice, and so on."""
+    import numpy as np
+    import torch
+
+    g = torch.Generator(device=dev)
+    g.manual_seed(12345)
+    gal = F.fhelin_plan_galois(plan)
+    info = F.fhelin_plan_info(plan)
+    evk = torch.empty((len(gal), beta, 2, L + K, N), dtype=torch.int64, device=dev)
+    for m, qm in enumerate(mods):
+        evk[:, :, :, m].random_(0, qm, generator=g)
+    ks = F.fhelin_keyset_load(ctx, gal, L, evk)
+    trial, pairs = {}, []
+    for b in batches:
+        x = torch.empty((b * info["n_in"], 2, L, N), dtype=torch.int64, device=dev)
+        for m in range(level):
+            x[:, :, m].random_(0, mods[m], generator=g)
+        y = torch.zeros((b * info["n_out"], 2, L, N), dtype=torch.int64, device=dev)
+        tb = {}
+        for name, fl in sched_flags.items():
+            out_level = level - 1 if fl & F.FHELIN_APPLY_RESCALE else level
+
+            def apply():
+                F.fhelin_linear_apply(ctx, plan, ks, pts, x, [level] * (b * info["n_in"]), y,
+                                      [out_level] * (b * info["n_out"]), fl)
+
+            apply()
+            torch.cuda.synchronize()
+            times = []
+            for _ in range(3):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                apply()
+                e1.record()
+                e1.synchronize()
+                times.append(e0.elapsed_time(e1))
+            tb[name] = round(float(np.median(times)), 3)
+        trial[str(b)] = tb
+        pairs.append((b, min(tb, key=tb.get)))
+        del x, y
+    torch.cuda.synchronize()
+    F.fhelin_keyset_release(ks)
+    del evk
+    F.fhelin_ctx_trim(ctx)  # the trial's workspaces and blocks: not held against the serving budget
+    return {"level": level, "trial_ms": trial, "by_batch": pairs}
+
+
 def serve_bench(args) -> dict:
     """Serving run: Poisson arrivals mixing an N=2^15 job (ResNet-20-block conv 3x3
     16->16 on 32x32, 8 + 2 primes, levels 2..8) and an N=2^16 job (ResNet-18 stage-1
@@ -246,6 +304,9 @@ def serve_bench(args) -> dict:
     gen = torch.Generator(device=dev)
     gen.manual_seed(int(root.sub(synth.TAG_KEYS).u64(1)[0] & 0x7FFFFFFFFFFFFFFF))
     info = {}
+    sched_flags = {"hoisted": F.FHELIN_APPLY_RESCALE | F.FHELIN_APPLY_HOIST_MODDOWN,
+                   "rotation": F.FHELIN_APPLY_RESCALE}
+    schedule = {}
     for name, j in jobs.items():
         pr = F.fhelin_primes_generate(j["log_n"], 50, j["K"] + j["L"])
         p, q = pr[: j["K"]], pr[j["K"]:]
@@ -258,12 +319,19 @@ def serve_bench(args) -> dict:
         plan = F.fhelin_plan_create(ctx, F.FHELIN_LAYER_CONV, **kw)
         W = torch.from_numpy(root.sub(synth.TAG_W).sub(j["c"]).he_normal((j["c"], j["c"], 3, 3), 9 * j["c"])).to(dev)
         pts = F.fhelin_plan_encode_weights(ctx, plan, W, None, None, j["L"], 2.0 ** 40)
-        F.fhelin_plan_destroy(plan)
-        ex.add_layer(name, j["params"], kw, F.FHELIN_LAYER_CONV, pts)
-        gal = ex.layers[name]["galois"]
         N, L, K = 1 << j["log_n"], j["L"], j["K"]
         beta = -(-L // -(-L // j["dnum"]))
         mods = q + p
+        if args.serve_schedule == "fastest":
+            schedule[name] = fastest_schedule(F, ctx, plan, pts, sched_flags, N, L, K, beta, mods,
+                                              (j["lmin"] + L) // 2, dev)
+            print(f"serving layer {name}: schedule {schedule[name]}", file=sys.stderr, flush=True)
+        else:
+            schedule[name] = {"by_batch": [(1, args.serve_schedule)]}
+        F.fhelin_plan_destroy(plan)
+        ex.add_layer(name, j["params"], kw, F.FHELIN_LAYER_CONV, pts,
+                     flags=[(m, sched_flags[sc]) for m, sc in schedule[name]["by_batch"]])
+        gal = ex.layers[name]["galois"]
 
         def source(stream, gal=gal, N=N, L=L, K=K, beta=beta, mods=mods):
             evk = torch.empty((len(gal), beta, 2, L + K, N), dtype=torch.int64, device=dev)
@@ -299,7 +367,7 @@ def serve_bench(args) -> dict:
     out = {"workload": "Poisson mix of conv 16->16 @32x32 (N=2^15, levels 2..8) and conv 64->64 @64x64 "
                        "(N=2^16, 8 in / 8 out ciphertexts, levels 2..12), "
                        f"{args.serve_clients} clients with their own keys, HBM budget 200 GiB",
-           "rates": {}}
+           "schedule": schedule, "rates": {}}
     for ri, rate in enumerate(float(r) for r in args.serve_rates.split(",")):
         row = {}
         modes = [(f"continuous_s{k}" if "," in args.serve_streams else "continuous", int(k), 64)

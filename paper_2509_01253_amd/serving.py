@@ -310,17 +310,33 @@ class GpuExecutor:
         ctx = self.F.fhelin_ctx_create(log_n, q, p, dnum)
         self.params[name] = dict(ctx=ctx, log_n=log_n, N=1 << log_n, L=len(q), K=len(p), dnum=dnum)
 
-    def add_layer(self, name, params, plan_kwargs, kind, pts):
+    def add_layer(self, name, params, plan_kwargs, kind, pts, flags=None):
+        """flags: this layer's apply flags (its schedule), default the executor's; or a
+        list of (max_batch, flags) pairs in increasing max_batch, the last one covering
+        every larger batch: a batch runs with the flags of the first pair that admits it."""
         P = self.params[params]
+        fl = self.flags if flags is None else flags
+        by_batch = [(1 << 30, fl)] if isinstance(fl, int) else [(int(m), int(f)) for m, f in fl]
+        by_batch[-1] = (1 << 30, by_batch[-1][1])
         plan = self.F.fhelin_plan_create(P["ctx"], kind, **plan_kwargs)
         info = self.F.fhelin_plan_info(plan)
         self.layers[name] = dict(params=params, plan=plan, pts=pts, n_in=info["n_in"], n_out=info["n_out"],
-                                 galois=self.F.fhelin_plan_galois(plan))
+                                 galois=self.F.fhelin_plan_galois(plan), flags=by_batch)
         if self.reserve_requests > 0:
-            need = self.F.fhelin_plan_workspace_bytes(P["ctx"], plan, self.reserve_requests, self.flags)
+            # each schedule for the largest batch it runs (at most reserve_requests)
             for i, st in enumerate(self.streams):
-                self.F.fhelin_plan_reserve_workspace(P["ctx"], plan, self.reserve_requests, self.flags, stream=st)
-                self.ws[(params, i)] = max(self.ws.get((params, i), 0), need)
+                for m, f in by_batch:
+                    n = min(self.reserve_requests, m)
+                    need = self.F.fhelin_plan_workspace_bytes(P["ctx"], plan, n, f)
+                    self.F.fhelin_plan_reserve_workspace(P["ctx"], plan, n, f, stream=st)
+                    self.ws[(params, i)] = max(self.ws.get((params, i), 0), need)
+
+    def layer_flags(self, layer, n_req):
+        """Apply flags of `layer` for a batch of n_req requests."""
+        for m, f in self.layers[layer]["flags"]:
+            if n_req <= m:
+                return f
+        return self.layers[layer]["flags"][-1][1]
 
     def add_client_keys(self, client, params, source, nbytes):
         """source(stream) -> (galois list, level, evk tensor); nbytes = resident size."""
@@ -348,7 +364,8 @@ class GpuExecutor:
 
     def workspace_growth(self, layer, n_req, stream):
         Ly = self.layers[layer]
-        need = self.F.fhelin_plan_workspace_bytes(self.params[Ly["params"]]["ctx"], Ly["plan"], n_req, self.flags)
+        need = self.F.fhelin_plan_workspace_bytes(self.params[Ly["params"]]["ctx"], Ly["plan"], n_req,
+                                                  self.layer_flags(layer, n_req))
         have = self.ws.get((Ly["params"], stream), 0)
         return max(0, need - have)
 
@@ -378,15 +395,14 @@ class GpuExecutor:
                     x[i * n_in:(i + 1) * n_in, :, : r.x.shape[2]] = r.x
             y = torch.empty((len(batch) * Ly["n_out"], 2, L, N), dtype=torch.int64, device=x.device)
             xl = [r.level for r in batch for _ in range(Ly["n_in"])]
-            resc = bool(self.flags & F.FHELIN_APPLY_RESCALE)
+            fl = self.layer_flags(layer, len(batch))
+            resc = bool(fl & F.FHELIN_APPLY_RESCALE)
             yl = [r.level - (1 if resc else 0) for r in batch for _ in range(Ly["n_out"])]
-            F.fhelin_linear_apply_multi(P["ctx"], Ly["plan"], key_handles, Ly["pts"], x, xl, y, yl, self.flags,
-                                        stream=s)
+            F.fhelin_linear_apply_multi(P["ctx"], Ly["plan"], key_handles, Ly["pts"], x, xl, y, yl, fl, stream=s)
             ev = torch.cuda.Event()
             ev.record(s)
         key = (Ly["params"], stream)
-        self.ws[key] = max(self.ws.get(key, 0), F.fhelin_plan_workspace_bytes(P["ctx"], Ly["plan"], len(batch),
-                                                                            self.flags))
+        self.ws[key] = max(self.ws.get(key, 0), F.fhelin_plan_workspace_bytes(P["ctx"], Ly["plan"], len(batch), fl))
         return (ev, x, yl), y, self.io_bytes(layer, batch)
 
     def done(self, token):

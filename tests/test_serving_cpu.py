@@ -228,3 +228,14 @@ def test_run_reports_latency_percentiles():
     st = srv.stats(res)
     assert st["completed"] == 20 and st["rejected"] == 0
     assert st["p99_ms"] >= st["p50_ms"] > 0
+
+
+def test_executor_flags_by_batch_size():
+    """A layer registered with (max_batch, flags) pairs runs a batch with the flags of
+    the first pair that admits it; the last pair covers every larger batch."""
+    from paper_2509_01253_amd.serving import GpuExecutor
+
+    ex = GpuExecutor.__new__(GpuExecutor)  # host logic only: no streams or contexts
+    ex.layers = {"a": {"flags": [(1, 3), (4, 1)]}, "b": {"flags": [(1 << 30, 3)]}}
+    assert [ex.layer_flags("a", n) for n in (1, 2, 4, 5, 64)] == [3, 1, 1, 1, 1]
+    assert [ex.layer_flags("b", n) for n in (1, 64)] == [3, 3]
