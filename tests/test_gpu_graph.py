@@ -12,11 +12,12 @@ from tests.helpers import Client, encode_pts
 pytestmark = pytest.mark.gpu
 
 
-def test_graph_replays_match_eager():
+@pytest.mark.parametrize("hoisted", [True, False], ids=["double_hoisted", "per_rotation"])
+def test_graph_replays_match_eager(hoisted):
     import torch
 
     from paper_2509_01253_amd import fhelin as F
-    print("graph replay", flush=True)
+    print(f"graph replay hoisted={hoisted}", flush=True)
     prm = O.make_params(12, 6, 2, 3, 50, 2.0 ** 40)
     st = synth.Stream(5000)
     n, n1 = 64, 8
@@ -41,7 +42,7 @@ def test_graph_replays_match_eager():
         x = dev(inputs[0])
         y = dev(np.zeros_like(inputs[0]))
         out_levels = [l - 1 for l in levels]
-        flags = F.FHELIN_APPLY_RESCALE | F.FHELIN_APPLY_HOIST_MODDOWN
+        flags = F.FHELIN_APPLY_RESCALE | (F.FHELIN_APPLY_HOIST_MODDOWN if hoisted else 0)
         with torch.cuda.stream(stream):
             g = F.fhelin_graph_capture_linear(ctx, plan, ks, pset, x, levels, y, out_levels, flags, stream=stream)
         y_eager = dev(np.zeros_like(inputs[0]))
@@ -63,7 +64,7 @@ def test_graph_replays_match_eager():
             t = rep % len(levels)
             l = levels[t]
             ref = O.rescale(prm, O.linear(prm, inputs[rep][t, :, :l][None], l, sched, pts, keys,
-                                          hoist_moddown=True)[0], l)
+                                          hoist_moddown=hoisted)[0], l)
             assert np.array_equal(got[t, :, : l - 1], ref), rep
         F.fhelin_graph_destroy(g)
         F.fhelin_ptset_release(pset)
