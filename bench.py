@@ -235,7 +235,6 @@ def fastest_schedule(F, ctx, plan, pts, sched_flags, N, L, K, beta, mods, level,
     workspaces that must stay).  Returns the choice per batch size and the
     (max_batch, schedule) pairs for the executor: a batch up to the first size takes
     the first choice, and so on."""
-    import numpy as np
     import torch
 
     g = torch.Generator(device=dev)
