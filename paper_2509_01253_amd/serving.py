@@ -313,7 +313,11 @@ class GpuExecutor:
     def add_layer(self, name, params, plan_kwargs, kind, pts, flags=None):
         """flags: this layer's apply flags (its schedule), default the executor's; or a
         list of (max_batch, flags) pairs in increasing max_batch, the last one covering
-        every larger batch: a batch runs with the flags of the first pair that admits it."""
+        every larger batch: a batch runs with the flags of the first pair that admits it.
+        With pairs of different schedules a request's output ciphertext depends on the
+        size of the batch it ran in (the schedules round differently; both decrypt to
+        the layer within the scheme's error); one flags value keeps every output
+        bit-identical however the requests are batched."""
         P = self.params[params]
         fl = self.flags if flags is None else flags
         by_batch = [(1 << 30, fl)] if isinstance(fl, int) else [(int(m), int(f)) for m, f in fl]
