@@ -3,8 +3,9 @@ times (double-hoisted schedule, default tune, N = 2^16, 12 + 3 primes of 50 bits
 dnum 4).  Key material, plaintexts and ciphertexts are uniform residues: the
 kernels' results are exact integer functions of them, so bit-exactness needs no
 valid encryption (decryption error is covered at smaller N).  The oracle computes
-sampled requests one by one; every other output is checked against the same
-request evaluated alone."""
+sampled requests one by one -- one of every digit count the batch holds (level 4:
+2 digits, level 8: 3, level 12: 4) -- and every other sampled output is checked
+against the same request evaluated alone."""
 import numpy as np
 import pytest
 
@@ -33,10 +34,11 @@ def _uniform_ct(prm, level, st):
     return np.stack([synth.uniform_limbs(st, prm.q[:level], prm.N) for _ in range(2)])
 
 
-def test_fc256_batch64_full_size():
-    """Batched FC 256x256 with the benchmark's split (n1 = 32): 64 requests at levels
-    4..12 in one call; the two lowest-level requests bit-exact against the oracle,
-    four others equal to the same request evaluated alone."""
+@pytest.fixture(scope="module")
+def fc_batch():
+    """The batched FC workload: 64 requests at levels 4..12 (seeded), FC 256x256 with
+    the benchmark's split (n1 = 32), evaluated on the GPU in one call under the
+    double-hoisted schedule (the benchmark's) and under the per-rotation schedule."""
     import torch
 
     from paper_2509_01253_amd import fhelin as F
@@ -52,35 +54,65 @@ def test_fc256_batch64_full_size():
         keys = _uniform_keys(prm, galois, st.sub(1))
         pts = _uniform_pts(prm, 256, prm.L, st.sub(2))
         levels = [int(v) for v in st.sub(3).integers(64, 4, 12)]
+        assert {4, 8, 12} <= set(levels)
         cts = [_uniform_ct(prm, l, st.sub(100 + i)) for i, l in enumerate(levels)]
         print("inputs ready", flush=True)
         ks = F.fhelin_keyset_load(ctx, galois, prm.L, dev(keys_at(prm, keys, prm.L)))
         pset = F.fhelin_pt_import(ctx, dev(pts), level=prm.L)
         x = dev(pad_cts(cts, prm.L, prm.N))
-        y = dev(np.zeros((64, 2, prm.L, prm.N), np.uint64))
-        flags = F.FHELIN_APPLY_RESCALE | F.FHELIN_APPLY_HOIST_MODDOWN
-        F.fhelin_linear_apply(ctx, plan, ks, pset, x, levels, y, [l - 1 for l in levels], flags)
-        got = host(y)
+        out = {}
+        for name, flags in (("dh", F.FHELIN_APPLY_RESCALE | F.FHELIN_APPLY_HOIST_MODDOWN),
+                            ("rot", F.FHELIN_APPLY_RESCALE)):
+            y = dev(np.zeros((64, 2, prm.L, prm.N), np.uint64))
+            F.fhelin_linear_apply(ctx, plan, ks, pset, x, levels, y, [l - 1 for l in levels], flags)
+            out[name] = host(y)
+            del y
         print("gpu done", flush=True)
-        # four requests alone
-        for t in (0, 17, 40, 63):
+        # four requests alone, under the benchmark's schedule
+        alone = {}
+        flags = F.FHELIN_APPLY_RESCALE | F.FHELIN_APPLY_HOIST_MODDOWN
+        for t in (0, 13, 40, 63):
             y1 = dev(np.zeros((1, 2, prm.L, prm.N), np.uint64))
             F.fhelin_linear_apply(ctx, plan, ks, pset, dev(pad_cts([cts[t]], prm.L, prm.N)), [levels[t]], y1,
                                   [levels[t] - 1], flags)
-            assert np.array_equal(host(y1)[0, :, : levels[t] - 1], got[t, :, : levels[t] - 1]), t
-        # the oracle on the two lowest-level requests
-        pts6 = pts.reshape(1, 1, sched.G, sched.B, prm.L + prm.K, prm.N)
-        for t in sorted(range(64), key=lambda i: levels[i])[:2]:
-            l = levels[t]
-            want = O.rescale(prm, O.linear(prm, cts[t][None], l, sched, pts6, keys, hoist_moddown=True)[0], l)
-            assert np.array_equal(got[t, :, : l - 1], want), (t, l)
-            print(f"oracle request {t} (level {l}) bit-exact", flush=True)
+            alone[t] = host(y1)[0]
         F.fhelin_ptset_release(pset)
         F.fhelin_keyset_release(ks)
         F.fhelin_plan_destroy(plan)
     finally:
         F.fhelin_ctx_destroy(ctx)
         torch.cuda.synchronize()
+    pts6 = pts.reshape(1, 1, sched.G, sched.B, prm.L + prm.K, prm.N)
+    return dict(prm=prm, sched=sched, keys=keys, pts6=pts6, levels=levels, cts=cts, out=out, alone=alone)
+
+
+def test_fc256_batch64_request_alone(fc_batch):
+    """Requests of every level range give the same bits alone as in the batch of 64."""
+    levels, got = fc_batch["levels"], fc_batch["out"]["dh"]
+    for t, y1 in fc_batch["alone"].items():
+        l = levels[t]
+        assert np.array_equal(y1[:, : l - 1], got[t, :, : l - 1]), (t, l)
+
+
+@pytest.mark.parametrize("level", [4, 8, 12])
+def test_fc256_batch64_oracle_double_hoisted(fc_batch, level):
+    """The first request of the batch at `level` (2, 3 and 4 key-switch digits)
+    bit-exact against the oracle's double-hoisted layer plus rescale."""
+    prm, sched, levels = fc_batch["prm"], fc_batch["sched"], fc_batch["levels"]
+    t = levels.index(level)
+    print(f"oracle: request {t} at level {level}, beta {prm.beta(level)}", flush=True)
+    want = O.rescale(prm, O.linear(prm, fc_batch["cts"][t][None], level, sched, fc_batch["pts6"], fc_batch["keys"],
+                                   hoist_moddown=True)[0], level)
+    assert np.array_equal(fc_batch["out"]["dh"][t, :, : level - 1], want), (t, level)
+
+
+def test_fc256_batch64_oracle_per_rotation(fc_batch):
+    """The same batch under the per-rotation ModDown schedule: a level-7 request
+    (3 digits) bit-exact against the oracle's per-rotation layer plus rescale."""
+    prm, sched, levels = fc_batch["prm"], fc_batch["sched"], fc_batch["levels"]
+    t = levels.index(7)
+    want = O.rescale(prm, O.linear(prm, fc_batch["cts"][t][None], 7, sched, fc_batch["pts6"], fc_batch["keys"])[0], 7)
+    assert np.array_equal(fc_batch["out"]["rot"][t, :, :6], want), t
 
 
 def test_resnet18_stem_conv_full_size():

@@ -253,10 +253,18 @@ def test_encode_weights_with_shuffle(F, kind):
         F.fhelin_pt_export(lay.ctx, lay.pset, level, out)
         got = host(out)
         want = encode_pts(prm, slots, level, prm.scale).reshape(n_pt, level + prm.K, prm.N)
-        q0 = prm.q[0]
-        d = (got[:, 0].astype(np.int64) - want[:, 0].astype(np.int64))
-        d = np.where(d > q0 // 2, d - q0, np.where(d < -(q0 // 2), d + q0, d))
-        assert np.abs(d).max() <= 1
+        # every q and p row: the residues of one integer polynomial that differs from
+        # the oracle's encoding by at most one unit per coefficient, the same
+        # difference on every row (both sides round in FP64, in different orders)
+        d0 = None
+        for j, q in enumerate(prm.q[:level] + prm.p):
+            d = (got[:, j].astype(np.int64) - want[:, j].astype(np.int64))
+            d = np.where(d > q // 2, d - q, np.where(d < -(q // 2), d + q, d))
+            assert np.abs(d).max() <= 1, j
+            if d0 is None:
+                d0 = d
+            assert np.array_equal(d, d0), j
+        assert np.mean(d0 != 0) < 1e-3
         cts = [cl.encrypt_slots(s, level, prm.scale) for s in xs]
         res = lay.apply(cts, [level] * len(cts))
         dec = np.stack([cl.decrypt_slots(r, level - 1, prm.scale ** 2 / prm.q[level - 1]).real for r in res])
@@ -508,3 +516,62 @@ def test_reserved_workspace_then_apply_allocates_nothing(F):
             assert np.array_equal(got[t], want), t
     finally:
         lay.close()
+
+
+# ---------------------------------------------------------------------------
+# the benchmark's moduli layout at a small ring: 12 + 3 primes, dnum 4 (alpha 3)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("dh", [False, True])
+def test_fc_four_digits_multi_client(F, dh):
+    """N = 2^12 with the batched FC workload's modulus layout (12 q + 3 p of 50 bits,
+    dnum 4, so levels 10..12 switch keys with 4 digits and 7..9 with 3), BSGS 16 x 8,
+    requests of three clients at levels 12, 11, 10, 9, 8, 7, 4 and 1 in one call:
+    every output bit-exact against the oracle under the same schedule, decrypting to
+    the FP64 layer within 1e-3 (level 1 has no prime to rescale by and is run
+    without rescale in a second call)."""
+    print(f"four digits multi-client dh={dh}", flush=True)
+    prm = O.make_params(12, 12, 3, 4, 50, 2.0 ** 40)
+    assert prm.alpha == 3 and prm.beta(12) == 4 and prm.beta(9) == 3
+    st = synth.Stream(4950 + dh)
+    n, n1 = 128, 16
+    W = st.he_normal((n, n), n)
+    sched = O.fc_schedule(n, n1)
+    pts = encode_pts(prm, O.fc_slots(W, n, n1, prm.S), prm.L, prm.scale)
+    clients = [Client(prm, 4960 + i) for i in range(3)]
+    keysets = [cl.keyset(sched.rotations()) for cl in clients]
+    owner = [0, 1, 2, 1, 0, 2, 0]
+    levels = [12, 11, 10, 9, 8, 7, 4]
+    xs = [st.uniform(n, 0, 1) for _ in owner]
+    cts = [clients[o].encrypt_slots(O.fc_input_slots(x, n, prm.S), l, prm.scale) for o, x, l in zip(owner, xs, levels)]
+    ctx = ctx_for(F, prm)
+    try:
+        plan = F.fhelin_plan_create(ctx, F.FHELIN_LAYER_FC, fc_n=n, fc_out=n, fc_in=n, n1=n1)
+        handles = [F.fhelin_keyset_load(ctx, ks.galois, prm.L, dev(keys_at(prm, ks, prm.L))) for ks in keysets]
+        pset = F.fhelin_pt_import(ctx, dev(pts.reshape(-1, prm.L + prm.K, prm.N)), level=prm.L)
+        x = dev(pad_cts(cts, prm.L, prm.N))
+        y = dev(np.zeros((len(cts), 2, prm.L, prm.N), np.uint64))
+        hd = F.FHELIN_APPLY_HOIST_MODDOWN if dh else 0
+        F.fhelin_linear_apply_multi(ctx, plan, [handles[o] for o in owner], pset, x, levels, y,
+                                    [l - 1 for l in levels], F.FHELIN_APPLY_RESCALE | hd)
+        got = host(y)
+        for t, (o, l) in enumerate(zip(owner, levels)):
+            want = O.rescale(prm, O.linear(prm, cts[t][None], l, sched, pts, keysets[o], hoist_moddown=dh)[0], l)
+            assert np.array_equal(got[t, :, : l - 1], want), (t, l)
+            z = clients[o].decrypt_slots(got[t, :, : l - 1], l - 1, prm.scale ** 2 / prm.q[l - 1]).real
+            assert _rel(z[:n], W @ xs[t]) < 1e-3, (t, l)
+        # a level-1 request (one digit, one prime) beside a level-12 one, no rescale
+        x1 = st.uniform(n, 0, 1)
+        c1 = clients[1].encrypt_slots(O.fc_input_slots(x1, n, prm.S), 1, prm.scale)
+        x2 = dev(pad_cts([c1, cts[0]], prm.L, prm.N))
+        y2 = dev(np.zeros((2, 2, prm.L, prm.N), np.uint64))
+        F.fhelin_linear_apply_multi(ctx, plan, [handles[1], handles[0]], pset, x2, [1, 12], y2, [1, 12], hd)
+        got2 = host(y2)
+        assert np.array_equal(got2[0, :, :1], O.linear(prm, c1[None], 1, sched, pts, keysets[1], hoist_moddown=dh)[0])
+        assert np.array_equal(got2[1, :, :12], O.linear(prm, cts[0][None], 12, sched, pts, keysets[0],
+                                                         hoist_moddown=dh)[0])
+        F.fhelin_ptset_release(pset)
+        for h in handles:
+            F.fhelin_keyset_release(h)
+        F.fhelin_plan_destroy(plan)
+    finally:
+        F.fhelin_ctx_destroy(ctx)

@@ -116,6 +116,25 @@ def test_ntt_naive_is_evaluation(log_n):
     assert np.array_equal(O.intt_naive(A, log_n, q), a)
 
 
+def test_ntt_naive_at_is_evaluation():
+    """The single-output form of the definition (the checker of the sampled NTT
+    comparisons at N = 2^15, 2^16) against polynomial evaluation in Python integers
+    at sampled k of a 2^15 ring with a 50-bit prime, and against the full-transform
+    routine on every k of a 2^9 ring."""
+    for log_n, bits, ks in ((15, 50, (0, 1, 12345, (1 << 15) - 1)), (9, 50, range(1 << 9))):
+        q = O.gen_primes(log_n, bits, 1)[0]
+        psi = O.min_root(q, log_n)
+        rng = np.random.default_rng(100 + log_n)
+        a = rng.integers(0, q, 1 << log_n, dtype=np.uint64)
+        full = O.ntt_naive(a, log_n, q) if log_n <= 9 else None
+        for k in ks:
+            got = O.ntt_naive_at(a, k, log_n, q, psi)
+            if full is not None:
+                assert got == int(full[k]), k
+            else:
+                assert got == _eval_py(a, pow(psi, 2 * _brv(k, log_n) + 1, q), q), k
+
+
 def _schoolbook_py(a, b, q):
     n = len(a)
     c = [0] * n
