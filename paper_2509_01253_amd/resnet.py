@@ -72,6 +72,47 @@ def conv_channel_babies(spec: LayerSpec, slots: int) -> int:
     return n1
 
 
+def shuffle_perms(specs, stream) -> dict:
+    """Seeded channel (conv) / neuron (FC) permutations of every layer, as
+    {name: (perm_out, perm_in)} for fhelin_plan_encode_weights (paper Sec. 4.4:
+    each round's weights fold this round's shuffle sigma_r of the outputs and the
+    unshuffle sigma_{r-1}^-1 of the previous round's outputs).
+
+    The client holds every activation in its shuffled order a'[t] = a[sigma[t]]
+    and never learns sigma: ReLU, the stride subsampling and the average pool act
+    per channel and commute with a channel permutation.  A residual addition needs
+    both operands under the same permutation, so the conv whose output is added to
+    a block's skip path (c2) takes the skip path's permutation: the block input's
+    in an identity block, the downsampling conv's (drawn fresh) otherwise.  The
+    stem's input is the image in its own order (sigma_0 = id) and the final FC's
+    output is not shuffled (the client reads the logits; paper Sec. 5)."""
+    perm = {}
+    cur = None  # permutation of the activation entering the next layer (None = identity)
+    by = {s.name: s for s in specs}
+    order = [s.name for s in specs]
+    stem = by["stem"]
+    perm["stem"] = (stream.permutation(stem.c_out), None)
+    cur = perm["stem"][0]
+    names = order[1:-1]
+    i = 0
+    while i < len(names):
+        c1, c2 = by[names[i]], by[names[i + 1]]
+        ds = by[names[i + 2]] if i + 2 < len(names) and names[i + 2].endswith("ds") else None
+        p1 = stream.permutation(c1.c_out)
+        perm[c1.name] = (p1, cur)
+        if ds is not None:
+            pskip = stream.permutation(ds.c_out)
+            perm[ds.name] = (pskip, cur)
+            i += 3
+        else:
+            pskip = cur
+            i += 2
+        perm[c2.name] = (pskip, p1)
+        cur = pskip
+    perm["fc"] = (None, cur)
+    return perm
+
+
 def init_weights(specs, stream) -> dict:
     """He-normal weights (batch norm folded), seeded."""
     W = {}
@@ -147,7 +188,7 @@ class EncryptedStack:
     client.keys(galois list, level) -> evk device tensor in the ABI layout."""
 
     def __init__(self, F, ctx, log_n, specs, weights, client, level: int, scale: float, q_level_top: int,
-                 flags, stream):
+                 flags, stream, perms=None):
         import torch
 
         self.F, self.ctx, self.torch = F, ctx, torch
@@ -166,7 +207,10 @@ class EncryptedStack:
                                             n1=min(16, sp.fc_n))
             info = F.fhelin_plan_info(plan)
             Wd = torch.from_numpy(np.ascontiguousarray(weights[sp.name])).cuda()
-            pts = F.fhelin_plan_encode_weights(ctx, plan, Wd, None, None, level, scale)
+            po, pi = (perms or {}).get(sp.name, (None, None))
+            po = None if po is None else torch.from_numpy(np.ascontiguousarray(po, np.int32)).cuda()
+            pi = None if pi is None else torch.from_numpy(np.ascontiguousarray(pi, np.int32)).cuda()
+            pts = F.fhelin_plan_encode_weights(ctx, plan, Wd, po, pi, level, scale)
             gal = F.fhelin_plan_galois(plan)
             ks = F.fhelin_keyset_load(ctx, gal, level, client.keys(gal, level)) if gal else None
             x = torch.zeros((info["n_in"], 2, level, self.N), dtype=torch.int64, device="cuda")

@@ -2,7 +2,9 @@
 resolution so the test stays small; same structure: stem, four stages with
 strided and downsampling convs, FC): one captured graph per layer, replayed
 for two inferences; client decrypt / ReLU / residual / re-encrypt between
-rounds.  The decrypted logits match the FP64 network, and one layer's output
+rounds.  Every layer folds its seeded channel shuffle and the previous round's
+unshuffle into its weights, so the client only ever holds shuffled activations;
+the decrypted logits still match the FP64 network, and one layer's output
 ciphertext is checked bit-for-bit against the oracle."""
 import numpy as np
 import pytest
@@ -46,13 +48,18 @@ def test_resnet_stack_graphs():
     ctx = F.fhelin_ctx_create(prm.log_n, prm.q, prm.p, prm.dnum)
     stream = torch.cuda.Stream()
     flags = F.FHELIN_APPLY_RESCALE | F.FHELIN_APPLY_HOIST_MODDOWN
+    perms = resnet.shuffle_perms(specs, st.sub(synth.TAG_PERM))
     stack = resnet.EncryptedStack(F, ctx, prm.log_n, specs, W, client, level, prm.scale, prm.q[level - 1], flags,
-                                  stream)
+                                  stream, perms=perms)
+
+    def plain(spec, a):  # the FP64 layer, unshuffled: the oracle's convolution / matrix product
+        return O.conv_ref(W[spec.name], a) if spec.kind == "conv" else W[spec.name] @ a
+
     try:
         fw = resnet.Forward(specs, W)
         for img in range(2):
             x = st.sub(synth.TAG_X).sub(img).uniform(3 * 256, 0, 1).reshape(3, 16, 16)
-            want = fw.run(x, fw.plain_linear)
+            want = fw.run(x, plain)
             got = fw.run(x, stack.linear)
             err = np.abs(got - want).max() / np.abs(want).max()
             print(f"image {img}: logits rel err {err:.2e}", flush=True)

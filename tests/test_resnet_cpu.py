@@ -54,3 +54,43 @@ def test_forward_matches_direct_resnet():
             h = relu(y + sc)
     want = W["fc"] @ h.mean(axis=(1, 2))
     assert np.allclose(got, want)
+
+
+def test_shuffled_rounds_give_the_same_logits():
+    """With every layer's seeded shuffle and the previous round's unshuffle folded
+    into its weights (W'[t][u] = W[perm_out[t]][perm_in[u]], the oracle's folding),
+    the client works on shuffled activations only -- ReLU, residual additions,
+    subsampling and pooling in shuffled order -- and still receives the network's
+    logits; intermediate activations are the true ones permuted (the client sees no
+    channel order), and every layer but the FC shuffles its output."""
+    st = synth.Stream(78)
+    specs = resnet.resnet18_layers(h=8, w=8, widths=(4, 8, 8, 16), n_classes=10)
+    W = resnet.init_weights(specs, st.sub(synth.TAG_W))
+    perms = resnet.shuffle_perms(specs, st.sub(synth.TAG_PERM))
+    assert set(perms) == {s.name for s in specs}
+    assert perms["stem"][1] is None and perms["fc"][0] is None
+    for s in specs[:-1]:
+        assert sorted(perms[s.name][0]) == list(range(s.c_out))
+    fw = resnet.Forward(specs, W)
+    x = st.uniform(3 * 64, 0, 1).reshape(3, 8, 8)
+    seen = {}
+
+    def shuffled(spec, a):
+        po, pi = perms[spec.name]
+        Wp = O.fold_permutations(W[spec.name], po, pi)
+        out = O.conv_ref(Wp, a) if spec.kind == "conv" else Wp @ a
+        seen[spec.name] = out
+        return out
+
+    def plain(spec, a):
+        out = O.conv_ref(W[spec.name], a) if spec.kind == "conv" else W[spec.name] @ a
+        seen["plain_" + spec.name] = out
+        return out
+
+    got = fw.run(x, shuffled)
+    want = fw.run(x, plain)
+    assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
+    # the stem's output reaches the client permuted, not in the true order
+    p = perms["stem"][0]
+    assert np.allclose(seen["stem"], seen["plain_stem"][p])
+    assert not np.allclose(seen["stem"], seen["plain_stem"])
