@@ -81,12 +81,19 @@ def test_measured_traffic_only_for_the_measured_library_and_workload(tmp_path, m
 
 def test_algorithmic_bytes_closed_form():
     N, K, alpha = 1 << 16, 3, 3
-    # level 4: beta = 2 digits; one key switch reads 2 * 2 * (4 + 3) key limbs and moves
-    # 2 + 2 ciphertext limbs per level; a MAC reads one plaintext limb per level
-    assert bench.algo_bytes(4, 1, 0, K, alpha, N) == (2 * 2 * 7 + 4 * 4) * N * 8
-    assert bench.algo_bytes(4, 0, 1, K, alpha, N) == 4 * N * 8
+    # level 4: beta = 2 digits.  A hoisted baby rotation reads its key, 2 * 2 * (4 + 3)
+    # limbs, and writes 2 * 4 output limbs; a giant rotation (a full key switch) reads the
+    # key and moves 2 + 2 ciphertext limbs per level; a MAC reads one plaintext limb per level
+    assert bench.algo_bytes(4, 1, 0, 0, K, alpha, N) == (2 * 2 * 7 + 2 * 4) * N * 8
+    assert bench.algo_bytes(4, 0, 1, 0, K, alpha, N) == (2 * 2 * 7 + 4 * 4) * N * 8
+    assert bench.algo_bytes(4, 0, 0, 1, K, alpha, N) == 4 * N * 8
     # level 3 needs one digit, level 4 two
-    assert bench.algo_bytes(3, 1, 0, K, alpha, N) == (2 * 1 * 6 + 4 * 3) * N * 8
+    assert bench.algo_bytes(3, 0, 1, 0, K, alpha, N) == (2 * 1 * 6 + 4 * 3) * N * 8
     # linear in the counts
-    assert bench.algo_bytes(12, 40, 256, K, alpha, N) == \
-        40 * bench.algo_bytes(12, 1, 0, K, alpha, N) + 256 * bench.algo_bytes(12, 0, 1, K, alpha, N)
+    assert bench.algo_bytes(12, 31, 7, 256, K, alpha, N) == \
+        31 * bench.algo_bytes(12, 1, 0, 0, K, alpha, N) + 7 * bench.algo_bytes(12, 0, 1, 0, K, alpha, N) + \
+        256 * bench.algo_bytes(12, 0, 0, 1, K, alpha, N)
+    # the survey's per-unit figures at level 12 (beta 4): hoisted extra rotation 60 MiB of key
+    # plus 12 MiB out; full key switch 84 MiB
+    assert bench.algo_bytes(12, 1, 0, 0, K, alpha, N) == (60 + 12) << 20
+    assert bench.algo_bytes(12, 0, 1, 0, K, alpha, N) == 84 << 20
