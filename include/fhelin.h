@@ -250,6 +250,25 @@ int fhelin_linear_apply_multi(fhelin_ctx *ctx, const fhelin_plan *plan, const fh
                               const fhelin_ptset *pts, const fhelin_ct_batch *in, const fhelin_ct_batch *out,
                               int32_t flags, void *stream);
 
+/* Allocation-free fhelin_linear_apply, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments, checks and results as fhelin_linear_apply
+ * (bit for bit), but the layer's intermediate buffers live in a fixed scratch
+ * array of 256 MiB per GPU inside the library (reserved when the library's code
+ * is loaded on the device, held until the process ends) instead of the stream's
+ * workspace: the call performs no hipMalloc, hipFree or other device allocation.
+ * Requests are processed in chunks that fit the scratch; a layer of which one
+ * request needs more than 256 MiB (fhelin_plan_workspace_bytes with n_requests
+ * 1) is rejected with FHELIN_E_UNSUPPORTED_PARAM before any kernel is launched --
+ * at N = 2^16 that is every layer, at N = 2^15 a multiplexed conv at level 8
+ * fits.  Every call on a GPU shares that GPU's scratch and leaves its contents
+ * behind: calls that may overlap in time on one GPU (other streams, other
+ * threads, other contexts) race and must be serialised by the caller.  With
+ * profiling enabled (fhelin_profile_enable) the call records HIP events. */
+int fhelin_linear_apply_noalloc(fhelin_ctx *ctx, const fhelin_plan *plan, const fhelin_keyset *ks,
+                                const fhelin_ptset *pts, const fhelin_ct_batch *in, const fhelin_ct_batch *out,
+                                int32_t flags, void *stream);
+
 /* Tile and chunk choices of a plan's schedule.  They change speed only: every
  * choice gives bit-identical results.
  *   chunk   requests per chunk, 0 = as many as 64 ciphertexts allow (a smaller

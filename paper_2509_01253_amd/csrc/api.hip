@@ -9,7 +9,8 @@ int primes_generate(int log_n, int bits, int count, uint64_t *out);
 const char *last_error();
 int plan_create(Ctx *c, const fhelin_layer_desc *d, Plan **out);
 int linear_apply(Ctx *c, const Plan *p, const KeySet *const *kss, const PtSet *pts, const fhelin_ct_batch *in,
-                 const fhelin_ct_batch *out, int flags, hipStream_t s, int max_chunk);
+                 const fhelin_ct_batch *out, int flags, hipStream_t s, int max_chunk, uint64_t *fixed_ws = nullptr,
+                 size_t fixed_bytes = 0);
 size_t linear_workspace_bytes(const Ctx *c, const Plan *p, int n_requests, int max_chunk, int flags);
 int plan_autotune(Ctx *c, Plan *p, const KeySet *const *kss, const PtSet *pts, const fhelin_ct_batch *in,
                   const fhelin_ct_batch *out, int flags, hipStream_t s, Tune *best_out, double *best_ms);
@@ -172,6 +173,60 @@ static int ntt_rows(Ctx *c, uint64_t *rows, const int32_t *mods, int n_rows, int
     return rc;
 }
 
+// ---------------------------------------------------------------------------
+// fixed device scratch of the allocation-free layer call
+// ---------------------------------------------------------------------------
+// One array per GPU, held until the process ends.  Host code never uses the array's
+// name as an address (on the host it is only a stand-in for the symbol): the device
+// address of each GPU's copy comes from hipGetSymbolAddress with that GPU current,
+// once per device, and is kept in scratch_ptr.
+constexpr size_t SCRATCH_BYTES = (size_t)256 << 20;
+constexpr int SCRATCH_MAX_DEVICES = 64;
+static __device__ __align__(256) uint64_t scratch[SCRATCH_BYTES / sizeof(uint64_t)];
+static std::mutex scratch_mu;
+static uint64_t *scratch_ptr[SCRATCH_MAX_DEVICES];
+
+// With `device` current: look up (once) the device address of its scratch array.
+static int scratch_init(int device) {
+    FL_CHECK(device >= 0 && device < SCRATCH_MAX_DEVICES, FHELIN_E_UNSUPPORTED_PARAM, "device index out of range");
+    std::lock_guard<std::mutex> g(scratch_mu);
+    if (scratch_ptr[device]) return FHELIN_OK;
+    void *ptr = nullptr;
+    FL_TRY_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    FL_CHECK(ptr != nullptr, FHELIN_E_HIP, "hipGetSymbolAddress returned a null scratch address");
+    scratch_ptr[device] = (uint64_t *)ptr;
+    return FHELIN_OK;
+}
+
+static int linear_apply_noalloc(Ctx *c, const Plan *p, const KeySet *ks, const PtSet *pts, const fhelin_ct_batch *in,
+                                const fhelin_ct_batch *out, int flags, hipStream_t s) {
+    FL_CHECK(p && in && out, FHELIN_E_INVALID_ARG, "linear_apply_noalloc: null argument");
+    FL_CHECK(p->n_in >= 1 && in->n_ct % p->n_in == 0, FHELIN_E_INVALID_ARG,
+             "input count is not a multiple of the plan's n_in");
+    const int R = in->n_ct / p->n_in;
+    FL_CHECK(out->n_ct == R * p->n_out, FHELIN_E_INVALID_ARG, "output count must be requests * n_out");
+    uint64_t *ws;
+    {
+        std::lock_guard<std::mutex> g(scratch_mu);
+        ws = scratch_ptr[c->device];
+    }
+    FL_CHECK(ws != nullptr, FHELIN_E_HIP, "fixed scratch of the device not initialised");
+    // requests in groups of at most MAX_BATCH (one key-set pointer each, on the stack)
+    const KeySet *kss[MAX_BATCH];
+    for (int r = 0; r < MAX_BATCH; ++r) kss[r] = ks;
+    const int64_t in_es = (int64_t)2 * in->stride * c->N, out_es = (int64_t)2 * out->stride * c->N;
+    for (int r0 = 0; r0 < R || r0 == 0; r0 += MAX_BATCH) {
+        const int n = std::min(MAX_BATCH, R - r0);
+        fhelin_ct_batch bi{in->data + (int64_t)r0 * p->n_in * in_es, n * p->n_in, in->stride,
+                           in->levels + (int64_t)r0 * p->n_in};
+        fhelin_ct_batch bo{out->data + (int64_t)r0 * p->n_out * out_es, n * p->n_out, out->stride,
+                           out->levels + (int64_t)r0 * p->n_out};
+        FL_RET(linear_apply(c, p, kss, pts, &bi, &bo, flags, s, MAX_BATCH, ws, SCRATCH_BYTES));
+        if (R == 0) break;
+    }
+    return FHELIN_OK;
+}
+
 }  // namespace fl
 
 using namespace fl;
@@ -198,8 +253,15 @@ FHELIN_EXPORT int fhelin_primes_generate(int32_t log_n, int32_t bits, int32_t co
 FHELIN_EXPORT int fhelin_ctx_create(const fhelin_params *prm, fhelin_ctx **out) {
     API_BEGIN Ctx *c = nullptr;
     int rc = ctx_create(prm, &c);
-    if (rc == FHELIN_OK) *out = (fhelin_ctx *)c;
-    return rc;
+    if (rc != FHELIN_OK) return rc;
+    // the context's device is current here: find its fixed scratch (allocation-free calls)
+    rc = scratch_init(c->device);
+    if (rc != FHELIN_OK) {
+        ctx_destroy(c);
+        return rc;
+    }
+    *out = (fhelin_ctx *)c;
+    return FHELIN_OK;
     API_END
 }
 
@@ -465,6 +527,17 @@ FHELIN_EXPORT int fhelin_plan_autotune(fhelin_ctx *ctx, fhelin_plan *plan, const
     }
     if (best_ms) *best_ms = ms;
     return FHELIN_OK;
+    API_END
+}
+
+FHELIN_EXPORT int fhelin_linear_apply_noalloc(fhelin_ctx *ctx, const fhelin_plan *plan, const fhelin_keyset *ks,
+                                              const fhelin_ptset *pts, const fhelin_ct_batch *in,
+                                              const fhelin_ct_batch *out, int32_t flags, void *stream) {
+    API_BEGIN FL_CHECK(ctx, FHELIN_E_INVALID_ARG, "null context");
+    Ctx *c = (Ctx *)ctx;
+    DeviceGuard g(c);
+    return linear_apply_noalloc(c, (const Plan *)plan, (const KeySet *)ks, (const PtSet *)pts, in, out, flags,
+                                (hipStream_t)stream);
     API_END
 }
 

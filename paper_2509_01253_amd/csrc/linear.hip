@@ -728,8 +728,11 @@ static int apply_chunk_dh(Ctx *c, const Plan *p, const KeySet *const *kss, const
     return export_out(c, bout, Y, out, (int64_t)r0 * p->n_out, rescale, s);
 }
 
+// fixed_ws / fixed_bytes: a caller-provided scratch buffer instead of the stream's workspace
+// (nothing is allocated then; the chunk shrinks until it fits, results do not depend on it)
 int linear_apply(Ctx *c, const Plan *p, const KeySet *const *kss, const PtSet *pts, const fhelin_ct_batch *in,
-                 const fhelin_ct_batch *out, int flags, hipStream_t s, int max_chunk) {
+                 const fhelin_ct_batch *out, int flags, hipStream_t s, int max_chunk, uint64_t *fixed_ws,
+                 size_t fixed_bytes) {
     FL_CHECK(c && p && pts && in && out, FHELIN_E_INVALID_ARG, "linear_apply: null argument");
     FL_RET(check_batch(c, in, "linear_apply input"));
     FL_RET(check_batch(c, out, "linear_apply output"));
@@ -771,12 +774,21 @@ int linear_apply(Ctx *c, const Plan *p, const KeySet *const *kss, const PtSet *p
     MacArgs ma{};
     int Bp = 0;
     for (int b = 0; b < B; ++b) ma.bmap[b] = galois_of_rotation(p->rb[b], c->log_n) == 1 ? -1 : Bp++;
-    const int chunk = chunk_of(p, R, max_chunk);
+    int chunk = chunk_of(p, R, max_chunk);
     uint64_t *ws;
     const bool dh = flags & FHELIN_APPLY_HOIST_MODDOWN;
-    FL_RET(workspace_get(c, s, (dh ? limbs_per_request_dh(c, p, Bp) : limbs_per_request(c, p, Bp)) * chunk * N *
-                                   sizeof(uint64_t),
-                         &ws));
+    const size_t per_request =
+        (dh ? limbs_per_request_dh(c, p, Bp) : limbs_per_request(c, p, Bp)) * (size_t)N * sizeof(uint64_t);
+    if (fixed_ws) {
+        const size_t fit = fixed_bytes / per_request;
+        FL_CHECK(fit >= 1, FHELIN_E_UNSUPPORTED_PARAM,
+                 "one request of this layer needs " + std::to_string(per_request) + " bytes of scratch; the fixed "
+                 "scratch holds " + std::to_string(fixed_bytes));
+        chunk = std::min<int>(chunk, (int)std::min<size_t>(fit, MAX_BATCH));
+        ws = fixed_ws;
+    } else {
+        FL_RET(workspace_get(c, s, per_request * chunk, &ws));
+    }
 
     const int64_t ct = 2 * L * N, dg = (int64_t)c->dnum * (L + K) * N;
     if (dh) {
@@ -874,11 +886,11 @@ int linear_apply(Ctx *c, const Plan *p, const KeySet *const *kss, const PtSet *p
 static int time_apply(Ctx *c, const Plan *p, const KeySet *const *kss, const PtSet *pts, const fhelin_ct_batch *in,
                       const fhelin_ct_batch *out, int flags, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
                       double *ms) {
-    FL_RET(linear_apply(c, p, kss, pts, in, out, flags, s, MAX_BATCH));  // warm (workspace, caches)
+    FL_RET(linear_apply(c, p, kss, pts, in, out, flags, s, MAX_BATCH, nullptr, 0));  // warm (workspace, caches)
     float best = 0;
     for (int rep = 0; rep < 2; ++rep) {
         FL_TRY_HIP(hipEventRecord(e0, s));
-        FL_RET(linear_apply(c, p, kss, pts, in, out, flags, s, MAX_BATCH));
+        FL_RET(linear_apply(c, p, kss, pts, in, out, flags, s, MAX_BATCH, nullptr, 0));
         FL_TRY_HIP(hipEventRecord(e1, s));
         FL_TRY_HIP(hipEventSynchronize(e1));
         float t = 0;
@@ -931,7 +943,7 @@ int plan_autotune(Ctx *c, Plan *p, const KeySet *const *kss, const PtSet *pts, c
     }
     p->tune = best;
     // leave `out` holding the layer computed with the chosen tune
-    FL_RET(linear_apply(c, p, kss, pts, in, out, flags, s, MAX_BATCH));
+    FL_RET(linear_apply(c, p, kss, pts, in, out, flags, s, MAX_BATCH, nullptr, 0));
     FL_TRY_HIP(hipStreamSynchronize(s));
     if (best_out) *best_out = best;
     if (best_ms) *best_ms = best_t;

@@ -34,6 +34,16 @@ FHELIN_LAYER_CONV = 2
 FHELIN_APPLY_RESCALE = 1
 FHELIN_APPLY_HOIST_MODDOWN = 2
 
+FHELIN_OK = 0
+FHELIN_E_INVALID_ARG = -1
+FHELIN_E_UNSUPPORTED_PARAM = -2
+FHELIN_E_LEVEL_MISMATCH = -3
+FHELIN_E_MISSING_GALOIS_KEY = -4
+FHELIN_E_OOM = -5
+FHELIN_E_BUDGET = -6
+FHELIN_E_HIP = -7
+FHELIN_E_UNIMPLEMENTED = -8
+
 STATUS = {
     0: "FHELIN_OK", -1: "FHELIN_E_INVALID_ARG", -2: "FHELIN_E_UNSUPPORTED_PARAM", -3: "FHELIN_E_LEVEL_MISMATCH",
     -4: "FHELIN_E_MISSING_GALOIS_KEY", -5: "FHELIN_E_OOM", -6: "FHELIN_E_BUDGET", -7: "FHELIN_E_HIP",
@@ -82,6 +92,8 @@ _SIGS = {
     "fhelin_plan_encode_weights": [_vp, _vp, _vp, _vp, _vp, _i32, _dbl, _vp, _pvp],
     "fhelin_linear_apply": [_vp, _vp, _vp, _vp, ctypes.POINTER(fhelin_ct_batch), ctypes.POINTER(fhelin_ct_batch),
                             _i32, _vp],
+    "fhelin_linear_apply_noalloc": [_vp, _vp, _vp, _vp, ctypes.POINTER(fhelin_ct_batch),
+                                    ctypes.POINTER(fhelin_ct_batch), _i32, _vp],
     "fhelin_plan_workspace_bytes": [_vp, _vp, _i32, _i32, ctypes.POINTER(_u64)],
     "fhelin_plan_reserve_workspace": [_vp, _vp, _i32, _i32, _vp],
     "fhelin_linear_apply_multi": [_vp, _vp, _vp, _vp, ctypes.POINTER(fhelin_ct_batch),
@@ -303,6 +315,14 @@ def fhelin_linear_apply(ctx, plan, ks, pts, x: torch.Tensor, x_levels, y: torch.
                         stream=None):
     bi, bo = ct_batch(x, x_levels), ct_batch(y, y_levels)
     _check(_lib.fhelin_linear_apply(ctx, plan, ks, pts, ctypes.byref(bi), ctypes.byref(bo), flags, _stream(stream)))
+
+
+def fhelin_linear_apply_noalloc(ctx, plan, ks, pts, x: torch.Tensor, x_levels, y: torch.Tensor, y_levels, flags=0,
+                                stream=None):
+    """fhelin_linear_apply with the library's fixed per-GPU scratch (no device allocation)."""
+    bi, bo = ct_batch(x, x_levels), ct_batch(y, y_levels)
+    _check(_lib.fhelin_linear_apply_noalloc(ctx, plan, ks, pts, ctypes.byref(bi), ctypes.byref(bo), flags,
+                                            _stream(stream)))
 
 
 def fhelin_plan_workspace_bytes(ctx, plan, n_requests: int, flags: int) -> int:
