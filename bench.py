@@ -74,6 +74,9 @@ def parse():
     ap.add_argument("--pmc-summary", type=str, default="",
                     help="instead of the benchmark: FETCH,WRITE,CALIB_FETCH,CALIB_WRITE rocprofv3 --pmc output "
                          "directories -> the measured-traffic file used for roofline.traffic")
+    ap.add_argument("--alu-rates", action="store_true",
+                    help="instead of the benchmark: issue rates of the integer ALU instructions the kernels use and "
+                         "of the register-resident NTT butterfly (fhelin_diag_alu_rate)")
     ap.add_argument("--calib-copy", type=float, default=0.0,
                     help="instead of the benchmark: copy this many GiB device-to-device 3 times (traffic-counter "
                          "calibration)")
@@ -82,17 +85,20 @@ def parse():
 
 WORKLOAD = dict(log_n=16, L=12, K=3, dnum=4, bits=50, scale=2.0 ** 40, fc=256, n1=32, lmin=4, lmax=12)
 
-# Integer-ALU ceiling of the NTT butterfly on MI355X: a lazy Shoup butterfly is 24
-# VALU instructions on gfx950 (64-bit products from v_mad_u64_u32 / v_mul_lo_u32 /
-# v_mul_hi_u32, which issue at the full VALU rate), and the chip issues one VALU
-# instruction per lane per clock on 256 CUs x 64 lanes at 2.4 GHz.
-ALU_LANE_OPS = 256 * 64 * 2.4e9
-BFLY_VALU_OPS = 24
+# Integer-ALU ceilings, from the chip's unit counts and clock and from instruction
+# counts of this build: 256 CUs x 4 SIMDs x 16 lanes issue one wave64 VALU instruction
+# per SIMD every 4 clocks at 2.4 GHz (39.3 T lane-instructions/s).  The instructions the
+# butterfly and the multiply-accumulate product compile to (v_mad_u64_u32, v_mul_lo_u32,
+# v_mul_hi_u32, 64-bit shifts, adds) all issue at that rate on MI355X (measured with
+# fhelin_diag_alu_rate, `bench.py --alu-rates`; the register-resident butterfly runs at
+# 100 clocks per wave, 4.0 per instruction).  Instructions per unit, from the gfx950
+# assembly of the probes (`python -m paper_2509_01253_amd.build --isa ...`):
+#   lazy forward butterfly with 53-bit twiddle companions: 400 VALU per 16 = 25;
+#   packed 28-bit product with one Montgomery reduction per 32: 725 VALU per 128 = 5.66.
+ALU_LANE_OPS = 256 * 4 * 16 * 2.4e9
+BFLY_VALU_OPS = 25
 PEAK_BFLY = ALU_LANE_OPS / BFLY_VALU_OPS / 1e12  # T butterflies (= modular multiplies) per second
-# A product of the packed multiply-accumulate is four v_mad_u64_u32 plus one add, and
-# every 16 products end in one ~16-instruction-per-product-share Montgomery reduction
-# of the three partial sums (about 30 instructions): 6 VALU instructions per product.
-MAC_VALU_OPS = 6
+MAC_VALU_OPS = 725 / 128
 PEAK_MAC = ALU_LANE_OPS / MAC_VALU_OPS / 1e12  # T modular products per second
 HBM_PEAK_GBPS = 8000.0
 # roofline of each kernel class: (bound, unit of `achieved`, peak)
@@ -511,6 +517,26 @@ def resnet18_bench(args) -> dict:
             "inferences_per_s": round(B / (total / 1e3), 3), "layers": rows}
 
 
+ALU_PROBES = {0: "v_add_u32", 1: "v_mul_lo_u32", 2: "v_mul_hi_u32", 3: "v_mad_u64_u32", 4: "v_fma_f64",
+              6: "v_lshl_add_u64", 7: "v_lshrrev_b64", 5: "ntt_butterfly", 8: "mac_product"}
+
+
+def alu_rates(F) -> dict:
+    """Clocks per wave-level instruction on one SIMD for the instructions the NTT and
+    multiply-accumulate kernels are built from, and the rate of the register-resident
+    lazy NTT butterfly, at 4 and 8 waves per SIMD (fhelin_diag_alu_rate)."""
+    out = {}
+    for op, name in ALU_PROBES.items():
+        iters = (1 << 14) if op == 5 else (1 << 16) if op == 8 else (1 << 18)
+        for wps in (4, 8):
+            ghz, clk, ops = F.fhelin_diag_alu_rate(op, wps, iters)
+            out.setdefault(name, {})[f"waves_per_simd_{wps}"] = {
+                "ghz": round(ghz, 4), "clk_per_wave_op": round(clk, 3), "lane_ops_per_s": ops}
+            print(f"{name} waves/SIMD {wps}: {ghz:.3f} GHz, {clk:.3f} clk per wave-op, {ops / 1e12:.3f} T/s",
+                  file=sys.stderr, flush=True)
+    return {"alu_rates": out}
+
+
 def main():
     args = parse()
     if args.pmc_summary:
@@ -528,6 +554,9 @@ def main():
     assert torch.cuda.is_available(), "bench needs a GPU"
     if args.resnet18 > 0:
         print(json.dumps({"resnet18": resnet18_bench(args)}))
+        return
+    if args.alu_rates:
+        print(json.dumps(alu_rates(F)), flush=True)
         return
     if args.calib_copy > 0:
         n = int(args.calib_copy * (1 << 30)) // 8

@@ -351,6 +351,23 @@ int fhelin_profile_enable(fhelin_ctx *ctx, int32_t enable);
 int fhelin_profile_read(fhelin_ctx *ctx, const char *kernel, int64_t *launches, double *total_ms, double *units,
                         double *bytes);
 
+/* Issue-rate probe of the GPU's integer ALUs (measures the "alu" rooflines): runs
+ * `iters` rounds (a multiple of 32, at most 2^24) of one operation on 8 independent
+ * register chains per lane, in 256-thread workgroups, waves_per_simd (1..8)
+ * workgroups per compute unit, on the current device (allocates and frees two small
+ * buffers, synchronises the device).  op: 0 v_add_u32, 1 v_mul_lo_u32,
+ * 2 v_mul_hi_u32, 3 v_mad_u64_u32, 4 v_fma_f64 (single instructions), 5 the NTT's
+ * lazy forward butterfly with 53-bit twiddle companions (16 per round, operands in
+ * registers), 6 v_lshl_add_u64, 7 v_lshrrev_b64, 8 one product of the packed 28-bit
+ * multiply-accumulate (four v_mad_u64_u32; one Montgomery reduction per 32
+ * products, operands in registers).  Outputs (each may be NULL):
+ * ghz = core clock measured in the
+ * kernel (clock counter over the constant-rate wall clock); clk_per_op = clocks per
+ * wave-level operation on one SIMD (4 for a wave64 instruction issued at the full
+ * rate); ops_per_s = lane-level operations per second over the whole GPU. */
+int fhelin_diag_alu_rate(int32_t op, int32_t waves_per_simd, int32_t iters, double *ghz, double *clk_per_op,
+                         double *ops_per_s);
+
 const char *fhelin_last_error(void);
 const char *fhelin_status_string(int status);
 

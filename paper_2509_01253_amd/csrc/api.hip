@@ -631,6 +631,12 @@ FHELIN_EXPORT int fhelin_profile_enable(fhelin_ctx *ctx, int32_t enable) {
     API_END
 }
 
+FHELIN_EXPORT int fhelin_diag_alu_rate(int32_t op, int32_t waves_per_simd, int32_t iters, double *ghz,
+                                       double *clk_per_op, double *ops_per_s) {
+    API_BEGIN return diag_alu_rate(op, waves_per_simd, iters, ghz, clk_per_op, ops_per_s);
+    API_END
+}
+
 FHELIN_EXPORT int fhelin_profile_read(fhelin_ctx *ctx, const char *kernel, int64_t *launches, double *total_ms,
                                       double *units, double *bytes) {
     API_BEGIN FL_CHECK(ctx && kernel, FHELIN_E_INVALID_ARG, "null argument");

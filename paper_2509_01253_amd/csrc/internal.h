@@ -442,4 +442,10 @@ int launch_moddown_combine(const Ctx *c, const Batch &b, const uint64_t *u, int6
 int launch_rescale(const Ctx *c, const Batch &b, const uint64_t *in, int64_t in_es, int in_stride, uint64_t *out,
                    int64_t out_es, int out_stride, hipStream_t s);
 
+// diagnostics: issue-rate probes (diag.hip; the butterfly probe lives beside the
+// butterfly in ntt.hip)
+int primes_generate(int log_n, int bits, int count, uint64_t *out);
+void launch_diag_bfly(int blocks, uint64_t *sink, uint64_t *stamps, int iters, uint64_t q, uint64_t w, uint64_t wp);
+int diag_alu_rate(int op, int waves_per_simd, int iters, double *ghz, double *clk_per_op, double *ops_per_s);
+
 }  // namespace fl

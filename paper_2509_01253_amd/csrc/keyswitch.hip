@@ -665,7 +665,13 @@ int launch_ext_lift_add(const Ctx *c, const Batch &b, const uint64_t *src, int64
         lmax = b.level[t] > lmax ? b.level[t] : lmax;
         units += 2.0 * (b.level[t] + c->K) * c->N;
     }
-    ProfScope ps(c, s, PK_COPY, units);
+    // bytes: each output element written once and its source read once (lift: the p slots
+    // are written without a read), plus the read-back of an accumulated destination
+    double bytes = 0;
+    for (int t = 0; t < b.n; ++t)
+        bytes += 8.0 * 2 * c->N * ((b.level[t] + c->K) + (lift ? b.level[t] : b.level[t] + c->K) +
+                                   (accumulate ? b.level[t] + c->K : 0));
+    ProfScope ps(c, s, PK_COPY, units, bytes);
     hipLaunchKernelGGL(k_ext_lift_add, dim3(c->N / 256, 2 * (lmax + c->K), b.n), dim3(256), 0, s, b, c->d_mods,
                        c->d_moddown, src, src_es, src_stride, lift, accumulate, dst, dst_es, c->log_n, c->L, c->K);
     FL_TRY_HIP(hipGetLastError());

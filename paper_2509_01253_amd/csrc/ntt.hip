@@ -520,6 +520,40 @@ static int launch_mont(const Ctx *c, const RowMap &rm, int to, hipStream_t s) {
 }
 
 int launch_to_mont(const Ctx *c, const RowMap &rm, hipStream_t s) { return launch_mont(c, rm, 1, s); }
+
+// ---------------------------------------------------------------------------
+// issue-rate probe of the forward butterfly (diagnostics): 16 register values per
+// thread, each round 16 butterflies (two radix-2 layers of 8 independent ones) with
+// the 53-bit companions, no memory traffic inside the loop
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(NTT_THREADS) k_diag_bfly(uint64_t *__restrict__ sink, uint64_t *__restrict__ stamps,
+                                                           int iters, uint64_t q, uint64_t w, uint64_t wp) {
+    const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+    uint64_t x[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) x[i] = (tid * 0x9E3779B97F4A7C15ull + i) % q;
+    const uint64_t c0 = clock64(), r0 = wall_clock64();
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int b = 0; b < 8; ++b) ct_bfly<true>(x[b], x[b + 8], w, wp, q);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) ct_bfly<true>(x[(b & 3) + (b >> 2) * 8], x[(b & 3) + (b >> 2) * 8 + 4], w, wp, q);
+    }
+    const uint64_t c1 = clock64(), r1 = wall_clock64();
+    if ((threadIdx.x & 63) == 0) {
+        const int wave = tid >> 6;
+        stamps[2 * wave] = c1 - c0;
+        stamps[2 * wave + 1] = r1 - r0;
+    }
+    uint64_t acc = 0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc ^= x[i];
+    sink[tid] = acc;
+}
+
+void launch_diag_bfly(int blocks, uint64_t *sink, uint64_t *stamps, int iters, uint64_t q, uint64_t w, uint64_t wp) {
+    hipLaunchKernelGGL(k_diag_bfly, dim3(blocks), dim3(NTT_THREADS), 0, 0, sink, stamps, iters, q, w, wp);
+}
 int launch_from_mont(const Ctx *c, const RowMap &rm, hipStream_t s) { return launch_mont(c, rm, 0, s); }
 
 }  // namespace fl

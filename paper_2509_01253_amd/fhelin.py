@@ -109,6 +109,7 @@ _SIGS = {
                                     ctypes.POINTER(fhelin_ct_batch), _i32, _vp, _pvp],
     "fhelin_graph_launch": [_vp, _vp],
     "fhelin_graph_destroy": [_vp],
+    "fhelin_diag_alu_rate": [_i32, _i32, _i32, ctypes.POINTER(_dbl), ctypes.POINTER(_dbl), ctypes.POINTER(_dbl)],
     "fhelin_profile_enable": [_vp, _i32],
     "fhelin_profile_read": [_vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
                             ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)],
@@ -403,6 +404,13 @@ def fhelin_ntt(ctx, rows: torch.Tensor, mod_index, inverse: bool, stream=None):
         raise ValueError("rows must be [n_rows][N] with one modulus index per row")
     _check(_lib.fhelin_ntt(ctx, _dev_ptr(rows, _W64, "rows"), ctypes.cast(mi, _vp), rows.shape[0],
                            1 if inverse else 0, _stream(stream)))
+
+
+def fhelin_diag_alu_rate(op: int, waves_per_simd: int, iters: int):
+    """(core GHz, clocks per wave-level op on one SIMD, lane-ops per second) of one probe."""
+    g, c, o = _dbl(), _dbl(), _dbl()
+    _check(_lib.fhelin_diag_alu_rate(op, waves_per_simd, iters, ctypes.byref(g), ctypes.byref(c), ctypes.byref(o)))
+    return g.value, c.value, o.value
 
 
 def fhelin_profile_enable(ctx, enable: bool = True):
