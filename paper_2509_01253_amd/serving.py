@@ -279,6 +279,30 @@ class Server:
         }
 
 
+class SessionShuffler:
+    """The server's secret per-round permutations (paper Sec. 4.4, "Unshuffle" and
+    "Shuffle"): sigma_r of a session's round r permutes that round's n output units
+    (FC neurons or conv channels) and is drawn from a keyed hash (BLAKE2b keyed with
+    the server's secret) of the session id, the round and n, so the server derives it
+    again when round r + 1 arrives and needs sigma_r^-1, and the client, who does not
+    know the secret, cannot.  sigma_0 = identity (the first layer's input is the
+    client's own)."""
+
+    def __init__(self, secret: bytes):
+        if len(secret) < 16:
+            raise ValueError("the shuffle secret needs at least 16 bytes")
+        self.secret = bytes(secret[:64])
+
+    def perm(self, session: str, rnd: int, n: int):
+        """sigma_rnd of `session` on n units (int32 array), None for round 0."""
+        if rnd <= 0:
+            return None
+        import hashlib
+        h = hashlib.blake2b(f"{session}\x00{int(rnd)}\x00{int(n)}".encode(), key=self.secret, digest_size=16)
+        rng = np.random.Generator(np.random.PCG64(int.from_bytes(h.digest(), "little")))
+        return rng.permutation(n).astype(np.int32)
+
+
 def poisson_timeline(rate: float, n: int, stream) -> np.ndarray:
     """Arrival offsets (s) of a Poisson process: cumulative exponential gaps."""
     return np.cumsum(stream.exponential(n, rate))
@@ -287,7 +311,7 @@ def poisson_timeline(rate: float, n: int, stream) -> np.ndarray:
 class GpuExecutor:
     """Executor over the fhelin C ABI (one context per parameter set)."""
 
-    def __init__(self, n_streams: int = 2, flags=None, reserve_requests: int = 0):
+    def __init__(self, n_streams: int = 2, flags=None, reserve_requests: int = 0, shuffler=None):
         import torch
 
         from paper_2509_01253_amd import fhelin as F
@@ -304,6 +328,8 @@ class GpuExecutor:
         # many requests of each layer, so no batch grows it (a grow synchronises the
         # stream and allocates while requests wait)
         self.reserve_requests = reserve_requests
+        # per-round secret permutations of shuffled layers (SessionShuffler)
+        self.shuffler = shuffler
 
     # registration
     def add_params(self, name, log_n, q, p, dnum):
@@ -335,6 +361,36 @@ class GpuExecutor:
                     self.F.fhelin_plan_reserve_workspace(P["ctx"], plan, n, f, stream=st)
                     self.ws[(params, i)] = max(self.ws.get((params, i), 0), need)
 
+    def add_shuffled_layer(self, name, params, plan_kwargs, kind, weights, units_out, units_in, scale,
+                           shuffle_out=True, flags=None):
+        """A layer whose plaintexts are encoded per request on the GPU with the
+        request's session permutations folded in (paper Sec. 4.4): the outputs shuffled
+        by sigma_r (unless shuffle_out is False: the network's last layer) and the
+        previous round's shuffle undone on the inputs by sigma_{r-1}.  weights: device
+        float64 tensor in fhelin_plan_encode_weights' layout; units_out / units_in: the
+        lengths of the two permutations (FC neurons or conv channels).  Requests of
+        such a layer share no plaintexts: each is encoded at the request's level and
+        applied on its own on the batch's stream, and its plaintexts are released when
+        the batch completes."""
+        if self.shuffler is None:
+            raise ValueError("a shuffled layer needs the executor's shuffler")
+        self.add_layer(name, params, plan_kwargs, kind, None, flags)
+        self.layers[name].update(weights=weights, units_out=int(units_out), units_in=int(units_in),
+                                 scale=float(scale), shuffle_out=bool(shuffle_out))
+
+    def request_perms(self, layer, req):
+        """(perm_out, perm_in) folded into `req`'s plaintexts (None = identity)."""
+        Ly = self.layers[layer]
+        po = self.shuffler.perm(req.session, req.round, Ly["units_out"]) if Ly["shuffle_out"] else None
+        pi = self.shuffler.perm(req.session, req.round - 1, Ly["units_in"])
+        return po, pi
+
+    def _pt_bytes(self, layer, level):
+        Ly = self.layers[layer]
+        P = self.params[Ly["params"]]
+        n_pt = self.F.fhelin_plan_info(Ly["plan"])["n_pt"]
+        return n_pt * (level + P["K"]) * P["N"] * 8
+
     def layer_flags(self, layer, n_req):
         """Apply flags of `layer` for a batch of n_req requests."""
         for m, f in self.layers[layer]["flags"]:
@@ -364,7 +420,8 @@ class GpuExecutor:
         Ly = self.layers[layer]
         P = self.params[Ly["params"]]
         per_ct = 2 * P["L"] * P["N"] * 8
-        return len(batch) * (Ly["n_in"] + Ly["n_out"]) * per_ct
+        pts = sum(self._pt_bytes(layer, r.level) for r in batch) if Ly.get("weights") is not None else 0
+        return len(batch) * (Ly["n_in"] + Ly["n_out"]) * per_ct + pts
 
     def workspace_growth(self, layer, n_req, stream):
         Ly = self.layers[layer]
@@ -402,17 +459,34 @@ class GpuExecutor:
             fl = self.layer_flags(layer, len(batch))
             resc = bool(fl & F.FHELIN_APPLY_RESCALE)
             yl = [r.level - (1 if resc else 0) for r in batch for _ in range(Ly["n_out"])]
-            F.fhelin_linear_apply_multi(P["ctx"], Ly["plan"], key_handles, Ly["pts"], x, xl, y, yl, fl, stream=s)
+            own_pts = []
+            if Ly.get("weights") is None:
+                F.fhelin_linear_apply_multi(P["ctx"], Ly["plan"], key_handles, Ly["pts"], x, xl, y, yl, fl, stream=s)
+            else:
+                # per-request plaintexts with the request's permutations folded in
+                ni, no = Ly["n_in"], Ly["n_out"]
+                for i, r in enumerate(batch):
+                    po, pi = self.request_perms(layer, r)
+                    po = None if po is None else torch.from_numpy(po).to(x.device)
+                    pi = None if pi is None else torch.from_numpy(pi).to(x.device)
+                    pts = F.fhelin_plan_encode_weights(P["ctx"], Ly["plan"], Ly["weights"], po, pi, r.level,
+                                                       Ly["scale"], stream=s)
+                    own_pts.append(pts)
+                    F.fhelin_linear_apply_multi(P["ctx"], Ly["plan"], key_handles[i:i + 1], pts,
+                                                x[i * ni:(i + 1) * ni], xl[i * ni:(i + 1) * ni],
+                                                y[i * no:(i + 1) * no], yl[i * no:(i + 1) * no], fl, stream=s)
             ev = torch.cuda.Event()
             ev.record(s)
         key = (Ly["params"], stream)
         self.ws[key] = max(self.ws.get(key, 0), F.fhelin_plan_workspace_bytes(P["ctx"], Ly["plan"], len(batch), fl))
-        return (ev, x, yl), y, self.io_bytes(layer, batch)
+        return (ev, x, yl, own_pts), y, self.io_bytes(layer, batch)
 
     def done(self, token):
         return token[0].query()
 
     def collect(self, token, y, reqs):
+        for pts in token[3]:  # per-request plaintexts: the batch has completed
+            self.F.fhelin_ptset_release(pts)
         n_out = len(token[2]) // len(reqs)
         return [(y[i * n_out:(i + 1) * n_out], token[2][i * n_out]) for i in range(len(reqs))]
 

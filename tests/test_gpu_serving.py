@@ -120,3 +120,86 @@ def test_served_results_equal_alone_and_oracle():
                 ref, out = O.conv_ref(Wcv, x), O.conv_output_from_slots(dec, cs, prm.S)
             assert np.abs(out - ref).max() / np.abs(ref).max() < 1e-3, r.rid
     ex.close()
+
+
+def test_served_shuffled_rounds_fold_the_session_permutations():
+    """Per-session, per-round shuffles (paper Sec. 4.4): each request's plaintexts are
+    encoded on the GPU with its session's sigma_r on the outputs and sigma_{r-1}^-1 on
+    the inputs (the network's last layer unshuffled).  Every served result equals the
+    same request evaluated alone with the same permutations and decrypts to the
+    permuted FP64 layer W'[t][u] = W[sigma_r[t]][sigma_{r-1}[u]] within 1e-3."""
+    import torch
+
+    from paper_2509_01253_amd import fhelin as F
+    from paper_2509_01253_amd.serving import GpuExecutor, Request, Server, SessionShuffler
+    print("serving shuffled rounds", flush=True)
+    st = synth.Stream(synth.master_seed(5)).sub(77)
+    prm = O.make_params(12, 5, 2, 3, 50, 2.0 ** 40)
+    shuf = SessionShuffler(b"server secret for the shuffles of this test")
+    ex = GpuExecutor(n_streams=2, shuffler=shuf)
+    ex.add_params("A", prm.log_n, prm.q, prm.p, prm.dnum)
+    n, n1 = 64, 8
+    W = st.he_normal((n, n), n)
+    Wd = torch.from_numpy(np.ascontiguousarray(W)).cuda()
+    kw = dict(fc_n=n, fc_out=n, fc_in=n, n1=n1)
+    ex.add_shuffled_layer("hidden", "A", kw, F.FHELIN_LAYER_FC, Wd, n, n, prm.scale)
+    ex.add_shuffled_layer("last", "A", kw, F.FHELIN_LAYER_FC, Wd, n, n, prm.scale, shuffle_out=False)
+    sched = O.fc_schedule(n, n1)
+    clients = {}
+    for ci in range(3):
+        cl = Client(prm, 9100 + ci)
+        keys = cl.keyset(sched.rotations())
+        evk = keys_at(prm, keys, prm.L)
+        clients[ci] = (cl, keys)
+        ex.add_client_keys(f"c{ci}", "A", (lambda g=keys.galois, e=evk: (lambda s: (g, prm.L, dev(e))))(),
+                           int(evk.nbytes))
+    srv = Server(ex, hbm_budget=8 << 30, streams=2, max_batch=8)
+    reqs, plain = [], {}
+    for ci in range(3):
+        srv.open_session(f"s{ci}", f"c{ci}")
+    rid = 0
+    for rnd in range(1, 5):  # rounds 1..3 hidden, round 4 the last layer
+        for ci in range(3):
+            cl, keys = clients[ci]
+            level = [5, 4, 3][ci]
+            x = st.uniform(n, 0, 1)
+            ct = cl.encrypt_slots(O.fc_input_slots(x, n, prm.S), level, prm.scale)
+            lname = "hidden" if rnd < 4 else "last"
+            reqs.append((0.0, Request(rid, f"c{ci}", f"s{ci}", rnd, lname, level, dev(pad_cts([ct], prm.L, prm.N)))))
+            plain[rid] = (ci, rnd, lname, ct, level, x)
+            rid += 1
+    torch.cuda.synchronize()
+    res = srv.run(reqs)
+    stats = srv.stats(res)
+    print(stats, flush=True)
+    assert stats["completed"] == 12 and stats["mean_batch"] > 1  # sessions shared launches
+    ctx = ex.params["A"]["ctx"]
+    flags = ex.flags
+    seen = set()
+    for r in res:
+        assert r.status == "ok"
+        ci, rnd, lname, ct, level, x = plain[r.rid]
+        cl, keys = clients[ci]
+        po = shuf.perm(f"s{ci}", rnd, n) if lname == "hidden" else None
+        pi = shuf.perm(f"s{ci}", rnd - 1, n)
+        assert (pi is None) == (rnd == 1)
+        if po is not None:
+            seen.add(tuple(po))
+        got = host(r.y)
+        # alone, with the same permutations and the same GPU encode
+        ks = F.fhelin_keyset_load(ctx, keys.galois, prm.L, dev(keys_at(prm, keys, prm.L)))
+        pts = F.fhelin_plan_encode_weights(ctx, ex.layers[lname]["plan"], Wd,
+                                           None if po is None else torch.from_numpy(po).cuda(),
+                                           None if pi is None else torch.from_numpy(pi).cuda(), level, prm.scale)
+        y1 = dev(np.zeros((1, 2, prm.L, prm.N), np.uint64))
+        F.fhelin_linear_apply(ctx, ex.layers[lname]["plan"], ks, pts, dev(pad_cts([ct], prm.L, prm.N)), [level], y1,
+                              [level - 1], flags)
+        alone = host(y1)
+        F.fhelin_ptset_release(pts)
+        F.fhelin_keyset_release(ks)
+        assert np.array_equal(got[:, :, : level - 1], alone[:, :, : level - 1]), r.rid
+        dec = cl.decrypt_slots(got[0, :, : level - 1], level - 1, prm.scale ** 2 / prm.q[level - 1]).real[:n]
+        ref = O.fold_permutations(W, po, pi) @ x
+        assert np.abs(dec - ref).max() / np.abs(ref).max() < 1e-3, r.rid
+    assert len(seen) == 9  # every (session, hidden round) drew its own permutation
+    ex.close()

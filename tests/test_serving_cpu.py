@@ -4,6 +4,9 @@ LRU eviction of idle key sets, batching of waiting requests across clients,
 and continuous batching (arrivals join later launches while others run)."""
 import itertools
 
+import numpy as np
+import pytest
+
 from paper_2509_01253_amd.serving import Request, Server
 
 
@@ -239,3 +242,21 @@ def test_executor_flags_by_batch_size():
     ex.layers = {"a": {"flags": [(1, 3), (4, 1)]}, "b": {"flags": [(1 << 30, 3)]}}
     assert [ex.layer_flags("a", n) for n in (1, 2, 4, 5, 64)] == [3, 1, 1, 1, 1]
     assert [ex.layer_flags("b", n) for n in (1, 64)] == [3, 3]
+
+
+def test_session_shuffler_permutations():
+    """sigma_r depends on the server secret, the session, the round and the unit
+    count, is a permutation, is reproducible (the server derives it again for the
+    next round's unshuffle), and sigma_0 is the identity."""
+    from paper_2509_01253_amd.serving import SessionShuffler
+    a = SessionShuffler(b"0123456789abcdef-secret")
+    b = SessionShuffler(b"0123456789abcdef-other!")
+    p = a.perm("s1", 3, 256)
+    assert p.dtype == np.int32 and sorted(p.tolist()) == list(range(256))
+    assert np.array_equal(p, a.perm("s1", 3, 256))
+    assert a.perm("s1", 0, 256) is None
+    others = [a.perm("s2", 3, 256), a.perm("s1", 4, 256), b.perm("s1", 3, 256)]
+    assert all(not np.array_equal(p, q) for q in others)
+    assert sorted(a.perm("s1", 3, 16).tolist()) == list(range(16))
+    with pytest.raises(ValueError):
+        SessionShuffler(b"short")
