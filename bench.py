@@ -48,20 +48,24 @@ def parse():
                     help="autotune the plan on the batch before warmup (default: the plan's default tune)")
     ap.add_argument("--no-one-at-a-time", action="store_true",
                     help="skip the extra one-request-at-a-time comparison after the timed steps")
-    ap.add_argument("--serve-requests", type=int, default=0,
-                    help="requests per arrival rate in an extra serving run (default 0 = no serving run)")
-    ap.add_argument("--serve-rates", type=str, default="20,100", help="Poisson arrival rates (req/s)")
+    ap.add_argument("--serve-requests", type=int, default=200,
+                    help="requests per arrival rate in the serving run after the timed steps (0 = no serving run)")
+    ap.add_argument("--serve-rates", type=str, default="100", help="Poisson arrival rates (req/s)")
     ap.add_argument("--serve-clients", type=int, default=32)
-    ap.add_argument("--serve-schedule", choices=["fastest", "hoisted", "rotation"], default="fastest",
-                    help="schedule of each served layer: the faster of the double-hoisted and the per-rotation "
-                         "ModDown schedule timed at the layer's middle level for single requests (used for batches "
-                         "of 1) and for batches of 4 (used for larger batches) (default), or one of them")
+    ap.add_argument("--serve-schedule", choices=["fastest", "hoisted", "rotation"], default="hoisted",
+                    help="schedule of each served layer: one of the two for every batch (default: the "
+                         "double-hoisted one, so a request's result is bit-identical however it is batched), or "
+                         "'fastest': the faster of the two timed at the layer's middle level for single requests "
+                         "(used for batches of 1) and for batches of 4 (used for larger batches)")
     ap.add_argument("--serve-reserve", type=int, default=64,
                     help="requests per batch the serving executor sizes every stream's workspace for at start-up "
                          "(0: grow on demand when a larger batch arrives)")
     ap.add_argument("--serve-streams", type=str, default="2",
                     help="streams (batches in flight at once) of the continuous-batching server; a comma list "
                          "runs one server per value")
+    ap.add_argument("--with-resnet18", type=int, default=1,
+                    help="after the timed steps, also time the ResNet-18-shaped stack (see --resnet18) for this many "
+                         "inferences per batch and report it under 'resnet18' (0 = skip)")
     ap.add_argument("--resnet18", type=int, default=0,
                     help="instead of the FC benchmark: time every linear layer of the ResNet-18-shaped stack on "
                          "64x64x3 inputs at N=2^16, level 3, for this many inferences per batch")
@@ -238,6 +242,65 @@ def cpu_baseline(level: int, n1: int, hoisted: bool) -> dict:
                       f"schedule, 256 pt-MACs, rescale) at level {level} of the N=2^16 workload; {dt:.1f} s"}
 
 
+def cpu_baseline_more() -> dict:
+    """The oracle on the other workloads: the plain 64x64 FC at N=2^12 and the
+    ResNet-20-block convolution at N=2^15, level 8, as whole layers (layers/s), and
+    the ResNet-18-shaped stack at N=2^16, level 3, extrapolated from one key-switched
+    rotation, one plaintext-ciphertext product and one rescale at level 3 times the
+    stack's counts (5273 rotations, 91712 products, 21 rescales)."""
+    from oracle import oracle as O
+    from paper_2509_01253_amd import synth
+
+    st = synth.Stream(synth.master_seed(3)).sub(98)
+
+    def keys(prm, sched):
+        gal = sorted({O.galois_of(r, prm.log_n) for r in sched.rotations()} - {1})
+        return O.KeySet(gal, np.stack([np.stack([np.stack([synth.uniform_limbs(st, prm.mods, prm.N)
+                                                           for _ in range(2)]) for _ in range(prm.dnum)])
+                                       for _ in gal]))
+
+    def layer(prm, sched, level):
+        ks = keys(prm, sched)
+        n_pt = sched.n_out * sched.n_in * sched.G * sched.B
+        pts = np.stack([synth.uniform_limbs(st, prm.q[:level] + prm.p, prm.N) for _ in range(n_pt)])
+        pts = pts.reshape(sched.n_out, sched.n_in, sched.G, sched.B, level + prm.K, prm.N)
+        cts = np.stack([np.stack([synth.uniform_limbs(st, prm.q[:level], prm.N) for _ in range(2)])
+                        for _ in range(sched.n_in)])
+        t0 = time.perf_counter()
+        ys = O.linear(prm, cts, level, sched, pts, ks)
+        for y in ys:
+            O.rescale(prm, y, level)
+        return time.perf_counter() - t0
+
+    out = {}
+    t = layer(O.make_params(12, 3, 1, 3, 36, 2.0 ** 30), O.fc_schedule(64, 64), 3)
+    out["fc64_n4096"] = {"layers_per_s": 1.0 / t, "s": t, "kind": "measured",
+                         "workload": "plain 64x64 FC (63 rotations, 64 pt-MACs), N=2^12, level 3, rescale"}
+    t = layer(O.make_params(15, 8, 2, 4, 50, 2.0 ** 40), O.conv_schedule(O.ConvShape(16, 16, 32, 32, 3), 1 << 14), 8)
+    out["conv16_n32768"] = {"layers_per_s": 1.0 / t, "s": t, "kind": "measured",
+                            "workload": "conv 3x3 16->16 @32x32 (8 + 15 rotations, 144 pt-MACs), N=2^15, level 8"}
+    prm = O.make_params(16, 12, 3, 4, 50, 2.0 ** 40)
+    g = O.galois_of(1, 16)
+    evk = keys(prm, O.fc_schedule(2, 1)).evk[0]
+    ct = np.stack([synth.uniform_limbs(st, prm.q[:3], prm.N) for _ in range(2)])
+    pt = synth.uniform_limbs(st, prm.q[:3], prm.N)
+    t0 = time.perf_counter()
+    O.rotate(prm, ct, g, evk, 3)
+    t_ks = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    O.mul_pt(prm, ct, pt, 3)
+    t_mac = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    O.rescale(prm, ct, 3)
+    t_rs = time.perf_counter() - t0
+    stack = 5273 * t_ks + 91712 * t_mac + 21 * t_rs
+    out["resnet18_stack_n65536"] = {"inferences_per_s": 1.0 / stack, "s": stack, "kind": "extrapolated",
+                                    "from": {"rotation_s": t_ks, "pt_mac_s": t_mac, "rescale_s": t_rs},
+                                    "workload": "21 linear layers of the ResNet-18-shaped stack at level 3: "
+                                                "5273 rotations, 91712 pt-MACs, 21 rescales"}
+    return out
+
+
 def fastest_schedule(F, ctx, plan, pts, sched_flags, N, L, K, beta, mods, level, dev, batches=(1, 4)) -> dict:
     """The faster schedule of a layer for batches of each size in `batches`, requests at
     `level`: a key set of uniform residues is loaded, every schedule is applied once to
@@ -296,8 +359,8 @@ def serve_bench(args) -> dict:
     16->16 on 32x32, 8 + 2 primes, levels 2..8) and an N=2^16 job (ResNet-18 stage-1
     conv 3x3 64->64 on 64x64, 8 input and 8 output ciphertexts, 12 + 3 primes, levels
     2..12), up to 32 clients with their own key sets, admitted by an HBM budget, with
-    continuous batching on 4 streams; compared with the same requests served one at a
-    time on one stream."""
+    continuous batching on `--serve-streams` streams; compared with the same requests
+    served one at a time on one stream."""
     import torch
 
     from paper_2509_01253_amd import fhelin as F
@@ -754,8 +817,16 @@ def main():
     res["hbm_step"]["copy_GBps"] = copy_gbps
     if args.serve_requests > 0:
         res["serving"] = serve_bench(args)
+    if args.with_resnet18 > 0:
+        import copy
+        rargs = copy.copy(args)
+        rargs.resnet18 = args.with_resnet18
+        rn = resnet18_bench(rargs)
+        res["resnet18"] = {k: rn[k] for k in ("workload", "inferences_per_batch", "stack_ms", "inferences_per_s")}
+        res["resnet18"]["per_inference_ms"] = round(rn["stack_ms"] / rn["inferences_per_batch"], 3)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(args.cpu_level, args.n1, args.schedule == "hoisted")
+        res["cpu_baseline"]["other_workloads"] = cpu_baseline_more()
     print(json.dumps(res), flush=True)
 
 
