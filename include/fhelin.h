@@ -78,9 +78,23 @@ typedef struct {
  * runs out. */
 int fhelin_primes_generate(int32_t log_n, int32_t bits, int32_t count, uint64_t *out);
 
-/* Context setup (roots of unity, NTT twiddles, base-conversion constants) on
- * the current HIP device.  The context owns its device tables. */
+/* Context setup on the current HIP device: the ring Z[X]/(X^N + 1) and the RNS
+ * modulus chain of the server's evaluation parameters (the RLWE parameters of
+ * paper Sec. 2.1 -- ring degree and ciphertext modulus -- fixed once at setup,
+ * paper Sec. 4.2; here in the full-RNS CKKS form of Cheon-Han-Kim-Kim-Song 2018
+ * with the hybrid key-switching digits of Han-Ki 2020).  Builds the minimal
+ * primitive 2N-th roots, NTT twiddles with their Shoup companions and every
+ * base-conversion constant.  The parameters are checked on the host before any
+ * device work: bad values return FHELIN_E_INVALID_ARG (null pointers) or
+ * FHELIN_E_UNSUPPORTED_PARAM (log_n, counts, dnum, moduli not prime, not 1 mod
+ * 2N, not below 2^60, not distinct, P not above every digit modulus) with a
+ * message and create nothing.  The encoding scale is not a context parameter:
+ * every encode call takes its own (scales change with rescales).  The context
+ * owns its device tables; destroy it after every handle created from it. */
 int fhelin_ctx_create(const fhelin_params *prm, fhelin_ctx **out);
+/* Handles are registered while alive: destroy/release calls (and the layer
+ * calls) reject a null, unknown or already destroyed handle with
+ * FHELIN_E_INVALID_ARG instead of freeing it twice. */
 int fhelin_ctx_destroy(fhelin_ctx *ctx);
 
 /* HBM budget (bytes) for everything the context allocates: keys, plaintexts
@@ -276,11 +290,16 @@ int fhelin_linear_apply_noalloc(fhelin_ctx *ctx, const fhelin_plan *plan, const 
  *   ks_eg   batch entries per workgroup of the key-switch inner product (each
  *           workgroup reuses an evaluation-key tile across its entries), 1..64
  *   mac_my  requests per thread in the plaintext multiply-accumulate: 2, 4, 8
- * A new plan starts at chunk 0, ks_eg 16, mac_my 2. */
+ *   ntt_threads  workgroup size of the two-pass NTT kernels (N >= 2^13): 128,
+ *           256 or 512 threads of 16 elements, i.e. column tiles of 8, 16 or 32
+ *           columns (2^16) in the first pass and 8, 16 or 32 blocks of 256 in the
+ *           second (LDS 17, 35 or 68 KiB per workgroup)
+ * A new plan starts at chunk 0, ks_eg 16, mac_my 2, ntt_threads 256. */
 typedef struct fhelin_tune {
     int32_t chunk;
     int32_t ks_eg;
     int32_t mac_my;
+    int32_t ntt_threads;
 } fhelin_tune;
 
 int fhelin_plan_get_tune(const fhelin_plan *plan, fhelin_tune *out);
@@ -290,7 +309,8 @@ int fhelin_plan_set_tune(fhelin_plan *plan, const fhelin_tune *tune);
 /* Autotuner: times the plan's schedule on the caller's batch (the arguments of
  * fhelin_linear_apply_multi) for candidate tunes, one field at a time starting
  * from the plan's current tune (chunk in {all, 32, 16, 8, 4} up to the request
- * count, ks_eg in {4, 8, 16}, mac_my in {2, 4, 8}), with HIP events on
+ * count, ks_eg in {4, 8, 16}, mac_my in {2, 4, 8}, ntt_threads in {256, 128, 512}
+ * when N >= 2^13), with HIP events on
  * `stream`, and keeps the fastest in the plan.  Every timed run computes the
  * layer, so `out` holds the layer's result on return.  Synchronises `stream`.
  * best (optional) receives the chosen tune, best_ms (optional) its time in ms. */

@@ -1,6 +1,7 @@
 // api.hip -- the extern "C" boundary: argument checks, handle ownership, stream plumbing,
 // and evaluation-key loading (hot-path row a2).
 #include <algorithm>
+#include <set>
 
 #include "internal.h"
 
@@ -174,6 +175,41 @@ static int ntt_rows(Ctx *c, uint64_t *rows, const int32_t *mods, int n_rows, int
 }
 
 // ---------------------------------------------------------------------------
+// live handles: every handle the library hands out is registered until its
+// destroy/release call, so a null, foreign or already destroyed handle passed to
+// a destroy/release or layer call is rejected (FHELIN_E_INVALID_ARG) instead of
+// being dereferenced
+// ---------------------------------------------------------------------------
+enum HandleKind : int { H_CTX = 0, H_KEYSET, H_PTSET, H_PLAN, H_GRAPH, H_KINDS };
+static std::mutex live_mu;
+static std::set<const void *> live_set[H_KINDS];
+static void live_add(int kind, const void *h) {
+    std::lock_guard<std::mutex> g(live_mu);
+    live_set[kind].insert(h);
+}
+static bool live_has(int kind, const void *h) {
+    std::lock_guard<std::mutex> g(live_mu);
+    return h && live_set[kind].count(h) > 0;
+}
+static bool live_remove(int kind, const void *h) {
+    std::lock_guard<std::mutex> g(live_mu);
+    return h && live_set[kind].erase(h) > 0;
+}
+static const char *const HANDLE_NAMES[H_KINDS] = {"context", "key set", "plaintext set", "plan", "graph"};
+#define FL_LIVE(kind, h)                                                                                    \
+    FL_CHECK(live_has((kind), (h)), FHELIN_E_INVALID_ARG,                                                   \
+             std::string("null, unknown or destroyed ") + HANDLE_NAMES[(kind)] + " handle")
+
+// handles of a layer call: context and plan live, key set (if given) and plaintext set live
+static int check_layer_handles(const void *ctx, const void *plan, const void *ks, const void *pts) {
+    FL_LIVE(H_CTX, ctx);
+    FL_LIVE(H_PLAN, plan);
+    if (ks) FL_LIVE(H_KEYSET, ks);
+    FL_LIVE(H_PTSET, pts);
+    return FHELIN_OK;
+}
+
+// ---------------------------------------------------------------------------
 // fixed device scratch of the allocation-free layer call
 // ---------------------------------------------------------------------------
 // One array per GPU, held until the process ends.  Host code never uses the array's
@@ -261,12 +297,14 @@ FHELIN_EXPORT int fhelin_ctx_create(const fhelin_params *prm, fhelin_ctx **out) 
         return rc;
     }
     *out = (fhelin_ctx *)c;
+    live_add(H_CTX, c);
     return FHELIN_OK;
     API_END
 }
 
 FHELIN_EXPORT int fhelin_ctx_destroy(fhelin_ctx *ctx) {
-    API_BEGIN FL_CHECK(ctx, FHELIN_E_INVALID_ARG, "ctx_destroy: null context");
+    API_BEGIN FL_CHECK(live_remove(H_CTX, ctx), FHELIN_E_INVALID_ARG,
+                       "ctx_destroy: null, unknown or destroyed context handle");
     Ctx *c = (Ctx *)ctx;
     DeviceGuard g(c);
     (void)hipDeviceSynchronize();
@@ -325,13 +363,17 @@ FHELIN_EXPORT int fhelin_keyset_load(fhelin_ctx *ctx, const uint32_t *galois, in
     DeviceGuard g(c);
     KeySet *k = nullptr;
     int rc = keyset_load(c, galois, n_keys, level, evk, src_on_device, (hipStream_t)stream, &k);
-    if (rc == FHELIN_OK) *out = (fhelin_keyset *)k;
+    if (rc == FHELIN_OK) {
+        *out = (fhelin_keyset *)k;
+        live_add(H_KEYSET, k);
+    }
     return rc;
     API_END
 }
 
 FHELIN_EXPORT int fhelin_keyset_release(fhelin_keyset *ks) {
-    API_BEGIN FL_CHECK(ks, FHELIN_E_INVALID_ARG, "null keyset");
+    API_BEGIN FL_CHECK(live_remove(H_KEYSET, ks), FHELIN_E_INVALID_ARG,
+                       "keyset_release: null, unknown or released key set handle");
     KeySet *k = (KeySet *)ks;
     DeviceGuard g(k->ctx);
     (void)hipDeviceSynchronize();
@@ -347,7 +389,10 @@ FHELIN_EXPORT int fhelin_pt_import(fhelin_ctx *ctx, const uint64_t *pt, int32_t 
     DeviceGuard g(c);
     PtSet *p = nullptr;
     int rc = pt_import(c, pt, n_pt, level, src_on_device, (hipStream_t)stream, &p);
-    if (rc == FHELIN_OK) *out = (fhelin_ptset *)p;
+    if (rc == FHELIN_OK) {
+        *out = (fhelin_ptset *)p;
+        live_add(H_PTSET, p);
+    }
     return rc;
     API_END
 }
@@ -359,7 +404,10 @@ FHELIN_EXPORT int fhelin_pt_encode(fhelin_ctx *ctx, const double *slots, int32_t
     DeviceGuard g(c);
     PtSet *p = nullptr;
     int rc = pt_encode(c, slots, n_pt, level, scale, (hipStream_t)stream, &p);
-    if (rc == FHELIN_OK) *out = (fhelin_ptset *)p;
+    if (rc == FHELIN_OK) {
+        *out = (fhelin_ptset *)p;
+        live_add(H_PTSET, p);
+    }
     return rc;
     API_END
 }
@@ -383,7 +431,8 @@ FHELIN_EXPORT int fhelin_ptset_info(const fhelin_ptset *pts, int32_t *n_pt, int3
 }
 
 FHELIN_EXPORT int fhelin_ptset_release(fhelin_ptset *pts) {
-    API_BEGIN FL_CHECK(pts, FHELIN_E_INVALID_ARG, "null plaintext set");
+    API_BEGIN FL_CHECK(live_remove(H_PTSET, pts), FHELIN_E_INVALID_ARG,
+                       "ptset_release: null, unknown or released plaintext set handle");
     PtSet *p = (PtSet *)pts;
     DeviceGuard g(p->ctx);
     (void)hipDeviceSynchronize();
@@ -396,13 +445,17 @@ FHELIN_EXPORT int fhelin_plan_create(fhelin_ctx *ctx, const fhelin_layer_desc *d
     API_BEGIN FL_CHECK(ctx && out, FHELIN_E_INVALID_ARG, "null argument");
     Plan *p = nullptr;
     int rc = plan_create((Ctx *)ctx, desc, &p);
-    if (rc == FHELIN_OK) *out = (fhelin_plan *)p;
+    if (rc == FHELIN_OK) {
+        *out = (fhelin_plan *)p;
+        live_add(H_PLAN, p);
+    }
     return rc;
     API_END
 }
 
 FHELIN_EXPORT int fhelin_plan_destroy(fhelin_plan *plan) {
-    API_BEGIN FL_CHECK(plan, FHELIN_E_INVALID_ARG, "null plan");
+    API_BEGIN FL_CHECK(live_remove(H_PLAN, plan), FHELIN_E_INVALID_ARG,
+                       "plan_destroy: null, unknown or destroyed plan handle");
     delete (Plan *)plan;
     return FHELIN_OK;
     API_END
@@ -448,7 +501,10 @@ FHELIN_EXPORT int fhelin_plan_encode_weights(fhelin_ctx *ctx, const fhelin_plan 
     DeviceGuard g(c);
     PtSet *p = nullptr;
     int rc = plan_encode_weights(c, (const Plan *)plan, weights, perm_out, perm_in, level, scale, (hipStream_t)stream, &p);
-    if (rc == FHELIN_OK) *out = (fhelin_ptset *)p;
+    if (rc == FHELIN_OK) {
+        *out = (fhelin_ptset *)p;
+        live_add(H_PTSET, p);
+    }
     return rc;
     API_END
 }
@@ -456,7 +512,7 @@ FHELIN_EXPORT int fhelin_plan_encode_weights(fhelin_ctx *ctx, const fhelin_plan 
 FHELIN_EXPORT int fhelin_linear_apply(fhelin_ctx *ctx, const fhelin_plan *plan, const fhelin_keyset *ks,
                                       const fhelin_ptset *pts, const fhelin_ct_batch *in, const fhelin_ct_batch *out,
                                       int32_t flags, void *stream) {
-    API_BEGIN FL_CHECK(ctx, FHELIN_E_INVALID_ARG, "null context");
+    API_BEGIN FL_RET(check_layer_handles(ctx, plan, ks, pts));
     Ctx *c = (Ctx *)ctx;
     DeviceGuard g(c);
     FL_CHECK(plan && in, FHELIN_E_INVALID_ARG, "null argument");
@@ -492,6 +548,7 @@ FHELIN_EXPORT int fhelin_plan_get_tune(const fhelin_plan *plan, fhelin_tune *out
     out->chunk = t.chunk;
     out->ks_eg = t.ks_eg;
     out->mac_my = t.mac_my;
+    out->ntt_threads = t.ntt_threads;
     return FHELIN_OK;
     API_END
 }
@@ -502,8 +559,9 @@ FHELIN_EXPORT int fhelin_plan_set_tune(fhelin_plan *plan, const fhelin_tune *tun
     t.chunk = tune->chunk;
     t.ks_eg = tune->ks_eg;
     t.mac_my = tune->mac_my;
+    t.ntt_threads = tune->ntt_threads;
     FL_CHECK(tune_valid(t), FHELIN_E_INVALID_ARG,
-             "tune out of range (chunk 0..64, ks_eg 1..64, mac_my 2, 4 or 8)");
+             "tune out of range (chunk 0..64, ks_eg 1..64, mac_my 2, 4 or 8, ntt_threads 128, 256 or 512)");
     ((Plan *)plan)->tune = t;
     return FHELIN_OK;
     API_END
@@ -524,6 +582,7 @@ FHELIN_EXPORT int fhelin_plan_autotune(fhelin_ctx *ctx, fhelin_plan *plan, const
         best->chunk = t.chunk;
         best->ks_eg = t.ks_eg;
         best->mac_my = t.mac_my;
+        best->ntt_threads = t.ntt_threads;
     }
     if (best_ms) *best_ms = ms;
     return FHELIN_OK;
@@ -533,7 +592,7 @@ FHELIN_EXPORT int fhelin_plan_autotune(fhelin_ctx *ctx, fhelin_plan *plan, const
 FHELIN_EXPORT int fhelin_linear_apply_noalloc(fhelin_ctx *ctx, const fhelin_plan *plan, const fhelin_keyset *ks,
                                               const fhelin_ptset *pts, const fhelin_ct_batch *in,
                                               const fhelin_ct_batch *out, int32_t flags, void *stream) {
-    API_BEGIN FL_CHECK(ctx, FHELIN_E_INVALID_ARG, "null context");
+    API_BEGIN FL_RET(check_layer_handles(ctx, plan, ks, pts));
     Ctx *c = (Ctx *)ctx;
     DeviceGuard g(c);
     return linear_apply_noalloc(c, (const Plan *)plan, (const KeySet *)ks, (const PtSet *)pts, in, out, flags,
@@ -545,7 +604,11 @@ FHELIN_EXPORT int fhelin_linear_apply_multi(fhelin_ctx *ctx, const fhelin_plan *
                                             const fhelin_keyset *const *ks_per_request, const fhelin_ptset *pts,
                                             const fhelin_ct_batch *in, const fhelin_ct_batch *out, int32_t flags,
                                             void *stream) {
-    API_BEGIN FL_CHECK(ctx && ks_per_request, FHELIN_E_INVALID_ARG, "null argument");
+    API_BEGIN FL_CHECK(ks_per_request, FHELIN_E_INVALID_ARG, "null argument");
+    FL_RET(check_layer_handles(ctx, plan, nullptr, pts));
+    if (in)
+        for (int r = 0; r < in->n_ct / std::max(1, ((const Plan *)plan)->n_in); ++r)
+            if (ks_per_request[r]) FL_LIVE(H_KEYSET, ks_per_request[r]);
     Ctx *c = (Ctx *)ctx;
     DeviceGuard g(c);
     return linear_apply(c, (const Plan *)plan, (const KeySet *const *)ks_per_request, (const PtSet *)pts, in, out,
@@ -564,7 +627,8 @@ FHELIN_EXPORT int fhelin_rescale(fhelin_ctx *ctx, const fhelin_ct_batch *in, con
 
 FHELIN_EXPORT int fhelin_rotate(fhelin_ctx *ctx, const fhelin_keyset *ks, const fhelin_ct_batch *in,
                                 const int32_t *steps, const fhelin_ct_batch *out, void *stream) {
-    API_BEGIN FL_CHECK(ctx, FHELIN_E_INVALID_ARG, "null context");
+    API_BEGIN FL_LIVE(H_CTX, ctx);
+    FL_LIVE(H_KEYSET, ks);
     Ctx *c = (Ctx *)ctx;
     DeviceGuard g(c);
     return rotate_batch(c, (const KeySet *)ks, in, steps, out, (hipStream_t)stream);
@@ -584,19 +648,23 @@ FHELIN_EXPORT int fhelin_graph_capture_linear(fhelin_ctx *ctx, const fhelin_plan
                                               const fhelin_ptset *pts, const fhelin_ct_batch *in,
                                               const fhelin_ct_batch *out, int32_t flags, void *stream,
                                               fhelin_graph **graph) {
-    API_BEGIN FL_CHECK(ctx && graph, FHELIN_E_INVALID_ARG, "null argument");
+    API_BEGIN FL_CHECK(graph, FHELIN_E_INVALID_ARG, "null argument");
+    FL_RET(check_layer_handles(ctx, plan, ks, pts));
     Ctx *c = (Ctx *)ctx;
     DeviceGuard g(c);
     Graph *gr = nullptr;
     int rc = graph_capture_linear(c, (const Plan *)plan, (const KeySet *)ks, (const PtSet *)pts, in, out, flags,
                                   (hipStream_t)stream, &gr);
-    if (rc == FHELIN_OK) *graph = (fhelin_graph *)gr;
+    if (rc == FHELIN_OK) {
+        *graph = (fhelin_graph *)gr;
+        live_add(H_GRAPH, gr);
+    }
     return rc;
     API_END
 }
 
 FHELIN_EXPORT int fhelin_graph_launch(fhelin_graph *graph, void *stream) {
-    API_BEGIN FL_CHECK(graph, FHELIN_E_INVALID_ARG, "null graph");
+    API_BEGIN FL_LIVE(H_GRAPH, graph);
     Graph *gr = (Graph *)graph;
     DeviceGuard g(gr->ctx);
     FL_TRY_HIP(hipGraphLaunch(gr->exec, (hipStream_t)stream));
@@ -605,7 +673,8 @@ FHELIN_EXPORT int fhelin_graph_launch(fhelin_graph *graph, void *stream) {
 }
 
 FHELIN_EXPORT int fhelin_graph_destroy(fhelin_graph *graph) {
-    API_BEGIN FL_CHECK(graph, FHELIN_E_INVALID_ARG, "null graph");
+    API_BEGIN FL_CHECK(live_remove(H_GRAPH, graph), FHELIN_E_INVALID_ARG,
+                       "graph_destroy: null, unknown or destroyed graph handle");
     Graph *gr = (Graph *)graph;
     DeviceGuard g(gr->ctx);
     (void)hipDeviceSynchronize();

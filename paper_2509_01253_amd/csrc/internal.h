@@ -328,6 +328,7 @@ struct Tune {
     int chunk = 0;    // requests per chunk (0: as many as fit MAX_BATCH ciphertexts)
     int ks_eg = 16;   // batch entries per key-switch inner-product workgroup
     int mac_my = 2;   // requests per thread in the multiply-accumulate
+    int ntt_threads = 256;  // workgroup size of the two-pass NTT kernels (128, 256, 512)
 };
 bool tune_valid(const Tune &t);
 
@@ -382,6 +383,9 @@ int launch_ntt(const Ctx *c, const RowMap &rows, int inverse, hipStream_t s, boo
 // out of place: rows of `src` (same row enumeration as `rows`, its own layout) transformed into `rows`
 int launch_ntt_from(const Ctx *c, const RowMap &rows, const RowMap &src, int inverse, hipStream_t s,
                     bool to_mont = false);
+// workgroup size of the two-pass NTT kernels for launches from the calling thread
+// (128, 256 or 512; anything else = 256); returns the previous setting
+int ntt_threads_set(int nt);
 // to/from Montgomery form over the rows (canonical in, canonical out)
 int launch_to_mont(const Ctx *c, const RowMap &rows, hipStream_t s);
 int launch_from_mont(const Ctx *c, const RowMap &rows, hipStream_t s);

@@ -17,6 +17,7 @@
 
 #include "internal.h"
 #include "modarith.h"
+#include "modup.h"
 
 namespace fl {
 
@@ -30,48 +31,15 @@ __device__ __forceinline__ int auto_index(int k, uint32_t g, int log_n) {
 }
 
 // ---------------------------------------------------------------------------
-// ModUp: grid (N/256, beta_max, n)
+// ModUp: grid (N/256, beta_max, n); the tile itself is modup_tile (modup.h)
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_modup(Batch b, const ModConst *__restrict__ mods,
                                                const ModUpTab *__restrict__ tabs, const uint64_t *__restrict__ coef,
                                                int64_t coef_es, const uint64_t *__restrict__ ntt, int64_t ntt_es,
                                                uint64_t *__restrict__ digits, int64_t digits_es, int log_n, int L,
                                                int K, int alpha, int dnum) {
-    const int t = blockIdx.z, j = blockIdx.y;
-    const int l = b.level[t];
-    const int beta = (l + alpha - 1) / alpha;
-    if (j >= beta) return;
-    const int64_t N = (int64_t)1 << log_n;
-    const int k = blockIdx.x * 256 + threadIdx.x;
-    const ModUpTab &tab = tabs[(l - 1) * dnum + j];
-    const int lo = tab.lo, cnt = tab.cnt;
-    const uint64_t *x = coef + t * coef_es;
-    const uint64_t *xn = ntt + t * ntt_es;
-    uint64_t *y = digits + t * digits_es + (int64_t)j * (L + K) * N;
-    uint64_t v[MAX_ALPHA];
-    uint64_t nneg = 0;
-#pragma unroll
-    for (int a = 0; a < MAX_ALPHA; ++a) {
-        if (a < cnt) {
-            const ModConst mc = mods[lo + a];
-            uint64_t w = shoup(x[(int64_t)(lo + a) * N + k], tab.inv_hat[a], tab.inv_hat_sh[a], mc.q);
-            v[a] = w;
-            nneg += w > mc.half ? 1 : 0;
-            y[(int64_t)(lo + a) * N + k] = xn[(int64_t)(lo + a) * N + k];
-        }
-    }
-    for (int e = 0; e < l + K; ++e) {
-        if (e >= lo && e < lo + cnt) continue;
-        const int slot = e < l ? e : L + (e - l);
-        const ModConst mc = mods[slot];
-        Acc128 acc{0, 0};
-#pragma unroll
-        for (int a = 0; a < MAX_ALPHA; ++a)
-            if (a < cnt) mac128(acc, v[a], tab.hat_mont[a][slot]);
-        uint64_t r = redc(acc, mc.q, mc.mont_neg_inv);
-        if (nneg) r = sub_mod(r, mont_mul(nneg, tab.qj_mont[slot], mc.q, mc.mont_neg_inv), mc.q);
-        y[(int64_t)slot * N + k] = r;
-    }
+    modup_tile(b, mods, tabs, coef, coef_es, ntt, ntt_es, digits, digits_es, log_n, L, K, alpha, dnum, blockIdx.x,
+               blockIdx.y, blockIdx.z);
 }
 
 int launch_modup(const Ctx *c, const Batch &b, const uint64_t *coef, int64_t coef_es, const uint64_t *ntt,

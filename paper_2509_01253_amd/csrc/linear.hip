@@ -338,7 +338,8 @@ static int launch_mac(const Ctx *c, const Plan *p, MacArgs &ma, const Batch &bou
 
 bool tune_valid(const Tune &t) {
     return t.chunk >= 0 && t.chunk <= MAX_BATCH && t.ks_eg >= 1 && t.ks_eg <= MAX_BATCH &&
-           (t.mac_my == 2 || t.mac_my == 4 || t.mac_my == 8);
+           (t.mac_my == 2 || t.mac_my == 4 || t.mac_my == 8) &&
+           (t.ntt_threads == 128 || t.ntt_threads == 256 || t.ntt_threads == 512);
 }
 
 // ---------------------------------------------------------------------------
@@ -761,6 +762,12 @@ int linear_apply(Ctx *c, const Plan *p, const KeySet *const *kss, const PtSet *p
         }
     }
     if (R == 0) return FHELIN_OK;
+    // the plan's NTT tile for every transform this call launches (restored on return)
+    struct NttTile {
+        int prev;
+        explicit NttTile(int nt) : prev(ntt_threads_set(nt)) {}
+        ~NttTile() { ntt_threads_set(prev); }
+    } ntt_tile(p->tune.ntt_threads);
     // key and plaintext sets loaded on another stream
     FL_RET(pts->ready.wait(s));
     if (!p->galois.empty()) {
@@ -916,13 +923,15 @@ int plan_autotune(Ctx *c, Plan *p, const KeySet *const *kss, const PtSet *pts, c
     Tune best = start;
     double best_t = 0;
     int rc = time_apply(c, p, kss, pts, in, out, flags, s, e0, e1, &best_t);
-    const int chunks[] = {0, 32, 16, 8, 4}, egs[] = {4, 8, 16}, mys[] = {2, 4, 8};
-    for (int field = 0; field < 3 && rc == FHELIN_OK; ++field) {
-        const int *vals = field == 0 ? chunks : field == 1 ? egs : mys;
+    const int chunks[] = {0, 32, 16, 8, 4}, egs[] = {4, 8, 16}, mys[] = {2, 4, 8}, nts[] = {256, 128, 512};
+    // the NTT tile matters only for the two-pass transforms (N >= 2^13)
+    const int n_fields = c->log_n > 12 ? 4 : 3;
+    for (int field = 0; field < n_fields && rc == FHELIN_OK; ++field) {
+        const int *vals = field == 0 ? chunks : field == 1 ? egs : field == 2 ? mys : nts;
         const int nv = field == 0 ? 5 : 3;
         for (int i = 0; i < nv && rc == FHELIN_OK; ++i) {
             Tune t = best;
-            int &f = field == 0 ? t.chunk : field == 1 ? t.ks_eg : t.mac_my;
+            int &f = field == 0 ? t.chunk : field == 1 ? t.ks_eg : field == 2 ? t.mac_my : t.ntt_threads;
             if (f == vals[i]) continue;
             if (field == 0 && vals[i] >= R) continue;  // same as "all" for this batch
             f = vals[i];

@@ -21,11 +21,15 @@
 
 namespace fl {
 
-constexpr int NTT_THREADS = 256;
-constexpr int TILE = 4096;  // elements per workgroup in the two-pass kernels
+constexpr int NTT_THREADS = 256;  // single-pass kernels (N <= 4096)
+// Two-pass kernels: NT threads per workgroup, 16 elements each (a tile of 16 NT
+// elements: 16 NT / 256 blocks of 256 in the row passes, NT / T columns in the column
+// passes).  NT in {128, 256, 512} is a tile choice of the plan (autotuned); results
+// do not depend on it.
+static thread_local int tl_ntt_threads = 256;
 
-__device__ __forceinline__ bool row_of(const RowMap &m, uint64_t *&ptr, int &mod) {
-    int t = blockIdx.z, r = blockIdx.y;
+// row r of batch entry t: its address and modulus index (false past the entry's rows)
+__device__ __forceinline__ bool row_at(const RowMap &m, int t, int r, uint64_t *&ptr, int &mod) {
     if (r >= rowmap_rows(m, t)) return false;
     int64_t off;
     rowmap_get(m, t, r, &off, &mod);
@@ -33,14 +37,22 @@ __device__ __forceinline__ bool row_of(const RowMap &m, uint64_t *&ptr, int &mod
     return true;
 }
 
+__device__ __forceinline__ bool row_of(const RowMap &m, uint64_t *&ptr, int &mod) {
+    return row_at(m, blockIdx.z, blockIdx.y, ptr, mod);
+}
+
 // out-of-place first pass: the same row of the source map (same row enumeration,
 // its own layout), or the destination itself when the map is empty
-__device__ __forceinline__ const uint64_t *src_row(const RowMap &src, const uint64_t *dst) {
+__device__ __forceinline__ const uint64_t *src_row_at(const RowMap &src, int t, int r, const uint64_t *dst) {
     if (!src.base) return dst;
     int64_t off;
     int mod;
-    rowmap_get(src, blockIdx.z, blockIdx.y, &off, &mod);
+    rowmap_get(src, t, r, &off, &mod);
     return src.base + off;
+}
+
+__device__ __forceinline__ const uint64_t *src_row(const RowMap &src, const uint64_t *dst) {
+    return src_row_at(src, blockIdx.z, blockIdx.y, dst);
 }
 
 // twiddle products: F53 (every modulus < 2^50) takes the 53-bit companions
@@ -244,23 +256,18 @@ __device__ __forceinline__ void inv_round_a(uint64_t (&X)[16], const Tw &t, uint
     }
 }
 
-// forward pass 1: stages with distance >= 256 on columns c + 256 rho, rho < N1 = 2^S
-template <int LOGN, bool F53>
-__global__ void __launch_bounds__(NTT_THREADS) k_ntt_fwd_cols(RowMap rm, RowMap src,
-                                                              const ModConst *__restrict__ mods,
-                                                              const uint64_t *__restrict__ tw,
-                                                              const uint64_t *__restrict__ twp) {
-    constexpr int N = 1 << LOGN, S = LOGN - 8, T = 1 << (S - 4), C = NTT_THREADS / T, CP = C + 1;
-    __shared__ uint64_t s[(1 << S) * CP];
-    uint64_t *x;
-    int mi;
-    if (!row_of(rm, x, mi)) return;
-    const uint64_t *xs = src_row(src, x);
+// forward pass 1: stages with distance >= 256 on columns c + 256 rho, rho < N1 = 2^S;
+// column tile bx of the row at x (read from xs), LDS scratch s of (2^S)(NT/T + 1) words
+template <int LOGN, bool F53, int NT>
+__device__ __forceinline__ void fwd_cols_tile(uint64_t *x, const uint64_t *xs, int mi, int bx,
+                                              const ModConst *__restrict__ mods, const uint64_t *__restrict__ tw,
+                                              const uint64_t *__restrict__ twp, uint64_t *s) {
+    constexpr int N = 1 << LOGN, S = LOGN - 8, T = 1 << (S - 4), C = NT / T, CP = C + 1;
     const uint64_t q = mods[mi].q;
     const uint64_t *w = tw + (size_t)mi * N, *wp = twp + (size_t)mi * N;
     const int c = threadIdx.x % C, r = threadIdx.x / C;
-    uint64_t *xc = x + blockIdx.x * C + c;
-    const uint64_t *xsc = xs + blockIdx.x * C + c;
+    uint64_t *xc = x + bx * C + c;
+    const uint64_t *xsc = xs + bx * C + c;
     uint64_t X[16];
 #pragma unroll
     for (int u = 0; u < 16; ++u) X[u] = xsc[256 * (r + T * u)];
@@ -281,22 +288,33 @@ __global__ void __launch_bounds__(NTT_THREADS) k_ntt_fwd_cols(RowMap rm, RowMap 
     for (int u = 0; u < 16; ++u) xc[256 * (16 * r + u)] = X[u];  // lazy [0, 4q)
 }
 
-// forward pass 2: the last 8 stages inside contiguous 256-blocks; 16 blocks per workgroup;
-// MONT: outputs in Montgomery form (one Shoup product by 2^64 mod q replaces the final reduction)
-template <int LOGN, bool MONT, bool F53>
-__global__ void __launch_bounds__(NTT_THREADS) k_ntt_fwd_rows(RowMap rm, const ModConst *__restrict__ mods,
-                                                              const uint64_t *__restrict__ tw,
-                                                              const uint64_t *__restrict__ twp) {
-    constexpr int N = 1 << LOGN, BS = 272;  // padded block stride in LDS (one pad word per 16)
-    __shared__ uint64_t s[16 * BS];
+template <int LOGN, bool F53, int NT>
+__global__ void __launch_bounds__(NT) k_ntt_fwd_cols(RowMap rm, RowMap src,
+                                                     const ModConst *__restrict__ mods,
+                                                     const uint64_t *__restrict__ tw,
+                                                     const uint64_t *__restrict__ twp) {
+    constexpr int S = LOGN - 8, T = 1 << (S - 4), C = NT / T, CP = C + 1;
+    __shared__ uint64_t s[(1 << S) * CP];
     uint64_t *x;
     int mi;
     if (!row_of(rm, x, mi)) return;
+    fwd_cols_tile<LOGN, F53, NT>(x, src_row(src, x), mi, blockIdx.x, mods, tw, twp, s);
+}
+
+// forward pass 2: the last 8 stages inside contiguous 256-blocks; NT/16 blocks per
+// workgroup (tile bx of the row at x, LDS scratch s of (NT/16) 272 words);
+// MONT: outputs in Montgomery form (one Shoup product by 2^64 mod q replaces the final reduction)
+template <int LOGN, bool MONT, bool F53, int NT>
+__device__ __forceinline__ void fwd_rows_tile(uint64_t *x, int mi, int bx, const ModConst *__restrict__ mods,
+                                              const uint64_t *__restrict__ tw, const uint64_t *__restrict__ twp,
+                                              uint64_t *s) {
+    constexpr int N = 1 << LOGN, BS = 272;  // padded block stride in LDS (one pad word per 16)
+    constexpr int NB = NT / 16, TILE = 16 * NT;  // 256-blocks per workgroup, elements per workgroup
     const uint64_t q = mods[mi].q;
     const uint64_t *w = tw + (size_t)mi * N, *wp = twp + (size_t)mi * N;
     const int blk = threadIdx.x >> 4, r = threadIdx.x & 15;
-    const int gb = blockIdx.x * 16 + blk;
-    uint64_t *xt = x + (size_t)blockIdx.x * TILE;
+    const int gb = bx * NB + blk;
+    uint64_t *xt = x + (size_t)bx * TILE;
     uint64_t X[16];
 #pragma unroll
     for (int u = 0; u < 16; ++u) X[u] = xt[blk * 256 + r + 16 * u];
@@ -321,17 +339,28 @@ __global__ void __launch_bounds__(NTT_THREADS) k_ntt_fwd_rows(RowMap rm, const M
         else sb[17 * r + u] = reduce4q(X[u], q);
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < TILE; e += NTT_THREADS) xt[e] = s[(e >> 8) * BS + (e & 255) + ((e & 255) >> 4)];
+    for (int e = threadIdx.x; e < TILE; e += NT) xt[e] = s[(e >> 8) * BS + (e & 255) + ((e & 255) >> 4)];
+}
+
+template <int LOGN, bool MONT, bool F53, int NT>
+__global__ void __launch_bounds__(NT) k_ntt_fwd_rows(RowMap rm, const ModConst *__restrict__ mods,
+                                                     const uint64_t *__restrict__ tw,
+                                                     const uint64_t *__restrict__ twp) {
+    __shared__ uint64_t s[(NT / 16) * 272];
+    uint64_t *x;
+    int mi;
+    if (!row_of(rm, x, mi)) return;
+    fwd_rows_tile<LOGN, MONT, F53, NT>(x, mi, blockIdx.x, mods, tw, twp, s);
 }
 
 // inverse pass 1: the first 8 stages (distance 1 .. 128) inside contiguous 256-blocks
-template <int LOGN, bool F53>
-__global__ void __launch_bounds__(NTT_THREADS) k_ntt_inv_rows(RowMap rm, RowMap src,
-                                                              const ModConst *__restrict__ mods,
-                                                              const uint64_t *__restrict__ itw,
-                                                              const uint64_t *__restrict__ itwp) {
+template <int LOGN, bool F53, int NT>
+__global__ void __launch_bounds__(NT) k_ntt_inv_rows(RowMap rm, RowMap src, const ModConst *__restrict__ mods,
+                                                     const uint64_t *__restrict__ itw,
+                                                     const uint64_t *__restrict__ itwp) {
     constexpr int N = 1 << LOGN, BS = 272;
-    __shared__ uint64_t s[16 * BS];
+    constexpr int NB = NT / 16, TILE = 16 * NT;
+    __shared__ uint64_t s[NB * BS];
     uint64_t *x;
     int mi;
     if (!row_of(rm, x, mi)) return;
@@ -339,7 +368,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_ntt_inv_rows(RowMap rm, RowMap 
     const uint64_t q = mods[mi].q;
     const uint64_t *w = itw + (size_t)mi * N, *wp = itwp + (size_t)mi * N;
     const int blk = threadIdx.x >> 4, r = threadIdx.x & 15;
-    const int gb = blockIdx.x * 16 + blk;
+    const int gb = blockIdx.x * NB + blk;
     uint64_t *xt = x + (size_t)blockIdx.x * TILE;
     const int64_t base = N + (int64_t)gb * 256;
     uint64_t X[16];
@@ -372,11 +401,11 @@ __global__ void __launch_bounds__(NTT_THREADS) k_ntt_inv_rows(RowMap rm, RowMap 
 }
 
 // inverse pass 2: stages with distance >= 256 on columns, then N^{-1}
-template <int LOGN, bool F53>
-__global__ void __launch_bounds__(NTT_THREADS) k_ntt_inv_cols(RowMap rm, const ModConst *__restrict__ mods,
-                                                              const uint64_t *__restrict__ itw,
-                                                              const uint64_t *__restrict__ itwp) {
-    constexpr int N = 1 << LOGN, S = LOGN - 8, T = 1 << (S - 4), C = NTT_THREADS / T, CP = C + 1;
+template <int LOGN, bool F53, int NT>
+__global__ void __launch_bounds__(NT) k_ntt_inv_cols(RowMap rm, const ModConst *__restrict__ mods,
+                                                     const uint64_t *__restrict__ itw,
+                                                     const uint64_t *__restrict__ itwp) {
+    constexpr int N = 1 << LOGN, S = LOGN - 8, T = 1 << (S - 4), C = NT / T, CP = C + 1;
     __shared__ uint64_t s[(1 << S) * CP];
     uint64_t *x;
     int mi;
@@ -421,6 +450,31 @@ __global__ void __launch_bounds__(256) k_to_mont(RowMap rm, const ModConst *__re
     }
 }
 
+template <int LOGN, bool F53, int NT>
+static void launch_two_pass(const Ctx *c, const RowMap &rm, const RowMap &src, int rows, int inverse, bool to_mont,
+                            hipStream_t s, double bfly_per_stage, double row_bytes) {
+    dim3 g((1 << LOGN) / (16 * NT), rows, rm.n_ct);
+    if (!inverse) {
+        {
+            ProfScope ps(c, s, PK_NTT_FWD_COLS, bfly_per_stage * (LOGN - 8), row_bytes);
+            hipLaunchKernelGGL((k_ntt_fwd_cols<LOGN, F53, NT>), g, dim3(NT), 0, s, rm, src, c->d_mods, c->d_tw, c->d_twp);
+        }
+        ProfScope ps(c, s, PK_NTT_FWD_ROWS, bfly_per_stage * 8, row_bytes);
+        if (to_mont)
+            hipLaunchKernelGGL((k_ntt_fwd_rows<LOGN, true, F53, NT>), g, dim3(NT), 0, s, rm, c->d_mods, c->d_tw, c->d_twp);
+        else
+            hipLaunchKernelGGL((k_ntt_fwd_rows<LOGN, false, F53, NT>), g, dim3(NT), 0, s, rm, c->d_mods, c->d_tw, c->d_twp);
+    } else {
+        {
+            ProfScope ps(c, s, PK_NTT_INV_ROWS, bfly_per_stage * 8, row_bytes);
+            hipLaunchKernelGGL((k_ntt_inv_rows<LOGN, F53, NT>), g, dim3(NT), 0, s, rm, src, c->d_mods, c->d_itw,
+                               c->d_itwp);
+        }
+        ProfScope ps(c, s, PK_NTT_INV_COLS, bfly_per_stage * (LOGN - 8), row_bytes);
+        hipLaunchKernelGGL((k_ntt_inv_cols<LOGN, F53, NT>), g, dim3(NT), 0, s, rm, c->d_mods, c->d_itw, c->d_itwp);
+    }
+}
+
 template <int LOGN, bool F53>
 static void launch_ntt_t(const Ctx *c, const RowMap &rm, const RowMap &src, int rows, int inverse, bool to_mont,
                          hipStream_t s) {
@@ -442,29 +496,16 @@ static void launch_ntt_t(const Ctx *c, const RowMap &rm, const RowMap &src, int 
         }
     } else {
         constexpr int L2 = LOGN > 12 ? LOGN : 13;
-        dim3 g(M / TILE, rows, rm.n_ct);
-        if (!inverse) {
-            {
-                ProfScope ps(c, s, PK_NTT_FWD_COLS, bfly_per_stage * (LOGN - 8), row_bytes);
-                hipLaunchKernelGGL((k_ntt_fwd_cols<L2, F53>), g, dim3(NTT_THREADS), 0, s, rm, src, c->d_mods, c->d_tw,
-                                   c->d_twp);
-            }
-            ProfScope ps(c, s, PK_NTT_FWD_ROWS, bfly_per_stage * 8, row_bytes);
-            if (to_mont)
-                hipLaunchKernelGGL((k_ntt_fwd_rows<L2, true, F53>), g, dim3(NTT_THREADS), 0, s, rm, c->d_mods, c->d_tw, c->d_twp);
-            else
-                hipLaunchKernelGGL((k_ntt_fwd_rows<L2, false, F53>), g, dim3(NTT_THREADS), 0, s, rm, c->d_mods, c->d_tw,
-                                   c->d_twp);
-        } else {
-            {
-                ProfScope ps(c, s, PK_NTT_INV_ROWS, bfly_per_stage * 8, row_bytes);
-                hipLaunchKernelGGL((k_ntt_inv_rows<L2, F53>), g, dim3(NTT_THREADS), 0, s, rm, src, c->d_mods, c->d_itw,
-                                   c->d_itwp);
-            }
-            ProfScope ps(c, s, PK_NTT_INV_COLS, bfly_per_stage * (LOGN - 8), row_bytes);
-            hipLaunchKernelGGL((k_ntt_inv_cols<L2, F53>), g, dim3(NTT_THREADS), 0, s, rm, c->d_mods, c->d_itw, c->d_itwp);
-        }
+        if (tl_ntt_threads == 128) launch_two_pass<L2, F53, 128>(c, rm, src, rows, inverse, to_mont, s, bfly_per_stage, row_bytes);
+        else if (tl_ntt_threads == 512) launch_two_pass<L2, F53, 512>(c, rm, src, rows, inverse, to_mont, s, bfly_per_stage, row_bytes);
+        else launch_two_pass<L2, F53, 256>(c, rm, src, rows, inverse, to_mont, s, bfly_per_stage, row_bytes);
     }
+}
+
+int ntt_threads_set(int nt) {
+    const int prev = tl_ntt_threads;
+    tl_ntt_threads = (nt == 128 || nt == 512) ? nt : 256;
+    return prev;
 }
 
 static int launch_mont(const Ctx *c, const RowMap &rm, int to, hipStream_t s);

@@ -66,7 +66,7 @@ class fhelin_ct_batch(ctypes.Structure):
 
 
 class fhelin_tune(ctypes.Structure):
-    _fields_ = [("chunk", _i32), ("ks_eg", _i32), ("mac_my", _i32)]
+    _fields_ = [("chunk", _i32), ("ks_eg", _i32), ("mac_my", _i32), ("ntt_threads", _i32)]
 
 
 _SIGS = {
@@ -349,11 +349,11 @@ def fhelin_linear_apply_multi(ctx, plan, ks_per_request, pts, x: torch.Tensor, x
 def fhelin_plan_get_tune(plan) -> dict:
     t = fhelin_tune()
     _check(_lib.fhelin_plan_get_tune(plan, ctypes.byref(t)))
-    return {"chunk": t.chunk, "ks_eg": t.ks_eg, "mac_my": t.mac_my}
+    return {"chunk": t.chunk, "ks_eg": t.ks_eg, "mac_my": t.mac_my, "ntt_threads": t.ntt_threads}
 
 
-def fhelin_plan_set_tune(plan, chunk: int = 0, ks_eg: int = 16, mac_my: int = 2):
-    t = fhelin_tune(chunk, ks_eg, mac_my)
+def fhelin_plan_set_tune(plan, chunk: int = 0, ks_eg: int = 16, mac_my: int = 2, ntt_threads: int = 256):
+    t = fhelin_tune(chunk, ks_eg, mac_my, ntt_threads)
     _check(_lib.fhelin_plan_set_tune(plan, ctypes.byref(t)))
 
 
@@ -366,7 +366,7 @@ def fhelin_plan_autotune(ctx, plan, ks_per_request, pts, x: torch.Tensor, x_leve
     t, ms = fhelin_tune(), _dbl()
     _check(_lib.fhelin_plan_autotune(ctx, plan, ctypes.cast(arr, _vp), pts, ctypes.byref(bi), ctypes.byref(bo),
                                      flags, _stream(stream), ctypes.byref(t), ctypes.byref(ms)))
-    return {"chunk": t.chunk, "ks_eg": t.ks_eg, "mac_my": t.mac_my}, float(ms.value)
+    return {"chunk": t.chunk, "ks_eg": t.ks_eg, "mac_my": t.mac_my, "ntt_threads": t.ntt_threads}, float(ms.value)
 
 
 def fhelin_graph_capture_linear(ctx, plan, ks, pts, x: torch.Tensor, x_levels, y: torch.Tensor, y_levels, flags=0,

@@ -50,3 +50,66 @@ def test_prime_helper_matches_oracle():
         assert list(out) == O.gen_primes(log_n, bits, count)
     bad = (ctypes.c_uint64 * 1)()
     assert lib.fhelin_primes_generate(16, 10, 1, ctypes.cast(bad, ctypes.c_void_p)) == -1
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("log_n", ctypes.c_int32), ("n_q", ctypes.c_int32), ("n_p", ctypes.c_int32),
+                ("dnum", ctypes.c_int32), ("q", ctypes.c_void_p), ("p", ctypes.c_void_p)]
+
+
+def _create(lib, log_n, q, p, dnum):
+    qa = (ctypes.c_uint64 * max(1, len(q)))(*q)
+    pa = (ctypes.c_uint64 * max(1, len(p)))(*p)
+    prm = _Params(log_n, len(q), len(p), dnum, ctypes.cast(qa, ctypes.c_void_p), ctypes.cast(pa, ctypes.c_void_p))
+    out = ctypes.c_void_p()
+    return lib.fhelin_ctx_create(ctypes.byref(prm), ctypes.byref(out)), out
+
+
+def test_ctx_create_rejects_bad_parameters_on_the_host():
+    """Parameter checks run before any HIP call (this machine has no GPU): each bad
+    set returns its status and a message, and nothing is created."""
+    from oracle import oracle as O
+    lib = ctypes.CDLL(LIB)
+    lib.fhelin_last_error.restype = ctypes.c_char_p
+    pr = O.gen_primes(12, 50, 8)           # q = 1 mod 2^13, descending
+    p, q = pr[:2], pr[2:8]
+    bad = {
+        "log_n": (9, q, p, 3, -2, b"log_n"),
+        "dnum 0": (12, q, p, 0, -2, b"dnum"),
+        "dnum > n_q": (12, q, p, 7, -2, b"dnum"),
+        "not prime": (12, q[:5] + [q[5] + 2 * 8192], p, 3, -2, b"prime"),
+        "not 1 mod 2N": (12, q[:5] + [pr[0] + 2], p, 3, -2, b"1 mod 2N"),
+        "duplicate": (12, q[:5] + [q[0]], p, 3, -2, b"distinct"),
+        "too large": (12, q[:5] + [(1 << 60) + 1], p, 3, -2, b"2^60"),
+        "P too small": (12, q, p[:1], 2, -2, b"special modulus"),
+        "no special prime": (12, q, [], 3, -2, b"n_p"),
+        "too many digits' primes": (12, O.gen_primes(12, 50, 20)[2:20], p, 2, -2, b"digits"),
+    }
+    for name, (log_n, qq, pp, dnum, status, msg) in bad.items():
+        rc, out = _create(lib, log_n, qq, pp, dnum)
+        assert rc == status, name
+        assert msg in lib.fhelin_last_error(), (name, lib.fhelin_last_error())
+        assert not out.value, name
+    assert lib.fhelin_ctx_create(None, None) == -1
+
+
+def test_null_and_unknown_handles_rejected_without_a_gpu():
+    """Destroy/release and layer calls take only handles the library handed out:
+    null or foreign pointers are rejected with FHELIN_E_INVALID_ARG before anything
+    is dereferenced."""
+    lib = ctypes.CDLL(LIB)
+    lib.fhelin_last_error.restype = ctypes.c_char_p
+    fake = ctypes.create_string_buffer(4096)
+    for fn in ("fhelin_ctx_destroy", "fhelin_keyset_release", "fhelin_ptset_release", "fhelin_plan_destroy",
+               "fhelin_graph_destroy"):
+        f = getattr(lib, fn)
+        f.argtypes = [ctypes.c_void_p]
+        assert f(None) == -1, fn
+        assert f(ctypes.addressof(fake)) == -1, fn
+        assert b"handle" in lib.fhelin_last_error()
+    lib.fhelin_graph_launch.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    assert lib.fhelin_graph_launch(ctypes.addressof(fake), None) == -1
+    lib.fhelin_linear_apply.argtypes = [ctypes.c_void_p] * 6 + [ctypes.c_int32, ctypes.c_void_p]
+    assert lib.fhelin_linear_apply(ctypes.addressof(fake), ctypes.addressof(fake), None, ctypes.addressof(fake),
+                                   None, None, 0, None) == -1
+    assert b"context" in lib.fhelin_last_error()

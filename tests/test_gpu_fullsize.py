@@ -61,12 +61,15 @@ def fc_batch():
         pset = F.fhelin_pt_import(ctx, dev(pts), level=prm.L)
         x = dev(pad_cts(cts, prm.L, prm.N))
         out = {}
-        for name, flags in (("dh", F.FHELIN_APPLY_RESCALE | F.FHELIN_APPLY_HOIST_MODDOWN),
-                            ("rot", F.FHELIN_APPLY_RESCALE)):
+        dhf = F.FHELIN_APPLY_RESCALE | F.FHELIN_APPLY_HOIST_MODDOWN
+        for name, flags, nt in (("dh", dhf, 256), ("rot", F.FHELIN_APPLY_RESCALE, 256), ("dh_nt128", dhf, 128),
+                                ("dh_nt512", dhf, 512)):
+            F.fhelin_plan_set_tune(plan, chunk=0, ks_eg=16, mac_my=2, ntt_threads=nt)
             y = dev(np.zeros((64, 2, prm.L, prm.N), np.uint64))
             F.fhelin_linear_apply(ctx, plan, ks, pset, x, levels, y, [l - 1 for l in levels], flags)
             out[name] = host(y)
             del y
+        F.fhelin_plan_set_tune(plan)
         print("gpu done", flush=True)
         # four requests alone, under the benchmark's schedule
         alone = {}
@@ -92,6 +95,14 @@ def test_fc256_batch64_request_alone(fc_batch):
     for t, y1 in fc_batch["alone"].items():
         l = levels[t]
         assert np.array_equal(y1[:, : l - 1], got[t, :, : l - 1]), (t, l)
+
+
+def test_fc256_batch64_ntt_tiles_identical(fc_batch):
+    """The batch under 128- and 512-thread NTT tiles gives the 256-thread tile's bits."""
+    levels, out = fc_batch["levels"], fc_batch["out"]
+    for name in ("dh_nt128", "dh_nt512"):
+        for t, l in enumerate(levels):
+            assert np.array_equal(out[name][t, :, : l - 1], out["dh"][t, :, : l - 1]), (name, t)
 
 
 @pytest.mark.parametrize("level", [4, 8, 12])

@@ -355,7 +355,7 @@ def test_tunes_bit_identical_and_autotune(F, dh):
             for c, l in zip(cts, levels)]
     lay = Layer(F, prm, keys, pts, prm.L, fc_n=n, fc_out=n, fc_in=n, n1=n1)
     try:
-        assert F.fhelin_plan_get_tune(lay.plan) == {"chunk": 0, "ks_eg": 16, "mac_my": 2}
+        assert F.fhelin_plan_get_tune(lay.plan) == {"chunk": 0, "ks_eg": 16, "mac_my": 2, "ntt_threads": 256}
         for tune in [dict(chunk=0, ks_eg=8, mac_my=2), dict(chunk=4, ks_eg=3, mac_my=4),
                      dict(chunk=1, ks_eg=16, mac_my=8), dict(chunk=5, ks_eg=1, mac_my=2)]:
             F.fhelin_plan_set_tune(lay.plan, **tune)
@@ -575,3 +575,100 @@ def test_fc_four_digits_multi_client(F, dh):
         F.fhelin_plan_destroy(plan)
     finally:
         F.fhelin_ctx_destroy(ctx)
+
+
+def test_budget_and_handle_lifetimes(F):
+    """A context's HBM budget (fhelin_ctx_set_budget) refuses key loads, plaintext
+    imports and workspace growth that would exceed it with FHELIN_E_BUDGET and leaves
+    the context usable; released or destroyed handles are rejected on a second
+    release instead of being freed twice."""
+    print("budget and handle lifetimes", flush=True)
+    prm = O.make_params(12, 4, 2, 2, 50, 2.0 ** 40)
+    st = synth.Stream(4990)
+    n, n1 = 32, 8
+    sched = O.fc_schedule(n, n1)
+    pts = encode_pts(prm, O.fc_slots(st.he_normal((n, n), n), n, n1, prm.S), prm.L, prm.scale)
+    cl = Client(prm, 4991)
+    keys = cl.keyset(sched.rotations())
+    ct = cl.encrypt_slots(O.fc_input_slots(st.uniform(n, 0, 1), n, prm.S), 4, prm.scale)
+    ctx = ctx_for(F, prm)
+    plan = F.fhelin_plan_create(ctx, F.FHELIN_LAYER_FC, fc_n=n, fc_out=n, fc_in=n, n1=n1)
+    evk, ptd = dev(keys_at(prm, keys, prm.L)), dev(pts.reshape(-1, prm.L + prm.K, prm.N))
+
+    def status(fn):
+        with pytest.raises(F.FhelinError) as ei:
+            fn()
+        return ei.value.status
+
+    F.fhelin_ctx_set_budget(ctx, 1 << 20)
+    assert status(lambda: F.fhelin_keyset_load(ctx, keys.galois, prm.L, evk)) == F.FHELIN_E_BUDGET
+    assert status(lambda: F.fhelin_pt_import(ctx, ptd, level=prm.L)) == F.FHELIN_E_BUDGET
+    F.fhelin_ctx_set_budget(ctx, 0)
+    ks = F.fhelin_keyset_load(ctx, keys.galois, prm.L, evk)
+    pset = F.fhelin_pt_import(ctx, ptd, level=prm.L)
+    F.fhelin_ctx_trim(ctx)
+    used = F.fhelin_ctx_memory(ctx)
+    x = dev(pad_cts([ct], prm.L, prm.N))
+    y = dev(np.zeros((1, 2, prm.L, prm.N), np.uint64))
+    flags = F.FHELIN_APPLY_RESCALE | F.FHELIN_APPLY_HOIST_MODDOWN
+    need = F.fhelin_plan_workspace_bytes(ctx, plan, 1, flags)
+    F.fhelin_ctx_set_budget(ctx, used + need // 2)
+    assert status(lambda: F.fhelin_linear_apply(ctx, plan, ks, pset, x, [4], y, [3], flags)) == F.FHELIN_E_BUDGET
+    F.fhelin_ctx_set_budget(ctx, used + need)
+    F.fhelin_linear_apply(ctx, plan, ks, pset, x, [4], y, [3], flags)
+    want = O.rescale(prm, O.linear(prm, ct[None], 4, sched, pts, keys, hoist_moddown=True)[0], 4)
+    assert np.array_equal(host(y)[0, :, :3], want)
+    # second releases are rejected, not double frees
+    F.fhelin_keyset_release(ks)
+    assert status(lambda: F.fhelin_keyset_release(ks)) == F.FHELIN_E_INVALID_ARG
+    F.fhelin_ptset_release(pset)
+    assert status(lambda: F.fhelin_ptset_release(pset)) == F.FHELIN_E_INVALID_ARG
+    F.fhelin_plan_destroy(plan)
+    assert status(lambda: F.fhelin_plan_destroy(plan)) == F.FHELIN_E_INVALID_ARG
+    F.fhelin_ctx_destroy(ctx)
+    assert status(lambda: F.fhelin_ctx_destroy(ctx)) == F.FHELIN_E_INVALID_ARG
+
+
+@pytest.mark.parametrize("dh", [False, True])
+def test_ntt_tiles_bit_identical(F, dh):
+    """The two-pass NTT kernels (N >= 2^13) at 128, 256 and 512 threads per workgroup
+    give the oracle's ciphertexts bit for bit (N = 2^14, uneven levels), alone and in
+    a batch; the autotuner's choice of the tile is one of them and leaves the layer's
+    result in the output."""
+    print(f"ntt tiles dh={dh}", flush=True)
+    prm = O.make_params(14, 5, 2, 3, 50, 2.0 ** 40)
+    st = synth.Stream(4980 + dh)
+    n, n1 = 64, 8
+    W = st.he_normal((n, n), n)
+    sched = O.fc_schedule(n, n1)
+    pts = encode_pts(prm, O.fc_slots(W, n, n1, prm.S), prm.L, prm.scale)
+    cl = Client(prm, 4981)
+    keys = cl.keyset(sched.rotations())
+    levels = [5, 2, 4, 3]
+    xs = [st.uniform(n, 0, 1) for _ in levels]
+    cts = [cl.encrypt_slots(O.fc_input_slots(x, n, prm.S), l, prm.scale) for x, l in zip(xs, levels)]
+    want = [O.rescale(prm, O.linear(prm, c[None], l, sched, pts, keys, hoist_moddown=dh)[0], l)
+            for c, l in zip(cts, levels)]
+    lay = Layer(F, prm, keys, pts, prm.L, fc_n=n, fc_out=n, fc_in=n, n1=n1)
+    try:
+        for nt in (128, 256, 512):
+            F.fhelin_plan_set_tune(lay.plan, chunk=0, ks_eg=16, mac_my=2, ntt_threads=nt)
+            got = lay.apply(cts, levels, stride=prm.L, dh=dh)
+            for t in range(len(levels)):
+                assert np.array_equal(got[t], want[t]), (nt, t)
+            z = cl.decrypt_slots(got[0], levels[0] - 1, prm.scale ** 2 / prm.q[levels[0] - 1]).real
+            assert _rel(z[:n], W @ xs[0]) < 1e-3
+        with pytest.raises(F.FhelinError):
+            F.fhelin_plan_set_tune(lay.plan, chunk=0, ks_eg=16, mac_my=2, ntt_threads=64)
+        x = dev(pad_cts(cts, prm.L, prm.N))
+        y = dev(np.zeros((len(cts), 2, prm.L, prm.N), np.uint64))
+        flags = F.FHELIN_APPLY_RESCALE | (F.FHELIN_APPLY_HOIST_MODDOWN if dh else 0)
+        best, ms = F.fhelin_plan_autotune(lay.ctx, lay.plan, [lay.ks] * len(cts), lay.pset, x, levels, y,
+                                          [l - 1 for l in levels], flags)
+        print("autotune", best, f"{ms:.3f} ms", flush=True)
+        assert best["ntt_threads"] in (128, 256, 512)
+        got = host(y)
+        for t, l in enumerate(levels):
+            assert np.array_equal(got[t, :, : l - 1], want[t]), t
+    finally:
+        lay.close()
