@@ -46,6 +46,10 @@ def parse():
                                                        "fastest split measured on MI355X)")
     ap.add_argument("--autotune", action="store_true",
                     help="autotune the plan on the batch before warmup (default: the plan's default tune)")
+    ap.add_argument("--persistent", type=int, default=-1,
+                    help="1: each key switch's ModUp and forward NTT in one persistent launch, 0: separate launches "
+                         "(default: the plan's default tune)")
+    ap.add_argument("--ntt-threads", type=int, default=0, help="workgroup size of the two-pass NTT kernels")
     ap.add_argument("--no-one-at-a-time", action="store_true",
                     help="skip the extra one-request-at-a-time comparison after the timed steps")
     ap.add_argument("--serve-requests", type=int, default=200,
@@ -107,13 +111,13 @@ PEAK_MAC = ALU_LANE_OPS / MAC_VALU_OPS / 1e12  # T modular products per second
 HBM_PEAK_GBPS = 8000.0
 # roofline of each kernel class: (bound, unit of `achieved`, peak)
 ROOF = {k: ("alu", "T modmul-butterflies/s", PEAK_BFLY) for k in
-        ("ntt_fwd_cols", "ntt_fwd_rows", "ntt_inv_rows", "ntt_inv_cols")}
+        ("ntt_fwd_cols", "ntt_fwd_rows", "ntt_inv_rows", "ntt_inv_cols", "modup_ntt")}
 ROOF["mac"] = ("alu", "T modular products/s", PEAK_MAC)
 for _k in ("ks_inner", "ks_rot", "ks_sum", "modup", "moddown_fbc", "combine", "copy", "rescale", "mont"):
     ROOF[_k] = ("hbm", "GB/s", HBM_PEAK_GBPS)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic.json")
 KERNELS = ["ntt_fwd_cols", "ntt_fwd_rows", "ntt_inv_rows", "ntt_inv_cols", "mac", "ks_inner", "ks_rot", "ks_sum", "modup",
-           "moddown_fbc", "combine", "rescale", "copy", "mont", "encode"]
+           "moddown_fbc", "combine", "rescale", "copy", "mont", "encode", "modup_ntt"]
 
 
 def _lib_digest() -> str:
@@ -184,18 +188,24 @@ def pmc_summary(dirs: str, args) -> None:
     gib = 1 << 20  # KiB in 1 GiB: the calibration copy moves 1 GiB each way
     f_scale, w_scale = gib / copy_kib(cfetch), gib / copy_kib(cwrite)
     fk, wk = per_kernel(fetch), per_kernel(write)
-    names = {"k_mac": "mac", "k_ks_inner": "ks_inner", "k_ks_rot": "ks_rot", "k_ks_sum": "ks_sum", "k_ntt_fwd_rows": "ntt_fwd_rows",
-             "k_ntt_fwd_cols": "ntt_fwd_cols", "k_ntt_inv_rows": "ntt_inv_rows", "k_ntt_inv_cols": "ntt_inv_cols",
-             "k_modup": "modup", "k_moddown_fbc": "moddown_fbc", "k_moddown_combine": "combine",
-             "k_copy_rows": "copy", "k_rescale": "rescale", "k_to_mont": "mont"}
+    # kernel -> the library's profiling class (several kernels may share one class)
+    names = {"k_mac": "mac", "k_ks_inner": "ks_inner", "k_ks_rot": "ks_rot", "k_ks_sum": "ks_sum",
+             "k_ntt_fwd_rows": "ntt_fwd_rows", "k_ntt_fwd_cols": "ntt_fwd_cols", "k_ntt_inv_rows": "ntt_inv_rows",
+             "k_ntt_inv_cols": "ntt_inv_cols", "k_modup": "modup", "k_modup_ntt": "modup_ntt",
+             "k_moddown_fbc": "moddown_fbc", "k_moddown_coef": "moddown_fbc", "k_moddown_combine": "combine",
+             "k_copy_rows": "copy", "k_ext_lift_add": "copy", "k_rescale": "rescale", "k_to_mont": "mont"}
     out = {"library_sha256": _lib_digest(), "bench_args": traffic_args(args), "fetch_scale": f_scale,
            "write_scale": w_scale, "kernels": {}}
+    acc = {}
     for raw, cls in names.items():
         if raw in fk and raw in wk:
-            fb = sum(fk[raw]) / len(fk[raw]) * 1024 * f_scale
-            wb = sum(wk[raw]) / len(wk[raw]) * 1024 * w_scale
-            out["kernels"][cls] = {"dispatches": len(fk[raw]), "fetch_bytes_per_dispatch": fb,
-                                   "write_bytes_per_dispatch": wb, "bytes_per_dispatch": fb + wb}
+            a = acc.setdefault(cls, [0, 0.0, 0.0])
+            a[0] += len(fk[raw])
+            a[1] += sum(fk[raw]) * 1024 * f_scale
+            a[2] += sum(wk[raw]) * 1024 * w_scale
+    for cls, (n, fb, wb) in acc.items():
+        out["kernels"][cls] = {"dispatches": n, "fetch_bytes_per_dispatch": fb / n, "write_bytes_per_dispatch": wb / n,
+                               "bytes_per_dispatch": (fb + wb) / n}
     with open(TRAFFIC_FILE, "w") as f:
         json.dump(out, f, indent=1)
     print(json.dumps({k: round(v["bytes_per_dispatch"] / 2**30, 3) for k, v in out["kernels"].items()}))
@@ -680,6 +690,13 @@ def main():
         F.fhelin_ptset_release(h[1])
         F.fhelin_keyset_release(h[0])
 
+    if args.persistent >= 0 or args.ntt_threads:
+        t = F.fhelin_plan_get_tune(plan)
+        if args.persistent >= 0:
+            t["persistent"] = args.persistent
+        if args.ntt_threads:
+            t["ntt_threads"] = args.ntt_threads
+        F.fhelin_plan_set_tune(plan, **t)
     tune_info = {"autotuned": False, "tune": F.fhelin_plan_get_tune(plan)}
     if args.autotune:
         ks, pts = step()
@@ -769,6 +786,9 @@ def main():
                     for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["ms_per_step"])},
     }
     res["tune"] = tune_info
+    faults = F.fhelin_ctx_faults(ctx)
+    if faults:
+        res["device_wait_faults"] = faults
     if not args.no_one_at_a_time:
         # the same requests one at a time (keys and weights resident): the unbatched GPU path
         ks, pts = step()
@@ -794,12 +814,15 @@ def main():
     # stored counters were taken with the library that is loaded
     step_bytes = sum(v["bytes"] for v in prof.values()) / args.steps
     meas = {k: measured_traffic(k, v["launches"], args) for k, v in prof.items()}
-    meas_step = (sum(meas[k] * prof[k]["launches"] for k in prof) / args.steps
-                 if all(meas[k] is not None for k in prof) else None)
+    have = [k for k in prof if meas[k] is not None]
+    # measured bytes of the classes the counters cover (all but the encode, whose FFT
+    # kernels are not mapped to a class); null when none is covered
+    meas_step = sum(meas[k] * prof[k]["launches"] for k in have) / args.steps if have else None
     res["hbm_step"] = {"model_bytes_per_step": round(step_bytes), "achieved_GBps": round(step_bytes / (ms / 1e3) / 1e9, 1),
                        "peak_GBps": HBM_PEAK_GBPS, "frac": round(step_bytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBPS, 4),
                        "measured_bytes_per_step": None if meas_step is None else round(meas_step),
-                       "measured_GBps": None if meas_step is None else round(meas_step / (ms / 1e3) / 1e9, 1)}
+                       "measured_GBps": None if meas_step is None else round(meas_step / (ms / 1e3) / 1e9, 1),
+                       "measured_classes": sorted(have)}
     # per-ciphertext accounting of the workload's metric (each request charged for the keys
     # and plaintexts it uses, although the batch reads them once): a ratio, not a rate
     rb, gk = F.fhelin_plan_rotations(plan)

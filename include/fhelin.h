@@ -294,12 +294,17 @@ int fhelin_linear_apply_noalloc(fhelin_ctx *ctx, const fhelin_plan *plan, const 
  *           256 or 512 threads of 16 elements, i.e. column tiles of 8, 16 or 32
  *           columns (2^16) in the first pass and 8, 16 or 32 blocks of 256 in the
  *           second (LDS 17, 35 or 68 KiB per workgroup)
- * A new plan starts at chunk 0, ks_eg 16, mac_my 2, ntt_threads 256. */
+ *   persistent  1: each key switch's ModUp and forward NTT run as one persistent
+ *           launch (N >= 2^13): workgroups claim ModUp chunks, then column tiles,
+ *           then row tiles in ticket order, each tile waiting (bounded) on device
+ *           counters for the tiles it reads; 0: three launches
+ * A new plan starts at chunk 0, ks_eg 16, mac_my 2, ntt_threads 256, persistent 0. */
 typedef struct fhelin_tune {
     int32_t chunk;
     int32_t ks_eg;
     int32_t mac_my;
     int32_t ntt_threads;
+    int32_t persistent;
 } fhelin_tune;
 
 int fhelin_plan_get_tune(const fhelin_plan *plan, fhelin_tune *out);
@@ -309,8 +314,8 @@ int fhelin_plan_set_tune(fhelin_plan *plan, const fhelin_tune *tune);
 /* Autotuner: times the plan's schedule on the caller's batch (the arguments of
  * fhelin_linear_apply_multi) for candidate tunes, one field at a time starting
  * from the plan's current tune (chunk in {all, 32, 16, 8, 4} up to the request
- * count, ks_eg in {4, 8, 16}, mac_my in {2, 4, 8}, ntt_threads in {256, 128, 512}
- * when N >= 2^13), with HIP events on
+ * count, ks_eg in {4, 8, 16}, mac_my in {2, 4, 8}, and when N >= 2^13 ntt_threads
+ * in {256, 128, 512} and persistent in {0, 1}), with HIP events on
  * `stream`, and keeps the fastest in the plan.  Every timed run computes the
  * layer, so `out` holds the layer's result on return.  Synchronises `stream`.
  * best (optional) receives the chosen tune, best_ms (optional) its time in ms. */
@@ -360,7 +365,8 @@ int fhelin_ntt(fhelin_ctx *ctx, uint64_t *rows, const int32_t *mod_index, int32_
  * ntt_inv_cols, ntt_fwd_1, ntt_inv_1, mac, ks_inner (one rotation per
  * entry), ks_rot (a list of rotations for every entry: hoisted baby steps),
  * ks_sum (a sum of key switches per entry: giant steps), modup, moddown_fbc,
- * combine, rescale, copy, mont, encode. */
+ * combine, rescale, copy, mont, encode, modup_ntt (the persistent ModUp + forward
+ * NTT launch). */
 int fhelin_profile_enable(fhelin_ctx *ctx, int32_t enable);
 /* Totals of one kernel class since enabling: launches, summed event time (ms),
  * summed algorithmic work units (butterflies for NTT passes, 64-bit
@@ -387,6 +393,12 @@ int fhelin_profile_read(fhelin_ctx *ctx, const char *kernel, int64_t *launches, 
  * rate); ops_per_s = lane-level operations per second over the whole GPU. */
 int fhelin_diag_alu_rate(int32_t op, int32_t waves_per_simd, int32_t iters, double *ghz, double *clk_per_op,
                          double *ops_per_s);
+
+/* Faults of bounded device-side waits since the last call: the persistent ModUp/NTT
+ * launch gives up a wait after a fixed number of polls instead of hanging, sets
+ * this context's fault word and finishes (its results are then wrong).  Waits for
+ * the device to be idle, returns the word in *faults (0 = none) and clears it. */
+int fhelin_ctx_faults(fhelin_ctx *ctx, uint32_t *faults);
 
 const char *fhelin_last_error(void);
 const char *fhelin_status_string(int status);

@@ -549,6 +549,7 @@ FHELIN_EXPORT int fhelin_plan_get_tune(const fhelin_plan *plan, fhelin_tune *out
     out->ks_eg = t.ks_eg;
     out->mac_my = t.mac_my;
     out->ntt_threads = t.ntt_threads;
+    out->persistent = t.persistent;
     return FHELIN_OK;
     API_END
 }
@@ -560,8 +561,10 @@ FHELIN_EXPORT int fhelin_plan_set_tune(fhelin_plan *plan, const fhelin_tune *tun
     t.ks_eg = tune->ks_eg;
     t.mac_my = tune->mac_my;
     t.ntt_threads = tune->ntt_threads;
+    t.persistent = tune->persistent;
     FL_CHECK(tune_valid(t), FHELIN_E_INVALID_ARG,
-             "tune out of range (chunk 0..64, ks_eg 1..64, mac_my 2, 4 or 8, ntt_threads 128, 256 or 512)");
+             "tune out of range (chunk 0..64, ks_eg 1..64, mac_my 2, 4 or 8, ntt_threads 128, 256 or 512, "
+             "persistent 0 or 1)");
     ((Plan *)plan)->tune = t;
     return FHELIN_OK;
     API_END
@@ -583,6 +586,7 @@ FHELIN_EXPORT int fhelin_plan_autotune(fhelin_ctx *ctx, fhelin_plan *plan, const
         best->ks_eg = t.ks_eg;
         best->mac_my = t.mac_my;
         best->ntt_threads = t.ntt_threads;
+        best->persistent = t.persistent;
     }
     if (best_ms) *best_ms = ms;
     return FHELIN_OK;
@@ -703,6 +707,23 @@ FHELIN_EXPORT int fhelin_profile_enable(fhelin_ctx *ctx, int32_t enable) {
 FHELIN_EXPORT int fhelin_diag_alu_rate(int32_t op, int32_t waves_per_simd, int32_t iters, double *ghz,
                                        double *clk_per_op, double *ops_per_s) {
     API_BEGIN return diag_alu_rate(op, waves_per_simd, iters, ghz, clk_per_op, ops_per_s);
+    API_END
+}
+
+FHELIN_EXPORT int fhelin_ctx_faults(fhelin_ctx *ctx, uint32_t *faults) {
+    API_BEGIN FL_LIVE(H_CTX, ctx);
+    FL_CHECK(faults, FHELIN_E_INVALID_ARG, "null argument");
+    Ctx *c = (Ctx *)ctx;
+    DeviceGuard g(c);
+    FL_TRY_HIP(hipDeviceSynchronize());
+    uint32_t v = 0;
+    FL_TRY_HIP(hipMemcpy(&v, c->d_fault, sizeof(v), hipMemcpyDeviceToHost));
+    if (v) {
+        const uint32_t zero = 0;
+        FL_TRY_HIP(hipMemcpy(c->d_fault, &zero, sizeof(zero), hipMemcpyHostToDevice));
+    }
+    *faults = v;
+    return FHELIN_OK;
     API_END
 }
 

@@ -351,6 +351,7 @@ int ctx_create(const fhelin_params *prm, Ctx **out) {
     }
     FL_RET(upload(c.get(), &c->d_slot_idx, si));
     FL_RET(upload(c.get(), &c->d_zero, std::vector<uint64_t>(32, 0)));
+    FL_RET(upload(c.get(), &c->d_fault, std::vector<uint32_t>(64, 0)));
 
     *out = c.release();
     return FHELIN_OK;
@@ -360,7 +361,7 @@ const char *const PROF_NAMES[PK_COUNT] = {"ntt_fwd_cols", "ntt_fwd_rows", "ntt_i
                                           "ntt_fwd_1",    "ntt_inv_1",    "mac",          "ks_inner",
                                           "modup",        "moddown_fbc",  "combine",      "rescale",
                                           "copy",         "mont",         "encode",       "ks_rot",
-                                          "ks_sum"};
+                                          "ks_sum",       "modup_ntt"};
 
 hipEvent_t Profiler::get() {
     if (!pool.empty()) {
@@ -442,6 +443,7 @@ Ctx::~Ctx() {
     (void)hipFree(d_zeta);
     (void)hipFree(d_slot_idx);
     (void)hipFree(d_zero);
+    (void)hipFree(d_fault);
 }
 
 void ctx_destroy(Ctx *c) { delete c; }

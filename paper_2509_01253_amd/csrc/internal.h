@@ -90,7 +90,7 @@ struct Workspace;
 enum ProfKind : int {
     PK_NTT_FWD_COLS = 0, PK_NTT_FWD_ROWS, PK_NTT_INV_ROWS, PK_NTT_INV_COLS, PK_NTT_FWD_1, PK_NTT_INV_1,
     PK_MAC, PK_KS_INNER, PK_MODUP, PK_MODDOWN_FBC, PK_COMBINE, PK_RESCALE, PK_COPY, PK_MONT, PK_ENCODE, PK_KS_ROT,
-    PK_KS_SUM, PK_COUNT
+    PK_KS_SUM, PK_MODUP_NTT, PK_COUNT
 };
 extern const char *const PROF_NAMES[PK_COUNT];
 
@@ -127,6 +127,7 @@ struct Ctx {
     double *d_zeta = nullptr;                      // exp(i pi k / N), k < N: [N] (re, im)
     int32_t *d_slot_idx = nullptr;                 // (5^j mod 2N - 1) / 2, j < N/2
     uint64_t *d_zero = nullptr;                    // 256 zero bytes (padding source of tile loads)
+    uint32_t *d_fault = nullptr;                   // bounded waits that gave up (persistent launches)
     // memory accounting
     uint64_t budget = 0;
     uint64_t used = 0;
@@ -329,6 +330,7 @@ struct Tune {
     int ks_eg = 16;   // batch entries per key-switch inner-product workgroup
     int mac_my = 2;   // requests per thread in the multiply-accumulate
     int ntt_threads = 256;  // workgroup size of the two-pass NTT kernels (128, 256, 512)
+    int persistent = 0;     // 1: each key switch's ModUp and forward NTT in one persistent launch
 };
 bool tune_valid(const Tune &t);
 
@@ -383,6 +385,16 @@ int launch_ntt(const Ctx *c, const RowMap &rows, int inverse, hipStream_t s, boo
 // out of place: rows of `src` (same row enumeration as `rows`, its own layout) transformed into `rows`
 int launch_ntt_from(const Ctx *c, const RowMap &rows, const RowMap &src, int inverse, hipStream_t s,
                     bool to_mont = false);
+// persistent ModUp + forward NTT (one launch): digits of the entries' ModUp written to
+// `digits` and transformed over the rows of `rm` (ROWS_MODUP or ROWS_DIGITS); ctl is a
+// control block of PERSIST_CTL_WORDS words (zeroed by the launch itself); N >= 2^13
+constexpr int PERSIST_DIGITS = 16;  // ModUp counters per entry (digits)
+constexpr int PERSIST_ROWS = 640;   // transform counters per entry (digit rows)
+constexpr int PERSIST_CTL_WORDS = 1 + MAX_BATCH * (PERSIST_DIGITS + PERSIST_ROWS);
+constexpr uint32_t PERSIST_SPIN_LIMIT = 1u << 20;  // polls before a wait gives up
+int launch_modup_ntt(const Ctx *c, const Batch &b, const uint64_t *coef, int64_t coef_es, const uint64_t *ntt,
+                     int64_t ntt_es, uint64_t *digits, int64_t digits_es, const RowMap &rm, uint32_t *ctl,
+                     hipStream_t s);
 // workgroup size of the two-pass NTT kernels for launches from the calling thread
 // (128, 256 or 512; anything else = 256); returns the previous setting
 int ntt_threads_set(int nt);

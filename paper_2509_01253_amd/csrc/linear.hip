@@ -339,7 +339,8 @@ static int launch_mac(const Ctx *c, const Plan *p, MacArgs &ma, const Batch &bou
 bool tune_valid(const Tune &t) {
     return t.chunk >= 0 && t.chunk <= MAX_BATCH && t.ks_eg >= 1 && t.ks_eg <= MAX_BATCH &&
            (t.mac_my == 2 || t.mac_my == 4 || t.mac_my == 8) &&
-           (t.ntt_threads == 128 || t.ntt_threads == 256 || t.ntt_threads == 512);
+           (t.ntt_threads == 128 || t.ntt_threads == 256 || t.ntt_threads == 512) &&
+           (t.persistent == 0 || t.persistent == 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -405,7 +406,18 @@ struct KsScratch {
     uint64_t *dg;  int64_t dg_es;   // [dnum][L+K] digits
     uint64_t *u;   int64_t u_es;    // [2][L+K]
     uint64_t *md;  int64_t md_es;   // [2][L]
+    uint32_t *ctl = nullptr;        // control block of the persistent ModUp + NTT launch (null: separate launches)
 };
+
+// ModUp of the coefficient-domain limbs at `coef` into digits, then their forward NTT over
+// the rows of `rm`: one persistent launch when a control block is given (N >= 2^13),
+// else the ModUp kernel and the two NTT passes
+static int modup_and_ntt(const Ctx *c, const Batch &b, const uint64_t *coef, int64_t coef_es, const uint64_t *ntt,
+                         int64_t ntt_es, uint64_t *dg, int64_t dg_es, const RowMap &rm, uint32_t *ctl, hipStream_t s) {
+    if (ctl && c->log_n >= 13) return launch_modup_ntt(c, b, coef, coef_es, ntt, ntt_es, dg, dg_es, rm, ctl, s);
+    FL_RET(launch_modup(c, b, coef, coef_es, ntt, ntt_es, dg, dg_es, s));
+    return launch_ntt(c, rm, 0, s);
+}
 
 // ModUp of the c1 polynomial of ct entries (NTT domain in, digits NTT domain out)
 static int modup_ct(const Ctx *c, const Batch &b, const uint64_t *ct, int64_t ct_es, int ct_stride,
@@ -414,9 +426,8 @@ static int modup_ct(const Ctx *c, const Batch &b, const uint64_t *ct, int64_t ct
     RowMap src = rows_ct(c, b, (uint64_t *)ct, ct_es, ct_stride, 1, 1);
     RowMap dst = rows_ct(c, b, w.tc, w.tc_es, c->L, 0, 1);
     FL_RET(launch_ntt_from(c, dst, src, 1, s));  // c1 to the coefficient domain, out of place
-    FL_RET(launch_modup(c, b, w.tc, w.tc_es, ct + (int64_t)ct_stride * N, ct_es, w.dg, w.dg_es, s));
-    FL_RET(launch_ntt(c, rows_kind(c, b, w.dg, w.dg_es, ROWS_MODUP, 0), 0, s));
-    return FHELIN_OK;
+    return modup_and_ntt(c, b, w.tc, w.tc_es, ct + (int64_t)ct_stride * N, ct_es, w.dg, w.dg_es,
+                         rows_kind(c, b, w.dg, w.dg_es, ROWS_MODUP, 0), w.ctl, s);
 }
 
 // inner product + ModDown + combine, digits already in w.dg
@@ -507,12 +518,15 @@ static int chunk_of(const Plan *p, int n_requests, int max_chunk) {
     return std::min(chunk, std::max(1, n_requests));
 }
 
+// the persistent launch's control block, after the chunk's buffers in the workspace
+static constexpr size_t CTL_BYTES = ((size_t)PERSIST_CTL_WORDS * 4 + 255) / 256 * 256;
+
 size_t linear_workspace_bytes(const Ctx *c, const Plan *p, int n_requests, int max_chunk, int flags) {
     int Bp = 0;
     for (int r : p->rb) Bp += galois_of_rotation(r, c->log_n) == 1 ? 0 : 1;
     const int chunk = chunk_of(p, n_requests, max_chunk);
     size_t per = (flags & FHELIN_APPLY_HOIST_MODDOWN) ? limbs_per_request_dh(c, p, Bp) : limbs_per_request(c, p, Bp);
-    return per * chunk * (size_t)c->N * sizeof(uint64_t);
+    return per * chunk * (size_t)c->N * sizeof(uint64_t) + (p->tune.persistent ? CTL_BYTES : 0);
 }
 
 // Export Y (NTT, [2][L] per entry) to the caller's batch, with or without rescale.
@@ -533,12 +547,11 @@ static int export_out(Ctx *c, const Batch &bout, uint64_t *Y, const fhelin_ct_ba
 // conversion and combination in one pass), which is where ModUp needs its input; the
 // digits' own limbs are copied there and transformed with the rest.
 static int giant_moddown_modup(const Ctx *c, const Batch &b, uint64_t *a1, int64_t a_es, uint64_t *tc,
-                               uint64_t *dg, int64_t dg_es, hipStream_t s) {
+                               uint64_t *dg, int64_t dg_es, uint32_t *ctl, hipStream_t s) {
     const int64_t LN = (int64_t)c->L * c->N;
     FL_RET(launch_ntt(c, rows_kind(c, b, a1, a_es, ROWS_EXT, 1), 1, s));
     FL_RET(launch_moddown_coef(c, b, a1, a_es, tc, LN, s));
-    FL_RET(launch_modup(c, b, tc, LN, tc, LN, dg, dg_es, s));
-    return launch_ntt(c, rows_kind(c, b, dg, dg_es, ROWS_DIGITS, 0), 0, s);
+    return modup_and_ntt(c, b, tc, LN, tc, LN, dg, dg_es, rows_kind(c, b, dg, dg_es, ROWS_DIGITS, 0), ctl, s);
 }
 
 // One chunk of requests with the double-hoisted schedule (Bossuat et al. 2021): baby
@@ -547,7 +560,7 @@ static int giant_moddown_modup(const Ctx *c, const Batch &b, uint64_t *a1, int64
 // ModDown per output ends the layer.
 static int apply_chunk_dh(Ctx *c, const Plan *p, const KeySet *const *kss, const PtSet *pts,
                           const fhelin_ct_batch *in, const fhelin_ct_batch *out, bool rescale, hipStream_t s,
-                          uint64_t *ws, int r0, int Rc, MacArgs ma, int Bp) {
+                          uint64_t *ws, int r0, int Rc, MacArgs ma, int Bp, uint32_t *ctl) {
     const int64_t N = c->N, L = c->L, K = c->K, E = L + K;
     const int B = (int)p->rb.size(), G = (int)p->gk.size();
     const int64_t ct = 2 * L * N, ext = 2 * E * N, dg = (int64_t)c->dnum * E * N;
@@ -579,7 +592,7 @@ static int apply_chunk_dh(Ctx *c, const Plan *p, const KeySet *const *kss, const
     if (has_identity) FL_RET(launch_ext_lift_add(c, bin, X, ct, (int)L, 1, 0, XL, ext, s));
     // 3. baby rotations in the extended basis: (P sigma(c0) + u0, u1)
     if (Bp > 0) {
-        KsScratch wb{TC, L * N, D, dg, nullptr, 0, MD, ct};
+        KsScratch wb{TC, L * N, D, dg, nullptr, 0, MD, ct, ctl};
         FL_RET(modup_ct(c, bin, X, ct, (int)L, wb, s));
         // one launch for every baby rotation when all key sets of the chunk hold the
         // rotations' keys at the same indices (always, for one client)
@@ -685,15 +698,16 @@ static int apply_chunk_dh(Ctx *c, const Plan *p, const KeySet *const *kss, const
                         bg.level[i] = bout.level[0];
                         bg.g[i] = 1;
                     }
-                    FL_RET(giant_moddown_modup(c, bg, A + jg[0] * ext + E * N, ext, RB, DG, (int64_t)Emax * dg, s));
+                    FL_RET(giant_moddown_modup(c, bg, A + jg[0] * ext + E * N, ext, RB, DG, (int64_t)Emax * dg, ctl, s));
                 } else {
                     for (int i = 0; i < sum.n; ++i)
                         FL_RET(giant_moddown_modup(c, bout, A + jg[i] * ext + E * N, a_es, TC, DG + sum.dig_off[i], dg,
-                                                   s));
+                                                   ctl, s));
                 }
             } else {
                 for (int i = 0; i < sum.n; ++i)
-                    FL_RET(giant_moddown_modup(c, bout, A + jg[i] * ext + E * N, a_es, TC, DG + sum.dig_off[i], dg, s));
+                    FL_RET(giant_moddown_modup(c, bout, A + jg[i] * ext + E * N, a_es, TC, DG + sum.dig_off[i], dg, ctl,
+                                               s));
             }
             uint64_t *dst = bufs[which];
             FL_RET(launch_ks_sum(c, bsum, sum, DG, dg, A, a_es, init, init_es, dst, ext, s));
@@ -715,7 +729,7 @@ static int apply_chunk_dh(Ctx *c, const Plan *p, const KeySet *const *kss, const
         }
         set_keys(bout, p->n_out, kss + r0, g);
         // ModUp(ModDown(A~_j.c1)) and the inner product, plus sigma(A~_j.c0), summed into YE
-        FL_RET(giant_moddown_modup(c, bout, Aj + E * N, a_es, TC, DG, dg, s));
+        FL_RET(giant_moddown_modup(c, bout, Aj + E * N, a_es, TC, DG, dg, ctl, s));
         FL_RET(launch_ks_inner_add(c, bout, DG, dg, YE, ext, Aj, a_es, 1, first ? 0 : 1, s, p->tune.ks_eg));
         first = false;
     }
@@ -786,21 +800,23 @@ int linear_apply(Ctx *c, const Plan *p, const KeySet *const *kss, const PtSet *p
     const bool dh = flags & FHELIN_APPLY_HOIST_MODDOWN;
     const size_t per_request =
         (dh ? limbs_per_request_dh(c, p, Bp) : limbs_per_request(c, p, Bp)) * (size_t)N * sizeof(uint64_t);
+    const size_t ctl_bytes = p->tune.persistent ? CTL_BYTES : 0;
     if (fixed_ws) {
-        const size_t fit = fixed_bytes / per_request;
+        const size_t fit = fixed_bytes > ctl_bytes ? (fixed_bytes - ctl_bytes) / per_request : 0;
         FL_CHECK(fit >= 1, FHELIN_E_UNSUPPORTED_PARAM,
-                 "one request of this layer needs " + std::to_string(per_request) + " bytes of scratch; the fixed "
-                 "scratch holds " + std::to_string(fixed_bytes));
+                 "one request of this layer needs " + std::to_string(per_request + ctl_bytes) + " bytes of scratch; "
+                 "the fixed scratch holds " + std::to_string(fixed_bytes));
         chunk = std::min<int>(chunk, (int)std::min<size_t>(fit, MAX_BATCH));
         ws = fixed_ws;
     } else {
-        FL_RET(workspace_get(c, s, per_request * chunk, &ws));
+        FL_RET(workspace_get(c, s, per_request * chunk + ctl_bytes, &ws));
     }
+    uint32_t *ctl = ctl_bytes ? (uint32_t *)((char *)ws + per_request * chunk) : nullptr;
 
     const int64_t ct = 2 * L * N, dg = (int64_t)c->dnum * (L + K) * N;
     if (dh) {
         for (int r0 = 0; r0 < R; r0 += chunk)
-            FL_RET(apply_chunk_dh(c, p, kss, pts, in, out, rescale, s, ws, r0, std::min(chunk, R - r0), ma, Bp));
+            FL_RET(apply_chunk_dh(c, p, kss, pts, in, out, rescale, s, ws, r0, std::min(chunk, R - r0), ma, Bp, ctl));
         return FHELIN_OK;
     }
     for (int r0 = 0; r0 < R; r0 += chunk) {
@@ -821,7 +837,7 @@ int linear_apply(Ctx *c, const Plan *p, const KeySet *const *kss, const PtSet *p
             bout.level[e] = (uint8_t)in->levels[(r0 + e / p->n_out) * p->n_in];
             bout.g[e] = 1;
         }
-        KsScratch w{TC, L * N, DG, dg, U, 2 * (L + K) * N, MD, 2 * L * N};
+        KsScratch w{TC, L * N, DG, dg, U, 2 * (L + K) * N, MD, 2 * L * N, ctl};
         // 1. import inputs to the NTT domain
         const int64_t in_es = (int64_t)2 * in->stride * N;
         RowMap src = rows_ct(c, bin, in->data + (int64_t)r0 * p->n_in * in_es, in_es, in->stride, 0, 2);
@@ -923,15 +939,18 @@ int plan_autotune(Ctx *c, Plan *p, const KeySet *const *kss, const PtSet *pts, c
     Tune best = start;
     double best_t = 0;
     int rc = time_apply(c, p, kss, pts, in, out, flags, s, e0, e1, &best_t);
-    const int chunks[] = {0, 32, 16, 8, 4}, egs[] = {4, 8, 16}, mys[] = {2, 4, 8}, nts[] = {256, 128, 512};
-    // the NTT tile matters only for the two-pass transforms (N >= 2^13)
-    const int n_fields = c->log_n > 12 ? 4 : 3;
+    const int chunks[] = {0, 32, 16, 8, 4}, egs[] = {4, 8, 16}, mys[] = {2, 4, 8}, nts[] = {256, 128, 512},
+              pers[] = {0, 1};
+    // the NTT tile and the persistent ModUp/NTT launch matter only for the two-pass
+    // transforms (N >= 2^13)
+    const int n_fields = c->log_n > 12 ? 5 : 3;
     for (int field = 0; field < n_fields && rc == FHELIN_OK; ++field) {
-        const int *vals = field == 0 ? chunks : field == 1 ? egs : field == 2 ? mys : nts;
-        const int nv = field == 0 ? 5 : 3;
+        const int *vals = field == 0 ? chunks : field == 1 ? egs : field == 2 ? mys : field == 3 ? nts : pers;
+        const int nv = field == 0 ? 5 : field == 4 ? 2 : 3;
         for (int i = 0; i < nv && rc == FHELIN_OK; ++i) {
             Tune t = best;
-            int &f = field == 0 ? t.chunk : field == 1 ? t.ks_eg : field == 2 ? t.mac_my : t.ntt_threads;
+            int &f = field == 0 ? t.chunk : field == 1 ? t.ks_eg : field == 2 ? t.mac_my : field == 3 ? t.ntt_threads
+                                                                                                    : t.persistent;
             if (f == vals[i]) continue;
             if (field == 0 && vals[i] >= R) continue;  // same as "all" for this batch
             f = vals[i];

@@ -18,6 +18,7 @@
 // Grid: x = tile within the limb, y = row within a batch entry, z = batch entry.
 #include "internal.h"
 #include "modarith.h"
+#include "modup.h"
 
 namespace fl {
 
@@ -500,6 +501,155 @@ static void launch_ntt_t(const Ctx *c, const RowMap &rm, const RowMap &src, int 
         else if (tl_ntt_threads == 512) launch_two_pass<L2, F53, 512>(c, rm, src, rows, inverse, to_mont, s, bfly_per_stage, row_bytes);
         else launch_two_pass<L2, F53, 256>(c, rm, src, rows, inverse, to_mont, s, bfly_per_stage, row_bytes);
     }
+}
+
+// ---------------------------------------------------------------------------
+// persistent ModUp + forward NTT (one launch for a key switch's digit
+// decomposition and its transform)
+// ---------------------------------------------------------------------------
+// Work items, claimed in ticket order from a counter: every ModUp chunk (entry, digit,
+// 256 coefficients), then every column tile of every digit row, then every row tile.
+// A column tile waits until all ModUp chunks of its digit are done; a row tile until
+// all column tiles of its row are.  An item only ever waits for items with smaller
+// tickets, which workgroups already running have claimed and which wait only for
+// smaller tickets still, so the launch drains whatever the number of resident
+// workgroups.  Waits are bounded: past spin_limit polls the workgroup sets the
+// context's fault word and goes on (the result is then wrong and the host reports
+// it), so no launch can hang.  Completion counters are released and acquired at
+// device scope (stores of a tile written back before its counter moves, caches
+// invalidated before the dependent tile reads).
+// Every wave fences at device scope on both sides: a tile's stores are written back
+// (the 8 L2s of the chip are not coherent with each other) before its counter moves,
+// and every wave of a dependent tile invalidates its caches before reading.  (Fencing
+// once per workgroup after a barrier was measured to leave stale data: the barrier
+// does not make the other waves' stores visible at device scope.)
+__device__ __forceinline__ void persist_wait(const uint32_t *ctr, uint32_t target, uint32_t *fault,
+                                             uint32_t spin_limit) {
+    if (threadIdx.x == 0) {
+        uint32_t spins = 0;
+        while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (++spins > spin_limit) {
+                atomicOr(fault, 1u);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+    }
+    __syncthreads();
+    __threadfence();
+}
+
+__device__ __forceinline__ void persist_done(uint32_t *ctr) {
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int LOGN, bool F53>
+__global__ void __launch_bounds__(256, 3) k_modup_ntt(Batch b, const ModConst *__restrict__ mods,
+                                                   const ModUpTab *__restrict__ tabs, const uint64_t *__restrict__ coef,
+                                                   int64_t coef_es, const uint64_t *__restrict__ ntt, int64_t ntt_es,
+                                                   uint64_t *__restrict__ digits, int64_t digits_es, RowMap rm,
+                                                   const uint64_t *__restrict__ tw, const uint64_t *__restrict__ twp,
+                                                   uint32_t *ctl, uint32_t *fault, int L, int K, int alpha, int dnum,
+                                                   int beta_max, int rows_max, uint32_t spin_limit) {
+    constexpr int N = 1 << LOGN, NT = 256, S = LOGN - 8, T = 1 << (S - 4), CP = NT / T + 1;
+    constexpr int TILES = N / (16 * NT), CHUNKS = N / 256;
+    constexpr int LDS_COLS = (1 << S) * CP, LDS_ROWS = (NT / 16) * 272;
+    __shared__ uint64_t s[LDS_COLS > LDS_ROWS ? LDS_COLS : LDS_ROWS];
+    __shared__ uint32_t item;
+    const uint32_t n = (uint32_t)b.n;
+    const uint32_t n_m = n * beta_max * CHUNKS, n_c = n * rows_max * TILES, total = n_m + 2 * n_c;
+    uint32_t *ticket = ctl, *cnt_m = ctl + 1, *cnt_c = cnt_m + n * PERSIST_DIGITS;
+    for (;;) {
+        __syncthreads();  // the previous item's readers of `item` and of the LDS are done
+        if (threadIdx.x == 0) item = atomicAdd(ticket, 1u);
+        __syncthreads();
+        const uint32_t it = item;
+        if (it >= total) break;
+        if (it < n_m) {
+            const int x = (int)(it % CHUNKS), j = (int)((it / CHUNKS) % beta_max), t = (int)(it / (CHUNKS * beta_max));
+            if (j >= (b.level[t] + alpha - 1) / alpha) continue;
+            modup_tile(b, mods, tabs, coef, coef_es, ntt, ntt_es, digits, digits_es, LOGN, L, K, alpha, dnum, x, j,
+                       t);
+            persist_done(&cnt_m[t * PERSIST_DIGITS + j]);
+            continue;
+        }
+        const bool row_pass = it >= n_m + n_c;
+        const uint32_t i2 = row_pass ? it - n_m - n_c : it - n_m;
+        const int x = (int)(i2 % TILES), r = (int)((i2 / TILES) % rows_max), t = (int)(i2 / (TILES * rows_max));
+        uint64_t *px;
+        int mi;
+        if (!row_at(rm, t, r, px, mi)) continue;
+        if (!row_pass) {
+            // digit of the row: its offset in the entry's digit buffer is (j (L+K) + slot) N
+            const int j = (int)(((px - rm.base) - (int64_t)t * rm.ct_stride) / N / (L + K));
+            persist_wait(&cnt_m[t * PERSIST_DIGITS + j], CHUNKS, fault, spin_limit);
+            fwd_cols_tile<LOGN, F53, NT>(px, px, mi, x, mods, tw, twp, s);
+            persist_done(&cnt_c[t * rows_max + r]);
+        } else {
+            persist_wait(&cnt_c[t * rows_max + r], TILES, fault, spin_limit);
+            fwd_rows_tile<LOGN, false, F53, NT>(px, mi, x, mods, tw, twp, s);
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) k_zero_u32(uint32_t *p, int n) {
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) p[i] = 0;
+}
+
+template <int LOGN, bool F53>
+static int launch_modup_ntt_t(const Ctx *c, const Batch &b, const uint64_t *coef, int64_t coef_es,
+                              const uint64_t *ntt, int64_t ntt_es, uint64_t *digits, int64_t digits_es,
+                              const RowMap &rm, uint32_t *ctl, hipStream_t s) {
+    int lmax = 0;
+    for (int t = 0; t < b.n; ++t) lmax = b.level[t] > lmax ? b.level[t] : lmax;
+    const int beta_max = (lmax + c->alpha - 1) / c->alpha;
+    const int rows_max = rowmap_max_rows(rm);
+    FL_CHECK(b.n <= MAX_BATCH && beta_max <= PERSIST_DIGITS && rows_max <= PERSIST_ROWS, FHELIN_E_UNSUPPORTED_PARAM,
+             "persistent ModUp/NTT: batch beyond its counters");
+    const int n_ctl = 1 + b.n * PERSIST_DIGITS + b.n * rows_max;
+    hipLaunchKernelGGL(k_zero_u32, dim3((n_ctl + 255) / 256), dim3(256), 0, s, ctl, n_ctl);
+    constexpr int N = 1 << LOGN;
+    double rows = 0, units = 0, bytes = 0;
+    for (int t = 0; t < b.n; ++t) {
+        const double l = b.level[t], beta = std::ceil(l / c->alpha);
+        rows += rowmap_rows(rm, t);
+        units += beta * (l + c->K) * c->N;
+        bytes += 8.0 * c->N * (l + beta * (l + c->K));
+    }
+    // work: the transforms' butterflies (the ModUp's conversions ride along); bytes: the
+    // ModUp's input and output once (the transforms' passes over the digits stay in the
+    // same launch)
+    (void)units;
+    ProfScope ps(c, s, PK_MODUP_NTT, rows * (N / 2) * LOGN, bytes);
+    const uint32_t total = (uint32_t)b.n * beta_max * (N / 256) + 2u * (uint32_t)b.n * rows_max * (N / 4096);
+    int cus = 256;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device);
+    // three workgroups per compute unit are resident at this kernel's register count
+    const uint32_t grid = std::min<uint32_t>(total, (uint32_t)cus * 3);
+    hipLaunchKernelGGL((k_modup_ntt<LOGN, F53>), dim3(grid), dim3(256), 0, s, b, c->d_mods, c->d_modup, coef, coef_es,
+                       ntt, ntt_es, digits, digits_es, rm, c->d_tw, c->d_twp, ctl, c->d_fault, c->L, c->K, c->alpha,
+                       c->dnum, beta_max, rows_max, (uint32_t)PERSIST_SPIN_LIMIT);
+    FL_TRY_HIP(hipGetLastError());
+    return FHELIN_OK;
+}
+
+int launch_modup_ntt(const Ctx *c, const Batch &b, const uint64_t *coef, int64_t coef_es, const uint64_t *ntt,
+                     int64_t ntt_es, uint64_t *digits, int64_t digits_es, const RowMap &rm, uint32_t *ctl,
+                     hipStream_t s) {
+    if (b.n == 0) return FHELIN_OK;
+    switch (c->log_n) {
+    case 13: return c->ntt53 ? launch_modup_ntt_t<13, true>(c, b, coef, coef_es, ntt, ntt_es, digits, digits_es, rm, ctl, s)
+                             : launch_modup_ntt_t<13, false>(c, b, coef, coef_es, ntt, ntt_es, digits, digits_es, rm, ctl, s);
+    case 14: return c->ntt53 ? launch_modup_ntt_t<14, true>(c, b, coef, coef_es, ntt, ntt_es, digits, digits_es, rm, ctl, s)
+                             : launch_modup_ntt_t<14, false>(c, b, coef, coef_es, ntt, ntt_es, digits, digits_es, rm, ctl, s);
+    case 15: return c->ntt53 ? launch_modup_ntt_t<15, true>(c, b, coef, coef_es, ntt, ntt_es, digits, digits_es, rm, ctl, s)
+                             : launch_modup_ntt_t<15, false>(c, b, coef, coef_es, ntt, ntt_es, digits, digits_es, rm, ctl, s);
+    case 16: return c->ntt53 ? launch_modup_ntt_t<16, true>(c, b, coef, coef_es, ntt, ntt_es, digits, digits_es, rm, ctl, s)
+                             : launch_modup_ntt_t<16, false>(c, b, coef, coef_es, ntt, ntt_es, digits, digits_es, rm, ctl, s);
+    }
+    return set_error(FHELIN_E_UNSUPPORTED_PARAM, "persistent ModUp/NTT needs N >= 2^13");
 }
 
 int ntt_threads_set(int nt) {

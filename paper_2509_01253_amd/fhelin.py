@@ -66,7 +66,7 @@ class fhelin_ct_batch(ctypes.Structure):
 
 
 class fhelin_tune(ctypes.Structure):
-    _fields_ = [("chunk", _i32), ("ks_eg", _i32), ("mac_my", _i32), ("ntt_threads", _i32)]
+    _fields_ = [("chunk", _i32), ("ks_eg", _i32), ("mac_my", _i32), ("ntt_threads", _i32), ("persistent", _i32)]
 
 
 _SIGS = {
@@ -109,6 +109,7 @@ _SIGS = {
                                     ctypes.POINTER(fhelin_ct_batch), _i32, _vp, _pvp],
     "fhelin_graph_launch": [_vp, _vp],
     "fhelin_graph_destroy": [_vp],
+    "fhelin_ctx_faults": [_vp, ctypes.POINTER(_u32)],
     "fhelin_diag_alu_rate": [_i32, _i32, _i32, ctypes.POINTER(_dbl), ctypes.POINTER(_dbl), ctypes.POINTER(_dbl)],
     "fhelin_profile_enable": [_vp, _i32],
     "fhelin_profile_read": [_vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
@@ -349,11 +350,13 @@ def fhelin_linear_apply_multi(ctx, plan, ks_per_request, pts, x: torch.Tensor, x
 def fhelin_plan_get_tune(plan) -> dict:
     t = fhelin_tune()
     _check(_lib.fhelin_plan_get_tune(plan, ctypes.byref(t)))
-    return {"chunk": t.chunk, "ks_eg": t.ks_eg, "mac_my": t.mac_my, "ntt_threads": t.ntt_threads}
+    return {"chunk": t.chunk, "ks_eg": t.ks_eg, "mac_my": t.mac_my, "ntt_threads": t.ntt_threads,
+            "persistent": t.persistent}
 
 
-def fhelin_plan_set_tune(plan, chunk: int = 0, ks_eg: int = 16, mac_my: int = 2, ntt_threads: int = 256):
-    t = fhelin_tune(chunk, ks_eg, mac_my, ntt_threads)
+def fhelin_plan_set_tune(plan, chunk: int = 0, ks_eg: int = 16, mac_my: int = 2, ntt_threads: int = 256,
+                         persistent: int = 0):
+    t = fhelin_tune(chunk, ks_eg, mac_my, ntt_threads, persistent)
     _check(_lib.fhelin_plan_set_tune(plan, ctypes.byref(t)))
 
 
@@ -366,7 +369,8 @@ def fhelin_plan_autotune(ctx, plan, ks_per_request, pts, x: torch.Tensor, x_leve
     t, ms = fhelin_tune(), _dbl()
     _check(_lib.fhelin_plan_autotune(ctx, plan, ctypes.cast(arr, _vp), pts, ctypes.byref(bi), ctypes.byref(bo),
                                      flags, _stream(stream), ctypes.byref(t), ctypes.byref(ms)))
-    return {"chunk": t.chunk, "ks_eg": t.ks_eg, "mac_my": t.mac_my, "ntt_threads": t.ntt_threads}, float(ms.value)
+    return {"chunk": t.chunk, "ks_eg": t.ks_eg, "mac_my": t.mac_my, "ntt_threads": t.ntt_threads,
+            "persistent": t.persistent}, float(ms.value)
 
 
 def fhelin_graph_capture_linear(ctx, plan, ks, pts, x: torch.Tensor, x_levels, y: torch.Tensor, y_levels, flags=0,
@@ -404,6 +408,13 @@ def fhelin_ntt(ctx, rows: torch.Tensor, mod_index, inverse: bool, stream=None):
         raise ValueError("rows must be [n_rows][N] with one modulus index per row")
     _check(_lib.fhelin_ntt(ctx, _dev_ptr(rows, _W64, "rows"), ctypes.cast(mi, _vp), rows.shape[0],
                            1 if inverse else 0, _stream(stream)))
+
+
+def fhelin_ctx_faults(ctx) -> int:
+    """Faults of bounded device-side waits since the last call (0 = none); clears them."""
+    v = _u32()
+    _check(_lib.fhelin_ctx_faults(ctx, ctypes.byref(v)))
+    return int(v.value)
 
 
 def fhelin_diag_alu_rate(op: int, waves_per_simd: int, iters: int):

@@ -97,3 +97,20 @@ def test_algorithmic_bytes_closed_form():
     # plus 12 MiB out; full key switch 84 MiB
     assert bench.algo_bytes(12, 1, 0, 0, K, alpha, N) == (60 + 12) << 20
     assert bench.algo_bytes(12, 0, 1, 0, K, alpha, N) == 84 << 20
+
+
+def test_pmc_summary_merges_kernels_of_one_class(tmp_path, monkeypatch):
+    """Kernels the library profiles under one class (the coefficient-domain and the
+    NTT-domain ModDown conversions) are pooled: bytes per dispatch over all of them."""
+    gib_kib = 1 << 20
+    cfetch = _counter_dir(tmp_path, "cf", [("__amd_rocclr_copyBuffer", gib_kib)])
+    cwrite = _counter_dir(tmp_path, "cw", [("__amd_rocclr_copyBuffer", gib_kib)])
+    fetch = _counter_dir(tmp_path, "f", [("fl::k_moddown_coef(fl::Batch)", 10.0), ("fl::k_moddown_fbc(fl::Batch)", 30.0)])
+    write = _counter_dir(tmp_path, "w", [("fl::k_moddown_coef(fl::Batch)", 1.0), ("fl::k_moddown_fbc(fl::Batch)", 3.0)])
+    out = tmp_path / "traffic.json"
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(out))
+    monkeypatch.setattr(bench, "_lib_digest", lambda: "abc")
+    bench.pmc_summary(",".join([fetch, write, cfetch, cwrite]), _args())
+    k = json.loads(out.read_text())["kernels"]["moddown_fbc"]
+    assert k["dispatches"] == 2
+    assert k["bytes_per_dispatch"] == pytest.approx((20.0 + 2.0) * 1024)

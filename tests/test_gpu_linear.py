@@ -355,7 +355,8 @@ def test_tunes_bit_identical_and_autotune(F, dh):
             for c, l in zip(cts, levels)]
     lay = Layer(F, prm, keys, pts, prm.L, fc_n=n, fc_out=n, fc_in=n, n1=n1)
     try:
-        assert F.fhelin_plan_get_tune(lay.plan) == {"chunk": 0, "ks_eg": 16, "mac_my": 2, "ntt_threads": 256}
+        assert F.fhelin_plan_get_tune(lay.plan) == {"chunk": 0, "ks_eg": 16, "mac_my": 2, "ntt_threads": 256,
+                                                     "persistent": 0}
         for tune in [dict(chunk=0, ks_eg=8, mac_my=2), dict(chunk=4, ks_eg=3, mac_my=4),
                      dict(chunk=1, ks_eg=16, mac_my=8), dict(chunk=5, ks_eg=1, mac_my=2)]:
             F.fhelin_plan_set_tune(lay.plan, **tune)
@@ -672,3 +673,53 @@ def test_ntt_tiles_bit_identical(F, dh):
             assert np.array_equal(got[t, :, : l - 1], want[t]), t
     finally:
         lay.close()
+
+
+@pytest.mark.parametrize("dh", [False, True])
+def test_persistent_modup_ntt_bit_exact(F, dh):
+    """Each key switch's ModUp and forward NTT as one persistent launch (ticket-ordered
+    tiles, bounded device-side waits): the oracle's ciphertexts bit for bit at
+    N = 2^13 and 2^14 for requests of three clients at uneven levels (1 to 4 digits),
+    the same bits as the separate launches, and no wait gave up."""
+    print(f"persistent modup+ntt dh={dh}", flush=True)
+    for log_n in (13, 14):
+        prm = O.make_params(log_n, 7, 2, 4, 50, 2.0 ** 40)
+        st = synth.Stream(5300 + 10 * log_n + dh)
+        n, n1 = 64, 8
+        W = st.he_normal((n, n), n)
+        sched = O.fc_schedule(n, n1)
+        pts = encode_pts(prm, O.fc_slots(W, n, n1, prm.S), prm.L, prm.scale)
+        clients = [Client(prm, 5310 + i) for i in range(3)]
+        keysets = [cl.keyset(sched.rotations()) for cl in clients]
+        owner = [0, 1, 2, 0, 1]
+        levels = [7, 5, 2, 6, 3]
+        xs = [st.uniform(n, 0, 1) for _ in owner]
+        cts = [clients[o].encrypt_slots(O.fc_input_slots(x, n, prm.S), l, prm.scale)
+               for o, x, l in zip(owner, xs, levels)]
+        ctx = ctx_for(F, prm)
+        try:
+            plan = F.fhelin_plan_create(ctx, F.FHELIN_LAYER_FC, fc_n=n, fc_out=n, fc_in=n, n1=n1)
+            handles = [F.fhelin_keyset_load(ctx, ks.galois, prm.L, dev(keys_at(prm, ks, prm.L))) for ks in keysets]
+            pset = F.fhelin_pt_import(ctx, dev(pts.reshape(-1, prm.L + prm.K, prm.N)), level=prm.L)
+            x = dev(pad_cts(cts, prm.L, prm.N))
+            flags = F.FHELIN_APPLY_RESCALE | (F.FHELIN_APPLY_HOIST_MODDOWN if dh else 0)
+            outs = {}
+            for pers in (1, 0):
+                F.fhelin_plan_set_tune(plan, persistent=pers)
+                y = dev(np.zeros((len(cts), 2, prm.L, prm.N), np.uint64))
+                F.fhelin_linear_apply_multi(ctx, plan, [handles[o] for o in owner], pset, x, levels, y,
+                                            [l - 1 for l in levels], flags)
+                outs[pers] = host(y)
+            assert F.fhelin_ctx_faults(ctx) == 0
+            for t, (o, l) in enumerate(zip(owner, levels)):
+                want = O.rescale(prm, O.linear(prm, cts[t][None], l, sched, pts, keysets[o], hoist_moddown=dh)[0], l)
+                assert np.array_equal(outs[1][t, :, : l - 1], want), (log_n, t, l)
+                assert np.array_equal(outs[0][t, :, : l - 1], want), (log_n, t, l)
+            z = clients[0].decrypt_slots(outs[1][0, :, :6], 6, prm.scale ** 2 / prm.q[6]).real
+            assert _rel(z[:n], W @ xs[0]) < 1e-3
+            F.fhelin_ptset_release(pset)
+            for h in handles:
+                F.fhelin_keyset_release(h)
+            F.fhelin_plan_destroy(plan)
+        finally:
+            F.fhelin_ctx_destroy(ctx)
