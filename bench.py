@@ -50,6 +50,9 @@ def parse():
                     help="1: each key switch's ModUp and forward NTT in one persistent launch, 0: separate launches "
                          "(default: the plan's default tune)")
     ap.add_argument("--ntt-threads", type=int, default=0, help="workgroup size of the two-pass NTT kernels")
+    ap.add_argument("--fuse-baby", type=int, default=-1,
+                    help="1: baby rotations computed inside the multiply-accumulate, 0: written by their own launch "
+                         "(default: the plan's default tune)")
     ap.add_argument("--no-one-at-a-time", action="store_true",
                     help="skip the extra one-request-at-a-time comparison after the timed steps")
     ap.add_argument("--serve-requests", type=int, default=200,
@@ -113,11 +116,14 @@ HBM_PEAK_GBPS = 8000.0
 ROOF = {k: ("alu", "T modmul-butterflies/s", PEAK_BFLY) for k in
         ("ntt_fwd_cols", "ntt_fwd_rows", "ntt_inv_rows", "ntt_inv_cols", "modup_ntt")}
 ROOF["mac"] = ("alu", "T modular products/s", PEAK_MAC)
+# the fused baby-rotation multiply-accumulate counts the rotations' key products with
+# the plaintext products (its key products also carry a reduction every beta terms)
+ROOF["rot_mac"] = ("alu", "T modular products/s", PEAK_MAC)
 for _k in ("ks_inner", "ks_rot", "ks_sum", "modup", "moddown_fbc", "combine", "copy", "rescale", "mont"):
     ROOF[_k] = ("hbm", "GB/s", HBM_PEAK_GBPS)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic.json")
 KERNELS = ["ntt_fwd_cols", "ntt_fwd_rows", "ntt_inv_rows", "ntt_inv_cols", "mac", "ks_inner", "ks_rot", "ks_sum", "modup",
-           "moddown_fbc", "combine", "rescale", "copy", "mont", "encode", "modup_ntt"]
+           "moddown_fbc", "combine", "rescale", "copy", "mont", "encode", "modup_ntt", "rot_mac"]
 
 
 def _lib_digest() -> str:
@@ -142,7 +148,13 @@ def measured_traffic(kernel: str, launches: int, args):
 
 
 def traffic_args(args) -> dict:
-    return {"batch": args.batch, "n1": args.n1, "schedule": args.schedule, "autotune": bool(args.autotune)}
+    out = {"batch": args.batch, "n1": args.n1, "schedule": args.schedule, "autotune": bool(args.autotune)}
+    # tune overrides, when given, change the launches the counters were taken from
+    for k, unset in (("persistent", -1), ("ntt_threads", 0), ("fuse_baby", -1)):
+        v = getattr(args, k, unset)
+        if v != unset:
+            out[k] = v
+    return out
 
 
 def stream_rates(a, b) -> dict:
@@ -189,7 +201,7 @@ def pmc_summary(dirs: str, args) -> None:
     f_scale, w_scale = gib / copy_kib(cfetch), gib / copy_kib(cwrite)
     fk, wk = per_kernel(fetch), per_kernel(write)
     # kernel -> the library's profiling class (several kernels may share one class)
-    names = {"k_mac": "mac", "k_ks_inner": "ks_inner", "k_ks_rot": "ks_rot", "k_ks_sum": "ks_sum",
+    names = {"k_mac": "mac", "k_rot_mac": "rot_mac", "k_ks_inner": "ks_inner", "k_ks_rot": "ks_rot", "k_ks_sum": "ks_sum",
              "k_ntt_fwd_rows": "ntt_fwd_rows", "k_ntt_fwd_cols": "ntt_fwd_cols", "k_ntt_inv_rows": "ntt_inv_rows",
              "k_ntt_inv_cols": "ntt_inv_cols", "k_modup": "modup", "k_modup_ntt": "modup_ntt",
              "k_moddown_fbc": "moddown_fbc", "k_moddown_coef": "moddown_fbc", "k_moddown_combine": "combine",
@@ -690,10 +702,12 @@ def main():
         F.fhelin_ptset_release(h[1])
         F.fhelin_keyset_release(h[0])
 
-    if args.persistent >= 0 or args.ntt_threads:
+    if args.persistent >= 0 or args.ntt_threads or args.fuse_baby >= 0:
         t = F.fhelin_plan_get_tune(plan)
         if args.persistent >= 0:
             t["persistent"] = args.persistent
+        if args.fuse_baby >= 0:
+            t["fuse_baby"] = args.fuse_baby
         if args.ntt_threads:
             t["ntt_threads"] = args.ntt_threads
         F.fhelin_plan_set_tune(plan, **t)

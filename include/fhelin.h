@@ -298,13 +298,20 @@ int fhelin_linear_apply_noalloc(fhelin_ctx *ctx, const fhelin_plan *plan, const 
  *           launch (N >= 2^13): workgroups claim ModUp chunks, then column tiles,
  *           then row tiles in ticket order, each tile waiting (bounded) on device
  *           counters for the tiles it reads; 0: three launches
- * A new plan starts at chunk 0, ks_eg 16, mac_my 2, ntt_threads 256, persistent 0. */
+ *   fuse_baby  1: in the double-hoisted schedule, the baby rotations of a chunk
+ *           whose requests share one key set are computed inside the plaintext
+ *           multiply-accumulate (never written to memory) when the context has
+ *           at most 4 digits and moduli below 2^55; 0: a rotation launch writes
+ *           them and the multiply-accumulate reads them back
+ * A new plan starts at chunk 0, ks_eg 16, mac_my 2, ntt_threads 256, persistent 0,
+ * fuse_baby 0. */
 typedef struct fhelin_tune {
     int32_t chunk;
     int32_t ks_eg;
     int32_t mac_my;
     int32_t ntt_threads;
     int32_t persistent;
+    int32_t fuse_baby;
 } fhelin_tune;
 
 int fhelin_plan_get_tune(const fhelin_plan *plan, fhelin_tune *out);
@@ -315,7 +322,8 @@ int fhelin_plan_set_tune(fhelin_plan *plan, const fhelin_tune *tune);
  * fhelin_linear_apply_multi) for candidate tunes, one field at a time starting
  * from the plan's current tune (chunk in {all, 32, 16, 8, 4} up to the request
  * count, ks_eg in {4, 8, 16}, mac_my in {2, 4, 8}, and when N >= 2^13 ntt_threads
- * in {256, 128, 512} and persistent in {0, 1}), with HIP events on
+ * in {256, 128, 512} and persistent in {0, 1}; fuse_baby in {0, 1} for the
+ * double-hoisted schedule when every request uses one key set), with HIP events on
  * `stream`, and keeps the fastest in the plan.  Every timed run computes the
  * layer, so `out` holds the layer's result on return.  Synchronises `stream`.
  * best (optional) receives the chosen tune, best_ms (optional) its time in ms. */

@@ -550,6 +550,7 @@ FHELIN_EXPORT int fhelin_plan_get_tune(const fhelin_plan *plan, fhelin_tune *out
     out->mac_my = t.mac_my;
     out->ntt_threads = t.ntt_threads;
     out->persistent = t.persistent;
+    out->fuse_baby = t.fuse_baby;
     return FHELIN_OK;
     API_END
 }
@@ -562,9 +563,10 @@ FHELIN_EXPORT int fhelin_plan_set_tune(fhelin_plan *plan, const fhelin_tune *tun
     t.mac_my = tune->mac_my;
     t.ntt_threads = tune->ntt_threads;
     t.persistent = tune->persistent;
+    t.fuse_baby = tune->fuse_baby;
     FL_CHECK(tune_valid(t), FHELIN_E_INVALID_ARG,
              "tune out of range (chunk 0..64, ks_eg 1..64, mac_my 2, 4 or 8, ntt_threads 128, 256 or 512, "
-             "persistent 0 or 1)");
+             "persistent 0 or 1, fuse_baby 0 or 1)");
     ((Plan *)plan)->tune = t;
     return FHELIN_OK;
     API_END
@@ -587,6 +589,7 @@ FHELIN_EXPORT int fhelin_plan_autotune(fhelin_ctx *ctx, fhelin_plan *plan, const
         best->mac_my = t.mac_my;
         best->ntt_threads = t.ntt_threads;
         best->persistent = t.persistent;
+        best->fuse_baby = t.fuse_baby;
     }
     if (best_ms) *best_ms = ms;
     return FHELIN_OK;

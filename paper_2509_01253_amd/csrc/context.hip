@@ -361,7 +361,7 @@ const char *const PROF_NAMES[PK_COUNT] = {"ntt_fwd_cols", "ntt_fwd_rows", "ntt_i
                                           "ntt_fwd_1",    "ntt_inv_1",    "mac",          "ks_inner",
                                           "modup",        "moddown_fbc",  "combine",      "rescale",
                                           "copy",         "mont",         "encode",       "ks_rot",
-                                          "ks_sum",       "modup_ntt"};
+                                          "ks_sum",       "modup_ntt",    "rot_mac"};
 
 hipEvent_t Profiler::get() {
     if (!pool.empty()) {

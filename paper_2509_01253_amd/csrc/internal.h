@@ -90,7 +90,7 @@ struct Workspace;
 enum ProfKind : int {
     PK_NTT_FWD_COLS = 0, PK_NTT_FWD_ROWS, PK_NTT_INV_ROWS, PK_NTT_INV_COLS, PK_NTT_FWD_1, PK_NTT_INV_1,
     PK_MAC, PK_KS_INNER, PK_MODUP, PK_MODDOWN_FBC, PK_COMBINE, PK_RESCALE, PK_COPY, PK_MONT, PK_ENCODE, PK_KS_ROT,
-    PK_KS_SUM, PK_MODUP_NTT, PK_COUNT
+    PK_KS_SUM, PK_MODUP_NTT, PK_ROT_MAC, PK_COUNT
 };
 extern const char *const PROF_NAMES[PK_COUNT];
 
@@ -331,6 +331,7 @@ struct Tune {
     int mac_my = 2;   // requests per thread in the multiply-accumulate
     int ntt_threads = 256;  // workgroup size of the two-pass NTT kernels (128, 256, 512)
     int persistent = 0;     // 1: each key switch's ModUp and forward NTT in one persistent launch
+    int fuse_baby = 0;      // 1: double-hoisted baby rotations computed inside the multiply-accumulate
 };
 bool tune_valid(const Tune &t);
 

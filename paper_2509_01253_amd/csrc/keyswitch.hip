@@ -15,20 +15,12 @@
 // Every kernel maps one thread to one coefficient; grid.z is the batch entry.
 #include <cmath>
 
+#include "galois.h"
 #include "internal.h"
 #include "modarith.h"
 #include "modup.h"
 
 namespace fl {
-
-// automorphism X -> X^g as a permutation of the bit-reversed NTT order:
-// slot k holds a(psi^(2 brv(k) + 1)); sigma_g(a) at slot k is a at the slot of exponent
-// (2 brv(k) + 1) g mod 2N.
-__device__ __forceinline__ int auto_index(int k, uint32_t g, int log_n) {
-    uint32_t b = __builtin_bitreverse32((uint32_t)k) >> (32 - log_n);
-    uint32_t e = ((2u * b + 1u) * g) & ((2u << log_n) - 1u);
-    return (int)(__builtin_bitreverse32((e - 1u) >> 1) >> (32 - log_n));
-}
 
 // ---------------------------------------------------------------------------
 // ModUp: grid (N/256, beta_max, n); the tile itself is modup_tile (modup.h)

@@ -16,6 +16,7 @@
 // evaluation key or plaintext tile is read once per chunk.
 #include <algorithm>
 
+#include "galois.h"
 #include "internal.h"
 #include "modarith.h"
 
@@ -336,11 +337,302 @@ static int launch_mac(const Ctx *c, const Plan *p, MacArgs &ma, const Batch &bou
     return FHELIN_OK;
 }
 
+// Baby rotations fused into the multiply-accumulate (double-hoisted schedule, one key
+// set for the whole chunk).  The rotated inputs of a tile,
+//   R~_b = (P sigma_b(c0) + <sigma_b(D), evk_b>_0, <sigma_b(D), evk_b>_1)
+// over the extended basis, are computed into LDS from the hoisted digits D and the key
+// rows and multiplied there as in k_mac; they never go to memory (the separate
+// rotation launch writes them, 2 (l + K) limbs per rotation and request, and the
+// multiply-accumulate reads them back).  Staging thread (tb, kk) computes term t0 + tb
+// at coefficient k0 + kk for every request of the group: the digits and c0 are
+// gathered at sigma_b(k) -- the 16 coefficients of a 16-aligned group map onto one
+// 16-aligned group, one 128-byte line per term and digit -- and the key rows are read
+// at k.  The next tile's loads are issued before the current tile is multiplied.  Each
+// staged value is the one the rotation launch would have written (exact arithmetic,
+// reduced to [0, q)), so the outputs are bit-identical to the unfused path.
+struct RotMacArgs {
+    const uint64_t *dig;     // hoisted digits [dnum][L+K] per input entry (NTT domain)
+    int64_t dig_es;
+    const uint64_t *xq;      // inputs [2][L] per input entry (NTT domain): c0 of the addend
+    int64_t xq_es;
+    const uint64_t *evk;     // the key set of every request of the chunk
+    const ModDownTab *mdt;   // P mod q_s (Montgomery form)
+    int key_level, alpha;
+    uint32_t g[MAX_BABY];    // Galois element of baby b (1: the identity, read from a.x)
+    int32_t kidx[MAX_BABY];  // key index of baby b in the set (0 for the identity)
+};
+
+constexpr int ROTMAC_MAXB = 4;  // digits per request the fused kernel holds (dnum <= 4)
+
+template <int MY, int NC, int ET>
+__global__ void __launch_bounds__(256) k_rot_mac(MacArgs a, RotMacArgs r, Batch b, const ModConst *__restrict__ mods,
+                                                 int log_n, int L, int K, int R, int JT) {
+    static_assert(ET % MY == 0 && ET <= 8, "bad request group");
+    constexpr int ES = ET / MY, MAXB = ROTMAC_MAXB;
+    using Acc = LazyAcc<true>;
+    __shared__ uint64_t Rs[ET][MAC_TB][2][MAC_K];
+    __shared__ int32_t rin[MAX_BATCH];   // first input entry of the request at each position of the order
+    __shared__ int32_t rbeta[MAX_BATCH]; // its digit count
+    const int s = blockIdx.y;
+    if (s < L && s >= a.pt_level) return;
+    const int64_t N = (int64_t)1 << log_n;
+    const int k0 = blockIdx.x * MAC_K, o = blockIdx.z;
+    const int kl = threadIdx.x & 15, jj = threadIdx.x >> 4;
+    const int jloc = jj % JT, es = jj / JT;
+    const bool computes = es < ES;
+    const int esc = computes ? es : 0;
+    const int ls = L + K;
+    const int64_t ct = (int64_t)2 * ls * N, row = (int64_t)ls * N;
+    const int terms = a.n_in * a.B;
+    const int prows = a.pt_level + K;
+    const int prow = s < L ? s : a.pt_level + (s - L);
+    const ModConst mc = mods[s];
+    int n_act = R;
+    if (s < L) {
+        n_act = 0;
+        while (n_act < R && s < b.level[a.order[n_act] * a.n_out + o]) ++n_act;
+    }
+    const bool resident = NC > 1 || terms <= MAC_TB;
+    if (threadIdx.x < MAX_BATCH) {
+        const int q = threadIdx.x < R ? a.order[threadIdx.x] : 0;
+        rin[threadIdx.x] = q * a.n_in;
+        rbeta[threadIdx.x] = (b.level[q * a.n_out + o] + r.alpha - 1) / r.alpha;
+    }
+    __syncthreads();
+    // staging role
+    const int tb = threadIdx.x >> 4, kk = threadIdx.x & 15, k = k0 + kk;
+    const int kbeta = (r.key_level + r.alpha - 1) / r.alpha;
+    const int64_t kpart = (int64_t)(r.key_level + K) * N;
+    const int64_t krow = (int64_t)(s < L ? s : r.key_level + (s - L)) * N + k;
+    const bool has_add = s < L;  // P = 0 mod p_i
+    const uint64_t p_mont = r.mdt->p_mont[has_add ? s : 0];
+    uint64_t pd[ET][MAXB], pc[ET], pkb[MAXB], pka[MAXB];
+    int cnt[ET];
+    bool ident = false;
+    auto fetch = [&](int g0, int t0) {
+        const int t = t0 + tb;
+        const bool tv = t < terms;
+        const int ii = (int)(((uint32_t)t * a.b_magic) >> 20), bb = t - ii * a.B;
+        const int bbc = tv ? bb : 0, iic = tv ? ii : 0;
+        const uint32_t g = r.g[bbc];
+        ident = g == 1u;
+        const int src = ident ? k : auto_index(k, g, log_n);
+        // key rows at k (rows past the key's digits repeat its last one, never used)
+        const uint64_t *key = r.evk + (int64_t)r.kidx[bbc] * 2 * kbeta * kpart + krow;
+#pragma unroll
+        for (int j = 0; j < MAXB; ++j) {
+            const int jr = j < kbeta ? j : kbeta - 1;
+            pkb[j] = key[(2 * jr) * kpart];
+            pka[j] = key[(2 * jr + 1) * kpart];
+        }
+        // every address first, then the loads
+        const uint64_t *srcs[ET][MAXB + 1];
+#pragma unroll
+        for (int rr = 0; rr < ET; ++rr) {
+            const int rq = g0 + rr;
+            const bool live = tv && rq < n_act;
+            const int e_in = rin[live ? rq : 0] + iic;
+            // the identity reads both polynomials of a.x (P x on the extended basis), a
+            // rotation its digits at sigma_b(k); both are rows ls N apart
+            cnt[rr] = !live ? 0 : ident ? 2 : rbeta[rq];
+            const uint64_t *base = ident ? a.x + e_in * ct + (int64_t)s * N + k
+                                         : r.dig + e_in * r.dig_es + (int64_t)s * N + src;
+#pragma unroll
+            for (int j = 0; j < MAXB; ++j) srcs[rr][j] = j < cnt[rr] ? base + j * row : a.zero;
+            srcs[rr][MAXB] = live && !ident && has_add ? r.xq + e_in * r.xq_es + (int64_t)s * N + src : a.zero;
+        }
+#pragma unroll
+        for (int rr = 0; rr < ET; ++rr) {
+#pragma unroll
+            for (int j = 0; j < MAXB; ++j) pd[rr][j] = *srcs[rr][j];
+            pc[rr] = *srcs[rr][MAXB];
+        }
+    };
+    auto stash = [&]() {
+        uint64_t kb[MAXB], ka[MAXB];
+#pragma unroll
+        for (int j = 0; j < MAXB; ++j) {
+            kb[j] = Acc::prep(pkb[j]);
+            ka[j] = Acc::prep(pka[j]);
+        }
+#pragma unroll
+        for (int rr = 0; rr < ET; ++rr) {
+            uint64_t v0 = pd[rr][0], v1 = pd[rr][1];
+            if (!ident) {
+                Acc a0, a1;
+                a0.zero();
+                a1.zero();
+                // rows past the request's digits were loaded from the zero word
+#pragma unroll
+                for (int j = 0; j < MAXB; ++j) {
+                    const uint64_t dv = Acc::prep(pd[rr][j]);
+                    a0.mac(dv, kb[j]);
+                    a1.mac(dv, ka[j]);
+                }
+                v0 = a0.reduce(mc.q, mc.mont_neg_inv);
+                v1 = a1.reduce(mc.q, mc.mont_neg_inv);
+                if (has_add) v0 = add_mod(v0, mont_mul(pc[rr], p_mont, mc.q, mc.mont_neg_inv), mc.q);
+            }
+            if (cnt[rr] == 0) v0 = v1 = 0;
+            Rs[rr][tb][0][kk] = Acc::prep(v0);
+            Rs[rr][tb][1][kk] = Acc::prep(v1);
+        }
+    };
+    if (n_act > 0) fetch(0, 0);
+    for (int jc = 0; jc < a.G; jc += JT) {
+        const int j = jc + jloc;
+        uint64_t pv[NC][MAC_TB];
+        auto load_pv = [&](uint64_t(&col)[MAC_TB], int t0) {
+#pragma unroll
+            for (int tt = 0; tt < MAC_TB; ++tt) {
+                const int t = t0 + tt;
+                const uint64_t *src = a.zero;
+                if (t < terms && j < a.G) {
+                    const int ii = t / a.B, bb = t % a.B;
+                    const int64_t pidx = ((int64_t)(o * a.n_in + ii) * a.G + j) * a.B + bb;
+                    src = a.pts + (pidx * prows + prow) * N + k0 + kl;
+                }
+                col[tt] = *src;
+            }
+#pragma unroll
+            for (int tt = 0; tt < MAC_TB; ++tt) col[tt] = Acc::prep(col[tt]);
+        };
+        if (resident) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) load_pv(pv[c], c * MAC_TB);
+        }
+        for (int g0 = 0; g0 < n_act; g0 += ET) {
+            Acc acc[MY][2];
+#pragma unroll
+            for (int m = 0; m < MY; ++m) {
+                acc[m][0].zero();
+                acc[m][1].zero();
+            }
+            for (int t0 = 0; t0 < terms; t0 += MAC_TB) {
+                if (!resident) load_pv(pv[0], t0);
+                __syncthreads();  // readers of the previous tile are done
+                stash();
+                __syncthreads();
+                int gn = g0, tn = t0 + MAC_TB;
+                bool more = true;
+                if (tn >= terms) {
+                    tn = 0;
+                    gn = g0 + ET;
+                    if (gn >= n_act) {
+                        gn = 0;
+                        more = jc + JT < a.G;
+                    }
+                }
+                if (more) fetch(gn, tn);
+                auto compute = [&](const uint64_t(&col)[MAC_TB]) {
+#pragma unroll
+                    for (int tt = 0; tt < MAC_TB; ++tt) {
+#pragma unroll
+                        for (int m = 0; m < MY; ++m) {
+                            const int rr = esc + m * ES;
+                            acc[m][0].mac(Rs[rr][tt][0][kl], col[tt]);
+                            acc[m][1].mac(Rs[rr][tt][1][kl], col[tt]);
+                        }
+                    }
+                };
+                if constexpr (NC > 1) {
+                    if (resident && t0 >= MAC_TB) compute(pv[1]);
+                    else compute(pv[0]);
+                } else {
+                    compute(pv[0]);
+                }
+                if ((t0 / MAC_TB) % (Acc::TERMS / MAC_TB) == Acc::TERMS / MAC_TB - 1 || t0 + MAC_TB >= terms) {
+#pragma unroll
+                    for (int m = 0; m < MY; ++m)
+#pragma unroll
+                        for (int p = 0; p < 2; ++p) acc[m][p].set(acc[m][p].reduce(mc.q, mc.mont_neg_inv));
+                }
+            }
+            if (computes && j < a.G) {
+#pragma unroll
+                for (int m = 0; m < MY; ++m) {
+                    const int rq = g0 + esc + m * ES;
+                    if (rq < n_act) {
+                        const int64_t e = (int64_t)a.order[rq] * a.n_out + o;
+                        uint64_t *dst = a.acc + (e * a.G + j) * ct + (int64_t)s * N + k0 + kl;
+                        dst[0] = acc[m][0].value();
+                        dst[row] = acc[m][1].value();
+                    }
+                }
+            }
+        }
+    }
+}
+
+// The fused launch applies to a chunk whose requests share one key set, holding every
+// baby key, with at most ROTMAC_MAXB digits and packed (small-modulus) arithmetic.
+static bool rot_mac_applies(const Ctx *c, const Plan *p, const KeySet *const *kss, int Rc) {
+    if (!p->tune.fuse_baby || !c->small || (c->L + c->alpha - 1) / c->alpha > ROTMAC_MAXB) return false;
+    for (int r = 1; r < Rc; ++r)
+        if (kss[r] != kss[0]) return false;
+    return kss[0] != nullptr;
+}
+
+static int launch_rot_mac(const Ctx *c, const Plan *p, MacArgs &ma, RotMacArgs &ra, const Batch &bout,
+                          const Batch &bin, hipStream_t s) {
+    const int R = bout.n / p->n_out;
+    // work: the multiply-accumulate's products plus the rotations' key products (2 beta
+    // per rotation, polynomial pair and active limb); bytes: the digits and c0 once per
+    // input entry, the lifted input for the identity, each baby key once, the
+    // plaintexts once and the accumulators written
+    double units = 0, bytes = 0;
+    int lmax = 0;
+    const double limb = 8.0 * c->N;
+    for (int e = 0; e < bout.n; ++e) {
+        lmax = std::max<int>(lmax, bout.level[e]);
+        const double l = bout.level[e], act = l + c->K, beta = std::ceil(l / c->alpha);
+        units += 2.0 * act * (double)c->N * ma.G * ma.B * p->n_in;
+        units += 2.0 * beta * act * (double)c->N * ma.Bp * p->n_in / p->n_out;
+        bytes += limb * 2 * act * ma.G;
+    }
+    for (int e = 0; e < bin.n; ++e) {
+        const double l = bin.level[e], act = l + c->K, beta = std::ceil(l / c->alpha);
+        bytes += limb * (beta * act + l + (ma.Bp < ma.B ? 2 * l : 0));
+    }
+    const double kl = ra.key_level;
+    bytes += limb * ma.Bp * 2 * std::ceil(kl / c->alpha) * (std::min<double>(kl, lmax) + c->K);
+    bytes += limb * (double)p->n_pt() * (c->K + std::min(lmax, ma.pt_level));
+    int idx[MAX_BATCH];
+    for (int r = 0; r < R; ++r) idx[r] = r;
+    std::stable_sort(idx, idx + R, [&](int x, int y) { return bout.level[x * p->n_out] > bout.level[y * p->n_out]; });
+    for (int r = 0; r < R; ++r) ma.order[r] = idx[r];
+    ma.zero = c->d_zero;
+    ma.b_magic = (uint32_t)(((1u << 20) + ma.B - 1) / ma.B);
+    const int JT = std::min(ma.G, 16);
+    const int MY = p->tune.mac_my;
+    int ET = MY;
+    while (ET * 2 <= MAC_ET && (ET * 2) / MY <= 16 / JT) ET *= 2;
+    ProfScope ps(c, s, PK_ROT_MAC, units, bytes);
+    dim3 grid(c->N / MAC_K, c->L + c->K, p->n_out);
+    const int terms = p->n_in * ma.B, NC = terms > MAC_TB && terms <= 2 * MAC_TB ? 2 : 1;
+#define FL_RM(Y, C, E) hipLaunchKernelGGL((k_rot_mac<Y, C, E>), grid, dim3(256), 0, s, ma, ra, bout, c->d_mods, \
+                                          c->log_n, c->L, c->K, R, JT)
+#define FL_RM_E(Y, C) \
+    if (ET == 2) FL_RM(2, C, 2); \
+    else if (ET == 4 && Y <= 4) FL_RM((Y <= 4 ? Y : 4), C, 4); \
+    else FL_RM(Y, C, 8)
+#define FL_RM_Y(C) \
+    if (MY == 2) { FL_RM_E(2, C); } \
+    else if (MY == 4) { FL_RM_E(4, C); } \
+    else { FL_RM(8, C, 8); }
+    if (NC == 2) { FL_RM_Y(2) } else { FL_RM_Y(1) }
+#undef FL_RM_Y
+#undef FL_RM_E
+#undef FL_RM
+    FL_TRY_HIP(hipGetLastError());
+    return FHELIN_OK;
+}
+
 bool tune_valid(const Tune &t) {
     return t.chunk >= 0 && t.chunk <= MAX_BATCH && t.ks_eg >= 1 && t.ks_eg <= MAX_BATCH &&
            (t.mac_my == 2 || t.mac_my == 4 || t.mac_my == 8) &&
            (t.ntt_threads == 128 || t.ntt_threads == 256 || t.ntt_threads == 512) &&
-           (t.persistent == 0 || t.persistent == 1);
+           (t.persistent == 0 || t.persistent == 1) && (t.fuse_baby == 0 || t.fuse_baby == 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -590,8 +882,40 @@ static int apply_chunk_dh(Ctx *c, const Plan *p, const KeySet *const *kss, const
     bool has_identity = false;
     for (int b = 0; b < B; ++b) has_identity |= ma.bmap[b] < 0;
     if (has_identity) FL_RET(launch_ext_lift_add(c, bin, X, ct, (int)L, 1, 0, XL, ext, s));
-    // 3. baby rotations in the extended basis: (P sigma(c0) + u0, u1)
-    if (Bp > 0) {
+    // 3. baby rotations in the extended basis: (P sigma(c0) + u0, u1), either inside the
+    // multiply-accumulate (one key set for the chunk) or by their own launch
+    const bool fused = Bp > 0 && rot_mac_applies(c, p, kss + r0, Rc);
+    ma.x = XL;
+    ma.rb = RB;
+    ma.pts = pts->data;
+    ma.acc = A;
+    ma.n_in = p->n_in;
+    ma.n_out = p->n_out;
+    ma.B = B;
+    ma.Bp = Bp;
+    ma.G = G;
+    ma.pt_level = pts->level;
+    ma.ext = 1;
+    if (fused) {
+        KsScratch wb{TC, L * N, D, dg, nullptr, 0, MD, ct, ctl};
+        FL_RET(modup_ct(c, bin, X, ct, (int)L, wb, s));
+        const KeySet *ks = kss[r0];
+        RotMacArgs ra{};
+        ra.dig = D;
+        ra.dig_es = dg;
+        ra.xq = X;
+        ra.xq_es = ct;
+        ra.evk = ks->evk;
+        ra.mdt = c->d_moddown;
+        ra.key_level = ks->level;
+        ra.alpha = c->alpha;
+        for (int b = 0; b < B; ++b) {
+            const uint32_t g = galois_of_rotation(p->rb[b], c->log_n);
+            ra.g[b] = g;
+            ra.kidx[b] = g == 1 ? 0 : ks->find(g);
+        }
+        FL_RET(launch_rot_mac(c, p, ma, ra, bout, bin, s));
+    } else if (Bp > 0) {
         KsScratch wb{TC, L * N, D, dg, nullptr, 0, MD, ct, ctl};
         FL_RET(modup_ct(c, bin, X, ct, (int)L, wb, s));
         // one launch for every baby rotation when all key sets of the chunk hold the
@@ -626,18 +950,7 @@ static int apply_chunk_dh(Ctx *c, const Plan *p, const KeySet *const *kss, const
         for (int e = 0; e < Ein; ++e) bin.g[e] = 1;
     }
     // 4. multiply-accumulate over the extended basis
-    ma.x = XL;
-    ma.rb = RB;
-    ma.pts = pts->data;
-    ma.acc = A;
-    ma.n_in = p->n_in;
-    ma.n_out = p->n_out;
-    ma.B = B;
-    ma.Bp = Bp;
-    ma.G = G;
-    ma.pt_level = pts->level;
-    ma.ext = 1;
-    FL_RET(launch_mac(c, p, ma, bout, s));
+    if (!fused) FL_RET(launch_mac(c, p, ma, bout, s));
     // 5. giant steps summed in the extended basis.  When the chunk's key sets hold the
     // giant keys at the same indices, the key switches of a group of up to MAX_SUM
     // steps (each with its own digit buffer) go to one launch that adds them to the
@@ -939,21 +1252,32 @@ int plan_autotune(Ctx *c, Plan *p, const KeySet *const *kss, const PtSet *pts, c
     Tune best = start;
     double best_t = 0;
     int rc = time_apply(c, p, kss, pts, in, out, flags, s, e0, e1, &best_t);
-    const int chunks[] = {0, 32, 16, 8, 4}, egs[] = {4, 8, 16}, mys[] = {2, 4, 8}, nts[] = {256, 128, 512},
-              pers[] = {0, 1};
-    // the NTT tile and the persistent ModUp/NTT launch matter only for the two-pass
-    // transforms (N >= 2^13)
-    const int n_fields = c->log_n > 12 ? 5 : 3;
-    for (int field = 0; field < n_fields && rc == FHELIN_OK; ++field) {
-        const int *vals = field == 0 ? chunks : field == 1 ? egs : field == 2 ? mys : field == 3 ? nts : pers;
-        const int nv = field == 0 ? 5 : field == 4 ? 2 : 3;
-        for (int i = 0; i < nv && rc == FHELIN_OK; ++i) {
+    // one field at a time, in this order; the NTT tile and the persistent ModUp/NTT
+    // launch matter only for the two-pass transforms (N >= 2^13), the fused baby
+    // rotations only for the double-hoisted schedule with one key set and at most
+    // four digits
+    struct Field {
+        int Tune::*f;
+        std::vector<int> vals;
+        bool on;
+    };
+    bool one_set = kss != nullptr && R > 0;
+    for (int r = 1; one_set && r < R; ++r) one_set = kss[r] == kss[0];
+    const bool fusable = (flags & FHELIN_APPLY_HOIST_MODDOWN) && one_set && c->small &&
+                         (c->L + c->alpha - 1) / c->alpha <= ROTMAC_MAXB;
+    const Field fields[] = {{&Tune::chunk, {0, 32, 16, 8, 4}, true},
+                            {&Tune::ks_eg, {4, 8, 16}, true},
+                            {&Tune::mac_my, {2, 4, 8}, true},
+                            {&Tune::ntt_threads, {256, 128, 512}, c->log_n > 12},
+                            {&Tune::persistent, {0, 1}, c->log_n > 12},
+                            {&Tune::fuse_baby, {0, 1}, fusable}};
+    for (const Field &fd : fields) {
+        if (!fd.on) continue;
+        for (size_t i = 0; i < fd.vals.size() && rc == FHELIN_OK; ++i) {
             Tune t = best;
-            int &f = field == 0 ? t.chunk : field == 1 ? t.ks_eg : field == 2 ? t.mac_my : field == 3 ? t.ntt_threads
-                                                                                                    : t.persistent;
-            if (f == vals[i]) continue;
-            if (field == 0 && vals[i] >= R) continue;  // same as "all" for this batch
-            f = vals[i];
+            if (t.*fd.f == fd.vals[i]) continue;
+            if (fd.f == &Tune::chunk && fd.vals[i] >= R) continue;  // same as "all" for this batch
+            t.*fd.f = fd.vals[i];
             p->tune = t;
             double ms = 0;
             rc = time_apply(c, p, kss, pts, in, out, flags, s, e0, e1, &ms);

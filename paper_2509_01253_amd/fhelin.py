@@ -66,7 +66,8 @@ class fhelin_ct_batch(ctypes.Structure):
 
 
 class fhelin_tune(ctypes.Structure):
-    _fields_ = [("chunk", _i32), ("ks_eg", _i32), ("mac_my", _i32), ("ntt_threads", _i32), ("persistent", _i32)]
+    _fields_ = [("chunk", _i32), ("ks_eg", _i32), ("mac_my", _i32), ("ntt_threads", _i32), ("persistent", _i32),
+                ("fuse_baby", _i32)]
 
 
 _SIGS = {
@@ -351,12 +352,12 @@ def fhelin_plan_get_tune(plan) -> dict:
     t = fhelin_tune()
     _check(_lib.fhelin_plan_get_tune(plan, ctypes.byref(t)))
     return {"chunk": t.chunk, "ks_eg": t.ks_eg, "mac_my": t.mac_my, "ntt_threads": t.ntt_threads,
-            "persistent": t.persistent}
+            "persistent": t.persistent, "fuse_baby": t.fuse_baby}
 
 
 def fhelin_plan_set_tune(plan, chunk: int = 0, ks_eg: int = 16, mac_my: int = 2, ntt_threads: int = 256,
-                         persistent: int = 0):
-    t = fhelin_tune(chunk, ks_eg, mac_my, ntt_threads, persistent)
+                         persistent: int = 0, fuse_baby: int = 0):
+    t = fhelin_tune(chunk, ks_eg, mac_my, ntt_threads, persistent, fuse_baby)
     _check(_lib.fhelin_plan_set_tune(plan, ctypes.byref(t)))
 
 
@@ -370,7 +371,7 @@ def fhelin_plan_autotune(ctx, plan, ks_per_request, pts, x: torch.Tensor, x_leve
     _check(_lib.fhelin_plan_autotune(ctx, plan, ctypes.cast(arr, _vp), pts, ctypes.byref(bi), ctypes.byref(bo),
                                      flags, _stream(stream), ctypes.byref(t), ctypes.byref(ms)))
     return {"chunk": t.chunk, "ks_eg": t.ks_eg, "mac_my": t.mac_my, "ntt_threads": t.ntt_threads,
-            "persistent": t.persistent}, float(ms.value)
+            "persistent": t.persistent, "fuse_baby": t.fuse_baby}, float(ms.value)
 
 
 def fhelin_graph_capture_linear(ctx, plan, ks, pts, x: torch.Tensor, x_levels, y: torch.Tensor, y_levels, flags=0,

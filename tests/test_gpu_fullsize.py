@@ -62,10 +62,11 @@ def fc_batch():
         x = dev(pad_cts(cts, prm.L, prm.N))
         out = {}
         dhf = F.FHELIN_APPLY_RESCALE | F.FHELIN_APPLY_HOIST_MODDOWN
-        for name, flags, nt, pers in (("dh", dhf, 256, 0), ("rot", F.FHELIN_APPLY_RESCALE, 256, 0),
-                                      ("dh_nt128", dhf, 128, 0), ("dh_nt512", dhf, 512, 0), ("dh_persist", dhf, 256, 1),
-                                      ("rot_persist", F.FHELIN_APPLY_RESCALE, 256, 1)):
-            F.fhelin_plan_set_tune(plan, chunk=0, ks_eg=16, mac_my=2, ntt_threads=nt, persistent=pers)
+        for name, flags, nt, pers, fuse in (("dh", dhf, 256, 0, 0), ("rot", F.FHELIN_APPLY_RESCALE, 256, 0, 0),
+                                            ("dh_fused", dhf, 256, 0, 1), ("dh_nt128", dhf, 128, 0, 0),
+                                            ("dh_nt512", dhf, 512, 0, 0), ("dh_persist", dhf, 256, 1, 0),
+                                            ("rot_persist", F.FHELIN_APPLY_RESCALE, 256, 1, 0)):
+            F.fhelin_plan_set_tune(plan, chunk=0, ks_eg=16, mac_my=2, ntt_threads=nt, persistent=pers, fuse_baby=fuse)
             y = dev(np.zeros((64, 2, prm.L, prm.N), np.uint64))
             F.fhelin_linear_apply(ctx, plan, ks, pset, x, levels, y, [l - 1 for l in levels], flags)
             out[name] = host(y)
@@ -100,11 +101,13 @@ def test_fc256_batch64_request_alone(fc_batch):
 
 
 def test_fc256_batch64_ntt_tiles_identical(fc_batch):
-    """The batch under 128- and 512-thread NTT tiles, and with every key switch's ModUp
-    and forward NTT in one persistent launch, gives the default launches' bits (both
-    schedules)."""
+    """The batch under 128- and 512-thread NTT tiles, with every key switch's ModUp and
+    forward NTT in one persistent launch, and with the baby rotations computed inside
+    the multiply-accumulate instead of written by their own launch, gives the default
+    launches' bits (both schedules)."""
     levels, out = fc_batch["levels"], fc_batch["out"]
-    for name, ref in (("dh_nt128", "dh"), ("dh_nt512", "dh"), ("dh_persist", "dh"), ("rot_persist", "rot")):
+    for name, ref in (("dh_nt128", "dh"), ("dh_nt512", "dh"), ("dh_persist", "dh"), ("rot_persist", "rot"),
+                      ("dh_fused", "dh")):
         for t, l in enumerate(levels):
             assert np.array_equal(out[name][t, :, : l - 1], out[ref][t, :, : l - 1]), (name, t)
 

@@ -356,9 +356,10 @@ def test_tunes_bit_identical_and_autotune(F, dh):
     lay = Layer(F, prm, keys, pts, prm.L, fc_n=n, fc_out=n, fc_in=n, n1=n1)
     try:
         assert F.fhelin_plan_get_tune(lay.plan) == {"chunk": 0, "ks_eg": 16, "mac_my": 2, "ntt_threads": 256,
-                                                     "persistent": 0}
+                                                     "persistent": 0, "fuse_baby": 0}
         for tune in [dict(chunk=0, ks_eg=8, mac_my=2), dict(chunk=4, ks_eg=3, mac_my=4),
-                     dict(chunk=1, ks_eg=16, mac_my=8), dict(chunk=5, ks_eg=1, mac_my=2)]:
+                     dict(chunk=1, ks_eg=16, mac_my=8), dict(chunk=5, ks_eg=1, mac_my=2),
+                     dict(chunk=0, ks_eg=8, mac_my=4, fuse_baby=1), dict(chunk=3, ks_eg=4, mac_my=8, fuse_baby=1)]:
             F.fhelin_plan_set_tune(lay.plan, **tune)
             got = lay.apply(cts, levels, stride=prm.L, dh=dh)
             for t in range(len(levels)):
@@ -380,6 +381,67 @@ def test_tunes_bit_identical_and_autotune(F, dh):
         got = host(y)
         for t, l in enumerate(levels):
             assert np.array_equal(got[t, :, : l - 1], want[t]), t
+    finally:
+        lay.close()
+
+
+# ---------------------------------------------------------------------------
+# baby rotations inside the multiply-accumulate
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("kind", ["fc", "conv"])
+def test_fused_baby_rotations_bit_exact(F, kind):
+    """The double-hoisted schedule with its baby rotations computed inside the
+    multiply-accumulate (one key set for the chunk) against the separate rotation
+    launch and the oracle, bit for bit: N = 2^12 with 12 q + 3 p primes and dnum 4
+    (requests of 1 to 4 digits at uneven levels), every MAC tile (2, 4, 8 requests per
+    thread); FC with 32 baby x 4 giant steps (two 16-term chunks) and a 3x3 conv over
+    two input and two output ciphertexts (an identity baby step per input)."""
+    print(f"fused baby rotations {kind}", flush=True)
+    prm = O.make_params(12, 12, 3, 4, 50, 2.0 ** 40)
+    st = synth.Stream(5400 + (kind == "conv"))
+    cl = Client(prm, 5401)
+    if kind == "fc":
+        n, n1 = 128, 32
+        W = st.he_normal((n, n), n)
+        sched = O.fc_schedule(n, n1)
+        pts = encode_pts(prm, O.fc_slots(W, n, n1, prm.S), prm.L, prm.scale)
+        levels = [12, 10, 9, 7, 4, 2, 11, 1, 6]
+        cts = [cl.encrypt_slots(O.fc_input_slots(st.uniform(n, 0, 1), n, prm.S), l, prm.scale) for l in levels]
+        desc = dict(fc_n=n, fc_out=n, fc_in=n, n1=n1)
+        reqs = [[c] for c in cts]
+    else:
+        cs = O.ConvShape(16, 16, 16, 16, 3)
+        W = st.he_normal((16, 16, 3, 3), 144)
+        sched = O.conv_schedule(cs, prm.S)
+        assert sched.n_in == 2 and sched.n_out == 2
+        pts = encode_pts(prm, O.conv_slots(W, cs, prm.S), prm.L, prm.scale)
+        req_levels = [12, 9, 5, 3]
+        reqs = [[cl.encrypt_slots(sl, l, prm.scale)
+                 for sl in O.conv_input_slots(st.uniform(16 * 256, 0, 1).reshape(16, 16, 16), cs, prm.S)]
+                for l in req_levels]
+        levels = [l for l in req_levels for _ in range(2)]
+        cts = [c for r in reqs for c in r]
+        desc = dict(c_in=16, c_out=16, h=16, w=16, k=3)
+    keys = cl.keyset(sched.rotations())
+    lay = Layer(F, prm, keys, pts, prm.L, **desc)
+    try:
+        outs = {}
+        for fuse in (1, 0):
+            for my in (2, 4, 8):
+                F.fhelin_plan_set_tune(lay.plan, mac_my=my, fuse_baby=fuse)
+                F.fhelin_profile_enable(lay.ctx, True)
+                outs[(fuse, my)] = lay.apply(cts, levels, rescale=False, stride=prm.L, dh=True)
+                n_fused = F.fhelin_profile_read(lay.ctx, "rot_mac")[0]
+                n_rot = F.fhelin_profile_read(lay.ctx, "ks_rot")[0]
+                F.fhelin_profile_enable(lay.ctx, False)
+                assert (n_fused > 0, n_rot > 0) == ((True, False) if fuse else (False, True)), (fuse, my)
+        n_out = sched.n_out
+        for r, req in enumerate(reqs):
+            l = levels[r * len(req)]
+            want = O.linear(prm, np.stack(req), l, sched, pts, keys, hoist_moddown=True)
+            for o in range(n_out):
+                for key, got in outs.items():
+                    assert np.array_equal(got[r * n_out + o], want[o]), (key, r, o, l)
     finally:
         lay.close()
 
