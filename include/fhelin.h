@@ -408,6 +408,72 @@ int fhelin_diag_alu_rate(int32_t op, int32_t waves_per_simd, int32_t iters, doub
  * the device to be idle, returns the word in *faults (0 = none) and clears it. */
 int fhelin_ctx_faults(fhelin_ctx *ctx, uint32_t *faults);
 
+/* ---- the paper's own pipeline: RLWE over Z_{2^64}[X]/Phi_M ----------------------
+ *
+ * The scheme of Sec. 2.1: M = t^alpha (t an odd prime), N = phi(M), ciphertexts
+ * (a, b) of two polynomials of N coefficients (power basis, uint64: the discrete
+ * torus with q = 2^64), b - s a = mu + e, a message m mod p = 2^log_p carried as
+ * m 2^64 / p.  The server round of Sec. 4.4 runs in three calls: partial trace
+ * extraction of the client's chunks (the lemma on partial trace extraction),
+ * an integer-weight layer on the extracted rows (convolution / FC with the
+ * round's shuffle folded into the weights' rows), and fast packing of the
+ * outputs back into RLWE ciphertexts (Sec. 2.3-2.4), whose automorphisms are
+ * key-switched with the gadget keys of Sec. 4.2.  A ciphertext is [2][N]
+ * (a then b); batches are contiguous.  All buffers are device memory owned by
+ * the caller; the handle owns its key matrices and workspace.  Work goes to
+ * `stream` (NULL = null stream). */
+typedef struct fhelin_native fhelin_native;
+
+typedef struct fhelin_native_params {
+    int32_t t, alpha;   /* M = t^alpha <= 8192, t an odd prime, alpha >= 2 */
+    int32_t gamma;      /* partial trace extraction level, 1 or 2 (Sec. 4.4) */
+    int32_t beta;       /* packing level gamma..alpha-1: phi(t^beta) outputs per packed
+                           ciphertext, output o at coefficient o M / t^beta */
+    int32_t log_d, l;   /* gadget base D = 2^log_d (1..16) and depth l (1..8), log_d l < 64 */
+    int32_t log_p;      /* message modulus p = 2^log_p (1..31) */
+} fhelin_native_params;
+
+/* FHELIN_E_UNSUPPORTED_PARAM for parameters outside the ranges above (checked on
+ * the host).  The handle lives on the current device. */
+int fhelin_native_create(const fhelin_native_params *prm, fhelin_native **out);
+int fhelin_native_destroy(fhelin_native *nt);
+
+/* Key-switching keys of the packing (Sec. 4.2): for each tower level
+ * i = gamma..alpha-1 the Galois element 1 + t^i mod M and its l gadget
+ * encryptions RLWE_s(s(X^(1+t^i)) 2^64 / D^k), k = 1..l: device
+ * [alpha-gamma][l][2][N] uint64, read during the call's stream work only.  The
+ * handle keeps, per key polynomial, its N x N product matrix modulo Phi_M
+ * ((alpha-gamma) 2 N l N 8 bytes of device memory); FHELIN_E_OOM if that fails. */
+int fhelin_native_keys_load(fhelin_native *nt, const uint64_t *ksk, void *stream);
+
+/* Partial trace extraction (Sec. 4.4 and its lemma): chunks
+ * [n_chunks][phi(t^gamma)][2][N], the client's encryptions of m(X^d) for
+ * d = 1..t-1 (gamma = 1) or d = k (j t + 1) mod M, k = 1..t-1, j = 0..t-1
+ * (gamma = 2), in that order.  Writes rows [n_chunks N][2][N]: row c N + i is
+ * u sum_d ct_d (X^(d (M - i)) - X^(d (M/t - r))), r = i mod M/t,
+ * u = M^-1 mod p taken in (-p/2, p/2], whose trace down to K_gamma decrypts to
+ * coefficient i of chunk c.  n_chunks <= 65535. */
+int fhelin_native_extract(fhelin_native *nt, const uint64_t *chunks, int32_t n_chunks, uint64_t *rows,
+                          void *stream);
+
+/* Integer layer on rows (Sec. 4.4 "Convolution", "Shuffle"): out[o] =
+ * sum_k val[k] rows[col[k]] modulo 2^64 for k in [row_ptr[o], row_ptr[o+1]) (CSR,
+ * int32 device arrays; the shuffle is the order of the CSR rows).  rows
+ * [n_rows][2][N], out [n_out][2][N]; column indices must be < the rows given
+ * (not checked on the device).  n_out <= 65535. */
+int fhelin_native_linear(fhelin_native *nt, const int32_t *row_ptr, const int32_t *col, const int32_t *val,
+                         int32_t n_out, const uint64_t *rows, uint64_t *out, void *stream);
+
+/* Fast packing (Sec. 2.4, 4.4): rows [n_rows][2][N], each with trace down to
+ * K_gamma decrypting to a scalar y_o, into packed [ceil(n_rows / phi(t^beta))][2][N]
+ * encrypting sum_o y_o X^(o M / t^beta) (rows past n_rows count as zero).  Uses
+ * t^(beta-gamma) - 1 + (alpha-beta)(t-1) key switches per packed ciphertext.
+ * FHELIN_E_MISSING_GALOIS_KEY before fhelin_native_keys_load.  The handle's
+ * workspace grows to fhelin_native_pack_workspace bytes (a regrow synchronises
+ * the stream); calls that share the handle must not overlap in time. */
+int fhelin_native_pack(fhelin_native *nt, const uint64_t *rows, int32_t n_rows, uint64_t *packed, void *stream);
+int fhelin_native_pack_workspace(const fhelin_native *nt, int32_t n_rows, uint64_t *bytes);
+
 const char *fhelin_last_error(void);
 const char *fhelin_status_string(int status);
 

@@ -4,6 +4,7 @@
 #include <set>
 
 #include "internal.h"
+#include "native.h"
 
 namespace fl {
 int primes_generate(int log_n, int bits, int count, uint64_t *out);
@@ -72,8 +73,9 @@ int plan_encode_weights(Ctx *c, const Plan *pl, const double *W, const int32_t *
 // device set of the context for the duration of a call
 struct DeviceGuard {
     int prev = -1;
-    explicit DeviceGuard(const Ctx *c) {
-        if (hipGetDevice(&prev) == hipSuccess && prev != c->device) (void)hipSetDevice(c->device);
+    explicit DeviceGuard(const Ctx *c) : DeviceGuard(c->device) {}
+    explicit DeviceGuard(int device) {
+        if (hipGetDevice(&prev) == hipSuccess && prev != device) (void)hipSetDevice(device);
     }
     ~DeviceGuard() {
         int cur;
@@ -180,7 +182,7 @@ static int ntt_rows(Ctx *c, uint64_t *rows, const int32_t *mods, int n_rows, int
 // a destroy/release or layer call is rejected (FHELIN_E_INVALID_ARG) instead of
 // being dereferenced
 // ---------------------------------------------------------------------------
-enum HandleKind : int { H_CTX = 0, H_KEYSET, H_PTSET, H_PLAN, H_GRAPH, H_KINDS };
+enum HandleKind : int { H_CTX = 0, H_KEYSET, H_PTSET, H_PLAN, H_GRAPH, H_NATIVE, H_KINDS };
 static std::mutex live_mu;
 static std::set<const void *> live_set[H_KINDS];
 static void live_add(int kind, const void *h) {
@@ -195,7 +197,8 @@ static bool live_remove(int kind, const void *h) {
     std::lock_guard<std::mutex> g(live_mu);
     return h && live_set[kind].erase(h) > 0;
 }
-static const char *const HANDLE_NAMES[H_KINDS] = {"context", "key set", "plaintext set", "plan", "graph"};
+static const char *const HANDLE_NAMES[H_KINDS] = {"context", "key set", "plaintext set", "plan", "graph",
+                                                   "native pipeline"};
 #define FL_LIVE(kind, h)                                                                                    \
     FL_CHECK(live_has((kind), (h)), FHELIN_E_INVALID_ARG,                                                   \
              std::string("null, unknown or destroyed ") + HANDLE_NAMES[(kind)] + " handle")
@@ -710,6 +713,67 @@ FHELIN_EXPORT int fhelin_profile_enable(fhelin_ctx *ctx, int32_t enable) {
 FHELIN_EXPORT int fhelin_diag_alu_rate(int32_t op, int32_t waves_per_simd, int32_t iters, double *ghz,
                                        double *clk_per_op, double *ops_per_s) {
     API_BEGIN return diag_alu_rate(op, waves_per_simd, iters, ghz, clk_per_op, ops_per_s);
+    API_END
+}
+
+// ---- the paper's own pipeline (native.hip) -------------------------------------
+FHELIN_EXPORT int fhelin_native_create(const fhelin_native_params *prm, fhelin_native **out) {
+    API_BEGIN FL_CHECK(out, FHELIN_E_INVALID_ARG, "null argument");
+    Native *n = nullptr;
+    FL_RET(native_create(prm, &n));
+    *out = (fhelin_native *)n;
+    live_add(H_NATIVE, n);
+    return FHELIN_OK;
+    API_END
+}
+
+FHELIN_EXPORT int fhelin_native_destroy(fhelin_native *nt) {
+    API_BEGIN FL_CHECK(live_remove(H_NATIVE, nt), FHELIN_E_INVALID_ARG, "null, unknown or destroyed native handle");
+    native_destroy((Native *)nt);
+    return FHELIN_OK;
+    API_END
+}
+
+FHELIN_EXPORT int fhelin_native_keys_load(fhelin_native *nt, const uint64_t *ksk, void *stream) {
+    API_BEGIN FL_LIVE(H_NATIVE, nt);
+    Native *n = (Native *)nt;
+    DeviceGuard g(n->device);
+    return native_keys_load(n, ksk, (hipStream_t)stream);
+    API_END
+}
+
+FHELIN_EXPORT int fhelin_native_extract(fhelin_native *nt, const uint64_t *chunks, int32_t n_chunks, uint64_t *rows,
+                                        void *stream) {
+    API_BEGIN FL_LIVE(H_NATIVE, nt);
+    Native *n = (Native *)nt;
+    DeviceGuard g(n->device);
+    return native_extract(n, chunks, n_chunks, rows, (hipStream_t)stream);
+    API_END
+}
+
+FHELIN_EXPORT int fhelin_native_linear(fhelin_native *nt, const int32_t *row_ptr, const int32_t *col, const int32_t *val,
+                                       int32_t n_out, const uint64_t *rows, uint64_t *out, void *stream) {
+    API_BEGIN FL_LIVE(H_NATIVE, nt);
+    Native *n = (Native *)nt;
+    DeviceGuard g(n->device);
+    return native_linear(n, row_ptr, col, val, n_out, rows, out, (hipStream_t)stream);
+    API_END
+}
+
+FHELIN_EXPORT int fhelin_native_pack(fhelin_native *nt, const uint64_t *rows, int32_t n_rows, uint64_t *packed,
+                                     void *stream) {
+    API_BEGIN FL_LIVE(H_NATIVE, nt);
+    Native *n = (Native *)nt;
+    DeviceGuard g(n->device);
+    return native_pack(n, rows, n_rows, packed, (hipStream_t)stream);
+    API_END
+}
+
+FHELIN_EXPORT int fhelin_native_pack_workspace(const fhelin_native *nt, int32_t n_rows, uint64_t *bytes) {
+    API_BEGIN FL_LIVE(H_NATIVE, nt);
+    FL_CHECK(bytes && n_rows >= 0, FHELIN_E_INVALID_ARG, "null argument or negative row count");
+    *bytes = native_pack_workspace((const Native *)nt, n_rows);
+    return FHELIN_OK;
     API_END
 }
 

@@ -1,0 +1,539 @@
+// native.hip -- the paper's own server pipeline (Sec. 2.1-2.4, 4.2, 4.4): RLWE over the
+// discrete torus q = 2^64 in Z_q[X]/Phi_M, M = t^alpha, N = phi(M).
+//
+//   extraction  for every chunk and coefficient i, E_i = u sum_d ct(m(X^d))
+//               (X^(d (M-i)) - X^(d (M/t - r))), r = i mod M/t, u = M^-1 mod p
+//               (the lemma on partial trace extraction with the two-term dual basis
+//               element M conj(Omega*_i)); the client sent the powers m(X^d).
+//   linear      F_o = sum_i W[o][i] E_i (integer weights, CSR), the shuffle folded
+//               into W's rows.
+//   packing     phi(t^beta) rows into one ciphertext of sum_o y_o X^(o M/t^beta):
+//               leaves l_e = sum_j X^(j M/t^gamma) F_(e + j t^(beta-gamma)); per level
+//               i = gamma..beta-1 a merge of t sub-packs y_k, v_m = sum_k
+//               X^(k (M/t^(i+1) - m M/t)) y_k, S = v_(t-1), S = v_m + tau_i(S); then
+//               Tr_{K/K_beta} as, per level j = alpha-1 down to beta, S = P,
+//               S = P + tau_j(S) (t - 1 times); tau_i = sigma_(1 + t^i).
+//   tau(S)      automorphism then key switch with a gadget of base D = 2^log_d, depth l:
+//               a' = sigma(a), b' = sigma(b), digits d_i of a' (balanced, stored with
+//               the offset D/2), a'' = -sum_i d_i k_i.a, b'' = b' - sum_i d_i k_i.b.
+//               The products d_i k_i modulo Phi_M are one matrix product per key:
+//               K[j][i N + m] = coefficient j of X^m k_i, precomputed at key load, so a
+//               batch of ciphertexts switches as C = A K^T (A = digits).
+//
+// Polynomials are N uint64 coefficients of the power basis; ciphertexts [2][N] (a, b).
+// Reduction of a cyclic index x < M: X^(N + r) = -sum_{k < t-1} X^(k M/t + r), so
+// coefficient j of a polynomial given modulo X^M - 1 as c is c[j] - c[N + j mod M/t].
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "internal.h"
+#include "native.h"
+
+namespace fl {
+
+// ---------------------------------------------------------------------------
+// device helpers
+// ---------------------------------------------------------------------------
+struct NatDims {
+    int M, N, Mt;
+};
+
+// coefficient x (< M) of X^e c taken modulo X^M - 1 (c has N coefficients)
+__device__ __forceinline__ uint64_t cyc_at(const uint64_t *__restrict__ c, int x, int e, const NatDims &d) {
+    int s = x - e;
+    s += s < 0 ? d.M : 0;
+    return s < d.N ? c[s] : 0;
+}
+
+// coefficient j (< N) of X^e c modulo Phi_M
+__device__ __forceinline__ uint64_t mono_at(const uint64_t *__restrict__ c, int j, int e, const NatDims &d) {
+    return cyc_at(c, j, e, d) - cyc_at(c, d.N + j % d.Mt, e, d);
+}
+
+// coefficient x (< M) of c(X^g) modulo X^M - 1: c at g^-1 x mod M (ginv = g^-1 mod M)
+__device__ __forceinline__ uint64_t aut_cyc(const uint64_t *__restrict__ c, int x, int ginv, const NatDims &d) {
+    const int s = (int)(((int64_t)x * ginv) % d.M);
+    return s < d.N ? c[s] : 0;
+}
+
+__device__ __forceinline__ uint64_t aut_at(const uint64_t *__restrict__ c, int j, int ginv, const NatDims &d) {
+    return aut_cyc(c, j, ginv, d) - aut_cyc(c, d.N + j % d.Mt, ginv, d);
+}
+
+// ---------------------------------------------------------------------------
+// extraction: grid (ceil(N / 256), N rows, chunks)
+// ---------------------------------------------------------------------------
+struct NatPowers {
+    int n;
+    int32_t d[NAT_MAX_POW];
+};
+
+__global__ void __launch_bounds__(256) k_nat_extract(const uint64_t *__restrict__ pows, uint64_t *__restrict__ rows,
+                                                     NatDims dm, NatPowers pw, uint64_t u) {
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= dm.N) return;
+    const int i = blockIdx.y, ch = blockIdx.z;
+    const int r = i % dm.Mt;
+    const int64_t ct = 2 * (int64_t)dm.N;
+    const uint64_t *src = pows + (int64_t)ch * pw.n * ct;
+    uint64_t acc0 = 0, acc1 = 0;
+    for (int k = 0; k < pw.n; ++k) {
+        const int d = pw.d[k];
+        const int e1 = (int)(((int64_t)d * (dm.M - i)) % dm.M), e2 = (int)(((int64_t)d * (dm.Mt - r)) % dm.M);
+        const uint64_t *a = src + k * ct, *b = a + dm.N;
+        acc0 += mono_at(a, j, e1, dm) - mono_at(a, j, e2, dm);
+        acc1 += mono_at(b, j, e1, dm) - mono_at(b, j, e2, dm);
+    }
+    uint64_t *o = rows + ((int64_t)ch * dm.N + i) * ct;
+    o[j] = acc0 * u;
+    o[dm.N + j] = acc1 * u;
+}
+
+// ---------------------------------------------------------------------------
+// integer layer on rows (CSR): grid (ceil(2N / 256), n_out)
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_nat_linear(const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+                                                    const int32_t *__restrict__ val, const uint64_t *__restrict__ rows,
+                                                    uint64_t *__restrict__ out, int n2) {
+    const int c = blockIdx.x * 256 + threadIdx.x;
+    const int o = blockIdx.y;
+    if (c >= n2) return;
+    const int k0 = row_ptr[o], k1 = row_ptr[o + 1];
+    uint64_t acc = 0;
+    int k = k0;
+    // four independent loads in flight
+    for (; k + 4 <= k1; k += 4) {
+        uint64_t v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = rows[(int64_t)col[k + q] * n2 + c];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc += (uint64_t)(int64_t)val[k + q] * v[q];
+    }
+    for (; k < k1; ++k) acc += (uint64_t)(int64_t)val[k] * rows[(int64_t)col[k] * n2 + c];
+    out[(int64_t)o * n2 + c] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// packing pieces
+// ---------------------------------------------------------------------------
+// leaves: grid (ceil(N / 256), T, packs); out [packs][T][2][N]
+__global__ void __launch_bounds__(256) k_nat_leaves(const uint64_t *__restrict__ F, int n_rows, uint64_t *__restrict__ out,
+                                                    NatDims dm, int n_pack, int T, int phig, int estep) {
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= dm.N) return;
+    const int e = blockIdx.y, g = blockIdx.z;
+    const int64_t ct = 2 * (int64_t)dm.N;
+    uint64_t a0 = 0, a1 = 0;
+    for (int q = 0; q < phig; ++q) {
+        const int row = g * n_pack + e + q * T;
+        if (row >= n_rows) break;
+        const uint64_t *f = F + row * ct;
+        a0 += mono_at(f, j, q * estep, dm);
+        a1 += mono_at(f + dm.N, j, q * estep, dm);
+    }
+    uint64_t *o = out + ((int64_t)g * T + e) * ct;
+    o[j] = a0;
+    o[dm.N + j] = a1;
+}
+
+// merge terms: grid (ceil(N / 256), step * t, packs); cur [packs][t step][2][N] ->
+// v [packs][step][t][2][N], v[r][m] = sum_k X^(k (th - m Mt)) cur[r + k step]
+__global__ void __launch_bounds__(256) k_nat_merge_v(const uint64_t *__restrict__ cur, uint64_t *__restrict__ v,
+                                                     NatDims dm, int t, int step, int th) {
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= dm.N) return;
+    const int r = blockIdx.y / t, m = blockIdx.y % t, g = blockIdx.z;
+    const int64_t ct = 2 * (int64_t)dm.N;
+    const uint64_t *base = cur + (int64_t)g * t * step * ct;
+    uint64_t a0 = 0, a1 = 0;
+    int em = th - m * dm.Mt;
+    em %= dm.M;
+    em += em < 0 ? dm.M : 0;
+    for (int k = 0; k < t; ++k) {
+        const uint64_t *y = base + (int64_t)(r + k * step) * ct;
+        const int e = (int)(((int64_t)k * em) % dm.M);
+        a0 += mono_at(y, j, e, dm);
+        a1 += mono_at(y + dm.N, j, e, dm);
+    }
+    uint64_t *o = v + (((int64_t)g * step + r) * t + m) * ct;
+    o[j] = a0;
+    o[dm.N + j] = a1;
+}
+
+// automorphism + gadget digits of a batch: grid (ceil(N / 256), n); S [n] (es apart),
+// digits [n][l][N] (offset by D/2, < D), bp [n][N] = sigma(b)
+__global__ void __launch_bounds__(256) k_nat_aut_decomp(const uint64_t *__restrict__ S, int64_t s_es,
+                                                        uint32_t *__restrict__ dig, uint64_t *__restrict__ bp,
+                                                        NatDims dm, int ginv, int log_d, int l) {
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= dm.N) return;
+    const int c = blockIdx.y;
+    const uint64_t *a = S + c * s_es, *b = a + dm.N;
+    const uint64_t av = aut_at(a, j, ginv, dm);
+    bp[(int64_t)c * dm.N + j] = aut_at(b, j, ginv, dm);
+    // round to the top l log_d bits, then balanced digits from the least significant
+    const int bits = log_d * l, sh = 64 - bits;
+    uint64_t top = (av >> sh) + ((av >> (sh - 1)) & 1);  // < 2^bits + 1; a carry past the top wraps
+    const uint64_t D = 1ull << log_d, mask = D - 1;
+    uint32_t *o = dig + (int64_t)c * l * dm.N + j;
+    for (int i = l - 1; i >= 0; --i) {
+        int64_t d = (int64_t)(top & mask);
+        top >>= log_d;
+        if (d >= (int64_t)(D >> 1)) {
+            d -= (int64_t)D;
+            top += 1;
+        }
+        o[(int64_t)i * dm.N] = (uint32_t)(d + (int64_t)(D >> 1));
+    }
+}
+
+// C = A K^T for both key parts, plus the addend: out[c][p][j] = add[c][p][j] (+ bp[c][j]
+// for p = 1) - (sum_k A[c][k] K_p[j][k] - corr_p[j]), A[c][k] = digit + D/2 < 2^16,
+// corr_p[j] = (D/2) sum_k K_p[j][k].  Each product: v_mad_u64_u32 on the low key word and
+// a 32-bit multiply-add of the high word (the sum is needed modulo 2^64 only).
+// Tile: 32 ciphertexts x 128 coefficients per workgroup, thread (tc, tj) owns
+// ciphertexts tc, tc + 16 and coefficients tj + 16 q (q < 8); K chunks of 16 staged in LDS.
+constexpr int KS_TC = 32, KS_TJ = 128, KS_TK = 16;
+
+__global__ void __launch_bounds__(256) k_nat_ksprod(const uint32_t *__restrict__ A, const uint64_t *__restrict__ Ka,
+                                                    const uint64_t *__restrict__ Kb, const uint64_t *__restrict__ corr_a,
+                                                    const uint64_t *__restrict__ corr_b, const uint64_t *__restrict__ bp,
+                                                    const uint64_t *__restrict__ add, int64_t add_es,
+                                                    uint64_t *__restrict__ out, int64_t out_es, int n, int N, int KD) {
+    __shared__ uint32_t As[KS_TK][KS_TC + 1];
+    __shared__ uint64_t Ks[2][KS_TK][KS_TJ + 1];
+    const int c0 = blockIdx.y * KS_TC, j0 = blockIdx.x * KS_TJ;
+    const int tc = threadIdx.x >> 4, tj = threadIdx.x & 15;
+    uint64_t lo[2][2][8];
+    uint32_t hi[2][2][8];
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                lo[p][x][q] = 0;
+                hi[p][x][q] = 0;
+            }
+    for (int k0 = 0; k0 < KD; k0 += KS_TK) {
+        __syncthreads();
+        // A tile: 32 x 16 digits (two per thread)
+        for (int e = threadIdx.x; e < KS_TC * KS_TK; e += 256) {
+            const int cc = e / KS_TK, kk = e % KS_TK;
+            const int c = c0 + cc, k = k0 + kk;
+            As[kk][cc] = c < n && k < KD ? A[(int64_t)c * KD + k] : 0u;
+        }
+        // K tiles: 128 x 16 per part
+        for (int e = threadIdx.x; e < KS_TJ * KS_TK; e += 256) {
+            const int jj = e / KS_TK, kk = e % KS_TK;
+            const int j = j0 + jj, k = k0 + kk;
+            const bool ok = j < N && k < KD;
+            Ks[0][kk][jj] = ok ? Ka[(int64_t)j * KD + k] : 0;
+            Ks[1][kk][jj] = ok ? Kb[(int64_t)j * KD + k] : 0;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int kk = 0; kk < KS_TK; ++kk) {
+            const uint32_t a[2] = {As[kk][tc], As[kk][tc + 16]};
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+#pragma unroll
+                for (int p = 0; p < 2; ++p) {
+                    const uint64_t kv = Ks[p][kk][tj + 16 * q];
+                    const uint32_t kl = (uint32_t)kv, kh = (uint32_t)(kv >> 32);
+#pragma unroll
+                    for (int x = 0; x < 2; ++x) {
+                        lo[p][x][q] += (uint64_t)a[x] * kl;
+                        hi[p][x][q] += a[x] * kh;
+                    }
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int x = 0; x < 2; ++x) {
+        const int c = c0 + tc + 16 * x;
+        if (c >= n) continue;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int j = j0 + tj + 16 * q;
+            if (j >= N) continue;
+            const uint64_t sa = lo[0][x][q] + ((uint64_t)hi[0][x][q] << 32) - corr_a[j];
+            const uint64_t sb = lo[1][x][q] + ((uint64_t)hi[1][x][q] << 32) - corr_b[j];
+            const uint64_t *ad = add + c * add_es;
+            uint64_t *o = out + c * out_es;
+            o[j] = ad[j] - sa;
+            o[N + j] = ad[N + j] + bp[(int64_t)c * N + j] - sb;
+        }
+    }
+}
+
+// key product matrices: K[lv][p][j][i N + m] = coefficient j of X^m k_(lv, i, p);
+// grid (ceil(N / 256), l N, levels * 2)
+__global__ void __launch_bounds__(256) k_nat_kmat(const uint64_t *__restrict__ ksk, uint64_t *__restrict__ K, NatDims dm,
+                                                  int l) {
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= dm.N) return;
+    const int km = blockIdx.y, i = km / dm.N, m = km % dm.N;
+    const int lv = blockIdx.z >> 1, p = blockIdx.z & 1;
+    const uint64_t *k = ksk + (((int64_t)lv * l + i) * 2 + p) * dm.N;
+    const int64_t KD = (int64_t)l * dm.N;
+    K[(((int64_t)lv * 2 + p) * dm.N + j) * KD + km] = mono_at(k, j, m, dm);
+}
+
+// corr[lv][p][j] = (D/2) sum_k K[lv][p][j][k]; one workgroup per row (lv, p, j)
+__global__ void __launch_bounds__(256) k_nat_kcorr(const uint64_t *__restrict__ K, uint64_t *__restrict__ corr,
+                                                   int64_t KD, uint64_t half_d) {
+    __shared__ uint64_t part[256];
+    const uint64_t *row = K + (int64_t)blockIdx.x * KD;
+    uint64_t s = 0;
+    for (int64_t k = threadIdx.x; k < KD; k += 256) s += row[k];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) corr[blockIdx.x] = part[0] * half_d;
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+static bool is_odd_prime(int t) {
+    if (t < 3 || t % 2 == 0) return false;
+    for (int f = 3; f * f <= t; f += 2)
+        if (t % f == 0) return false;
+    return true;
+}
+
+static int64_t ipow(int64_t b, int e) {
+    int64_t r = 1;
+    while (e-- > 0) r *= b;
+    return r;
+}
+
+static int64_t inv_mod(int64_t a, int64_t m) {
+    // extended Euclid; a and m coprime
+    int64_t g = m, x = 0, x1 = 1, aa = a % m;
+    if (aa < 0) aa += m;
+    while (aa) {
+        const int64_t q = g / aa;
+        int64_t t = g - q * aa;
+        g = aa;
+        aa = t;
+        t = x - q * x1;
+        x = x1;
+        x1 = t;
+    }
+    x %= m;
+    return x < 0 ? x + m : x;
+}
+
+int native_create(const fhelin_native_params *prm, Native **out) {
+    FL_CHECK(prm && out, FHELIN_E_INVALID_ARG, "native_create: null argument");
+    const fhelin_native_params &q = *prm;
+    FL_CHECK(is_odd_prime(q.t), FHELIN_E_UNSUPPORTED_PARAM, "t must be an odd prime");
+    FL_CHECK(q.alpha >= 2 && ipow(q.t, q.alpha) <= NAT_MAX_M, FHELIN_E_UNSUPPORTED_PARAM,
+             "M = t^alpha must satisfy alpha >= 2 and M <= " + std::to_string(NAT_MAX_M));
+    FL_CHECK(q.gamma >= 1 && q.gamma <= 2 && q.gamma <= q.beta && q.beta <= q.alpha - 1, FHELIN_E_UNSUPPORTED_PARAM,
+             "need 1 <= gamma <= 2 and gamma <= beta <= alpha - 1");
+    FL_CHECK(q.log_d >= 1 && q.log_d <= 16 && q.l >= 1 && q.l <= 8 && q.log_d * q.l < 64, FHELIN_E_UNSUPPORTED_PARAM,
+             "gadget: 1 <= log_d <= 16, 1 <= l <= 8, log_d l < 64");
+    FL_CHECK(q.log_p >= 1 && q.log_p <= 31, FHELIN_E_UNSUPPORTED_PARAM, "message modulus: 1 <= log_p <= 31");
+    std::unique_ptr<Native> n(new Native());
+    n->prm = q;
+    n->M = (int)ipow(q.t, q.alpha);
+    n->Mt = n->M / q.t;
+    n->N = n->M - n->Mt;
+    n->n_pack = (int)((q.t - 1) * ipow(q.t, q.beta - 1));
+    n->T = (int)ipow(q.t, q.beta - q.gamma);
+    n->phig = (int)((q.t - 1) * ipow(q.t, q.gamma - 1));
+    const int64_t p = 1ll << q.log_p;
+    int64_t u = inv_mod(n->M, p);
+    if (u > p / 2) u -= p;
+    n->u = (uint64_t)u;
+    FL_CHECK(n->phig <= NAT_MAX_POW, FHELIN_E_UNSUPPORTED_PARAM, "too many powers at this gamma");
+    if (q.gamma == 1) {
+        for (int k = 1; k < q.t; ++k) n->powers.push_back(k);
+    } else {
+        for (int k = 1; k < q.t; ++k)
+            for (int j = 0; j < q.t; ++j) n->powers.push_back((int)(((int64_t)k * (j * q.t + 1)) % n->M));
+    }
+    for (int i = q.gamma; i < q.alpha; ++i) {
+        const int g = (int)((1 + ipow(q.t, i)) % n->M);
+        n->tau.push_back(g);
+        n->tau_inv.push_back((int)inv_mod(g, n->M));
+    }
+    FL_TRY_HIP(hipGetDevice(&n->device));
+    *out = n.release();
+    return FHELIN_OK;
+}
+
+void native_destroy(Native *n) {
+    if (!n) return;
+    (void)hipSetDevice(n->device);
+    (void)hipDeviceSynchronize();
+    if (n->kmat) (void)hipFree(n->kmat);
+    if (n->kcorr) (void)hipFree(n->kcorr);
+    if (n->ws) (void)hipFree(n->ws);
+    delete n;
+}
+
+static int nat_workspace(Native *n, size_t bytes, hipStream_t s, uint8_t **out) {
+    if (n->ws_bytes < bytes) {
+        if (n->ws) {
+            FL_TRY_HIP(hipStreamSynchronize(s));
+            FL_TRY_HIP(hipFree(n->ws));
+            n->ws = nullptr;
+            n->ws_bytes = 0;
+        }
+        if (hipMalloc(&n->ws, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return set_error(FHELIN_E_OOM, "native workspace: device allocation failed");
+        }
+        n->ws_bytes = bytes;
+    }
+    *out = (uint8_t *)n->ws;
+    return FHELIN_OK;
+}
+
+static NatDims dims(const Native *n) { return NatDims{n->M, n->N, n->Mt}; }
+
+int native_keys_load(Native *n, const uint64_t *ksk, hipStream_t s) {
+    FL_CHECK(n && ksk, FHELIN_E_INVALID_ARG, "native_keys_load: null argument");
+    const int levels = (int)n->tau.size(), l = n->prm.l;
+    const int64_t KD = (int64_t)l * n->N;
+    const size_t kbytes = (size_t)levels * 2 * n->N * KD * sizeof(uint64_t);
+    if (!n->kmat) {
+        if (hipMalloc((void **)&n->kmat, kbytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return set_error(FHELIN_E_OOM, "native keys: device allocation failed");
+        }
+        if (hipMalloc((void **)&n->kcorr, (size_t)levels * 2 * n->N * sizeof(uint64_t)) != hipSuccess) {
+            (void)hipGetLastError();
+            return set_error(FHELIN_E_OOM, "native keys: device allocation failed");
+        }
+    }
+    const NatDims dm = dims(n);
+    hipLaunchKernelGGL(k_nat_kmat, dim3((n->N + 255) / 256, (unsigned)KD, levels * 2), dim3(256), 0, s, ksk, n->kmat, dm,
+                       l);
+    FL_TRY_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_nat_kcorr, dim3(levels * 2 * n->N), dim3(256), 0, s, n->kmat, n->kcorr, KD,
+                       (uint64_t)1 << (n->prm.log_d - 1));
+    FL_TRY_HIP(hipGetLastError());
+    n->keys = true;
+    return FHELIN_OK;
+}
+
+int native_extract(Native *n, const uint64_t *pows, int n_chunks, uint64_t *rows, hipStream_t s) {
+    FL_CHECK(n && pows && rows && n_chunks >= 0, FHELIN_E_INVALID_ARG, "native_extract: null argument");
+    FL_CHECK(n_chunks <= 65535, FHELIN_E_INVALID_ARG, "native_extract: at most 65535 chunks per call");
+    if (n_chunks == 0) return FHELIN_OK;
+    NatPowers pw{};
+    pw.n = (int)n->powers.size();
+    for (int k = 0; k < pw.n; ++k) pw.d[k] = n->powers[k];
+    hipLaunchKernelGGL(k_nat_extract, dim3((n->N + 255) / 256, n->N, n_chunks), dim3(256), 0, s, pows, rows, dims(n), pw,
+                       n->u);
+    FL_TRY_HIP(hipGetLastError());
+    return FHELIN_OK;
+}
+
+int native_linear(Native *n, const int32_t *row_ptr, const int32_t *col, const int32_t *val, int n_out,
+                  const uint64_t *rows, uint64_t *out, hipStream_t s) {
+    FL_CHECK(n && row_ptr && col && val && rows && out && n_out >= 0, FHELIN_E_INVALID_ARG,
+             "native_linear: null argument");
+    FL_CHECK(n_out <= 65535, FHELIN_E_INVALID_ARG, "native_linear: at most 65535 outputs per call");
+    if (n_out == 0) return FHELIN_OK;
+    const int n2 = 2 * n->N;
+    hipLaunchKernelGGL(k_nat_linear, dim3((n2 + 255) / 256, n_out), dim3(256), 0, s, row_ptr, col, val, rows, out, n2);
+    FL_TRY_HIP(hipGetLastError());
+    return FHELIN_OK;
+}
+
+size_t native_pack_workspace(const Native *n, int n_rows) {
+    const size_t packs = (size_t)(n_rows + n->n_pack - 1) / n->n_pack;
+    const size_t ct = 2 * (size_t)n->N * sizeof(uint64_t);
+    const size_t nmax = packs * n->T;  // the leaves: the widest level
+    // current sub-packs, merge terms (t per merge), results, and the digits and sigma(b)
+    // of a key-switch batch
+    return 3 * nmax * ct + nmax * (size_t)n->prm.l * n->N * sizeof(uint32_t) + nmax * n->N * sizeof(uint64_t);
+}
+
+// S_out = add + tau(S_in) for a batch of cnt ciphertexts with the key of tower level lv.
+// S_out may be S_in: the digits kernel reads S_in completely before the product kernel
+// writes S_out (same stream).
+static int nat_ks_step(Native *n, int lv, const uint64_t *S, int64_t s_es, const uint64_t *add, int64_t add_es,
+                       uint64_t *out, int64_t out_es, int cnt, uint32_t *dig, uint64_t *bp, hipStream_t s) {
+    const NatDims dm = dims(n);
+    const int l = n->prm.l;
+    const int64_t KD = (int64_t)l * n->N;
+    const uint64_t *Ka = n->kmat + (int64_t)lv * 2 * n->N * KD, *Kb = Ka + (int64_t)n->N * KD;
+    const uint64_t *ca = n->kcorr + (int64_t)lv * 2 * n->N, *cb = ca + n->N;
+    for (int c0 = 0; c0 < cnt; c0 += 65535) {
+        const int c = std::min(cnt - c0, 65535);
+        hipLaunchKernelGGL(k_nat_aut_decomp, dim3((n->N + 255) / 256, c), dim3(256), 0, s, S + c0 * s_es, s_es, dig, bp,
+                           dm, n->tau_inv[lv], n->prm.log_d, l);
+        FL_TRY_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_nat_ksprod, dim3((n->N + KS_TJ - 1) / KS_TJ, (c + KS_TC - 1) / KS_TC), dim3(256), 0, s, dig,
+                           Ka, Kb, ca, cb, bp, add + c0 * add_es, add_es, out + c0 * out_es, out_es, c, n->N, (int)KD);
+        FL_TRY_HIP(hipGetLastError());
+    }
+    return FHELIN_OK;
+}
+
+int native_pack(Native *n, const uint64_t *rows, int n_rows, uint64_t *packed, hipStream_t s) {
+    FL_CHECK(n && rows && packed && n_rows >= 0, FHELIN_E_INVALID_ARG, "native_pack: null argument");
+    FL_CHECK(n->keys, FHELIN_E_MISSING_GALOIS_KEY, "native_pack: keys not loaded");
+    if (n_rows == 0) return FHELIN_OK;
+    const int t = n->prm.t, packs = (n_rows + n->n_pack - 1) / n->n_pack;
+    FL_CHECK(packs <= 65535 && (int64_t)packs * n->T <= (1 << 22), FHELIN_E_INVALID_ARG,
+             "native_pack: too many rows per call");
+    const NatDims dm = dims(n);
+    const int64_t ct = 2 * (int64_t)n->N;
+    uint8_t *ws;
+    FL_RET(nat_workspace(n, native_pack_workspace(n, n_rows), s, &ws));
+    const int64_t nmax = (int64_t)packs * n->T;
+    uint64_t *cur = (uint64_t *)ws, *v = cur + nmax * ct, *S = v + nmax * ct;
+    uint32_t *dig = (uint32_t *)(S + nmax * ct);
+    uint64_t *bp = (uint64_t *)(dig + nmax * n->prm.l * n->N);
+    const unsigned gx = (n->N + 255) / 256;
+    // leaves
+    hipLaunchKernelGGL(k_nat_leaves, dim3(gx, n->T, packs), dim3(256), 0, s, rows, n_rows, cur, dm, n->n_pack, n->T,
+                       n->phig, (int)(n->M / ipow(t, n->prm.gamma)));
+    FL_TRY_HIP(hipGetLastError());
+    // merges up the tower: level i has len = t^(beta - i) sub-packs per pack
+    int len = n->T;
+    for (int i = n->prm.gamma; i < n->prm.beta; ++i) {
+        const int lv = i - n->prm.gamma, step = len / t, th = (int)(n->M / ipow(t, i + 1));
+        hipLaunchKernelGGL(k_nat_merge_v, dim3(gx, step * t, packs), dim3(256), 0, s, cur, v, dm, t, step, th);
+        FL_TRY_HIP(hipGetLastError());
+        // S = v_(t-1); S = v_m + tau_i(S) for m = t-2 .. 0 (a merge's t terms are ct apart)
+        const int cnt = packs * step;
+        const uint64_t *src = v + (int64_t)(t - 1) * ct;
+        int64_t src_es = (int64_t)t * ct;
+        for (int m = t - 2; m >= 0; --m) {
+            FL_RET(nat_ks_step(n, lv, src, src_es, v + (int64_t)m * ct, (int64_t)t * ct, S, ct, cnt, dig, bp, s));
+            src = S;
+            src_es = ct;
+        }
+        std::swap(cur, S);
+        len = step;
+    }
+    // Tr_{K/K_beta}: per level j = alpha-1 down to beta, T_j = P, T_j = P + tau_j(T_j)
+    // (t - 1 times)
+    for (int j = n->prm.alpha - 1; j >= n->prm.beta; --j) {
+        const int lv = j - n->prm.gamma;
+        const uint64_t *src = cur;
+        for (int k = 0; k < t - 1; ++k) {
+            FL_RET(nat_ks_step(n, lv, src, ct, cur, ct, S, ct, packs, dig, bp, s));
+            src = S;
+        }
+        std::swap(cur, S);
+    }
+    FL_TRY_HIP(hipMemcpyAsync(packed, cur, (size_t)packs * ct * sizeof(uint64_t), hipMemcpyDeviceToDevice, s));
+    return FHELIN_OK;
+}
+
+}  // namespace fl

@@ -65,6 +65,11 @@ class fhelin_ct_batch(ctypes.Structure):
     _fields_ = [("data", _vp), ("n_ct", _i32), ("stride", _i32), ("levels", ctypes.POINTER(_i32))]
 
 
+class fhelin_native_params(ctypes.Structure):
+    _fields_ = [("t", _i32), ("alpha", _i32), ("gamma", _i32), ("beta", _i32), ("log_d", _i32), ("l", _i32),
+                ("log_p", _i32)]
+
+
 class fhelin_tune(ctypes.Structure):
     _fields_ = [("chunk", _i32), ("ks_eg", _i32), ("mac_my", _i32), ("ntt_threads", _i32), ("persistent", _i32),
                 ("fuse_baby", _i32)]
@@ -111,6 +116,13 @@ _SIGS = {
     "fhelin_graph_launch": [_vp, _vp],
     "fhelin_graph_destroy": [_vp],
     "fhelin_ctx_faults": [_vp, ctypes.POINTER(_u32)],
+    "fhelin_native_create": [ctypes.POINTER(fhelin_native_params), _pvp],
+    "fhelin_native_destroy": [_vp],
+    "fhelin_native_keys_load": [_vp, _vp, _vp],
+    "fhelin_native_extract": [_vp, _vp, _i32, _vp, _vp],
+    "fhelin_native_linear": [_vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp],
+    "fhelin_native_pack": [_vp, _vp, _i32, _vp, _vp],
+    "fhelin_native_pack_workspace": [_vp, _i32, ctypes.POINTER(_u64)],
     "fhelin_diag_alu_rate": [_i32, _i32, _i32, ctypes.POINTER(_dbl), ctypes.POINTER(_dbl), ctypes.POINTER(_dbl)],
     "fhelin_profile_enable": [_vp, _i32],
     "fhelin_profile_read": [_vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
@@ -415,6 +427,61 @@ def fhelin_ctx_faults(ctx) -> int:
     """Faults of bounded device-side waits since the last call (0 = none); clears them."""
     v = _u32()
     _check(_lib.fhelin_ctx_faults(ctx, ctypes.byref(v)))
+    return int(v.value)
+
+
+# ---- the paper's own pipeline: RLWE over Z_{2^64}[X]/Phi_M ----------------------
+def _u64_tensor(x: torch.Tensor, what: str):
+    if not (x.is_cuda and x.dtype in (torch.uint64, torch.int64) and x.is_contiguous()):
+        raise ValueError(f"{what}: expected a contiguous 64-bit CUDA tensor")
+    return _vp(x.data_ptr())
+
+
+def _i32_tensor(x: torch.Tensor, what: str):
+    if not (x.is_cuda and x.dtype == torch.int32 and x.is_contiguous()):
+        raise ValueError(f"{what}: expected a contiguous int32 CUDA tensor")
+    return _vp(x.data_ptr())
+
+
+def fhelin_native_create(t: int, alpha: int, gamma: int, beta: int, log_d: int, l: int, log_p: int):
+    prm = fhelin_native_params(t, alpha, gamma, beta, log_d, l, log_p)
+    out = _vp()
+    _check(_lib.fhelin_native_create(ctypes.byref(prm), ctypes.byref(out)))
+    return out
+
+
+def fhelin_native_destroy(nt):
+    _check(_lib.fhelin_native_destroy(nt))
+
+
+def fhelin_native_keys_load(nt, ksk: torch.Tensor, stream=None):
+    """ksk: [alpha-gamma][l][2][N] keys of the Galois elements 1 + t^i."""
+    _check(_lib.fhelin_native_keys_load(nt, _u64_tensor(ksk, "ksk"), _stream(stream)))
+
+
+def fhelin_native_extract(nt, chunks: torch.Tensor, rows: torch.Tensor, stream=None):
+    """chunks [n_chunks][phi(t^gamma)][2][N] -> rows [n_chunks N][2][N]."""
+    _check(_lib.fhelin_native_extract(nt, _u64_tensor(chunks, "chunks"), chunks.shape[0], _u64_tensor(rows, "rows"),
+                                      _stream(stream)))
+
+
+def fhelin_native_linear(nt, row_ptr: torch.Tensor, col: torch.Tensor, val: torch.Tensor, rows: torch.Tensor,
+                         out: torch.Tensor, stream=None):
+    """out[o] = sum val[k] rows[col[k]] over CSR row o (int32 CUDA arrays)."""
+    _check(_lib.fhelin_native_linear(nt, _i32_tensor(row_ptr, "row_ptr"), _i32_tensor(col, "col"),
+                                     _i32_tensor(val, "val"), out.shape[0], _u64_tensor(rows, "rows"),
+                                     _u64_tensor(out, "out"), _stream(stream)))
+
+
+def fhelin_native_pack(nt, rows: torch.Tensor, packed: torch.Tensor, stream=None):
+    """rows [n][2][N] -> packed [ceil(n / phi(t^beta))][2][N]."""
+    _check(_lib.fhelin_native_pack(nt, _u64_tensor(rows, "rows"), rows.shape[0], _u64_tensor(packed, "packed"),
+                                   _stream(stream)))
+
+
+def fhelin_native_pack_workspace(nt, n_rows: int) -> int:
+    v = _u64()
+    _check(_lib.fhelin_native_pack_workspace(nt, n_rows, ctypes.byref(v)))
     return int(v.value)
 
 

@@ -113,3 +113,33 @@ def test_null_and_unknown_handles_rejected_without_a_gpu():
     assert lib.fhelin_linear_apply(ctypes.addressof(fake), ctypes.addressof(fake), None, ctypes.addressof(fake),
                                    None, None, 0, None) == -1
     assert b"context" in lib.fhelin_last_error()
+
+
+class _NatPrm(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in ("t", "alpha", "gamma", "beta", "log_d", "l", "log_p")]
+
+
+def test_native_create_rejects_bad_parameters_on_the_host():
+    """The paper's own pipeline checks its parameters before any device call: t an odd
+    prime, M = t^alpha <= 8192, 1 <= gamma <= 2, gamma <= beta <= alpha - 1, the gadget
+    and the message modulus in range; null and unknown handles are rejected."""
+    lib = ctypes.CDLL(LIB)
+    lib.fhelin_last_error.restype = ctypes.c_char_p
+    lib.fhelin_native_create.argtypes = [ctypes.POINTER(_NatPrm), ctypes.POINTER(ctypes.c_void_p)]
+    good = dict(t=3, alpha=7, gamma=1, beta=6, log_d=9, l=3, log_p=8)
+    bad = {"t even": dict(t=4), "t not prime": dict(t=9), "t = 2": dict(t=2), "alpha 1": dict(alpha=1),
+           "M too large": dict(alpha=9), "gamma 0": dict(gamma=0), "gamma 3": dict(gamma=3, beta=5),
+           "beta < gamma": dict(gamma=2, beta=1), "beta = alpha": dict(beta=7), "log_d 0": dict(log_d=0),
+           "log_d 17": dict(log_d=17), "l 9": dict(l=9, log_d=4), "gadget 64 bits": dict(log_d=16, l=4),
+           "log_p 0": dict(log_p=0), "log_p 32": dict(log_p=32)}
+    for name, change in bad.items():
+        out = ctypes.c_void_p()
+        prm = _NatPrm(**{**good, **change})
+        assert lib.fhelin_native_create(ctypes.byref(prm), ctypes.byref(out)) == -2, name
+        assert not out.value, name
+    assert lib.fhelin_native_create(None, None) == -1
+    fake = ctypes.create_string_buffer(4096)
+    lib.fhelin_native_destroy.argtypes = [ctypes.c_void_p]
+    assert lib.fhelin_native_destroy(None) == -1
+    assert lib.fhelin_native_destroy(ctypes.addressof(fake)) == -1
+    assert b"native" in lib.fhelin_last_error()

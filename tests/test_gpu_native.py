@@ -1,0 +1,141 @@
+"""The paper's own server pipeline on the GPU (RLWE over Z_{2^64}[X]/Phi_M): partial
+trace extraction, the integer layer on the extracted rows with a folded shuffle, and
+fast packing, through the C ABI, compared with the oracle element by element at every
+stage, and the packed ciphertexts decrypted to the integer layer's outputs."""
+import numpy as np
+import pytest
+
+from oracle import native_rlwe as R
+from tests.gpu_util import dev, host
+
+pytestmark = pytest.mark.gpu
+
+
+def _csr(W):
+    """CSR of an integer matrix: (row_ptr, col, val) as int32 arrays."""
+    rows, cols = np.nonzero(W)
+    row_ptr = np.zeros(W.shape[0] + 1, np.int32)
+    np.add.at(row_ptr, rows + 1, 1)
+    return np.cumsum(row_ptr).astype(np.int32), cols.astype(np.int32), W[rows, cols].astype(np.int32)
+
+
+def _i32(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, np.int32)).cuda()
+
+
+def _conv_like(rng, n_out, n_in, nnz, mag):
+    """Integer weights with nnz nonzeros per output (a convolution's row shape)."""
+    W = np.zeros((n_out, n_in), np.int64)
+    for o in range(n_out):
+        idx = rng.choice(n_in, nnz, replace=False)
+        W[o, idx] = rng.integers(-mag, mag, nnz)
+    return W
+
+
+def _run(F, P, chunks, W, perm, keys, sample_rows=None):
+    """GPU pipeline; returns (rows, F rows, packed) on the host."""
+    import torch
+    nt = F.fhelin_native_create(P.t, P.alpha, P.gamma, P.beta, P.log_d, P.l, P.log_p)
+    try:
+        ksk = np.stack([keys[d] for d in P.taus()])
+        F.fhelin_native_keys_load(nt, dev(ksk))
+        x = dev(chunks)
+        rows = torch.zeros((chunks.shape[0] * P.N, 2, P.N), dtype=torch.int64, device="cuda")
+        F.fhelin_native_extract(nt, x, rows)
+        rp, col, val = _csr(np.asarray(W)[perm])
+        out = torch.zeros((W.shape[0], 2, P.N), dtype=torch.int64, device="cuda")
+        F.fhelin_native_linear(nt, _i32(rp), _i32(col), _i32(val), rows, out)
+        n_packs = (W.shape[0] + P.n_pack - 1) // P.n_pack
+        packed = torch.zeros((n_packs, 2, P.N), dtype=torch.int64, device="cuda")
+        F.fhelin_native_pack(nt, out, packed)
+        return host(rows), host(out), host(packed)
+    finally:
+        F.fhelin_native_destroy(nt)
+
+
+@pytest.mark.parametrize("t,alpha,gamma,beta", [(3, 4, 1, 3), (3, 4, 2, 3), (5, 3, 1, 2), (5, 3, 2, 2), (7, 2, 1, 1),
+                                                (3, 5, 1, 2)])
+def test_native_pipeline_bit_exact_small_rings(t, alpha, gamma, beta):
+    from paper_2509_01253_amd import fhelin as F
+    print(f"native t={t} alpha={alpha} gamma={gamma} beta={beta}", flush=True)
+    P = R.NativeParams(t, alpha, gamma, beta, 9, 3, 8, 2.0 ** 28)
+    cl = R.NativeClient(P, 100 + t * 10 + alpha)
+    keys = cl.keyset()
+    rng = np.random.default_rng(t * 100 + alpha * 10 + gamma)
+    n_in = P.N + P.N // 3
+    x = rng.integers(0, 16, n_in)
+    chunks = []
+    for c in range(2):
+        m = np.zeros(P.N, np.int64)
+        part = x[c * P.N: (c + 1) * P.N]
+        m[: part.size] = part
+        chunks.append(cl.encrypt_powers(m))
+    chunks = np.stack(chunks)
+    n_out = 2 * P.n_pack + 5  # two full packs and a partial one
+    W = _conv_like(rng, n_out, n_in, min(24, n_in), 8)
+    perm = rng.permutation(n_out)
+    rows, Fo, packed = _run(F, P, chunks, W, perm, keys)
+    want_rows = np.concatenate([R.extract(P, c) for c in chunks])
+    assert np.array_equal(rows, want_rows)
+    want_F = R.linear_rows(W[perm], want_rows[:n_in])
+    assert np.array_equal(Fo, want_F)
+    y = (W[perm] @ x) % P.p
+    pos = R.unpack_positions(P)
+    for g in range(packed.shape[0]):
+        want = R.pack(P, want_F[g * P.n_pack: (g + 1) * P.n_pack], keys)
+        assert np.array_equal(packed[g], want), g
+        dec = cl.decrypt(packed[g])
+        seg = y[g * P.n_pack: (g + 1) * P.n_pack]
+        exp = np.zeros(P.N, np.int64)
+        exp[pos[: seg.size]] = seg
+        assert np.array_equal(dec, exp), g
+
+
+@pytest.mark.parametrize("gamma", [1, 2])
+def test_native_pipeline_paper_8bit_set(gamma):
+    """The paper's 8-bit parameter set (M = 3^7, D = 512, l = 3, p = 2^8) with packs of
+    phi(3^6) = 486 outputs: a convolution-shaped layer (144 weights of 4 bits per
+    output) over two chunks; rows and layer outputs compared on sampled rows, every
+    packed ciphertext element by element, and the decryptions equal to the layer."""
+    from paper_2509_01253_amd import fhelin as F
+    print(f"native 3^7 gamma={gamma}", flush=True)
+    P = R.NativeParams(3, 7, gamma, 6, 9, 3, 8, 2.0 ** 28)
+    cl = R.NativeClient(P, 700 + gamma)
+    keys = cl.keyset()
+    rng = np.random.default_rng(710 + gamma)
+    n_in = 2 * P.N
+    x = rng.integers(0, 16, n_in)
+    chunks = np.stack([cl.encrypt_powers(x[c * P.N: (c + 1) * P.N]) for c in range(2)])
+    n_out = 2 * P.n_pack + 7
+    W = _conv_like(rng, n_out, n_in, 144, 8)
+    perm = rng.permutation(n_out)
+    rows, Fo, packed = _run(F, P, chunks, W, perm, keys)
+    for c in range(2):
+        want = R.extract(P, chunks[c])
+        sel = rng.choice(P.N, 40, replace=False)
+        assert np.array_equal(rows[c * P.N + sel], want[sel]), c
+    sel = rng.choice(n_out, 30, replace=False)
+    assert np.array_equal(Fo[sel], R.linear_rows(W[perm][sel], rows))
+    y = (W[perm] @ x) % P.p
+    pos = R.unpack_positions(P)
+    for g in range(packed.shape[0]):
+        want = R.pack(P, Fo[g * P.n_pack: (g + 1) * P.n_pack], keys)
+        assert np.array_equal(packed[g], want), g
+        seg = y[g * P.n_pack: (g + 1) * P.n_pack]
+        assert np.array_equal(cl.decrypt(packed[g])[pos[: seg.size]], seg), g
+
+
+def test_native_pack_needs_keys_and_rejects_stale_handles():
+    from paper_2509_01253_amd import fhelin as F
+    import torch
+    nt = F.fhelin_native_create(3, 4, 1, 3, 9, 3, 8)
+    rows = torch.zeros((5, 2, 54), dtype=torch.int64, device="cuda")
+    packed = torch.zeros((1, 2, 54), dtype=torch.int64, device="cuda")
+    with pytest.raises(F.FhelinError) as e:
+        F.fhelin_native_pack(nt, rows, packed)
+    assert e.value.status == F.FHELIN_E_MISSING_GALOIS_KEY
+    assert F.fhelin_native_pack_workspace(nt, 18) > 0
+    F.fhelin_native_destroy(nt)
+    with pytest.raises(F.FhelinError):
+        F.fhelin_native_destroy(nt)
