@@ -50,6 +50,11 @@ def parse():
                     help="1: each key switch's ModUp and forward NTT in one persistent launch, 0: separate launches "
                          "(default: the plan's default tune)")
     ap.add_argument("--ntt-threads", type=int, default=0, help="workgroup size of the two-pass NTT kernels")
+    ap.add_argument("--with-native", type=int, default=1,
+                    help="1: add the paper's own pipeline (ResNet-20 linear layers at its 8-bit set, gamma 1 and 2) "
+                         "to the default run's line; 0: skip")
+    ap.add_argument("--native", type=int, default=0,
+                    help="only the paper's own pipeline at this gamma (1 or 2): one JSON line")
     ap.add_argument("--fuse-baby", type=int, default=-1,
                     help="1: baby rotations computed inside the multiply-accumulate, 0: written by their own launch "
                          "(default: the plan's default tune)")
@@ -606,6 +611,121 @@ ALU_PROBES = {0: "v_add_u32", 1: "v_mul_lo_u32", 2: "v_mul_hi_u32", 3: "v_mad_u6
               6: "v_lshl_add_u64", 7: "v_lshrrev_b64", 5: "ntt_butterfly", 8: "mac_product"}
 
 
+# The paper's own pipeline (RLWE over Z_{2^64}[X]/Phi_M): its 8-bit parameter set
+# (M = 3^7, gadget D = 2^9, l = 3, p = 2^8) with packs of phi(3^6) = 486 outputs.
+NATIVE = {"t": 3, "alpha": 7, "beta": 6, "log_d": 9, "l": 3, "log_p": 8}
+# 64-bit products per key-switch product in the packing GEMM's inner loop (gfx950
+# assembly of k_nat_ksprod: one v_mad_u64_u32 on the key's low word, one v_mul_lo_u32 on
+# its high word and half a v_add3_u32 per product: 327 VALU per 128 products)
+NAT_KS_VALU_OPS = 327 / 128
+PEAK_NAT_KS = ALU_LANE_OPS / NAT_KS_VALU_OPS / 1e12
+
+
+def resnet20_layers() -> list:
+    """The linear layers of ResNet-20 on CIFAR-10 (32x32x3): a 3x3 stem, three stages of
+    three basic blocks (16, 32, 64 channels; the first convolution of stages 2 and 3
+    has stride 2 and a 1x1 stride-2 projection on the skip path), FC 64 -> 10 after the
+    client's average pooling: (c_in, c_out, h, w, k, stride), the FC as a 1x1
+    convolution on a 1x1 input."""
+    L = [(3, 16, 32, 32, 3, 1)] + [(16, 16, 32, 32, 3, 1)] * 6
+    for c_in, c, h in ((16, 32, 32), (32, 64, 16)):
+        L += [(c_in, c, h, h, 3, 2), (c_in, c, h, h, 1, 2)] + [(c, c, h // 2, h // 2, 3, 1)] * 5
+    return L + [(64, 10, 1, 1, 1, 1)]
+
+
+def native_bench(gamma: int, reps: int = 2) -> dict:
+    """Server compute of one ResNet-20 inference under the paper's own pipeline at its
+    8-bit parameter set and extraction level gamma: per layer, partial trace extraction
+    of the input chunks (ceil(E / N) chunks of phi(t^gamma) encrypted powers), the
+    convolution on the extracted rows (4-bit weights, the round's shuffle as the output
+    rows' order) and fast packing of the outputs (486 per packed ciphertext).
+    Keys and input ciphertexts are uniform (RLWE samples are indistinguishable from
+    uniform, so the cost is the same).  Times: HIP events on the launch stream, best of
+    `reps` passes after a warm-up pass; per-kernel-class rooflines from the pipeline's own
+    profiler over one more pass."""
+    import torch
+
+    from paper_2509_01253_amd import fhelin as F
+
+    c = NATIVE
+    t, alpha, beta = c["t"], c["alpha"], c["beta"]
+    M = t ** alpha
+    N = M - M // t
+    n_pack = (t - 1) * t ** (beta - 1)
+    phig = (t - 1) * t ** (gamma - 1)
+    nt = F.fhelin_native_create(t, alpha, gamma, beta, c["log_d"], c["l"], c["log_p"])
+    rng = np.random.default_rng(20 + gamma)
+    gen = torch.Generator(device="cuda").manual_seed(20 + gamma)
+
+    def uniform(*shape):
+        return torch.randint(-2 ** 63, 2 ** 63 - 1, shape, dtype=torch.int64, device="cuda", generator=gen)
+
+    F.fhelin_native_keys_load(nt, uniform(alpha - gamma, c["l"], 2, N))
+    layers = []
+    for (c_in, c_out, h, w, k, stride) in resnet20_layers():
+        E = c_in * h * w
+        n_out = c_out * ((h - 1) // stride + 1) * ((w - 1) // stride + 1)
+        n_chunks = (E + N - 1) // N
+        wts = rng.integers(-8, 8, (c_out, c_in, k, k)).astype(np.int32)
+        layers.append(dict(
+            shape=(c_in, c_out, h, w, k, stride), E=E, n_out=n_out, n_chunks=n_chunks,
+            wts=torch.from_numpy(wts).cuda(), out_row=torch.from_numpy(rng.permutation(n_out).astype(np.int32)).cuda(),
+            chunks=uniform(n_chunks, phig, 2, N), rows=torch.empty((n_chunks * N, 2, N), dtype=torch.int64, device="cuda"),
+            out=torch.empty((n_out, 2, N), dtype=torch.int64, device="cuda"),
+            packed=torch.empty(((n_out + n_pack - 1) // n_pack, 2, N), dtype=torch.int64, device="cuda")))
+
+    def run_pass():
+        ev = []
+        for L in layers:
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+            e[0].record()
+            F.fhelin_native_extract(nt, L["chunks"], L["rows"])
+            e[1].record()
+            F.fhelin_native_conv(nt, *L["shape"], L["wts"], L["out_row"], L["rows"], L["out"])
+            e[2].record()
+            F.fhelin_native_pack(nt, L["out"], L["packed"])
+            e[3].record()
+            ev.append(e)
+        torch.cuda.synchronize()
+        return [(a.elapsed_time(b), b.elapsed_time(cc), cc.elapsed_time(d)) for a, b, cc, d in ev]
+
+    run_pass()
+    best = None
+    for _ in range(reps):
+        r = run_pass()
+        if best is None or sum(map(sum, r)) < sum(map(sum, best)):
+            best = r
+    F.fhelin_native_profile_enable(nt, True)
+    run_pass()
+    roof = {}
+    for kname, bound in (("ksprod", "alu"), ("extract", "hbm"), ("linear", "hbm"), ("aut_decomp", "hbm"),
+                         ("merge", "hbm"), ("leaves", "hbm")):
+        n_l, ms_k, units, byts = F.fhelin_native_profile_read(nt, kname)
+        if n_l == 0 or ms_k <= 0:
+            continue
+        if bound == "alu":
+            ach, peak, unit = units / (ms_k / 1e3) / 1e12, PEAK_NAT_KS, "T 64-bit products/s"
+        else:
+            ach, peak, unit = byts / (ms_k / 1e3) / 1e9, HBM_PEAK_GBPS, "GB/s"
+        roof[kname] = {"bound": bound, "achieved": round(ach, 4), "peak": round(peak, 4), "unit": unit,
+                       "frac": round(ach / peak, 4), "launches": n_l, "ms_per_inference": round(ms_k, 3),
+                       "avg_launch_ms": round(ms_k / n_l, 4)}
+    F.fhelin_native_profile_enable(nt, False)
+    F.fhelin_native_destroy(nt)
+    tot = [sum(x[i] for x in best) for i in range(3)]
+    packs = sum(L["packed"].shape[0] for L in layers)
+    ks = packs * (t ** (beta - gamma) - 1 + (alpha - beta) * (t - 1))
+    ms = sum(tot)
+    return {"workload": f"ResNet-20 / CIFAR-10 linear layers ({len(layers)}: 21 convolutions incl. two 1x1 "
+                        f"projections, FC 64->10), paper's 8-bit set: M = 3^7, N = {N}, D = 2^9, l = 3, p = 2^8, "
+                        f"gamma = {gamma}, beta = {beta} ({n_pack} outputs per packed ciphertext), 4-bit weights, "
+                        f"uniform keys and inputs",
+            "gamma": gamma, "per_inference_ms": round(ms, 3), "inferences_per_s": round(1e3 / ms, 3),
+            "extract_ms": round(tot[0], 3), "linear_ms": round(tot[1], 3), "pack_ms": round(tot[2], 3),
+            "packed_ciphertexts": packs, "key_switches": ks, "key_switches_per_s": round(ks / (tot[2] / 1e3), 1),
+            "rooflines": roof, "dominant": max(roof, key=lambda k: roof[k]["ms_per_inference"]) if roof else None}
+
+
 def alu_rates(F) -> dict:
     """Clocks per wave-level instruction on one SIMD for the instructions the NTT and
     multiply-accumulate kernels are built from, and the rate of the register-resident
@@ -642,6 +762,9 @@ def main():
         return
     if args.alu_rates:
         print(json.dumps(alu_rates(F)), flush=True)
+        return
+    if args.native > 0:
+        print(json.dumps({"native_resnet20": native_bench(args.native)}), flush=True)
         return
     if args.calib_copy > 0:
         n = int(args.calib_copy * (1 << 30)) // 8
@@ -861,6 +984,8 @@ def main():
         rn = resnet18_bench(rargs)
         res["resnet18"] = {k: rn[k] for k in ("workload", "inferences_per_batch", "stack_ms", "inferences_per_s")}
         res["resnet18"]["per_inference_ms"] = round(rn["stack_ms"] / rn["inferences_per_batch"], 3)
+    if args.with_native:
+        res["native_resnet20"] = [native_bench(g) for g in (1, 2)]
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(args.cpu_level, args.n1, args.schedule == "hoisted")
         res["cpu_baseline"]["other_workloads"] = cpu_baseline_more()

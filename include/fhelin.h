@@ -464,6 +464,18 @@ int fhelin_native_extract(fhelin_native *nt, const uint64_t *chunks, int32_t n_c
 int fhelin_native_linear(fhelin_native *nt, const int32_t *row_ptr, const int32_t *col, const int32_t *val,
                          int32_t n_out, const uint64_t *rows, uint64_t *out, void *stream);
 
+/* The same layer for a convolution (Sec. 4.4 "Convolution": the server reshapes the
+ * rows to H x W x C_in and convolves with the rows' coefficients as the batch):
+ * rows [c_in h w][2][N] in channels-last order (row (y w + x) c_in + ci), weights
+ * [c_out][c_in][k][k] int32 device array, k odd, zero padding k / 2, the given
+ * stride; output (position p = y' w' + x', channel co), w' = (w - 1) / stride + 1,
+ * goes to out row out_row[p c_out + co] (the shuffle; a permutation of
+ * [0, c_out h' w')).  An FC layer is the case h = w = k = 1.  Indices are not
+ * checked on the device. */
+int fhelin_native_conv(fhelin_native *nt, int32_t c_in, int32_t c_out, int32_t h, int32_t w, int32_t k,
+                       int32_t stride, const int32_t *weights, const int32_t *out_row, const uint64_t *rows,
+                       uint64_t *out, void *stream);
+
 /* Fast packing (Sec. 2.4, 4.4): rows [n_rows][2][N], each with trace down to
  * K_gamma decrypting to a scalar y_o, into packed [ceil(n_rows / phi(t^beta))][2][N]
  * encrypting sum_o y_o X^(o M / t^beta) (rows past n_rows count as zero).  Uses
@@ -473,6 +485,17 @@ int fhelin_native_linear(fhelin_native *nt, const int32_t *row_ptr, const int32_
  * the stream); calls that share the handle must not overlap in time. */
 int fhelin_native_pack(fhelin_native *nt, const uint64_t *rows, int32_t n_rows, uint64_t *packed, void *stream);
 int fhelin_native_pack_workspace(const fhelin_native *nt, int32_t n_rows, uint64_t *bytes);
+
+/* Per-kernel-class timing of the native pipeline (HIP events around every launch on
+ * its stream while enabled; enabling or disabling clears the sums).  Classes:
+ * "extract", "linear", "leaves", "merge", "aut_decomp", "ksprod" (the key-switch
+ * products, units = 64-bit products), "kmat" (key load).  read waits for the
+ * recorded launches and returns launches, total ms, work units and the byte model
+ * of each class (any output pointer may be NULL).  While enabled, a linear call
+ * reads its nonzero count back from the device (a host synchronisation). */
+int fhelin_native_profile_enable(fhelin_native *nt, int32_t enable);
+int fhelin_native_profile_read(fhelin_native *nt, const char *kernel, int64_t *launches, double *ms, double *units,
+                               double *bytes);
 
 const char *fhelin_last_error(void);
 const char *fhelin_status_string(int status);

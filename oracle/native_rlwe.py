@@ -275,6 +275,27 @@ def linear_rows(W: np.ndarray, rows: np.ndarray) -> np.ndarray:
     return out
 
 
+def conv_matrix(c_in: int, c_out: int, h: int, w: int, k: int, stride: int, wts: np.ndarray) -> np.ndarray:
+    """The integer matrix of a convolution over channels-last flattened inputs (index
+    (y w + x) c_in + ci), zero padding k // 2: row (position p = y' w' + x', channel co),
+    w' = (w - 1) // stride + 1, holds wts[co][ci][dy][dx] at the window's inputs (the
+    paper's remark that a convolution is a matrix-vector product with its Toeplitz
+    matrix, Sec. 4.4)."""
+    ho, wo = (h - 1) // stride + 1, (w - 1) // stride + 1
+    W = np.zeros((ho * wo * c_out, h * w * c_in), np.int64)
+    for yo in range(ho):
+        for xo in range(wo):
+            for co in range(c_out):
+                r = (yo * wo + xo) * c_out + co
+                for dy in range(k):
+                    for dx in range(k):
+                        y, x = stride * yo + dy - k // 2, stride * xo + dx - k // 2
+                        if 0 <= y < h and 0 <= x < w:
+                            for ci in range(c_in):
+                                W[r, (y * w + x) * c_in + ci] += wts[co, ci, dy, dx]
+    return W
+
+
 def pack(P: NativeParams, rows: np.ndarray, keys: dict, count: list | None = None) -> np.ndarray:
     """Fast packing of phi(t^beta) rows (fewer are zero-padded) into one ciphertext of
     sum_o y_o X^(o M / t^beta).  `count`, if given, gets the number of key switches."""

@@ -760,12 +760,39 @@ FHELIN_EXPORT int fhelin_native_linear(fhelin_native *nt, const int32_t *row_ptr
     API_END
 }
 
+FHELIN_EXPORT int fhelin_native_conv(fhelin_native *nt, int32_t c_in, int32_t c_out, int32_t h, int32_t w, int32_t k,
+                                     int32_t stride, const int32_t *weights, const int32_t *out_row,
+                                     const uint64_t *rows, uint64_t *out, void *stream) {
+    API_BEGIN FL_LIVE(H_NATIVE, nt);
+    Native *n = (Native *)nt;
+    DeviceGuard g(n->device);
+    return native_conv(n, c_in, c_out, h, w, k, stride, weights, out_row, rows, out, (hipStream_t)stream);
+    API_END
+}
+
 FHELIN_EXPORT int fhelin_native_pack(fhelin_native *nt, const uint64_t *rows, int32_t n_rows, uint64_t *packed,
                                      void *stream) {
     API_BEGIN FL_LIVE(H_NATIVE, nt);
     Native *n = (Native *)nt;
     DeviceGuard g(n->device);
     return native_pack(n, rows, n_rows, packed, (hipStream_t)stream);
+    API_END
+}
+
+FHELIN_EXPORT int fhelin_native_profile_enable(fhelin_native *nt, int32_t enable) {
+    API_BEGIN FL_LIVE(H_NATIVE, nt);
+    Native *n = (Native *)nt;
+    DeviceGuard g(n->device);
+    return native_profile_enable(n, enable != 0);
+    API_END
+}
+
+FHELIN_EXPORT int fhelin_native_profile_read(fhelin_native *nt, const char *kernel, int64_t *launches, double *ms,
+                                             double *units, double *bytes) {
+    API_BEGIN FL_LIVE(H_NATIVE, nt);
+    Native *n = (Native *)nt;
+    DeviceGuard g(n->device);
+    return native_profile_read(n, kernel, launches, ms, units, bytes);
     API_END
 }
 

@@ -9,6 +9,10 @@ namespace fl {
 constexpr int NAT_MAX_M = 8192;  // M = t^alpha
 constexpr int NAT_MAX_POW = 64;  // powers m(X^d) per chunk: phi(t^gamma)
 
+// kernel classes of the native pipeline's profiler
+enum NatKind : int { NK_EXTRACT = 0, NK_LINEAR, NK_LEAVES, NK_MERGE, NK_AUT_DECOMP, NK_KSPROD, NK_KMAT, NK_COUNT };
+extern const char *const NAT_KIND_NAMES[NK_COUNT];
+
 struct Native {
     fhelin_native_params prm{};
     int M = 0, N = 0, Mt = 0;
@@ -24,7 +28,31 @@ struct Native {
     bool keys = false;
     void *ws = nullptr;
     size_t ws_bytes = 0;
+    // profiler: HIP events around every launch while enabled (not under graph capture)
+    struct Rec {
+        int kind;
+        hipEvent_t a, b;
+        double units, bytes;
+    };
+    bool prof = false;
+    std::vector<Rec> pending;
+    double sum_ms[NK_COUNT] = {}, sum_units[NK_COUNT] = {}, sum_bytes[NK_COUNT] = {};
+    int64_t launches[NK_COUNT] = {};
 };
+
+// brackets one launch with events while the handle's profiler is on
+struct NatProf {
+    Native *n;
+    hipStream_t s;
+    int kind;
+    double units, bytes;
+    hipEvent_t a{};
+    bool on = false;
+    NatProf(Native *n_, hipStream_t s_, int k, double u, double by);
+    ~NatProf();
+};
+int native_profile_enable(Native *n, bool on);
+int native_profile_read(Native *n, const char *kind, int64_t *launches, double *ms, double *units, double *bytes);
 
 int native_create(const fhelin_native_params *prm, Native **out);
 void native_destroy(Native *n);
@@ -32,6 +60,8 @@ int native_keys_load(Native *n, const uint64_t *ksk, hipStream_t s);
 int native_extract(Native *n, const uint64_t *pows, int n_chunks, uint64_t *rows, hipStream_t s);
 int native_linear(Native *n, const int32_t *row_ptr, const int32_t *col, const int32_t *val, int n_out,
                   const uint64_t *rows, uint64_t *out, hipStream_t s);
+int native_conv(Native *n, int c_in, int c_out, int h, int w, int k, int stride, const int32_t *wts,
+                const int32_t *out_row, const uint64_t *rows, uint64_t *out, hipStream_t s);
 size_t native_pack_workspace(const Native *n, int n_rows);
 int native_pack(Native *n, const uint64_t *rows, int n_rows, uint64_t *packed, hipStream_t s);
 

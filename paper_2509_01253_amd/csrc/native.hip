@@ -161,22 +161,30 @@ __global__ void __launch_bounds__(256) k_nat_merge_v(const uint64_t *__restrict_
     o[dm.N + j] = a1;
 }
 
-// automorphism + gadget digits of a batch: grid (ceil(N / 256), n); S [n] (es apart),
-// digits [n][l][N] (offset by D/2, < D), bp [n][N] = sigma(b)
+// automorphism + gadget digits of a batch, and the output's start value: grid
+// (ceil(N / 256), n); S [n] (s_es apart); digits [n][l][N] (offset by D/2, < D);
+// out[c] = (add_a + corr_a, add_b + sigma(b) + corr_b), to which the product kernel
+// adds -sum_k A K.  out must not overlap S or add.
 __global__ void __launch_bounds__(256) k_nat_aut_decomp(const uint64_t *__restrict__ S, int64_t s_es,
-                                                        uint32_t *__restrict__ dig, uint64_t *__restrict__ bp,
+                                                        const uint64_t *__restrict__ add, int64_t add_es,
+                                                        uint64_t *__restrict__ out, int64_t out_es,
+                                                        const uint64_t *__restrict__ corr_a,
+                                                        const uint64_t *__restrict__ corr_b, uint32_t *__restrict__ dig,
                                                         NatDims dm, int ginv, int log_d, int l) {
     const int j = blockIdx.x * 256 + threadIdx.x;
     if (j >= dm.N) return;
     const int c = blockIdx.y;
     const uint64_t *a = S + c * s_es, *b = a + dm.N;
-    const uint64_t av = aut_at(a, j, ginv, dm);
-    bp[(int64_t)c * dm.N + j] = aut_at(b, j, ginv, dm);
+    const uint64_t av = aut_at(a, j, ginv, dm), bv = aut_at(b, j, ginv, dm);
+    const uint64_t *ad = add + c * add_es;
+    uint64_t *o = out + c * out_es;
+    o[j] = ad[j] + corr_a[j];
+    o[dm.N + j] = ad[dm.N + j] + bv + corr_b[j];
     // round to the top l log_d bits, then balanced digits from the least significant
     const int bits = log_d * l, sh = 64 - bits;
     uint64_t top = (av >> sh) + ((av >> (sh - 1)) & 1);  // < 2^bits + 1; a carry past the top wraps
     const uint64_t D = 1ull << log_d, mask = D - 1;
-    uint32_t *o = dig + (int64_t)c * l * dm.N + j;
+    uint32_t *dg = dig + (int64_t)c * l * dm.N + j;
     for (int i = l - 1; i >= 0; --i) {
         int64_t d = (int64_t)(top & mask);
         top >>= log_d;
@@ -184,26 +192,26 @@ __global__ void __launch_bounds__(256) k_nat_aut_decomp(const uint64_t *__restri
             d -= (int64_t)D;
             top += 1;
         }
-        o[(int64_t)i * dm.N] = (uint32_t)(d + (int64_t)(D >> 1));
+        dg[(int64_t)i * dm.N] = (uint32_t)(d + (int64_t)(D >> 1));
     }
 }
 
-// C = A K^T for both key parts, plus the addend: out[c][p][j] = add[c][p][j] (+ bp[c][j]
-// for p = 1) - (sum_k A[c][k] K_p[j][k] - corr_p[j]), A[c][k] = digit + D/2 < 2^16,
-// corr_p[j] = (D/2) sum_k K_p[j][k].  Each product: v_mad_u64_u32 on the low key word and
-// a 32-bit multiply-add of the high word (the sum is needed modulo 2^64 only).
-// Tile: 32 ciphertexts x 128 coefficients per workgroup, thread (tc, tj) owns
-// ciphertexts tc, tc + 16 and coefficients tj + 16 q (q < 8); K chunks of 16 staged in LDS.
+// out[c][p][j] -= sum_k A[c][k] K_p[j][k] (mod 2^64) for both key parts, A[c][k] = digit +
+// D/2 < 2^16 (the offset is removed by corr_p[j] = (D/2) sum_k K_p[j][k], added by the
+// digits kernel).  Each product: v_mad_u64_u32 on the key's low word and a 32-bit
+// multiply-add of its high word.  Tile: 32 ciphertexts x 128 coefficients per workgroup,
+// thread (tc, tj) owns ciphertexts tc, tc + 16 and coefficients tj + 16 q (q < 8); K
+// chunks of 16 staged in LDS.  grid.z splits K into slices of kc (small batches): the
+// slices' sums are added with 64-bit atomics (exact modulo 2^64 in any order).
 constexpr int KS_TC = 32, KS_TJ = 128, KS_TK = 16;
 
 __global__ void __launch_bounds__(256) k_nat_ksprod(const uint32_t *__restrict__ A, const uint64_t *__restrict__ Ka,
-                                                    const uint64_t *__restrict__ Kb, const uint64_t *__restrict__ corr_a,
-                                                    const uint64_t *__restrict__ corr_b, const uint64_t *__restrict__ bp,
-                                                    const uint64_t *__restrict__ add, int64_t add_es,
-                                                    uint64_t *__restrict__ out, int64_t out_es, int n, int N, int KD) {
+                                                    const uint64_t *__restrict__ Kb, uint64_t *__restrict__ out,
+                                                    int64_t out_es, int n, int N, int KD, int kc) {
     __shared__ uint32_t As[KS_TK][KS_TC + 1];
     __shared__ uint64_t Ks[2][KS_TK][KS_TJ + 1];
     const int c0 = blockIdx.y * KS_TC, j0 = blockIdx.x * KS_TJ;
+    const int kb = blockIdx.z * kc, ke = min(KD, kb + kc);
     const int tc = threadIdx.x >> 4, tj = threadIdx.x & 15;
     uint64_t lo[2][2][8];
     uint32_t hi[2][2][8];
@@ -216,19 +224,19 @@ __global__ void __launch_bounds__(256) k_nat_ksprod(const uint32_t *__restrict__
                 lo[p][x][q] = 0;
                 hi[p][x][q] = 0;
             }
-    for (int k0 = 0; k0 < KD; k0 += KS_TK) {
+    for (int k0 = kb; k0 < ke; k0 += KS_TK) {
         __syncthreads();
         // A tile: 32 x 16 digits (two per thread)
         for (int e = threadIdx.x; e < KS_TC * KS_TK; e += 256) {
             const int cc = e / KS_TK, kk = e % KS_TK;
             const int c = c0 + cc, k = k0 + kk;
-            As[kk][cc] = c < n && k < KD ? A[(int64_t)c * KD + k] : 0u;
+            As[kk][cc] = c < n && k < ke ? A[(int64_t)c * KD + k] : 0u;
         }
         // K tiles: 128 x 16 per part
         for (int e = threadIdx.x; e < KS_TJ * KS_TK; e += 256) {
             const int jj = e / KS_TK, kk = e % KS_TK;
             const int j = j0 + jj, k = k0 + kk;
-            const bool ok = j < N && k < KD;
+            const bool ok = j < N && k < ke;
             Ks[0][kk][jj] = ok ? Ka[(int64_t)j * KD + k] : 0;
             Ks[1][kk][jj] = ok ? Kb[(int64_t)j * KD + k] : 0;
         }
@@ -251,22 +259,64 @@ __global__ void __launch_bounds__(256) k_nat_ksprod(const uint32_t *__restrict__
             }
         }
     }
+    const bool split = gridDim.z > 1;
 #pragma unroll
     for (int x = 0; x < 2; ++x) {
         const int c = c0 + tc + 16 * x;
         if (c >= n) continue;
+        uint64_t *o = out + c * out_es;
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int j = j0 + tj + 16 * q;
             if (j >= N) continue;
-            const uint64_t sa = lo[0][x][q] + ((uint64_t)hi[0][x][q] << 32) - corr_a[j];
-            const uint64_t sb = lo[1][x][q] + ((uint64_t)hi[1][x][q] << 32) - corr_b[j];
-            const uint64_t *ad = add + c * add_es;
-            uint64_t *o = out + c * out_es;
-            o[j] = ad[j] - sa;
-            o[N + j] = ad[N + j] + bp[(int64_t)c * N + j] - sb;
+#pragma unroll
+            for (int p = 0; p < 2; ++p) {
+                const uint64_t sum = lo[p][x][q] + ((uint64_t)hi[p][x][q] << 32);
+                uint64_t *dst = o + p * N + j;
+                if (split) atomicAdd((unsigned long long *)dst, (unsigned long long)(0 - sum));
+                else *dst -= sum;
+            }
         }
     }
+}
+
+// convolution on rows (channels-last inputs, index (y w + x) c_in + ci; zero padding
+// k / 2): computed output (position, co) = sum over the window of wts[co][ci][dy][dx]
+// times input row, written to out row out_row[position c_out + co] (the shuffle).  A
+// thread owns one of the 2N columns and 16 output channels: each input value is read
+// once for all 16.  grid (ceil(2N / 256), output positions, ceil(c_out / 16)).
+constexpr int CONV_CO = 16;
+
+__global__ void __launch_bounds__(256) k_nat_conv(const uint64_t *__restrict__ rows, const int32_t *__restrict__ wts,
+                                                  const int32_t *__restrict__ out_row, uint64_t *__restrict__ out,
+                                                  int c_in, int c_out, int h, int w, int k, int stride, int wo,
+                                                  int n2) {
+    const int col = blockIdx.x * 256 + threadIdx.x;
+    if (col >= n2) return;
+    const int pos = blockIdx.y, yo = pos / wo, xo = pos % wo, co0 = blockIdx.z * CONV_CO;
+    const int nco = min(CONV_CO, c_out - co0);
+    uint64_t acc[CONV_CO];
+#pragma unroll
+    for (int q = 0; q < CONV_CO; ++q) acc[q] = 0;
+    for (int dy = 0; dy < k; ++dy) {
+        const int y = stride * yo + dy - k / 2;
+        if (y < 0 || y >= h) continue;
+        for (int dx = 0; dx < k; ++dx) {
+            const int x = stride * xo + dx - k / 2;
+            if (x < 0 || x >= w) continue;
+            const uint64_t *in = rows + ((int64_t)(y * w + x) * c_in) * n2 + col;
+            for (int ci = 0; ci < c_in; ++ci) {
+                const uint64_t v = in[(int64_t)ci * n2];
+                const int32_t *wp = wts + ((int64_t)co0 * c_in + ci) * k * k + dy * k + dx;
+#pragma unroll
+                for (int q = 0; q < CONV_CO; ++q)
+                    if (q < nco) acc[q] += (uint64_t)(int64_t)wp[(int64_t)q * c_in * k * k] * v;
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < CONV_CO; ++q)
+        if (q < nco) out[(int64_t)out_row[pos * c_out + co0 + q] * n2 + col] = acc[q];
 }
 
 // key product matrices: K[lv][p][j][i N + m] = coefficient j of X^m k_(lv, i, p);
@@ -301,6 +351,69 @@ __global__ void __launch_bounds__(256) k_nat_kcorr(const uint64_t *__restrict__ 
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
+const char *const NAT_KIND_NAMES[NK_COUNT] = {"extract", "linear", "leaves", "merge", "aut_decomp", "ksprod", "kmat"};
+
+NatProf::NatProf(Native *n_, hipStream_t s_, int k, double u, double by) : n(n_), s(s_), kind(k), units(u), bytes(by) {
+    if (!n->prof) return;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
+    if (hipEventCreate(&a) != hipSuccess) return;
+    if (hipEventRecord(a, s) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return;
+    }
+    on = true;
+}
+
+NatProf::~NatProf() {
+    if (!on) return;
+    hipEvent_t b;
+    if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return;
+    }
+    (void)hipEventRecord(b, s);
+    n->pending.push_back(Native::Rec{kind, a, b, units, bytes});
+}
+
+static void nat_prof_drain(Native *n) {
+    for (auto &r : n->pending) {
+        float ms = 0;
+        if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+            n->sum_ms[r.kind] += ms;
+            n->sum_units[r.kind] += r.units;
+            n->sum_bytes[r.kind] += r.bytes;
+            n->launches[r.kind] += 1;
+        }
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    n->pending.clear();
+}
+
+int native_profile_enable(Native *n, bool on) {
+    nat_prof_drain(n);
+    for (int k = 0; k < NK_COUNT; ++k) {
+        n->sum_ms[k] = n->sum_units[k] = n->sum_bytes[k] = 0;
+        n->launches[k] = 0;
+    }
+    n->prof = on;
+    return FHELIN_OK;
+}
+
+int native_profile_read(Native *n, const char *kind, int64_t *launches, double *ms, double *units, double *bytes) {
+    FL_CHECK(kind, FHELIN_E_INVALID_ARG, "null kernel class");
+    nat_prof_drain(n);
+    for (int k = 0; k < NK_COUNT; ++k) {
+        if (std::strcmp(kind, NAT_KIND_NAMES[k]) != 0) continue;
+        if (launches) *launches = n->launches[k];
+        if (ms) *ms = n->sum_ms[k];
+        if (units) *units = n->sum_units[k];
+        if (bytes) *bytes = n->sum_bytes[k];
+        return FHELIN_OK;
+    }
+    return set_error(FHELIN_E_INVALID_ARG, std::string("unknown native kernel class: ") + kind);
+}
 static bool is_odd_prime(int t) {
     if (t < 3 || t % 2 == 0) return false;
     for (int f = 3; f * f <= t; f += 2)
@@ -375,6 +488,7 @@ void native_destroy(Native *n) {
     if (!n) return;
     (void)hipSetDevice(n->device);
     (void)hipDeviceSynchronize();
+    nat_prof_drain(n);
     if (n->kmat) (void)hipFree(n->kmat);
     if (n->kcorr) (void)hipFree(n->kcorr);
     if (n->ws) (void)hipFree(n->ws);
@@ -417,12 +531,15 @@ int native_keys_load(Native *n, const uint64_t *ksk, hipStream_t s) {
         }
     }
     const NatDims dm = dims(n);
+    {
+    NatProf ps(n, s, NK_KMAT, (double)levels * 2 * n->N * KD, (double)kbytes + levels * l * 2.0 * n->N * 8);
     hipLaunchKernelGGL(k_nat_kmat, dim3((n->N + 255) / 256, (unsigned)KD, levels * 2), dim3(256), 0, s, ksk, n->kmat, dm,
                        l);
     FL_TRY_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_nat_kcorr, dim3(levels * 2 * n->N), dim3(256), 0, s, n->kmat, n->kcorr, KD,
                        (uint64_t)1 << (n->prm.log_d - 1));
     FL_TRY_HIP(hipGetLastError());
+    }
     n->keys = true;
     return FHELIN_OK;
 }
@@ -434,6 +551,9 @@ int native_extract(Native *n, const uint64_t *pows, int n_chunks, uint64_t *rows
     NatPowers pw{};
     pw.n = (int)n->powers.size();
     for (int k = 0; k < pw.n; ++k) pw.d[k] = n->powers[k];
+    // bytes: the chunks' powers read once, the rows written
+    const double ctb = 16.0 * n->N;
+    NatProf ps(n, s, NK_EXTRACT, (double)n_chunks * n->N, n_chunks * (pw.n * ctb + (double)n->N * ctb));
     hipLaunchKernelGGL(k_nat_extract, dim3((n->N + 255) / 256, n->N, n_chunks), dim3(256), 0, s, pows, rows, dims(n), pw,
                        n->u);
     FL_TRY_HIP(hipGetLastError());
@@ -447,6 +567,11 @@ int native_linear(Native *n, const int32_t *row_ptr, const int32_t *col, const i
     FL_CHECK(n_out <= 65535, FHELIN_E_INVALID_ARG, "native_linear: at most 65535 outputs per call");
     if (n_out == 0) return FHELIN_OK;
     const int n2 = 2 * n->N;
+    // units: products; bytes: every referenced row once and the outputs (the rows shared
+    // between outputs are read again from the caches)
+    int32_t nnz = 0;
+    if (n->prof) FL_TRY_HIP(hipMemcpy(&nnz, row_ptr + n_out, sizeof(nnz), hipMemcpyDeviceToHost));
+    NatProf ps(n, s, NK_LINEAR, (double)nnz * n2, (double)n_out * n2 * 8.0);
     hipLaunchKernelGGL(k_nat_linear, dim3((n2 + 255) / 256, n_out), dim3(256), 0, s, row_ptr, col, val, rows, out, n2);
     FL_TRY_HIP(hipGetLastError());
     return FHELIN_OK;
@@ -456,16 +581,15 @@ size_t native_pack_workspace(const Native *n, int n_rows) {
     const size_t packs = (size_t)(n_rows + n->n_pack - 1) / n->n_pack;
     const size_t ct = 2 * (size_t)n->N * sizeof(uint64_t);
     const size_t nmax = packs * n->T;  // the leaves: the widest level
-    // current sub-packs, merge terms (t per merge), results, and the digits and sigma(b)
-    // of a key-switch batch
-    return 3 * nmax * ct + nmax * (size_t)n->prm.l * n->N * sizeof(uint32_t) + nmax * n->N * sizeof(uint64_t);
+    // current sub-packs, merge terms (t per merge), results, and the digits of a
+    // key-switch batch
+    return 3 * nmax * ct + nmax * (size_t)n->prm.l * n->N * sizeof(uint32_t);
 }
 
-// S_out = add + tau(S_in) for a batch of cnt ciphertexts with the key of tower level lv.
-// S_out may be S_in: the digits kernel reads S_in completely before the product kernel
-// writes S_out (same stream).
+// out = add + tau(S) for a batch of cnt ciphertexts with the key of tower level lv; out
+// overlaps neither S nor add.
 static int nat_ks_step(Native *n, int lv, const uint64_t *S, int64_t s_es, const uint64_t *add, int64_t add_es,
-                       uint64_t *out, int64_t out_es, int cnt, uint32_t *dig, uint64_t *bp, hipStream_t s) {
+                       uint64_t *out, int64_t out_es, int cnt, uint32_t *dig, hipStream_t s) {
     const NatDims dm = dims(n);
     const int l = n->prm.l;
     const int64_t KD = (int64_t)l * n->N;
@@ -473,11 +597,24 @@ static int nat_ks_step(Native *n, int lv, const uint64_t *S, int64_t s_es, const
     const uint64_t *ca = n->kcorr + (int64_t)lv * 2 * n->N, *cb = ca + n->N;
     for (int c0 = 0; c0 < cnt; c0 += 65535) {
         const int c = std::min(cnt - c0, 65535);
-        hipLaunchKernelGGL(k_nat_aut_decomp, dim3((n->N + 255) / 256, c), dim3(256), 0, s, S + c0 * s_es, s_es, dig, bp,
-                           dm, n->tau_inv[lv], n->prm.log_d, l);
-        FL_TRY_HIP(hipGetLastError());
-        hipLaunchKernelGGL(k_nat_ksprod, dim3((n->N + KS_TJ - 1) / KS_TJ, (c + KS_TC - 1) / KS_TC), dim3(256), 0, s, dig,
-                           Ka, Kb, ca, cb, bp, add + c0 * add_es, add_es, out + c0 * out_es, out_es, c, n->N, (int)KD);
+        {
+            NatProf pa(n, s, NK_AUT_DECOMP, (double)c * n->N, (double)c * n->N * (2 * 8.0 + 2 * 8.0 + 2 * 8.0 + 4.0 * l));
+            hipLaunchKernelGGL(k_nat_aut_decomp, dim3((n->N + 255) / 256, c), dim3(256), 0, s, S + c0 * s_es, s_es,
+                               add + c0 * add_es, add_es, out + c0 * out_es, out_es, ca, cb, dig, dm, n->tau_inv[lv],
+                               n->prm.log_d, l);
+            FL_TRY_HIP(hipGetLastError());
+        }
+        // a small batch splits K so that about 1024 workgroups run
+        const int gx = (n->N + KS_TJ - 1) / KS_TJ, gy = (c + KS_TC - 1) / KS_TC;
+        const int splits = std::max(1, std::min(16, 1024 / (gx * gy)));
+        const int kc = (int)(((KD + splits - 1) / splits + KS_TK - 1) / KS_TK * KS_TK);
+        const int gz = (int)((KD + kc - 1) / kc);
+        // units: 64-bit products (both key parts); bytes: digits, both key matrices (once
+        // per launch) and the output read and written
+        NatProf pk(n, s, NK_KSPROD, 2.0 * c * n->N * (double)KD,
+                   (double)c * KD * 4 + 2.0 * n->N * KD * 8 + (double)c * n->N * 8 * 4);
+        hipLaunchKernelGGL(k_nat_ksprod, dim3(gx, gy, gz), dim3(256), 0, s, dig, Ka, Kb, out + c0 * out_es, out_es, c, n->N,
+                           (int)KD, kc);
         FL_TRY_HIP(hipGetLastError());
     }
     return FHELIN_OK;
@@ -497,42 +634,78 @@ int native_pack(Native *n, const uint64_t *rows, int n_rows, uint64_t *packed, h
     const int64_t nmax = (int64_t)packs * n->T;
     uint64_t *cur = (uint64_t *)ws, *v = cur + nmax * ct, *S = v + nmax * ct;
     uint32_t *dig = (uint32_t *)(S + nmax * ct);
-    uint64_t *bp = (uint64_t *)(dig + nmax * n->prm.l * n->N);
     const unsigned gx = (n->N + 255) / 256;
     // leaves
-    hipLaunchKernelGGL(k_nat_leaves, dim3(gx, n->T, packs), dim3(256), 0, s, rows, n_rows, cur, dm, n->n_pack, n->T,
-                       n->phig, (int)(n->M / ipow(t, n->prm.gamma)));
-    FL_TRY_HIP(hipGetLastError());
+    {
+        NatProf ps(n, s, NK_LEAVES, (double)nmax * n->N, (double)(n_rows + nmax) * ct * 8);
+        hipLaunchKernelGGL(k_nat_leaves, dim3(gx, n->T, packs), dim3(256), 0, s, rows, n_rows, cur, dm, n->n_pack, n->T,
+                           n->phig, (int)(n->M / ipow(t, n->prm.gamma)));
+        FL_TRY_HIP(hipGetLastError());
+    }
     // merges up the tower: level i has len = t^(beta - i) sub-packs per pack
     int len = n->T;
     for (int i = n->prm.gamma; i < n->prm.beta; ++i) {
         const int lv = i - n->prm.gamma, step = len / t, th = (int)(n->M / ipow(t, i + 1));
-        hipLaunchKernelGGL(k_nat_merge_v, dim3(gx, step * t, packs), dim3(256), 0, s, cur, v, dm, t, step, th);
-        FL_TRY_HIP(hipGetLastError());
-        // S = v_(t-1); S = v_m + tau_i(S) for m = t-2 .. 0 (a merge's t terms are ct apart)
+        {
+            NatProf pm(n, s, NK_MERGE, (double)packs * len * n->N, (double)packs * len * ct * 8 * 2);
+            hipLaunchKernelGGL(k_nat_merge_v, dim3(gx, step * t, packs), dim3(256), 0, s, cur, v, dm, t, step, th);
+            FL_TRY_HIP(hipGetLastError());
+        }
+        // S = v_(t-1); S = v_m + tau_i(S) for m = t-2 .. 0 (a merge's t terms are ct apart);
+        // the results alternate between S and cur (consumed by the merge terms above)
         const int cnt = packs * step;
         const uint64_t *src = v + (int64_t)(t - 1) * ct;
         int64_t src_es = (int64_t)t * ct;
+        uint64_t *dst = S, *other = cur;
         for (int m = t - 2; m >= 0; --m) {
-            FL_RET(nat_ks_step(n, lv, src, src_es, v + (int64_t)m * ct, (int64_t)t * ct, S, ct, cnt, dig, bp, s));
-            src = S;
+            FL_RET(nat_ks_step(n, lv, src, src_es, v + (int64_t)m * ct, (int64_t)t * ct, dst, ct, cnt, dig, s));
+            src = dst;
             src_es = ct;
+            std::swap(dst, other);
         }
-        std::swap(cur, S);
+        // the level's result is in src; the other buffer is free
+        cur = (uint64_t *)src;
+        S = dst;
         len = step;
     }
     // Tr_{K/K_beta}: per level j = alpha-1 down to beta, T_j = P, T_j = P + tau_j(T_j)
-    // (t - 1 times)
+    // (t - 1 times); the partial results alternate between the two free buffers
+    uint64_t *fa = S, *fb = v;
     for (int j = n->prm.alpha - 1; j >= n->prm.beta; --j) {
         const int lv = j - n->prm.gamma;
         const uint64_t *src = cur;
+        uint64_t *dst = fa, *other = fb;
         for (int k = 0; k < t - 1; ++k) {
-            FL_RET(nat_ks_step(n, lv, src, ct, cur, ct, S, ct, packs, dig, bp, s));
-            src = S;
+            FL_RET(nat_ks_step(n, lv, src, ct, cur, ct, dst, ct, packs, dig, s));
+            src = dst;
+            std::swap(dst, other);
         }
-        std::swap(cur, S);
+        // result in src; the old P and the other buffer are free
+        uint64_t *old = cur;
+        cur = (uint64_t *)src;
+        fa = old;
+        fb = dst;
     }
     FL_TRY_HIP(hipMemcpyAsync(packed, cur, (size_t)packs * ct * sizeof(uint64_t), hipMemcpyDeviceToDevice, s));
+    return FHELIN_OK;
+}
+
+int native_conv(Native *n, int c_in, int c_out, int h, int w, int k, int stride, const int32_t *wts,
+                const int32_t *out_row, const uint64_t *rows, uint64_t *out, hipStream_t s) {
+    FL_CHECK(n && wts && out_row && rows && out, FHELIN_E_INVALID_ARG, "native_conv: null argument");
+    FL_CHECK(c_in >= 1 && c_out >= 1 && h >= 1 && w >= 1 && k >= 1 && k % 2 == 1 && stride >= 1,
+             FHELIN_E_INVALID_ARG, "native_conv: need positive sizes, an odd kernel and a positive stride");
+    const int ho = (h - 1) / stride + 1, wo = (w - 1) / stride + 1;
+    FL_CHECK(ho * wo <= 65535 && (c_out + CONV_CO - 1) / CONV_CO <= 65535, FHELIN_E_INVALID_ARG,
+             "native_conv: too many output positions");
+    const int n2 = 2 * n->N;
+    // units: products; bytes: every input row once and the outputs (a row shared by
+    // overlapping windows is read again from the caches)
+    NatProf ps(n, s, NK_LINEAR, (double)ho * wo * c_out * c_in * k * k * n2,
+               ((double)c_in * h * w + (double)c_out * ho * wo) * n2 * 8.0);
+    hipLaunchKernelGGL(k_nat_conv, dim3((n2 + 255) / 256, ho * wo, (c_out + CONV_CO - 1) / CONV_CO), dim3(256), 0, s,
+                       rows, wts, out_row, out, c_in, c_out, h, w, k, stride, wo, n2);
+    FL_TRY_HIP(hipGetLastError());
     return FHELIN_OK;
 }
 

@@ -122,7 +122,11 @@ _SIGS = {
     "fhelin_native_extract": [_vp, _vp, _i32, _vp, _vp],
     "fhelin_native_linear": [_vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp],
     "fhelin_native_pack": [_vp, _vp, _i32, _vp, _vp],
+    "fhelin_native_conv": [_vp, _i32, _i32, _i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp],
     "fhelin_native_pack_workspace": [_vp, _i32, ctypes.POINTER(_u64)],
+    "fhelin_native_profile_enable": [_vp, _i32],
+    "fhelin_native_profile_read": [_vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
+                                   ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)],
     "fhelin_diag_alu_rate": [_i32, _i32, _i32, ctypes.POINTER(_dbl), ctypes.POINTER(_dbl), ctypes.POINTER(_dbl)],
     "fhelin_profile_enable": [_vp, _i32],
     "fhelin_profile_read": [_vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
@@ -473,10 +477,30 @@ def fhelin_native_linear(nt, row_ptr: torch.Tensor, col: torch.Tensor, val: torc
                                      _u64_tensor(out, "out"), _stream(stream)))
 
 
+def fhelin_native_conv(nt, c_in: int, c_out: int, h: int, w: int, k: int, stride: int, weights: torch.Tensor,
+                       out_row: torch.Tensor, rows: torch.Tensor, out: torch.Tensor, stream=None):
+    """Convolution on channels-last rows; output (position, co) to out[out_row[pos c_out + co]]."""
+    _check(_lib.fhelin_native_conv(nt, c_in, c_out, h, w, k, stride, _i32_tensor(weights, "weights"),
+                                   _i32_tensor(out_row, "out_row"), _u64_tensor(rows, "rows"), _u64_tensor(out, "out"),
+                                   _stream(stream)))
+
+
 def fhelin_native_pack(nt, rows: torch.Tensor, packed: torch.Tensor, stream=None):
     """rows [n][2][N] -> packed [ceil(n / phi(t^beta))][2][N]."""
     _check(_lib.fhelin_native_pack(nt, _u64_tensor(rows, "rows"), rows.shape[0], _u64_tensor(packed, "packed"),
                                    _stream(stream)))
+
+
+def fhelin_native_profile_enable(nt, enable: bool = True):
+    _check(_lib.fhelin_native_profile_enable(nt, 1 if enable else 0))
+
+
+def fhelin_native_profile_read(nt, kernel: str):
+    """(launches, total_ms, units, bytes) of one kernel class of the native pipeline."""
+    n, ms, u, by = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _check(_lib.fhelin_native_profile_read(nt, kernel.encode(), ctypes.byref(n), ctypes.byref(ms), ctypes.byref(u),
+                                           ctypes.byref(by)))
+    return int(n.value), float(ms.value), float(u.value), float(by.value)
 
 
 def fhelin_native_pack_workspace(nt, n_rows: int) -> int:

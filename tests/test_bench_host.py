@@ -114,3 +114,4 @@ def test_pmc_summary_merges_kernels_of_one_class(tmp_path, monkeypatch):
     k = json.loads(out.read_text())["kernels"]["moddown_fbc"]
     assert k["dispatches"] == 2
     assert k["bytes_per_dispatch"] == pytest.approx((20.0 + 2.0) * 1024)
+

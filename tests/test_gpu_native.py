@@ -139,3 +139,55 @@ def test_native_pack_needs_keys_and_rejects_stale_handles():
     F.fhelin_native_destroy(nt)
     with pytest.raises(F.FhelinError):
         F.fhelin_native_destroy(nt)
+
+
+@pytest.mark.parametrize("t,alpha,gamma,beta,shape", [
+    (3, 4, 1, 3, (3, 5, 4, 4, 3, 1)), (3, 4, 2, 3, (4, 6, 4, 4, 3, 2)), (5, 3, 1, 2, (6, 20, 4, 4, 1, 2)),
+    (3, 7, 1, 6, (16, 16, 8, 8, 3, 1)), (3, 7, 2, 6, (64, 10, 1, 1, 1, 1))])
+def test_native_conv_layer_bit_exact(t, alpha, gamma, beta, shape):
+    """The convolution kernel on extracted rows (channels-last windows, zero padding,
+    strides 1 and 2, the FC case h = w = k = 1) with the shuffle as the output rows:
+    element by element equal to the oracle's matrix product with the convolution's
+    matrix, then packed, and decrypting to the integer layer."""
+    import torch
+
+    from paper_2509_01253_amd import fhelin as F
+    c_in, c_out, h, w, k, st = shape
+    print(f"native conv t={t} alpha={alpha} gamma={gamma} {shape}", flush=True)
+    P = R.NativeParams(t, alpha, gamma, beta, 9, 3, 8, 2.0 ** 28)
+    cl = R.NativeClient(P, 300 + t + alpha + gamma)
+    keys = cl.keyset()
+    rng = np.random.default_rng(310 + t + c_in)
+    E = c_in * h * w
+    n_chunks = (E + P.N - 1) // P.N
+    x = rng.integers(0, 16, E)
+    xs = np.zeros(n_chunks * P.N, np.int64)
+    xs[:E] = x
+    chunks = np.stack([cl.encrypt_powers(xs[c * P.N: (c + 1) * P.N]) for c in range(n_chunks)])
+    wts = rng.integers(-8, 8, (c_out, c_in, k, k)).astype(np.int32)
+    Wc = R.conv_matrix(c_in, c_out, h, w, k, st, wts)
+    n_out = Wc.shape[0]
+    out_row = rng.permutation(n_out).astype(np.int32)
+    Wp = np.zeros_like(Wc)
+    Wp[out_row] = Wc
+    nt = F.fhelin_native_create(t, alpha, gamma, beta, 9, 3, 8)
+    try:
+        F.fhelin_native_keys_load(nt, dev(np.stack([keys[d] for d in P.taus()])))
+        rows = torch.zeros((n_chunks * P.N, 2, P.N), dtype=torch.int64, device="cuda")
+        F.fhelin_native_extract(nt, dev(chunks), rows)
+        out = torch.zeros((n_out, 2, P.N), dtype=torch.int64, device="cuda")
+        F.fhelin_native_conv(nt, c_in, c_out, h, w, k, st, _i32(wts), _i32(out_row), rows, out)
+        n_packs = (n_out + P.n_pack - 1) // P.n_pack
+        packed = torch.zeros((n_packs, 2, P.N), dtype=torch.int64, device="cuda")
+        F.fhelin_native_pack(nt, out, packed)
+        got_rows, got, got_p = host(rows), host(out), host(packed)
+    finally:
+        F.fhelin_native_destroy(nt)
+    sel = rng.choice(n_out, min(n_out, 40), replace=False)
+    assert np.array_equal(got[sel], R.linear_rows(Wp[sel], got_rows[:E]))
+    y = (Wp @ x) % P.p
+    pos = R.unpack_positions(P)
+    for g in range(n_packs):
+        assert np.array_equal(got_p[g], R.pack(P, got[g * P.n_pack: (g + 1) * P.n_pack], keys)), g
+        seg = y[g * P.n_pack: (g + 1) * P.n_pack]
+        assert np.array_equal(cl.decrypt(got_p[g])[pos[: seg.size]], seg), g

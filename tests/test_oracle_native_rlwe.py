@@ -152,3 +152,22 @@ def test_packing_key_switch_counts_against_the_paper_table():
             ours = P.key_switches_per_pack() / P.n_pack
             paper = V.key_switches_per_coefficient(t, alpha, gamma)
             assert ours < paper, (t, alpha, gamma, ours, paper)
+
+
+def test_conv_matrix_is_the_windowed_sum():
+    """conv_matrix x equals the convolution computed directly on an H x W x C_in array
+    (numpy slicing of a zero-padded image), for strides 1 and 2 and kernels 1 and 3."""
+    rng = np.random.default_rng(5)
+    for c_in, c_out, h, w, k, s in ((2, 3, 5, 4, 3, 1), (3, 2, 6, 6, 3, 2), (4, 5, 4, 4, 1, 2), (6, 3, 1, 1, 1, 1)):
+        wts = rng.integers(-8, 8, (c_out, c_in, k, k))
+        img = rng.integers(0, 16, (h, w, c_in))
+        pad = np.zeros((h + 2 * (k // 2), w + 2 * (k // 2), c_in), np.int64)
+        pad[k // 2: k // 2 + h, k // 2: k // 2 + w] = img
+        ho, wo = (h - 1) // s + 1, (w - 1) // s + 1
+        direct = np.zeros((ho, wo, c_out), np.int64)
+        for yo in range(ho):
+            for xo in range(wo):
+                win = pad[s * yo: s * yo + k, s * xo: s * xo + k]  # k x k x c_in
+                direct[yo, xo] = np.einsum("yxc,ocyx->o", win, wts)
+        got = R.conv_matrix(c_in, c_out, h, w, k, s, wts) @ img.reshape(-1)
+        assert np.array_equal(got, direct.reshape(-1)), (c_in, c_out, h, w, k, s)
