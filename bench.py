@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--with-native", type=int, default=1,
                     help="1: add the paper's own pipeline (ResNet-20 linear layers at its 8-bit set, gamma 1 and 2) "
                          "to the default run's line; 0: skip")
+    ap.add_argument("--native-engine", type=int, default=0,
+                    help="key-switch products of the native pipeline: 0 int8 matrix cores, 1 64-bit ALU")
     ap.add_argument("--native", type=int, default=0,
                     help="only the paper's own pipeline at this gamma (1 or 2): one JSON line")
     ap.add_argument("--fuse-baby", type=int, default=-1,
@@ -619,6 +621,10 @@ NATIVE = {"t": 3, "alpha": 7, "beta": 6, "log_d": 9, "l": 3, "log_p": 8}
 # its high word and half a v_add3_u32 per product: 327 VALU per 128 products)
 NAT_KS_VALU_OPS = 327 / 128
 PEAK_NAT_KS = ALU_LANE_OPS / NAT_KS_VALU_OPS / 1e12
+# the int8 matrix-core engine: each 64-bit product is 2 digit halves x 8 key bytes = 16
+# int8 multiply-adds (32 ops), priced against MI355X's dense int8 peak
+INT8_OPS_PER_PRODUCT = 32
+PEAK_INT8_TOPS = 5000.0
 
 
 def resnet20_layers() -> list:
@@ -633,7 +639,7 @@ def resnet20_layers() -> list:
     return L + [(64, 10, 1, 1, 1, 1)]
 
 
-def native_bench(gamma: int, reps: int = 2) -> dict:
+def native_bench(gamma: int, reps: int = 2, engine: int = 0) -> dict:
     """Server compute of one ResNet-20 inference under the paper's own pipeline at its
     8-bit parameter set and extraction level gamma: per layer, partial trace extraction
     of the input chunks (ceil(E / N) chunks of phi(t^gamma) encrypted powers), the
@@ -653,7 +659,7 @@ def native_bench(gamma: int, reps: int = 2) -> dict:
     N = M - M // t
     n_pack = (t - 1) * t ** (beta - 1)
     phig = (t - 1) * t ** (gamma - 1)
-    nt = F.fhelin_native_create(t, alpha, gamma, beta, c["log_d"], c["l"], c["log_p"])
+    nt = F.fhelin_native_create(t, alpha, gamma, beta, c["log_d"], c["l"], c["log_p"], engine)
     rng = np.random.default_rng(20 + gamma)
     gen = torch.Generator(device="cuda").manual_seed(20 + gamma)
 
@@ -703,7 +709,10 @@ def native_bench(gamma: int, reps: int = 2) -> dict:
         n_l, ms_k, units, byts = F.fhelin_native_profile_read(nt, kname)
         if n_l == 0 or ms_k <= 0:
             continue
-        if bound == "alu":
+        if bound == "alu" and engine == 0:
+            bound = "mfma"
+            ach, peak, unit = units * INT8_OPS_PER_PRODUCT / (ms_k / 1e3) / 1e12, PEAK_INT8_TOPS, "T int8 ops/s"
+        elif bound == "alu":
             ach, peak, unit = units / (ms_k / 1e3) / 1e12, PEAK_NAT_KS, "T 64-bit products/s"
         else:
             ach, peak, unit = byts / (ms_k / 1e3) / 1e9, HBM_PEAK_GBPS, "GB/s"
@@ -720,7 +729,8 @@ def native_bench(gamma: int, reps: int = 2) -> dict:
                         f"projections, FC 64->10), paper's 8-bit set: M = 3^7, N = {N}, D = 2^9, l = 3, p = 2^8, "
                         f"gamma = {gamma}, beta = {beta} ({n_pack} outputs per packed ciphertext), 4-bit weights, "
                         f"uniform keys and inputs",
-            "gamma": gamma, "per_inference_ms": round(ms, 3), "inferences_per_s": round(1e3 / ms, 3),
+            "gamma": gamma, "engine": "int8 matrix cores" if engine == 0 else "64-bit ALU",
+            "per_inference_ms": round(ms, 3), "inferences_per_s": round(1e3 / ms, 3),
             "extract_ms": round(tot[0], 3), "linear_ms": round(tot[1], 3), "pack_ms": round(tot[2], 3),
             "packed_ciphertexts": packs, "key_switches": ks, "key_switches_per_s": round(ks / (tot[2] / 1e3), 1),
             "rooflines": roof, "dominant": max(roof, key=lambda k: roof[k]["ms_per_inference"]) if roof else None}
@@ -764,7 +774,7 @@ def main():
         print(json.dumps(alu_rates(F)), flush=True)
         return
     if args.native > 0:
-        print(json.dumps({"native_resnet20": native_bench(args.native)}), flush=True)
+        print(json.dumps({"native_resnet20": native_bench(args.native, engine=args.native_engine)}), flush=True)
         return
     if args.calib_copy > 0:
         n = int(args.calib_copy * (1 << 30)) // 8

@@ -431,10 +431,14 @@ typedef struct fhelin_native_params {
                            ciphertext, output o at coefficient o M / t^beta */
     int32_t log_d, l;   /* gadget base D = 2^log_d (1..16) and depth l (1..8), log_d l < 64 */
     int32_t log_p;      /* message modulus p = 2^log_p (1..31) */
+    int32_t engine;     /* key-switch products: 0 = int8 matrix cores (balanced 4/5-bit
+                           digit halves x balanced key bytes, exact i32 sums, needs
+                           log_d <= 9), 1 = 64-bit integer ALU products */
 } fhelin_native_params;
 
 /* FHELIN_E_UNSUPPORTED_PARAM for parameters outside the ranges above (checked on
- * the host).  The handle lives on the current device. */
+ * the host).  The handle lives on the current device.  Both engines give the same
+ * bits. */
 int fhelin_native_create(const fhelin_native_params *prm, fhelin_native **out);
 int fhelin_native_destroy(fhelin_native *nt);
 
@@ -443,7 +447,8 @@ int fhelin_native_destroy(fhelin_native *nt);
  * encryptions RLWE_s(s(X^(1+t^i)) 2^64 / D^k), k = 1..l: device
  * [alpha-gamma][l][2][N] uint64, read during the call's stream work only.  The
  * handle keeps, per key polynomial, its N x N product matrix modulo Phi_M
- * ((alpha-gamma) 2 N l N 8 bytes of device memory); FHELIN_E_OOM if that fails. */
+ * (about (alpha-gamma) 2 N l N 8 bytes of device memory, as 64-bit words or as
+ * eight signed byte planes); FHELIN_E_OOM if that fails. */
 int fhelin_native_keys_load(fhelin_native *nt, const uint64_t *ksk, void *stream);
 
 /* Partial trace extraction (Sec. 4.4 and its lemma): chunks

@@ -319,6 +319,182 @@ __global__ void __launch_bounds__(256) k_nat_conv(const uint64_t *__restrict__ r
         if (q < nco) out[(int64_t)out_row[pos * c_out + co0 + q] * n2 + col] = acc[q];
 }
 
+// ---------------------------------------------------------------------------
+// int8 matrix-core engine.  A balanced digit d in [-D/2, D/2) (D <= 2^9) is
+// lo + 16 hi with lo in [-8, 8), hi in [-16, 16]; a key entry K (mod 2^64) is
+// sum_b 2^(8b) s_b with balanced bytes s_b in [-128, 128).  Then
+//   sum_k d_k K_k = sum_b 2^(8b) (sum_k lo_k s_bk + 16 sum_k hi_k s_bk)   (mod 2^64)
+// and each inner sum is an int8 matrix product with an exact int32 sum
+// (|sum| <= 16 128 l N < 2^31 for l N <= 2^19).
+// ---------------------------------------------------------------------------
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+// digits of a batch as two int8 planes A8[h][c][KDp] (k = i N + m, zero past l N) and
+// the output's start value out = (add_a, add_b + sigma(b)); grid (ceil(N / 256), n)
+__global__ void __launch_bounds__(256) k_nat_aut_decomp8(const uint64_t *__restrict__ S, int64_t s_es,
+                                                         const uint64_t *__restrict__ add, int64_t add_es,
+                                                         uint64_t *__restrict__ out, int64_t out_es,
+                                                         int8_t *__restrict__ A8, int64_t a_half, NatDims dm, int ginv,
+                                                         int log_d, int l, int KDp) {
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    const int c = blockIdx.y;
+    int8_t *lo = A8 + (int64_t)c * KDp, *hi = lo + a_half;
+    if (j < KDp - l * dm.N) {  // the padding of the row
+        lo[l * dm.N + j] = 0;
+        hi[l * dm.N + j] = 0;
+    }
+    if (j >= dm.N) return;
+    const uint64_t *a = S + c * s_es, *b = a + dm.N;
+    const uint64_t av = aut_at(a, j, ginv, dm), bv = aut_at(b, j, ginv, dm);
+    const uint64_t *ad = add + c * add_es;
+    uint64_t *o = out + c * out_es;
+    o[j] = ad[j];
+    o[dm.N + j] = ad[dm.N + j] + bv;
+    const int bits = log_d * l, sh = 64 - bits;
+    uint64_t top = (av >> sh) + ((av >> (sh - 1)) & 1);
+    const uint64_t D = 1ull << log_d, mask = D - 1;
+    for (int i = l - 1; i >= 0; --i) {
+        int d = (int)(top & mask);
+        top >>= log_d;
+        if (d >= (int)(D >> 1)) {
+            d -= (int)D;
+            top += 1;
+        }
+        const int h = (d + 8) >> 4;  // floor division: lo = d - 16 h in [-8, 8)
+        lo[i * dm.N + j] = (int8_t)(d - 16 * h);
+        hi[i * dm.N + j] = (int8_t)h;
+    }
+}
+
+// out[c][p][j] -= sum_k d[c][k] K_p[j][k] (mod 2^64) on the matrix cores.  Workgroup:
+// 64 ciphertexts x 64 coefficients, four waves of 32 x 32 (2 x 2 tiles of 16 x 16),
+// v_mfma_i32_16x16x64_i8: lane l feeds row (or column) l mod 16 with the 16 bytes at
+// k0 + 16 (l / 16), the same k positions for both operands, so the product is
+// independent of how the instruction orders k; result lane l, register r: row
+// 4 (l / 16) + r, column l mod 16.  Byte planes go one at a time (b outer), each
+// folded into the 64-bit results after its K loop.  grid.z splits K as in k_nat_ksprod.
+__global__ void __launch_bounds__(256) k_nat_ksprod8(const int8_t *__restrict__ A8, int64_t a_half,
+                                                     const int8_t *__restrict__ B8, uint64_t *__restrict__ out,
+                                                     int64_t out_es, int n, int N, int KDp, int kc) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int cbase = blockIdx.y * 64 + (w & 1) * 32, jbase = blockIdx.x * 64 + (w >> 1) * 32;
+    const int kb = blockIdx.z * kc, ke = min(KDp, kb + kc);
+    const int r16 = lane & 15, g = lane >> 4;
+    const int64_t plane = (int64_t)N * KDp;
+    uint64_t res[2][2][2][4];
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int bq = 0; bq < 2; ++bq)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) res[p][a][bq][r] = 0;
+    // the lane's rows; rows past the batch or the ring read row 0 and are masked
+    int crow[2], jrow[2];
+    bool cok[2], jok[2];
+#pragma unroll
+    for (int t2 = 0; t2 < 2; ++t2) {
+        crow[t2] = cbase + t2 * 16 + r16;
+        cok[t2] = crow[t2] < n;
+        jrow[t2] = jbase + t2 * 16 + r16;
+        jok[t2] = jrow[t2] < N;
+    }
+    for (int b = 0; b < 8; ++b) {
+        v4i acc[2][2][2][2];  // [part][half][c tile][j tile]
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int bq = 0; bq < 2; ++bq) acc[p][h][a][bq] = v4i{0, 0, 0, 0};
+        for (int k0 = kb; k0 < ke; k0 += 64) {
+            const int k = k0 + 16 * g;
+            v4i af[2][2], bf[2][2];
+#pragma unroll
+            for (int t2 = 0; t2 < 2; ++t2) {
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const v4i v = *(const v4i *)(A8 + h * a_half + (int64_t)(cok[t2] ? crow[t2] : 0) * KDp + k);
+                    af[h][t2] = cok[t2] ? v : v4i{0, 0, 0, 0};
+                }
+#pragma unroll
+                for (int p = 0; p < 2; ++p) {
+                    const v4i v = *(const v4i *)(B8 + (p * 8 + b) * plane + (int64_t)(jok[t2] ? jrow[t2] : 0) * KDp + k);
+                    bf[p][t2] = jok[t2] ? v : v4i{0, 0, 0, 0};
+                }
+            }
+#pragma unroll
+            for (int p = 0; p < 2; ++p)
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+#pragma unroll
+                    for (int a = 0; a < 2; ++a)
+#pragma unroll
+                        for (int bq = 0; bq < 2; ++bq)
+                            acc[p][h][a][bq] =
+                                __builtin_amdgcn_mfma_i32_16x16x64_i8(af[h][a], bf[p][bq], acc[p][h][a][bq], 0, 0, 0);
+        }
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int bq = 0; bq < 2; ++bq)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        res[p][a][bq][r] += (uint64_t)((int64_t)acc[p][0][a][bq][r] + 16 * (int64_t)acc[p][1][a][bq][r])
+                                            << (8 * b);
+    }
+    const bool split = gridDim.z > 1;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int c = cbase + a * 16 + 4 * g + r;
+            if (c >= n) continue;
+            uint64_t *o = out + c * out_es;
+#pragma unroll
+            for (int bq = 0; bq < 2; ++bq) {
+                const int j = jbase + bq * 16 + r16;
+                if (j >= N) continue;
+#pragma unroll
+                for (int p = 0; p < 2; ++p) {
+                    uint64_t *dst = o + p * N + j;
+                    if (split) atomicAdd((unsigned long long *)dst, (unsigned long long)(0 - res[p][a][bq][r]));
+                    else *dst -= res[p][a][bq][r];
+                }
+            }
+        }
+}
+
+// balanced byte planes of the key product matrices: B8[lv][p][b][j][k] = s_b of
+// coefficient j of X^m k_(lv, i, p), k = i N + m (zero for k >= l N);
+// grid (ceil(N / 256), KDp, levels * 2)
+__global__ void __launch_bounds__(256) k_nat_kmat8(const uint64_t *__restrict__ ksk, int8_t *__restrict__ B8, NatDims dm,
+                                                   int l, int KDp) {
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= dm.N) return;
+    const int km = blockIdx.y;
+    const int lv = blockIdx.z >> 1, p = blockIdx.z & 1;
+    uint64_t v = 0;
+    if (km < l * dm.N) {
+        const int i = km / dm.N, m = km % dm.N;
+        v = mono_at(ksk + (((int64_t)lv * l + i) * 2 + p) * dm.N, j, m, dm);
+    }
+    const int64_t plane = (int64_t)dm.N * KDp;
+    int8_t *o = B8 + ((int64_t)(lv * 2 + p) * 8) * plane + (int64_t)j * KDp + km;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        int s = (int)(v & 0xff);
+        s -= s >= 128 ? 256 : 0;
+        v = (v - (uint64_t)(int64_t)s) >> 8;
+        o[b * plane] = (int8_t)s;
+    }
+}
+
 // key product matrices: K[lv][p][j][i N + m] = coefficient j of X^m k_(lv, i, p);
 // grid (ceil(N / 256), l N, levels * 2)
 __global__ void __launch_bounds__(256) k_nat_kmat(const uint64_t *__restrict__ ksk, uint64_t *__restrict__ K, NatDims dm,
@@ -455,6 +631,9 @@ int native_create(const fhelin_native_params *prm, Native **out) {
     FL_CHECK(q.log_d >= 1 && q.log_d <= 16 && q.l >= 1 && q.l <= 8 && q.log_d * q.l < 64, FHELIN_E_UNSUPPORTED_PARAM,
              "gadget: 1 <= log_d <= 16, 1 <= l <= 8, log_d l < 64");
     FL_CHECK(q.log_p >= 1 && q.log_p <= 31, FHELIN_E_UNSUPPORTED_PARAM, "message modulus: 1 <= log_p <= 31");
+    FL_CHECK(q.engine == 0 || q.engine == 1, FHELIN_E_UNSUPPORTED_PARAM, "engine: 0 (int8 matrix cores) or 1 (ALU)");
+    FL_CHECK(q.engine == 1 || q.log_d <= 9, FHELIN_E_UNSUPPORTED_PARAM,
+             "the int8 engine splits digits into 4- and 5-bit halves: log_d <= 9");
     std::unique_ptr<Native> n(new Native());
     n->prm = q;
     n->M = (int)ipow(q.t, q.alpha);
@@ -463,6 +642,7 @@ int native_create(const fhelin_native_params *prm, Native **out) {
     n->n_pack = (int)((q.t - 1) * ipow(q.t, q.beta - 1));
     n->T = (int)ipow(q.t, q.beta - q.gamma);
     n->phig = (int)((q.t - 1) * ipow(q.t, q.gamma - 1));
+    n->KDp = (q.l * n->N + 63) / 64 * 64;
     const int64_t p = 1ll << q.log_p;
     int64_t u = inv_mod(n->M, p);
     if (u > p / 2) u -= p;
@@ -490,6 +670,7 @@ void native_destroy(Native *n) {
     (void)hipDeviceSynchronize();
     nat_prof_drain(n);
     if (n->kmat) (void)hipFree(n->kmat);
+    if (n->kmat8) (void)hipFree(n->kmat8);
     if (n->kcorr) (void)hipFree(n->kcorr);
     if (n->ws) (void)hipFree(n->ws);
     delete n;
@@ -519,6 +700,20 @@ int native_keys_load(Native *n, const uint64_t *ksk, hipStream_t s) {
     FL_CHECK(n && ksk, FHELIN_E_INVALID_ARG, "native_keys_load: null argument");
     const int levels = (int)n->tau.size(), l = n->prm.l;
     const int64_t KD = (int64_t)l * n->N;
+    const NatDims dm = dims(n);
+    if (n->prm.engine == 0) {
+        const size_t bytes8 = (size_t)levels * 2 * 8 * n->N * n->KDp;
+        if (!n->kmat8 && hipMalloc((void **)&n->kmat8, bytes8) != hipSuccess) {
+            (void)hipGetLastError();
+            return set_error(FHELIN_E_OOM, "native keys: device allocation failed");
+        }
+        NatProf ps(n, s, NK_KMAT, (double)levels * 2 * n->N * n->KDp, (double)bytes8 + levels * l * 2.0 * n->N * 8);
+        hipLaunchKernelGGL(k_nat_kmat8, dim3((n->N + 255) / 256, (unsigned)n->KDp, levels * 2), dim3(256), 0, s, ksk,
+                           n->kmat8, dm, l, n->KDp);
+        FL_TRY_HIP(hipGetLastError());
+        n->keys = true;
+        return FHELIN_OK;
+    }
     const size_t kbytes = (size_t)levels * 2 * n->N * KD * sizeof(uint64_t);
     if (!n->kmat) {
         if (hipMalloc((void **)&n->kmat, kbytes) != hipSuccess) {
@@ -530,15 +725,14 @@ int native_keys_load(Native *n, const uint64_t *ksk, hipStream_t s) {
             return set_error(FHELIN_E_OOM, "native keys: device allocation failed");
         }
     }
-    const NatDims dm = dims(n);
     {
-    NatProf ps(n, s, NK_KMAT, (double)levels * 2 * n->N * KD, (double)kbytes + levels * l * 2.0 * n->N * 8);
-    hipLaunchKernelGGL(k_nat_kmat, dim3((n->N + 255) / 256, (unsigned)KD, levels * 2), dim3(256), 0, s, ksk, n->kmat, dm,
-                       l);
-    FL_TRY_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_nat_kcorr, dim3(levels * 2 * n->N), dim3(256), 0, s, n->kmat, n->kcorr, KD,
-                       (uint64_t)1 << (n->prm.log_d - 1));
-    FL_TRY_HIP(hipGetLastError());
+        NatProf ps(n, s, NK_KMAT, (double)levels * 2 * n->N * KD, (double)kbytes + levels * l * 2.0 * n->N * 8);
+        hipLaunchKernelGGL(k_nat_kmat, dim3((n->N + 255) / 256, (unsigned)KD, levels * 2), dim3(256), 0, s, ksk, n->kmat,
+                           dm, l);
+        FL_TRY_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_nat_kcorr, dim3(levels * 2 * n->N), dim3(256), 0, s, n->kmat, n->kcorr, KD,
+                           (uint64_t)1 << (n->prm.log_d - 1));
+        FL_TRY_HIP(hipGetLastError());
     }
     n->keys = true;
     return FHELIN_OK;
@@ -583,7 +777,8 @@ size_t native_pack_workspace(const Native *n, int n_rows) {
     const size_t nmax = packs * n->T;  // the leaves: the widest level
     // current sub-packs, merge terms (t per merge), results, and the digits of a
     // key-switch batch
-    return 3 * nmax * ct + nmax * (size_t)n->prm.l * n->N * sizeof(uint32_t);
+    const size_t dig = std::max(nmax * (size_t)n->prm.l * n->N * sizeof(uint32_t), 2 * nmax * (size_t)n->KDp);
+    return 3 * nmax * ct + dig;
 }
 
 // out = add + tau(S) for a batch of cnt ciphertexts with the key of tower level lv; out
@@ -593,10 +788,34 @@ static int nat_ks_step(Native *n, int lv, const uint64_t *S, int64_t s_es, const
     const NatDims dm = dims(n);
     const int l = n->prm.l;
     const int64_t KD = (int64_t)l * n->N;
-    const uint64_t *Ka = n->kmat + (int64_t)lv * 2 * n->N * KD, *Kb = Ka + (int64_t)n->N * KD;
-    const uint64_t *ca = n->kcorr + (int64_t)lv * 2 * n->N, *cb = ca + n->N;
     for (int c0 = 0; c0 < cnt; c0 += 65535) {
         const int c = std::min(cnt - c0, 65535);
+        if (n->prm.engine == 0) {
+            int8_t *A8 = (int8_t *)dig;
+            const int64_t a_half = (int64_t)c * n->KDp;
+            {
+                NatProf pa(n, s, NK_AUT_DECOMP, (double)c * n->N, (double)c * n->N * (2 * 8.0 + 2 * 8.0 + 2 * 8.0 + 2.0 * l));
+                hipLaunchKernelGGL(k_nat_aut_decomp8, dim3((std::max(n->N, n->KDp - (int)KD) + 255) / 256, c), dim3(256),
+                                   0, s, S + c0 * s_es, s_es, add + c0 * add_es, add_es, out + c0 * out_es, out_es, A8,
+                                   a_half, dm, n->tau_inv[lv], n->prm.log_d, l, n->KDp);
+                FL_TRY_HIP(hipGetLastError());
+            }
+            const int gx = (n->N + 63) / 64, gy = (c + 63) / 64;
+            const int splits = std::max(1, std::min(16, 1024 / (gx * gy)));
+            const int kc = (n->KDp / 64 + splits - 1) / splits * 64;
+            const int gz = (n->KDp + kc - 1) / kc;
+            const int8_t *B8 = n->kmat8 + (int64_t)lv * 2 * 8 * n->N * n->KDp;
+            // units: 64-bit products (both key parts); bytes: both digit planes and the
+            // sixteen key planes once per launch, the output read and written
+            NatProf pk(n, s, NK_KSPROD, 2.0 * c * n->N * (double)KD,
+                       2.0 * c * n->KDp + 16.0 * n->N * n->KDp + (double)c * n->N * 8 * 4);
+            hipLaunchKernelGGL(k_nat_ksprod8, dim3(gx, gy, gz), dim3(256), 0, s, A8, a_half, B8, out + c0 * out_es, out_es, c,
+                               n->N, n->KDp, kc);
+            FL_TRY_HIP(hipGetLastError());
+            continue;
+        }
+        const uint64_t *Ka = n->kmat + (int64_t)lv * 2 * n->N * KD, *Kb = Ka + (int64_t)n->N * KD;
+        const uint64_t *ca = n->kcorr + (int64_t)lv * 2 * n->N, *cb = ca + n->N;
         {
             NatProf pa(n, s, NK_AUT_DECOMP, (double)c * n->N, (double)c * n->N * (2 * 8.0 + 2 * 8.0 + 2 * 8.0 + 4.0 * l));
             hipLaunchKernelGGL(k_nat_aut_decomp, dim3((n->N + 255) / 256, c), dim3(256), 0, s, S + c0 * s_es, s_es,

@@ -116,7 +116,7 @@ def test_null_and_unknown_handles_rejected_without_a_gpu():
 
 
 class _NatPrm(ctypes.Structure):
-    _fields_ = [(n, ctypes.c_int32) for n in ("t", "alpha", "gamma", "beta", "log_d", "l", "log_p")]
+    _fields_ = [(n, ctypes.c_int32) for n in ("t", "alpha", "gamma", "beta", "log_d", "l", "log_p", "engine")]
 
 
 def test_native_create_rejects_bad_parameters_on_the_host():
@@ -126,12 +126,13 @@ def test_native_create_rejects_bad_parameters_on_the_host():
     lib = ctypes.CDLL(LIB)
     lib.fhelin_last_error.restype = ctypes.c_char_p
     lib.fhelin_native_create.argtypes = [ctypes.POINTER(_NatPrm), ctypes.POINTER(ctypes.c_void_p)]
-    good = dict(t=3, alpha=7, gamma=1, beta=6, log_d=9, l=3, log_p=8)
+    good = dict(t=3, alpha=7, gamma=1, beta=6, log_d=9, l=3, log_p=8, engine=0)
     bad = {"t even": dict(t=4), "t not prime": dict(t=9), "t = 2": dict(t=2), "alpha 1": dict(alpha=1),
            "M too large": dict(alpha=9), "gamma 0": dict(gamma=0), "gamma 3": dict(gamma=3, beta=5),
            "beta < gamma": dict(gamma=2, beta=1), "beta = alpha": dict(beta=7), "log_d 0": dict(log_d=0),
            "log_d 17": dict(log_d=17), "l 9": dict(l=9, log_d=4), "gadget 64 bits": dict(log_d=16, l=4),
-           "log_p 0": dict(log_p=0), "log_p 32": dict(log_p=32)}
+           "log_p 0": dict(log_p=0), "log_p 32": dict(log_p=32), "engine 2": dict(engine=2),
+           "int8 engine, 10-bit digits": dict(log_d=10, l=2)}
     for name, change in bad.items():
         out = ctypes.c_void_p()
         prm = _NatPrm(**{**good, **change})

@@ -33,10 +33,10 @@ def _conv_like(rng, n_out, n_in, nnz, mag):
     return W
 
 
-def _run(F, P, chunks, W, perm, keys, sample_rows=None):
+def _run(F, P, chunks, W, perm, keys, engine=0):
     """GPU pipeline; returns (rows, F rows, packed) on the host."""
     import torch
-    nt = F.fhelin_native_create(P.t, P.alpha, P.gamma, P.beta, P.log_d, P.l, P.log_p)
+    nt = F.fhelin_native_create(P.t, P.alpha, P.gamma, P.beta, P.log_d, P.l, P.log_p, engine)
     try:
         ksk = np.stack([keys[d] for d in P.taus()])
         F.fhelin_native_keys_load(nt, dev(ksk))
@@ -54,11 +54,13 @@ def _run(F, P, chunks, W, perm, keys, sample_rows=None):
         F.fhelin_native_destroy(nt)
 
 
+@pytest.mark.parametrize("engine", [0, 1])
 @pytest.mark.parametrize("t,alpha,gamma,beta", [(3, 4, 1, 3), (3, 4, 2, 3), (5, 3, 1, 2), (5, 3, 2, 2), (7, 2, 1, 1),
                                                 (3, 5, 1, 2)])
-def test_native_pipeline_bit_exact_small_rings(t, alpha, gamma, beta):
+def test_native_pipeline_bit_exact_small_rings(t, alpha, gamma, beta, engine):
+    """Both key-switch engines (int8 matrix cores, 64-bit ALU) give the oracle's bits."""
     from paper_2509_01253_amd import fhelin as F
-    print(f"native t={t} alpha={alpha} gamma={gamma} beta={beta}", flush=True)
+    print(f"native t={t} alpha={alpha} gamma={gamma} beta={beta} engine={engine}", flush=True)
     P = R.NativeParams(t, alpha, gamma, beta, 9, 3, 8, 2.0 ** 28)
     cl = R.NativeClient(P, 100 + t * 10 + alpha)
     keys = cl.keyset()
@@ -75,7 +77,7 @@ def test_native_pipeline_bit_exact_small_rings(t, alpha, gamma, beta):
     n_out = 2 * P.n_pack + 5  # two full packs and a partial one
     W = _conv_like(rng, n_out, n_in, min(24, n_in), 8)
     perm = rng.permutation(n_out)
-    rows, Fo, packed = _run(F, P, chunks, W, perm, keys)
+    rows, Fo, packed = _run(F, P, chunks, W, perm, keys, engine)
     want_rows = np.concatenate([R.extract(P, c) for c in chunks])
     assert np.array_equal(rows, want_rows)
     want_F = R.linear_rows(W[perm], want_rows[:n_in])
@@ -92,14 +94,15 @@ def test_native_pipeline_bit_exact_small_rings(t, alpha, gamma, beta):
         assert np.array_equal(dec, exp), g
 
 
+@pytest.mark.parametrize("engine", [0, 1])
 @pytest.mark.parametrize("gamma", [1, 2])
-def test_native_pipeline_paper_8bit_set(gamma):
+def test_native_pipeline_paper_8bit_set(gamma, engine):
     """The paper's 8-bit parameter set (M = 3^7, D = 512, l = 3, p = 2^8) with packs of
     phi(3^6) = 486 outputs: a convolution-shaped layer (144 weights of 4 bits per
     output) over two chunks; rows and layer outputs compared on sampled rows, every
     packed ciphertext element by element, and the decryptions equal to the layer."""
     from paper_2509_01253_amd import fhelin as F
-    print(f"native 3^7 gamma={gamma}", flush=True)
+    print(f"native 3^7 gamma={gamma} engine={engine}", flush=True)
     P = R.NativeParams(3, 7, gamma, 6, 9, 3, 8, 2.0 ** 28)
     cl = R.NativeClient(P, 700 + gamma)
     keys = cl.keyset()
@@ -110,7 +113,7 @@ def test_native_pipeline_paper_8bit_set(gamma):
     n_out = 2 * P.n_pack + 7
     W = _conv_like(rng, n_out, n_in, 144, 8)
     perm = rng.permutation(n_out)
-    rows, Fo, packed = _run(F, P, chunks, W, perm, keys)
+    rows, Fo, packed = _run(F, P, chunks, W, perm, keys, engine)
     for c in range(2):
         want = R.extract(P, chunks[c])
         sel = rng.choice(P.N, 40, replace=False)
@@ -170,7 +173,7 @@ def test_native_conv_layer_bit_exact(t, alpha, gamma, beta, shape):
     out_row = rng.permutation(n_out).astype(np.int32)
     Wp = np.zeros_like(Wc)
     Wp[out_row] = Wc
-    nt = F.fhelin_native_create(t, alpha, gamma, beta, 9, 3, 8)
+    nt = F.fhelin_native_create(t, alpha, gamma, beta, 9, 3, 8, (t + alpha) % 2)
     try:
         F.fhelin_native_keys_load(nt, dev(np.stack([keys[d] for d in P.taus()])))
         rows = torch.zeros((n_chunks * P.N, 2, P.N), dtype=torch.int64, device="cuda")
