@@ -476,7 +476,9 @@ int fhelin_native_linear(fhelin_native *nt, const int32_t *row_ptr, const int32_
  * stride; output (position p = y' w' + x', channel co), w' = (w - 1) / stride + 1,
  * goes to out row out_row[p c_out + co] (the shuffle; a permutation of
  * [0, c_out h' w')).  An FC layer is the case h = w = k = 1.  Indices are not
- * checked on the device. */
+ * checked on the device.  The handle keeps a transposed copy of the weights
+ * (c_in k k 16 ceil(c_out / 16) int32; a regrow synchronises the stream), so
+ * calls that share the handle must not overlap in time. */
 int fhelin_native_conv(fhelin_native *nt, int32_t c_in, int32_t c_out, int32_t h, int32_t w, int32_t k,
                        int32_t stride, const int32_t *weights, const int32_t *out_row, const uint64_t *rows,
                        uint64_t *out, void *stream);

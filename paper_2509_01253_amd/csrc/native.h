@@ -30,6 +30,8 @@ struct Native {
     bool keys = false;
     void *ws = nullptr;
     size_t ws_bytes = 0;
+    int32_t *wt = nullptr;  // a convolution's transposed weights
+    size_t wt_bytes = 0;
     // profiler: HIP events around every launch while enabled (not under graph capture)
     struct Rec {
         int kind;

@@ -284,20 +284,30 @@ __global__ void __launch_bounds__(256) k_nat_ksprod(const uint32_t *__restrict__
 // k / 2): computed output (position, co) = sum over the window of wts[co][ci][dy][dx]
 // times input row, written to out row out_row[position c_out + co] (the shuffle).  A
 // thread owns one of the 2N columns and 16 output channels: each input value is read
-// once for all 16.  grid (ceil(2N / 256), output positions, ceil(c_out / 16)).
+// once for all 16, whose weights (transposed to wT[ci][dy][dx][cop], cop = c_out
+// rounded up to 16, zero past c_out) are one 64-byte uniform load.
+// grid (ceil(2N / 256), output positions, cop / 16).
 constexpr int CONV_CO = 16;
 
-__global__ void __launch_bounds__(256) k_nat_conv(const uint64_t *__restrict__ rows, const int32_t *__restrict__ wts,
+__global__ void __launch_bounds__(256) k_nat_conv_wt(const int32_t *__restrict__ wts, int32_t *__restrict__ wT,
+                                                     int c_in, int c_out, int k, int cop) {
+    const int idx = blockIdx.x * 256 + threadIdx.x;
+    if (idx >= c_in * k * k * cop) return;
+    const int co = idx % cop, t = idx / cop, ci = t / (k * k), r = t % (k * k);
+    wT[idx] = co < c_out ? wts[((int64_t)co * c_in + ci) * k * k + r] : 0;
+}
+
+__global__ void __launch_bounds__(256) k_nat_conv(const uint64_t *__restrict__ rows, const int32_t *__restrict__ wT,
                                                   const int32_t *__restrict__ out_row, uint64_t *__restrict__ out,
-                                                  int c_in, int c_out, int h, int w, int k, int stride, int wo,
+                                                  int c_in, int c_out, int cop, int h, int w, int k, int stride, int wo,
                                                   int n2) {
     const int col = blockIdx.x * 256 + threadIdx.x;
     if (col >= n2) return;
     const int pos = blockIdx.y, yo = pos / wo, xo = pos % wo, co0 = blockIdx.z * CONV_CO;
-    const int nco = min(CONV_CO, c_out - co0);
     uint64_t acc[CONV_CO];
 #pragma unroll
     for (int q = 0; q < CONV_CO; ++q) acc[q] = 0;
+    const int64_t ci_stride = (int64_t)k * k * cop;
     for (int dy = 0; dy < k; ++dy) {
         const int y = stride * yo + dy - k / 2;
         if (y < 0 || y >= h) continue;
@@ -305,18 +315,27 @@ __global__ void __launch_bounds__(256) k_nat_conv(const uint64_t *__restrict__ r
             const int x = stride * xo + dx - k / 2;
             if (x < 0 || x >= w) continue;
             const uint64_t *in = rows + ((int64_t)(y * w + x) * c_in) * n2 + col;
+            const int32_t *wp = wT + (int64_t)(dy * k + dx) * cop + co0;
             for (int ci = 0; ci < c_in; ++ci) {
                 const uint64_t v = in[(int64_t)ci * n2];
-                const int32_t *wp = wts + ((int64_t)co0 * c_in + ci) * k * k + dy * k + dx;
+                const int4 *w4 = (const int4 *)(wp + ci * ci_stride);
+                int32_t wv[CONV_CO];
 #pragma unroll
-                for (int q = 0; q < CONV_CO; ++q)
-                    if (q < nco) acc[q] += (uint64_t)(int64_t)wp[(int64_t)q * c_in * k * k] * v;
+                for (int q4 = 0; q4 < CONV_CO / 4; ++q4) {
+                    const int4 t4 = w4[q4];
+                    wv[4 * q4] = t4.x;
+                    wv[4 * q4 + 1] = t4.y;
+                    wv[4 * q4 + 2] = t4.z;
+                    wv[4 * q4 + 3] = t4.w;
+                }
+#pragma unroll
+                for (int q = 0; q < CONV_CO; ++q) acc[q] += (uint64_t)(int64_t)wv[q] * v;
             }
         }
     }
 #pragma unroll
     for (int q = 0; q < CONV_CO; ++q)
-        if (q < nco) out[(int64_t)out_row[pos * c_out + co0 + q] * n2 + col] = acc[q];
+        if (co0 + q < c_out) out[(int64_t)out_row[pos * c_out + co0 + q] * n2 + col] = acc[q];
 }
 
 // ---------------------------------------------------------------------------
@@ -373,7 +392,7 @@ __global__ void __launch_bounds__(256) k_nat_aut_decomp8(const uint64_t *__restr
 // independent of how the instruction orders k; result lane l, register r: row
 // 4 (l / 16) + r, column l mod 16.  Byte planes go one at a time (b outer), each
 // folded into the 64-bit results after its K loop.  grid.z splits K as in k_nat_ksprod.
-__global__ void __launch_bounds__(256) k_nat_ksprod8(const int8_t *__restrict__ A8, int64_t a_half,
+__global__ void __launch_bounds__(256, 2) k_nat_ksprod8(const int8_t *__restrict__ A8, int64_t a_half,
                                                      const int8_t *__restrict__ B8, uint64_t *__restrict__ out,
                                                      int64_t out_es, int n, int N, int KDp, int kc) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -671,6 +690,7 @@ void native_destroy(Native *n) {
     nat_prof_drain(n);
     if (n->kmat) (void)hipFree(n->kmat);
     if (n->kmat8) (void)hipFree(n->kmat8);
+    if (n->wt) (void)hipFree(n->wt);
     if (n->kcorr) (void)hipFree(n->kcorr);
     if (n->ws) (void)hipFree(n->ws);
     delete n;
@@ -915,15 +935,34 @@ int native_conv(Native *n, int c_in, int c_out, int h, int w, int k, int stride,
     FL_CHECK(c_in >= 1 && c_out >= 1 && h >= 1 && w >= 1 && k >= 1 && k % 2 == 1 && stride >= 1,
              FHELIN_E_INVALID_ARG, "native_conv: need positive sizes, an odd kernel and a positive stride");
     const int ho = (h - 1) / stride + 1, wo = (w - 1) / stride + 1;
-    FL_CHECK(ho * wo <= 65535 && (c_out + CONV_CO - 1) / CONV_CO <= 65535, FHELIN_E_INVALID_ARG,
-             "native_conv: too many output positions");
+    const int cop = (c_out + CONV_CO - 1) / CONV_CO * CONV_CO;
+    FL_CHECK(ho * wo <= 65535 && cop / CONV_CO <= 65535 && (int64_t)c_in * k * k * cop <= (1 << 26),
+             FHELIN_E_INVALID_ARG, "native_conv: layer too large");
+    // the transposed weights live in the handle (calls sharing the handle must not overlap)
+    const size_t wbytes = (size_t)c_in * k * k * cop * sizeof(int32_t);
+    if (n->wt_bytes < wbytes) {
+        if (n->wt) {
+            FL_TRY_HIP(hipStreamSynchronize(s));
+            FL_TRY_HIP(hipFree(n->wt));
+            n->wt = nullptr;
+            n->wt_bytes = 0;
+        }
+        if (hipMalloc((void **)&n->wt, wbytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return set_error(FHELIN_E_OOM, "native_conv: device allocation failed");
+        }
+        n->wt_bytes = wbytes;
+    }
+    hipLaunchKernelGGL(k_nat_conv_wt, dim3((unsigned)((wbytes / 4 + 255) / 256)), dim3(256), 0, s, wts, n->wt, c_in, c_out,
+                       k, cop);
+    FL_TRY_HIP(hipGetLastError());
     const int n2 = 2 * n->N;
     // units: products; bytes: every input row once and the outputs (a row shared by
     // overlapping windows is read again from the caches)
     NatProf ps(n, s, NK_LINEAR, (double)ho * wo * c_out * c_in * k * k * n2,
                ((double)c_in * h * w + (double)c_out * ho * wo) * n2 * 8.0);
-    hipLaunchKernelGGL(k_nat_conv, dim3((n2 + 255) / 256, ho * wo, (c_out + CONV_CO - 1) / CONV_CO), dim3(256), 0, s,
-                       rows, wts, out_row, out, c_in, c_out, h, w, k, stride, wo, n2);
+    hipLaunchKernelGGL(k_nat_conv, dim3((n2 + 255) / 256, ho * wo, cop / CONV_CO), dim3(256), 0, s, rows, n->wt, out_row,
+                       out, c_in, c_out, cop, h, w, k, stride, wo, n2);
     FL_TRY_HIP(hipGetLastError());
     return FHELIN_OK;
 }
