@@ -129,6 +129,9 @@ int fhelin_ctx_root(const fhelin_ctx *ctx, int32_t mod_index, uint64_t *psi);
  * transformed to the NTT domain and kept resident.  Charged to the budget. */
 int fhelin_keyset_load(fhelin_ctx *ctx, const uint32_t *galois, int32_t n_keys, int32_t level,
                        const uint64_t *evk, int32_t src_on_device, void *stream, fhelin_keyset **out);
+/* Release waits on the host for the load and for every use of the key set enqueued
+ * so far (layer calls, rotations, graph replays), each on its own stream, then
+ * frees it; other streams keep running. */
 int fhelin_keyset_release(fhelin_keyset *ks);
 
 /* ---- plaintexts -------------------------------------------------------- */
@@ -150,6 +153,7 @@ int fhelin_pt_encode(fhelin_ctx *ctx, const double *slots, int32_t n_pt, int32_t
  * (device; q rows 0..level-1 then the special rows), level <= the set's level. */
 int fhelin_pt_export(fhelin_ctx *ctx, const fhelin_ptset *pts, int32_t level, uint64_t *out, void *stream);
 int fhelin_ptset_info(const fhelin_ptset *pts, int32_t *n_pt, int32_t *level);
+/* Like fhelin_keyset_release: waits for the set's own uses, not the device. */
 int fhelin_ptset_release(fhelin_ptset *pts);
 
 /* ---- linear-layer plans ------------------------------------------------ */

@@ -21,6 +21,8 @@ int plan_autotune(Ctx *c, Plan *p, const KeySet *const *kss, const PtSet *pts, c
 // buffers, replayed with hipGraphLaunch.
 struct Graph {
     Ctx *ctx = nullptr;
+    const KeySet *ks = nullptr;  // the key and plaintext sets the captured kernels read
+    const PtSet *pts = nullptr;
     std::shared_ptr<WsBuf> ws;  // the workspace the captured kernels use
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -38,6 +40,8 @@ static int graph_capture_linear(Ctx *c, const Plan *p, const KeySet *ks, const P
     uint64_t *ws;
     std::unique_ptr<Graph> gr(new Graph());
     gr->ctx = c;
+    gr->ks = ks;
+    gr->pts = pts;
     FL_RET(workspace_get(c, s, linear_workspace_bytes(c, p, in->n_ct / std::max(1, p->n_in), MAX_BATCH, flags), &ws,
                          &gr->ws));
     const int R = in->n_ct / std::max(1, p->n_in);
@@ -379,7 +383,9 @@ FHELIN_EXPORT int fhelin_keyset_release(fhelin_keyset *ks) {
                        "keyset_release: null, unknown or released key set handle");
     KeySet *k = (KeySet *)ks;
     DeviceGuard g(k->ctx);
-    (void)hipDeviceSynchronize();
+    // wait for the load and for the uses enqueued since, on their own streams only
+    (void)k->ready.host_wait();
+    k->uses.host_wait();
     keyset_free(k);
     return FHELIN_OK;
     API_END
@@ -420,7 +426,9 @@ FHELIN_EXPORT int fhelin_pt_export(fhelin_ctx *ctx, const fhelin_ptset *pts, int
     API_BEGIN FL_CHECK(ctx && pts, FHELIN_E_INVALID_ARG, "null argument");
     Ctx *c = (Ctx *)ctx;
     DeviceGuard g(c);
-    return pt_export(c, (const PtSet *)pts, level, out, (hipStream_t)stream);
+    const int rc = pt_export(c, (const PtSet *)pts, level, out, (hipStream_t)stream);
+    ((const PtSet *)pts)->uses.note((hipStream_t)stream);
+    return rc;
     API_END
 }
 
@@ -438,7 +446,8 @@ FHELIN_EXPORT int fhelin_ptset_release(fhelin_ptset *pts) {
                        "ptset_release: null, unknown or released plaintext set handle");
     PtSet *p = (PtSet *)pts;
     DeviceGuard g(p->ctx);
-    (void)hipDeviceSynchronize();
+    (void)p->ready.host_wait();
+    p->uses.host_wait();
     ptset_free(p);
     return FHELIN_OK;
     API_END
@@ -678,6 +687,9 @@ FHELIN_EXPORT int fhelin_graph_launch(fhelin_graph *graph, void *stream) {
     Graph *gr = (Graph *)graph;
     DeviceGuard g(gr->ctx);
     FL_TRY_HIP(hipGraphLaunch(gr->exec, (hipStream_t)stream));
+    // a release of the sets waits for this replay (the graph must not outlive them)
+    if (gr->ks && live_has(H_KEYSET, gr->ks)) gr->ks->uses.note((hipStream_t)stream);
+    if (gr->pts && live_has(H_PTSET, gr->pts)) gr->pts->uses.note((hipStream_t)stream);
     return FHELIN_OK;
     API_END
 }

@@ -419,6 +419,33 @@ Ready::~Ready() {
     if (ev) (void)hipEventDestroy(ev);
 }
 
+void UseLog::note(hipStream_t s) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
+    std::lock_guard<std::mutex> g(mu);
+    for (auto &e : ev)
+        if (e.first == s) {
+            (void)hipEventRecord(e.second, s);
+            return;
+        }
+    hipEvent_t e;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        return;
+    }
+    (void)hipEventRecord(e, s);
+    ev.emplace_back(s, e);
+}
+
+void UseLog::host_wait() {
+    std::lock_guard<std::mutex> g(mu);
+    for (auto &e : ev) (void)hipEventSynchronize(e.second);
+}
+
+UseLog::~UseLog() {
+    for (auto &e : ev) (void)hipEventDestroy(e.second);
+}
+
 Ctx::~Ctx() {
     ws.clear();
     for (auto &b : cache) (void)hipFree(b.second);

@@ -299,6 +299,21 @@ struct Ready {
     ~Ready();
 };
 
+// The streams a key or plaintext set was used on, each with an event recorded after
+// its last use enqueued there: a release waits for these uses, not for the whole
+// device.  note() is skipped while the stream is capturing (a graph launch notes its
+// own uses).
+struct UseLog {
+    std::mutex mu;
+    std::vector<std::pair<hipStream_t, hipEvent_t>> ev;
+    void note(hipStream_t s);
+    void host_wait();
+    UseLog() = default;
+    UseLog(const UseLog &) = delete;
+    UseLog &operator=(const UseLog &) = delete;
+    ~UseLog();
+};
+
 struct KeySet {
     Ctx *ctx = nullptr;
     int level = 0, beta = 0, n_keys = 0;
@@ -306,6 +321,7 @@ struct KeySet {
     uint64_t *evk = nullptr;
     size_t bytes = 0;
     Ready ready;
+    mutable UseLog uses;
     int64_t key_stride() const { return (int64_t)beta * 2 * (level + ctx->K) * ctx->N; }
     const uint64_t *key_ptr(int idx) const { return evk + (int64_t)idx * key_stride(); }
     int find(uint32_t g) const {
@@ -321,6 +337,7 @@ struct PtSet {
     uint64_t *data = nullptr;  // [n_pt][level][N], NTT domain, Montgomery form
     size_t bytes = 0;
     Ready ready;
+    mutable UseLog uses;
 };
 
 // Tile and chunk choices of a layer schedule (results do not depend on them).  The

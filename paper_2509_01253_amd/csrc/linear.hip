@@ -1089,6 +1089,19 @@ int linear_apply(Ctx *c, const Plan *p, const KeySet *const *kss, const PtSet *p
         }
     }
     if (R == 0) return FHELIN_OK;
+    // whatever this call enqueues, the key and plaintext sets' release waits for it
+    struct NoteUses {
+        const KeySet *const *kss;
+        const PtSet *pts;
+        int R;
+        hipStream_t s;
+        ~NoteUses() {
+            pts->uses.note(s);
+            const KeySet *prev = nullptr;
+            for (int r = 0; kss && r < R; ++r)
+                if (kss[r] && kss[r] != prev) (prev = kss[r])->uses.note(s);
+        }
+    } note_uses{p->galois.empty() ? nullptr : kss, pts, R, s};
     // the plan's NTT tile for every transform this call launches (restored on return)
     struct NttTile {
         int prev;
@@ -1320,6 +1333,13 @@ int rotate_batch(Ctx *c, const KeySet *ks, const fhelin_ct_batch *in, const int3
         FL_CHECK(in->levels[t] <= ks->level, FHELIN_E_LEVEL_MISMATCH, "keys loaded below the ciphertext level");
     }
     if (ks) FL_RET(ks->ready.wait(s));
+    struct NoteUse {
+        const KeySet *ks;
+        hipStream_t s;
+        ~NoteUse() {
+            if (ks) ks->uses.note(s);
+        }
+    } note_use{ks, s};
     const int64_t N = c->N, L = c->L, K = c->K;
     const int64_t ct = 2 * L * N, dg = (int64_t)c->dnum * (L + K) * N;
     const int64_t per = ct * 2 + L * N + dg + 2 * (L + K) * N + 2 * L * N;

@@ -785,3 +785,52 @@ def test_persistent_modup_ntt_bit_exact(F, dh):
             F.fhelin_plan_destroy(plan)
         finally:
             F.fhelin_ctx_destroy(ctx)
+
+
+def test_release_waits_for_the_sets_own_uses(F):
+    """Key and plaintext sets released right after a layer call on one stream (no
+    synchronisation by the caller) are freed only after that call's work: a key set of
+    another client loaded at once on a second stream -- into the released block, which
+    the context reuses -- does not disturb the first call's results (three rounds)."""
+    import torch
+    print("release waits for uses", flush=True)
+    prm = O.make_params(12, 5, 2, 3, 50, 2.0 ** 40)
+    st = synth.Stream(5600)
+    n, n1 = 64, 8
+    W = st.he_normal((n, n), n)
+    sched = O.fc_schedule(n, n1)
+    pts = encode_pts(prm, O.fc_slots(W, n, n1, prm.S), prm.L, prm.scale)
+    cl = Client(prm, 5601)
+    keys = cl.keyset(sched.rotations())
+    other = Client(prm, 5602).keyset(sched.rotations())
+    levels = [5, 4, 5, 3, 5, 2, 4, 5]
+    cts = [cl.encrypt_slots(O.fc_input_slots(st.uniform(n, 0, 1), n, prm.S), l, prm.scale) for l in levels]
+    want = [O.rescale(prm, O.linear(prm, c[None], l, sched, pts, keys, hoist_moddown=True)[0], l)
+            for c, l in zip(cts, levels)]
+    ctx = ctx_for(F, prm)
+    try:
+        plan = F.fhelin_plan_create(ctx, F.FHELIN_LAYER_FC, fc_n=n, fc_out=n, fc_in=n, n1=n1)
+        evk, evk2 = dev(keys_at(prm, keys, prm.L)), dev(keys_at(prm, other, prm.L))
+        pt_dev = dev(pts.reshape(-1, prm.L + prm.K, prm.N))
+        x = dev(pad_cts(cts, prm.L, prm.N))
+        torch.cuda.synchronize()
+        s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+        flags = F.FHELIN_APPLY_RESCALE | F.FHELIN_APPLY_HOIST_MODDOWN
+        for rnd in range(3):
+            with torch.cuda.stream(s1):
+                y = torch.zeros((len(cts), 2, prm.L, prm.N), dtype=torch.int64, device="cuda")
+            ks = F.fhelin_keyset_load(ctx, keys.galois, prm.L, evk, stream=s1)
+            pset = F.fhelin_pt_import(ctx, pt_dev, level=prm.L, stream=s1)
+            F.fhelin_linear_apply(ctx, plan, ks, pset, x, levels, y, [l - 1 for l in levels], flags, stream=s1)
+            F.fhelin_keyset_release(ks)
+            F.fhelin_ptset_release(pset)
+            ks2 = F.fhelin_keyset_load(ctx, other.galois, prm.L, evk2, stream=s2)
+            s1.synchronize()
+            s2.synchronize()
+            got = host(y)
+            for t, l in enumerate(levels):
+                assert np.array_equal(got[t, :, : l - 1], want[t]), (rnd, t)
+            F.fhelin_keyset_release(ks2)
+        F.fhelin_plan_destroy(plan)
+    finally:
+        F.fhelin_ctx_destroy(ctx)

@@ -203,3 +203,102 @@ def test_served_shuffled_rounds_fold_the_session_permutations():
         assert np.abs(dec - ref).max() / np.abs(ref).max() < 1e-3, r.rid
     assert len(seen) == 9  # every (session, hidden round) drew its own permutation
     ex.close()
+
+
+def test_served_with_batch_size_dependent_schedules():
+    """A layer registered with two schedules by batch size (per-rotation ModDown for a
+    request alone, double-hoisted for batches): every served result equals the oracle's
+    layer under the schedule its batch selected and decrypts to the FP64 layer; and an
+    N = 2^15 convolution (12 3x3 channels, uniform keys) served in batches equals each
+    request evaluated alone."""
+    import torch
+
+    from paper_2509_01253_amd import fhelin as F
+    from paper_2509_01253_amd.serving import GpuExecutor, Request, Server
+    print("serving two schedules", flush=True)
+    st = synth.Stream(synth.master_seed(5)).sub(91)
+    rot = F.FHELIN_APPLY_RESCALE
+    dh = F.FHELIN_APPLY_RESCALE | F.FHELIN_APPLY_HOIST_MODDOWN
+    ex = GpuExecutor(n_streams=2)
+    prm = O.make_params(12, 5, 2, 3, 50, 2.0 ** 40)
+    ex.add_params("A", prm.log_n, prm.q, prm.p, prm.dnum)
+    n, n1 = 64, 8
+    W = st.he_normal((n, n), n)
+    sched = O.fc_schedule(n, n1)
+    pts = encode_pts(prm, O.fc_slots(W, n, n1, prm.S), prm.L, prm.scale)
+    pset = F.fhelin_pt_import(ex.params["A"]["ctx"], dev(pts.reshape(-1, prm.L + prm.K, prm.N)), level=prm.L)
+    ex.add_layer("fc", "A", dict(fc_n=n, fc_out=n, fc_in=n, n1=n1), F.FHELIN_LAYER_FC, pset,
+                 flags=[(1, rot), (8, dh)])
+    # the N = 2^15 convolution with uniform keys and plaintexts
+    pb = O.make_params(15, 6, 2, 3, 50, 2.0 ** 40)
+    ex.add_params("B", pb.log_n, pb.q, pb.p, pb.dnum)
+    cs = O.ConvShape(12, 12, 32, 32, 3)
+    sched_b = O.conv_schedule(cs, pb.S)
+    lvl_b = 4
+    n_pt_b = sched_b.n_out * sched_b.n_in * sched_b.G * sched_b.B
+    pts_b = np.stack([synth.uniform_limbs(st, pb.q[:lvl_b] + pb.p, pb.N) for _ in range(n_pt_b)])
+    pset_b = F.fhelin_pt_import(ex.params["B"]["ctx"], dev(pts_b), level=lvl_b)
+    ex.add_layer("conv", "B", dict(c_in=12, c_out=12, h=32, w=32, k=3), F.FHELIN_LAYER_CONV, pset_b)
+    gal_b = F.fhelin_plan_galois(ex.layers["conv"]["plan"])
+    clients = []
+    for ci in range(3):
+        cl = Client(prm, 9200 + ci)
+        keys = cl.keyset(sched.rotations())
+        evk = keys_at(prm, keys, prm.L)
+        ex.add_client_keys(f"c{ci}", "A", (lambda g=keys.galois, e=evk: (lambda s: (g, prm.L, dev(e))))(),
+                           int(evk.nbytes))
+        kb = np.stack([np.stack([np.stack([synth.uniform_limbs(st, pb.q[:lvl_b] + pb.p, pb.N) for _ in range(2)])
+                                 for _ in range(pb.beta(lvl_b))]) for _ in gal_b])
+        ex.add_client_keys(f"c{ci}", "B", (lambda g=gal_b, e=kb: (lambda s: (g, lvl_b, dev(e))))(), int(kb.nbytes))
+        clients.append((cl, keys, kb))
+    srv = Server(ex, hbm_budget=16 << 30, streams=2, max_batch=8)
+    for ci in range(3):
+        srv.open_session(f"s{ci}", f"c{ci}")
+    reqs, plain, rnd = [], {}, [1, 1, 1]
+    # a burst (batched, double-hoisted) then spaced arrivals (alone, per-rotation), then
+    # a burst of convolutions
+    times = [0.0] * 6 + [0.3, 0.6, 0.9] + [1.2] * 6
+    for i, tt in enumerate(times):
+        ci = i % 3
+        cl, keys, kb = clients[ci]
+        if i < 9:
+            level = [5, 4, 3][i % 3]
+            x = st.uniform(n, 0, 1)
+            ct = cl.encrypt_slots(O.fc_input_slots(x, n, prm.S), level, prm.scale)
+            t = dev(pad_cts([ct], prm.L, prm.N))
+            reqs.append((tt, Request(i, f"c{ci}", f"s{ci}", rnd[ci], "fc", level, t)))
+            plain[i] = ("fc", ci, ct, level, x)
+        else:
+            cts = [np.stack([synth.uniform_limbs(st, pb.q[:lvl_b], pb.N) for _ in range(2)])
+                   for _ in range(sched_b.n_in)]
+            t = dev(pad_cts(cts, pb.L, pb.N))
+            reqs.append((tt, Request(i, f"c{ci}", f"s{ci}", rnd[ci], "conv", lvl_b, t)))
+            plain[i] = ("conv", ci, cts, lvl_b, None)
+        rnd[ci] += 1
+    torch.cuda.synchronize()
+    res = srv.run(reqs)
+    print(srv.stats(res), flush=True)
+    sizes = {r.rid: r.batch for r in res}
+    assert any(sizes[i] == 1 for i in range(6, 9)) and any(sizes[i] > 1 for i in range(6))
+    for r in res:
+        assert r.status == "ok", r.rid
+        kind, ci, cts, level, x = plain[r.rid]
+        got = host(r.y)
+        if kind == "fc":
+            cl, keys, _ = clients[ci]
+            fl = ex.layer_flags("fc", r.batch)
+            want = O.rescale(prm, O.linear(prm, cts[None], level, sched, pts, keys,
+                                           hoist_moddown=bool(fl & F.FHELIN_APPLY_HOIST_MODDOWN))[0], level)
+            assert np.array_equal(got[0, :, : level - 1], want), (r.rid, r.batch)
+            z = cl.decrypt_slots(want, level - 1, prm.scale ** 2 / prm.q[level - 1]).real[:n]
+            assert np.abs(z - W @ x).max() / np.abs(W @ x).max() < 1e-3, r.rid
+        else:
+            ctx = ex.params["B"]["ctx"]
+            ks = F.fhelin_keyset_load(ctx, gal_b, lvl_b, dev(clients[ci][2]))
+            y1 = dev(np.zeros((sched_b.n_out, 2, pb.L, pb.N), np.uint64))
+            F.fhelin_linear_apply(ctx, ex.layers["conv"]["plan"], ks, pset_b, dev(pad_cts(cts, pb.L, pb.N)),
+                                  [lvl_b] * len(cts), y1, [lvl_b - 1] * sched_b.n_out, ex.layer_flags("conv", 1))
+            alone = host(y1)
+            F.fhelin_keyset_release(ks)
+            assert np.array_equal(got[:, :, : lvl_b - 1], alone[:, :, : lvl_b - 1]), r.rid
+    ex.close()
