@@ -391,12 +391,21 @@ __global__ void __launch_bounds__(256) k_nat_aut_decomp8(const uint64_t *__restr
 // k0 + 16 (l / 16), the same k positions for both operands, so the product is
 // independent of how the instruction orders k; result lane l, register r: row
 // 4 (l / 16) + r, column l mod 16.  Byte planes go one at a time (b outer), each
-// folded into the 64-bit results after its K loop.  grid.z splits K as in k_nat_ksprod.
+// folded into the 64-bit results after its K loop.  A K chunk of both operands (the
+// digit halves of 64 ciphertexts, both key parts of 64 coefficients: 16 KiB) is staged
+// in LDS once per workgroup, double-buffered: the next chunk's global loads are in
+// flight while the current one's products run.  Rows are padded to 80 bytes.
+// grid.z splits K as in k_nat_ksprod.
+constexpr int K8_ROW = 5;  // 16-byte words per staged row (4 used)
+
 __global__ void __launch_bounds__(256, 2) k_nat_ksprod8(const int8_t *__restrict__ A8, int64_t a_half,
                                                      const int8_t *__restrict__ B8, uint64_t *__restrict__ out,
                                                      int64_t out_es, int n, int N, int KDp, int kc) {
+    __shared__ v4i As[2][2][64 * K8_ROW];  // [buffer][digit half][row * 5 + word]
+    __shared__ v4i Bs[2][2][64 * K8_ROW];  // [buffer][key part][row * 5 + word]
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int cbase = blockIdx.y * 64 + (w & 1) * 32, jbase = blockIdx.x * 64 + (w >> 1) * 32;
+    const int c0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
+    const int wc = (w & 1) * 32, wj = (w >> 1) * 32;
     const int kb = blockIdx.z * kc, ke = min(KDp, kb + kc);
     const int r16 = lane & 15, g = lane >> 4;
     const int64_t plane = (int64_t)N * KDp;
@@ -409,17 +418,39 @@ __global__ void __launch_bounds__(256, 2) k_nat_ksprod8(const int8_t *__restrict
             for (int bq = 0; bq < 2; ++bq)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) res[p][a][bq][r] = 0;
-    // the lane's rows; rows past the batch or the ring read row 0 and are masked
-    int crow[2], jrow[2];
-    bool cok[2], jok[2];
+    // staging role: thread t moves words t and t + 256 of each operand (word = half or
+    // part, row, 16-byte quarter of the 64-byte chunk row)
+    int sh[2], srow[2], sq[2];
+    bool aok[2], bok[2];
 #pragma unroll
-    for (int t2 = 0; t2 < 2; ++t2) {
-        crow[t2] = cbase + t2 * 16 + r16;
-        cok[t2] = crow[t2] < n;
-        jrow[t2] = jbase + t2 * 16 + r16;
-        jok[t2] = jrow[t2] < N;
+    for (int u = 0; u < 2; ++u) {
+        const int idx = threadIdx.x + 256 * u;
+        sh[u] = idx >> 8;
+        srow[u] = (idx >> 2) & 63;
+        sq[u] = idx & 3;
+        aok[u] = c0 + srow[u] < n;
+        bok[u] = j0 + srow[u] < N;
     }
     for (int b = 0; b < 8; ++b) {
+        const int8_t *Bp = B8 + (int64_t)b * plane;
+        v4i ra[2], rb[2];
+        auto gload = [&](int k0) {
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int k = k0 + 16 * sq[u];
+                const v4i va = *(const v4i *)(A8 + sh[u] * a_half + (int64_t)(aok[u] ? c0 + srow[u] : 0) * KDp + k);
+                ra[u] = aok[u] ? va : v4i{0, 0, 0, 0};
+                const v4i vb = *(const v4i *)(Bp + sh[u] * 8 * plane + (int64_t)(bok[u] ? j0 + srow[u] : 0) * KDp + k);
+                rb[u] = bok[u] ? vb : v4i{0, 0, 0, 0};
+            }
+        };
+        auto sstore = [&](int buf) {
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                As[buf][sh[u]][srow[u] * K8_ROW + sq[u]] = ra[u];
+                Bs[buf][sh[u]][srow[u] * K8_ROW + sq[u]] = rb[u];
+            }
+        };
         v4i acc[2][2][2][2];  // [part][half][c tile][j tile]
 #pragma unroll
         for (int p = 0; p < 2; ++p)
@@ -429,21 +460,23 @@ __global__ void __launch_bounds__(256, 2) k_nat_ksprod8(const int8_t *__restrict
                 for (int a = 0; a < 2; ++a)
 #pragma unroll
                     for (int bq = 0; bq < 2; ++bq) acc[p][h][a][bq] = v4i{0, 0, 0, 0};
+        __syncthreads();  // the previous plane's readers are done with both buffers
+        if (kb < ke) {
+            gload(kb);
+            sstore(0);
+        }
+        __syncthreads();
+        int cur = 0;
         for (int k0 = kb; k0 < ke; k0 += 64) {
-            const int k = k0 + 16 * g;
+            const bool more = k0 + 64 < ke;
+            if (more) gload(k0 + 64);
             v4i af[2][2], bf[2][2];
 #pragma unroll
             for (int t2 = 0; t2 < 2; ++t2) {
 #pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    const v4i v = *(const v4i *)(A8 + h * a_half + (int64_t)(cok[t2] ? crow[t2] : 0) * KDp + k);
-                    af[h][t2] = cok[t2] ? v : v4i{0, 0, 0, 0};
-                }
+                for (int h = 0; h < 2; ++h) af[h][t2] = As[cur][h][(wc + t2 * 16 + r16) * K8_ROW + g];
 #pragma unroll
-                for (int p = 0; p < 2; ++p) {
-                    const v4i v = *(const v4i *)(B8 + (p * 8 + b) * plane + (int64_t)(jok[t2] ? jrow[t2] : 0) * KDp + k);
-                    bf[p][t2] = jok[t2] ? v : v4i{0, 0, 0, 0};
-                }
+                for (int p = 0; p < 2; ++p) bf[p][t2] = Bs[cur][p][(wj + t2 * 16 + r16) * K8_ROW + g];
             }
 #pragma unroll
             for (int p = 0; p < 2; ++p)
@@ -455,6 +488,9 @@ __global__ void __launch_bounds__(256, 2) k_nat_ksprod8(const int8_t *__restrict
                         for (int bq = 0; bq < 2; ++bq)
                             acc[p][h][a][bq] =
                                 __builtin_amdgcn_mfma_i32_16x16x64_i8(af[h][a], bf[p][bq], acc[p][h][a][bq], 0, 0, 0);
+            if (more) sstore(cur ^ 1);
+            __syncthreads();
+            cur ^= 1;
         }
 #pragma unroll
         for (int p = 0; p < 2; ++p)
@@ -472,12 +508,12 @@ __global__ void __launch_bounds__(256, 2) k_nat_ksprod8(const int8_t *__restrict
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int c = cbase + a * 16 + 4 * g + r;
+            const int c = c0 + wc + a * 16 + 4 * g + r;
             if (c >= n) continue;
             uint64_t *o = out + c * out_es;
 #pragma unroll
             for (int bq = 0; bq < 2; ++bq) {
-                const int j = jbase + bq * 16 + r16;
+                const int j = j0 + wj + bq * 16 + r16;
                 if (j >= N) continue;
 #pragma unroll
                 for (int p = 0; p < 2; ++p) {
