@@ -610,7 +610,8 @@ def resnet18_bench(args) -> dict:
 
 
 ALU_PROBES = {0: "v_add_u32", 1: "v_mul_lo_u32", 2: "v_mul_hi_u32", 3: "v_mad_u64_u32", 4: "v_fma_f64",
-              6: "v_lshl_add_u64", 7: "v_lshrrev_b64", 5: "ntt_butterfly", 8: "mac_product"}
+              6: "v_lshl_add_u64", 7: "v_lshrrev_b64", 5: "ntt_butterfly", 8: "mac_product",
+              9: "mfma_i32_16x16x64_i8"}
 
 
 # The paper's own pipeline (RLWE over Z_{2^64}[X]/Phi_M): its 8-bit parameter set
@@ -739,11 +740,12 @@ def native_bench(gamma: int, reps: int = 2, engine: int = 0) -> dict:
 def alu_rates(F) -> dict:
     """Clocks per wave-level instruction on one SIMD for the instructions the NTT and
     multiply-accumulate kernels are built from, and the rate of the register-resident
-    lazy NTT butterfly, at 4 and 8 waves per SIMD (fhelin_diag_alu_rate)."""
+    lazy NTT butterfly, at 4 and 8 waves per SIMD, and of the int8 matrix-core
+    product at 2 and 4 (fhelin_diag_alu_rate)."""
     out = {}
     for op, name in ALU_PROBES.items():
-        iters = (1 << 14) if op == 5 else (1 << 16) if op == 8 else (1 << 18)
-        for wps in (4, 8):
+        iters = (1 << 14) if op in (5, 9) else (1 << 16) if op == 8 else (1 << 18)
+        for wps in ((2, 4) if op == 9 else (4, 8)):
             ghz, clk, ops = F.fhelin_diag_alu_rate(op, wps, iters)
             out.setdefault(name, {})[f"waves_per_simd_{wps}"] = {
                 "ghz": round(ghz, 4), "clk_per_wave_op": round(clk, 3), "lane_ops_per_s": ops}

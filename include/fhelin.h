@@ -398,11 +398,13 @@ int fhelin_profile_read(fhelin_ctx *ctx, const char *kernel, int64_t *launches, 
  * lazy forward butterfly with 53-bit twiddle companions (16 per round, operands in
  * registers), 6 v_lshl_add_u64, 7 v_lshrrev_b64, 8 one product of the packed 28-bit
  * multiply-accumulate (four v_mad_u64_u32; one Montgomery reduction per 32
- * products, operands in registers).  Outputs (each may be NULL):
- * ghz = core clock measured in the
+ * products, operands in registers), 9 v_mfma_i32_16x16x64_i8 (the int8 matrix-core
+ * product of the native key-switch engine) on 16 independent accumulators per wave.
+ * Outputs (each may be NULL): ghz = core clock measured in the
  * kernel (clock counter over the constant-rate wall clock); clk_per_op = clocks per
  * wave-level operation on one SIMD (4 for a wave64 instruction issued at the full
- * rate); ops_per_s = lane-level operations per second over the whole GPU. */
+ * rate; for op 9 one matrix instruction); ops_per_s = lane-level operations per
+ * second over the whole GPU (op 9: int8 operations, a multiply-add counting two). */
 int fhelin_diag_alu_rate(int32_t op, int32_t waves_per_simd, int32_t iters, double *ghz, double *clk_per_op,
                          double *ops_per_s);
 

@@ -31,6 +31,7 @@ enum DiagOp : int {
     DIAG_LSHL_ADD_U64 = 6,
     DIAG_LSHRREV_B64 = 7,
     DIAG_MAC28 = 8,
+    DIAG_MFMA_I8 = 9,
 };
 
 __device__ __forceinline__ void diag_stamp(uint64_t *stamps, uint64_t c0, uint64_t r0) {
@@ -135,8 +136,37 @@ __global__ void __launch_bounds__(256) k_diag_mac28(uint64_t *__restrict__ sink,
     sink[tid] = s;
 }
 
+// The int8 matrix-core product of the key-switch engine: v_mfma_i32_16x16x64_i8 on
+// MFMA_ACCS independent accumulators per wave (the product kernel keeps 16), operands in
+// registers, 16 instructions per round.
+constexpr int MFMA_ACCS = 16;
+typedef int diag_v4i __attribute__((ext_vector_type(4)));
+__global__ void __launch_bounds__(256) k_diag_mfma_i8(uint64_t *__restrict__ sink, uint64_t *__restrict__ stamps,
+                                                      int iters) {
+    const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+    diag_v4i a[2], b[2], acc[MFMA_ACCS];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        a[i] = diag_v4i{(int)(tid * 2654435761u + i), (int)tid, i, 3};
+        b[i] = diag_v4i{(int)(tid ^ 0x5bd1e995u), i, (int)tid + 7, 1};
+    }
+#pragma unroll
+    for (int i = 0; i < MFMA_ACCS; ++i) acc[i] = diag_v4i{0, 0, 0, 0};
+    const uint64_t c0 = clock64(), r0 = wall_clock64();
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int i = 0; i < MFMA_ACCS; ++i)
+            acc[i] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[i & 1], b[(i >> 1) & 1], acc[i], 0, 0, 0);
+    }
+    diag_stamp(stamps, c0, r0);
+    uint64_t s = 0;
+#pragma unroll
+    for (int i = 0; i < MFMA_ACCS; ++i) s ^= (uint64_t)(uint32_t)(acc[i][0] ^ acc[i][1] ^ acc[i][2] ^ acc[i][3]) << (i & 31);
+    sink[tid] = s;
+}
+
 int diag_alu_rate(int op, int waves_per_simd, int iters, double *ghz, double *clk_per_op, double *ops_per_s) {
-    FL_CHECK(op >= DIAG_ADD_U32 && op <= DIAG_MAC28, FHELIN_E_INVALID_ARG, "diag: unknown probe");
+    FL_CHECK(op >= DIAG_ADD_U32 && op <= DIAG_MFMA_I8, FHELIN_E_INVALID_ARG, "diag: unknown probe");
     FL_CHECK(waves_per_simd >= 1 && waves_per_simd <= 8, FHELIN_E_INVALID_ARG, "diag: waves_per_simd in 1..8");
     FL_CHECK(iters >= 32 && iters <= (1 << 24) && iters % 32 == 0, FHELIN_E_INVALID_ARG,
              "diag: iters must be a multiple of 32 in [32, 2^24]");
@@ -171,6 +201,7 @@ int diag_alu_rate(int op, int waves_per_simd, int iters, double *ghz, double *cl
         case DIAG_LSHL_ADD_U64: hipLaunchKernelGGL(k_diag_op<DIAG_LSHL_ADD_U64>, dim3(blocks), dim3(256), 0, 0, sink, stamps, iters, 1u); break;
         case DIAG_LSHRREV_B64: hipLaunchKernelGGL(k_diag_op<DIAG_LSHRREV_B64>, dim3(blocks), dim3(256), 0, 0, sink, stamps, iters, 1u); break;
         case DIAG_MAC28: hipLaunchKernelGGL(k_diag_mac28, dim3(blocks), dim3(256), 0, 0, sink, stamps, iters, q, ninv); break;
+        case DIAG_MFMA_I8: hipLaunchKernelGGL(k_diag_mfma_i8, dim3(blocks), dim3(256), 0, 0, sink, stamps, iters); break;
         }
     };
     do {
@@ -208,13 +239,20 @@ int diag_alu_rate(int op, int waves_per_simd, int iters, double *ghz, double *cl
     }
     // operations per lane: single instructions count CHAINS per round; the butterfly
     // probe runs 16 butterflies per round, the multiply-accumulate probe MAC_CHAINS
-    // products per round
-    const double per_lane =
-        (op == DIAG_NTT_BFLY ? 16.0 : op == DIAG_MAC28 ? (double)MAC_CHAINS : (double)DIAG_CHAINS) * iters;
+    // products per round; the matrix-core probe MFMA_ACCS wave-level instructions per
+    // round, each 16 x 16 x 64 multiply-adds (2 int8 operations each)
+    const double per_lane = (op == DIAG_NTT_BFLY ? 16.0
+                             : op == DIAG_MAC28  ? (double)MAC_CHAINS
+                             : op == DIAG_MFMA_I8 ? (double)MFMA_ACCS
+                                                  : (double)DIAG_CHAINS) *
+                            iters;
     const double wave_ops_per_simd = per_lane * waves / (4.0 * cus);
     if (ghz) *ghz = f / 1e9;
     if (clk_per_op) *clk_per_op = ms > 0 ? (ms * 1e-3 * f) / wave_ops_per_simd : 0;
-    if (ops_per_s) *ops_per_s = ms > 0 ? per_lane * threads / (ms * 1e-3) : 0;
+    if (ops_per_s)
+        *ops_per_s = ms <= 0                ? 0
+                     : op == DIAG_MFMA_I8 ? per_lane * waves * (16.0 * 16 * 64 * 2) / (ms * 1e-3)
+                                          : per_lane * threads / (ms * 1e-3);
     return FHELIN_OK;
 }
 

@@ -24,6 +24,7 @@
 // Reduction of a cyclic index x < M: X^(N + r) = -sum_{k < t-1} X^(k M/t + r), so
 // coefficient j of a polynomial given modulo X^M - 1 as c is c[j] - c[N + j mod M/t].
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <vector>
 
@@ -348,19 +349,35 @@ __global__ void __launch_bounds__(256) k_nat_conv(const uint64_t *__restrict__ r
 // ---------------------------------------------------------------------------
 typedef int v4i __attribute__((ext_vector_type(4)));
 
-// digits of a batch as two int8 planes A8[h][c][KDp] (k = i N + m, zero past l N) and
-// the output's start value out = (add_a, add_b + sigma(b)); grid (ceil(N / 256), n)
+// Operand layout of the int8 product (digit halves and key byte planes alike): rows
+// in tiles of 64 (padded), each tile's K in 64-byte chunks, each chunk as four 1 KiB
+// blocks of 16 rows, so that one block is one contiguous load of 64 lanes x 16 bytes.
+// Within a block, quarter q (16 bytes) of row r sits in slot 4 r + (q ^ k8_swz(r)):
+// the 16 (or 8) lanes that one LDS read cycle serves then hit distinct banks.
+__device__ __forceinline__ int k8_swz(int r) { return ((r >> 2) & 1) | ((((r >> 1) ^ (r >> 3)) & 1) << 1); }
+
+// byte offset of (row, k) in one operand part with nkc 64-byte chunks per row
+__device__ __forceinline__ int64_t k8_at(int row, int k, int nkc) {
+    const int rr = row & 15, q = (k >> 4) & 3;
+    return (((int64_t)(row >> 6) * nkc + (k >> 6)) * 4 + ((row >> 4) & 3)) * 1024 + (4 * rr + (q ^ k8_swz(rr))) * 16 +
+           (k & 15);
+}
+
+// digits of a batch as two int8 planes (h = 0: low halves, 1: high), row c, k = i N + m
+// (zero past l N), in the tiled operand layout (a_half bytes per plane), and the
+// output's start value out = (add_a, add_b + sigma(b)); grid (ceil(N / 256), n)
 __global__ void __launch_bounds__(256) k_nat_aut_decomp8(const uint64_t *__restrict__ S, int64_t s_es,
                                                          const uint64_t *__restrict__ add, int64_t add_es,
                                                          uint64_t *__restrict__ out, int64_t out_es,
                                                          int8_t *__restrict__ A8, int64_t a_half, NatDims dm, int ginv,
                                                          int log_d, int l, int KDp) {
     const int j = blockIdx.x * 256 + threadIdx.x;
-    const int c = blockIdx.y;
-    int8_t *lo = A8 + (int64_t)c * KDp, *hi = lo + a_half;
+    const int c = blockIdx.y, nkc = KDp >> 6;
+    int8_t *lo = A8, *hi = A8 + a_half;
     if (j < KDp - l * dm.N) {  // the padding of the row
-        lo[l * dm.N + j] = 0;
-        hi[l * dm.N + j] = 0;
+        const int64_t o = k8_at(c, l * dm.N + j, nkc);
+        lo[o] = 0;
+        hi[o] = 0;
     }
     if (j >= dm.N) return;
     const uint64_t *a = S + c * s_es, *b = a + dm.N;
@@ -380,8 +397,9 @@ __global__ void __launch_bounds__(256) k_nat_aut_decomp8(const uint64_t *__restr
             top += 1;
         }
         const int h = (d + 8) >> 4;  // floor division: lo = d - 16 h in [-8, 8)
-        lo[i * dm.N + j] = (int8_t)(d - 16 * h);
-        hi[i * dm.N + j] = (int8_t)h;
+        const int64_t o = k8_at(c, i * dm.N + j, nkc);
+        lo[o] = (int8_t)(d - 16 * h);
+        hi[o] = (int8_t)h;
     }
 }
 
@@ -391,67 +409,111 @@ __global__ void __launch_bounds__(256) k_nat_aut_decomp8(const uint64_t *__restr
 // k0 + 16 (l / 16), the same k positions for both operands, so the product is
 // independent of how the instruction orders k; result lane l, register r: row
 // 4 (l / 16) + r, column l mod 16.  Byte planes go one at a time (b outer), each
-// folded into the 64-bit results after its K loop.  A K chunk of both operands (the
-// digit halves of 64 ciphertexts, both key parts of 64 coefficients: 16 KiB) is staged
-// in LDS once per workgroup, double-buffered: the next chunk's global loads are in
-// flight while the current one's products run.  Rows are padded to 80 bytes.
-// grid.z splits K as in k_nat_ksprod.
-constexpr int K8_ROW = 5;  // 16-byte words per staged row (4 used)
+// folded into the 64-bit results after its K loop.
+//
+// Staging: a stage is one 64-byte K chunk of both operands (the digit halves of 64
+// ciphertexts and both key parts of 64 coefficients: sixteen 1 KiB blocks of 16 rows,
+// each contiguous in the tiled operand layout and copied to LDS as it is).
+// The chunks of all planes form one sequence; their loads go straight from global
+// memory into a ring of K8_NS stages in LDS (global_load_lds, 16 bytes per lane, no
+// registers), K8_NS - 1 stages ahead of the products.  Each wave fills four blocks of
+// every stage and waits only for its own loads of the stage it reads next (vmcnt); a
+// barrier then tells every wave that all loads of that stage have landed and that the
+// slot it refills next has been read.  Fragments are double-buffered in registers, so
+// a stage's products run while the next stage's fragments are read.
+// Rows past the batch or the ring (the padding of the last tile) hold any values and
+// only feed outputs that are not written.  grid.z splits K as in k_nat_ksprod.
+constexpr int K8_NS = 4;             // stages in the LDS ring
+constexpr int K8_STAGE = 16 * 1024;  // bytes per stage
+
+typedef __attribute__((address_space(3))) void *lds_ptr_t;
+
+// wait until at most N vector-memory operations of this wave are outstanding and all
+// of its LDS operations are done
+template <int N>
+__device__ __forceinline__ void k8_wait() {
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (0 << 8));
+}
+
+// Tile of this workgroup.  Workgroups go to the eight XCDs round-robin by linear id;
+// each XCD is given a contiguous run of tiles instead, ordered in groups of K8_GROUP
+// ciphertext tiles (coefficient tiles outer within a group), so that the workgroups
+// resident on one XCD at a time share their digit and key chunks in its L2.  The K
+// split is outermost.
+constexpr int K8_GROUP = 8;
+__device__ __forceinline__ void k8_tile(int &tc, int &tj, int &tz) {
+    const int gx = gridDim.x, gy = gridDim.y, G = gx * gy * gridDim.z;
+    const int pid = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+    const int xcd = pid & 7, q = G >> 3, r = G & 7;
+    const int L = xcd * q + min(xcd, r) + (pid >> 3);
+    const int per_z = gx * gy;
+    tz = L / per_z;
+    const int m = L - tz * per_z, span = K8_GROUP * gx;
+    const int grp = m / span, first = grp * K8_GROUP, gsize = min(gy - first, K8_GROUP);
+    const int in = m - grp * span;
+    tc = first + in % gsize;
+    tj = in / gsize;
+}
 
 __global__ void __launch_bounds__(256, 2) k_nat_ksprod8(const int8_t *__restrict__ A8, int64_t a_half,
                                                      const int8_t *__restrict__ B8, uint64_t *__restrict__ out,
                                                      int64_t out_es, int n, int N, int KDp, int kc) {
-    __shared__ v4i As[2][2][64 * K8_ROW];  // [buffer][digit half][row * 5 + word]
-    __shared__ v4i Bs[2][2][64 * K8_ROW];  // [buffer][key part][row * 5 + word]
+    __shared__ __attribute__((aligned(16))) int8_t ring[K8_NS * K8_STAGE];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int c0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
+    int tc, tj, tz;
+    k8_tile(tc, tj, tz);
+    const int c0 = tc * 64, j0 = tj * 64;
     const int wc = (w & 1) * 32, wj = (w >> 1) * 32;
-    const int kb = blockIdx.z * kc, ke = min(KDp, kb + kc);
+    const int kb = tz * kc, ke = min(KDp, kb + kc);
+    const int nk = (ke - kb) >> 6, total = 8 * nk;  // chunks per plane, stages in all
     const int r16 = lane & 15, g = lane >> 4;
-    const int64_t plane = (int64_t)N * KDp;
+    const int64_t plane = (int64_t)((N + 63) & ~63) * KDp;  // bytes per key byte plane
+    // loads: wave w fills blocks 4w .. 4w + 3 of a stage (waves 0, 1: the digit halves,
+    // waves 2, 3: the key parts; block 4 s + t holds rows 16 t .. 16 t + 15 of operand
+    // part s), lane l the 16 bytes at 16 l of the block
+    const int nkc = KDp >> 6;
+    const int8_t *src[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int bl = 4 * w + i, part = (bl >> 2) & 1, t = bl & 3;
+        src[i] = (bl < 8 ? A8 + part * a_half + ((int64_t)tc * nkc * 4 + t) * 1024
+                         : B8 + (int64_t)part * 8 * plane + ((int64_t)tj * nkc * 4 + t) * 1024) +
+                 16 * lane;
+    }
+    auto issue = [&](int st) {
+        const int b = st / nk, kcs = (kb >> 6) + (st - b * nk);
+        const int64_t off = (w >= 2 ? (int64_t)b * plane : 0) + (int64_t)kcs * 4096;
+        int8_t *dst = ring + (st % K8_NS) * K8_STAGE + w * 4096;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            __builtin_amdgcn_global_load_lds((const void *)(src[i] + off), (lds_ptr_t)(dst + i * 1024), 16, 0, 0);
+    };
     uint64_t res[2][2][2][4];
+    v4i acc[2][2][2][2];  // [part][half][c tile][j tile]
 #pragma unroll
     for (int p = 0; p < 2; ++p)
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
-            for (int bq = 0; bq < 2; ++bq)
+            for (int bq = 0; bq < 2; ++bq) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) res[p][a][bq][r] = 0;
-    // staging role: thread t moves words t and t + 256 of each operand (word = half or
-    // part, row, 16-byte quarter of the 64-byte chunk row)
-    int sh[2], srow[2], sq[2];
-    bool aok[2], bok[2];
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-        const int idx = threadIdx.x + 256 * u;
-        sh[u] = idx >> 8;
-        srow[u] = (idx >> 2) & 63;
-        sq[u] = idx & 3;
-        aok[u] = c0 + srow[u] < n;
-        bok[u] = j0 + srow[u] < N;
-    }
-    for (int b = 0; b < 8; ++b) {
-        const int8_t *Bp = B8 + (int64_t)b * plane;
-        v4i ra[2], rb[2];
-        auto gload = [&](int k0) {
-#pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                const int k = k0 + 16 * sq[u];
-                const v4i va = *(const v4i *)(A8 + sh[u] * a_half + (int64_t)(aok[u] ? c0 + srow[u] : 0) * KDp + k);
-                ra[u] = aok[u] ? va : v4i{0, 0, 0, 0};
-                const v4i vb = *(const v4i *)(Bp + sh[u] * 8 * plane + (int64_t)(bok[u] ? j0 + srow[u] : 0) * KDp + k);
-                rb[u] = bok[u] ? vb : v4i{0, 0, 0, 0};
+                for (int h = 0; h < 2; ++h) acc[p][h][a][bq] = v4i{0, 0, 0, 0};
             }
-        };
-        auto sstore = [&](int buf) {
+    const int slot = 16 * (4 * r16 + (g ^ k8_swz(r16)));
+    auto frags = [&](v4i (&af)[2][2], v4i (&bf)[2][2], int st) {
+        const int8_t *stg = ring + (st % K8_NS) * K8_STAGE + slot;
 #pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                As[buf][sh[u]][srow[u] * K8_ROW + sq[u]] = ra[u];
-                Bs[buf][sh[u]][srow[u] * K8_ROW + sq[u]] = rb[u];
-            }
-        };
-        v4i acc[2][2][2][2];  // [part][half][c tile][j tile]
+        for (int t2 = 0; t2 < 2; ++t2) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) af[h][t2] = *(const v4i *)(stg + 1024 * (4 * h + (wc >> 4) + t2));
+#pragma unroll
+            for (int p = 0; p < 2; ++p) bf[p][t2] = *(const v4i *)(stg + 1024 * (8 + 4 * p + (wj >> 4) + t2));
+        }
+    };
+    auto products = [&](const v4i (&af)[2][2], const v4i (&bf)[2][2]) {
 #pragma unroll
         for (int p = 0; p < 2; ++p)
 #pragma unroll
@@ -459,49 +521,62 @@ __global__ void __launch_bounds__(256, 2) k_nat_ksprod8(const int8_t *__restrict
 #pragma unroll
                 for (int a = 0; a < 2; ++a)
 #pragma unroll
-                    for (int bq = 0; bq < 2; ++bq) acc[p][h][a][bq] = v4i{0, 0, 0, 0};
-        __syncthreads();  // the previous plane's readers are done with both buffers
-        if (kb < ke) {
-            gload(kb);
-            sstore(0);
-        }
-        __syncthreads();
-        int cur = 0;
-        for (int k0 = kb; k0 < ke; k0 += 64) {
-            const bool more = k0 + 64 < ke;
-            if (more) gload(k0 + 64);
-            v4i af[2][2], bf[2][2];
-#pragma unroll
-            for (int t2 = 0; t2 < 2; ++t2) {
-#pragma unroll
-                for (int h = 0; h < 2; ++h) af[h][t2] = As[cur][h][(wc + t2 * 16 + r16) * K8_ROW + g];
-#pragma unroll
-                for (int p = 0; p < 2; ++p) bf[p][t2] = Bs[cur][p][(wj + t2 * 16 + r16) * K8_ROW + g];
-            }
-#pragma unroll
-            for (int p = 0; p < 2; ++p)
-#pragma unroll
-                for (int h = 0; h < 2; ++h)
-#pragma unroll
-                    for (int a = 0; a < 2; ++a)
-#pragma unroll
-                        for (int bq = 0; bq < 2; ++bq)
-                            acc[p][h][a][bq] =
-                                __builtin_amdgcn_mfma_i32_16x16x64_i8(af[h][a], bf[p][bq], acc[p][h][a][bq], 0, 0, 0);
-            if (more) sstore(cur ^ 1);
-            __syncthreads();
-            cur ^= 1;
-        }
+                    for (int bq = 0; bq < 2; ++bq)
+                        acc[p][h][a][bq] =
+                            __builtin_amdgcn_mfma_i32_16x16x64_i8(af[h][a], bf[p][bq], acc[p][h][a][bq], 0, 0, 0);
+    };
+    auto fold = [&](int it) {  // after the last chunk of plane b: fold and restart
+        if ((it + 1) % nk) return;
+        const int b = it / nk;
 #pragma unroll
         for (int p = 0; p < 2; ++p)
 #pragma unroll
             for (int a = 0; a < 2; ++a)
 #pragma unroll
-                for (int bq = 0; bq < 2; ++bq)
+                for (int bq = 0; bq < 2; ++bq) {
 #pragma unroll
                     for (int r = 0; r < 4; ++r)
-                        res[p][a][bq][r] += (uint64_t)((int64_t)acc[p][0][a][bq][r] + 16 * (int64_t)acc[p][1][a][bq][r])
-                                            << (8 * b);
+                        res[p][a][bq][r] +=
+                            (uint64_t)((int64_t)acc[p][0][a][bq][r] + 16 * (int64_t)acc[p][1][a][bq][r]) << (8 * b);
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) acc[p][h][a][bq] = v4i{0, 0, 0, 0};
+                }
+    };
+    // every wave's loads of stage it + 1 are in LDS and every wave has its fragments of
+    // stage it in registers (own LDS reads drained), so stage it's slot can be refilled
+    auto sync_next = [&](int it) {
+        if (it + K8_NS - 1 < total) k8_wait<4 * (K8_NS - 2)>();
+        else k8_wait<0>();
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+    };
+    // the ring starts full; stage it's products run while stage it + 1's fragments are
+    // read and stage it + K8_NS is loaded into the slot stage it left
+    for (int st = 0; st < K8_NS && st < total; ++st) issue(st);
+    if (K8_NS - 1 < total) k8_wait<4 * (K8_NS - 1)>();
+    else k8_wait<0>();
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    v4i fa0[2][2], fb0[2][2], fa1[2][2], fb1[2][2];
+    frags(fa0, fb0, 0);
+    for (int it = 0; it < total; it += 2) {
+        products(fa0, fb0);
+        if (it + 1 < total) {
+            sync_next(it);
+            if (it + K8_NS < total) issue(it + K8_NS);
+            frags(fa1, fb1, it + 1);
+        }
+        fold(it);
+        if (it + 1 >= total) break;
+        products(fa1, fb1);
+        if (it + 2 < total) {
+            sync_next(it + 1);
+            if (it + 1 + K8_NS < total) issue(it + 1 + K8_NS);
+            frags(fa0, fb0, it + 2);
+        }
+        fold(it + 1);
     }
     const bool split = gridDim.z > 1;
 #pragma unroll
@@ -525,22 +600,24 @@ __global__ void __launch_bounds__(256, 2) k_nat_ksprod8(const int8_t *__restrict
         }
 }
 
-// balanced byte planes of the key product matrices: B8[lv][p][b][j][k] = s_b of
-// coefficient j of X^m k_(lv, i, p), k = i N + m (zero for k >= l N);
-// grid (ceil(N / 256), KDp, levels * 2)
+// balanced byte planes of the key product matrices: plane B8[lv][p][b] holds s_b of
+// coefficient j of X^m k_(lv, i, p) at row j, k = i N + m (zero for k >= l N and for
+// the padding rows j >= N) in the tiled operand layout; grid (ceil(JP / 256), KDp,
+// levels * 2), JP = N rounded up to 64
 __global__ void __launch_bounds__(256) k_nat_kmat8(const uint64_t *__restrict__ ksk, int8_t *__restrict__ B8, NatDims dm,
                                                    int l, int KDp) {
+    const int JP = (dm.N + 63) & ~63;
     const int j = blockIdx.x * 256 + threadIdx.x;
-    if (j >= dm.N) return;
+    if (j >= JP) return;
     const int km = blockIdx.y;
     const int lv = blockIdx.z >> 1, p = blockIdx.z & 1;
     uint64_t v = 0;
-    if (km < l * dm.N) {
+    if (km < l * dm.N && j < dm.N) {
         const int i = km / dm.N, m = km % dm.N;
         v = mono_at(ksk + (((int64_t)lv * l + i) * 2 + p) * dm.N, j, m, dm);
     }
-    const int64_t plane = (int64_t)dm.N * KDp;
-    int8_t *o = B8 + ((int64_t)(lv * 2 + p) * 8) * plane + (int64_t)j * KDp + km;
+    const int64_t plane = (int64_t)JP * KDp;
+    int8_t *o = B8 + ((int64_t)(lv * 2 + p) * 8) * plane + k8_at(j, km, KDp >> 6);
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
         int s = (int)(v & 0xff);
@@ -715,6 +792,7 @@ int native_create(const fhelin_native_params *prm, Native **out) {
         n->tau_inv.push_back((int)inv_mod(g, n->M));
     }
     FL_TRY_HIP(hipGetDevice(&n->device));
+    FL_TRY_HIP(hipDeviceGetAttribute(&n->cus, hipDeviceAttributeMultiprocessorCount, n->device));
     *out = n.release();
     return FHELIN_OK;
 }
@@ -758,13 +836,14 @@ int native_keys_load(Native *n, const uint64_t *ksk, hipStream_t s) {
     const int64_t KD = (int64_t)l * n->N;
     const NatDims dm = dims(n);
     if (n->prm.engine == 0) {
-        const size_t bytes8 = (size_t)levels * 2 * 8 * n->N * n->KDp;
+        const int JP = (n->N + 63) & ~63;
+        const size_t bytes8 = (size_t)levels * 2 * 8 * JP * n->KDp;
         if (!n->kmat8 && hipMalloc((void **)&n->kmat8, bytes8) != hipSuccess) {
             (void)hipGetLastError();
             return set_error(FHELIN_E_OOM, "native keys: device allocation failed");
         }
         NatProf ps(n, s, NK_KMAT, (double)levels * 2 * n->N * n->KDp, (double)bytes8 + levels * l * 2.0 * n->N * 8);
-        hipLaunchKernelGGL(k_nat_kmat8, dim3((n->N + 255) / 256, (unsigned)n->KDp, levels * 2), dim3(256), 0, s, ksk,
+        hipLaunchKernelGGL(k_nat_kmat8, dim3((JP + 255) / 256, (unsigned)n->KDp, levels * 2), dim3(256), 0, s, ksk,
                            n->kmat8, dm, l, n->KDp);
         FL_TRY_HIP(hipGetLastError());
         n->keys = true;
@@ -833,8 +912,27 @@ size_t native_pack_workspace(const Native *n, int n_rows) {
     const size_t nmax = packs * n->T;  // the leaves: the widest level
     // current sub-packs, merge terms (t per merge), results, and the digits of a
     // key-switch batch
-    const size_t dig = std::max(nmax * (size_t)n->prm.l * n->N * sizeof(uint32_t), 2 * nmax * (size_t)n->KDp);
+    const size_t dig = std::max(nmax * (size_t)n->prm.l * n->N * sizeof(uint32_t), 2 * ((nmax + 63) & ~(size_t)63) * n->KDp);
     return 3 * nmax * ct + dig;
+}
+
+// K chunks per workgroup of the int8 product for `tiles` output tiles, `chunks` 64-byte
+// K chunks and `slots` resident workgroups: the split whose rounds of workgroups times
+// chunks per workgroup (plus a few chunks' worth of set-up and atomics per split) is
+// least, fewest splits on ties, at most 16 splits.
+static int k8_split(int tiles, int chunks, int slots) {
+    int best = chunks;
+    double best_cost = 1e300;
+    for (int s = 1; s <= 16 && s <= chunks; ++s) {
+        const int per = (chunks + s - 1) / s, gz = (chunks + per - 1) / per;
+        const double rounds = std::ceil((double)tiles * gz / slots);
+        const double cost = rounds * (per + 4.0) + (gz > 1 ? 1.0 : 0.0);
+        if (cost < best_cost - 1e-9) {
+            best_cost = cost;
+            best = per;
+        }
+    }
+    return best;
 }
 
 // out = add + tau(S) for a batch of cnt ciphertexts with the key of tower level lv; out
@@ -848,7 +946,7 @@ static int nat_ks_step(Native *n, int lv, const uint64_t *S, int64_t s_es, const
         const int c = std::min(cnt - c0, 65535);
         if (n->prm.engine == 0) {
             int8_t *A8 = (int8_t *)dig;
-            const int64_t a_half = (int64_t)c * n->KDp;
+            const int64_t a_half = (int64_t)((c + 63) & ~63) * n->KDp;
             {
                 NatProf pa(n, s, NK_AUT_DECOMP, (double)c * n->N, (double)c * n->N * (2 * 8.0 + 2 * 8.0 + 2 * 8.0 + 2.0 * l));
                 hipLaunchKernelGGL(k_nat_aut_decomp8, dim3((std::max(n->N, n->KDp - (int)KD) + 255) / 256, c), dim3(256),
@@ -857,10 +955,9 @@ static int nat_ks_step(Native *n, int lv, const uint64_t *S, int64_t s_es, const
                 FL_TRY_HIP(hipGetLastError());
             }
             const int gx = (n->N + 63) / 64, gy = (c + 63) / 64;
-            const int splits = std::max(1, std::min(16, 1024 / (gx * gy)));
-            const int kc = (n->KDp / 64 + splits - 1) / splits * 64;
+            const int kc = 64 * k8_split(gx * gy, n->KDp / 64, 2 * std::max(n->cus, 1));
             const int gz = (n->KDp + kc - 1) / kc;
-            const int8_t *B8 = n->kmat8 + (int64_t)lv * 2 * 8 * n->N * n->KDp;
+            const int8_t *B8 = n->kmat8 + (int64_t)lv * 2 * 8 * ((n->N + 63) & ~63) * n->KDp;
             // units: 64-bit products (both key parts); bytes: both digit planes and the
             // sixteen key planes once per launch, the output read and written
             NatProf pk(n, s, NK_KSPROD, 2.0 * c * n->N * (double)KD,
