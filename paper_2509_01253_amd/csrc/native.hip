@@ -286,7 +286,11 @@ __global__ void __launch_bounds__(256) k_nat_ksprod(const uint32_t *__restrict__
 // times input row, written to out row out_row[position c_out + co] (the shuffle).  A
 // thread owns one of the 2N columns and 16 output channels: each input value is read
 // once for all 16, whose weights (transposed to wT[ci][dy][dx][cop], cop = c_out
-// rounded up to 16, zero past c_out) are one 64-byte uniform load.
+// rounded up to 16, zero past c_out) are one 64-byte uniform load.  The weights are
+// stored offset by 2^31 (sign bit flipped), u = W + 2^31 in [0, 2^32), so that with
+// v = v_lo + 2^32 v_hi every product is two unsigned 32 x 32 -> 64 multiply-adds:
+//   sum W v = sum u v_lo + 2^32 sum u v_hi - 2^31 sum v   (mod 2^64),
+// the last sum (over the window's inputs) shared by the 16 channels.
 // grid (ceil(2N / 256), output positions, cop / 16).
 constexpr int CONV_CO = 16;
 
@@ -295,7 +299,8 @@ __global__ void __launch_bounds__(256) k_nat_conv_wt(const int32_t *__restrict__
     const int idx = blockIdx.x * 256 + threadIdx.x;
     if (idx >= c_in * k * k * cop) return;
     const int co = idx % cop, t = idx / cop, ci = t / (k * k), r = t % (k * k);
-    wT[idx] = co < c_out ? wts[((int64_t)co * c_in + ci) * k * k + r] : 0;
+    const uint32_t wv = co < c_out ? (uint32_t)wts[((int64_t)co * c_in + ci) * k * k + r] : 0u;
+    wT[idx] = (int32_t)(wv ^ 0x80000000u);
 }
 
 __global__ void __launch_bounds__(256) k_nat_conv(const uint64_t *__restrict__ rows, const int32_t *__restrict__ wT,
@@ -305,9 +310,9 @@ __global__ void __launch_bounds__(256) k_nat_conv(const uint64_t *__restrict__ r
     const int col = blockIdx.x * 256 + threadIdx.x;
     if (col >= n2) return;
     const int pos = blockIdx.y, yo = pos / wo, xo = pos % wo, co0 = blockIdx.z * CONV_CO;
-    uint64_t acc[CONV_CO];
+    uint64_t acc[CONV_CO], acc_hi[CONV_CO], sum = 0;
 #pragma unroll
-    for (int q = 0; q < CONV_CO; ++q) acc[q] = 0;
+    for (int q = 0; q < CONV_CO; ++q) acc[q] = acc_hi[q] = 0;
     const int64_t ci_stride = (int64_t)k * k * cop;
     for (int dy = 0; dy < k; ++dy) {
         const int y = stride * yo + dy - k / 2;
@@ -319,24 +324,30 @@ __global__ void __launch_bounds__(256) k_nat_conv(const uint64_t *__restrict__ r
             const int32_t *wp = wT + (int64_t)(dy * k + dx) * cop + co0;
             for (int ci = 0; ci < c_in; ++ci) {
                 const uint64_t v = in[(int64_t)ci * n2];
+                const uint32_t vl = (uint32_t)v, vh = (uint32_t)(v >> 32);
+                sum += v;
                 const int4 *w4 = (const int4 *)(wp + ci * ci_stride);
-                int32_t wv[CONV_CO];
+                uint32_t wv[CONV_CO];
 #pragma unroll
                 for (int q4 = 0; q4 < CONV_CO / 4; ++q4) {
                     const int4 t4 = w4[q4];
-                    wv[4 * q4] = t4.x;
-                    wv[4 * q4 + 1] = t4.y;
-                    wv[4 * q4 + 2] = t4.z;
-                    wv[4 * q4 + 3] = t4.w;
+                    wv[4 * q4] = (uint32_t)t4.x;
+                    wv[4 * q4 + 1] = (uint32_t)t4.y;
+                    wv[4 * q4 + 2] = (uint32_t)t4.z;
+                    wv[4 * q4 + 3] = (uint32_t)t4.w;
                 }
 #pragma unroll
-                for (int q = 0; q < CONV_CO; ++q) acc[q] += (uint64_t)(int64_t)wv[q] * v;
+                for (int q = 0; q < CONV_CO; ++q) {
+                    acc[q] += (uint64_t)wv[q] * vl;
+                    acc_hi[q] += (uint64_t)wv[q] * vh;
+                }
             }
         }
     }
+    const uint64_t corr = sum << 31;
 #pragma unroll
     for (int q = 0; q < CONV_CO; ++q)
-        if (co0 + q < c_out) out[(int64_t)out_row[pos * c_out + co0 + q] * n2 + col] = acc[q];
+        if (co0 + q < c_out) out[(int64_t)out_row[pos * c_out + co0 + q] * n2 + col] = acc[q] + (acc_hi[q] << 32) - corr;
 }
 
 // ---------------------------------------------------------------------------
