@@ -622,6 +622,11 @@ NATIVE = {"t": 3, "alpha": 7, "beta": 6, "log_d": 9, "l": 3, "log_p": 8}
 # its high word and half a v_add3_u32 per product: 327 VALU per 128 products)
 NAT_KS_VALU_OPS = 327 / 128
 PEAK_NAT_KS = ALU_LANE_OPS / NAT_KS_VALU_OPS / 1e12
+# the convolution on extracted rows: 64-bit products with offset weights, two
+# v_mad_u64_u32 each and the window sum (gfx950 assembly of k_nat_conv's inner loop:
+# 35 VALU per 16 products)
+NAT_CONV_VALU_OPS = 35 / 16
+PEAK_NAT_CONV = ALU_LANE_OPS / NAT_CONV_VALU_OPS / 1e12
 # the int8 matrix-core engine: each 64-bit product is 2 digit halves x 8 key bytes = 16
 # int8 multiply-adds (32 ops), priced against MI355X's dense int8 peak
 INT8_OPS_PER_PRODUCT = 32
@@ -705,12 +710,14 @@ def native_bench(gamma: int, reps: int = 2, engine: int = 0) -> dict:
     F.fhelin_native_profile_enable(nt, True)
     run_pass()
     roof = {}
-    for kname, bound in (("ksprod", "alu"), ("extract", "hbm"), ("linear", "hbm"), ("aut_decomp", "hbm"),
+    for kname, bound in (("ksprod", "alu"), ("extract", "hbm"), ("linear", "alu"), ("aut_decomp", "hbm"),
                          ("merge", "hbm"), ("leaves", "hbm")):
         n_l, ms_k, units, byts = F.fhelin_native_profile_read(nt, kname)
         if n_l == 0 or ms_k <= 0:
             continue
-        if bound == "alu" and engine == 0:
+        if kname == "linear":
+            ach, peak, unit = units / (ms_k / 1e3) / 1e12, PEAK_NAT_CONV, "T 64-bit products/s"
+        elif bound == "alu" and engine == 0:
             bound = "mfma"
             ach, peak, unit = units * INT8_OPS_PER_PRODUCT / (ms_k / 1e3) / 1e12, PEAK_INT8_TOPS, "T int8 ops/s"
         elif bound == "alu":
@@ -718,7 +725,9 @@ def native_bench(gamma: int, reps: int = 2, engine: int = 0) -> dict:
         else:
             ach, peak, unit = byts / (ms_k / 1e3) / 1e9, HBM_PEAK_GBPS, "GB/s"
         roof[kname] = {"bound": bound, "achieved": round(ach, 4), "peak": round(peak, 4), "unit": unit,
-                       "frac": round(ach / peak, 4), "launches": n_l, "ms_per_inference": round(ms_k, 3),
+                       "frac": round(ach / peak, 4),
+                       "hbm_frac": round(byts / (ms_k / 1e3) / 1e9 / HBM_PEAK_GBPS, 4),
+                       "launches": n_l, "ms_per_inference": round(ms_k, 3),
                        "avg_launch_ms": round(ms_k / n_l, 4)}
     F.fhelin_native_profile_enable(nt, False)
     F.fhelin_native_destroy(nt)

@@ -1101,9 +1101,18 @@ int native_conv(Native *n, int c_in, int c_out, int h, int w, int k, int stride,
                        k, cop);
     FL_TRY_HIP(hipGetLastError());
     const int n2 = 2 * n->N;
-    // units: products; bytes: every input row once and the outputs (a row shared by
-    // overlapping windows is read again from the caches)
-    NatProf ps(n, s, NK_LINEAR, (double)ho * wo * c_out * c_in * k * k * n2,
+    // units: products over the taps inside the image; bytes: every input row once and
+    // the outputs (a row shared by overlapping windows is read again from the caches)
+    auto taps = [&](int len, int olen) {
+        double t = 0;
+        for (int o = 0; o < olen; ++o)
+            for (int d = 0; d < k; ++d) {
+                const int v = stride * o + d - k / 2;
+                t += v >= 0 && v < len;
+            }
+        return t;
+    };
+    NatProf ps(n, s, NK_LINEAR, taps(h, ho) * taps(w, wo) * c_out * c_in * n2,
                ((double)c_in * h * w + (double)c_out * ho * wo) * n2 * 8.0);
     hipLaunchKernelGGL(k_nat_conv, dim3((n2 + 255) / 256, ho * wo, cop / CONV_CO), dim3(256), 0, s, rows, n->wt, out_row,
                        out, c_in, c_out, cop, h, w, k, stride, wo, n2);
