@@ -108,13 +108,14 @@ WORKLOAD = dict(log_n=16, L=12, K=3, dnum=4, bits=50, scale=2.0 ** 40, fc=256, n
 # per SIMD every 4 clocks at 2.4 GHz (39.3 T lane-instructions/s).  The instructions the
 # butterfly and the multiply-accumulate product compile to (v_mad_u64_u32, v_mul_lo_u32,
 # v_mul_hi_u32, 64-bit shifts, adds) all issue at that rate on MI355X (measured with
-# fhelin_diag_alu_rate, `bench.py --alu-rates`; the register-resident butterfly runs at
-# 100 clocks per wave, 4.0 per instruction).  Instructions per unit, from the gfx950
-# assembly of the probes (`python -m paper_2509_01253_amd.build --isa ...`):
-#   lazy forward butterfly with 53-bit twiddle companions: 400 VALU per 16 = 25;
+# fhelin_diag_alu_rate, `bench.py --alu-rates`; the register-resident butterfly issues
+# at about 4 clocks per instruction).  Instructions per unit, from the gfx950 assembly
+# of the probes (`python -m paper_2509_01253_amd.build --isa ...`):
+#   lazy forward butterfly with 53-bit twiddle companions (the product's low words as
+#   two chained multiply-adds with the negated modulus): 352 VALU per 16 = 22;
 #   packed 28-bit product with one Montgomery reduction per 32: 725 VALU per 128 = 5.66.
 ALU_LANE_OPS = 256 * 4 * 16 * 2.4e9
-BFLY_VALU_OPS = 25
+BFLY_VALU_OPS = 22
 PEAK_BFLY = ALU_LANE_OPS / BFLY_VALU_OPS / 1e12  # T butterflies (= modular multiplies) per second
 MAC_VALU_OPS = 725 / 128
 PEAK_MAC = ALU_LANE_OPS / MAC_VALU_OPS / 1e12  # T modular products per second

@@ -31,14 +31,23 @@ __device__ __forceinline__ uint64_t shoup_lazy(uint64_t a, uint64_t w, uint64_t 
 // a / 2^53 < 1/2.  The estimate is floor(a w / q) or one less -- the 64-bit form's
 // [0, 2q) -- from four 32-bit multiplies (the pre-shifted ph makes the last one a
 // multiply-add).
+//
+// The result a w - qe q (mod 2^64) is formed as a w + qe (2^64 - q): the low words as
+// two chained 32 x 32 -> 64 multiply-adds, the four cross terms only in the high word.
 __device__ __forceinline__ uint64_t shoup53_lazy(uint64_t a, uint64_t w, uint64_t wp, uint64_t q) {
     const uint32_t al = (uint32_t)a, ah = (uint32_t)(a >> 32);
     const uint32_t pl = (uint32_t)wp, ph11 = (uint32_t)(wp >> 32), ph = ph11 >> 11;
-    uint64_t m = __umulhi(al, pl);
-    m += (uint64_t)ah * pl;
+    uint64_t m = (uint64_t)ah * pl + __umulhi(al, pl);
+    asm("" : "+v"(m));  // keeps the high product as the first multiply-add's addend
     m += (uint64_t)al * ph;
     const uint64_t qe = (uint64_t)ah * ph11 + (m >> 21);
-    return a * w - qe * q;
+    const uint64_t nq = 0 - q;
+    const uint32_t wl = (uint32_t)w, wh = (uint32_t)(w >> 32), nql = (uint32_t)nq, nqh = (uint32_t)(nq >> 32);
+    const uint32_t el = (uint32_t)qe, eh = (uint32_t)(qe >> 32);
+    const uint64_t lo = (uint64_t)al * wl + (uint64_t)el * nql;
+    uint32_t x = ah * wl + al * wh + eh * nql + el * nqh;
+    asm("" : "+v"(x));  // a 32-bit add into the high word, not a 64-bit one
+    return (uint64_t)(uint32_t)lo | ((uint64_t)((uint32_t)(lo >> 32) + x) << 32);
 }
 
 // a - q unless that borrows (the borrow of the subtraction selects, no separate compare)
