@@ -74,6 +74,10 @@ def parse():
     ap.add_argument("--serve-reserve", type=int, default=64,
                     help="requests per batch the serving executor sizes every stream's workspace for at start-up "
                          "(0: grow on demand when a larger batch arrives)")
+    ap.add_argument("--serve-budget-gib", type=str, default="200",
+                    help="HBM budget of the serving run (GiB): key sets, plaintexts and workspaces are admitted "
+                         "against it and idle clients' key sets are evicted when it is full; '+X' means the "
+                         "resident layer data and reserved workspaces plus X GiB for key sets and batches")
     ap.add_argument("--serve-streams", type=str, default="2",
                     help="streams (batches in flight at once) of the continuous-batching server; a comma list "
                          "runs one server per value")
@@ -447,6 +451,10 @@ def serve_bench(args) -> dict:
             ex.add_client_keys(f"c{ci}", j["params"], source, nbytes)
         info[name] = dict(n_in=ex.layers[name]["n_in"], N=N, L=L, q=q)
     torch.cuda.synchronize()
+    fixed = ex.library_bytes()  # resident plaintexts and reserved workspaces
+    bg = args.serve_budget_gib.strip()
+    budget = int(fixed + float(bg[1:]) * (1 << 30)) if bg.startswith("+") else int(float(bg) * (1 << 30))
+    key_set_bytes = {name: ex.key_size[("c0", j["params"])] for name, j in jobs.items()}
 
     def make_requests(rate, seed):
         st = root.sub(synth.TAG_ARRIVAL).sub(seed)
@@ -469,15 +477,18 @@ def serve_bench(args) -> dict:
 
     out = {"workload": "Poisson mix of conv 16->16 @32x32 (N=2^15, levels 2..8) and conv 64->64 @64x64 "
                        "(N=2^16, 8 in / 8 out ciphertexts, levels 2..12), "
-                       f"{args.serve_clients} clients with their own keys, HBM budget 200 GiB",
+                       f"{args.serve_clients} clients with their own keys, HBM budget {budget / (1 << 30):.1f} GiB",
+           "budget_bytes": budget, "fixed_bytes": fixed, "key_set_bytes": key_set_bytes,
            "schedule": schedule, "rates": {}}
     for ri, rate in enumerate(float(r) for r in args.serve_rates.split(",")):
         row = {}
         modes = [(f"continuous_s{k}" if "," in args.serve_streams else "continuous", int(k), 64)
                  for k in args.serve_streams.split(",")] + [("one_at_a_time", 1, 1)]
         for mode, streams, mb in modes:
+            print(f"serving rate {rate:g} req/s, {mode}: start (budget {budget / (1 << 30):.1f} GiB, resident "
+                  f"{fixed / (1 << 30):.1f} GiB)", file=sys.stderr, flush=True)
             reqs = make_requests(rate, ri)
-            srv = Server(ex, hbm_budget=200 << 30, streams=streams, max_batch=mb)
+            srv = Server(ex, hbm_budget=budget, streams=streams, max_batch=mb)
             for ci in range(args.serve_clients):
                 srv.open_session(f"s{ci}", f"c{ci}")
             res = srv.run(reqs)

@@ -11,7 +11,10 @@ The server side of the hybrid protocol (paper Sec. 3-4) as a serving system:
   evicted (and re-uploaded if the client returns).
 * Admission.  A batch is dispatched only if its outputs, input staging,
   workspace growth and missing key sets fit the HBM budget; otherwise the
-  requests wait until in-flight work completes and frees memory.
+  requests wait until in-flight work completes and frees memory.  A request
+  that does not fit even alone, with nothing in flight and no idle key set
+  left to evict, can never run: it is rejected ("exceeds the HBM budget")
+  instead of waiting.
 * Continuous batching.  Up to `streams` batches are in flight on separate
   HIP streams (two by default: one batch runs while the next is admitted and
   launched; on MI355X four concurrent batches of N=2^16 convolutions ran at
@@ -225,6 +228,12 @@ class Server:
             done += 1
         return done
 
+    def _reject_head(self, reason: str):
+        req = self.queue.popleft()
+        self.rejected += 1
+        now = self.clock()
+        self.results[req.rid] = Result(req.rid, reason, arrival=req.arrival, start=now, end=now)
+
     def pump(self):
         """One scheduling round: retire finished batches, fill free streams."""
         self._poll()
@@ -232,8 +241,14 @@ class Server:
             if st not in self.inflight:
                 if self.inflight and len(self.queue) < self.overlap_min_queue:
                     break
-                if not self._try_dispatch(st):
-                    break
+                while not self._try_dispatch(st):
+                    # nothing in flight frees memory later and every idle key set is
+                    # already gone: the head request cannot fit, now or later
+                    if self.inflight or not self.queue:
+                        return
+                    self._reject_head("exceeds the HBM budget")
+                    if not self.queue:
+                        return
 
     def run(self, timeline, poll_s: float = 2e-4, time_limit: float = 600.0):
         """Serve `timeline`, a list of (arrival_offset_s, Request) sorted by time, in real

@@ -206,6 +206,38 @@ def test_waits_when_nothing_can_be_evicted():
     assert srv.evictions == 1
 
 
+def test_request_that_can_never_fit_is_rejected():
+    """With nothing in flight and nothing left to evict, a request whose key set,
+    io and workspace exceed the budget is rejected at once (the run ends) while a
+    later request that fits is still served."""
+    clk = FakeClock()
+
+    class BigKeys(FakeExecutor):
+        def key_bytes(self, client, params):
+            return 1000 if client == "big" else self.kb
+
+    ex = BigKeys(clk, key_bytes=100, io_per_req=10, ws_per_req=5)
+    srv = Server(ex, hbm_budget=300, streams=2, clock=clk)
+    for c in ("big", "a"):
+        srv.open_session(f"s-{c}", c)
+    srv.submit(_req(0, "big"))
+    srv.submit(_req(1, "a"))
+    srv.pump()
+    assert srv.results[0].status == "exceeds the HBM budget"
+    assert srv.rejected == 1 and [l[1] for l in ex.launches] == [[1]]
+    # through run(): a timeline whose only request never fits ends at once
+    import paper_2509_01253_amd.serving as S
+    srv2 = Server(BigKeys(clk), hbm_budget=300, streams=2, clock=clk)
+    srv2.open_session("s-big", "big")
+    orig = S.time.sleep
+    S.time.sleep = lambda s: setattr(clk, "t", clk.t + s)
+    try:
+        res = srv2.run([(0.0, _req(2, "big"))], time_limit=5.0)
+    finally:
+        S.time.sleep = orig
+    assert res[0].status == "exceeds the HBM budget" and srv2.stats(res) == {"completed": 0, "rejected": 1}
+
+
 def test_run_reports_latency_percentiles():
     clk = FakeClock()
 
