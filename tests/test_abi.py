@@ -144,3 +144,16 @@ def test_native_create_rejects_bad_parameters_on_the_host():
     assert lib.fhelin_native_destroy(None) == -1
     assert lib.fhelin_native_destroy(ctypes.addressof(fake)) == -1
     assert b"native" in lib.fhelin_last_error()
+
+
+def test_issue_rate_probe_rejects_bad_arguments_on_the_host():
+    """fhelin_diag_alu_rate checks the probe, the waves per SIMD and the round count
+    before any device call (op 9 is the int8 matrix-core probe)."""
+    lib = ctypes.CDLL(LIB)
+    lib.fhelin_last_error.restype = ctypes.c_char_p
+    d = ctypes.c_double
+    lib.fhelin_diag_alu_rate.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(d),
+                                         ctypes.POINTER(d), ctypes.POINTER(d)]
+    for op, wps, iters in ((10, 2, 32), (-1, 2, 32), (9, 0, 32), (9, 9, 32), (9, 2, 31), (9, 2, 16), (5, 4, 1 << 25)):
+        assert lib.fhelin_diag_alu_rate(op, wps, iters, None, None, None) == -1, (op, wps, iters)
+    assert b"diag" in lib.fhelin_last_error()
