@@ -24,6 +24,7 @@ struct Native {
     std::vector<int> tau, tau_inv; // Galois elements 1 + t^i (i = gamma .. alpha-1) and inverses mod M
     int device = 0;
     int cus = 0;               // compute units of the device
+    int lds_max = 0;           // shared memory per workgroup (bytes)
     int KDp = 0;               // l N rounded up to a multiple of 64 (int8 engine)
     uint64_t *kmat = nullptr;  // [alpha-gamma][2][N][l N] key product matrices (64-bit engine)
     int8_t *kmat8 = nullptr;   // [alpha-gamma][2][8][N][KDp] their balanced bytes (int8 engine)
