@@ -146,7 +146,9 @@ def test_native_pack_needs_keys_and_rejects_stale_handles():
 
 @pytest.mark.parametrize("t,alpha,gamma,beta,shape", [
     (3, 4, 1, 3, (3, 5, 4, 4, 3, 1)), (3, 4, 2, 3, (4, 6, 4, 4, 3, 2)), (5, 3, 1, 2, (6, 20, 4, 4, 1, 2)),
-    (3, 7, 1, 6, (16, 16, 8, 8, 3, 1)), (3, 7, 2, 6, (64, 10, 1, 1, 1, 1))])
+    (3, 7, 1, 6, (16, 16, 8, 8, 3, 1)), (3, 7, 2, 6, (64, 10, 1, 1, 1, 1)),
+    # wider than 16 output channels: several channel groups, the last one padded
+    (3, 4, 1, 3, (8, 40, 4, 4, 3, 1)), (5, 3, 2, 2, (4, 17, 3, 3, 3, 2)), (3, 7, 1, 6, (32, 64, 3, 3, 3, 1))])
 def test_native_conv_layer_bit_exact(t, alpha, gamma, beta, shape):
     """The convolution kernel on extracted rows (channels-last windows, zero padding,
     strides 1 and 2, the FC case h = w = k = 1) with the shuffle as the output rows:
