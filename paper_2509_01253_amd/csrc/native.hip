@@ -1014,11 +1014,11 @@ size_t native_pack_workspace(const Native *n, int n_rows) {
 // K chunks per workgroup of the int8 product for `tiles` output tiles, `chunks` 64-byte
 // K chunks and `slots` resident workgroups: the split whose rounds of workgroups times
 // chunks per workgroup (plus a few chunks' worth of set-up and atomics per split) is
-// least, fewest splits on ties, at most 16 splits.
+// least, fewest splits on ties, at most 32 splits.
 static int k8_split(int tiles, int chunks, int slots) {
     int best = chunks;
     double best_cost = 1e300;
-    for (int s = 1; s <= 16 && s <= chunks; ++s) {
+    for (int s = 1; s <= 32 && s <= chunks; ++s) {
         const int per = (chunks + s - 1) / s, gz = (chunks + per - 1) / per;
         const double rounds = std::ceil((double)tiles * gz / slots);
         const double cost = rounds * (per + 4.0) + (gz > 1 ? 1.0 : 0.0);
