@@ -129,6 +129,43 @@ def test_native_pipeline_paper_8bit_set(gamma, engine):
         assert np.array_equal(cl.decrypt(packed[g])[pos[: seg.size]], seg), g
 
 
+@pytest.mark.parametrize("gamma", [1, 2])
+def test_native_pipeline_paper_12bit_set(gamma):
+    """The paper's 12-bit set (M = 7^4, N = 2058, D = 2^16, l = 2, p = 2^12, noise
+    2^-51) on the 64-bit ALU engine (the int8 engine takes D <= 2^9), packs of
+    phi(7^3) = 294 outputs: a convolution-shaped layer (144 weights of 4 bits per
+    output) over two chunks (one at gamma = 2, whose 42 powers make the oracle's
+    extraction slow); rows and layer outputs compared on sampled rows, every packed
+    ciphertext element by element, and the decryptions equal to the layer mod p."""
+    from paper_2509_01253_amd import fhelin as F
+    print(f"native 7^4 gamma={gamma} engine=1", flush=True)
+    P = R.NativeParams(7, 4, gamma, 3, 16, 2, 12, 2.0 ** 13)
+    cl = R.NativeClient(P, 1200 + gamma)
+    keys = cl.keyset()
+    rng = np.random.default_rng(1210 + gamma)
+    n_chunks = 2 if gamma == 1 else 1
+    n_in = n_chunks * P.N
+    x = rng.integers(0, 16, n_in)
+    chunks = np.stack([cl.encrypt_powers(x[c * P.N: (c + 1) * P.N]) for c in range(n_chunks)])
+    n_out = 2 * P.n_pack + 7
+    W = _conv_like(rng, n_out, n_in, 144, 8)
+    perm = rng.permutation(n_out)
+    rows, Fo, packed = _run(F, P, chunks, W, perm, keys, engine=1)
+    for c in range(n_chunks):
+        want = R.extract(P, chunks[c])
+        sel = rng.choice(P.N, 40, replace=False)
+        assert np.array_equal(rows[c * P.N + sel], want[sel]), c
+    sel = rng.choice(n_out, 30, replace=False)
+    assert np.array_equal(Fo[sel], R.linear_rows(W[perm][sel], rows))
+    y = (W[perm] @ x) % P.p
+    pos = R.unpack_positions(P)
+    for g in range(packed.shape[0]):
+        want = R.pack(P, Fo[g * P.n_pack: (g + 1) * P.n_pack], keys)
+        assert np.array_equal(packed[g], want), g
+        seg = y[g * P.n_pack: (g + 1) * P.n_pack]
+        assert np.array_equal(cl.decrypt(packed[g])[pos[: seg.size]], seg), g
+
+
 def test_native_pack_needs_keys_and_rejects_stale_handles():
     from paper_2509_01253_amd import fhelin as F
     import torch
