@@ -13,10 +13,12 @@ What is computed, each from its definition:
     modulo Phi_M = sum_{k<t} X^(k M/t), i.e. X^(N + r) = -sum_{k<t-1} X^(k M/t + r)
     for r < M/t;
   * automorphisms sigma_d: X^i -> X^(d i mod M) (Sec. 2.2);
-  * key switching with a gadget of base D = 2^log_d and depth l (Sec. 4.2): the key
-    for sigma_d is the l encryptions of s(X^d) 2^64 / D^i; a ciphertext under s(X^d)
-    is decomposed into l balanced digit polynomials of its mask and recombined with
-    the key;
+  * key switching with a gadget of base D and depth l (Sec. 4.2; D = 2^log_d, or any
+    even base such as the paper's 310): the key for sigma_d is the l encryptions of
+    s(X^d) g_i with g_i = round(2^64 / D^i) (exactly 2^64 / D^i for a power of two); a
+    ciphertext under s(X^d) is decomposed into l balanced digit polynomials of its
+    mask (the mask as a torus value rounded to a multiple of 1 / D^l, written in
+    balanced base D) and recombined with the key;
   * partial trace extraction (Sec. 4.4, the lemma on partial trace extraction): the
     client sends encryptions of m(X^d) for d in the level-gamma set ({1..t-1} for
     gamma = 1, {k (j t + 1)} for gamma = 2); the server forms, for every coefficient
@@ -58,19 +60,32 @@ class NativeParams:
     alpha: int
     gamma: int        # partial trace extraction level (1 or 2)
     beta: int         # packing level: phi(t^beta) coefficients per packed ciphertext
-    log_d: int        # gadget base D = 2^log_d
+    log_d: int        # gadget base D = 2^log_d (when base is 0)
     l: int            # gadget depth
     log_p: int        # message modulus p = 2^log_p
     sigma: float      # error standard deviation in units of 2^-64 (the paper's Delta 2^64)
+    base: int = 0     # an even gadget base that is not a power of two (0: D = 2^log_d)
     M: int = field(init=False)
     N: int = field(init=False)
 
     def __post_init__(self):
         assert self.t >= 3 and all(self.t % f for f in range(2, int(self.t ** 0.5) + 1)), "t: odd prime"
         assert 1 <= self.gamma <= 2 and self.gamma <= self.beta <= self.alpha - 1
-        assert self.log_d * self.l < 64 and self.log_p < 32
+        assert self.log_p < 32
+        if self.base:
+            assert self.base % 2 == 0 and 4 <= self.base <= 1 << 16 and self.base ** self.l < 1 << 63
+        else:
+            assert self.log_d * self.l < 64
         self.M = self.t ** self.alpha
         self.N = self.M - self.M // self.t
+
+    @property
+    def D(self) -> int:
+        return self.base or 1 << self.log_d
+
+    def gadget(self, i: int) -> int:
+        """g_i = round(2^64 / D^i), i = 1..l."""
+        return ((1 << 65) // self.D ** i + 1) // 2
 
     @property
     def Mt(self) -> int:
@@ -195,10 +210,11 @@ class NativeClient:
         return self.decode(self.phase(ct))
 
     def ksk(self, d: int) -> np.ndarray:
-        """Key for sigma_d: the l encryptions of s(X^d) 2^64 / D^i, [l][2][N]."""
+        """Key for sigma_d: the l encryptions of s(X^d) g_i, g_i = round(2^64 / D^i),
+        [l][2][N]."""
         P = self.P
         sd = automorphism(P, self.s, d)
-        return np.stack([self.encrypt_torus((sd << U64(64 - P.log_d * i)).astype(U64)) for i in range(1, P.l + 1)])
+        return np.stack([self.encrypt_torus((sd * U64(P.gadget(i) % 2 ** 64)).astype(U64)) for i in range(1, P.l + 1)])
 
     def keyset(self) -> dict:
         """Keys of every Galois element the packing uses."""
@@ -216,16 +232,22 @@ class NativeClient:
 # ---------------------------------------------------------------------------
 def decompose(P: NativeParams, a: np.ndarray) -> np.ndarray:
     """Balanced gadget digits of a: a / 2^64 ~ sum_{i=1..l} d_i / D^i with d_i in
-    [-D/2, D/2); returns int64 [l][...] (i = 1 first).  a is first rounded to its top
-    l log_d bits."""
-    bits = P.log_d * P.l
-    sh = 64 - bits
-    top = ((a.astype(U64) + (U64(1) << U64(sh - 1))) >> U64(sh)).astype(np.int64)  # < 2^bits
-    D = 1 << P.log_d
+    [-D/2, D/2); returns int64 [l][...] (i = 1 first).  a / 2^64 is first rounded to a
+    multiple of 1 / D^l: top = floor((a D^l + 2^63) / 2^64) (for D = 2^log_d, the top
+    l log_d bits of a rounded); a carry out of the top digit is dropped (the torus
+    wraps)."""
+    D, l = P.D, P.l
+    if P.base:
+        Dl = D ** l
+        flat = [(int(x) * Dl + (1 << 63)) >> 64 for x in np.asarray(a, U64).ravel()]
+        top = np.array(flat, dtype=np.int64).reshape(np.shape(a))  # <= D^l < 2^63
+    else:
+        sh = 64 - P.log_d * l
+        top = ((a.astype(U64) + (U64(1) << U64(sh - 1))) >> U64(sh)).astype(np.int64)  # < 2^(l log_d)
     digs = []
-    for _ in range(P.l):  # least significant digit first
-        d = top & (D - 1)
-        top = top >> P.log_d
+    for _ in range(l):  # least significant digit first
+        d = top % D
+        top = top // D
         neg = d >= D // 2
         d = np.where(neg, d - D, d)
         top = top + neg

@@ -171,3 +171,63 @@ def test_conv_matrix_is_the_windowed_sum():
                 direct[yo, xo] = np.einsum("yxc,ocyx->o", win, wts)
         got = R.conv_matrix(c_in, c_out, h, w, k, s, wts) @ img.reshape(-1)
         assert np.array_equal(got, direct.reshape(-1)), (c_in, c_out, h, w, k, s)
+
+
+def test_gadget_digits_general_base():
+    """A base that is not a power of two (the paper's 310, l = 4): digits in
+    [-D/2, D/2) and sum_i d_i g_i within 2^63 / D^l (rounding to a multiple of 1/D^l)
+    plus l D / 4 (each g_i = round(2^64 / D^i) off by at most 1/2) of a, modulo 2^64;
+    and base 512 given explicitly decomposes exactly as log_d = 9."""
+    P = R.NativeParams(5, 3, 1, 2, 0, 4, 16, 2.0 ** 13, base=310)
+    assert [P.gadget(i) for i in (1, 2)] == [round(2 ** 64 / 310), round(2 ** 64 / 310 ** 2)]
+    rng = np.random.default_rng(31)
+    a = rng.integers(0, 2 ** 64, 2000, dtype=np.uint64, endpoint=False)
+    a[:4] = [0, 2 ** 64 - 1, 2 ** 63, 2 ** 63 - 1]
+    dg = R.decompose(P, a)
+    assert dg.shape == (4, 2000) and dg.min() >= -155 and dg.max() < 155
+    bound = 2 ** 63 / 310 ** 4 + 4 * 310 / 4
+    for k in range(2000):
+        rec = sum(int(dg[i, k]) * P.gadget(i + 1) for i in range(4)) % 2 ** 64
+        err = (int(a[k]) - rec) % 2 ** 64
+        err = err - 2 ** 64 if err >= 2 ** 63 else err
+        assert abs(err) <= bound, k
+    P2 = R.NativeParams(3, 3, 1, 1, 0, 3, 8, 2.0 ** 28, base=512)
+    P9 = _params(3, 3, beta=1, log_d=9, l=3)
+    assert np.array_equal(R.decompose(P2, a), R.decompose(P9, a))
+    assert [P2.gadget(i) for i in (1, 2, 3)] == [2 ** 55, 2 ** 46, 2 ** 37]
+
+
+@pytest.mark.parametrize("t,a,gamma,beta", [(5, 3, 1, 2), (3, 4, 2, 3)])
+def test_base_310_key_switching_and_packing_decrypt(t, a, gamma, beta):
+    """Key switching and the whole pipeline with the paper's 16-bit-set gadget (base
+    310, depth 4) on small rings: every Galois key switch decrypts to the automorphism
+    of the message, and the packed ciphertexts decrypt to the integer layer."""
+    P = R.NativeParams(t, a, gamma, beta, 0, 4, 16, 2.0 ** 13, base=310)
+    Rg = V.Ring(t, a)
+    cl = R.NativeClient(P, 41 + t)
+    keys = cl.keyset()
+    rnd = random.Random(t + a)
+    m = [rnd.randrange(P.p) for _ in range(P.N)]
+    ct = cl.encrypt(m)
+    for d in P.taus():
+        out = R.apply_galois(P, ct, d, keys)
+        assert np.array_equal(cl.decrypt(out), np.array([v % P.p for v in Rg.sigma(m, d)])), d
+    rng = np.random.default_rng(t * a)
+    n_in = P.N + P.N // 2
+    x = rng.integers(0, 16, n_in)
+    chunks = []
+    for c in range(2):
+        mm = np.zeros(P.N, np.int64)
+        part = x[c * P.N: (c + 1) * P.N]
+        mm[: part.size] = part
+        chunks.append(cl.encrypt_powers(mm))
+    n_out = P.n_pack + 3
+    W = rng.integers(-8, 8, (n_out, n_in))
+    rows = np.concatenate([R.extract(P, c) for c in chunks])[:n_in]
+    F = R.linear_rows(W, rows)
+    y = (W @ x) % P.p
+    pos = R.unpack_positions(P)
+    for g in range(0, n_out, P.n_pack):
+        dec = cl.decrypt(R.pack(P, F[g: g + P.n_pack], keys))
+        seg = y[g: g + P.n_pack]
+        assert np.array_equal(dec[pos[: seg.size]], seg), g
