@@ -439,7 +439,12 @@ typedef struct fhelin_native_params {
     int32_t log_p;      /* message modulus p = 2^log_p (1..31) */
     int32_t engine;     /* key-switch products: 0 = int8 matrix cores (balanced 4/5-bit
                            digit halves x balanced key bytes, exact i32 sums, needs
-                           log_d <= 9), 1 = 64-bit integer ALU products */
+                           D <= 512), 1 = 64-bit integer ALU products */
+    int32_t base;       /* 0: gadget base D = 2^log_d; otherwise D itself (the paper's
+                           16-bit set takes 310): even, 4..65536, D^l < 2^63, log_d
+                           ignored.  The keys then encrypt s(X^g) round(2^64 / D^i)
+                           and a mask a is decomposed as round(a D^l / 2^64) written
+                           in balanced base D, the carry out of the top digit dropped */
 } fhelin_native_params;
 
 /* FHELIN_E_UNSUPPORTED_PARAM for parameters outside the ranges above (checked on

@@ -13,6 +13,12 @@ constexpr int NAT_MAX_POW = 64;  // powers m(X^d) per chunk: phi(t^gamma)
 enum NatKind : int { NK_EXTRACT = 0, NK_LINEAR, NK_LEAVES, NK_MERGE, NK_AUT_DECOMP, NK_KSPROD, NK_KMAT, NK_COUNT };
 extern const char *const NAT_KIND_NAMES[NK_COUNT];
 
+// the gadget of the key switching: base D (2^log_d when log_d > 0), depth l, D^l
+struct NatGadget {
+    int log_d = 0, l = 0;
+    uint64_t D = 0, Dl = 0;
+};
+
 struct Native {
     fhelin_native_params prm{};
     int M = 0, N = 0, Mt = 0;
@@ -22,6 +28,7 @@ struct Native {
     uint64_t u = 0;  // M^-1 mod p (balanced), as a 64-bit two's-complement integer
     std::vector<int> powers;       // d of the client's powers m(X^d)
     std::vector<int> tau, tau_inv; // Galois elements 1 + t^i (i = gamma .. alpha-1) and inverses mod M
+    NatGadget gad;
     int device = 0;
     int cus = 0;               // compute units of the device
     int lds_max = 0;           // shared memory per workgroup (bytes)

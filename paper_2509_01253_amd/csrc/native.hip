@@ -13,7 +13,8 @@
 //               X^(k (M/t^(i+1) - m M/t)) y_k, S = v_(t-1), S = v_m + tau_i(S); then
 //               Tr_{K/K_beta} as, per level j = alpha-1 down to beta, S = P,
 //               S = P + tau_j(S) (t - 1 times); tau_i = sigma_(1 + t^i).
-//   tau(S)      automorphism then key switch with a gadget of base D = 2^log_d, depth l:
+//   tau(S)      automorphism then key switch with a gadget of base D (2^log_d, or an even
+//               base such as the paper's 310), depth l:
 //               a' = sigma(a), b' = sigma(b), digits d_i of a' (balanced, stored with
 //               the offset D/2), a'' = -sum_i d_i k_i.a, b'' = b' - sum_i d_i k_i.b.
 //               The products d_i k_i modulo Phi_M are one matrix product per key:
@@ -60,6 +61,35 @@ __device__ __forceinline__ uint64_t aut_cyc(const uint64_t *__restrict__ c, int 
 
 __device__ __forceinline__ uint64_t aut_at(const uint64_t *__restrict__ c, int j, int ginv, const NatDims &d) {
     return aut_cyc(c, j, ginv, d) - aut_cyc(c, d.N + j % d.Mt, ginv, d);
+}
+
+// a mask coefficient as a torus value rounded to a multiple of 1 / D^l: floor((a D^l +
+// 2^63) / 2^64), at most D^l (for D = 2^log_d: the top l log_d bits of a, rounded)
+__device__ __forceinline__ uint64_t gadget_top(uint64_t a, const NatGadget &g) {
+    if (g.log_d) {
+        const int sh = 64 - g.log_d * g.l;
+        return (a >> sh) + ((a >> (sh - 1)) & 1);
+    }
+    return __umul64hi(a, g.Dl) + ((a * g.Dl) >> 63);
+}
+
+// the next balanced base-D digit of top (least significant first), in [-D/2, D/2); a
+// carry out of the top digit is dropped by the caller (the torus wraps)
+__device__ __forceinline__ int gadget_digit(uint64_t &top, const NatGadget &g) {
+    int64_t d;
+    if (g.log_d) {
+        d = (int64_t)(top & (g.D - 1));
+        top >>= g.log_d;
+    } else {
+        const uint64_t q = top / g.D;
+        d = (int64_t)(top - q * g.D);
+        top = q;
+    }
+    if (d >= (int64_t)(g.D >> 1)) {
+        d -= (int64_t)g.D;
+        top += 1;
+    }
+    return (int)d;
 }
 
 // ---------------------------------------------------------------------------
@@ -240,7 +270,7 @@ __global__ void __launch_bounds__(256) k_nat_aut_decomp(const uint64_t *__restri
                                                         uint64_t *__restrict__ out, int64_t out_es,
                                                         const uint64_t *__restrict__ corr_a,
                                                         const uint64_t *__restrict__ corr_b, uint32_t *__restrict__ dig,
-                                                        NatDims dm, int ginv, int log_d, int l) {
+                                                        NatDims dm, int ginv, NatGadget g) {
     const int j = blockIdx.x * 256 + threadIdx.x;
     if (j >= dm.N) return;
     const int c = blockIdx.y;
@@ -250,20 +280,10 @@ __global__ void __launch_bounds__(256) k_nat_aut_decomp(const uint64_t *__restri
     uint64_t *o = out + c * out_es;
     o[j] = ad[j] + corr_a[j];
     o[dm.N + j] = ad[dm.N + j] + bv + corr_b[j];
-    // round to the top l log_d bits, then balanced digits from the least significant
-    const int bits = log_d * l, sh = 64 - bits;
-    uint64_t top = (av >> sh) + ((av >> (sh - 1)) & 1);  // < 2^bits + 1; a carry past the top wraps
-    const uint64_t D = 1ull << log_d, mask = D - 1;
-    uint32_t *dg = dig + (int64_t)c * l * dm.N + j;
-    for (int i = l - 1; i >= 0; --i) {
-        int64_t d = (int64_t)(top & mask);
-        top >>= log_d;
-        if (d >= (int64_t)(D >> 1)) {
-            d -= (int64_t)D;
-            top += 1;
-        }
-        dg[(int64_t)i * dm.N] = (uint32_t)(d + (int64_t)(D >> 1));
-    }
+    // rounded, then balanced digits from the least significant
+    uint64_t top = gadget_top(av, g);
+    uint32_t *dg = dig + (int64_t)c * g.l * dm.N + j;
+    for (int i = g.l - 1; i >= 0; --i) dg[(int64_t)i * dm.N] = (uint32_t)(gadget_digit(top, g) + (int)(g.D >> 1));
 }
 
 // out[c][p][j] -= sum_k A[c][k] K_p[j][k] (mod 2^64) for both key parts, A[c][k] = digit +
@@ -450,9 +470,9 @@ __global__ void __launch_bounds__(256) k_nat_aut_decomp8(const uint64_t *__restr
                                                          const uint64_t *__restrict__ add, int64_t add_es,
                                                          uint64_t *__restrict__ out, int64_t out_es,
                                                          int8_t *__restrict__ A8, int64_t a_half, NatDims dm, int ginv,
-                                                         int log_d, int l, int KDp) {
+                                                         NatGadget g, int KDp) {
     const int j = blockIdx.x * 256 + threadIdx.x;
-    const int c = blockIdx.y, nkc = KDp >> 6;
+    const int c = blockIdx.y, nkc = KDp >> 6, l = g.l;
     int8_t *lo = A8, *hi = A8 + a_half;
     if (j < KDp - l * dm.N) {  // the padding of the row
         const int64_t o = k8_at(c, l * dm.N + j, nkc);
@@ -466,16 +486,9 @@ __global__ void __launch_bounds__(256) k_nat_aut_decomp8(const uint64_t *__restr
     uint64_t *o = out + c * out_es;
     o[j] = ad[j];
     o[dm.N + j] = ad[dm.N + j] + bv;
-    const int bits = log_d * l, sh = 64 - bits;
-    uint64_t top = (av >> sh) + ((av >> (sh - 1)) & 1);
-    const uint64_t D = 1ull << log_d, mask = D - 1;
+    uint64_t top = gadget_top(av, g);
     for (int i = l - 1; i >= 0; --i) {
-        int d = (int)(top & mask);
-        top >>= log_d;
-        if (d >= (int)(D >> 1)) {
-            d -= (int)D;
-            top += 1;
-        }
+        const int d = gadget_digit(top, g);
         const int h = (d + 8) >> 4;  // floor division: lo = d - 16 h in [-8, 8)
         const int64_t o = k8_at(c, i * dm.N + j, nkc);
         lo[o] = (int8_t)(d - 16 * h);
@@ -840,14 +853,33 @@ int native_create(const fhelin_native_params *prm, Native **out) {
              "M = t^alpha must satisfy alpha >= 2 and M <= " + std::to_string(NAT_MAX_M));
     FL_CHECK(q.gamma >= 1 && q.gamma <= 2 && q.gamma <= q.beta && q.beta <= q.alpha - 1, FHELIN_E_UNSUPPORTED_PARAM,
              "need 1 <= gamma <= 2 and gamma <= beta <= alpha - 1");
-    FL_CHECK(q.log_d >= 1 && q.log_d <= 16 && q.l >= 1 && q.l <= 8 && q.log_d * q.l < 64, FHELIN_E_UNSUPPORTED_PARAM,
-             "gadget: 1 <= log_d <= 16, 1 <= l <= 8, log_d l < 64");
+    NatGadget gad;
+    gad.l = q.l;
+    FL_CHECK(q.l >= 1 && q.l <= 8, FHELIN_E_UNSUPPORTED_PARAM, "gadget: 1 <= l <= 8");
+    if (q.base == 0) {
+        FL_CHECK(q.log_d >= 1 && q.log_d <= 16 && q.log_d * q.l < 64, FHELIN_E_UNSUPPORTED_PARAM,
+                 "gadget: 1 <= log_d <= 16, log_d l < 64");
+        gad.log_d = q.log_d;
+        gad.D = 1ull << q.log_d;
+    } else {
+        FL_CHECK(q.base >= 4 && q.base <= 65536 && q.base % 2 == 0, FHELIN_E_UNSUPPORTED_PARAM,
+                 "gadget base: even, 4..65536");
+        gad.D = (uint64_t)q.base;
+    }
+    if (q.base != 0) {  // D^l, the scale of the rounding (a power of two rounds by shifts)
+        gad.Dl = 1;
+        for (int i = 0; i < q.l; ++i) {
+            FL_CHECK(gad.Dl <= ((1ull << 63) - 1) / gad.D, FHELIN_E_UNSUPPORTED_PARAM, "gadget: D^l must be below 2^63");
+            gad.Dl *= gad.D;
+        }
+    }
     FL_CHECK(q.log_p >= 1 && q.log_p <= 31, FHELIN_E_UNSUPPORTED_PARAM, "message modulus: 1 <= log_p <= 31");
     FL_CHECK(q.engine == 0 || q.engine == 1, FHELIN_E_UNSUPPORTED_PARAM, "engine: 0 (int8 matrix cores) or 1 (ALU)");
-    FL_CHECK(q.engine == 1 || q.log_d <= 9, FHELIN_E_UNSUPPORTED_PARAM,
-             "the int8 engine splits digits into 4- and 5-bit halves: log_d <= 9");
+    FL_CHECK(q.engine == 1 || gad.D <= 512, FHELIN_E_UNSUPPORTED_PARAM,
+             "the int8 engine splits digits into 4- and 5-bit halves: D <= 512");
     std::unique_ptr<Native> n(new Native());
     n->prm = q;
+    n->gad = gad;
     n->M = (int)ipow(q.t, q.alpha);
     n->Mt = n->M / q.t;
     n->N = n->M - n->Mt;
@@ -946,8 +978,7 @@ int native_keys_load(Native *n, const uint64_t *ksk, hipStream_t s) {
         hipLaunchKernelGGL(k_nat_kmat, dim3((n->N + 255) / 256, (unsigned)KD, levels * 2), dim3(256), 0, s, ksk, n->kmat,
                            dm, l);
         FL_TRY_HIP(hipGetLastError());
-        hipLaunchKernelGGL(k_nat_kcorr, dim3(levels * 2 * n->N), dim3(256), 0, s, n->kmat, n->kcorr, KD,
-                           (uint64_t)1 << (n->prm.log_d - 1));
+        hipLaunchKernelGGL(k_nat_kcorr, dim3(levels * 2 * n->N), dim3(256), 0, s, n->kmat, n->kcorr, KD, n->gad.D >> 1);
         FL_TRY_HIP(hipGetLastError());
     }
     n->keys = true;
@@ -1046,7 +1077,7 @@ static int nat_ks_step(Native *n, int lv, const uint64_t *S, int64_t s_es, const
                 NatProf pa(n, s, NK_AUT_DECOMP, (double)c * n->N, (double)c * n->N * (2 * 8.0 + 2 * 8.0 + 2 * 8.0 + 2.0 * l));
                 hipLaunchKernelGGL(k_nat_aut_decomp8, dim3((std::max(n->N, n->KDp - (int)KD) + 255) / 256, c), dim3(256),
                                    0, s, S + c0 * s_es, s_es, add + c0 * add_es, add_es, out + c0 * out_es, out_es, A8,
-                                   a_half, dm, n->tau_inv[lv], n->prm.log_d, l, n->KDp);
+                                   a_half, dm, n->tau_inv[lv], n->gad, n->KDp);
                 FL_TRY_HIP(hipGetLastError());
             }
             const int gx = (n->N + 63) / 64, gy = (c + 63) / 64;
@@ -1068,7 +1099,7 @@ static int nat_ks_step(Native *n, int lv, const uint64_t *S, int64_t s_es, const
             NatProf pa(n, s, NK_AUT_DECOMP, (double)c * n->N, (double)c * n->N * (2 * 8.0 + 2 * 8.0 + 2 * 8.0 + 4.0 * l));
             hipLaunchKernelGGL(k_nat_aut_decomp, dim3((n->N + 255) / 256, c), dim3(256), 0, s, S + c0 * s_es, s_es,
                                add + c0 * add_es, add_es, out + c0 * out_es, out_es, ca, cb, dig, dm, n->tau_inv[lv],
-                               n->prm.log_d, l);
+                               n->gad);
             FL_TRY_HIP(hipGetLastError());
         }
         // a small batch splits K so that about 1024 workgroups run

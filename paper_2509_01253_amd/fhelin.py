@@ -67,7 +67,7 @@ class fhelin_ct_batch(ctypes.Structure):
 
 class fhelin_native_params(ctypes.Structure):
     _fields_ = [("t", _i32), ("alpha", _i32), ("gamma", _i32), ("beta", _i32), ("log_d", _i32), ("l", _i32),
-                ("log_p", _i32), ("engine", _i32)]
+                ("log_p", _i32), ("engine", _i32), ("base", _i32)]
 
 
 class fhelin_tune(ctypes.Structure):
@@ -450,8 +450,9 @@ def _i32_tensor(x: torch.Tensor, what: str):
 NATIVE_ENGINE_MFMA, NATIVE_ENGINE_VALU = 0, 1
 
 
-def fhelin_native_create(t: int, alpha: int, gamma: int, beta: int, log_d: int, l: int, log_p: int, engine: int = 0):
-    prm = fhelin_native_params(t, alpha, gamma, beta, log_d, l, log_p, engine)
+def fhelin_native_create(t: int, alpha: int, gamma: int, beta: int, log_d: int, l: int, log_p: int, engine: int = 0,
+                         base: int = 0):
+    prm = fhelin_native_params(t, alpha, gamma, beta, log_d, l, log_p, engine, base)
     out = _vp()
     _check(_lib.fhelin_native_create(ctypes.byref(prm), ctypes.byref(out)))
     return out

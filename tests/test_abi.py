@@ -116,7 +116,7 @@ def test_null_and_unknown_handles_rejected_without_a_gpu():
 
 
 class _NatPrm(ctypes.Structure):
-    _fields_ = [(n, ctypes.c_int32) for n in ("t", "alpha", "gamma", "beta", "log_d", "l", "log_p", "engine")]
+    _fields_ = [(n, ctypes.c_int32) for n in ("t", "alpha", "gamma", "beta", "log_d", "l", "log_p", "engine", "base")]
 
 
 def test_native_create_rejects_bad_parameters_on_the_host():
@@ -126,18 +126,30 @@ def test_native_create_rejects_bad_parameters_on_the_host():
     lib = ctypes.CDLL(LIB)
     lib.fhelin_last_error.restype = ctypes.c_char_p
     lib.fhelin_native_create.argtypes = [ctypes.POINTER(_NatPrm), ctypes.POINTER(ctypes.c_void_p)]
-    good = dict(t=3, alpha=7, gamma=1, beta=6, log_d=9, l=3, log_p=8, engine=0)
+    good = dict(t=3, alpha=7, gamma=1, beta=6, log_d=9, l=3, log_p=8, engine=0, base=0)
     bad = {"t even": dict(t=4), "t not prime": dict(t=9), "t = 2": dict(t=2), "alpha 1": dict(alpha=1),
            "M too large": dict(alpha=9), "gamma 0": dict(gamma=0), "gamma 3": dict(gamma=3, beta=5),
            "beta < gamma": dict(gamma=2, beta=1), "beta = alpha": dict(beta=7), "log_d 0": dict(log_d=0),
            "log_d 17": dict(log_d=17), "l 9": dict(l=9, log_d=4), "gadget 64 bits": dict(log_d=16, l=4),
            "log_p 0": dict(log_p=0), "log_p 32": dict(log_p=32), "engine 2": dict(engine=2),
-           "int8 engine, 10-bit digits": dict(log_d=10, l=2)}
+           "int8 engine, 10-bit digits": dict(log_d=10, l=2), "odd base": dict(base=311),
+           "base 2": dict(base=2), "base above 2^16": dict(base=65538, engine=1, l=2),
+           "D^l >= 2^63": dict(base=310, l=8, engine=1), "int8 engine, base 514": dict(base=514, l=2)}
     for name, change in bad.items():
         out = ctypes.c_void_p()
         prm = _NatPrm(**{**good, **change})
         assert lib.fhelin_native_create(ctypes.byref(prm), ctypes.byref(out)) == -2, name
         assert not out.value, name
+    # the paper's 16-bit set gadget passes the parameter checks on both engines (without
+    # a GPU the call then fails at the device query, not as an unsupported parameter)
+    lib.fhelin_native_destroy.argtypes = [ctypes.c_void_p]
+    for eng in (0, 1):
+        out = ctypes.c_void_p()
+        prm = _NatPrm(**{**good, "t": 5, "alpha": 5, "beta": 4, "l": 4, "log_p": 16, "base": 310, "engine": eng})
+        rc = lib.fhelin_native_create(ctypes.byref(prm), ctypes.byref(out))
+        assert rc != -2, lib.fhelin_last_error()
+        if rc == 0:
+            assert lib.fhelin_native_destroy(out) == 0
     assert lib.fhelin_native_create(None, None) == -1
     fake = ctypes.create_string_buffer(4096)
     lib.fhelin_native_destroy.argtypes = [ctypes.c_void_p]

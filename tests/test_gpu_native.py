@@ -36,7 +36,7 @@ def _conv_like(rng, n_out, n_in, nnz, mag):
 def _run(F, P, chunks, W, perm, keys, engine=0):
     """GPU pipeline; returns (rows, F rows, packed) on the host."""
     import torch
-    nt = F.fhelin_native_create(P.t, P.alpha, P.gamma, P.beta, P.log_d, P.l, P.log_p, engine)
+    nt = F.fhelin_native_create(P.t, P.alpha, P.gamma, P.beta, P.log_d, P.l, P.log_p, engine, P.base)
     try:
         ksk = np.stack([keys[d] for d in P.taus()])
         F.fhelin_native_keys_load(nt, dev(ksk))
@@ -162,6 +162,79 @@ def test_native_pipeline_paper_12bit_set(gamma):
     for g in range(packed.shape[0]):
         want = R.pack(P, Fo[g * P.n_pack: (g + 1) * P.n_pack], keys)
         assert np.array_equal(packed[g], want), g
+        seg = y[g * P.n_pack: (g + 1) * P.n_pack]
+        assert np.array_equal(cl.decrypt(packed[g])[pos[: seg.size]], seg), g
+
+
+@pytest.mark.parametrize("engine", [0, 1])
+@pytest.mark.parametrize("t,alpha,gamma,beta", [(5, 3, 1, 2), (3, 4, 2, 3)])
+def test_native_pipeline_base_310_small_rings(t, alpha, gamma, beta, engine):
+    """The paper's 16-bit-set gadget (base 310, depth 4, p = 2^16) on small rings,
+    both key-switch engines: rows, layer outputs and every packed ciphertext element
+    by element against the oracle, decryptions equal to the layer."""
+    from paper_2509_01253_amd import fhelin as F
+    print(f"native base 310 t={t} alpha={alpha} gamma={gamma} beta={beta} engine={engine}", flush=True)
+    P = R.NativeParams(t, alpha, gamma, beta, 0, 4, 16, 2.0 ** 13, base=310)
+    cl = R.NativeClient(P, 500 + t * 10 + alpha)
+    keys = cl.keyset()
+    rng = np.random.default_rng(510 + t * 10 + gamma)
+    n_in = P.N + P.N // 3
+    x = rng.integers(0, 16, n_in)
+    chunks = []
+    for c in range(2):
+        m = np.zeros(P.N, np.int64)
+        part = x[c * P.N: (c + 1) * P.N]
+        m[: part.size] = part
+        chunks.append(cl.encrypt_powers(m))
+    chunks = np.stack(chunks)
+    n_out = 2 * P.n_pack + 5
+    W = _conv_like(rng, n_out, n_in, min(24, n_in), 8)
+    perm = rng.permutation(n_out)
+    rows, Fo, packed = _run(F, P, chunks, W, perm, keys, engine)
+    want_rows = np.concatenate([R.extract(P, c) for c in chunks])
+    assert np.array_equal(rows, want_rows)
+    want_F = R.linear_rows(W[perm], want_rows[:n_in])
+    assert np.array_equal(Fo, want_F)
+    y = (W[perm] @ x) % P.p
+    pos = R.unpack_positions(P)
+    for g in range(packed.shape[0]):
+        assert np.array_equal(packed[g], R.pack(P, want_F[g * P.n_pack: (g + 1) * P.n_pack], keys)), g
+        seg = y[g * P.n_pack: (g + 1) * P.n_pack]
+        assert np.array_equal(cl.decrypt(packed[g])[pos[: seg.size]], seg), g
+
+
+@pytest.mark.parametrize("gamma,engine", [(1, 0), (2, 1)])
+def test_native_pipeline_paper_16bit_set(gamma, engine):
+    """The paper's 16-bit set (M = 5^5, N = 2500, D = 310, l = 4, p = 2^16, noise
+    2^-51), packs of phi(5^4) = 500 outputs; gamma = 1 on the int8 matrix cores
+    (digits of base 310 fit the 4/5-bit split), gamma = 2 on the 64-bit ALU engine
+    (one chunk: its 20 powers make the oracle's extraction slow).  Sampled rows and
+    layer outputs, every packed ciphertext element by element, decryptions equal to
+    the layer mod p."""
+    from paper_2509_01253_amd import fhelin as F
+    print(f"native 5^5 base 310 gamma={gamma} engine={engine}", flush=True)
+    P = R.NativeParams(5, 5, gamma, 4, 0, 4, 16, 2.0 ** 13, base=310)
+    cl = R.NativeClient(P, 1600 + gamma)
+    keys = cl.keyset()
+    rng = np.random.default_rng(1610 + gamma)
+    n_chunks = 2 if gamma == 1 else 1
+    n_in = n_chunks * P.N
+    x = rng.integers(0, 16, n_in)
+    chunks = np.stack([cl.encrypt_powers(x[c * P.N: (c + 1) * P.N]) for c in range(n_chunks)])
+    n_out = 2 * P.n_pack + 7
+    W = _conv_like(rng, n_out, n_in, 144, 8)
+    perm = rng.permutation(n_out)
+    rows, Fo, packed = _run(F, P, chunks, W, perm, keys, engine)
+    for c in range(n_chunks):
+        want = R.extract(P, chunks[c])
+        sel = rng.choice(P.N, 40, replace=False)
+        assert np.array_equal(rows[c * P.N + sel], want[sel]), c
+    sel = rng.choice(n_out, 30, replace=False)
+    assert np.array_equal(Fo[sel], R.linear_rows(W[perm][sel], rows))
+    y = (W[perm] @ x) % P.p
+    pos = R.unpack_positions(P)
+    for g in range(packed.shape[0]):
+        assert np.array_equal(packed[g], R.pack(P, Fo[g * P.n_pack: (g + 1) * P.n_pack], keys)), g
         seg = y[g * P.n_pack: (g + 1) * P.n_pack]
         assert np.array_equal(cl.decrypt(packed[g])[pos[: seg.size]], seg), g
 
