@@ -55,6 +55,9 @@ def parse():
                          "to the default run's line; 0: skip")
     ap.add_argument("--native-engine", type=int, default=0,
                     help="key-switch products of the native pipeline: 0 int8 matrix cores, 1 64-bit ALU")
+    ap.add_argument("--native-bits", type=int, choices=[8, 12, 16], default=8,
+                    help="parameter set of --native: the paper's 8-, 12- or 16-bit precision set (the 12-bit set's "
+                         "D = 2^16 needs --native-engine 1)")
     ap.add_argument("--native", type=int, default=0,
                     help="only the paper's own pipeline at this gamma (1 or 2): one JSON line")
     ap.add_argument("--fuse-baby", type=int, default=-1,
@@ -628,7 +631,12 @@ ALU_PROBES = {0: "v_add_u32", 1: "v_mul_lo_u32", 2: "v_mul_hi_u32", 3: "v_mad_u6
 
 # The paper's own pipeline (RLWE over Z_{2^64}[X]/Phi_M): its 8-bit parameter set
 # (M = 3^7, gadget D = 2^9, l = 3, p = 2^8) with packs of phi(3^6) = 486 outputs.
-NATIVE = {"t": 3, "alpha": 7, "beta": 6, "log_d": 9, "l": 3, "log_p": 8}
+NATIVE = {"t": 3, "alpha": 7, "beta": 6, "log_d": 9, "l": 3, "log_p": 8, "base": 0}
+# the table's other sets (gamma in [1, 2] columns): 12 bits M = 7^4, D = 2^16, l = 2;
+# 16 bits M = 5^5, D = 310, l = 4; packs of phi(t^(alpha-1)) outputs
+NATIVE_SETS = {8: NATIVE,
+               12: {"t": 7, "alpha": 4, "beta": 3, "log_d": 16, "l": 2, "log_p": 12, "base": 0},
+               16: {"t": 5, "alpha": 5, "beta": 4, "log_d": 0, "l": 4, "log_p": 16, "base": 310}}
 # 64-bit products per key-switch product in the packing GEMM's inner loop (gfx950
 # assembly of k_nat_ksprod: one v_mad_u64_u32 on the key's low word, one v_mul_lo_u32 on
 # its high word and half a v_add3_u32 per product: 327 VALU per 128 products)
@@ -657,9 +665,9 @@ def resnet20_layers() -> list:
     return L + [(64, 10, 1, 1, 1, 1)]
 
 
-def native_bench(gamma: int, reps: int = 2, engine: int = 0) -> dict:
+def native_bench(gamma: int, reps: int = 2, engine: int = 0, bits: int = 8) -> dict:
     """Server compute of one ResNet-20 inference under the paper's own pipeline at its
-    8-bit parameter set and extraction level gamma: per layer, partial trace extraction
+    `bits`-bit parameter set (8 by default) and extraction level gamma: per layer, partial trace extraction
     of the input chunks (ceil(E / N) chunks of phi(t^gamma) encrypted powers), the
     convolution on the extracted rows (4-bit weights, the round's shuffle as the output
     rows' order) and fast packing of the outputs (486 per packed ciphertext).
@@ -671,13 +679,13 @@ def native_bench(gamma: int, reps: int = 2, engine: int = 0) -> dict:
 
     from paper_2509_01253_amd import fhelin as F
 
-    c = NATIVE
+    c = NATIVE_SETS[bits]
     t, alpha, beta = c["t"], c["alpha"], c["beta"]
     M = t ** alpha
     N = M - M // t
     n_pack = (t - 1) * t ** (beta - 1)
     phig = (t - 1) * t ** (gamma - 1)
-    nt = F.fhelin_native_create(t, alpha, gamma, beta, c["log_d"], c["l"], c["log_p"], engine)
+    nt = F.fhelin_native_create(t, alpha, gamma, beta, c["log_d"], c["l"], c["log_p"], engine, c["base"])
     rng = np.random.default_rng(20 + gamma)
     gen = torch.Generator(device="cuda").manual_seed(20 + gamma)
 
@@ -747,8 +755,10 @@ def native_bench(gamma: int, reps: int = 2, engine: int = 0) -> dict:
     packs = sum(L["packed"].shape[0] for L in layers)
     ks = packs * (t ** (beta - gamma) - 1 + (alpha - beta) * (t - 1))
     ms = sum(tot)
+    dstr = str(c["base"]) if c["base"] else f"2^{c['log_d']}"
     return {"workload": f"ResNet-20 / CIFAR-10 linear layers ({len(layers)}: 21 convolutions incl. two 1x1 "
-                        f"projections, FC 64->10), paper's 8-bit set: M = 3^7, N = {N}, D = 2^9, l = 3, p = 2^8, "
+                        f"projections, FC 64->10), paper's {bits}-bit set: M = {t}^{alpha}, N = {N}, D = {dstr}, "
+                        f"l = {c['l']}, p = 2^{c['log_p']}, "
                         f"gamma = {gamma}, beta = {beta} ({n_pack} outputs per packed ciphertext), 4-bit weights, "
                         f"uniform keys and inputs",
             "gamma": gamma, "engine": "int8 matrix cores" if engine == 0 else "64-bit ALU",
@@ -797,7 +807,8 @@ def main():
         print(json.dumps(alu_rates(F)), flush=True)
         return
     if args.native > 0:
-        print(json.dumps({"native_resnet20": native_bench(args.native, engine=args.native_engine)}), flush=True)
+        print(json.dumps({"native_resnet20": native_bench(args.native, engine=args.native_engine,
+                                                          bits=args.native_bits)}), flush=True)
         return
     if args.calib_copy > 0:
         n = int(args.calib_copy * (1 << 30)) // 8
