@@ -998,8 +998,8 @@ int native_extract(Native *n, const uint64_t *pows, int n_chunks, uint64_t *rows
     const size_t lds = (size_t)pw.n * 2 * n->N * sizeof(uint64_t);
     // the staged kernel needs two workgroups per compute unit to hide its staging (with
     // one, the gather kernel measured faster: 5.5 against 8.0 ms per ResNet-20
-    // inference at M = 3^7, gamma = 2)
-    if (n->N <= EXT_T * EXT_J && 2 * lds <= (size_t)n->lds_max) {
+    // inference at M = 3^7, gamma = 2) and keeps its dynamic LDS within 64 KiB
+    if (n->N <= EXT_T * EXT_J && 2 * lds <= (size_t)n->lds_max && lds <= 65536) {
         // about two workgroups per resident slot (a slot per compute unit and whole
         // copy of the powers that fits its LDS): each copy serves as many rows as can be
         const int per_cu = std::max(1, (int)(std::max(n->lds_max, 1) / std::max<size_t>(lds, 1)));
