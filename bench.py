@@ -56,8 +56,7 @@ def parse():
     ap.add_argument("--native-engine", type=int, default=0,
                     help="key-switch products of the native pipeline: 0 int8 matrix cores, 1 64-bit ALU")
     ap.add_argument("--native-bits", type=int, choices=[8, 12, 16], default=8,
-                    help="parameter set of --native: the paper's 8-, 12- or 16-bit precision set (the 12-bit set's "
-                         "D = 2^16 needs --native-engine 1)")
+                    help="parameter set of --native: the paper's 8-, 12- or 16-bit precision set")
     ap.add_argument("--native", type=int, default=0,
                     help="only the paper's own pipeline at this gamma (1 or 2): one JSON line")
     ap.add_argument("--fuse-baby", type=int, default=-1,
@@ -647,8 +646,9 @@ PEAK_NAT_KS = ALU_LANE_OPS / NAT_KS_VALU_OPS / 1e12
 # 35 VALU per 16 products)
 NAT_CONV_VALU_OPS = 35 / 16
 PEAK_NAT_CONV = ALU_LANE_OPS / NAT_CONV_VALU_OPS / 1e12
-# the int8 matrix-core engine: each 64-bit product is 2 digit halves x 8 key bytes = 16
-# int8 multiply-adds (32 ops), priced against MI355X's dense int8 peak
+# the int8 matrix-core engine: each 64-bit product is 2 digit pieces (3 for gadget
+# bases above 2^9) x 8 key bytes int8 multiply-adds (2 ops each), priced against
+# MI355X's dense int8 peak
 INT8_OPS_PER_PRODUCT = 32
 PEAK_INT8_TOPS = 5000.0
 
@@ -739,7 +739,9 @@ def native_bench(gamma: int, reps: int = 2, engine: int = 0, bits: int = 8) -> d
             ach, peak, unit = units / (ms_k / 1e3) / 1e12, PEAK_NAT_CONV, "T 64-bit products/s"
         elif bound == "alu" and engine == 0:
             bound = "mfma"
-            ach, peak, unit = units * INT8_OPS_PER_PRODUCT / (ms_k / 1e3) / 1e12, PEAK_INT8_TOPS, "T int8 ops/s"
+            pieces = 3 if (c["base"] or 1 << c["log_d"]) > 512 else 2
+            ach, peak, unit = (units * INT8_OPS_PER_PRODUCT * pieces / 2 / (ms_k / 1e3) / 1e12, PEAK_INT8_TOPS,
+                               "T int8 ops/s")
         elif bound == "alu":
             ach, peak, unit = units / (ms_k / 1e3) / 1e12, PEAK_NAT_KS, "T 64-bit products/s"
         else:

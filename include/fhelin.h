@@ -437,9 +437,10 @@ typedef struct fhelin_native_params {
                            ciphertext, output o at coefficient o M / t^beta */
     int32_t log_d, l;   /* gadget base D = 2^log_d (1..16) and depth l (1..8), log_d l < 64 */
     int32_t log_p;      /* message modulus p = 2^log_p (1..31) */
-    int32_t engine;     /* key-switch products: 0 = int8 matrix cores (balanced 4/5-bit
-                           digit halves x balanced key bytes, exact i32 sums, needs
-                           D <= 512), 1 = 64-bit integer ALU products */
+    int32_t engine;     /* key-switch products: 0 = int8 matrix cores (digits split into
+                           two balanced int8 pieces for D <= 512, three up to D = 2^16,
+                           times balanced key bytes, exact i32 sums; l M <= 2^19),
+                           1 = 64-bit integer ALU products */
     int32_t base;       /* 0: gadget base D = 2^log_d; otherwise D itself (the paper's
                            16-bit set takes 310): even, 4..65536, D^l < 2^63, log_d
                            ignored.  The keys then encrypt s(X^g) round(2^64 / D^i)

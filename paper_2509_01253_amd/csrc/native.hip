@@ -440,12 +440,14 @@ __global__ void __launch_bounds__(256) k_nat_conv(const uint64_t *__restrict__ r
 }
 
 // ---------------------------------------------------------------------------
-// int8 matrix-core engine.  A balanced digit d in [-D/2, D/2) (D <= 2^9) is
-// lo + 16 hi with lo in [-8, 8), hi in [-16, 16]; a key entry K (mod 2^64) is
-// sum_b 2^(8b) s_b with balanced bytes s_b in [-128, 128).  Then
-//   sum_k d_k K_k = sum_b 2^(8b) (sum_k lo_k s_bk + 16 sum_k hi_k s_bk)   (mod 2^64)
-// and each inner sum is an int8 matrix product with an exact int32 sum
-// (|sum| <= 16 128 l N < 2^31 for l N <= 2^19).
+// int8 matrix-core engine.  A balanced digit d in [-D/2, D/2) is split into H int8
+// pieces: for D <= 2^9, d = p0 + 16 p1 with p0 in [-8, 8), p1 in [-16, 16] (H = 2); up
+// to D = 2^16, d = p0 + 32 p1 + 1024 p2 with p0, p1 in [-16, 16), p2 in [-32, 32]
+// (H = 3).  A key entry K (mod 2^64) is sum_b 2^(8b) s_b with balanced bytes s_b in
+// [-128, 128).  Then
+//   sum_k d_k K_k = sum_b 2^(8b) sum_h w_h (sum_k p_hk s_bk)   (mod 2^64),  w_h = 16^h or 32^h,
+// and each inner sum is an int8 matrix product with an exact int32 sum (|sum| <= 32
+// 128 K < 2^31 for K <= 2^19).
 // ---------------------------------------------------------------------------
 typedef int v4i __attribute__((ext_vector_type(4)));
 
@@ -463,9 +465,11 @@ __device__ __forceinline__ int64_t k8_at(int row, int k, int nkc) {
            (k & 15);
 }
 
-// digits of a batch as two int8 planes (h = 0: low halves, 1: high), row c, k = i N + m
-// (zero past l N), in the tiled operand layout (a_half bytes per plane), and the
-// output's start value out = (add_a, add_b + sigma(b)); grid (ceil(N / 256), n)
+// digits of a batch as H int8 planes (the pieces of each digit, least significant
+// first), row c, k = i N + m (zero past l N), in the tiled operand layout (a_half bytes
+// per plane), and the output's start value out = (add_a, add_b + sigma(b)); grid
+// (ceil(N / 256), n)
+template <int H>
 __global__ void __launch_bounds__(256) k_nat_aut_decomp8(const uint64_t *__restrict__ S, int64_t s_es,
                                                          const uint64_t *__restrict__ add, int64_t add_es,
                                                          uint64_t *__restrict__ out, int64_t out_es,
@@ -473,11 +477,10 @@ __global__ void __launch_bounds__(256) k_nat_aut_decomp8(const uint64_t *__restr
                                                          NatGadget g, int KDp) {
     const int j = blockIdx.x * 256 + threadIdx.x;
     const int c = blockIdx.y, nkc = KDp >> 6, l = g.l;
-    int8_t *lo = A8, *hi = A8 + a_half;
     if (j < KDp - l * dm.N) {  // the padding of the row
         const int64_t o = k8_at(c, l * dm.N + j, nkc);
-        lo[o] = 0;
-        hi[o] = 0;
+#pragma unroll
+        for (int h = 0; h < H; ++h) A8[h * a_half + o] = 0;
     }
     if (j >= dm.N) return;
     const uint64_t *a = S + c * s_es, *b = a + dm.N;
@@ -489,10 +492,18 @@ __global__ void __launch_bounds__(256) k_nat_aut_decomp8(const uint64_t *__restr
     uint64_t top = gadget_top(av, g);
     for (int i = l - 1; i >= 0; --i) {
         const int d = gadget_digit(top, g);
-        const int h = (d + 8) >> 4;  // floor division: lo = d - 16 h in [-8, 8)
         const int64_t o = k8_at(c, i * dm.N + j, nkc);
-        lo[o] = (int8_t)(d - 16 * h);
-        hi[o] = (int8_t)h;
+        if constexpr (H == 2) {  // d = p0 + 16 p1, p0 in [-8, 8), p1 in [-16, 16] (|d| <= 256)
+            const int p1 = (d + 8) >> 4;
+            A8[o] = (int8_t)(d - 16 * p1);
+            A8[a_half + o] = (int8_t)p1;
+        } else {  // d = p0 + 32 p1 + 1024 p2, p0, p1 in [-16, 16), p2 in [-32, 32] (|d| <= 2^15)
+            const int p0 = ((d + 16) & 31) - 16, d1 = (d - p0) >> 5;
+            const int p1 = ((d1 + 16) & 31) - 16, p2 = (d1 - p1) >> 5;
+            A8[o] = (int8_t)p0;
+            A8[a_half + o] = (int8_t)p1;
+            A8[2 * a_half + o] = (int8_t)p2;
+        }
     }
 }
 
@@ -504,20 +515,20 @@ __global__ void __launch_bounds__(256) k_nat_aut_decomp8(const uint64_t *__restr
 // 4 (l / 16) + r, column l mod 16.  Byte planes go one at a time (b outer), each
 // folded into the 64-bit results after its K loop.
 //
-// Staging: a stage is one 64-byte K chunk of both operands (the digit halves of 64
-// ciphertexts and both key parts of 64 coefficients: sixteen 1 KiB blocks of 16 rows,
-// each contiguous in the tiled operand layout and copied to LDS as it is).
+// Staging: a stage is one 64-byte K chunk of both operands (the digit pieces of 64
+// ciphertexts and both key parts of 64 coefficients: 4 H + 8 blocks of 1 KiB holding 16
+// rows each, contiguous in the tiled operand layout and copied to LDS as they are).
 // The chunks of all planes form one sequence; their loads go straight from global
 // memory into a ring of K8_NS stages in LDS (global_load_lds, 16 bytes per lane, no
-// registers), K8_NS - 1 stages ahead of the products.  Each wave fills four blocks of
-// every stage and waits only for its own loads of the stage it reads next (vmcnt); a
-// barrier then tells every wave that all loads of that stage have landed and that the
-// slot it refills next has been read.  Fragments are double-buffered in registers, so
-// a stage's products run while the next stage's fragments are read.
+// registers), one stage fewer than the ring ahead of the products.  Each wave fills a
+// quarter of every stage's blocks and waits only for its own loads of the stage it
+// reads next (vmcnt); a barrier then tells every wave that all loads of that stage have
+// landed and that the slot it refills next has been read.  With two pieces the
+// fragments are double-buffered in registers, so a stage's products run while the next
+// stage's fragments are read.
 // Rows past the batch or the ring (the padding of the last tile) hold any values and
 // only feed outputs that are not written.  grid.z splits K as in k_nat_ksprod.
-constexpr int K8_NS = 4;             // stages in the LDS ring
-constexpr int K8_STAGE = 16 * 1024;  // bytes per stage
+constexpr int K8_NS = 4;  // stages in the LDS ring (two digit pieces)
 
 typedef __attribute__((address_space(3))) void *lds_ptr_t;
 
@@ -549,10 +560,27 @@ __device__ __forceinline__ void k8_tile(int &tc, int &tj, int &tz) {
     tj = in / gsize;
 }
 
+// H digit pieces (2 for D <= 512: d = p0 + 16 p1; 3 for larger D up to 2^16: d = p0 +
+// 32 p1 + 1024 p2), each an int8 plane of the tiled layout; a stage holds 4 H + 8
+// blocks.  Three pieces take a three-stage ring and single-buffered fragments (the
+// accumulators grow by half).
+template <int H>
+struct K8Cfg {
+    static constexpr int NS = H == 2 ? K8_NS : 3;   // stages in the ring
+    static constexpr int NB = 4 * H + 8;            // 1 KiB blocks per stage
+    static constexpr int BPW = NB / 4;              // blocks each wave loads
+    static constexpr int STAGE = NB * 1024;
+    static constexpr int NF = H == 2 ? 2 : 1;       // fragment buffers
+    static constexpr int SHIFT = H == 2 ? 4 : 5;    // piece h weighs 2^(SHIFT h)
+};
+
+template <int H>
 __global__ void __launch_bounds__(256, 2) k_nat_ksprod8(const int8_t *__restrict__ A8, int64_t a_half,
                                                      const int8_t *__restrict__ B8, uint64_t *__restrict__ out,
                                                      int64_t out_es, int n, int N, int KDp, int kc) {
-    __shared__ __attribute__((aligned(16))) int8_t ring[K8_NS * K8_STAGE];
+    using C = K8Cfg<H>;
+    constexpr int NS = C::NS, NB = C::NB, BPW = C::BPW, STAGE = C::STAGE, NF = C::NF;
+    __shared__ __attribute__((aligned(16))) int8_t ring[NS * STAGE];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     int tc, tj, tz;
     k8_tile(tc, tj, tz);
@@ -562,28 +590,32 @@ __global__ void __launch_bounds__(256, 2) k_nat_ksprod8(const int8_t *__restrict
     const int nk = (ke - kb) >> 6, total = 8 * nk;  // chunks per plane, stages in all
     const int r16 = lane & 15, g = lane >> 4;
     const int64_t plane = (int64_t)((N + 63) & ~63) * KDp;  // bytes per key byte plane
-    // loads: wave w fills blocks 4w .. 4w + 3 of a stage (waves 0, 1: the digit halves,
-    // waves 2, 3: the key parts; block 4 s + t holds rows 16 t .. 16 t + 15 of operand
-    // part s), lane l the 16 bytes at 16 l of the block
+    // loads: wave w fills blocks BPW w .. BPW w + BPW - 1 of a stage; block 4 h + t holds
+    // rows 16 t .. 16 t + 15 of digit piece h, block 4 H + 4 p + t those of key part p;
+    // lane l the 16 bytes at 16 l of the block
     const int nkc = KDp >> 6;
-    const int8_t *src[4];
+    const int8_t *src[BPW];
+    bool keyb[BPW];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int bl = 4 * w + i, part = (bl >> 2) & 1, t = bl & 3;
-        src[i] = (bl < 8 ? A8 + part * a_half + ((int64_t)tc * nkc * 4 + t) * 1024
-                         : B8 + (int64_t)part * 8 * plane + ((int64_t)tj * nkc * 4 + t) * 1024) +
+    for (int i = 0; i < BPW; ++i) {
+        const int bl = BPW * w + i;
+        keyb[i] = bl >= 4 * H;
+        const int part = (keyb[i] ? bl - 4 * H : bl) >> 2, t = bl & 3;
+        src[i] = (keyb[i] ? B8 + (int64_t)part * 8 * plane + ((int64_t)tj * nkc * 4 + t) * 1024
+                          : A8 + part * a_half + ((int64_t)tc * nkc * 4 + t) * 1024) +
                  16 * lane;
     }
     auto issue = [&](int st) {
         const int b = st / nk, kcs = (kb >> 6) + (st - b * nk);
-        const int64_t off = (w >= 2 ? (int64_t)b * plane : 0) + (int64_t)kcs * 4096;
-        int8_t *dst = ring + (st % K8_NS) * K8_STAGE + w * 4096;
+        int8_t *dst = ring + (st % NS) * STAGE + w * BPW * 1024;
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-            __builtin_amdgcn_global_load_lds((const void *)(src[i] + off), (lds_ptr_t)(dst + i * 1024), 16, 0, 0);
+        for (int i = 0; i < BPW; ++i)
+            __builtin_amdgcn_global_load_lds(
+                (const void *)(src[i] + (keyb[i] ? (int64_t)b * plane : 0) + (int64_t)kcs * 4096),
+                (lds_ptr_t)(dst + i * 1024), 16, 0, 0);
     };
     uint64_t res[2][2][2][4];
-    v4i acc[2][2][2][2];  // [part][half][c tile][j tile]
+    v4i acc[2][H][2][2];  // [part][piece][c tile][j tile]
 #pragma unroll
     for (int p = 0; p < 2; ++p)
 #pragma unroll
@@ -593,30 +625,31 @@ __global__ void __launch_bounds__(256, 2) k_nat_ksprod8(const int8_t *__restrict
 #pragma unroll
                 for (int r = 0; r < 4; ++r) res[p][a][bq][r] = 0;
 #pragma unroll
-                for (int h = 0; h < 2; ++h) acc[p][h][a][bq] = v4i{0, 0, 0, 0};
+                for (int h = 0; h < H; ++h) acc[p][h][a][bq] = v4i{0, 0, 0, 0};
             }
     const int slot = 16 * (4 * r16 + (g ^ k8_swz(r16)));
-    auto frags = [&](v4i (&af)[2][2], v4i (&bf)[2][2], int st) {
-        const int8_t *stg = ring + (st % K8_NS) * K8_STAGE + slot;
+    v4i fa[NF][H][2], fb[NF][2][2];
+    auto frags = [&](int f, int st) {
+        const int8_t *stg = ring + (st % NS) * STAGE + slot;
 #pragma unroll
         for (int t2 = 0; t2 < 2; ++t2) {
 #pragma unroll
-            for (int h = 0; h < 2; ++h) af[h][t2] = *(const v4i *)(stg + 1024 * (4 * h + (wc >> 4) + t2));
+            for (int h = 0; h < H; ++h) fa[f][h][t2] = *(const v4i *)(stg + 1024 * (4 * h + (wc >> 4) + t2));
 #pragma unroll
-            for (int p = 0; p < 2; ++p) bf[p][t2] = *(const v4i *)(stg + 1024 * (8 + 4 * p + (wj >> 4) + t2));
+            for (int p = 0; p < 2; ++p) fb[f][p][t2] = *(const v4i *)(stg + 1024 * (4 * H + 4 * p + (wj >> 4) + t2));
         }
     };
-    auto products = [&](const v4i (&af)[2][2], const v4i (&bf)[2][2]) {
+    auto products = [&](int f) {
 #pragma unroll
         for (int p = 0; p < 2; ++p)
 #pragma unroll
-            for (int h = 0; h < 2; ++h)
+            for (int h = 0; h < H; ++h)
 #pragma unroll
                 for (int a = 0; a < 2; ++a)
 #pragma unroll
                     for (int bq = 0; bq < 2; ++bq)
                         acc[p][h][a][bq] =
-                            __builtin_amdgcn_mfma_i32_16x16x64_i8(af[h][a], bf[p][bq], acc[p][h][a][bq], 0, 0, 0);
+                            __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[f][h][a], fb[f][p][bq], acc[p][h][a][bq], 0, 0, 0);
     };
     auto fold = [&](int it) {  // after the last chunk of plane b: fold and restart
         if ((it + 1) % nk) return;
@@ -628,46 +661,49 @@ __global__ void __launch_bounds__(256, 2) k_nat_ksprod8(const int8_t *__restrict
 #pragma unroll
                 for (int bq = 0; bq < 2; ++bq) {
 #pragma unroll
-                    for (int r = 0; r < 4; ++r)
-                        res[p][a][bq][r] +=
-                            (uint64_t)((int64_t)acc[p][0][a][bq][r] + 16 * (int64_t)acc[p][1][a][bq][r]) << (8 * b);
+                    for (int r = 0; r < 4; ++r) {
+                        int64_t v = 0;
 #pragma unroll
-                    for (int h = 0; h < 2; ++h) acc[p][h][a][bq] = v4i{0, 0, 0, 0};
+                        for (int h = 0; h < H; ++h) v += (int64_t)acc[p][h][a][bq][r] << (C::SHIFT * h);
+                        res[p][a][bq][r] += (uint64_t)v << (8 * b);
+                    }
+#pragma unroll
+                    for (int h = 0; h < H; ++h) acc[p][h][a][bq] = v4i{0, 0, 0, 0};
                 }
     };
     // every wave's loads of stage it + 1 are in LDS and every wave has its fragments of
     // stage it in registers (own LDS reads drained), so stage it's slot can be refilled
     auto sync_next = [&](int it) {
-        if (it + K8_NS - 1 < total) k8_wait<4 * (K8_NS - 2)>();
+        if (it + NS - 1 < total) k8_wait<BPW * (NS - 2)>();
         else k8_wait<0>();
         asm volatile("" ::: "memory");
         __builtin_amdgcn_s_barrier();
         asm volatile("" ::: "memory");
     };
     // the ring starts full; stage it's products run while stage it + 1's fragments are
-    // read and stage it + K8_NS is loaded into the slot stage it left
-    for (int st = 0; st < K8_NS && st < total; ++st) issue(st);
-    if (K8_NS - 1 < total) k8_wait<4 * (K8_NS - 1)>();
+    // read (into the other buffer when there are two) and stage it + NS is loaded into
+    // the slot stage it left
+    for (int st = 0; st < NS && st < total; ++st) issue(st);
+    if (NS - 1 < total) k8_wait<BPW * (NS - 1)>();
     else k8_wait<0>();
     asm volatile("" ::: "memory");
     __builtin_amdgcn_s_barrier();
     asm volatile("" ::: "memory");
-    v4i fa0[2][2], fb0[2][2], fa1[2][2], fb1[2][2];
-    frags(fa0, fb0, 0);
+    frags(0, 0);
     for (int it = 0; it < total; it += 2) {
-        products(fa0, fb0);
+        products(0);
         if (it + 1 < total) {
             sync_next(it);
-            if (it + K8_NS < total) issue(it + K8_NS);
-            frags(fa1, fb1, it + 1);
+            if (it + NS < total) issue(it + NS);
+            frags(1 % NF, it + 1);
         }
         fold(it);
         if (it + 1 >= total) break;
-        products(fa1, fb1);
+        products(1 % NF);
         if (it + 2 < total) {
             sync_next(it + 1);
-            if (it + 1 + K8_NS < total) issue(it + 1 + K8_NS);
-            frags(fa0, fb0, it + 2);
+            if (it + 1 + NS < total) issue(it + 1 + NS);
+            frags(0, it + 2);
         }
         fold(it + 1);
     }
@@ -875,8 +911,8 @@ int native_create(const fhelin_native_params *prm, Native **out) {
     }
     FL_CHECK(q.log_p >= 1 && q.log_p <= 31, FHELIN_E_UNSUPPORTED_PARAM, "message modulus: 1 <= log_p <= 31");
     FL_CHECK(q.engine == 0 || q.engine == 1, FHELIN_E_UNSUPPORTED_PARAM, "engine: 0 (int8 matrix cores) or 1 (ALU)");
-    FL_CHECK(q.engine == 1 || gad.D <= 512, FHELIN_E_UNSUPPORTED_PARAM,
-             "the int8 engine splits digits into 4- and 5-bit halves: D <= 512");
+    FL_CHECK(q.engine == 1 || (gad.D <= 65536 && (int64_t)q.l * ipow(q.t, q.alpha) <= (1 << 19)),
+             FHELIN_E_UNSUPPORTED_PARAM, "the int8 engine splits digits into int8 pieces: D <= 2^16");
     std::unique_ptr<Native> n(new Native());
     n->prm = q;
     n->gad = gad;
@@ -1038,7 +1074,7 @@ size_t native_pack_workspace(const Native *n, int n_rows) {
     const size_t nmax = packs * n->T;  // the leaves: the widest level
     // current sub-packs, merge terms (t per merge), results, and the digits of a
     // key-switch batch
-    const size_t dig = std::max(nmax * (size_t)n->prm.l * n->N * sizeof(uint32_t), 2 * ((nmax + 63) & ~(size_t)63) * n->KDp);
+    const size_t dig = std::max(nmax * (size_t)n->prm.l * n->N * sizeof(uint32_t), 3 * ((nmax + 63) & ~(size_t)63) * n->KDp);
     return 3 * nmax * ct + dig;
 }
 
@@ -1072,24 +1108,33 @@ static int nat_ks_step(Native *n, int lv, const uint64_t *S, int64_t s_es, const
         const int c = std::min(cnt - c0, 65535);
         if (n->prm.engine == 0) {
             int8_t *A8 = (int8_t *)dig;
+            const bool three = n->gad.D > 512;  // digit pieces: 2, or 3 beyond D = 2^9
             const int64_t a_half = (int64_t)((c + 63) & ~63) * n->KDp;
             {
                 NatProf pa(n, s, NK_AUT_DECOMP, (double)c * n->N, (double)c * n->N * (2 * 8.0 + 2 * 8.0 + 2 * 8.0 + 2.0 * l));
-                hipLaunchKernelGGL(k_nat_aut_decomp8, dim3((std::max(n->N, n->KDp - (int)KD) + 255) / 256, c), dim3(256),
-                                   0, s, S + c0 * s_es, s_es, add + c0 * add_es, add_es, out + c0 * out_es, out_es, A8,
-                                   a_half, dm, n->tau_inv[lv], n->gad, n->KDp);
+                const dim3 gd((std::max(n->N, n->KDp - (int)KD) + 255) / 256, c);
+                if (three)
+                    hipLaunchKernelGGL(k_nat_aut_decomp8<3>, gd, dim3(256), 0, s, S + c0 * s_es, s_es, add + c0 * add_es,
+                                       add_es, out + c0 * out_es, out_es, A8, a_half, dm, n->tau_inv[lv], n->gad, n->KDp);
+                else
+                    hipLaunchKernelGGL(k_nat_aut_decomp8<2>, gd, dim3(256), 0, s, S + c0 * s_es, s_es, add + c0 * add_es,
+                                       add_es, out + c0 * out_es, out_es, A8, a_half, dm, n->tau_inv[lv], n->gad, n->KDp);
                 FL_TRY_HIP(hipGetLastError());
             }
             const int gx = (n->N + 63) / 64, gy = (c + 63) / 64;
             const int kc = 64 * k8_split(gx * gy, n->KDp / 64, 2 * std::max(n->cus, 1));
             const int gz = (n->KDp + kc - 1) / kc;
             const int8_t *B8 = n->kmat8 + (int64_t)lv * 2 * 8 * ((n->N + 63) & ~63) * n->KDp;
-            // units: 64-bit products (both key parts); bytes: both digit planes and the
+            // units: 64-bit products (both key parts); bytes: the digit planes and the
             // sixteen key planes once per launch, the output read and written
             NatProf pk(n, s, NK_KSPROD, 2.0 * c * n->N * (double)KD,
-                       2.0 * c * n->KDp + 16.0 * n->N * n->KDp + (double)c * n->N * 8 * 4);
-            hipLaunchKernelGGL(k_nat_ksprod8, dim3(gx, gy, gz), dim3(256), 0, s, A8, a_half, B8, out + c0 * out_es, out_es, c,
-                               n->N, n->KDp, kc);
+                       (three ? 3.0 : 2.0) * c * n->KDp + 16.0 * n->N * n->KDp + (double)c * n->N * 8 * 4);
+            if (three)
+                hipLaunchKernelGGL(k_nat_ksprod8<3>, dim3(gx, gy, gz), dim3(256), 0, s, A8, a_half, B8, out + c0 * out_es,
+                                   out_es, c, n->N, n->KDp, kc);
+            else
+                hipLaunchKernelGGL(k_nat_ksprod8<2>, dim3(gx, gy, gz), dim3(256), 0, s, A8, a_half, B8, out + c0 * out_es,
+                                   out_es, c, n->N, n->KDp, kc);
             FL_TRY_HIP(hipGetLastError());
             continue;
         }

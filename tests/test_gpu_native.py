@@ -129,16 +129,16 @@ def test_native_pipeline_paper_8bit_set(gamma, engine):
         assert np.array_equal(cl.decrypt(packed[g])[pos[: seg.size]], seg), g
 
 
-@pytest.mark.parametrize("gamma", [1, 2])
-def test_native_pipeline_paper_12bit_set(gamma):
+@pytest.mark.parametrize("gamma,engine", [(1, 0), (1, 1), (2, 0), (2, 1)])
+def test_native_pipeline_paper_12bit_set(gamma, engine):
     """The paper's 12-bit set (M = 7^4, N = 2058, D = 2^16, l = 2, p = 2^12, noise
-    2^-51) on the 64-bit ALU engine (the int8 engine takes D <= 2^9), packs of
+    2^-51) on both engines (the int8 matrix cores split its digits into three pieces), packs of
     phi(7^3) = 294 outputs: a convolution-shaped layer (144 weights of 4 bits per
     output) over two chunks (one at gamma = 2, whose 42 powers make the oracle's
     extraction slow); rows and layer outputs compared on sampled rows, every packed
     ciphertext element by element, and the decryptions equal to the layer mod p."""
     from paper_2509_01253_amd import fhelin as F
-    print(f"native 7^4 gamma={gamma} engine=1", flush=True)
+    print(f"native 7^4 gamma={gamma} engine={engine}", flush=True)
     P = R.NativeParams(7, 4, gamma, 3, 16, 2, 12, 2.0 ** 13)
     cl = R.NativeClient(P, 1200 + gamma)
     keys = cl.keyset()
@@ -150,7 +150,7 @@ def test_native_pipeline_paper_12bit_set(gamma):
     n_out = 2 * P.n_pack + 7
     W = _conv_like(rng, n_out, n_in, 144, 8)
     perm = rng.permutation(n_out)
-    rows, Fo, packed = _run(F, P, chunks, W, perm, keys, engine=1)
+    rows, Fo, packed = _run(F, P, chunks, W, perm, keys, engine)
     for c in range(n_chunks):
         want = R.extract(P, chunks[c])
         sel = rng.choice(P.N, 40, replace=False)
@@ -201,6 +201,44 @@ def test_native_pipeline_base_310_small_rings(t, alpha, gamma, beta, engine):
         assert np.array_equal(packed[g], R.pack(P, want_F[g * P.n_pack: (g + 1) * P.n_pack], keys)), g
         seg = y[g * P.n_pack: (g + 1) * P.n_pack]
         assert np.array_equal(cl.decrypt(packed[g])[pos[: seg.size]], seg), g
+
+
+@pytest.mark.parametrize("t,alpha,gamma,beta,log_d,l,base", [(3, 4, 1, 3, 12, 2, 0), (5, 3, 2, 2, 0, 2, 1000),
+                                                              (3, 4, 2, 3, 16, 2, 0)])
+def test_native_three_piece_digits_small_rings(t, alpha, gamma, beta, log_d, l, base):
+    """Gadget bases above 2^9 (2^12, 1000, 2^16) on small rings: the int8 engine's
+    three-piece digits against the oracle (rows, layer outputs, every packed ciphertext
+    element by element) and the ALU engine giving the same bits."""
+    from paper_2509_01253_amd import fhelin as F
+    print(f"native three pieces t={t} alpha={alpha} gamma={gamma} log_d={log_d} l={l} base={base}", flush=True)
+    P = R.NativeParams(t, alpha, gamma, beta, log_d, l, 12, 2.0 ** 13, base=base)
+    cl = R.NativeClient(P, 900 + t * 10 + alpha + base % 97)
+    keys = cl.keyset()
+    rng = np.random.default_rng(910 + t * 10 + gamma)
+    n_in = P.N + P.N // 3
+    x = rng.integers(0, 16, n_in)
+    chunks = []
+    for c in range(2):
+        m = np.zeros(P.N, np.int64)
+        part = x[c * P.N: (c + 1) * P.N]
+        m[: part.size] = part
+        chunks.append(cl.encrypt_powers(m))
+    chunks = np.stack(chunks)
+    n_out = 2 * P.n_pack + 5
+    W = _conv_like(rng, n_out, n_in, min(24, n_in), 8)
+    perm = rng.permutation(n_out)
+    rows, Fo, packed = _run(F, P, chunks, W, perm, keys, 0)
+    want_rows = np.concatenate([R.extract(P, c) for c in chunks])
+    assert np.array_equal(rows, want_rows)
+    want_F = R.linear_rows(W[perm], want_rows[:n_in])
+    assert np.array_equal(Fo, want_F)
+    y = (W[perm] @ x) % P.p
+    pos = R.unpack_positions(P)
+    for g in range(packed.shape[0]):
+        assert np.array_equal(packed[g], R.pack(P, want_F[g * P.n_pack: (g + 1) * P.n_pack], keys)), g
+        seg = y[g * P.n_pack: (g + 1) * P.n_pack]
+        assert np.array_equal(cl.decrypt(packed[g])[pos[: seg.size]], seg), g
+    assert np.array_equal(_run(F, P, chunks, W, perm, keys, 1)[2], packed)
 
 
 @pytest.mark.parametrize("gamma,engine", [(1, 0), (2, 1)])
