@@ -100,25 +100,44 @@ struct NatPowers {
     int32_t d[NAT_MAX_POW];
 };
 
+// The t - 1 rows i = r + q M/t (q < t - 1) share r = i mod M/t and with it the second
+// term X^(d (M/t - r)) of every power: a thread gathers that term's coefficients once
+// for up to EXT_Q rows and the first term's for each of them.
+// grid (ceil(N / 256), M/t * ceil((t - 1) / EXT_Q), chunks).
+constexpr int EXT_Q = 8;
 __global__ void __launch_bounds__(256) k_nat_extract(const uint64_t *__restrict__ pows, uint64_t *__restrict__ rows,
-                                                     NatDims dm, NatPowers pw, uint64_t u) {
+                                                     NatDims dm, NatPowers pw, uint64_t u, int t) {
     const int j = blockIdx.x * 256 + threadIdx.x;
     if (j >= dm.N) return;
-    const int i = blockIdx.y, ch = blockIdx.z;
-    const int r = i % dm.Mt;
+    const int r = blockIdx.y % dm.Mt, q0 = blockIdx.y / dm.Mt * EXT_Q, ch = blockIdx.z;
+    const int nq = min(EXT_Q, t - 1 - q0);
     const int64_t ct = 2 * (int64_t)dm.N;
     const uint64_t *src = pows + (int64_t)ch * pw.n * ct;
-    uint64_t acc0 = 0, acc1 = 0;
+    uint64_t acc0[EXT_Q], acc1[EXT_Q], g0 = 0, g1 = 0;
+#pragma unroll
+    for (int q = 0; q < EXT_Q; ++q) acc0[q] = acc1[q] = 0;
     for (int k = 0; k < pw.n; ++k) {
         const int d = pw.d[k];
-        const int e1 = (int)(((int64_t)d * (dm.M - i)) % dm.M), e2 = (int)(((int64_t)d * (dm.Mt - r)) % dm.M);
         const uint64_t *a = src + k * ct, *b = a + dm.N;
-        acc0 += mono_at(a, j, e1, dm) - mono_at(a, j, e2, dm);
-        acc1 += mono_at(b, j, e1, dm) - mono_at(b, j, e2, dm);
+        const int e2 = (int)(((int64_t)d * (dm.Mt - r)) % dm.M);
+        g0 += mono_at(a, j, e2, dm);
+        g1 += mono_at(b, j, e2, dm);
+#pragma unroll
+        for (int q = 0; q < EXT_Q; ++q)
+            if (q < nq) {
+                const int i = r + (q0 + q) * dm.Mt;
+                const int e1 = (int)(((int64_t)d * (dm.M - i)) % dm.M);
+                acc0[q] += mono_at(a, j, e1, dm);
+                acc1[q] += mono_at(b, j, e1, dm);
+            }
     }
-    uint64_t *o = rows + ((int64_t)ch * dm.N + i) * ct;
-    o[j] = acc0 * u;
-    o[dm.N + j] = acc1 * u;
+#pragma unroll
+    for (int q = 0; q < EXT_Q; ++q)
+        if (q < nq) {
+            uint64_t *o = rows + ((int64_t)ch * dm.N + r + (q0 + q) * dm.Mt) * ct;
+            o[j] = (acc0[q] - g0) * u;
+            o[dm.N + j] = (acc1[q] - g1) * u;
+        }
 }
 
 // The same rows with the chunk's powers staged in LDS once per workgroup: a workgroup
@@ -1044,8 +1063,9 @@ int native_extract(Native *n, const uint64_t *pows, int n_chunks, uint64_t *rows
         hipLaunchKernelGGL(k_nat_extract_lds, dim3((n->N + rpg - 1) / rpg, n_chunks), dim3(EXT_T), lds, s, pows, rows,
                            dims(n), pw, n->u, rpg);
     } else {
-        hipLaunchKernelGGL(k_nat_extract, dim3((n->N + 255) / 256, n->N, n_chunks), dim3(256), 0, s, pows, rows,
-                           dims(n), pw, n->u);
+        const int passes = (n->prm.t - 2) / EXT_Q + 1;  // ceil((t - 1) / EXT_Q)
+        hipLaunchKernelGGL(k_nat_extract, dim3((n->N + 255) / 256, n->Mt * passes, n_chunks), dim3(256), 0, s, pows,
+                           rows, dims(n), pw, n->u, n->prm.t);
     }
     FL_TRY_HIP(hipGetLastError());
     return FHELIN_OK;
