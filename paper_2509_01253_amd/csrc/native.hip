@@ -209,6 +209,141 @@ __global__ void __launch_bounds__(EXT_T) k_nat_extract_lds(const uint64_t *__res
     }
 }
 
+// The rows streamed through LDS one power polynomial at a time, for rings with M <= 4096
+// whose powers do not fit LDS whole.  A workgroup computes the rows i = r + q M/t,
+// q0 <= q < q0 + nq, of one chunk and accumulates them in the cyclic ring Z[X]/(X^M - 1)
+// at all M positions (the reduction modulo Phi_M, coefficient j minus coefficient
+// N + j mod M/t, is linear and taken once at the end): a gather per position and row
+// instead of two per coefficient, the second term X^(d (M/t - r)) gathered once for the
+// nq rows.  Units u = b n_pow + k (polynomial b of power k) pass through two LDS slots
+// of EXS_SLOT words, [0, N) the unit's coefficients and [N, M) zeros; the next unit's
+// loads are in registers while the current one is read.  Thread x owns positions
+// x + EXS_T p, p < X (M <= X EXS_T); rows per workgroup Q at most.
+// grid (M/t ceil((t - 1) / Q), chunks), EXS_T threads, 64 KiB of static LDS.
+constexpr int EXS_T = 512;
+constexpr int EXS_SLOT = 4096;  // words per slot: M <= 4096
+template <int X, int Q>
+__global__ void __launch_bounds__(EXS_T, 2) k_nat_extract_stream(const uint64_t *__restrict__ pows,
+                                                                 uint64_t *__restrict__ rows, NatDims dm,
+                                                                 NatPowers pw, uint64_t u, int t) {
+    __shared__ uint64_t L[2 * EXS_SLOT];
+    const int tid = threadIdx.x;
+    const int r = blockIdx.x % dm.Mt, q0 = blockIdx.x / dm.Mt * Q, ch = blockIdx.y;
+    const int nq = min(Q, t - 1 - q0);
+    const int64_t ct = 2 * (int64_t)dm.N;
+    const uint64_t *src = pows + (int64_t)ch * pw.n * ct;
+    const int U = 2 * pw.n;
+    uint64_t acc[Q][X], g[X], pre[X];
+#pragma unroll
+    for (int p = 0; p < X; ++p) {
+        g[p] = 0;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) acc[q][p] = 0;
+    }
+    // unit u into the staging registers: coefficient x of polynomial b of power k, zero
+    // for N <= x < M
+    auto load = [&](int uu) {
+        const uint64_t *c = src + (uu % pw.n) * ct + (uu / pw.n) * dm.N;
+#pragma unroll
+        for (int p = 0; p < X; ++p) {
+            const int x = tid + EXS_T * p;
+            pre[p] = x < dm.N ? c[x] : 0;
+        }
+    };
+    // positions M <= x < X EXS_T (at most EXS_SLOT) hold zeros and gather in-slot values
+    // that are never read back
+    auto store = [&](int slot) {
+#pragma unroll
+        for (int p = 0; p < X; ++p) L[slot * EXS_SLOT + tid + EXS_T * p] = pre[p];
+    };
+    // x mod M for x < 2^26 by a multiply: mmag = floor(2^44 / M) + 1 overshoots 1 / M by
+    // under 2^-44, so x mmag / 2^44 exceeds x / M by under 2^-18, less than the gap
+    // 1 / M >= 2^-13 between x / M's fraction and 1
+    const uint64_t mmag = (1ull << 44) / (uint64_t)dm.M + 1;
+    auto mod_m = [&](uint32_t x) { return x - (uint32_t)(((uint64_t)x * mmag) >> 44) * (uint32_t)dm.M; };
+    uint32_t xb[X];  // byte offsets of the thread's positions
+#pragma unroll
+    for (int p = 0; p < X; ++p) xb[p] = 8u * (uint32_t)(tid + EXS_T * p);
+    const uint32_t mb = 8u * (uint32_t)dm.M;
+    // coefficient x of X^e c modulo X^M - 1 is c at (x + M - e) mod M: with ob = 8 (M - e),
+    // M - e in [1, M], and x < EXS_SLOT the byte index xb + ob is below 8 (EXS_SLOT + M),
+    // and the unsigned minimum of it and itself less 8 M is the remainder's (below
+    // 8 EXS_SLOT)
+    auto gather = [&](const char *base, uint32_t x8, uint32_t ob) {
+        const uint32_t sb = x8 + ob;
+        return *(const uint64_t *)(base + min(sb, sb - mb));
+    };
+    auto compute = [&](int slot, int uu) {
+        const char *base = (const char *)(L + slot * EXS_SLOT);
+        const uint32_t d = (uint32_t)pw.d[uu % pw.n];
+        const uint32_t e2 = mod_m(d * (uint32_t)(dm.Mt - r));
+        // e1 of row r + (q0 + q) M/t is d (M - r - q0 M/t) - q d M/t modulo M
+        uint32_t e1 = mod_m(d * (uint32_t)(dm.M - r - q0 * dm.Mt));
+        const uint32_t step = mod_m(d * (uint32_t)dm.Mt);
+        {
+            const uint32_t ob = 8u * ((uint32_t)dm.M - e2);
+#pragma unroll
+            for (int p = 0; p < X; ++p) g[p] += gather(base, xb[p], ob);
+        }
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            if (q >= nq) break;
+            const uint32_t ob = 8u * ((uint32_t)dm.M - e1);
+#pragma unroll
+            for (int p = 0; p < X; ++p) acc[q][p] += gather(base, xb[p], ob);
+            e1 = e1 >= step ? e1 - step : e1 + (uint32_t)dm.M - step;
+        }
+    };
+    // polynomial b of the rows done: the coefficients at N <= x < M through the free slot,
+    // then coefficient j of row i is (F(j) - F(N + j mod M/t)) u
+    auto fold = [&](int slot, int b) {
+        uint64_t *w = L + slot * EXS_SLOT;  // [q][M/t]
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            if (q >= nq) break;
+#pragma unroll
+            for (int p = 0; p < X; ++p) {
+                const int x = tid + EXS_T * p;
+                if (x >= dm.N && x < dm.M) w[q * dm.Mt + x - dm.N] = acc[q][p] - g[p];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            if (q >= nq) break;
+            uint64_t *o = rows + ((int64_t)ch * dm.N + r + (q0 + q) * dm.Mt) * ct + (int64_t)b * dm.N;
+#pragma unroll
+            for (int p = 0; p < X; ++p) {
+                const int x = tid + EXS_T * p;
+                if (x < dm.N) o[x] = (acc[q][p] - g[p] - w[q * dm.Mt + x % dm.Mt]) * u;
+            }
+        }
+#pragma unroll
+        for (int p = 0; p < X; ++p) {
+            g[p] = 0;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) acc[q][p] = 0;
+        }
+        __syncthreads();
+    };
+    // one unit from `slot`; the next goes to the other slot, the one after into registers
+    auto step = [&](int slot, int uu) {
+        compute(slot, uu);
+        if (uu % pw.n == pw.n - 1) fold(1 - slot, uu / pw.n);
+        if (uu + 1 < U) store(1 - slot);
+        if (uu + 2 < U) load(uu + 2);
+        __syncthreads();
+    };
+    load(0);
+    store(0);
+    load(1);  // U = 2 n_pow >= 2
+    __syncthreads();
+    for (int uu = 0; uu < U; uu += 2) {
+        step(0, uu);
+        step(1, uu + 1);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // integer layer on rows (CSR): grid (ceil(2N / 256), n_out)
 // ---------------------------------------------------------------------------
@@ -1040,6 +1175,35 @@ int native_keys_load(Native *n, const uint64_t *ksk, hipStream_t s) {
     return FHELIN_OK;
 }
 
+// the streamed kernel's instance for M (positions per thread X = ceil(M / EXS_T)) and t
+// (rows per workgroup Q: 2 for t <= 5, else 3; with more, the accumulators leave room for
+// one workgroup per compute unit only, measured slower: 16.0 against 15.1 ms of
+// extraction per ResNet-20 inference for M = 7^4 at gamma = 2 with Q = 6 and 3)
+using ExsKernel = void (*)(const uint64_t *, uint64_t *, NatDims, NatPowers, uint64_t, int);
+template <int Q>
+static ExsKernel exs_kernel_q(int X) {
+    switch (X) {
+    case 1: return k_nat_extract_stream<1, Q>;
+    case 2: return k_nat_extract_stream<2, Q>;
+    case 3: return k_nat_extract_stream<3, Q>;
+    case 4: return k_nat_extract_stream<4, Q>;
+    case 5: return k_nat_extract_stream<5, Q>;
+    case 6: return k_nat_extract_stream<6, Q>;
+    case 7: return k_nat_extract_stream<7, Q>;
+    case 8: return k_nat_extract_stream<8, Q>;
+    default: return nullptr;
+    }
+}
+static int exs_rows(int t) { return t <= 5 ? 2 : 3; }
+static ExsKernel exs_kernel(int M, int t) {
+    const int X = (M + EXS_T - 1) / EXS_T;
+    switch (exs_rows(t)) {
+    case 2: return exs_kernel_q<2>(X);
+    case 3: return exs_kernel_q<3>(X);
+    default: return nullptr;
+    }
+}
+
 int native_extract(Native *n, const uint64_t *pows, int n_chunks, uint64_t *rows, hipStream_t s) {
     FL_CHECK(n && pows && rows && n_chunks >= 0, FHELIN_E_INVALID_ARG, "native_extract: null argument");
     FL_CHECK(n_chunks <= 65535, FHELIN_E_INVALID_ARG, "native_extract: at most 65535 chunks per call");
@@ -1062,6 +1226,10 @@ int native_extract(Native *n, const uint64_t *pows, int n_chunks, uint64_t *rows
         const int rpg = std::max(4, (n->N + groups - 1) / groups);
         hipLaunchKernelGGL(k_nat_extract_lds, dim3((n->N + rpg - 1) / rpg, n_chunks), dim3(EXT_T), lds, s, pows, rows,
                            dims(n), pw, n->u, rpg);
+    } else if (n->M <= EXS_SLOT) {
+        const int Q = exs_rows(n->prm.t), passes = (n->prm.t - 1 + Q - 1) / Q;
+        hipLaunchKernelGGL(exs_kernel(n->M, n->prm.t), dim3(n->Mt * passes, n_chunks), dim3(EXS_T), 0, s, pows,
+                           rows, dims(n), pw, n->u, n->prm.t);
     } else {
         const int passes = (n->prm.t - 2) / EXT_Q + 1;  // ceil((t - 1) / EXT_Q)
         hipLaunchKernelGGL(k_nat_extract, dim3((n->N + 255) / 256, n->Mt * passes, n_chunks), dim3(256), 0, s, pows,

@@ -94,6 +94,30 @@ def test_native_pipeline_bit_exact_small_rings(t, alpha, gamma, beta, engine):
         assert np.array_equal(dec, exp), g
 
 
+@pytest.mark.parametrize("t,alpha,gamma,n_chunks", [(11, 3, 1, 2), (13, 3, 1, 2), (7, 3, 2, 2), (3, 8, 1, 1)])
+def test_native_extract_rings_outside_lds(t, alpha, gamma, n_chunks):
+    """Extraction where the chunk's powers do not fit LDS whole: rings with M <= 4096
+    streamed power by power (t = 11: four workgroups of rows per residue r, the last
+    with one row; t = 13: four of three; M = 7^3 at gamma = 2: 42 powers, two of
+    three) and M = 3^8 > 4096 on the gather kernel; uniform 64-bit inputs (extraction
+    is linear over Z_{2^64}), every row element by element."""
+    from paper_2509_01253_amd import fhelin as F
+    import torch
+    print(f"native extract t={t} alpha={alpha} gamma={gamma} chunks={n_chunks}", flush=True)
+    P = R.NativeParams(t, alpha, gamma, alpha - 1, 9, 3, 8, 2.0 ** 28)
+    rng = np.random.default_rng(1300 + t * 10 + alpha + gamma)
+    pows = rng.integers(0, 2 ** 64, (n_chunks, len(P.powers()), 2, P.N), dtype=np.uint64)
+    nt = F.fhelin_native_create(P.t, P.alpha, P.gamma, P.beta, P.log_d, P.l, P.log_p, 0, P.base)
+    try:
+        rows = torch.zeros((n_chunks * P.N, 2, P.N), dtype=torch.int64, device="cuda")
+        F.fhelin_native_extract(nt, dev(pows), rows)
+        got = host(rows)
+    finally:
+        F.fhelin_native_destroy(nt)
+    for c in range(n_chunks):
+        assert np.array_equal(got[c * P.N: (c + 1) * P.N], R.extract(P, pows[c])), c
+
+
 @pytest.mark.parametrize("engine", [0, 1])
 @pytest.mark.parametrize("gamma", [1, 2])
 def test_native_pipeline_paper_8bit_set(gamma, engine):
