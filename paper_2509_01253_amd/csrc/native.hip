@@ -242,8 +242,8 @@ __global__ void __launch_bounds__(EXS_T, 2) k_nat_extract_stream(const uint64_t 
     }
     // unit u into the staging registers: coefficient x of polynomial b of power k, zero
     // for N <= x < M
-    auto load = [&](int uu) {
-        const uint64_t *c = src + (uu % pw.n) * ct + (uu / pw.n) * dm.N;
+    auto load = [&](int b, int k) {
+        const uint64_t *c = src + k * ct + b * dm.N;
 #pragma unroll
         for (int p = 0; p < X; ++p) {
             const int x = tid + EXS_T * p;
@@ -273,9 +273,9 @@ __global__ void __launch_bounds__(EXS_T, 2) k_nat_extract_stream(const uint64_t 
         const uint32_t sb = x8 + ob;
         return *(const uint64_t *)(base + min(sb, sb - mb));
     };
-    auto compute = [&](int slot, int uu) {
+    auto compute = [&](int slot, int k) {
         const char *base = (const char *)(L + slot * EXS_SLOT);
-        const uint32_t d = (uint32_t)pw.d[uu % pw.n];
+        const uint32_t d = (uint32_t)pw.d[k];
         const uint32_t e2 = mod_m(d * (uint32_t)(dm.Mt - r));
         // e1 of row r + (q0 + q) M/t is d (M - r - q0 M/t) - q d M/t modulo M
         uint32_t e1 = mod_m(d * (uint32_t)(dm.M - r - q0 * dm.Mt));
@@ -326,17 +326,31 @@ __global__ void __launch_bounds__(EXS_T, 2) k_nat_extract_stream(const uint64_t 
         }
         __syncthreads();
     };
+    // units counted without divisions: (bc, kc) the one computed, (bl, kl) the one last
+    // loaded into registers
+    int bc = 0, kc = 0, bl = 0, kl = 0;
+    auto next = [&](int &b, int &k) {
+        if (++k == pw.n) {
+            k = 0;
+            ++b;
+        }
+    };
     // one unit from `slot`; the next goes to the other slot, the one after into registers
     auto step = [&](int slot, int uu) {
-        compute(slot, uu);
-        if (uu % pw.n == pw.n - 1) fold(1 - slot, uu / pw.n);
+        compute(slot, kc);
+        if (kc == pw.n - 1) fold(1 - slot, bc);
         if (uu + 1 < U) store(1 - slot);
-        if (uu + 2 < U) load(uu + 2);
+        if (uu + 2 < U) {
+            next(bl, kl);
+            load(bl, kl);
+        }
+        next(bc, kc);
         __syncthreads();
     };
-    load(0);
+    load(bl, kl);
     store(0);
-    load(1);  // U = 2 n_pow >= 2
+    next(bl, kl);
+    load(bl, kl);  // U = 2 n_pow >= 2
     __syncthreads();
     for (int uu = 0; uu < U; uu += 2) {
         step(0, uu);
