@@ -93,7 +93,7 @@ __device__ __forceinline__ int gadget_digit(uint64_t &top, const NatGadget &g) {
 }
 
 // ---------------------------------------------------------------------------
-// extraction: grid (ceil(N / 256), N rows, chunks)
+// extraction: the rows of each chunk from the encryptions of its powers
 // ---------------------------------------------------------------------------
 struct NatPowers {
     int n;
