@@ -579,8 +579,8 @@ __global__ void __launch_bounds__(256) k_nat_conv(const uint64_t *__restrict__ r
             if (x < 0 || x >= w) continue;
             const uint64_t *in = rows + ((int64_t)(y * w + x) * c_in) * n2 + col;
             const int32_t *wp = wT + (int64_t)(dy * k + dx) * cop + co0;
-            for (int ci = 0; ci < c_in; ++ci) {
-                const uint64_t v = in[(int64_t)ci * n2];
+            // input ci times the 16 channels' weights
+            auto mac = [&](uint64_t v, int ci) {
                 const uint32_t vl = (uint32_t)v, vh = (uint32_t)(v >> 32);
                 sum += v;
                 const int4 *w4 = (const int4 *)(wp + ci * ci_stride);
@@ -598,6 +598,18 @@ __global__ void __launch_bounds__(256) k_nat_conv(const uint64_t *__restrict__ r
                     acc[q] += (uint64_t)wv[q] * vl;
                     acc_hi[q] += (uint64_t)wv[q] * vh;
                 }
+            };
+            // inputs two at a time, the next two loaded while these are multiplied; the
+            // loads past the last input re-read it (clamped index, no branch between a
+            // load and its use)
+            const int last = c_in - 1;
+            uint64_t va = in[0], vb = in[(int64_t)min(1, last) * n2];
+            for (int ci = 0; ci < c_in; ci += 2) {
+                const uint64_t a = va, b = vb;
+                va = in[(int64_t)min(ci + 2, last) * n2];
+                vb = in[(int64_t)min(ci + 3, last) * n2];
+                mac(a, ci);
+                if (ci + 1 < c_in) mac(b, ci + 1);
             }
         }
     }
