@@ -429,6 +429,93 @@ __global__ void __launch_bounds__(256) k_nat_merge_v(const uint64_t *__restrict_
     o[dm.N + j] = a1;
 }
 
+// The same merge terms with the t sub-packs of a merge read once: a workgroup takes one
+// (r, pack), stages polynomial b of cur[r + k step] in LDS for k = 0..t-1 and
+// accumulates all t terms m in registers in the cyclic ring Z[X]/(X^M - 1) at all M
+// positions, reduced modulo Phi_M (coefficient j minus coefficient N + j mod M/t) once
+// at the end through LDS, as the streamed extraction does.  Thread x owns positions
+// x + MGS_T p, p < X (M <= X MGS_T <= MGS_SLOT); the slot holds the staged polynomial at
+// [0, N), zeros up to X MGS_T.  grid (step, packs), MGS_T threads, 32 KiB of LDS.
+constexpr int MGS_T = 512;
+constexpr int MGS_SLOT = 4096;
+template <int X, int TT>
+__global__ void __launch_bounds__(MGS_T) k_nat_merge_s(const uint64_t *__restrict__ cur, uint64_t *__restrict__ v,
+                                                       NatDims dm, int step, int th) {
+    __shared__ uint64_t L[MGS_SLOT];
+    const int r = blockIdx.x, g = blockIdx.y, tid = threadIdx.x;
+    const int64_t ct = 2 * (int64_t)dm.N;
+    const uint64_t *base = cur + (int64_t)g * TT * step * ct;
+    // term m shifts sub-pack k by k (th - m M/t) modulo M
+    int em[TT];
+#pragma unroll
+    for (int m = 0; m < TT; ++m) {
+        int e = (th - m * dm.Mt) % dm.M;
+        em[m] = e < 0 ? e + dm.M : e;
+    }
+    uint32_t xb[X];  // byte offsets of the thread's positions
+#pragma unroll
+    for (int p = 0; p < X; ++p) xb[p] = 8u * (uint32_t)(tid + MGS_T * p);
+    const uint32_t mb = 8u * (uint32_t)dm.M;
+    const char *lb = (const char *)L;
+#pragma unroll 1
+    for (int b = 0; b < 2; ++b) {
+        uint64_t F[TT][X];
+        int e[TT];  // k em[m] modulo M for the current k
+#pragma unroll
+        for (int m = 0; m < TT; ++m) {
+            e[m] = 0;
+#pragma unroll
+            for (int p = 0; p < X; ++p) F[m][p] = 0;
+        }
+#pragma unroll 1
+        for (int k = 0; k < TT; ++k) {
+            const uint64_t *y = base + (int64_t)(r + k * step) * ct + (int64_t)b * dm.N;
+            __syncthreads();  // the previous polynomial's (or fold's) readers are done
+#pragma unroll
+            for (int p = 0; p < X; ++p) {
+                const int x = tid + MGS_T * p;
+                L[x] = x < dm.N ? y[x] : 0;
+            }
+            __syncthreads();
+            // coefficient x of X^e y modulo X^M - 1 is y at (x + M - e) mod M; with
+            // o = M - e in [1, M] and x < MGS_SLOT the byte index xb + 8 o is below
+            // 8 (MGS_SLOT + M), and the unsigned minimum of it and itself less 8 M is the
+            // remainder's for x < M and in the slot for the rest
+#pragma unroll
+            for (int m = 0; m < TT; ++m) {
+                const uint32_t ob = 8u * (uint32_t)(dm.M - e[m]);
+#pragma unroll
+                for (int p = 0; p < X; ++p) {
+                    const uint32_t sb = xb[p] + ob;
+                    F[m][p] += *(const uint64_t *)(lb + min(sb, sb - mb));
+                }
+                e[m] += em[m];
+                e[m] -= e[m] >= dm.M ? dm.M : 0;
+            }
+        }
+        // the coefficients at N <= x < M of every term through the slot, then
+        // coefficient j of term m is F_m(j) - F_m(N + j mod M/t)
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < TT; ++m)
+#pragma unroll
+            for (int p = 0; p < X; ++p) {
+                const int x = tid + MGS_T * p;
+                if (x >= dm.N && x < dm.M) L[m * dm.Mt + x - dm.N] = F[m][p];
+            }
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < TT; ++m) {
+            uint64_t *o = v + (((int64_t)g * step + r) * TT + m) * ct + (int64_t)b * dm.N;
+#pragma unroll
+            for (int p = 0; p < X; ++p) {
+                const int x = tid + MGS_T * p;
+                if (x < dm.N) o[x] = F[m][p] - L[m * dm.Mt + x % dm.Mt];
+            }
+        }
+    }
+}
+
 // automorphism + gadget digits of a batch, and the output's start value: grid
 // (ceil(N / 256), n); S [n] (s_es apart); digits [n][l][N] (offset by D/2, < D);
 // out[c] = (add_a + corr_a, add_b + sigma(b) + corr_b), to which the product kernel
@@ -1230,6 +1317,33 @@ static ExsKernel exs_kernel(int M, int t) {
     }
 }
 
+// the LDS-staged merge kernel's instance for M and t (nullptr: the gather kernel)
+using MgsKernel = void (*)(const uint64_t *, uint64_t *, NatDims, int, int);
+template <int TT>
+static MgsKernel mgs_kernel_t(int X) {
+    switch (X) {
+    case 1: return k_nat_merge_s<1, TT>;
+    case 2: return k_nat_merge_s<2, TT>;
+    case 3: return k_nat_merge_s<3, TT>;
+    case 4: return k_nat_merge_s<4, TT>;
+    case 5: return k_nat_merge_s<5, TT>;
+    case 6: return k_nat_merge_s<6, TT>;
+    case 7: return k_nat_merge_s<7, TT>;
+    case 8: return k_nat_merge_s<8, TT>;
+    default: return nullptr;
+    }
+}
+static MgsKernel mgs_kernel(int M, int t) {
+    const int X = (M + MGS_T - 1) / MGS_T;
+    if (M > MGS_SLOT) return nullptr;
+    switch (t) {
+    case 3: return mgs_kernel_t<3>(X);
+    case 5: return mgs_kernel_t<5>(X);
+    case 7: return mgs_kernel_t<7>(X);
+    default: return nullptr;
+    }
+}
+
 int native_extract(Native *n, const uint64_t *pows, int n_chunks, uint64_t *rows, hipStream_t s) {
     FL_CHECK(n && pows && rows && n_chunks >= 0, FHELIN_E_INVALID_ARG, "native_extract: null argument");
     FL_CHECK(n_chunks <= 65535, FHELIN_E_INVALID_ARG, "native_extract: at most 65535 chunks per call");
@@ -1405,7 +1519,13 @@ int native_pack(Native *n, const uint64_t *rows, int n_rows, uint64_t *packed, h
         const int lv = i - n->prm.gamma, step = len / t, th = (int)(n->M / ipow(t, i + 1));
         {
             NatProf pm(n, s, NK_MERGE, (double)packs * len * n->N, (double)packs * len * ct * 8 * 2);
-            hipLaunchKernelGGL(k_nat_merge_v, dim3(gx, step * t, packs), dim3(256), 0, s, cur, v, dm, t, step, th);
+            // the staged kernel when it has a workgroup per compute unit at least (with
+            // fewer, the gather kernel's many small workgroups finish sooner)
+            const MgsKernel mk = mgs_kernel(n->M, t);
+            if (mk && (int64_t)step * packs >= std::max(n->cus, 1))
+                hipLaunchKernelGGL(mk, dim3(step, packs), dim3(MGS_T), 0, s, cur, v, dm, step, th);
+            else
+                hipLaunchKernelGGL(k_nat_merge_v, dim3(gx, step * t, packs), dim3(256), 0, s, cur, v, dm, t, step, th);
             FL_TRY_HIP(hipGetLastError());
         }
         // S = v_(t-1); S = v_m + tau_i(S) for m = t-2 .. 0 (a merge's t terms are ct apart);

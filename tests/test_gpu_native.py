@@ -118,6 +118,34 @@ def test_native_extract_rings_outside_lds(t, alpha, gamma, n_chunks):
         assert np.array_equal(got[c * P.N: (c + 1) * P.N], R.extract(P, pows[c])), c
 
 
+@pytest.mark.parametrize("t,alpha,gamma,beta,packs", [(3, 5, 1, 4, 30), (3, 5, 2, 4, 90), (5, 4, 1, 3, 60),
+                                                       (7, 3, 1, 2, 260)])
+def test_native_pack_many_packs(t, alpha, gamma, beta, packs):
+    """Packing enough outputs that a merge level has a workgroup per compute unit for
+    every (sub-pack, pack) pair, where the merge terms stage their sub-packs in LDS
+    (the smaller levels of the same call keep the gather kernel): uniform 64-bit
+    layer outputs, the last pack partial, every packed ciphertext element by element
+    against the oracle."""
+    from paper_2509_01253_amd import fhelin as F
+    import torch
+    print(f"native pack t={t} alpha={alpha} gamma={gamma} beta={beta} packs={packs}", flush=True)
+    P = R.NativeParams(t, alpha, gamma, beta, 9, 3, 8, 2.0 ** 28)
+    keys = R.NativeClient(P, 1400 + t * 10 + alpha + gamma).keyset()
+    rng = np.random.default_rng(1410 + t * 10 + alpha + gamma)
+    n_out = packs * P.n_pack - 7
+    rows = rng.integers(0, 2 ** 64, (n_out, 2, P.N), dtype=np.uint64)
+    nt = F.fhelin_native_create(P.t, P.alpha, P.gamma, P.beta, P.log_d, P.l, P.log_p, 0, P.base)
+    try:
+        F.fhelin_native_keys_load(nt, dev(np.stack([keys[d] for d in P.taus()])))
+        packed = torch.zeros((packs, 2, P.N), dtype=torch.int64, device="cuda")
+        F.fhelin_native_pack(nt, dev(rows), packed)
+        got = host(packed)
+    finally:
+        F.fhelin_native_destroy(nt)
+    for g in range(packs):
+        assert np.array_equal(got[g], R.pack(P, rows[g * P.n_pack: (g + 1) * P.n_pack], keys)), g
+
+
 @pytest.mark.parametrize("engine", [0, 1])
 @pytest.mark.parametrize("gamma", [1, 2])
 def test_native_pipeline_paper_8bit_set(gamma, engine):
