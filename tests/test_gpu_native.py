@@ -118,18 +118,19 @@ def test_native_extract_rings_outside_lds(t, alpha, gamma, n_chunks):
         assert np.array_equal(got[c * P.N: (c + 1) * P.N], R.extract(P, pows[c])), c
 
 
-@pytest.mark.parametrize("t,alpha,gamma,beta,packs", [(3, 5, 1, 4, 30), (3, 5, 2, 4, 90), (5, 4, 1, 3, 60),
-                                                       (7, 3, 1, 2, 260)])
-def test_native_pack_many_packs(t, alpha, gamma, beta, packs):
+@pytest.mark.parametrize("t,alpha,gamma,beta,packs,log_d,l", [(3, 5, 1, 4, 30, 9, 3), (3, 5, 2, 4, 90, 9, 3),
+                                                               (5, 4, 1, 3, 60, 9, 3), (7, 3, 1, 2, 260, 9, 3),
+                                                               (5, 4, 1, 3, 60, 16, 2)])
+def test_native_pack_many_packs(t, alpha, gamma, beta, packs, log_d, l):
     """Packing enough outputs that a merge level has a workgroup per compute unit for
     every (sub-pack, pack) pair, where the merge terms stage their sub-packs in LDS
-    (the smaller levels of the same call keep the gather kernel): uniform 64-bit
-    layer outputs, the last pack partial, every packed ciphertext element by element
-    against the oracle."""
+    (the smaller levels of the same call keep the gather kernel; key switches with two
+    digit pieces at D = 2^9, three at 2^16): uniform 64-bit layer outputs, the last
+    pack partial, every packed ciphertext element by element against the oracle."""
     from paper_2509_01253_amd import fhelin as F
     import torch
-    print(f"native pack t={t} alpha={alpha} gamma={gamma} beta={beta} packs={packs}", flush=True)
-    P = R.NativeParams(t, alpha, gamma, beta, 9, 3, 8, 2.0 ** 28)
+    print(f"native pack t={t} alpha={alpha} gamma={gamma} beta={beta} packs={packs} log_d={log_d}", flush=True)
+    P = R.NativeParams(t, alpha, gamma, beta, log_d, l, 8 if log_d == 9 else 12, 2.0 ** 28 if log_d == 9 else 2.0 ** 13)
     keys = R.NativeClient(P, 1400 + t * 10 + alpha + gamma).keyset()
     rng = np.random.default_rng(1410 + t * 10 + alpha + gamma)
     n_out = packs * P.n_pack - 7
